@@ -1,0 +1,136 @@
+/*
+ * kbisim.h -- C ABI of the MI355X (gfx950) k-bisimulation library.
+ *
+ * The library computes the k-bisimulation partition of a node- and
+ * edge-labelled directed graph (Definition 1 of the paper "External memory
+ * bisimulation reduction of big graphs", Section 2.1) by the signature
+ * method of its construction algorithm (Algorithm 1, Build_Bisim, Section 3):
+ * round i joins every edge (src, label, dst) with pId_{i-1}(dst), forms each
+ * node's signature from pId_{i-1}(node) and the set of (label, pId_{i-1}(dst))
+ * pairs (Definition 3, with the previous id as head -- Kaushik's equivalent
+ * definition, Appendix), and maps distinct signatures to new ids
+ * (S.insert, Section 2.2). All rounds run as HIP kernels on one GPU with the
+ * graph resident in device memory.
+ *
+ * Canonical ids. pId_i(u) is the 0-based rank of u's signature among the
+ * distinct signatures of round i, in lexicographic order of the int sequence
+ * [pId_{i-1}(u), l1, p1, l2, p2, ...] with the pairs ascending and a proper
+ * prefix ordered first; pId_0(u) is the rank of u's label among the distinct
+ * node labels (Section 3.1, "k = 0"). Labels are compared as integers. The
+ * ids of round i are therefore dense in [0, B_i) and fully determined by the
+ * graph (the paper leaves the numbering free, Section 3.2).
+ *
+ * Early stop. With early stop on (default) the round loop ends after the
+ * first round i with B_i == B_{i-1} (Section 3.2, "Early stopping
+ * condition"); its ids equal those of every later round.
+ *
+ * Errors. Every call returns a kbisim_status; 0 is success. On error the
+ * out-parameters are left untouched and a handle stays usable;
+ * kbisim_last_error() gives a message for the calling thread. A handle is not
+ * thread-safe; distinct handles may be used from distinct threads.
+ *
+ * Limits: 0 <= N < 2^31, 0 <= E < 2^32 - 1, labels int32 >= 0.
+ */
+#ifndef KBISIM_H
+#define KBISIM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  KBISIM_OK = 0,
+  KBISIM_EINVAL = -1,    /* invalid argument or input graph */
+  KBISIM_ENOMEM = -2,    /* device or host allocation failed, or over budget */
+  KBISIM_EDEVICE = -3,   /* a HIP call failed */
+  KBISIM_ESTATE = -4,    /* call not valid in the current state */
+  KBISIM_EBUSY = -5,     /* server: no capacity right now */
+  KBISIM_ECANCELED = -6, /* server: request was cancelled */
+  KBISIM_ETIMEDOUT = -7  /* server: wait timed out */
+} kbisim_status;
+
+typedef enum { KBISIM_MEM_HOST = 0, KBISIM_MEM_DEVICE = 1 } kbisim_mem;
+
+typedef struct kbisim_graph kbisim_graph;
+
+/* A graph as N node labels and E labelled edges (src, label, dst). The four
+ * arrays live in host or device memory (`mem`); they are read during
+ * kbisim_create only. Edges form a multiset: duplicates are allowed and
+ * ignored (signatures are sets), self-loops are allowed. */
+typedef struct {
+  int64_t num_nodes;          /* N >= 0 */
+  int64_t num_edges;          /* E >= 0 */
+  const int32_t* node_label;  /* [N], values >= 0 */
+  const int32_t* edge_src;    /* [E], values in [0, N) */
+  const int32_t* edge_label;  /* [E], values >= 0 */
+  const int32_t* edge_dst;    /* [E], values in [0, N) */
+  kbisim_mem mem;             /* where the four arrays live */
+  void* stream;               /* hipStream_t for all work of this handle; NULL = default stream */
+} kbisim_graph_desc;
+
+typedef struct {
+  int32_t early_stop; /* 1 (default): stop at the first round with B_i == B_{i-1} */
+  int32_t hash_bits;  /* 1..64 (default 64): bits kept of the signature hash; fewer bits
+                         only cost time (equal hashes are always verified key by key) */
+  int32_t profile;    /* 1: time each kernel class with HIP events (kbisim_profile) */
+} kbisim_options;
+
+/* Fills *opt with the defaults above. */
+void kbisim_options_default(kbisim_options* opt);
+
+/* Copies the graph into library-owned device memory, builds the CSR edge
+ * table and computes pId_0 on desc->stream. The caller's arrays may be freed
+ * once this returns (device arrays: once the stream has reached this point).
+ * opt may be NULL. On success *out receives a new handle. */
+kbisim_status kbisim_create(const kbisim_graph_desc* desc, const kbisim_options* opt,
+                            kbisim_graph** out);
+
+/* Runs refinement rounds until round k has been computed or the fixed point
+ * is reached (early stop). Resumable: a later call with a larger k continues
+ * from the last round; k at or below the rounds already done does nothing.
+ * *rounds_done (may be NULL) receives the number of rounds executed so far.
+ * k < 0 is KBISIM_EINVAL. Synchronises the handle's stream. */
+kbisim_status kbisim_refine(kbisim_graph* g, int32_t k, int32_t* rounds_done);
+
+/* Writes the ids of the last computed round (pId_k) to pid_out[N] in host or
+ * device memory (device: enqueued on the handle's stream, then synchronised),
+ * *num_blocks = B of that round, and counts[0..min(counts_cap, rounds+1)) =
+ * B_0, B_1, ... . Any pointer may be NULL to skip that output. */
+kbisim_status kbisim_result(const kbisim_graph* g, int32_t* pid_out, kbisim_mem mem,
+                            int64_t* num_blocks, int64_t* counts, int32_t counts_cap);
+
+/* Kernel classes timed when options.profile = 1. */
+typedef enum {
+  KBISIM_PROF_SIG_THREAD = 0, /* signatures, out-degree <= 16 (one thread per node) */
+  KBISIM_PROF_SIG_WAVE = 1,   /* signatures, out-degree <= 64 (one wave per node) */
+  KBISIM_PROF_SIG_BLOCK = 2,  /* signatures, out-degree <= 4096 (one workgroup per node) */
+  KBISIM_PROF_SIG_HUB = 3,    /* signatures, larger out-degree */
+  KBISIM_PROF_ORDER = 4,      /* ordering signatures inside blocks (all kernels) */
+  KBISIM_PROF_ASSIGN = 5,     /* scan + id assignment */
+  KBISIM_PROF_ROUND = 6,      /* one whole round */
+  KBISIM_PROF_COUNT = 7
+} kbisim_prof_class;
+
+/* Timings collected when options.profile = 1 with HIP events recorded on the
+ * handle's stream around each launch of class c: ms[c] = summed milliseconds,
+ * launches[c] = number of timed launches, since create or the last reset
+ * (reset != 0 clears after reading). cap = entries of ms/launches. */
+kbisim_status kbisim_profile(const kbisim_graph* g, double* ms, int64_t* launches, int32_t cap,
+                             int32_t reset);
+
+/* Frees everything owned by the handle. NULL is ignored. */
+void kbisim_destroy(kbisim_graph* g);
+
+/* Static text for a status code. */
+const char* kbisim_status_str(kbisim_status s);
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char* kbisim_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KBISIM_H */

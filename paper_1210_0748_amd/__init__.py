@@ -1,0 +1,14 @@
+"""MI355X-native k-bisimulation partition refinement.
+
+Python binding of the C ABI in ``include/kbisim.h`` (``libkbisim.so``, HIP
+kernels for gfx950). Arguments are marshalled here; every step of the
+refinement runs in the library's kernels. PyTorch supplies device memory and
+the stream.
+"""
+from ._binding import (KbisimError, Graph, refine, kbisim_create, kbisim_refine, kbisim_result,
+                       kbisim_profile, kbisim_destroy, kbisim_status_str, kbisim_last_error,
+                       lib_path, load_library, PROF_CLASSES)
+
+__all__ = ["KbisimError", "Graph", "refine", "kbisim_create", "kbisim_refine", "kbisim_result",
+           "kbisim_profile", "kbisim_destroy", "kbisim_status_str", "kbisim_last_error",
+           "lib_path", "load_library", "PROF_CLASSES"]

@@ -1,0 +1,230 @@
+"""ctypes binding of libkbisim.so (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libkbisim.so")
+
+KBISIM_MEM_HOST = 0
+KBISIM_MEM_DEVICE = 1
+PROF_CLASSES = ["sig_thread", "sig_wave", "sig_block", "sig_hub", "order", "assign", "round"]
+
+STATUS = {0: "KBISIM_OK", -1: "KBISIM_EINVAL", -2: "KBISIM_ENOMEM", -3: "KBISIM_EDEVICE",
+          -4: "KBISIM_ESTATE", -5: "KBISIM_EBUSY", -6: "KBISIM_ECANCELED", -7: "KBISIM_ETIMEDOUT"}
+
+
+class KbisimError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s: %s" % (STATUS.get(status, status), message))
+        self.status = status
+
+
+class GraphDesc(ctypes.Structure):
+    _fields_ = [("num_nodes", ctypes.c_int64), ("num_edges", ctypes.c_int64),
+                ("node_label", ctypes.c_void_p), ("edge_src", ctypes.c_void_p),
+                ("edge_label", ctypes.c_void_p), ("edge_dst", ctypes.c_void_p),
+                ("mem", ctypes.c_int), ("stream", ctypes.c_void_p)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("early_stop", ctypes.c_int32), ("hash_bits", ctypes.c_int32),
+                ("profile", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib_path():
+    return _LIB_PATH
+
+
+def load_library():
+    """Loads libkbisim.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError("libkbisim.so not built: run `python -m paper_1210_0748_amd.build` "
+                          "(or __graft_entry__.build())")
+    lib = ctypes.CDLL(_LIB_PATH)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    lib.kbisim_options_default.argtypes = [ctypes.POINTER(Options)]
+    lib.kbisim_options_default.restype = None
+    lib.kbisim_create.argtypes = [ctypes.POINTER(GraphDesc), ctypes.POINTER(Options), ctypes.POINTER(vp)]
+    lib.kbisim_create.restype = ctypes.c_int
+    lib.kbisim_refine.argtypes = [vp, i32, ctypes.POINTER(i32)]
+    lib.kbisim_refine.restype = ctypes.c_int
+    lib.kbisim_result.argtypes = [vp, vp, ctypes.c_int, ctypes.POINTER(i64), vp, i32]
+    lib.kbisim_result.restype = ctypes.c_int
+    lib.kbisim_profile.argtypes = [vp, vp, vp, i32, i32]
+    lib.kbisim_profile.restype = ctypes.c_int
+    lib.kbisim_destroy.argtypes = [vp]
+    lib.kbisim_destroy.restype = None
+    lib.kbisim_status_str.argtypes = [ctypes.c_int]
+    lib.kbisim_status_str.restype = ctypes.c_char_p
+    lib.kbisim_last_error.argtypes = []
+    lib.kbisim_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(st):
+    if st != 0:
+        lib = load_library()
+        raise KbisimError(st, lib.kbisim_last_error().decode())
+
+
+def kbisim_status_str(status):
+    return load_library().kbisim_status_str(int(status)).decode()
+
+
+def kbisim_last_error():
+    return load_library().kbisim_last_error().decode()
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _arrays(node_label, src, elab, dst):
+    """Returns (mem kind, pointers, keepalive) for torch CUDA tensors or numpy."""
+    try:
+        import torch
+        is_torch = isinstance(node_label, torch.Tensor)
+    except ImportError:  # pragma: no cover
+        is_torch = False
+    if is_torch:
+        arrs = []
+        dev = None
+        for a in (node_label, src, elab, dst):
+            if a.dtype != torch.int32:
+                raise TypeError("arrays must be int32")
+            if not a.is_cuda:
+                raise TypeError("torch tensors must be on the GPU (use numpy for host arrays)")
+            if dev is not None and a.device != dev:
+                raise TypeError("all arrays must be on one device")
+            dev = a.device
+            arrs.append(a.contiguous())
+        return KBISIM_MEM_DEVICE, [a.data_ptr() for a in arrs], arrs
+    arrs = [np.ascontiguousarray(np.asarray(a), dtype=np.int32) for a in (node_label, src, elab, dst)]
+    return KBISIM_MEM_HOST, [a.ctypes.data for a in arrs], arrs
+
+
+def kbisim_create(num_nodes, node_label, src, elab, dst, *, stream=None, early_stop=True,
+                  hash_bits=64, profile=False):
+    """Creates a device-resident graph handle (see kbisim.h). Returns the handle."""
+    lib = load_library()
+    mem, ptrs, keep = _arrays(node_label, src, elab, dst)
+    n, m = int(num_nodes), int(keep[1].shape[0])
+    if int(keep[0].shape[0]) != n or int(keep[2].shape[0]) != m or int(keep[3].shape[0]) != m:
+        raise KbisimError(-1, "array lengths do not match num_nodes / num_edges")
+    desc = GraphDesc(n, m, ptrs[0] or None, ptrs[1] or None, ptrs[2] or None, ptrs[3] or None, mem,
+                     _stream_ptr(stream))
+    opt = Options()
+    lib.kbisim_options_default(ctypes.byref(opt))
+    opt.early_stop = 1 if early_stop else 0
+    opt.hash_bits = int(hash_bits)
+    opt.profile = 1 if profile else 0
+    h = ctypes.c_void_p()
+    _check(lib.kbisim_create(ctypes.byref(desc), ctypes.byref(opt), ctypes.byref(h)))
+    return h
+
+
+def kbisim_refine(handle, k):
+    rd = ctypes.c_int32(0)
+    _check(load_library().kbisim_refine(handle, int(k), ctypes.byref(rd)))
+    return int(rd.value)
+
+
+def kbisim_result(handle, pid_out=None, counts_cap=0):
+    """pid_out: torch CUDA int32 tensor, numpy int32 array or None.
+    Returns (num_blocks, counts list)."""
+    lib = load_library()
+    nb = ctypes.c_int64(0)
+    counts = np.zeros(max(int(counts_cap), 0), np.int64)
+    mem, ptr = KBISIM_MEM_HOST, None
+    if pid_out is not None:
+        if isinstance(pid_out, np.ndarray):
+            assert pid_out.dtype == np.int32 and pid_out.flags.c_contiguous
+            ptr = pid_out.ctypes.data
+        else:
+            assert pid_out.dtype.__repr__().endswith("int32") and pid_out.is_contiguous()
+            mem, ptr = KBISIM_MEM_DEVICE, pid_out.data_ptr()
+    _check(lib.kbisim_result(handle, ptr, mem, ctypes.byref(nb),
+                             counts.ctypes.data if counts_cap else None, int(counts_cap)))
+    return int(nb.value), [int(c) for c in counts]
+
+
+def kbisim_profile(handle, reset=False):
+    n = len(PROF_CLASSES)
+    ms = np.zeros(n, np.float64)
+    cnt = np.zeros(n, np.int64)
+    _check(load_library().kbisim_profile(handle, ms.ctypes.data, cnt.ctypes.data, n, 1 if reset else 0))
+    return {c: (float(ms[i]), int(cnt[i])) for i, c in enumerate(PROF_CLASSES)}
+
+
+def kbisim_destroy(handle):
+    if handle:
+        load_library().kbisim_destroy(handle)
+
+
+class Graph:
+    """Owning wrapper of a kbisim handle."""
+
+    def __init__(self, num_nodes, node_label, src, elab, dst, **kw):
+        self.num_nodes = int(num_nodes)
+        self._h = kbisim_create(num_nodes, node_label, src, elab, dst, **kw)
+        self.rounds_done = 0
+
+    def refine(self, k):
+        self.rounds_done = kbisim_refine(self._h, k)
+        return self.rounds_done
+
+    def result(self, device=None):
+        """Ids of the last round: a torch CUDA tensor if `device` is given,
+        else a numpy array. Also returns (num_blocks, counts)."""
+        cap = self.rounds_done + 1
+        if device is not None:
+            import torch
+            out = torch.empty(self.num_nodes, dtype=torch.int32, device=device)
+        else:
+            out = np.empty(self.num_nodes, np.int32)
+        nb, counts = kbisim_result(self._h, out if self.num_nodes else None, cap)
+        return out, nb, counts
+
+    def profile(self, reset=False):
+        return kbisim_profile(self._h, reset)
+
+    def close(self):
+        if self._h:
+            kbisim_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def refine(num_nodes, node_label, src, elab, dst, k, **kw):
+    """One-shot: returns (pid numpy array, counts, rounds_done)."""
+    with Graph(num_nodes, node_label, src, elab, dst, **kw) as g:
+        rd = g.refine(k)
+        pid, _, counts = g.result()
+        return pid, counts, rd

@@ -1,0 +1,118 @@
+// Once-per-graph steps: input validation, the k = 0 partition (Algorithm 1,
+// iteration 0: nodes sorted by label, one id per distinct label), dense
+// ranks of the edge labels, and the edge table grouped by source node (the
+// sort of the edge table that iteration 1 performs, kept as CSR).
+#pragma once
+
+#include "common.h"
+
+namespace kb {
+
+// err bit 1: src/dst outside [0, N); bit 2: negative edge label;
+// bit 4: negative node label. maxv[0] = max node label, maxv[1] = max edge label.
+__global__ void validate_edges_k(const int32_t* __restrict__ src, const int32_t* __restrict__ lab,
+                                 const int32_t* __restrict__ dst, uint64_t m, int64_t n,
+                                 uint32_t* __restrict__ err, uint32_t* __restrict__ maxv) {
+  uint32_t e_bits = 0, mx = 0;
+  for (uint64_t e = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < m;
+       e += uint64_t(gridDim.x) * blockDim.x) {
+    const int32_t s = src[e], d = dst[e], l = lab[e];
+    if (s < 0 || s >= n || d < 0 || d >= n) e_bits |= 1u;
+    if (l < 0)
+      e_bits |= 2u;
+    else
+      mx = uint32_t(l) > mx ? uint32_t(l) : mx;
+  }
+  if (e_bits) atomicOr(err, e_bits);
+  mx = wave_max(mx);
+  if (__lane_id() == 0) atomicMax(&maxv[1], mx);
+}
+
+__global__ void validate_nodes_k(const int32_t* __restrict__ label, uint64_t n,
+                                 uint32_t* __restrict__ err, uint32_t* __restrict__ maxv) {
+  uint32_t bad = 0, mx = 0;
+  for (uint64_t v = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < n;
+       v += uint64_t(gridDim.x) * blockDim.x) {
+    const int32_t l = label[v];
+    if (l < 0)
+      bad = 4u;
+    else
+      mx = uint32_t(l) > mx ? uint32_t(l) : mx;
+  }
+  if (bad) atomicOr(err, bad);
+  mx = wave_max(mx);
+  if (__lane_id() == 0) atomicMax(&maxv[0], mx);
+}
+
+__global__ void to_u32_iota_k(const int32_t* __restrict__ in, uint32_t* __restrict__ key,
+                              uint32_t* __restrict__ val, uint32_t n) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  key[i] = uint32_t(in[i]);
+  val[i] = i;
+}
+
+// flag[p] = 1 where the sorted key changes (first position of each run).
+__global__ void run_start_flags_k(const uint32_t* __restrict__ key, uint32_t n,
+                                  uint8_t* __restrict__ flag8, uint32_t* __restrict__ flag32) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const uint8_t f = (p == 0 || key[p] != key[p - 1]) ? 1 : 0;
+  if (flag8) flag8[p] = f;
+  if (flag32) flag32[p] = f;
+}
+
+// rank[val[p]] = cls[p] - 1 (cls = inclusive scan of the run-start flags).
+__global__ void rank_scatter_k(const uint32_t* __restrict__ val, const uint32_t* __restrict__ cls,
+                               uint32_t n, uint32_t* __restrict__ rank) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) rank[val[p]] = cls[p] - 1;
+}
+
+__global__ void degree_k(const int32_t* __restrict__ src, uint64_t m, uint32_t* __restrict__ deg) {
+  for (uint64_t e = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < m;
+       e += uint64_t(gridDim.x) * blockDim.x)
+    atomicAdd(&deg[src[e]], 1u);
+}
+
+// Places edge e in its source's CSR range; order inside a range is
+// irrelevant because every round sorts a node's keys.
+template <typename AdjT>
+__global__ void fill_adj_k(const int32_t* __restrict__ src, const uint32_t* __restrict__ erank,
+                           const int32_t* __restrict__ dst, uint64_t m, const uint32_t* __restrict__ rowptr,
+                           uint32_t* __restrict__ cursor, int dst_bits, AdjT* __restrict__ adj) {
+  for (uint64_t e = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < m;
+       e += uint64_t(gridDim.x) * blockDim.x) {
+    const uint32_t s = uint32_t(src[e]);
+    const uint32_t pos = rowptr[s] + atomicAdd(&cursor[s], 1u);
+    adj[pos] = (AdjT(erank[e]) << dst_bits) | AdjT(uint32_t(dst[e]));
+  }
+}
+
+// Degree buckets: 0 thread (<=16), 1 wave (<=64), 2 block (<=4096), 3 hub.
+__global__ void bucket_flags_k(const uint32_t* __restrict__ rowptr, uint32_t n, uint32_t t_max,
+                               uint32_t w_max, uint32_t b_max, uint32_t* __restrict__ fw,
+                               uint32_t* __restrict__ fb, uint32_t* __restrict__ fh,
+                               uint32_t* __restrict__ hub_deg) {
+  const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const uint32_t d = rowptr[v + 1] - rowptr[v];
+  fw[v] = d > t_max && d <= w_max;
+  fb[v] = d > w_max && d <= b_max;
+  fh[v] = d > b_max;
+  hub_deg[v] = d > b_max ? d : 0u;
+}
+
+__global__ void compact_index_k(const uint32_t* __restrict__ f, const uint32_t* __restrict__ off,
+                                uint32_t n, uint32_t* __restrict__ out) {
+  const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n && f[v]) out[off[v]] = v;
+}
+
+__global__ void gather_u32_k(const uint32_t* __restrict__ src, const uint32_t* __restrict__ idx,
+                             uint32_t n, uint32_t* __restrict__ out) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = src[idx[i]];
+}
+
+}  // namespace kb

@@ -1,0 +1,161 @@
+// Host-side round driver for one graph resident in device memory.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace kb {
+
+// Owning device allocation that only grows.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void ensure(size_t b) {
+    if (b <= bytes && p) return;
+    if (p) (void)hipDeviceSynchronize();  // work queued on the old buffer must finish
+    release();
+    const size_t want = b ? b : 1;
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      throw OutOfMemory("hipMalloc of " + std::to_string(want) + " bytes failed");
+    }
+    bytes = want;
+  }
+  template <typename T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+// Pinned host words for small device->host readbacks.
+struct HostWords {
+  uint64_t* p = nullptr;
+  HostWords() {
+    if (hipHostMalloc(reinterpret_cast<void**>(&p), 64 * sizeof(uint64_t), hipHostMallocDefault) !=
+        hipSuccess) {
+      (void)hipGetLastError();
+      p = nullptr;
+      throw OutOfMemory("hipHostMalloc of readback words failed");
+    }
+  }
+  ~HostWords() {
+    if (p) (void)hipHostFree(p);
+  }
+  HostWords(const HostWords&) = delete;
+  HostWords& operator=(const HostWords&) = delete;
+};
+
+struct Options {
+  bool early_stop = true;
+  int hash_bits = 64;
+  bool profile = false;
+};
+
+constexpr int kProfClasses = 7;
+
+// Segment lists produced by classification: small (one wave), medium (one
+// workgroup), large (global passes).
+struct SegLists {
+  DevBuf s_start, s_size, m_start, m_size, l_start, l_size;
+  uint32_t ns = 0, nm = 0, nl = 0;
+};
+
+class Engine {
+ public:
+  Engine(int64_t n, int64_t m, hipStream_t s, const Options& o);
+  ~Engine();
+
+  // desc arrays: device pointers (copies already made by the caller if host)
+  void build(const int32_t* node_label, const int32_t* src, const int32_t* lab, const int32_t* dst);
+  // Runs rounds until `k` rounds are done or the fixed point is hit.
+  void refine(int32_t k);
+  void result(int32_t* pid_out, bool to_device) const;
+
+  int64_t num_nodes() const { return n_; }
+  int64_t blocks() const { return B_; }
+  int32_t rounds_done() const { return rounds_; }
+  const std::vector<int64_t>& counts() const { return counts_; }
+  bool fixed() const { return fixed_; }
+  std::array<double, kProfClasses> prof_ms{};
+  std::array<int64_t, kProfClasses> prof_n{};
+  int adj_bytes() const { return adj64_ ? 8 : 4; }
+  int key_bytes() const { return key64_ ? 8 : 4; }
+  uint32_t num_edge_labels() const { return n_elab_; }
+
+ private:
+  template <typename AdjT>
+  void build_adj(const int32_t* src, const uint32_t* erank, const int32_t* dst);
+  template <typename AdjT, typename KeyT>
+  void round_impl();
+  template <typename KeyT>
+  void order_groups(int key_bits, const void* kv);
+  template <typename KeyT>
+  void resolve_lists(SegLists& L, const void* kv, uint32_t d0);
+  void make_lists(const uint32_t* seg_start, const uint32_t* seg_size, const uint8_t* seg_done,
+                  uint32_t nseg, SegLists& out);
+  void run_round();
+  void assign_ids_into(int32_t* pid_out);
+  uint64_t read_word(const void* dev, int bytes);
+  template <typename Tin, typename Tout, bool kIncl>
+  void scan_dev(const Tin* in, Tout* out, uint64_t n);
+  uint32_t* radix_scratch(uint64_t n);
+
+  void ev_begin(int cls);
+  void ev_end(int cls);
+  void ev_collect();
+
+  int64_t n_, m_;
+  hipStream_t st_;
+  Options opt_;
+  HostWords hw_;
+
+  bool adj64_ = false, key64_ = false;
+  int dst_bits_ = 1, lab_bits_ = 0;
+  uint32_t n_elab_ = 0;
+
+  // graph
+  DevBuf rowptr_, adj_, wlist_, blist_, hlist_, hub_off_, hub_tmp_;
+  uint32_t nw_ = 0, nb_ = 0, nh_ = 0;
+  // partition state
+  DevBuf pid_[2], ord_, flag_, bstart_;
+  int cur_ = 0;
+  int64_t B_ = 0;
+  int32_t rounds_ = 0;
+  bool fixed_ = false;
+  std::vector<int64_t> counts_;
+  // round scratch
+  DevBuf ukey_, ucnt_, hsh_, cls_, scanpart_, radix_;
+  DevBuf seg_start_, seg_size_, seg_done_, cf_small_, cf_medium_, cf_large_, off_;
+  SegLists lists_a_, lists_b_;
+  DevBuf l_ioff_, l_mixed_, l_open_, l_open_off_, u_start_, u_size_, u_ioff_;
+  DevBuf k0_, k1_, v0_, v1_, sflag_, soff_, ipos_, sub_item_;
+  DevBuf next_l_start_[2], next_l_size_[2];
+
+  // profiling
+  struct EvPair {
+    hipEvent_t a, b;
+    int cls;
+  };
+  std::vector<EvPair> ev_pool_;
+  size_t ev_used_ = 0;
+};
+
+}  // namespace kb

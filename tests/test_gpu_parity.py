@@ -1,0 +1,160 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle: ids of
+every round bit-exact, block counts and rounds_done equal."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from golden_io import graph_of, load
+from gpu_util import need_gpu, gpu_rounds, oracle_rounds, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def check_parity(g, k, **kw):
+    torch, kb = need_gpu()
+    say("parity case %s N=%d E=%d k=%d %s" % (g.name, g.num_nodes, g.num_edges, k, kw))
+    hist, counts, rd = gpu_rounds(torch, kb, g, k, **kw)
+    r = oracle_rounds(g, k, early_stop=kw.get("early_stop", True))
+    assert rd == r.rounds_done, (rd, r.rounds_done)
+    assert counts == r.counts, (counts, r.counts)
+    for j, row in enumerate(hist):
+        bad = np.flatnonzero(row != r.history[j])
+        assert bad.size == 0, "round %d: %d ids differ, first at node %d (gpu %d, oracle %d)" % (
+            j, bad.size, bad[0], row[bad[0]], r.history[j][bad[0]])
+
+
+def test_worked_example():
+    check_parity(graph_of(load("figure1.json"), "figure1"), 6)
+
+
+def test_worked_example_golden_values():
+    """The GPU reproduces the hand-derived canonical ids of Figure 1 directly."""
+    torch, kb = need_gpu()
+    fx = load("figure1.json")
+    g = graph_of(fx, "figure1")
+    hist, counts, rd = gpu_rounds(torch, kb, g, 10)
+    assert counts == fx["canonical"]["counts"] and rd == fx["canonical"]["rounds_done"]
+    for j, row in enumerate(fx["canonical"]["pid"]):
+        assert hist[j].tolist() == row
+
+
+@pytest.mark.parametrize("table", ["table4", "table5"])
+def test_update_tables(table):
+    check_parity(graph_of(load("updates.json")[table], table), 4)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_small(seed):
+    rng = np.random.default_rng(1000 + seed)
+    n = int(rng.integers(1, 60))
+    e = int(rng.integers(0, 4 * n))
+    g = synth.random_small_graph(rng, n, e, int(rng.integers(1, 4)), int(rng.integers(1, 5)),
+                                 dag=seed % 3 == 0)
+    g.name = "small%d" % seed
+    check_parity(g, n + 1)
+
+
+def test_uniform_10k_50k_k5():
+    g, k = synth.make_config("uniform-10k-50k")
+    check_parity(g, k)
+
+
+def test_uniform_no_early_stop():
+    g = synth.uniform_graph(3000, 6000, num_node_labels=2, num_edge_labels=2, seed=4, name="u3k")
+    check_parity(g, 9, early_stop=False)
+
+
+def test_host_inputs():
+    g = synth.uniform_graph(2000, 9000, seed=6, name="host-inputs")
+    check_parity(g, 6, device_inputs=False)
+
+
+def test_degree_buckets():
+    """Out-degrees at every bucket edge: 0, 1, 15..17, 63..65, 4095..4097 and a
+    20k hub, among 3k low-degree nodes."""
+    degs = [0, 1, 15, 16, 17, 63, 64, 65, 4095, 4096, 4097, 20000] * 2
+    g = synth.degree_graph(degs + [2] * 3000, num_node_labels=2, num_edge_labels=3, seed=3,
+                           name="degrees")
+    check_parity(g, 6)
+
+
+def test_powerlaw_mid():
+    """Power-law graph with hubs and large blocks (global passes)."""
+    g = synth.powerlaw_graph(200_000, 2_000_000, seed=7, deg_cap=30_000, name="powerlaw-200k")
+    check_parity(g, 10)
+
+
+@pytest.mark.parametrize("bits", [1, 4])
+def test_hash_collisions(bits):
+    """Hash cut to a few bits: equal hashes are verified, so ids are unchanged."""
+    g = synth.powerlaw_graph(20_000, 150_000, seed=9, deg_cap=5_000, num_node_labels=3,
+                             num_edge_labels=2, name="collide")
+    check_parity(g, 8, hash_bits=bits)
+
+
+def test_identical_hubs():
+    """Two hubs with identical long signatures and two that differ only at
+    their last key: long verification and a deep split."""
+    rng = np.random.default_rng(5)
+    n = 12_000
+    base = rng.integers(100, n, size=9000)
+    src, dst = [], []
+    for h in range(4):
+        d = base.copy()
+        if h == 3:
+            d[-1] = 0  # node 0 is unique-labelled: last key differs
+        src.append(np.full(d.shape[0], h))
+        dst.append(d)
+    src.append(rng.integers(100, n, size=20000))
+    dst.append(rng.integers(0, n, size=20000))
+    src = np.concatenate(src).astype(np.int32)
+    dst = np.concatenate(dst).astype(np.int32)
+    lab = np.zeros(n, np.int32)
+    lab[0] = 1
+    g = synth.Graph(n, lab, src, np.zeros(src.shape[0], np.int32), dst, name="hubs")
+    check_parity(g, 6)
+
+
+def test_empty_and_trivial():
+    torch, kb = need_gpu()
+    z = np.zeros(0, np.int32)
+    pid, counts, rd = kb.refine(0, z, z, z, z, 3)
+    assert pid.size == 0 and counts == [0, 0] and rd == 1
+    g = synth.Graph(5, np.array([3, 1, 3, 0, 1], np.int32), z, z, z, name="noedges")
+    check_parity(g, 4)
+    check_parity(synth.worked_example(), 0)
+
+
+def test_resume_and_idempotent():
+    torch, kb = need_gpu()
+    g = synth.uniform_graph(5000, 20000, seed=12)
+    r = oracle.refine(g.num_nodes, g.node_label, g.src, g.elab, g.dst, 4)
+    with kb.Graph(g.num_nodes, *to_dev(torch, g)) as h:
+        h.refine(2)
+        h.refine(1)  # below the rounds done: no-op
+        assert h.refine(4) == r.rounds_done
+        pid, nb, counts = h.result()
+        assert np.array_equal(pid, r.pid) and counts == r.counts
+        out = torch.empty(g.num_nodes, dtype=torch.int32, device="cuda:0")
+        pid_d, _, _ = h.result(device="cuda:0")
+        assert np.array_equal(pid_d.cpu().numpy(), r.pid)
+
+
+def test_invalid_inputs():
+    torch, kb = need_gpu()
+    g = synth.worked_example()
+    bad = g.dst.copy()
+    bad[0] = 6
+    with pytest.raises(kb.KbisimError) as e:
+        kb.Graph(6, g.node_label, g.src, g.elab, bad)
+    assert e.value.status == -1
+    lab = g.node_label.copy()
+    lab[2] = -3
+    with pytest.raises(kb.KbisimError) as e:
+        kb.Graph(6, lab, g.src, g.elab, g.dst)
+    assert e.value.status == -1
+    with kb.Graph(6, g.node_label, g.src, g.elab, g.dst) as h:
+        with pytest.raises(kb.KbisimError):
+            h.refine(-1)
+        assert h.refine(2) == 2  # the handle still works after an error
