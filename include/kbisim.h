@@ -72,9 +72,12 @@ typedef struct {
 
 typedef struct {
   int32_t early_stop; /* 1 (default): stop at the first round with B_i == B_{i-1} */
-  int32_t hash_bits;  /* 1..64 (default 64): bits kept of the signature hash; fewer bits
-                         only cost time (equal hashes are always verified key by key) */
-  int32_t profile;    /* 1: time each kernel class with HIP events (kbisim_profile) */
+  int32_t profile;    /* 1: time each kernel class with HIP events (kbisim_profile) and
+                         count the work of the signature kernels (kbisim_work) */
+  int32_t medium_cap; /* tuning: blocks of 65..medium_cap members are ordered by one
+                         workgroup in LDS, larger ones by global radix passes; 64..2048,
+                         values <= 64 send every block above 64 members to the global
+                         passes; 0 = library default. Ids do not depend on it. */
 } kbisim_options;
 
 /* Fills *opt with the defaults above. */
@@ -119,6 +122,12 @@ typedef enum {
  * (reset != 0 clears after reading). cap = entries of ms/launches. */
 kbisim_status kbisim_profile(const kbisim_graph* g, double* ms, int64_t* launches, int32_t cap,
                              int32_t reset);
+
+/* Work done by the signature kernels when options.profile = 1, summed over
+ * rounds: nodes_edges[2c] = nodes processed by bucket c (KBISIM_PROF_SIG_*,
+ * c = 0..3) and nodes_edges[2c+1] = their out-edges. Nodes alone in their
+ * block are skipped by every bucket and not counted. cap = entries (8). */
+kbisim_status kbisim_work(const kbisim_graph* g, int64_t* nodes_edges, int32_t cap, int32_t reset);
 
 /* Frees everything owned by the handle. NULL is ignored. */
 void kbisim_destroy(kbisim_graph* g);

@@ -31,8 +31,8 @@ class GraphDesc(ctypes.Structure):
 
 
 class Options(ctypes.Structure):
-    _fields_ = [("early_stop", ctypes.c_int32), ("hash_bits", ctypes.c_int32),
-                ("profile", ctypes.c_int32)]
+    _fields_ = [("early_stop", ctypes.c_int32), ("profile", ctypes.c_int32),
+                ("medium_cap", ctypes.c_int32)]
 
 
 _lib = None
@@ -62,6 +62,8 @@ def load_library():
     lib.kbisim_result.restype = ctypes.c_int
     lib.kbisim_profile.argtypes = [vp, vp, vp, i32, i32]
     lib.kbisim_profile.restype = ctypes.c_int
+    lib.kbisim_work.argtypes = [vp, vp, i32, i32]
+    lib.kbisim_work.restype = ctypes.c_int
     lib.kbisim_destroy.argtypes = [vp]
     lib.kbisim_destroy.restype = None
     lib.kbisim_status_str.argtypes = [ctypes.c_int]
@@ -120,7 +122,7 @@ def _arrays(node_label, src, elab, dst):
 
 
 def kbisim_create(num_nodes, node_label, src, elab, dst, *, stream=None, early_stop=True,
-                  hash_bits=64, profile=False):
+                  profile=False, medium_cap=None):
     """Creates a device-resident graph handle (see kbisim.h). Returns the handle."""
     lib = load_library()
     mem, ptrs, keep = _arrays(node_label, src, elab, dst)
@@ -132,8 +134,9 @@ def kbisim_create(num_nodes, node_label, src, elab, dst, *, stream=None, early_s
     opt = Options()
     lib.kbisim_options_default(ctypes.byref(opt))
     opt.early_stop = 1 if early_stop else 0
-    opt.hash_bits = int(hash_bits)
     opt.profile = 1 if profile else 0
+    if medium_cap is not None:
+        opt.medium_cap = int(medium_cap)
     h = ctypes.c_void_p()
     _check(lib.kbisim_create(ctypes.byref(desc), ctypes.byref(opt), ctypes.byref(h)))
     return h
@@ -172,6 +175,13 @@ def kbisim_profile(handle, reset=False):
     return {c: (float(ms[i]), int(cnt[i])) for i, c in enumerate(PROF_CLASSES)}
 
 
+def kbisim_work(handle, reset=False):
+    """Per signature bucket: (active nodes, their edges), summed over rounds."""
+    w = np.zeros(8, np.int64)
+    _check(load_library().kbisim_work(handle, w.ctypes.data, 8, 1 if reset else 0))
+    return {PROF_CLASSES[c]: (int(w[2 * c]), int(w[2 * c + 1])) for c in range(4)}
+
+
 def kbisim_destroy(handle):
     if handle:
         load_library().kbisim_destroy(handle)
@@ -203,6 +213,9 @@ class Graph:
 
     def profile(self, reset=False):
         return kbisim_profile(self._h, reset)
+
+    def work(self, reset=False):
+        return kbisim_work(self._h, reset)
 
     def close(self):
         if self._h:

@@ -63,10 +63,12 @@ struct HostWords {
   HostWords& operator=(const HostWords&) = delete;
 };
 
+constexpr uint32_t kDefaultMediumCap = 512;
+
 struct Options {
   bool early_stop = true;
-  int hash_bits = 64;
   bool profile = false;
+  uint32_t medium_cap = kDefaultMediumCap;  // groups above this size use the global pass
 };
 
 constexpr int kProfClasses = 7;
@@ -74,7 +76,7 @@ constexpr int kProfClasses = 7;
 // Segment lists produced by classification: small (one wave), medium (one
 // workgroup), large (global passes).
 struct SegLists {
-  DevBuf s_start, s_size, m_start, m_size, l_start, l_size;
+  DevBuf s_start, s_size, s_depth, m_start, m_size, m_depth, l_start, l_size, l_depth;
   uint32_t ns = 0, nm = 0, nl = 0;
 };
 
@@ -96,6 +98,9 @@ class Engine {
   bool fixed() const { return fixed_; }
   std::array<double, kProfClasses> prof_ms{};
   std::array<int64_t, kProfClasses> prof_n{};
+  // per signature bucket: active nodes and their edges, summed over rounds
+  void work_counts(uint64_t* out8);
+  void reset_work();
   int adj_bytes() const { return adj64_ ? 8 : 4; }
   int key_bytes() const { return key64_ ? 8 : 4; }
   uint32_t num_edge_labels() const { return n_elab_; }
@@ -108,9 +113,9 @@ class Engine {
   template <typename KeyT>
   void order_groups(int key_bits, const void* kv);
   template <typename KeyT>
-  void resolve_lists(SegLists& L, const void* kv, uint32_t d0);
-  void make_lists(const uint32_t* seg_start, const uint32_t* seg_size, const uint8_t* seg_done,
-                  uint32_t nseg, SegLists& out);
+  void resolve_lists(SegLists& L, const void* kv);
+  void make_lists(const uint32_t* seg_start, const uint32_t* seg_size, const uint32_t* seg_depth,
+                  const uint8_t* seg_done, uint32_t nseg, SegLists& out);
   void run_round();
   void assign_ids_into(int32_t* pid_out);
   uint64_t read_word(const void* dev, int bytes);
@@ -118,8 +123,8 @@ class Engine {
   void scan_dev(const Tin* in, Tout* out, uint64_t n);
   uint32_t* radix_scratch(uint64_t n);
 
-  void ev_begin(int cls);
-  void ev_end(int cls);
+  int ev_begin(int cls);  // returns a slot for ev_end, or -1 when not profiling
+  void ev_end(int slot);
   void ev_collect();
 
   int64_t n_, m_;
@@ -142,12 +147,12 @@ class Engine {
   bool fixed_ = false;
   std::vector<int64_t> counts_;
   // round scratch
-  DevBuf ukey_, ucnt_, hsh_, cls_, scanpart_, radix_;
-  DevBuf seg_start_, seg_size_, seg_done_, cf_small_, cf_medium_, cf_large_, off_;
+  DevBuf ukey_, ucnt_, cls_, scanpart_, radix_;
+  DevBuf seg_start_, seg_size_, seg_depth_, seg_done_, cf_small_, cf_medium_, cf_large_, off_;
   SegLists lists_a_, lists_b_;
-  DevBuf l_ioff_, l_mixed_, l_open_, l_open_off_, u_start_, u_size_, u_ioff_;
+  DevBuf l_ioff_, l_split_, l_long_, l_open_, l_open_off_, u_start_, u_size_, u_pos_, u_ioff_;
   DevBuf k0_, k1_, v0_, v1_, sflag_, soff_, ipos_, sub_item_;
-  DevBuf next_l_start_[2], next_l_size_[2];
+  DevBuf next_l_start_[2], next_l_size_[2], next_l_depth_[2];
 
   // profiling
   struct EvPair {
@@ -155,6 +160,7 @@ class Engine {
     int cls;
   };
   std::vector<EvPair> ev_pool_;
+  DevBuf work_;
   size_t ev_used_ = 0;
 };
 

@@ -1,7 +1,7 @@
 // k-bisimulation on one MI355X: host round driver and the C ABI (kbisim.h).
 //
 // Per round (Algorithm 1, one iteration j > 0):
-//   signature kernels  -- join with pId_{j-1}(dst), per-node sort + unique + hash
+//   signature kernels  -- join with pId_{j-1}(dst), per-node sort + unique
 //   order_groups       -- order the signatures inside every block of pId_{j-1}
 //   assign_ids         -- scan of class starts -> pId_j, block starts, B_j
 // The graph (CSR by source, packed label|dst words) stays in device memory.
@@ -58,23 +58,23 @@ uint32_t* Engine::radix_scratch(uint64_t n) {
   return radix_.as<uint32_t>();
 }
 
-void Engine::ev_begin(int cls) {
-  if (!opt_.profile) return;
+int Engine::ev_begin(int cls) {
+  if (!opt_.profile) return -1;
   if (ev_used_ == ev_pool_.size()) {
     EvPair e;
     KB_CHECK(hipEventCreate(&e.a));
     KB_CHECK(hipEventCreate(&e.b));
     ev_pool_.push_back(e);
   }
-  ev_pool_[ev_used_].cls = cls;
-  KB_CHECK(hipEventRecord(ev_pool_[ev_used_].a, st_));
+  const int slot = int(ev_used_++);
+  ev_pool_[slot].cls = cls;
+  KB_CHECK(hipEventRecord(ev_pool_[slot].a, st_));
+  return slot;
 }
 
-void Engine::ev_end(int cls) {
-  if (!opt_.profile) return;
-  (void)cls;
-  KB_CHECK(hipEventRecord(ev_pool_[ev_used_].b, st_));
-  ++ev_used_;
+void Engine::ev_end(int slot) {
+  if (slot < 0) return;
+  KB_CHECK(hipEventRecord(ev_pool_[size_t(slot)].b, st_));
 }
 
 void Engine::ev_collect() {
@@ -125,10 +125,10 @@ void Engine::build_adj(const int32_t* src, const uint32_t* erank, const int32_t*
     scan_dev<uint32_t, uint32_t, false>(fw.as<uint32_t>(), ow.as<uint32_t>(), N + 1);
     scan_dev<uint32_t, uint32_t, false>(fb.as<uint32_t>(), ob.as<uint32_t>(), N + 1);
     scan_dev<uint32_t, uint32_t, false>(fh.as<uint32_t>(), oh.as<uint32_t>(), N + 1);
+    hw_.p[1] = hw_.p[2] = hw_.p[3] = 0;  // before the copies are queued
     KB_CHECK(hipMemcpyAsync(&hw_.p[1], ow.as<uint32_t>() + N, 4, hipMemcpyDeviceToHost, st_));
     KB_CHECK(hipMemcpyAsync(&hw_.p[2], ob.as<uint32_t>() + N, 4, hipMemcpyDeviceToHost, st_));
     KB_CHECK(hipMemcpyAsync(&hw_.p[3], oh.as<uint32_t>() + N, 4, hipMemcpyDeviceToHost, st_));
-    hw_.p[1] = hw_.p[2] = hw_.p[3] = 0;
     KB_CHECK(hipStreamSynchronize(st_));
     nw_ = uint32_t(hw_.p[1]);
     nb_ = uint32_t(hw_.p[2]);
@@ -245,7 +245,6 @@ void Engine::build(const int32_t* node_label, const int32_t* src, const int32_t*
   // per-round buffers
   ukey_.ensure(std::max<uint64_t>(E, 1) * (key64_ ? 8 : 4));
   ucnt_.ensure(std::max<uint64_t>(N, 1) * 4);
-  hsh_.ensure(std::max<uint64_t>(N, 1) * 8);
   KB_CHECK(hipStreamSynchronize(st_));
 }
 
@@ -271,16 +270,19 @@ void Engine::assign_ids_into(int32_t* pid_out) {
 // ---------------------------------------------------------------------------
 // Group ordering.
 
-void Engine::make_lists(const uint32_t* seg_start, const uint32_t* seg_size, const uint8_t* seg_done,
-                        uint32_t nseg, SegLists& out) {
+void Engine::make_lists(const uint32_t* seg_start, const uint32_t* seg_size, const uint32_t* seg_depth,
+                        const uint8_t* seg_done, uint32_t nseg, SegLists& out) {
   out.ns = out.nm = out.nl = 0;
   if (nseg == 0) return;
   const uint64_t n1 = uint64_t(nseg) + 1;
   for (DevBuf* b : {&cf_small_, &cf_medium_, &cf_large_}) b->ensure(n1 * 4);
   off_.ensure(3 * n1 * 4);
-  classify_segments_k<<<grid_for(n1), kNT, 0, st_>>>(seg_size, seg_done, nseg, cf_small_.as<uint32_t>(),
-                                                     cf_medium_.as<uint32_t>(), cf_large_.as<uint32_t>());
+  classify_segments_k<<<grid_for(nseg), kNT, 0, st_>>>(seg_size, seg_done, nseg, opt_.medium_cap,
+                                                       cf_small_.as<uint32_t>(),
+                                                       cf_medium_.as<uint32_t>(), cf_large_.as<uint32_t>());
   KB_LAUNCH_CHECK();
+  // exclusive scans over nseg + 1 entries: entry nseg is the list length
+  // (the flag at index nseg is never read into it)
   uint32_t* o = off_.as<uint32_t>();
   scan_dev<uint32_t, uint32_t, false>(cf_small_.as<uint32_t>(), o, n1);
   scan_dev<uint32_t, uint32_t, false>(cf_medium_.as<uint32_t>(), o + n1, n1);
@@ -295,34 +297,38 @@ void Engine::make_lists(const uint32_t* seg_start, const uint32_t* seg_size, con
   out.nm = hw32[1];
   out.nl = hw32[2];
   struct {
-    DevBuf *st, *sz;
+    DevBuf *st, *sz, *dp;
     uint32_t cnt;
     const uint32_t* f;
     const uint32_t* off;
-  } parts[3] = {{&out.s_start, &out.s_size, out.ns, cf_small_.as<uint32_t>(), o},
-                {&out.m_start, &out.m_size, out.nm, cf_medium_.as<uint32_t>(), o + n1},
-                {&out.l_start, &out.l_size, out.nl, cf_large_.as<uint32_t>(), o + 2 * n1}};
+  } parts[3] = {{&out.s_start, &out.s_size, &out.s_depth, out.ns, cf_small_.as<uint32_t>(), o},
+                {&out.m_start, &out.m_size, &out.m_depth, out.nm, cf_medium_.as<uint32_t>(), o + n1},
+                {&out.l_start, &out.l_size, &out.l_depth, out.nl, cf_large_.as<uint32_t>(), o + 2 * n1}};
   for (auto& pp : parts) {
     if (!pp.cnt) continue;
     pp.st->ensure(uint64_t(pp.cnt) * 4);
     pp.sz->ensure(uint64_t(pp.cnt) * 4);
-    scatter_segments_k<<<grid_for(nseg), kNT, 0, st_>>>(seg_start, seg_size, nseg, pp.f, pp.off,
-                                                        pp.st->as<uint32_t>(), pp.sz->as<uint32_t>());
+    pp.dp->ensure(uint64_t(pp.cnt) * 4);
+    scatter_segments_k<<<grid_for(nseg), kNT, 0, st_>>>(seg_start, seg_size, seg_depth, nseg, pp.f, pp.off,
+                                                        pp.st->as<uint32_t>(), pp.sz->as<uint32_t>(),
+                                                        pp.dp->as<uint32_t>());
     KB_LAUNCH_CHECK();
   }
 }
 
 template <typename KeyT>
-void Engine::resolve_lists(SegLists& L, const void* kvp, uint32_t d0) {
+void Engine::resolve_lists(SegLists& L, const void* kvp) {
   const KeyView<KeyT>& kv = *static_cast<const KeyView<KeyT>*>(kvp);
   if (L.ns) {
-    resolve_k<64, kSmallCap, KeyT><<<L.ns, 64, 0, st_>>>(L.s_start.as<uint32_t>(), L.s_size.as<uint32_t>(), d0,
-                                                        ord_.as<uint32_t>(), flag_.as<uint8_t>(), kv);
+    resolve_k<64, kSmallCap, KeyT><<<L.ns, 64, 0, st_>>>(L.s_start.as<uint32_t>(), L.s_size.as<uint32_t>(),
+                                                        L.s_depth.as<uint32_t>(), ord_.as<uint32_t>(),
+                                                        flag_.as<uint8_t>(), kv);
     KB_LAUNCH_CHECK();
   }
   if (L.nm) {
     resolve_k<kMediumNT, kMediumCap, KeyT><<<L.nm, kMediumNT, 0, st_>>>(
-        L.m_start.as<uint32_t>(), L.m_size.as<uint32_t>(), d0, ord_.as<uint32_t>(), flag_.as<uint8_t>(), kv);
+        L.m_start.as<uint32_t>(), L.m_size.as<uint32_t>(), L.m_depth.as<uint32_t>(), ord_.as<uint32_t>(),
+        flag_.as<uint8_t>(), kv);
     KB_LAUNCH_CHECK();
   }
 }
@@ -333,62 +339,74 @@ void Engine::order_groups(int key_bits, const void* kvp) {
   const uint32_t B = uint32_t(B_);
   seg_start_.ensure(uint64_t(B) * 4 + 4);
   seg_size_.ensure(uint64_t(B) * 4 + 4);
+  seg_depth_.ensure(uint64_t(B) * 4 + 4);
   seg_done_.ensure(uint64_t(B) + 1);
   blocks_as_segments_k<<<grid_for(B), kNT, 0, st_>>>(bstart_.as<uint32_t>(), B, seg_start_.as<uint32_t>(),
-                                                     seg_size_.as<uint32_t>(), seg_done_.as<uint8_t>());
+                                                     seg_size_.as<uint32_t>(), seg_depth_.as<uint32_t>(),
+                                                     seg_done_.as<uint8_t>());
   KB_LAUNCH_CHECK();
-  make_lists(seg_start_.as<uint32_t>(), seg_size_.as<uint32_t>(), seg_done_.as<uint8_t>(), B, lists_a_);
-  resolve_lists<KeyT>(lists_a_, kvp, 0);
+  make_lists(seg_start_.as<uint32_t>(), seg_size_.as<uint32_t>(), seg_depth_.as<uint32_t>(),
+             seg_done_.as<uint8_t>(), B, lists_a_);
+  resolve_lists<KeyT>(lists_a_, kvp);
 
-  // Large groups: global most-significant-digit passes.
+  // Large groups: global passes, each splitting every open group.
   const uint32_t* Ls = lists_a_.l_start.as<uint32_t>();
   const uint32_t* Lz = lists_a_.l_size.as<uint32_t>();
+  const uint32_t* Ld = lists_a_.l_depth.as<uint32_t>();
   uint32_t nl = lists_a_.nl;
   int nx = 0;
-  const int dig_bits = key_bits + 1;
-  for (uint32_t t = 0; nl > 0; ++t) {
-    // items of the large groups and their offsets
+  const int dbits = key_bits + 1;
+  const uint64_t last_mask = dbits >= 64 ? ~0ull : ((1ull << dbits) - 1);
+  while (nl > 0) {
+    // item offsets of the large groups (sizes with a trailing zero)
     l_ioff_.ensure((uint64_t(nl) + 1) * 4);
-    {
-      DevBuf& tmp = l_open_;  // sizes with a trailing zero
-      tmp.ensure((uint64_t(nl) + 1) * 4);
-      KB_CHECK(hipMemcpyAsync(tmp.p, Lz, uint64_t(nl) * 4, hipMemcpyDeviceToDevice, st_));
-      KB_CHECK(hipMemsetAsync(tmp.as<uint32_t>() + nl, 0, 4, st_));
-      scan_dev<uint32_t, uint32_t, false>(tmp.as<uint32_t>(), l_ioff_.as<uint32_t>(), uint64_t(nl) + 1);
-    }
-    const uint32_t M = uint32_t(read_word(l_ioff_.as<uint32_t>() + nl, 4));
-    l_mixed_.ensure(nl);
-    KB_CHECK(hipMemsetAsync(l_mixed_.p, 0, nl, st_));
-    large_mixed_k<KeyT><<<grid_for(M), kNT, 0, st_>>>(Ls, l_ioff_.as<uint32_t>(), nl, M, ord_.as<uint32_t>(),
-                                                     l_mixed_.as<uint8_t>(), kv);
-    large_verify_k<KeyT><<<grid_for(M), kNT, 0, st_>>>(Ls, l_ioff_.as<uint32_t>(), nl, M, ord_.as<uint32_t>(),
-                                                      l_mixed_.as<uint8_t>(), t, kv);
-    KB_LAUNCH_CHECK();
     l_open_.ensure((uint64_t(nl) + 1) * 4);
-    l_open_off_.ensure((uint64_t(nl) + 1) * 4);
+    KB_CHECK(hipMemcpyAsync(l_open_.p, Lz, uint64_t(nl) * 4, hipMemcpyDeviceToDevice, st_));
     KB_CHECK(hipMemsetAsync(l_open_.as<uint32_t>() + nl, 0, 4, st_));
-    u8_to_u32_k<<<grid_for(nl), kNT, 0, st_>>>(l_mixed_.as<uint8_t>(), l_open_.as<uint32_t>(), nl);
+    scan_dev<uint32_t, uint32_t, false>(l_open_.as<uint32_t>(), l_ioff_.as<uint32_t>(), uint64_t(nl) + 1);
+    const uint32_t M = uint32_t(read_word(l_ioff_.as<uint32_t>() + nl, 4));
+    // split position of every group (kNoDiff: all members identical)
+    l_split_.ensure(uint64_t(nl) * 4);
+    KB_CHECK(hipMemsetAsync(l_split_.p, 0xff, uint64_t(nl) * 4, st_));
+    l_long_.ensure((uint64_t(M) + 1) * 4);
+    KB_CHECK(hipMemsetAsync(l_long_.as<uint32_t>() + M, 0, 4, st_));
+    large_split_pos_k<KeyT><<<grid_for(M), kNT, 0, st_>>>(Ls, Ld, l_ioff_.as<uint32_t>(), nl, M,
+                                                         ord_.as<uint32_t>(), l_split_.as<uint32_t>(),
+                                                         l_long_.as<uint32_t>(), l_long_.as<uint32_t>() + M, kv);
     KB_LAUNCH_CHECK();
+    large_split_pos_wave_k<KeyT><<<std::min<uint32_t>(grid_for(uint64_t(M) * kWave), 4096), kNT, 0, st_>>>(
+        Ls, Ld, l_ioff_.as<uint32_t>(), nl, ord_.as<uint32_t>(), l_split_.as<uint32_t>(), l_long_.as<uint32_t>(),
+        l_long_.as<uint32_t>() + M, kv);
+    KB_LAUNCH_CHECK();
+    l_open_off_.ensure((uint64_t(nl) + 1) * 4);
+    open_flags_k<<<grid_for(nl), kNT, 0, st_>>>(l_split_.as<uint32_t>(), nl, l_open_.as<uint32_t>());
+    KB_LAUNCH_CHECK();
+    KB_CHECK(hipMemsetAsync(l_open_.as<uint32_t>() + nl, 0, 4, st_));
     scan_dev<uint32_t, uint32_t, false>(l_open_.as<uint32_t>(), l_open_off_.as<uint32_t>(), uint64_t(nl) + 1);
     const uint32_t nU = uint32_t(read_word(l_open_off_.as<uint32_t>() + nl, 4));
     if (nU == 0) break;
     u_start_.ensure(uint64_t(nU) * 4);
     u_size_.ensure((uint64_t(nU) + 1) * 4);
-    scatter_segments_k<<<grid_for(nl), kNT, 0, st_>>>(Ls, Lz, nl, l_open_.as<uint32_t>(),
+    u_pos_.ensure(uint64_t(nU) * 4);
+    scatter_segments_k<<<grid_for(nl), kNT, 0, st_>>>(Ls, Lz, l_split_.as<uint32_t>(), nl, l_open_.as<uint32_t>(),
                                                       l_open_off_.as<uint32_t>(), u_start_.as<uint32_t>(),
-                                                      u_size_.as<uint32_t>());
+                                                      u_size_.as<uint32_t>(), u_pos_.as<uint32_t>());
     KB_LAUNCH_CHECK();
     KB_CHECK(hipMemsetAsync(u_size_.as<uint32_t>() + nU, 0, 4, st_));
     u_ioff_.ensure((uint64_t(nU) + 1) * 4);
     scan_dev<uint32_t, uint32_t, false>(u_size_.as<uint32_t>(), u_ioff_.as<uint32_t>(), uint64_t(nU) + 1);
     const uint32_t MU = uint32_t(read_word(u_ioff_.as<uint32_t>() + nU, 4));
 
-    // chunks of groups whose index fits beside the digit in 64 bits
+    // positions per sort digit and chunks of groups whose index fits beside
+    // the packed digits in 64 bits
+    const int need_g = nU > 1 ? bits_for(nU - 1) : 0;
+    uint32_t width = uint32_t(std::max(1, (64 - need_g) / dbits));
+    const int dig_bits = int(width) * dbits;
     const int gb = 64 - dig_bits;
-    const uint32_t chunk = gb >= 32 ? nU : std::max<uint32_t>(1, std::min<uint32_t>(nU, 1u << gb));
+    const uint32_t chunk = gb >= 32 ? nU : std::max<uint32_t>(1, std::min<uint32_t>(nU, 1u << std::max(gb, 0)));
     const int nxt = nx ^ 1;
-    next_l_start_[nxt].ensure(uint64_t(MU / kMediumCap + 1) * 4);
-    next_l_size_[nxt].ensure(uint64_t(MU / kMediumCap + 1) * 4);
+    for (DevBuf* b : {&next_l_start_[nxt], &next_l_size_[nxt], &next_l_depth_[nxt]})
+      b->ensure(uint64_t(MU / (std::max(opt_.medium_cap, kSmallCap) + 1) + 1) * 4);
     uint32_t nnext = 0;
     for (uint32_t c0 = 0; c0 < nU; c0 += chunk) {
       const uint32_t cn = std::min(chunk, nU - c0);
@@ -396,46 +414,52 @@ void Engine::order_groups(int key_bits, const void* kvp) {
       const uint32_t I1 = (c0 + cn == nU) ? MU : uint32_t(read_word(u_ioff_.as<uint32_t>() + c0 + cn, 4));
       const uint32_t cnt = I1 - I0;
       const uint32_t* gst = u_start_.as<uint32_t>() + c0;
+      const uint32_t* gps = u_pos_.as<uint32_t>() + c0;
       const uint32_t* gio = u_ioff_.as<uint32_t>() + c0;
       for (DevBuf* b : {&k0_, &k1_}) b->ensure(uint64_t(cnt) * 8);
       for (DevBuf* b : {&v0_, &v1_, &ipos_, &sub_item_}) b->ensure(uint64_t(cnt) * 4);
       for (DevBuf* b : {&sflag_, &soff_}) b->ensure((uint64_t(cnt) + 1) * 4);
-      large_gather_k<KeyT><<<grid_for(cnt), kNT, 0, st_>>>(gst, gio, cn, cnt, I0, ord_.as<uint32_t>(), t,
-                                                          dig_bits, k0_.as<uint64_t>(), v0_.as<uint32_t>(), kv);
+      large_gather_k<KeyT><<<grid_for(cnt), kNT, 0, st_>>>(gst, gps, gio, cn, cnt, I0, ord_.as<uint32_t>(), dig_bits,
+                                                          width, k0_.as<uint64_t>(), v0_.as<uint32_t>(), kv);
       KB_LAUNCH_CHECK();
       const int g_bits = cn > 1 ? bits_for(cn - 1) : 0;
       const bool f = radix_sort<uint64_t>(k0_.as<uint64_t>(), v0_.as<uint32_t>(), k1_.as<uint64_t>(),
                                           v1_.as<uint32_t>(), cnt, 0, dig_bits + g_bits, radix_scratch(cnt), st_);
       const uint64_t* K = f ? k1_.as<uint64_t>() : k0_.as<uint64_t>();
       const uint32_t* V = f ? v1_.as<uint32_t>() : v0_.as<uint32_t>();
-      large_split_k<<<grid_for(cnt), kNT, 0, st_>>>(gst, gio, cn, cnt, I0, K, V, dig_bits, ord_.as<uint32_t>(),
-                                                    flag_.as<uint8_t>(), sflag_.as<uint32_t>(),
-                                                    ipos_.as<uint32_t>());
+      large_write_k<<<grid_for(cnt), kNT, 0, st_>>>(gst, gio, cnt, I0, K, V, dig_bits, ord_.as<uint32_t>(),
+                                                    flag_.as<uint8_t>(), sflag_.as<uint32_t>(), ipos_.as<uint32_t>());
       KB_LAUNCH_CHECK();
       KB_CHECK(hipMemsetAsync(sflag_.as<uint32_t>() + cnt, 0, 4, st_));
       scan_dev<uint32_t, uint32_t, false>(sflag_.as<uint32_t>(), soff_.as<uint32_t>(), uint64_t(cnt) + 1);
       const uint32_t ns = uint32_t(read_word(soff_.as<uint32_t>() + cnt, 4));
       seg_start_.ensure(uint64_t(ns) * 4 + 4);
       seg_size_.ensure(uint64_t(ns) * 4 + 4);
+      seg_depth_.ensure(uint64_t(ns) * 4 + 4);
       seg_done_.ensure(uint64_t(ns) + 1);
-      const uint64_t dig_mask = dig_bits >= 64 ? ~0ull : ((1ull << dig_bits) - 1);
       large_subgroups_k<<<grid_for(cnt), kNT, 0, st_>>>(sflag_.as<uint32_t>(), soff_.as<uint32_t>(), cnt,
-                                                        ipos_.as<uint32_t>(), K, dig_mask, sub_item_.as<uint32_t>(),
-                                                        seg_start_.as<uint32_t>(), seg_done_.as<uint8_t>());
+                                                        ipos_.as<uint32_t>(), K, dig_bits, width, last_mask, gps,
+                                                        sub_item_.as<uint32_t>(), seg_start_.as<uint32_t>(),
+                                                        seg_depth_.as<uint32_t>(), seg_done_.as<uint8_t>());
       subgroup_sizes_k<<<grid_for(ns), kNT, 0, st_>>>(sub_item_.as<uint32_t>(), ns, cnt, seg_size_.as<uint32_t>());
       KB_LAUNCH_CHECK();
-      make_lists(seg_start_.as<uint32_t>(), seg_size_.as<uint32_t>(), seg_done_.as<uint8_t>(), ns, lists_b_);
-      resolve_lists<KeyT>(lists_b_, kvp, t + 1);
+      make_lists(seg_start_.as<uint32_t>(), seg_size_.as<uint32_t>(), seg_depth_.as<uint32_t>(),
+                 seg_done_.as<uint8_t>(), ns, lists_b_);
+      resolve_lists<KeyT>(lists_b_, kvp);
       if (lists_b_.nl) {
-        KB_CHECK(hipMemcpyAsync(next_l_start_[nxt].as<uint32_t>() + nnext, lists_b_.l_start.p,
-                                uint64_t(lists_b_.nl) * 4, hipMemcpyDeviceToDevice, st_));
-        KB_CHECK(hipMemcpyAsync(next_l_size_[nxt].as<uint32_t>() + nnext, lists_b_.l_size.p,
-                                uint64_t(lists_b_.nl) * 4, hipMemcpyDeviceToDevice, st_));
+        const uint64_t bytes = uint64_t(lists_b_.nl) * 4;
+        KB_CHECK(hipMemcpyAsync(next_l_start_[nxt].as<uint32_t>() + nnext, lists_b_.l_start.p, bytes,
+                                hipMemcpyDeviceToDevice, st_));
+        KB_CHECK(hipMemcpyAsync(next_l_size_[nxt].as<uint32_t>() + nnext, lists_b_.l_size.p, bytes,
+                                hipMemcpyDeviceToDevice, st_));
+        KB_CHECK(hipMemcpyAsync(next_l_depth_[nxt].as<uint32_t>() + nnext, lists_b_.l_depth.p, bytes,
+                                hipMemcpyDeviceToDevice, st_));
         nnext += lists_b_.nl;
       }
     }
     Ls = next_l_start_[nxt].as<uint32_t>();
     Lz = next_l_size_[nxt].as<uint32_t>();
+    Ld = next_l_depth_[nxt].as<uint32_t>();
     nl = nnext;
     nx = nxt;
   }
@@ -453,44 +477,50 @@ void Engine::round_impl() {
   a.bstart = bstart_.as<uint32_t>();
   a.ukey = ukey_.as<KeyT>();
   a.ucnt = ucnt_.as<uint32_t>();
-  a.hsh = hsh_.as<uint64_t>();
-  a.hash_mask = opt_.hash_bits >= 64 ? ~0ull : ((1ull << opt_.hash_bits) - 1);
   a.dst_bits = dst_bits_;
   a.pid_bits = pid_bits;
+  if (opt_.profile) {
+    if (!work_.p) {
+      work_.ensure(8 * sizeof(unsigned long long));
+      KB_CHECK(hipMemsetAsync(work_.p, 0, 8 * sizeof(unsigned long long), st_));
+    }
+    work_count_k<<<grid_for(N), kNT, 0, st_>>>(a.rowptr, a.pid, a.bstart, N, work_.as<unsigned long long>());
+    KB_LAUNCH_CHECK();
+  }
 
-  ev_begin(0);
+  int ev = ev_begin(0);
   sig_thread_k<AdjT, KeyT><<<grid_for(N), kNT, 0, st_>>>(a, N);
   KB_LAUNCH_CHECK();
-  ev_end(0);
+  ev_end(ev);
   if (nw_) {
-    ev_begin(1);
+    ev = ev_begin(1);
     sig_wave_k<AdjT, KeyT><<<grid_for(uint64_t(nw_) * kWave), kNT, 0, st_>>>(a, wlist_.as<uint32_t>(), nw_);
     KB_LAUNCH_CHECK();
-    ev_end(1);
+    ev_end(ev);
   }
   if (nb_) {
-    ev_begin(2);
+    ev = ev_begin(2);
     sig_block_k<AdjT, KeyT><<<nb_, kSigBlockNT, 0, st_>>>(a, blist_.as<uint32_t>(), nb_);
     KB_LAUNCH_CHECK();
-    ev_end(2);
+    ev_end(ev);
   }
   if (nh_) {
-    ev_begin(3);
+    ev = ev_begin(3);
     sig_hub_k<AdjT, KeyT><<<nh_, kHubNT, 0, st_>>>(a, hlist_.as<uint32_t>(), hub_off_.as<uint32_t>(),
                                                    hub_tmp_.as<KeyT>(), key_bits);
     KB_LAUNCH_CHECK();
-    ev_end(3);
+    ev_end(ev);
   }
 
-  KeyView<KeyT> kv{rowptr_.as<uint32_t>(), ukey_.as<KeyT>(), ucnt_.as<uint32_t>(), hsh_.as<uint64_t>()};
-  ev_begin(4);
+  KeyView<KeyT> kv{rowptr_.as<uint32_t>(), ukey_.as<KeyT>(), ucnt_.as<uint32_t>(), key_bits + 1};
+  const int evo = ev_begin(4);
   order_groups<KeyT>(key_bits, &kv);
-  ev_end(4);
+  ev_end(evo);
 }
 
 void Engine::run_round() {
   const int64_t B_old = B_;
-  ev_begin(6);
+  const int evr = ev_begin(6);
   if (n_ > 0) {
     if (adj64_) {
       if (key64_) round_impl<uint64_t, uint64_t>(); else round_impl<uint64_t, uint32_t>();
@@ -498,15 +528,26 @@ void Engine::run_round() {
       if (key64_) round_impl<uint32_t, uint64_t>(); else round_impl<uint32_t, uint32_t>();
     }
   }
-  ev_begin(5);
+  const int eva = ev_begin(5);
   assign_ids_into(pid_[cur_ ^ 1].as<int32_t>());
-  ev_end(5);
-  ev_end(6);
+  ev_end(eva);
+  ev_end(evr);
   cur_ ^= 1;
   ++rounds_;
   counts_.push_back(B_);
   fixed_ = (B_ == B_old);
   ev_collect();
+}
+
+void Engine::work_counts(uint64_t* out8) {
+  for (int i = 0; i < 8; ++i) out8[i] = 0;
+  if (!work_.p) return;
+  KB_CHECK(hipMemcpyAsync(out8, work_.p, 8 * sizeof(uint64_t), hipMemcpyDeviceToHost, st_));
+  KB_CHECK(hipStreamSynchronize(st_));
+}
+
+void Engine::reset_work() {
+  if (work_.p) KB_CHECK(hipMemsetAsync(work_.p, 0, 8 * sizeof(unsigned long long), st_));
 }
 
 void Engine::refine(int32_t k) {
@@ -570,8 +611,8 @@ extern "C" {
 void kbisim_options_default(kbisim_options* opt) {
   if (!opt) return;
   opt->early_stop = 1;
-  opt->hash_bits = 64;
   opt->profile = 0;
+  opt->medium_cap = int32_t(kb::kDefaultMediumCap);
 }
 
 kbisim_status kbisim_create(const kbisim_graph_desc* d, const kbisim_options* opt, kbisim_graph** out) {
@@ -585,9 +626,10 @@ kbisim_status kbisim_create(const kbisim_graph_desc* d, const kbisim_options* op
   if (d->mem != KBISIM_MEM_HOST && d->mem != KBISIM_MEM_DEVICE) return fail(KBISIM_EINVAL, "bad mem kind");
   kb::Options o;
   if (opt) {
-    if (opt->hash_bits < 1 || opt->hash_bits > 64) return fail(KBISIM_EINVAL, "hash_bits not in 1..64");
     o.early_stop = opt->early_stop != 0;
-    o.hash_bits = opt->hash_bits;
+    if (opt->medium_cap < 0 || opt->medium_cap > int32_t(kb::kMediumCap))
+      return fail(KBISIM_EINVAL, "medium_cap outside [0, 2048]");
+    if (opt->medium_cap > 0) o.medium_cap = uint32_t(opt->medium_cap);
     o.profile = opt->profile != 0;
   }
   return guarded([&]() {
@@ -663,6 +705,18 @@ kbisim_status kbisim_profile(const kbisim_graph* g, double* ms, int64_t* launche
     g->eng->prof_n.fill(0);
   }
   return KBISIM_OK;
+}
+
+kbisim_status kbisim_work(const kbisim_graph* g, int64_t* nodes_edges, int32_t cap, int32_t reset) {
+  if (!g || !g->eng) return fail(KBISIM_EINVAL, "null handle");
+  if (cap < 0) return fail(KBISIM_EINVAL, "negative cap");
+  return guarded([&]() {
+    uint64_t w[8];
+    g->eng->work_counts(w);
+    for (int i = 0; i < std::min(cap, 8); ++i) nodes_edges[i] = int64_t(w[i]);
+    if (reset) g->eng->reset_work();
+    return KBISIM_OK;
+  });
 }
 
 void kbisim_destroy(kbisim_graph* g) {

@@ -9,14 +9,19 @@
 // pid_prev (blocks contiguous, block b starting at bstart[b]), and only blocks
 // with two or more members need their members ordered by the key sequence.
 //
-// Ordering a group of positions is a most-significant-digit refinement over
-// key positions t = 0, 1, ...: at depth t the members of every still-open
-// subgroup are sorted by digit(t) = key[t] + 1, or 0 once the sequence has
-// ended, and split where the digit changes. A subgroup whose members end
-// together is a set of identical signatures. A subgroup whose members all
-// carry the same 64-bit hash and length is checked element by element and,
-// when identical, closed early; on any mismatch refinement simply continues,
-// so the hash can only save work and never changes an id.
+// Ordering a group is a most-significant-digit refinement with common-prefix
+// skipping. Every open subgroup S has a depth t(S): all members agree on the
+// keys before t(S). Each member finds the first position >= t(S) where its
+// sequence differs from that of the subgroup's first member (the leader); the
+// minimum d over the members is where S splits. If no member differs, S is a
+// set of identical signatures and closes. Otherwise the members are sorted by
+// digit(d) = key[d] + 1 (0 once the sequence has ended), split where the digit
+// changes, and every new subgroup gets depth d + 1. A subgroup whose sequences
+// ended at d, or that has one member, closes. When keys are narrow, several
+// consecutive digits are packed into one 64-bit sort digit (most significant
+// first), which consumes that many positions per iteration. Each iteration splits every
+// open subgroup, so the number of iterations does not depend on how long the
+// shared prefixes are. All comparisons are exact.
 //
 // flag[p] = 1 marks the first position of every class (distinct signature) in
 // `ord`; an inclusive scan of flag then yields the new dense ids.
@@ -28,29 +33,100 @@
 namespace kb {
 
 constexpr uint32_t kSmallCap = 64;     // groups handled by one wave
-constexpr uint32_t kMediumCap = 2048;  // groups handled by one workgroup in LDS
+constexpr uint32_t kMediumCap = 2048;  // largest group one workgroup can order in LDS
 constexpr int kMediumNT = 256;
+constexpr uint32_t kNoDiff = 0xffffffffu;
+constexpr uint32_t kUndecided = 0xfffffffeu;
+constexpr uint32_t kThreadWindow = 32;  // keys one thread compares before asking its wave
 
 template <typename KeyT>
 struct KeyView {
   const uint32_t* rowptr;
   const KeyT* ukey;
   const uint32_t* ucnt;
-  const uint64_t* hsh;
+  int dbits;  // bits of one digit: key bits + 1
 
   __device__ __forceinline__ uint64_t digit(uint32_t node, uint32_t t) const {
     return t < ucnt[node] ? uint64_t(ukey[rowptr[node] + t]) + 1ull : 0ull;
   }
-  // True when the key sequences of a and b agree from position t on (their
-  // earlier keys agree by construction) and their lengths agree.
-  __device__ __forceinline__ bool same_tail(uint32_t a, uint32_t b, uint32_t t) const {
-    const uint32_t ca = ucnt[a];
-    if (ca != ucnt[b]) return false;
+  // Digits of positions t .. t+w-1 packed most significant first (w * dbits
+  // <= 64), so comparing packed values compares the w positions in order.
+  __device__ __forceinline__ uint64_t digits(uint32_t node, uint32_t t, uint32_t w) const {
+    if (w == 1) return digit(node, t);
+    const uint32_t c = ucnt[node];
+    const KeyT* k = ukey + rowptr[node];
+    uint64_t v = 0;
+    for (uint32_t j = 0; j < w; ++j) {
+      const uint64_t d = (t + j < c) ? uint64_t(k[t + j]) + 1ull : 0ull;
+      v = (v << dbits) | d;
+    }
+    return v;
+  }
+  // Mask of the last packed digit: zero there means the sequence ended.
+  __device__ __forceinline__ uint64_t last_digit_mask() const {
+    return dbits >= 64 ? ~0ull : ((1ull << dbits) - 1);
+  }
+  // First position >= t where the key sequences of a and b differ (one of
+  // them ending counts as a difference), or kNoDiff if they are equal.
+  __device__ __forceinline__ uint32_t first_diff(uint32_t a, uint32_t b, uint32_t t) const {
+    const uint32_t ca = ucnt[a], cb = ucnt[b];
+    const uint32_t n = ca < cb ? ca : cb;
     const KeyT* ka = ukey + rowptr[a];
     const KeyT* kb_ = ukey + rowptr[b];
-    for (uint32_t j = t; j < ca; ++j)
-      if (ka[j] != kb_[j]) return false;
-    return true;
+    uint32_t j = t;
+    for (; j + 4 <= n; j += 4) {
+      const KeyT a0 = ka[j], a1 = ka[j + 1], a2 = ka[j + 2], a3 = ka[j + 3];
+      const KeyT b0 = kb_[j], b1 = kb_[j + 1], b2 = kb_[j + 2], b3 = kb_[j + 3];
+      if (a0 != b0) return j;
+      if (a1 != b1) return j + 1;
+      if (a2 != b2) return j + 2;
+      if (a3 != b3) return j + 3;
+    }
+    for (; j < n; ++j)
+      if (ka[j] != kb_[j]) return j;
+    if (ca == cb) return kNoDiff;
+    return n > t ? n : t;
+  }
+  // As first_diff, but looks at most at `window` positions from t; returns
+  // kUndecided when the sequences agree on the whole window and continue.
+  __device__ __forceinline__ uint32_t first_diff_window(uint32_t a, uint32_t b, uint32_t t,
+                                                        uint32_t window) const {
+    const uint32_t ca = ucnt[a], cb = ucnt[b];
+    const uint32_t n = ca < cb ? ca : cb;
+    const uint32_t stop = n > t ? ((n - t > window) ? t + window : n) : t;
+    const KeyT* ka = ukey + rowptr[a];
+    const KeyT* kb_ = ukey + rowptr[b];
+    uint32_t j = t;
+    for (; j + 4 <= stop; j += 4) {
+      const KeyT a0 = ka[j], a1 = ka[j + 1], a2 = ka[j + 2], a3 = ka[j + 3];
+      const KeyT b0 = kb_[j], b1 = kb_[j + 1], b2 = kb_[j + 2], b3 = kb_[j + 3];
+      if (a0 != b0) return j;
+      if (a1 != b1) return j + 1;
+      if (a2 != b2) return j + 2;
+      if (a3 != b3) return j + 3;
+    }
+    for (; j < stop; ++j)
+      if (ka[j] != kb_[j]) return j;
+    if (stop < n) return kUndecided;
+    if (ca == cb) return kNoDiff;
+    return n > t ? n : t;
+  }
+  // first_diff computed by a whole wave, 64 positions per step; every lane
+  // of the wave must call it with the same arguments.
+  __device__ __forceinline__ uint32_t wave_first_diff(uint32_t a, uint32_t b, uint32_t t) const {
+    const uint32_t ca = ucnt[a], cb = ucnt[b];
+    const uint32_t n = ca < cb ? ca : cb;
+    const KeyT* ka = ukey + rowptr[a];
+    const KeyT* kb_ = ukey + rowptr[b];
+    const uint32_t lane = __lane_id();
+    for (uint32_t base = t; base < n; base += kWave) {
+      const uint32_t j = base + lane;
+      const bool ne = j < n && ka[j] != kb_[j];
+      const uint64_t bal = __ballot(ne);
+      if (bal) return base + uint32_t(__ffsll((unsigned long long)bal) - 1);
+    }
+    if (ca == cb) return kNoDiff;
+    return n > t ? n : t;
   }
 };
 
@@ -83,74 +159,87 @@ __device__ __forceinline__ uint32_t block_inclusive_max(uint32_t v, uint32_t* sh
   return v > before ? v : before;
 }
 
-// Orders the members of one group (positions [s, s+m) of ord, m <= CAP)
-// lexicographically by their key sequences from depth d0 on, and sets flag[]
-// at the first position of every class inside the group (the group's own
-// first position is already flagged).
+// Orders the members of one group (positions [s, s+m) of ord, m <= CAP,
+// all agreeing on keys before gdepth) lexicographically and sets flag[] at
+// the first position of every class inside the group (the group's own first
+// position is already flagged).
 template <int NT, int CAP, typename KeyT>
 __global__ __launch_bounds__(NT) void resolve_k(const uint32_t* __restrict__ gstart,
-                                                const uint32_t* __restrict__ gsize, uint32_t d0,
+                                                const uint32_t* __restrict__ gsize,
+                                                const uint32_t* __restrict__ gdepth,
                                                 uint32_t* __restrict__ ord, uint8_t* __restrict__ flag,
                                                 KeyView<KeyT> kv) {
   __shared__ uint32_t node[CAP];
-  __shared__ uint32_t sub[CAP];
+  __shared__ uint32_t sub[CAP];   // index of the subgroup's first member
+  __shared__ uint32_t dep[CAP];   // depth of the member's subgroup
+  __shared__ uint32_t fdm[CAP];   // per leader: split position of its subgroup
   __shared__ uint64_t dig[CAP];
-  __shared__ uint8_t res[CAP];
+  __shared__ uint8_t res[CAP];    // member's subgroup is closed
   __shared__ uint8_t mark[CAP];
+  __shared__ uint32_t queue[CAP];  // members whose comparison needs a whole wave
+  __shared__ uint32_t qn;
   __shared__ uint32_t shm[NT / kWave > 0 ? NT / kWave : 1];
 
   const uint32_t s = gstart[blockIdx.x];
   const uint32_t m = gsize[blockIdx.x];
+  const uint32_t d0 = gdepth[blockIdx.x];
+  const uint32_t width = kv.dbits >= 64 ? 1u : uint32_t(64 / kv.dbits);  // positions per digit
   uint32_t P = 2;
   while (P < m) P <<= 1;
   for (uint32_t i = threadIdx.x; i < P; i += NT) {
-    if (i < m) {
-      node[i] = ord[s + i];
-      sub[i] = 0;
-      res[i] = 0;
-      dig[i] = 0;
-    } else {
-      node[i] = 0xffffffffu;
-      sub[i] = 0xffffffffu;
-      res[i] = 1;
-      dig[i] = ~0ull;
-    }
+    const bool in = i < m;
+    node[i] = in ? ord[s + i] : 0xffffffffu;
+    sub[i] = in ? 0u : 0xffffffffu;
+    dep[i] = d0;
+    res[i] = in ? 0 : 1;
+    dig[i] = in ? 0ull : ~0ull;
   }
   __syncthreads();
 
-  for (uint32_t t = d0;; ++t) {
-    // (a) close subgroups whose members carry identical signatures
-    for (uint32_t i = threadIdx.x; i < m; i += NT) mark[i] = 0;
+  for (;;) {
+    // (a) split position of every open subgroup: each thread compares its
+    // members over a short window; members that still agree are queued and
+    // compared by whole waves, 64 positions per step.
+    for (uint32_t i = threadIdx.x; i < m; i += NT) fdm[i] = kNoDiff;
+    if (threadIdx.x == 0) qn = 0;
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < m; i += NT) {
       const uint32_t L = sub[i];
       if (!res[i] && i != L) {
-        const uint32_t a = node[i], b = node[L];
-        if (kv.hsh[a] != kv.hsh[b] || kv.ucnt[a] != kv.ucnt[b]) mark[L] = 1;
+        const uint32_t d = kv.first_diff_window(node[i], node[L], dep[i], kThreadWindow);
+        if (d == kUndecided)
+          queue[atomicAdd(&qn, 1u)] = i;
+        else if (d != kNoDiff)
+          atomicMin(&fdm[L], d);
       }
     }
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < m; i += NT) {
+    for (uint32_t q = threadIdx.x / kWave; q < qn; q += NT / kWave) {
+      const uint32_t i = queue[q];
       const uint32_t L = sub[i];
-      if (!res[i] && i != L && !mark[L] && !kv.same_tail(node[i], node[L], t)) mark[L] = 1;
+      const uint32_t d = kv.wave_first_diff(node[i], node[L], dep[i] + kThreadWindow);
+      if (__lane_id() == 0 && d != kNoDiff) atomicMin(&fdm[L], d);
     }
     __syncthreads();
     bool open = false;
     for (uint32_t i = threadIdx.x; i < m; i += NT) {
       if (!res[i]) {
-        if (!mark[sub[i]])
-          res[i] = 1;
-        else
+        const uint32_t d = fdm[sub[i]];
+        if (d == kNoDiff) {
+          res[i] = 1;  // identical signatures (or a single member)
+          dig[i] = 0;
+        } else {
           open = true;
+          dig[i] = kv.digits(node[i], d, width);
+          dep[i] = d + width;
+        }
+      } else {
+        dig[i] = 0;
       }
     }
     if (!__syncthreads_or(open)) break;
 
-    // (b) digit at depth t of every open member
-    for (uint32_t i = threadIdx.x; i < m; i += NT) dig[i] = res[i] ? 0ull : kv.digit(node[i], t);
-    __syncthreads();
-
-    // (c) sort by (subgroup, digit); subgroups keep their position ranges
+    // (b) sort by (subgroup, digit); subgroups keep their position ranges
     for (uint32_t size = 2; size <= P; size <<= 1) {
       for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
         for (uint32_t i = threadIdx.x; i < P / 2; i += NT) {
@@ -160,16 +249,17 @@ __global__ __launch_bounds__(NT) void resolve_k(const uint32_t* __restrict__ gst
           const bool gt = sub[lo] != sub[hi] ? sub[lo] > sub[hi] : dig[lo] > dig[hi];
           if (gt == up) {
             uint32_t tu = sub[lo]; sub[lo] = sub[hi]; sub[hi] = tu;
-            uint64_t td = dig[lo]; dig[lo] = dig[hi]; dig[hi] = td;
             tu = node[lo]; node[lo] = node[hi]; node[hi] = tu;
-            uint8_t tr = res[lo]; res[lo] = res[hi]; res[hi] = tr;
+            tu = dep[lo]; dep[lo] = dep[hi]; dep[hi] = tu;
+            const uint64_t td = dig[lo]; dig[lo] = dig[hi]; dig[hi] = td;
+            const uint8_t tr = res[lo]; res[lo] = res[hi]; res[hi] = tr;
           }
         }
         __syncthreads();
       }
     }
 
-    // (d) split where the digit changes; close ended and single subgroups
+    // (c) split where the digit changes; close ended and single subgroups
     for (uint32_t i = threadIdx.x; i < m; i += NT)
       mark[i] = (i == 0 || sub[i] != sub[i - 1] || dig[i] != dig[i - 1]) ? 1 : 0;
     __syncthreads();
@@ -187,10 +277,8 @@ __global__ __launch_bounds__(NT) void resolve_k(const uint32_t* __restrict__ gst
     for (uint32_t i = threadIdx.x; i < m; i += NT) {
       if (mark[i] && i > 0) flag[s + i] = 1;
       if (!res[i]) {
-        const uint32_t L = sub[i];
         const bool single = mark[i] && (i + 1 == m || mark[i + 1]);
-        if (dig[i] == 0 || single) res[i] = 1;
-        (void)L;
+        if ((dig[i] & kv.last_digit_mask()) == 0 || single) res[i] = 1;
       }
     }
     __syncthreads();
@@ -202,53 +290,60 @@ __global__ __launch_bounds__(NT) void resolve_k(const uint32_t* __restrict__ gst
 // Segments (blocks of the previous round, or subgroups after a global split)
 // and their classification into work lists by size.
 
-// Segment j of the previous partition: block j with start bstart[j].
+// Segment j of the previous partition: block j with start bstart[j], depth 0.
 __global__ void blocks_as_segments_k(const uint32_t* __restrict__ bstart, uint32_t nblocks,
                                      uint32_t* __restrict__ seg_start, uint32_t* __restrict__ seg_size,
-                                     uint8_t* __restrict__ seg_done) {
+                                     uint32_t* __restrict__ seg_depth, uint8_t* __restrict__ seg_done) {
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= nblocks) return;
   const uint32_t a = bstart[j], b = bstart[j + 1];
   seg_start[j] = a;
   seg_size[j] = b - a;
+  seg_depth[j] = 0;
   seg_done[j] = (b - a) <= 1;
 }
 
-// cls[j] bits: 1 small, 2 medium, 4 large (exactly one bit, or none if done).
+// Open segments of up to kSmallCap members go to the wave resolver, up to
+// medium_cap (<= kMediumCap) to the workgroup resolver, the rest to the
+// global pass.
 __global__ void classify_segments_k(const uint32_t* __restrict__ seg_size,
                                     const uint8_t* __restrict__ seg_done, uint32_t nseg,
-                                    uint32_t* __restrict__ c_small, uint32_t* __restrict__ c_medium,
-                                    uint32_t* __restrict__ c_large) {
+                                    uint32_t medium_cap, uint32_t* __restrict__ c_small,
+                                    uint32_t* __restrict__ c_medium, uint32_t* __restrict__ c_large) {
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= nseg) return;
   const uint32_t z = seg_size[j];
   const bool done = seg_done[j] || z <= 1;
   c_small[j] = !done && z <= kSmallCap;
-  c_medium[j] = !done && z > kSmallCap && z <= kMediumCap;
-  c_large[j] = !done && z > kMediumCap;
+  c_medium[j] = !done && z > kSmallCap && z <= medium_cap;
+  c_large[j] = !done && z > kSmallCap && z > medium_cap;
 }
 
 // Scatters segment j to list position off[j] when its class flag is set
 // (off = exclusive scan of the flags).
 __global__ void scatter_segments_k(const uint32_t* __restrict__ seg_start,
-                                   const uint32_t* __restrict__ seg_size, uint32_t nseg,
+                                   const uint32_t* __restrict__ seg_size,
+                                   const uint32_t* __restrict__ seg_depth, uint32_t nseg,
                                    const uint32_t* __restrict__ cflag, const uint32_t* __restrict__ off,
-                                   uint32_t* __restrict__ out_start, uint32_t* __restrict__ out_size) {
+                                   uint32_t* __restrict__ out_start, uint32_t* __restrict__ out_size,
+                                   uint32_t* __restrict__ out_depth) {
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= nseg) return;
   if (cflag[j]) {
-    out_start[off[j]] = seg_start[j];
-    out_size[off[j]] = seg_size[j];
+    const uint32_t o = off[j];
+    out_start[o] = seg_start[j];
+    out_size[o] = seg_size[j];
+    out_depth[o] = seg_depth[j];
   }
 }
 
 // ---------------------------------------------------------------------------
-// Global most-significant-digit pass for groups larger than kMediumCap.
-// Items are the members of the large groups laid out group after group;
-// ioff[g] is the first item of group g (exclusive scan of the sizes).
+// Global pass for groups too large for the resolvers. Items are the members of
+// the large groups laid out group after group; ioff[g] is the absolute index
+// of the first item of group g.
 
 __device__ __forceinline__ uint32_t group_of_item(const uint32_t* ioff, uint32_t ng, uint32_t i) {
-  uint32_t lo = 0, hi = ng;  // find last g with ioff[g] <= i
+  uint32_t lo = 0, hi = ng;  // last g with ioff[g] <= i
   while (hi - lo > 1) {
     const uint32_t mid = (lo + hi) >> 1;
     if (ioff[mid] <= i)
@@ -259,60 +354,91 @@ __device__ __forceinline__ uint32_t group_of_item(const uint32_t* ioff, uint32_t
   return lo;
 }
 
-// mixed[g] = 1 unless every member of g has the leader's hash and length.
+// split[g] = min over members of the first difference with the leader.
+// Each thread compares one member over a short window; members that still
+// agree are appended to `longq` for large_split_pos_wave_k.
 template <typename KeyT>
-__global__ void large_mixed_k(const uint32_t* __restrict__ gstart, const uint32_t* __restrict__ ioff,
-                              uint32_t ng, uint32_t nitems, const uint32_t* __restrict__ ord,
-                              uint8_t* __restrict__ mixed, KeyView<KeyT> kv) {
+__global__ __launch_bounds__(256) void large_split_pos_k(
+    const uint32_t* __restrict__ gstart, const uint32_t* __restrict__ gdepth, const uint32_t* __restrict__ ioff,
+    uint32_t ng, uint32_t nitems, const uint32_t* __restrict__ ord, uint32_t* __restrict__ split,
+    uint32_t* __restrict__ longq, uint32_t* __restrict__ nlong, KeyView<KeyT> kv) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nitems) return;
-  const uint32_t g = group_of_item(ioff, ng, i);
-  const uint32_t a = ord[gstart[g] + (i - ioff[g])];
-  const uint32_t b = ord[gstart[g]];
-  if (kv.hsh[a] != kv.hsh[b] || kv.ucnt[a] != kv.ucnt[b]) mixed[g] = 1;
+  const bool in = i < nitems;
+  uint32_t g = 0, d = kNoDiff;
+  if (in) {
+    g = group_of_item(ioff, ng, i);
+    const uint32_t a = ord[gstart[g] + (i - ioff[g])];
+    const uint32_t b = ord[gstart[g]];
+    if (a != b) {
+      d = kv.first_diff_window(a, b, gdepth[g], kThreadWindow);
+      if (d == kUndecided) {
+        longq[atomicAdd(nlong, 1u)] = i;
+        d = kNoDiff;
+      }
+    }
+  }
+  // Members of one group are contiguous, so a wave usually covers a single
+  // group: reduce there and issue one atomic, and only when it can lower the
+  // stored minimum (huge groups would otherwise serialise on one address).
+  const uint32_t g0 = __shfl(g, 0, kWave);
+  const bool uniform = __ballot(in && g != g0) == 0;
+  if (uniform) {
+    const uint32_t dm = wave_min(d);
+    if (__lane_id() == 0 && dm != kNoDiff && dm < split[g0]) atomicMin(&split[g0], dm);
+  } else if (in && d != kNoDiff && d < split[g]) {
+    atomicMin(&split[g], d);
+  }
 }
 
+// One wave per queued member, grid-stride over the queue length in *nlong.
 template <typename KeyT>
-__global__ void large_verify_k(const uint32_t* __restrict__ gstart, const uint32_t* __restrict__ ioff,
-                               uint32_t ng, uint32_t nitems, const uint32_t* __restrict__ ord,
-                               uint8_t* __restrict__ mixed, uint32_t t, KeyView<KeyT> kv) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nitems) return;
-  const uint32_t g = group_of_item(ioff, ng, i);
-  if (mixed[g]) return;
-  const uint32_t a = ord[gstart[g] + (i - ioff[g])];
-  const uint32_t b = ord[gstart[g]];
-  if (a != b && !kv.same_tail(a, b, t)) mixed[g] = 1;
+__global__ void large_split_pos_wave_k(const uint32_t* __restrict__ gstart, const uint32_t* __restrict__ gdepth,
+                                       const uint32_t* __restrict__ ioff, uint32_t ng,
+                                       const uint32_t* __restrict__ ord, uint32_t* __restrict__ split,
+                                       const uint32_t* __restrict__ longq, const uint32_t* __restrict__ nlong,
+                                       KeyView<KeyT> kv) {
+  const uint32_t nq = *nlong;
+  const uint32_t waves = gridDim.x * (blockDim.x / kWave);
+  for (uint32_t q = (blockIdx.x * blockDim.x + threadIdx.x) / kWave; q < nq; q += waves) {
+    const uint32_t i = longq[q];
+    const uint32_t g = group_of_item(ioff, ng, i);
+    const uint32_t a = ord[gstart[g] + (i - ioff[g])];
+    const uint32_t b = ord[gstart[g]];
+    const uint32_t d = kv.wave_first_diff(a, b, gdepth[g] + kThreadWindow);
+    if (__lane_id() == 0 && d != kNoDiff) atomicMin(&split[g], d);
+  }
 }
 
-__global__ void u8_to_u32_k(const uint8_t* __restrict__ in, uint32_t* __restrict__ out, uint32_t n) {
+__global__ void open_flags_k(const uint32_t* __restrict__ split, uint32_t n, uint32_t* __restrict__ out) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = in[i];
+  if (i < n) out[i] = split[i] != kNoDiff;
 }
 
-// Sort keys of the open large groups: (group << dig_bits) | digit(t). Items
-// are numbered from item_base (ioff holds absolute item offsets).
+// Sort keys of the open large groups: (group << dig_bits) | the `width`
+// packed digits from split[g] on (dig_bits = width * kv.dbits). Items are
+// numbered from item_base (ioff holds absolute item offsets).
 template <typename KeyT>
-__global__ void large_gather_k(const uint32_t* __restrict__ gstart, const uint32_t* __restrict__ ioff,
-                               uint32_t ng, uint32_t nitems, uint32_t item_base,
-                               const uint32_t* __restrict__ ord, uint32_t t, int dig_bits,
-                               uint64_t* __restrict__ key, uint32_t* __restrict__ val, KeyView<KeyT> kv) {
+__global__ void large_gather_k(const uint32_t* __restrict__ gstart, const uint32_t* __restrict__ gpos,
+                               const uint32_t* __restrict__ ioff, uint32_t ng, uint32_t nitems,
+                               uint32_t item_base, const uint32_t* __restrict__ ord, int dig_bits,
+                               uint32_t width, uint64_t* __restrict__ key, uint32_t* __restrict__ val,
+                               KeyView<KeyT> kv) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nitems) return;
   const uint32_t ia = item_base + i;
   const uint32_t g = group_of_item(ioff, ng, ia);
   const uint32_t node = ord[gstart[g] + (ia - ioff[g])];
   const uint64_t hi = dig_bits >= 64 ? 0ull : (uint64_t(g) << dig_bits);
-  key[i] = hi | kv.digit(node, t);
+  key[i] = hi | kv.digits(node, gpos[g], width);
   val[i] = node;
 }
 
-// After the sort: write members back to ord, flag class starts, and emit the
-// subgroups (start position, size, ended) via start flags.
-__global__ void large_split_k(const uint32_t* __restrict__ gstart, const uint32_t* __restrict__ ioff,
-                              uint32_t ng, uint32_t nitems, uint32_t item_base,
-                              const uint64_t* __restrict__ key, const uint32_t* __restrict__ val,
-                              int dig_bits, uint32_t* __restrict__ ord, uint8_t* __restrict__ flag,
+// After the sort: write members back to ord, flag class starts, and mark the
+// first item of every subgroup.
+__global__ void large_write_k(const uint32_t* __restrict__ gstart, const uint32_t* __restrict__ ioff,
+                              uint32_t nitems, uint32_t item_base, const uint64_t* __restrict__ key,
+                              const uint32_t* __restrict__ val, int dig_bits,
+                              uint32_t* __restrict__ ord, uint8_t* __restrict__ flag,
                               uint32_t* __restrict__ start_flag, uint32_t* __restrict__ item_pos) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nitems) return;
@@ -324,22 +450,27 @@ __global__ void large_split_k(const uint32_t* __restrict__ gstart, const uint32_
   const bool st = (ia == ioff[g]) || key[i] != key[i - 1];
   start_flag[i] = st;
   if (st && ia != ioff[g]) flag[p] = 1;
-  (void)ng;
 }
 
-// Subgroup j starts at item S[j] (S = compacted start flags, S[ns] = nitems).
+// Subgroup j starts at item S[j] (S = compacted start flags); its depth is
+// `width` past the split position of its group; it is closed when its
+// sequences ended inside the digits (last packed digit zero).
 __global__ void large_subgroups_k(const uint32_t* __restrict__ start_flag,
                                   const uint32_t* __restrict__ start_off, uint32_t nitems,
                                   const uint32_t* __restrict__ item_pos, const uint64_t* __restrict__ key,
-                                  uint64_t dig_mask, uint32_t* __restrict__ sub_item,
-                                  uint32_t* __restrict__ seg_start, uint8_t* __restrict__ seg_done) {
+                                  int dig_bits, uint32_t width, uint64_t last_mask,
+                                  const uint32_t* __restrict__ gpos, uint32_t* __restrict__ sub_item,
+                                  uint32_t* __restrict__ seg_start, uint32_t* __restrict__ seg_depth,
+                                  uint8_t* __restrict__ seg_done) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nitems) return;
   if (start_flag[i]) {
     const uint32_t j = start_off[i];
+    const uint32_t g = dig_bits >= 64 ? 0u : uint32_t(key[i] >> dig_bits);
     sub_item[j] = i;
     seg_start[j] = item_pos[i];
-    seg_done[j] = (key[i] & dig_mask) == 0;  // sequences ended: identical signatures
+    seg_depth[j] = gpos[g] + width;
+    seg_done[j] = (key[i] & last_mask) == 0;
   }
 }
 

@@ -5,9 +5,9 @@
 // For every node u whose current block has at least two members, the kernels
 // gather key(e) = (edge label rank << pid_bits) | pid_prev[dst(e)] over u's
 // out-edges, sort the keys of u ascending, drop duplicates and write the
-// unique keys to ukey[rowptr[u] ...], their number to ucnt[u] and a 64-bit
-// hash of the set to hsh[u]. The key order equals the order of the pairs
-// (label, pid) because the label occupies the high bits.
+// unique keys to ukey[rowptr[u] ...] and their number to ucnt[u]. The key
+// order equals the order of the pairs (label, pid) because the label occupies
+// the high bits.
 //
 // Nodes alone in their block are skipped: a refinement never merges blocks
 // (Proposition 1), so such a node stays alone and its signature cannot
@@ -28,7 +28,6 @@ constexpr uint32_t kWaveMaxDeg = 64;
 constexpr uint32_t kBlockMaxDeg = 4096;
 constexpr int kSigBlockNT = 256;
 constexpr int kHubNT = 256;
-constexpr uint64_t kHashSalt = 0x9e3779b97f4a7c15ull;
 
 template <typename AdjT, typename KeyT>
 struct SigArgs {
@@ -38,8 +37,6 @@ struct SigArgs {
   const uint32_t* bstart;  // [B+1] block start positions (block sizes)
   KeyT* ukey;              // [E] unique keys per node at rowptr offsets
   uint32_t* ucnt;          // [N]
-  uint64_t* hsh;           // [N]
-  uint64_t hash_mask;
   int dst_bits;
   int pid_bits;
 
@@ -52,15 +49,7 @@ struct SigArgs {
     const int32_t p = pid[n];
     return bstart[p + 1] - bstart[p] > 1;
   }
-  __device__ __forceinline__ uint64_t finish(uint64_t h, uint32_t cnt) const {
-    return mix64(h ^ (uint64_t(cnt) * kHashSalt)) & hash_mask;
-  }
 };
-
-template <typename KeyT>
-__device__ __forceinline__ uint64_t key_hash(KeyT k) {
-  return mix64(uint64_t(k) + kHashSalt);
-}
 
 template <typename KeyT>
 __device__ __forceinline__ void cas_up(KeyT& a, KeyT& b, bool up) {
@@ -74,37 +63,39 @@ __device__ __forceinline__ void cas_up(KeyT& a, KeyT& b, bool up) {
 template <typename AdjT, typename KeyT>
 __global__ __launch_bounds__(256) void sig_thread_k(SigArgs<AdjT, KeyT> a, uint32_t n_nodes) {
   const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= n_nodes) return;
-  const uint32_t beg = a.rowptr[n];
-  const uint32_t deg = a.rowptr[n + 1] - beg;
-  if (deg > kThreadMaxDeg || !a.active(n)) return;
-  constexpr int M = kThreadMaxDeg;
-  KeyT k[M];
+  uint32_t beg = 0, deg = 0;
+  bool act = false;
+  if (n < n_nodes) {
+    beg = a.rowptr[n];
+    deg = a.rowptr[n + 1] - beg;
+    act = deg <= kThreadMaxDeg && a.active(n);
+  }
+  if (act) {
+    constexpr int M = kThreadMaxDeg;
+    KeyT k[M];
 #pragma unroll
-  for (int j = 0; j < M; ++j) k[j] = (uint32_t(j) < deg) ? a.key_of(a.adj[beg + j]) : ~KeyT(0);
+    for (int j = 0; j < M; ++j) k[j] = (uint32_t(j) < deg) ? a.key_of(a.adj[beg + j]) : ~KeyT(0);
 #pragma unroll
-  for (int size = 2; size <= M; size <<= 1) {
+    for (int size = 2; size <= M; size <<= 1) {
 #pragma unroll
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
 #pragma unroll
-      for (int i = 0; i < M; ++i) {
-        const int j = i ^ stride;
-        if (j > i) cas_up(k[i], k[j], (i & size) == 0);
+        for (int i = 0; i < M; ++i) {
+          const int j = i ^ stride;
+          if (j > i) cas_up(k[i], k[j], (i & size) == 0);
+        }
       }
     }
-  }
-  uint64_t h = 0;
-  uint32_t c = 0;
+    uint32_t c = 0;
 #pragma unroll
-  for (int j = 0; j < M; ++j) {
-    if (uint32_t(j) < deg && (j == 0 || k[j] != k[j - 1])) {
-      a.ukey[beg + c] = k[j];
-      ++c;
-      h += key_hash(k[j]);
+    for (int j = 0; j < M; ++j) {
+      if (uint32_t(j) < deg && (j == 0 || k[j] != k[j - 1])) {
+        a.ukey[beg + c] = k[j];
+        ++c;
+      }
     }
+    a.ucnt[n] = c;
   }
-  a.ucnt[n] = c;
-  a.hsh[n] = a.finish(h, c);
 }
 
 // ---- bucket 2: one wave per node, 16 < out-degree <= 64 ----------------------
@@ -142,11 +133,8 @@ __global__ __launch_bounds__(256) void sig_wave_k(SigArgs<AdjT, KeyT> a, const u
   const bool f = uint32_t(lane) < deg && (lane == 0 || k != prev);
   const uint64_t b = __ballot(f);
   if (f) a.ukey[beg + __popcll(b & lanemask_lt())] = k;
-  const uint64_t h = wave_sum<uint64_t>(f ? key_hash(k) : 0ull);
   if (lane == 0) {
-    const uint32_t c = __popcll(b);
-    a.ucnt[n] = c;
-    a.hsh[n] = a.finish(h, c);
+    a.ucnt[n] = __popcll(b);
   }
 }
 
@@ -171,27 +159,20 @@ __device__ __forceinline__ void block_bitonic(KeyT* s, uint32_t P) {
 }
 
 // Writes the unique keys of the sorted array s[0..deg) to out[0..) and
-// returns (count, hash-sum) to every thread.
+// returns their number to every thread.
 template <int NT, typename KeyT>
-__device__ __forceinline__ void block_unique_write(const KeyT* s, uint32_t deg, KeyT* out,
-                                                   uint32_t* count, uint64_t* hsum) {
+__device__ __forceinline__ uint32_t block_unique_write(const KeyT* s, uint32_t deg, KeyT* out) {
   __shared__ uint32_t shc[NT / kWave];
-  __shared__ uint64_t shh[NT / kWave];
   uint32_t carry = 0;
-  uint64_t h = 0;
   for (uint32_t base = 0; base < deg; base += NT) {
     const uint32_t i = base + threadIdx.x;
     const bool f = i < deg && (i == 0 || s[i] != s[i - 1]);
     uint32_t tot;
     const uint32_t ex = block_exclusive_scan<NT>(uint32_t(f), shc, &tot);
-    if (f) {
-      out[carry + ex] = s[i];
-      h += key_hash(s[i]);
-    }
+    if (f) out[carry + ex] = s[i];
     carry += tot;
   }
-  *count = carry;
-  *hsum = block_sum<NT>(h, shh);
+  return carry;
 }
 
 template <typename AdjT, typename KeyT>
@@ -209,12 +190,9 @@ __global__ __launch_bounds__(kSigBlockNT) void sig_block_k(SigArgs<AdjT, KeyT> a
     s[i] = i < deg ? a.key_of(a.adj[beg + i]) : ~KeyT(0);
   __syncthreads();
   block_bitonic(s, P);
-  uint32_t c;
-  uint64_t h;
-  block_unique_write<kSigBlockNT>(s, deg, a.ukey + beg, &c, &h);
+  const uint32_t c = block_unique_write<kSigBlockNT>(s, deg, a.ukey + beg);
   if (threadIdx.x == 0) {
     a.ucnt[n] = c;
-    a.hsh[n] = a.finish(h, c);
   }
 }
 
@@ -287,9 +265,7 @@ __global__ __launch_bounds__(kHubNT) void sig_hub_k(SigArgs<AdjT, KeyT> a, const
   // unique pass: read src (sorted), write A; in place when src == A, so each
   // chunk is read completely before any of it is written.
   __shared__ uint32_t shc[NW];
-  __shared__ uint64_t shh[NW];
   uint32_t carry = 0;
-  uint64_t h = 0;
   for (uint32_t base = 0; base < deg; base += kHubNT) {
     const uint32_t i = base + threadIdx.x;
     KeyT cur = 0;
@@ -300,18 +276,36 @@ __global__ __launch_bounds__(kHubNT) void sig_hub_k(SigArgs<AdjT, KeyT> a, const
     }
     uint32_t tot;
     const uint32_t ex = block_exclusive_scan<kHubNT>(uint32_t(f), shc, &tot);  // has barriers
-    if (f) {
-      A[carry + ex] = cur;
-      h += key_hash(cur);
-    }
+    if (f) A[carry + ex] = cur;
     carry += tot;
     __syncthreads();
   }
-  const uint64_t hs = block_sum<kHubNT>(h, shh);
   if (threadIdx.x == 0) {
     a.ucnt[n] = carry;
-    a.hsh[n] = a.finish(hs, carry);
   }
+}
+
+// Work of the signature kernels (profiling only, launched separately so the
+// timed kernels carry no counters): per bucket, active nodes and their edges.
+__global__ __launch_bounds__(256) void work_count_k(const uint32_t* __restrict__ rowptr,
+                                                    const int32_t* __restrict__ pid,
+                                                    const uint32_t* __restrict__ bstart, uint32_t n,
+                                                    unsigned long long* __restrict__ work) {
+  __shared__ unsigned long long acc[8];
+  if (threadIdx.x < 8) acc[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) {
+    const int32_t p = pid[v];
+    if (bstart[p + 1] - bstart[p] > 1) {
+      const uint32_t d = rowptr[v + 1] - rowptr[v];
+      const int b = d <= kThreadMaxDeg ? 0 : d <= kWaveMaxDeg ? 1 : d <= kBlockMaxDeg ? 2 : 3;
+      atomicAdd(&acc[2 * b], 1ull);
+      atomicAdd(&acc[2 * b + 1], (unsigned long long)d);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 8 && acc[threadIdx.x]) atomicAdd(&work[threadIdx.x], acc[threadIdx.x]);
 }
 
 }  // namespace kb

@@ -79,18 +79,34 @@ def test_degree_buckets():
     check_parity(g, 6)
 
 
-def test_powerlaw_mid():
-    """Power-law graph with hubs and large blocks (global passes)."""
+@pytest.mark.parametrize("medium_cap", [None, 64, 300])
+def test_powerlaw_mid(medium_cap):
+    """Power-law graph with hubs and large blocks; the split between the
+    workgroup resolver and the global passes must not change any id."""
     g = synth.powerlaw_graph(200_000, 2_000_000, seed=7, deg_cap=30_000, name="powerlaw-200k")
-    check_parity(g, 10)
+    check_parity(g, 10, medium_cap=medium_cap)
 
 
-@pytest.mark.parametrize("bits", [1, 4])
-def test_hash_collisions(bits):
-    """Hash cut to a few bits: equal hashes are verified, so ids are unchanged."""
-    g = synth.powerlaw_graph(20_000, 150_000, seed=9, deg_cap=5_000, num_node_labels=3,
-                             num_edge_labels=2, name="collide")
-    check_parity(g, 8, hash_bits=bits)
+@pytest.mark.parametrize("members,endings", [(40, 7), (300, 20), (3000, 50)])
+def test_deep_common_prefix(members, endings):
+    """Blocks (small, medium, large) whose signatures share their first 1000
+    keys and differ only after them."""
+    width = 1000
+    n_t = width + endings
+    n = n_t + members
+    lab = np.arange(n, dtype=np.int32)
+    lab[n_t:] = n_t  # all sources in one block
+    src, dst = [], []
+    for j in range(members):
+        s = n_t + j
+        src.append(np.full(width + 1, s))
+        dst.append(np.concatenate([np.arange(width), [width + (j * 7919) % endings]]))
+    src = np.concatenate(src).astype(np.int32)
+    dst = np.concatenate(dst).astype(np.int32)
+    g = synth.Graph(n, lab, src, np.zeros(src.shape[0], np.int32), dst,
+                    name="prefix%d" % members)
+    check_parity(g, 3)
+    check_parity(g, 3, medium_cap=64)
 
 
 def test_identical_hubs():
@@ -158,3 +174,46 @@ def test_invalid_inputs():
         with pytest.raises(kb.KbisimError):
             h.refine(-1)
         assert h.refine(2) == 2  # the handle still works after an error
+
+
+def test_profile_mode_same_ids():
+    """Profiling (event timers and work counters) leaves the ids unchanged."""
+    torch, kb = need_gpu()
+    g = synth.powerlaw_graph(30_000, 300_000, seed=21, deg_cap=6_000, name="prof")
+    r = oracle.refine(g.num_nodes, g.node_label, g.src, g.elab, g.dst, 6)
+    with kb.Graph(g.num_nodes, *to_dev(torch, g), profile=True) as h:
+        rd = h.refine(6)
+        pid, nb, counts = h.result()
+        prof = h.profile()
+        work = h.work()
+    assert rd == r.rounds_done and counts == r.counts and np.array_equal(pid, r.pid)
+    assert prof["round"][1] == rd and prof["sig_thread"][1] == rd
+    assert sum(v[0] for v in work.values()) > 0
+
+
+def test_wide_keys():
+    """More than 2^22 distinct edge labels on 1000 nodes: label bits + id bits
+    exceed 32, so the packed edge words and the keys are 64-bit."""
+    rng = np.random.default_rng(17)
+    n, e = 1000, (1 << 22) + 5000
+    src = rng.integers(0, n, size=e).astype(np.int32)
+    dst = rng.integers(0, n, size=e).astype(np.int32)
+    lab = rng.permutation(e).astype(np.int32) // 1  # all distinct
+    lab[:5000] = lab[5000:10000]                     # some shared labels
+    node_label = rng.integers(0, 3, size=n).astype(np.int32)
+    g = synth.Graph(n, node_label, src, lab, dst, name="widekeys")
+    check_parity(g, 3)
+
+
+def test_key_width_exactly_32():
+    """Label bits + id bits == 32: largest keys use all 32 bits."""
+    n = (1 << 21) + 7
+    rng = np.random.default_rng(23)
+    e = 3 * n
+    src = rng.integers(0, n, size=e).astype(np.int32)
+    dst = rng.integers(0, n, size=e).astype(np.int32)
+    lab = rng.integers(0, 2048, size=e).astype(np.int32)  # 11 label bits + 22 id bits... capped below
+    lab = (lab % 1024).astype(np.int32)  # 10 bits + 22 bits = 32
+    node_label = rng.integers(0, 4, size=n).astype(np.int32)
+    g = synth.Graph(n, node_label, src, lab, dst, name="key32")
+    check_parity(g, 2)
