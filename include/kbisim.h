@@ -75,7 +75,7 @@ typedef struct {
   int32_t profile;    /* 1: time each kernel class with HIP events (kbisim_profile) and
                          count the work of the signature kernels (kbisim_work) */
   int32_t medium_cap; /* tuning: blocks of 65..medium_cap members are ordered by one
-                         workgroup in LDS, larger ones by global radix passes; 64..2048,
+                         workgroup in LDS, larger ones by global radix passes; 64..1024,
                          values <= 64 send every block above 64 members to the global
                          passes; 0 = library default. Ids do not depend on it. */
 } kbisim_options;
@@ -131,6 +131,12 @@ kbisim_status kbisim_work(const kbisim_graph* g, int64_t* nodes_edges, int32_t c
 
 /* Frees everything owned by the handle. NULL is ignored. */
 void kbisim_destroy(kbisim_graph* g);
+
+/* The library keeps freed device memory in a process-wide cache for reuse by
+ * later handles (allocation is slow). This returns every cached block to
+ * the HIP runtime after the device has finished with it; *released_bytes
+ * (may be NULL) receives the amount. Handles stay valid. */
+kbisim_status kbisim_release_cached(int64_t* released_bytes);
 
 /* Static text for a status code. */
 const char* kbisim_status_str(kbisim_status s);

@@ -6,9 +6,9 @@ refinement runs in the library's kernels. PyTorch supplies device memory and
 the stream.
 """
 from ._binding import (KbisimError, Graph, refine, kbisim_create, kbisim_refine, kbisim_result,
-                       kbisim_profile, kbisim_work, kbisim_destroy, kbisim_status_str, kbisim_last_error,
+                       kbisim_profile, kbisim_work, kbisim_release_cached, kbisim_destroy, kbisim_status_str, kbisim_last_error,
                        lib_path, load_library, PROF_CLASSES)
 
 __all__ = ["KbisimError", "Graph", "refine", "kbisim_create", "kbisim_refine", "kbisim_result",
-           "kbisim_profile", "kbisim_work", "kbisim_destroy", "kbisim_status_str", "kbisim_last_error",
+           "kbisim_profile", "kbisim_work", "kbisim_release_cached", "kbisim_destroy", "kbisim_status_str", "kbisim_last_error",
            "lib_path", "load_library", "PROF_CLASSES"]

@@ -64,6 +64,8 @@ def load_library():
     lib.kbisim_profile.restype = ctypes.c_int
     lib.kbisim_work.argtypes = [vp, vp, i32, i32]
     lib.kbisim_work.restype = ctypes.c_int
+    lib.kbisim_release_cached.argtypes = [ctypes.POINTER(i64)]
+    lib.kbisim_release_cached.restype = ctypes.c_int
     lib.kbisim_destroy.argtypes = [vp]
     lib.kbisim_destroy.restype = None
     lib.kbisim_status_str.argtypes = [ctypes.c_int]
@@ -180,6 +182,13 @@ def kbisim_work(handle, reset=False):
     w = np.zeros(8, np.int64)
     _check(load_library().kbisim_work(handle, w.ctypes.data, 8, 1 if reset else 0))
     return {PROF_CLASSES[c]: (int(w[2 * c]), int(w[2 * c + 1])) for c in range(4)}
+
+
+def kbisim_release_cached():
+    """Frees the library's cache of device memory; returns the bytes released."""
+    b = ctypes.c_int64(0)
+    _check(load_library().kbisim_release_cached(ctypes.byref(b)))
+    return int(b.value)
 
 
 def kbisim_destroy(handle):

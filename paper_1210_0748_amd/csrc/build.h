@@ -52,6 +52,11 @@ __global__ void to_u32_iota_k(const int32_t* __restrict__ in, uint32_t* __restri
   val[i] = i;
 }
 
+__global__ void iota_k(uint32_t* __restrict__ out, uint32_t n) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = i;
+}
+
 // flag[p] = 1 where the sorted key changes (first position of each run).
 __global__ void run_start_flags_k(const uint32_t* __restrict__ key, uint32_t n,
                                   uint8_t* __restrict__ flag8, uint32_t* __restrict__ flag32) {
@@ -69,26 +74,6 @@ __global__ void rank_scatter_k(const uint32_t* __restrict__ val, const uint32_t*
   if (p < n) rank[val[p]] = cls[p] - 1;
 }
 
-__global__ void degree_k(const int32_t* __restrict__ src, uint64_t m, uint32_t* __restrict__ deg) {
-  for (uint64_t e = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < m;
-       e += uint64_t(gridDim.x) * blockDim.x)
-    atomicAdd(&deg[src[e]], 1u);
-}
-
-// Places edge e in its source's CSR range; order inside a range is
-// irrelevant because every round sorts a node's keys.
-template <typename AdjT>
-__global__ void fill_adj_k(const int32_t* __restrict__ src, const uint32_t* __restrict__ erank,
-                           const int32_t* __restrict__ dst, uint64_t m, const uint32_t* __restrict__ rowptr,
-                           uint32_t* __restrict__ cursor, int dst_bits, AdjT* __restrict__ adj) {
-  for (uint64_t e = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < m;
-       e += uint64_t(gridDim.x) * blockDim.x) {
-    const uint32_t s = uint32_t(src[e]);
-    const uint32_t pos = rowptr[s] + atomicAdd(&cursor[s], 1u);
-    adj[pos] = (AdjT(erank[e]) << dst_bits) | AdjT(uint32_t(dst[e]));
-  }
-}
-
 // Degree buckets: 0 thread (<=16), 1 wave (<=64), 2 block (<=4096), 3 hub.
 __global__ void bucket_flags_k(const uint32_t* __restrict__ rowptr, uint32_t n, uint32_t t_max,
                                uint32_t w_max, uint32_t b_max, uint32_t* __restrict__ fw,
@@ -103,6 +88,15 @@ __global__ void bucket_flags_k(const uint32_t* __restrict__ rowptr, uint32_t n, 
   hub_deg[v] = d > b_max ? d : 0u;
 }
 
+// *mx = max of v[0..n) by one block.
+__global__ __launch_bounds__(1024) void max_u32_k(const uint32_t* __restrict__ v, uint32_t n,
+                                                  uint32_t* __restrict__ mx) {
+  uint32_t m = 0;
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) m = v[i] > m ? v[i] : m;
+  m = wave_max(m);
+  if (__lane_id() == 0) atomicMax(mx, m);
+}
+
 __global__ void compact_index_k(const uint32_t* __restrict__ f, const uint32_t* __restrict__ off,
                                 uint32_t n, uint32_t* __restrict__ out) {
   const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
@@ -113,6 +107,58 @@ __global__ void gather_u32_k(const uint32_t* __restrict__ src, const uint32_t* _
                              uint32_t n, uint32_t* __restrict__ out) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = src[idx[i]];
+}
+
+// Label values below this bound are ranked through a presence table; larger
+// values through a sort.
+constexpr uint32_t kRankTableMax = 1u << 24;
+
+__global__ void mark_present_k(const int32_t* __restrict__ val, uint64_t n, uint32_t* __restrict__ present) {
+  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+       i += uint64_t(gridDim.x) * blockDim.x)
+    present[uint32_t(val[i])] = 1u;
+}
+
+__global__ void lookup_rank_k(const int32_t* __restrict__ val, const uint32_t* __restrict__ rank,
+                              uint32_t n, uint32_t* __restrict__ out_key, uint32_t* __restrict__ out_idx) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  out_key[i] = rank[uint32_t(val[i])];
+  if (out_idx) out_idx[i] = i;
+}
+
+// Sort input for the CSR build: key = source node, value = packed
+// (label rank << dst_bits) | dst. `erank` (per edge) or `rank_table` (per
+// label value) gives the label rank.
+template <typename AdjT>
+__global__ void pack_edges_k(const int32_t* __restrict__ src, const int32_t* __restrict__ lab,
+                             const int32_t* __restrict__ dst, uint64_t m, const uint32_t* __restrict__ erank,
+                             const uint32_t* __restrict__ rank_table, int dst_bits, uint32_t* __restrict__ key,
+                             AdjT* __restrict__ val) {
+  for (uint64_t e = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < m;
+       e += uint64_t(gridDim.x) * blockDim.x) {
+    const uint32_t r = erank ? erank[e] : rank_table[uint32_t(lab[e])];
+    key[e] = uint32_t(src[e]);
+    val[e] = (AdjT(r) << dst_bits) | AdjT(uint32_t(dst[e]));
+  }
+}
+
+// Degrees from edges sorted by source: the first and one-past-last position
+// of every run of equal sources (end stays 0 for nodes without edges).
+__global__ void run_bounds_k(const uint32_t* __restrict__ skey, uint64_t m, uint32_t* __restrict__ run_start,
+                             uint32_t* __restrict__ run_end) {
+  for (uint64_t p = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < m;
+       p += uint64_t(gridDim.x) * blockDim.x) {
+    const uint32_t k = skey[p];
+    if (p == 0 || skey[p - 1] != k) run_start[k] = uint32_t(p);
+    if (p + 1 == m || skey[p + 1] != k) run_end[k] = uint32_t(p + 1);
+  }
+}
+
+__global__ void degree_from_runs_k(const uint32_t* __restrict__ run_start, const uint32_t* __restrict__ run_end,
+                                   uint32_t n, uint32_t* __restrict__ deg) {
+  const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) deg[v] = run_end[v] ? run_end[v] - run_start[v] : 0u;
 }
 
 }  // namespace kb

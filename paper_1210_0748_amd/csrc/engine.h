@@ -7,41 +7,43 @@
 #include <cstdint>
 #include <cstring>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "common.h"
+#include "pool.h"
 
 namespace kb {
 
-// Owning device allocation that only grows.
+// Owning device allocation that only grows; memory comes from and returns
+// to the caching pool, tagged with the calling thread's current stream.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  hipStream_t s = nullptr;
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) Pool::instance().put(p, bytes, s);
     p = nullptr;
     bytes = 0;
   }
   void ensure(size_t b) {
     if (b <= bytes && p) return;
-    if (p) (void)hipDeviceSynchronize();  // work queued on the old buffer must finish
     release();
-    const size_t want = b ? b : 1;
-    hipError_t e = hipMalloc(&p, want);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      p = nullptr;
-      throw OutOfMemory("hipMalloc of " + std::to_string(want) + " bytes failed");
-    }
-    bytes = want;
+    s = current_stream();
+    p = Pool::instance().get(b ? b : 1, s, &bytes);
   }
   template <typename T>
   T* as() const {
     return static_cast<T*>(p);
+  }
+  void swap(DevBuf& o) {
+    std::swap(p, o.p);
+    std::swap(bytes, o.bytes);
+    std::swap(s, o.s);
   }
 };
 
@@ -107,7 +109,9 @@ class Engine {
 
  private:
   template <typename AdjT>
-  void build_adj(const int32_t* src, const uint32_t* erank, const int32_t* dst);
+  void build_adj(const int32_t* src, const int32_t* lab, const int32_t* dst, const uint32_t* erank,
+                 const uint32_t* rank_table);
+  uint32_t label_ranks(const int32_t* val, uint64_t n, uint32_t maxv, DevBuf& rank_table, DevBuf& rank);
   template <typename AdjT, typename KeyT>
   void round_impl();
   template <typename KeyT>
@@ -115,7 +119,7 @@ class Engine {
   template <typename KeyT>
   void resolve_lists(SegLists& L, const void* kv);
   void make_lists(const uint32_t* seg_start, const uint32_t* seg_size, const uint32_t* seg_depth,
-                  const uint8_t* seg_done, uint32_t nseg, SegLists& out);
+                  const uint8_t* seg_done, uint32_t nseg, SegLists& out, const uint32_t* nseg_dev = nullptr);
   void run_round();
   void assign_ids_into(int32_t* pid_out);
   uint64_t read_word(const void* dev, int bytes);
@@ -139,6 +143,7 @@ class Engine {
   // graph
   DevBuf rowptr_, adj_, wlist_, blist_, hlist_, hub_off_, hub_tmp_;
   uint32_t nw_ = 0, nb_ = 0, nh_ = 0;
+  uint32_t maxdeg_ = 0;
   // partition state
   DevBuf pid_[2], ord_, flag_, bstart_;
   int cur_ = 0;
@@ -150,8 +155,8 @@ class Engine {
   DevBuf ukey_, ucnt_, cls_, scanpart_, radix_;
   DevBuf seg_start_, seg_size_, seg_depth_, seg_done_, cf_small_, cf_medium_, cf_large_, off_;
   SegLists lists_a_, lists_b_;
-  DevBuf l_ioff_, l_split_, l_long_, l_open_, l_open_off_, u_start_, u_size_, u_pos_, u_ioff_;
-  DevBuf k0_, k1_, v0_, v1_, sflag_, soff_, ipos_, sub_item_;
+  DevBuf l_ioff_, l_fd_, l_long_, l_open_;
+  DevBuf k0_, k1_, k2_, k3_, k4_, v0_, v1_, v2_, v3_, v4_, sflag_, soff_, ipos_, sub_item_;
   DevBuf next_l_start_[2], next_l_size_[2], next_l_depth_[2];
 
   // profiling

@@ -93,24 +93,41 @@ void Engine::ev_collect() {
 // Build: validation, pId_0, edge-label ranks, CSR.
 
 template <typename AdjT>
-void Engine::build_adj(const int32_t* src, const uint32_t* erank, const int32_t* dst) {
+void Engine::build_adj(const int32_t* src, const int32_t* lab, const int32_t* dst, const uint32_t* erank,
+                       const uint32_t* rank_table) {
   const uint64_t N = uint64_t(n_), E = uint64_t(m_);
-  DevBuf deg, cursor;
-  deg.ensure((N + 1) * sizeof(uint32_t));
-  cursor.ensure((N + 1) * sizeof(uint32_t));
-  KB_CHECK(hipMemsetAsync(deg.p, 0, (N + 1) * sizeof(uint32_t), st_));
-  KB_CHECK(hipMemsetAsync(cursor.p, 0, (N + 1) * sizeof(uint32_t), st_));
-  if (E) {
-    degree_k<<<grid_stride_blocks(E), kNT, 0, st_>>>(src, E, deg.as<uint32_t>());
-    KB_LAUNCH_CHECK();
-  }
   rowptr_.ensure((N + 1) * sizeof(uint32_t));
-  scan_dev<uint32_t, uint32_t, false>(deg.as<uint32_t>(), rowptr_.as<uint32_t>(), N + 1);
-  adj_.ensure(std::max<uint64_t>(E, 1) * sizeof(AdjT));
   if (E) {
-    fill_adj_k<AdjT><<<grid_stride_blocks(E), kNT, 0, st_>>>(src, erank, dst, E, rowptr_.as<uint32_t>(),
-                                                           cursor.as<uint32_t>(), dst_bits_, adj_.as<AdjT>());
+    // sort the packed edges by source: CSR order without atomics
+    DevBuf ka, kb2, vb;
+    ka.ensure(E * 4);
+    kb2.ensure(E * 4);
+    adj_.ensure(E * sizeof(AdjT));
+    vb.ensure(E * sizeof(AdjT));
+    pack_edges_k<AdjT><<<grid_stride_blocks(E), kNT, 0, st_>>>(src, lab, dst, E, erank, rank_table, dst_bits_,
+                                                             ka.as<uint32_t>(), adj_.as<AdjT>());
     KB_LAUNCH_CHECK();
+    const bool f = radix_sort<uint32_t, AdjT>(ka.as<uint32_t>(), adj_.as<AdjT>(), kb2.as<uint32_t>(),
+                                              vb.as<AdjT>(), E, 0, bits_for(N > 1 ? N - 1 : 1),
+                                              radix_scratch(E), st_);
+    if (f) adj_.swap(vb);
+    const uint32_t* skey = f ? kb2.as<uint32_t>() : ka.as<uint32_t>();
+    DevBuf rs, re, deg;
+    rs.ensure(N * 4);
+    re.ensure(N * 4);
+    deg.ensure((N + 1) * 4);
+    KB_CHECK(hipMemsetAsync(re.p, 0, N * 4, st_));
+    KB_CHECK(hipMemsetAsync(deg.as<uint32_t>() + N, 0, 4, st_));
+    run_bounds_k<<<grid_stride_blocks(E), kNT, 0, st_>>>(skey, E, rs.as<uint32_t>(), re.as<uint32_t>());
+    KB_LAUNCH_CHECK();
+    degree_from_runs_k<<<grid_for(N), kNT, 0, st_>>>(rs.as<uint32_t>(), re.as<uint32_t>(), uint32_t(N),
+                                                     deg.as<uint32_t>());
+    KB_LAUNCH_CHECK();
+    scan_dev<uint32_t, uint32_t, false>(deg.as<uint32_t>(), rowptr_.as<uint32_t>(), N + 1);
+    KB_CHECK(hipStreamSynchronize(st_));  // temporaries are freed on return
+  } else {
+    adj_.ensure(sizeof(AdjT));
+    KB_CHECK(hipMemsetAsync(rowptr_.p, 0, (N + 1) * 4, st_));
   }
   // degree buckets
   if (N) {
@@ -122,6 +139,7 @@ void Engine::build_adj(const int32_t* src, const uint32_t* erank, const int32_t*
                                                  kWaveMaxDeg, kBlockMaxDeg, fw.as<uint32_t>(),
                                                  fb.as<uint32_t>(), fh.as<uint32_t>(), hd.as<uint32_t>());
     KB_LAUNCH_CHECK();
+
     scan_dev<uint32_t, uint32_t, false>(fw.as<uint32_t>(), ow.as<uint32_t>(), N + 1);
     scan_dev<uint32_t, uint32_t, false>(fb.as<uint32_t>(), ob.as<uint32_t>(), N + 1);
     scan_dev<uint32_t, uint32_t, false>(fh.as<uint32_t>(), oh.as<uint32_t>(), N + 1);
@@ -151,15 +169,61 @@ void Engine::build_adj(const int32_t* src, const uint32_t* erank, const int32_t*
       gather_u32_k<<<grid_for(nh_), kNT, 0, st_>>>(hd.as<uint32_t>(), hlist_.as<uint32_t>(), nh_,
                                                    hdl.as<uint32_t>());
       KB_LAUNCH_CHECK();
+      DevBuf mx;
+      mx.ensure(4);
+      KB_CHECK(hipMemsetAsync(mx.p, 0, 4, st_));
+      max_u32_k<<<1, 1024, 0, st_>>>(hdl.as<uint32_t>(), nh_, mx.as<uint32_t>());
+      KB_LAUNCH_CHECK();
       scan_dev<uint32_t, uint32_t, false>(hdl.as<uint32_t>(), hub_off_.as<uint32_t>(), nh_ + 1);
       const uint64_t tot = read_word(hub_off_.as<uint32_t>() + nh_, 4);
       hub_tmp_.ensure(std::max<uint64_t>(tot, 1) * (key64_ ? 8 : 4));
+      maxdeg_ = uint32_t(read_word(mx.p, 4));
+    } else {
+      maxdeg_ = kBlockMaxDeg;  // bound: no node has more edges than a block-bucket node
     }
     KB_CHECK(hipStreamSynchronize(st_));  // temporaries are freed on return
   }
 }
 
+// Dense ascending ranks of the label values `val[0..n)` (all >= 0, max
+// `maxv`): for small values through a presence table (rank_table[v] = rank
+// of value v), otherwise through a sort (rank[i] per element). Returns the
+// number of distinct values. Exactly one of the two outputs is filled.
+uint32_t Engine::label_ranks(const int32_t* val, uint64_t n, uint32_t maxv, DevBuf& rank_table, DevBuf& rank) {
+  if (n == 0) return 0;
+  if (maxv < kRankTableMax) {
+    const uint64_t t = uint64_t(maxv) + 2;
+    DevBuf present;
+    present.ensure(t * 4);
+    rank_table.ensure(t * 4);
+    KB_CHECK(hipMemsetAsync(present.p, 0, t * 4, st_));
+    mark_present_k<<<grid_stride_blocks(n), kNT, 0, st_>>>(val, n, present.as<uint32_t>());
+    KB_LAUNCH_CHECK();
+    scan_dev<uint32_t, uint32_t, false>(present.as<uint32_t>(), rank_table.as<uint32_t>(), t);
+    const uint32_t d = uint32_t(read_word(rank_table.as<uint32_t>() + (t - 1), 4));
+    return d;  // synchronised: `present` may be freed
+  }
+  DevBuf ka, kb2, va, vb;
+  for (DevBuf* b : {&ka, &kb2, &va, &vb}) b->ensure(n * 4);
+  to_u32_iota_k<<<grid_for(n), kNT, 0, st_>>>(val, ka.as<uint32_t>(), va.as<uint32_t>(), uint32_t(n));
+  KB_LAUNCH_CHECK();
+  const bool f = radix_sort<uint32_t>(ka.as<uint32_t>(), va.as<uint32_t>(), kb2.as<uint32_t>(), vb.as<uint32_t>(),
+                                      n, 0, bits_for(maxv), radix_scratch(n), st_);
+  uint32_t* keys = f ? kb2.as<uint32_t>() : ka.as<uint32_t>();
+  uint32_t* vals = f ? vb.as<uint32_t>() : va.as<uint32_t>();
+  uint32_t* fl = f ? ka.as<uint32_t>() : kb2.as<uint32_t>();   // the free key buffer
+  uint32_t* cl = f ? va.as<uint32_t>() : vb.as<uint32_t>();    // the free value buffer
+  run_start_flags_k<<<grid_for(n), kNT, 0, st_>>>(keys, uint32_t(n), nullptr, fl);
+  KB_LAUNCH_CHECK();
+  scan_dev<uint32_t, uint32_t, true>(fl, cl, n);
+  rank.ensure(n * 4);
+  rank_scatter_k<<<grid_for(n), kNT, 0, st_>>>(vals, cl, uint32_t(n), rank.as<uint32_t>());
+  KB_LAUNCH_CHECK();
+  return uint32_t(read_word(cl + (n - 1), 4));
+}
+
 void Engine::build(const int32_t* node_label, const int32_t* src, const int32_t* lab, const int32_t* dst) {
+  StreamScope scope(st_);
   const uint64_t N = uint64_t(n_), E = uint64_t(m_);
   DevBuf errb;
   errb.ensure(4 * sizeof(uint32_t));
@@ -182,14 +246,6 @@ void Engine::build(const int32_t* node_label, const int32_t* src, const int32_t*
   if (words[0] & 4u) throw InvalidInput("negative node label");
   const uint32_t max_nlab = words[1], max_elab = words[2];
 
-  const uint64_t big = std::max<uint64_t>(std::max<uint64_t>(N, E), 1);
-  DevBuf ka, kb2, va, vb;
-  ka.ensure(big * 4);
-  kb2.ensure(big * 4);
-  va.ensure(big * 4);
-  vb.ensure(big * 4);
-
-  // pId_0: nodes sorted by label; a new id per new label (Section 3.1, k = 0)
   pid_[0].ensure(std::max<uint64_t>(N, 1) * 4);
   pid_[1].ensure(std::max<uint64_t>(N, 1) * 4);
   ord_.ensure(std::max<uint64_t>(N, 1) * 4);
@@ -197,50 +253,50 @@ void Engine::build(const int32_t* node_label, const int32_t* src, const int32_t*
   bstart_.ensure((N + 1) * 4);
   cls_.ensure(std::max<uint64_t>(N, 1) * 4);
   cur_ = 0;
+
+  // pId_0: the rank of the node label; nodes sorted by it give `ord` and the
+  // blocks (Section 3.1, k = 0: sort by label, a new id per new label)
   if (N) {
-    to_u32_iota_k<<<grid_for(N), kNT, 0, st_>>>(node_label, ka.as<uint32_t>(), va.as<uint32_t>(), uint32_t(N));
+    DevBuf table, rank, ka, kb2, va, vb;
+    const uint32_t b0 = label_ranks(node_label, N, max_nlab, table, rank);
+    for (DevBuf* b : {&ka, &kb2, &va, &vb}) b->ensure(N * 4);
+    if (table.p) {
+      lookup_rank_k<<<grid_for(N), kNT, 0, st_>>>(node_label, table.as<uint32_t>(), uint32_t(N),
+                                                  ka.as<uint32_t>(), va.as<uint32_t>());
+    } else {
+      KB_CHECK(hipMemcpyAsync(ka.p, rank.p, N * 4, hipMemcpyDeviceToDevice, st_));
+      iota_k<<<grid_for(N), kNT, 0, st_>>>(va.as<uint32_t>(), uint32_t(N));
+    }
     KB_LAUNCH_CHECK();
     const bool f = radix_sort<uint32_t>(ka.as<uint32_t>(), va.as<uint32_t>(), kb2.as<uint32_t>(),
-                                        vb.as<uint32_t>(), N, 0, bits_for(max_nlab), radix_scratch(N), st_);
+                                        vb.as<uint32_t>(), N, 0, bits_for(b0 > 1 ? b0 - 1 : 1),
+                                        radix_scratch(N), st_);
     const uint32_t* keys = f ? kb2.as<uint32_t>() : ka.as<uint32_t>();
     const uint32_t* vals = f ? vb.as<uint32_t>() : va.as<uint32_t>();
     KB_CHECK(hipMemcpyAsync(ord_.p, vals, N * 4, hipMemcpyDeviceToDevice, st_));
     run_start_flags_k<<<grid_for(N), kNT, 0, st_>>>(keys, uint32_t(N), flag_.as<uint8_t>(), nullptr);
     KB_LAUNCH_CHECK();
+    assign_ids_into(pid_[0].as<int32_t>());  // synchronises before the temporaries go
+  } else {
+    assign_ids_into(pid_[0].as<int32_t>());
   }
-  assign_ids_into(pid_[0].as<int32_t>());
   counts_.assign(1, B_);
   rounds_ = 0;
   fixed_ = false;
 
   // edge labels: dense ascending ranks
-  DevBuf erank;
-  erank.ensure(std::max<uint64_t>(E, 1) * 4);
-  n_elab_ = 0;
-  if (E) {
-    to_u32_iota_k<<<grid_for(E), kNT, 0, st_>>>(lab, ka.as<uint32_t>(), va.as<uint32_t>(), uint32_t(E));
-    KB_LAUNCH_CHECK();
-    const bool f = radix_sort<uint32_t>(ka.as<uint32_t>(), va.as<uint32_t>(), kb2.as<uint32_t>(),
-                                        vb.as<uint32_t>(), E, 0, bits_for(max_elab), radix_scratch(E), st_);
-    uint32_t* keys = f ? kb2.as<uint32_t>() : ka.as<uint32_t>();
-    uint32_t* vals = f ? vb.as<uint32_t>() : va.as<uint32_t>();
-    uint32_t* fl = f ? ka.as<uint32_t>() : kb2.as<uint32_t>();  // the free key buffer
-    run_start_flags_k<<<grid_for(E), kNT, 0, st_>>>(keys, uint32_t(E), nullptr, fl);
-    KB_LAUNCH_CHECK();
-    uint32_t* clsE = f ? va.as<uint32_t>() : vb.as<uint32_t>();  // the free value buffer
-    scan_dev<uint32_t, uint32_t, true>(fl, clsE, E);
-    rank_scatter_k<<<grid_for(E), kNT, 0, st_>>>(vals, clsE, uint32_t(E), erank.as<uint32_t>());
-    KB_LAUNCH_CHECK();
-    n_elab_ = uint32_t(read_word(clsE + (E - 1), 4));
-  }
+  DevBuf etable, erank;
+  n_elab_ = label_ranks(lab, E, max_elab, etable, erank);
   lab_bits_ = n_elab_ > 1 ? bits_for(n_elab_ - 1) : 0;
   dst_bits_ = bits_for(N > 1 ? N - 1 : 1);
   adj64_ = dst_bits_ + lab_bits_ > 32;
   key64_ = lab_bits_ + bits_for(N > 1 ? N - 1 : 1) > 32;
+  const uint32_t* er = erank.p ? erank.as<uint32_t>() : nullptr;
+  const uint32_t* et = etable.p ? etable.as<uint32_t>() : nullptr;
   if (adj64_)
-    build_adj<uint64_t>(src, erank.as<uint32_t>(), dst);
+    build_adj<uint64_t>(src, lab, dst, er, et);
   else
-    build_adj<uint32_t>(src, erank.as<uint32_t>(), dst);
+    build_adj<uint32_t>(src, lab, dst, er, et);
 
   // per-round buffers
   ukey_.ensure(std::max<uint64_t>(E, 1) * (key64_ ? 8 : 4));
@@ -271,13 +327,13 @@ void Engine::assign_ids_into(int32_t* pid_out) {
 // Group ordering.
 
 void Engine::make_lists(const uint32_t* seg_start, const uint32_t* seg_size, const uint32_t* seg_depth,
-                        const uint8_t* seg_done, uint32_t nseg, SegLists& out) {
+                        const uint8_t* seg_done, uint32_t nseg, SegLists& out, const uint32_t* nseg_dev) {
   out.ns = out.nm = out.nl = 0;
   if (nseg == 0) return;
   const uint64_t n1 = uint64_t(nseg) + 1;
   for (DevBuf* b : {&cf_small_, &cf_medium_, &cf_large_}) b->ensure(n1 * 4);
   off_.ensure(3 * n1 * 4);
-  classify_segments_k<<<grid_for(nseg), kNT, 0, st_>>>(seg_size, seg_done, nseg, opt_.medium_cap,
+  classify_segments_k<<<grid_for(nseg), kNT, 0, st_>>>(seg_size, seg_done, nseg, nseg_dev, opt_.medium_cap,
                                                        cf_small_.as<uint32_t>(),
                                                        cf_medium_.as<uint32_t>(), cf_large_.as<uint32_t>());
   KB_LAUNCH_CHECK();
@@ -326,9 +382,16 @@ void Engine::resolve_lists(SegLists& L, const void* kvp) {
     KB_LAUNCH_CHECK();
   }
   if (L.nm) {
-    resolve_k<kMediumNT, kMediumCap, KeyT><<<L.nm, kMediumNT, 0, st_>>>(
-        L.m_start.as<uint32_t>(), L.m_size.as<uint32_t>(), L.m_depth.as<uint32_t>(), ord_.as<uint32_t>(),
-        flag_.as<uint8_t>(), kv);
+    // LDS is sized for the largest group the list can hold: smaller groups
+    // leave room for more resident workgroups per CU
+    if (opt_.medium_cap <= kMediumCapSmall)
+      resolve_k<kMediumNT, kMediumCapSmall, KeyT><<<L.nm, kMediumNT, 0, st_>>>(
+          L.m_start.as<uint32_t>(), L.m_size.as<uint32_t>(), L.m_depth.as<uint32_t>(), ord_.as<uint32_t>(),
+          flag_.as<uint8_t>(), kv);
+    else
+      resolve_k<kMediumNT, kMediumCap, KeyT><<<L.nm, kMediumNT, 0, st_>>>(
+          L.m_start.as<uint32_t>(), L.m_size.as<uint32_t>(), L.m_depth.as<uint32_t>(), ord_.as<uint32_t>(),
+          flag_.as<uint8_t>(), kv);
     KB_LAUNCH_CHECK();
   }
 }
@@ -349,7 +412,8 @@ void Engine::order_groups(int key_bits, const void* kvp) {
              seg_done_.as<uint8_t>(), B, lists_a_);
   resolve_lists<KeyT>(lists_a_, kvp);
 
-  // Large groups: global passes, each splitting every open group.
+  // Large groups: global passes, each splitting every group around its
+  // first member as a pivot.
   const uint32_t* Ls = lists_a_.l_start.as<uint32_t>();
   const uint32_t* Lz = lists_a_.l_size.as<uint32_t>();
   const uint32_t* Ld = lists_a_.l_depth.as<uint32_t>();
@@ -357,6 +421,7 @@ void Engine::order_groups(int key_bits, const void* kvp) {
   int nx = 0;
   const int dbits = key_bits + 1;
   const uint64_t last_mask = dbits >= 64 ? ~0ull : ((1ull << dbits) - 1);
+  const int fd_bits = bits_for(maxdeg_ > 0 ? maxdeg_ : 1);
   while (nl > 0) {
     // item offsets of the large groups (sizes with a trailing zero)
     l_ioff_.ensure((uint64_t(nl) + 1) * 4);
@@ -365,102 +430,107 @@ void Engine::order_groups(int key_bits, const void* kvp) {
     KB_CHECK(hipMemsetAsync(l_open_.as<uint32_t>() + nl, 0, 4, st_));
     scan_dev<uint32_t, uint32_t, false>(l_open_.as<uint32_t>(), l_ioff_.as<uint32_t>(), uint64_t(nl) + 1);
     const uint32_t M = uint32_t(read_word(l_ioff_.as<uint32_t>() + nl, 4));
-    // split position of every group (kNoDiff: all members identical)
-    l_split_.ensure(uint64_t(nl) * 4);
-    KB_CHECK(hipMemsetAsync(l_split_.p, 0xff, uint64_t(nl) * 4, st_));
+    const uint32_t* gio = l_ioff_.as<uint32_t>();
+
+    // first difference of every item with its group's pivot
+    l_fd_.ensure(uint64_t(M) * 4);
     l_long_.ensure((uint64_t(M) + 1) * 4);
     KB_CHECK(hipMemsetAsync(l_long_.as<uint32_t>() + M, 0, 4, st_));
-    large_split_pos_k<KeyT><<<grid_for(M), kNT, 0, st_>>>(Ls, Ld, l_ioff_.as<uint32_t>(), nl, M,
-                                                         ord_.as<uint32_t>(), l_split_.as<uint32_t>(),
-                                                         l_long_.as<uint32_t>(), l_long_.as<uint32_t>() + M, kv);
+    large_fd_k<KeyT><<<grid_for(M), kNT, 0, st_>>>(Ls, Ld, gio, nl, M, ord_.as<uint32_t>(), l_fd_.as<uint32_t>(),
+                                                  l_long_.as<uint32_t>(), l_long_.as<uint32_t>() + M, kv);
     KB_LAUNCH_CHECK();
-    large_split_pos_wave_k<KeyT><<<std::min<uint32_t>(grid_for(uint64_t(M) * kWave), 4096), kNT, 0, st_>>>(
-        Ls, Ld, l_ioff_.as<uint32_t>(), nl, ord_.as<uint32_t>(), l_split_.as<uint32_t>(), l_long_.as<uint32_t>(),
+    large_fd_wave_k<KeyT><<<std::min<uint32_t>(grid_for(uint64_t(M) * kWave), 4096), kNT, 0, st_>>>(
+        Ls, Ld, gio, nl, ord_.as<uint32_t>(), l_fd_.as<uint32_t>(), l_long_.as<uint32_t>(),
         l_long_.as<uint32_t>() + M, kv);
     KB_LAUNCH_CHECK();
-    l_open_off_.ensure((uint64_t(nl) + 1) * 4);
-    open_flags_k<<<grid_for(nl), kNT, 0, st_>>>(l_split_.as<uint32_t>(), nl, l_open_.as<uint32_t>());
-    KB_LAUNCH_CHECK();
-    KB_CHECK(hipMemsetAsync(l_open_.as<uint32_t>() + nl, 0, 4, st_));
-    scan_dev<uint32_t, uint32_t, false>(l_open_.as<uint32_t>(), l_open_off_.as<uint32_t>(), uint64_t(nl) + 1);
-    const uint32_t nU = uint32_t(read_word(l_open_off_.as<uint32_t>() + nl, 4));
-    if (nU == 0) break;
-    u_start_.ensure(uint64_t(nU) * 4);
-    u_size_.ensure((uint64_t(nU) + 1) * 4);
-    u_pos_.ensure(uint64_t(nU) * 4);
-    scatter_segments_k<<<grid_for(nl), kNT, 0, st_>>>(Ls, Lz, l_split_.as<uint32_t>(), nl, l_open_.as<uint32_t>(),
-                                                      l_open_off_.as<uint32_t>(), u_start_.as<uint32_t>(),
-                                                      u_size_.as<uint32_t>(), u_pos_.as<uint32_t>());
-    KB_LAUNCH_CHECK();
-    KB_CHECK(hipMemsetAsync(u_size_.as<uint32_t>() + nU, 0, 4, st_));
-    u_ioff_.ensure((uint64_t(nU) + 1) * 4);
-    scan_dev<uint32_t, uint32_t, false>(u_size_.as<uint32_t>(), u_ioff_.as<uint32_t>(), uint64_t(nU) + 1);
-    const uint32_t MU = uint32_t(read_word(u_ioff_.as<uint32_t>() + nU, 4));
 
-    // positions per sort digit and chunks of groups whose index fits beside
-    // the packed digits in 64 bits
-    const int need_g = nU > 1 ? bits_for(nU - 1) : 0;
-    uint32_t width = uint32_t(std::max(1, (64 - need_g) / dbits));
-    const int dig_bits = int(width) * dbits;
-    const int gb = 64 - dig_bits;
-    const uint32_t chunk = gb >= 32 ? nU : std::max<uint32_t>(1, std::min<uint32_t>(nU, 1u << std::max(gb, 0)));
-    const int nxt = nx ^ 1;
-    for (DevBuf* b : {&next_l_start_[nxt], &next_l_size_[nxt], &next_l_depth_[nxt]})
-      b->ensure(uint64_t(MU / (std::max(opt_.medium_cap, kSmallCap) + 1) + 1) * 4);
-    uint32_t nnext = 0;
-    for (uint32_t c0 = 0; c0 < nU; c0 += chunk) {
-      const uint32_t cn = std::min(chunk, nU - c0);
-      const uint32_t I0 = (c0 == 0) ? 0u : uint32_t(read_word(u_ioff_.as<uint32_t>() + c0, 4));
-      const uint32_t I1 = (c0 + cn == nU) ? MU : uint32_t(read_word(u_ioff_.as<uint32_t>() + c0 + cn, 4));
-      const uint32_t cnt = I1 - I0;
-      const uint32_t* gst = u_start_.as<uint32_t>() + c0;
-      const uint32_t* gps = u_pos_.as<uint32_t>() + c0;
-      const uint32_t* gio = u_ioff_.as<uint32_t>() + c0;
-      for (DevBuf* b : {&k0_, &k1_}) b->ensure(uint64_t(cnt) * 8);
-      for (DevBuf* b : {&v0_, &v1_, &ipos_, &sub_item_}) b->ensure(uint64_t(cnt) * 4);
-      for (DevBuf* b : {&sflag_, &soff_}) b->ensure((uint64_t(cnt) + 1) * 4);
-      large_gather_k<KeyT><<<grid_for(cnt), kNT, 0, st_>>>(gst, gps, gio, cn, cnt, I0, ord_.as<uint32_t>(), dig_bits,
-                                                          width, k0_.as<uint64_t>(), v0_.as<uint32_t>(), kv);
+    // sort key layout: one word when (group, side, distance, >= 1 digit) fit
+    const int g_bits = nl > 1 ? bits_for(nl - 1) : 0;
+    const int hi_bits = g_bits + 2 + fd_bits;
+    LargeKey lk;
+    lk.fd_bits = fd_bits;
+    if (hi_bits + dbits <= 64) {
+      lk.packed = true;
+      lk.width = uint32_t((64 - hi_bits) / dbits);
+    } else {
+      lk.packed = false;
+      lk.width = dbits >= 64 ? 1u : uint32_t(64 / dbits);
+    }
+    lk.dig_bits = int(lk.width) * dbits;
+    for (DevBuf* b : {&k0_, &k1_}) b->ensure(uint64_t(M) * 8);
+    for (DevBuf* b : {&v0_, &v1_, &ipos_, &sub_item_}) b->ensure(uint64_t(M) * 4);
+    for (DevBuf* b : {&sflag_, &soff_}) b->ensure((uint64_t(M) + 1) * 4);
+    const uint64_t* KA;
+    const uint64_t* KB = nullptr;
+    const uint32_t* V;
+    if (lk.packed) {
+      large_gather_k<KeyT><<<grid_for(M), kNT, 0, st_>>>(Ls, Ld, gio, nl, M, ord_.as<uint32_t>(), l_fd_.as<uint32_t>(),
+                                                        lk, k0_.as<uint64_t>(), nullptr, v0_.as<uint32_t>(), kv);
       KB_LAUNCH_CHECK();
-      const int g_bits = cn > 1 ? bits_for(cn - 1) : 0;
       const bool f = radix_sort<uint64_t>(k0_.as<uint64_t>(), v0_.as<uint32_t>(), k1_.as<uint64_t>(),
-                                          v1_.as<uint32_t>(), cnt, 0, dig_bits + g_bits, radix_scratch(cnt), st_);
-      const uint64_t* K = f ? k1_.as<uint64_t>() : k0_.as<uint64_t>();
-      const uint32_t* V = f ? v1_.as<uint32_t>() : v0_.as<uint32_t>();
-      large_write_k<<<grid_for(cnt), kNT, 0, st_>>>(gst, gio, cnt, I0, K, V, dig_bits, ord_.as<uint32_t>(),
-                                                    flag_.as<uint8_t>(), sflag_.as<uint32_t>(), ipos_.as<uint32_t>());
+                                          v1_.as<uint32_t>(), M, 0, hi_bits + lk.dig_bits, radix_scratch(M), st_);
+      KA = f ? k1_.as<uint64_t>() : k0_.as<uint64_t>();
+      V = f ? v1_.as<uint32_t>() : v0_.as<uint32_t>();
+    } else {
+      // two words: sort by lo (digits) carrying the item index, then stably
+      // by hi; the final order follows the second permutation
+      for (DevBuf* b : {&k2_, &k3_, &k4_}) b->ensure(uint64_t(M) * 8);
+      for (DevBuf* b : {&v2_, &v3_, &v4_}) b->ensure(uint64_t(M) * 4);
+      large_gather_k<KeyT><<<grid_for(M), kNT, 0, st_>>>(Ls, Ld, gio, nl, M, ord_.as<uint32_t>(), l_fd_.as<uint32_t>(),
+                                                        lk, k2_.as<uint64_t>(), k0_.as<uint64_t>(),
+                                                        v4_.as<uint32_t>(), kv);
+      iota_k<<<grid_for(M), kNT, 0, st_>>>(v0_.as<uint32_t>(), M);
       KB_LAUNCH_CHECK();
-      KB_CHECK(hipMemsetAsync(sflag_.as<uint32_t>() + cnt, 0, 4, st_));
-      scan_dev<uint32_t, uint32_t, false>(sflag_.as<uint32_t>(), soff_.as<uint32_t>(), uint64_t(cnt) + 1);
-      const uint32_t ns = uint32_t(read_word(soff_.as<uint32_t>() + cnt, 4));
-      seg_start_.ensure(uint64_t(ns) * 4 + 4);
-      seg_size_.ensure(uint64_t(ns) * 4 + 4);
-      seg_depth_.ensure(uint64_t(ns) * 4 + 4);
-      seg_done_.ensure(uint64_t(ns) + 1);
-      large_subgroups_k<<<grid_for(cnt), kNT, 0, st_>>>(sflag_.as<uint32_t>(), soff_.as<uint32_t>(), cnt,
-                                                        ipos_.as<uint32_t>(), K, dig_bits, width, last_mask, gps,
-                                                        sub_item_.as<uint32_t>(), seg_start_.as<uint32_t>(),
-                                                        seg_depth_.as<uint32_t>(), seg_done_.as<uint8_t>());
-      subgroup_sizes_k<<<grid_for(ns), kNT, 0, st_>>>(sub_item_.as<uint32_t>(), ns, cnt, seg_size_.as<uint32_t>());
+      const bool f1 = radix_sort<uint64_t>(k0_.as<uint64_t>(), v0_.as<uint32_t>(), k1_.as<uint64_t>(),
+                                           v1_.as<uint32_t>(), M, 0, lk.dig_bits, radix_scratch(M), st_);
+      const uint64_t* L1 = f1 ? k1_.as<uint64_t>() : k0_.as<uint64_t>();
+      const uint32_t* I1 = f1 ? v1_.as<uint32_t>() : v0_.as<uint32_t>();
+      gather_u64_k<<<grid_for(M), kNT, 0, st_>>>(k2_.as<uint64_t>(), I1, M, k3_.as<uint64_t>());
+      iota_k<<<grid_for(M), kNT, 0, st_>>>(v2_.as<uint32_t>(), M);
       KB_LAUNCH_CHECK();
-      make_lists(seg_start_.as<uint32_t>(), seg_size_.as<uint32_t>(), seg_depth_.as<uint32_t>(),
-                 seg_done_.as<uint8_t>(), ns, lists_b_);
-      resolve_lists<KeyT>(lists_b_, kvp);
-      if (lists_b_.nl) {
-        const uint64_t bytes = uint64_t(lists_b_.nl) * 4;
-        KB_CHECK(hipMemcpyAsync(next_l_start_[nxt].as<uint32_t>() + nnext, lists_b_.l_start.p, bytes,
-                                hipMemcpyDeviceToDevice, st_));
-        KB_CHECK(hipMemcpyAsync(next_l_size_[nxt].as<uint32_t>() + nnext, lists_b_.l_size.p, bytes,
-                                hipMemcpyDeviceToDevice, st_));
-        KB_CHECK(hipMemcpyAsync(next_l_depth_[nxt].as<uint32_t>() + nnext, lists_b_.l_depth.p, bytes,
-                                hipMemcpyDeviceToDevice, st_));
-        nnext += lists_b_.nl;
-      }
+      const bool f2 = radix_sort<uint64_t>(k3_.as<uint64_t>(), v2_.as<uint32_t>(), k4_.as<uint64_t>(),
+                                           v3_.as<uint32_t>(), M, 0, hi_bits, radix_scratch(M), st_);
+      KA = f2 ? k4_.as<uint64_t>() : k3_.as<uint64_t>();
+      const uint32_t* PS = f2 ? v3_.as<uint32_t>() : v2_.as<uint32_t>();
+      uint64_t* lo_out = (L1 == k0_.as<uint64_t>()) ? k1_.as<uint64_t>() : k0_.as<uint64_t>();
+      uint32_t* val_out = (I1 == v0_.as<uint32_t>()) ? v1_.as<uint32_t>() : v0_.as<uint32_t>();
+      two_word_finish_k<<<grid_for(M), kNT, 0, st_>>>(L1, I1, PS, v4_.as<uint32_t>(), M, lo_out, val_out);
+      KB_LAUNCH_CHECK();
+      KB = lo_out;
+      V = val_out;
+    }
+    large_write_k<<<grid_for(M), kNT, 0, st_>>>(Ls, gio, M, KA, KB, V, lk, ord_.as<uint32_t>(), flag_.as<uint8_t>(),
+                                                sflag_.as<uint32_t>(), ipos_.as<uint32_t>());
+    KB_LAUNCH_CHECK();
+    KB_CHECK(hipMemsetAsync(sflag_.as<uint32_t>() + M, 0, 4, st_));
+    scan_dev<uint32_t, uint32_t, false>(sflag_.as<uint32_t>(), soff_.as<uint32_t>(), uint64_t(M) + 1);
+    const uint32_t* ns_dev = soff_.as<uint32_t>() + M;  // number of subgroups, kept on the device
+    seg_start_.ensure(uint64_t(M) * 4 + 4);
+    seg_size_.ensure(uint64_t(M) * 4 + 4);
+    seg_depth_.ensure(uint64_t(M) * 4 + 4);
+    seg_done_.ensure(uint64_t(M) + 1);
+    large_subgroups_k<<<grid_for(M), kNT, 0, st_>>>(sflag_.as<uint32_t>(), soff_.as<uint32_t>(), M,
+                                                    ipos_.as<uint32_t>(), KA, KB, lk, last_mask, Ld,
+                                                    sub_item_.as<uint32_t>(), seg_start_.as<uint32_t>(),
+                                                    seg_depth_.as<uint32_t>(), seg_done_.as<uint8_t>());
+    subgroup_sizes_k<<<grid_for(M), kNT, 0, st_>>>(sub_item_.as<uint32_t>(), ns_dev, M, seg_size_.as<uint32_t>());
+    KB_LAUNCH_CHECK();
+    make_lists(seg_start_.as<uint32_t>(), seg_size_.as<uint32_t>(), seg_depth_.as<uint32_t>(),
+               seg_done_.as<uint8_t>(), M, lists_b_, ns_dev);
+    resolve_lists<KeyT>(lists_b_, kvp);
+    // the next pass works on the large subgroups (lists_b_ is reused below)
+    const int nxt = nx ^ 1;
+    nl = lists_b_.nl;
+    if (nl) {
+      const uint64_t bytes = uint64_t(nl) * 4;
+      for (DevBuf* b : {&next_l_start_[nxt], &next_l_size_[nxt], &next_l_depth_[nxt]}) b->ensure(bytes);
+      KB_CHECK(hipMemcpyAsync(next_l_start_[nxt].p, lists_b_.l_start.p, bytes, hipMemcpyDeviceToDevice, st_));
+      KB_CHECK(hipMemcpyAsync(next_l_size_[nxt].p, lists_b_.l_size.p, bytes, hipMemcpyDeviceToDevice, st_));
+      KB_CHECK(hipMemcpyAsync(next_l_depth_[nxt].p, lists_b_.l_depth.p, bytes, hipMemcpyDeviceToDevice, st_));
     }
     Ls = next_l_start_[nxt].as<uint32_t>();
     Lz = next_l_size_[nxt].as<uint32_t>();
     Ld = next_l_depth_[nxt].as<uint32_t>();
-    nl = nnext;
     nx = nxt;
   }
 }
@@ -540,6 +610,7 @@ void Engine::run_round() {
 }
 
 void Engine::work_counts(uint64_t* out8) {
+  StreamScope scope(st_);
   for (int i = 0; i < 8; ++i) out8[i] = 0;
   if (!work_.p) return;
   KB_CHECK(hipMemcpyAsync(out8, work_.p, 8 * sizeof(uint64_t), hipMemcpyDeviceToHost, st_));
@@ -551,6 +622,7 @@ void Engine::reset_work() {
 }
 
 void Engine::refine(int32_t k) {
+  StreamScope scope(st_);
   while (rounds_ < k) {
     if (fixed_ && opt_.early_stop) break;
     run_round();
@@ -628,12 +700,13 @@ kbisim_status kbisim_create(const kbisim_graph_desc* d, const kbisim_options* op
   if (opt) {
     o.early_stop = opt->early_stop != 0;
     if (opt->medium_cap < 0 || opt->medium_cap > int32_t(kb::kMediumCap))
-      return fail(KBISIM_EINVAL, "medium_cap outside [0, 2048]");
+      return fail(KBISIM_EINVAL, "medium_cap outside [0, 1024]");
     if (opt->medium_cap > 0) o.medium_cap = uint32_t(opt->medium_cap);
     o.profile = opt->profile != 0;
   }
   return guarded([&]() {
     hipStream_t s = static_cast<hipStream_t>(d->stream);
+    kb::StreamScope scope(s);
     auto* eng = new kb::Engine(d->num_nodes, d->num_edges, s, o);
     try {
       const uint64_t N = uint64_t(d->num_nodes), E = uint64_t(d->num_edges);
@@ -740,5 +813,14 @@ const char* kbisim_status_str(kbisim_status s) {
 }
 
 const char* kbisim_last_error(void) { return g_last_error.c_str(); }
+
+kbisim_status kbisim_release_cached(int64_t* released_bytes) {
+  return guarded([&]() {
+    const size_t b = kb::Pool::instance().cached_bytes();
+    kb::Pool::instance().trim();
+    if (released_bytes) *released_bytes = int64_t(b);
+    return KBISIM_OK;
+  });
+}
 
 }  // extern "C"

@@ -1,0 +1,138 @@
+// Process-wide caching allocator for device memory.
+//
+// A job allocates and frees a few GB of buffers; going to hipMalloc/hipFree
+// each time costs milliseconds and an implicit device synchronisation. Freed
+// blocks are kept per device and handed out again (best fit, at most twice
+// the requested size). A block remembers the stream of its last user through
+// an event: a later user on another stream first waits for that event, so
+// reuse is ordered after every kernel that touched the block. When hipMalloc
+// fails, all cached blocks are released and the allocation is retried.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <string>
+
+#include "common.h"
+
+namespace kb {
+
+class Pool {
+ public:
+  static Pool& instance() {
+    static Pool* p = new Pool();  // never destroyed: blocks may outlive static teardown
+    return *p;
+  }
+
+  void* get(size_t bytes, hipStream_t s, size_t* got) {
+    const size_t want = round(bytes);
+    int dev = 0;
+    KB_CHECK(hipGetDevice(&dev));
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      auto it = free_.lower_bound(want);
+      for (; it != free_.end() && it->first <= 2 * want; ++it) {
+        if (it->second.dev != dev) continue;
+        Blk b = it->second;
+        free_.erase(it);
+        cached_ -= b.bytes;
+        if (b.ev) {
+          if (b.stream != s) KB_CHECK(hipEventSynchronize(b.ev));
+          KB_CHECK(hipEventDestroy(b.ev));
+        }
+        *got = b.bytes;
+        return b.p;
+      }
+    }
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      trim();
+      e = hipMalloc(&p, want);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw OutOfMemory("hipMalloc of " + std::to_string(want) + " bytes failed");
+      }
+    }
+    *got = want;
+    return p;
+  }
+
+  void put(void* p, size_t bytes, hipStream_t s) {
+    if (!p) return;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    Blk b{p, bytes, s, dev, nullptr};
+    if (hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(b.ev, s) != hipSuccess) {
+      // cannot order a later reuse: give the block back to the runtime
+      (void)hipGetLastError();
+      if (b.ev) (void)hipEventDestroy(b.ev);
+      (void)hipStreamSynchronize(s);
+      (void)hipFree(p);
+      return;
+    }
+    std::lock_guard<std::mutex> lk(mu_);
+    free_.emplace(bytes, b);
+    cached_ += bytes;
+  }
+
+  // Releases every cached block (after the device has finished with them).
+  void trim() {
+    std::multimap<size_t, Blk> all;
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      all.swap(free_);
+      cached_ = 0;
+    }
+    for (auto& kv : all) {
+      if (kv.second.ev) {
+        (void)hipEventSynchronize(kv.second.ev);
+        (void)hipEventDestroy(kv.second.ev);
+      }
+      (void)hipFree(kv.second.p);
+    }
+  }
+
+  size_t cached_bytes() {
+    std::lock_guard<std::mutex> lk(mu_);
+    return cached_;
+  }
+
+ private:
+  struct Blk {
+    void* p;
+    size_t bytes;
+    hipStream_t stream;
+    int dev;
+    hipEvent_t ev;
+  };
+  static size_t round(size_t b) {
+    if (b == 0) b = 1;
+    const size_t g = b >= (size_t(1) << 20) ? (size_t(1) << 20) : 256;
+    return (b + g - 1) / g * g;
+  }
+  std::mutex mu_;
+  std::multimap<size_t, Blk> free_;
+  size_t cached_ = 0;
+};
+
+// Stream on which the calling thread's library work runs; device buffers
+// record it so the pool can order their reuse.
+inline hipStream_t& current_stream() {
+  static thread_local hipStream_t s = nullptr;
+  return s;
+}
+
+struct StreamScope {
+  hipStream_t prev;
+  explicit StreamScope(hipStream_t s) : prev(current_stream()) { current_stream() = s; }
+  ~StreamScope() { current_stream() = prev; }
+};
+
+}  // namespace kb

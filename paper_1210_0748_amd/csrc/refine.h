@@ -33,7 +33,8 @@
 namespace kb {
 
 constexpr uint32_t kSmallCap = 64;     // groups handled by one wave
-constexpr uint32_t kMediumCap = 2048;  // largest group one workgroup can order in LDS
+constexpr uint32_t kMediumCap = 1024;  // largest group one workgroup can order in LDS
+constexpr uint32_t kMediumCapSmall = 512;  // LDS size class for medium_cap <= 512
 constexpr int kMediumNT = 256;
 constexpr uint32_t kNoDiff = 0xffffffffu;
 constexpr uint32_t kUndecided = 0xfffffffeu;
@@ -159,10 +160,23 @@ __device__ __forceinline__ uint32_t block_inclusive_max(uint32_t v, uint32_t* sh
   return v > before ? v : before;
 }
 
+// Side of a member relative to the subgroup's leader, from the first
+// position d where they differ: below (0) when the member's digit there is
+// smaller, above (2) when larger; identical members are "equal" (1).
+// Ordering members by (side, d ascending for below / descending for above,
+// digits from d on) is their lexicographic order, except among members
+// with equal (side, d, digits), which agree on all positions before
+// d + width and form the next subgroups.
+__device__ __forceinline__ uint64_t side_key(uint32_t side, uint32_t rel) {
+  // below: rel ascending; equal; above: rel descending
+  return side == 0 ? uint64_t(rel) : side == 1 ? (1ull << 32) : ((2ull << 32) | uint64_t(0xffffffffu - rel));
+}
+
 // Orders the members of one group (positions [s, s+m) of ord, m <= CAP,
 // all agreeing on keys before gdepth) lexicographically and sets flag[] at
 // the first position of every class inside the group (the group's own first
-// position is already flagged).
+// position is already flagged). Each iteration splits every open subgroup
+// around its first member as a pivot (see side_key).
 template <int NT, int CAP, typename KeyT>
 __global__ __launch_bounds__(NT) void resolve_k(const uint32_t* __restrict__ gstart,
                                                 const uint32_t* __restrict__ gsize,
@@ -170,11 +184,11 @@ __global__ __launch_bounds__(NT) void resolve_k(const uint32_t* __restrict__ gst
                                                 uint32_t* __restrict__ ord, uint8_t* __restrict__ flag,
                                                 KeyView<KeyT> kv) {
   __shared__ uint32_t node[CAP];
-  __shared__ uint32_t sub[CAP];   // index of the subgroup's first member
-  __shared__ uint32_t dep[CAP];   // depth of the member's subgroup
-  __shared__ uint32_t fdm[CAP];   // per leader: split position of its subgroup
-  __shared__ uint64_t dig[CAP];
-  __shared__ uint8_t res[CAP];    // member's subgroup is closed
+  __shared__ uint32_t sub[CAP];    // index of the subgroup's first member (the pivot)
+  __shared__ uint32_t dep[CAP];    // depth of the member's subgroup
+  __shared__ uint64_t hk[CAP];     // first difference with the pivot, then side_key
+  __shared__ uint64_t dig[CAP];    // packed digits from the first difference on
+  __shared__ uint8_t res[CAP];     // member's subgroup is closed
   __shared__ uint8_t mark[CAP];
   __shared__ uint32_t queue[CAP];  // members whose comparison needs a whole wave
   __shared__ uint32_t qn;
@@ -192,66 +206,77 @@ __global__ __launch_bounds__(NT) void resolve_k(const uint32_t* __restrict__ gst
     sub[i] = in ? 0u : 0xffffffffu;
     dep[i] = d0;
     res[i] = in ? 0 : 1;
+    hk[i] = in ? 0ull : ~0ull;
     dig[i] = in ? 0ull : ~0ull;
   }
   __syncthreads();
 
   for (;;) {
-    // (a) split position of every open subgroup: each thread compares its
-    // members over a short window; members that still agree are queued and
-    // compared by whole waves, 64 positions per step.
-    for (uint32_t i = threadIdx.x; i < m; i += NT) fdm[i] = kNoDiff;
+    // (a) first difference of every open member with its pivot: a short
+    // window per thread, then whole waves (64 positions per step)
     if (threadIdx.x == 0) qn = 0;
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < m; i += NT) {
+      uint32_t d = kNoDiff;
       const uint32_t L = sub[i];
       if (!res[i] && i != L) {
-        const uint32_t d = kv.first_diff_window(node[i], node[L], dep[i], kThreadWindow);
-        if (d == kUndecided)
-          queue[atomicAdd(&qn, 1u)] = i;
-        else if (d != kNoDiff)
-          atomicMin(&fdm[L], d);
+        d = kv.first_diff_window(node[i], node[L], dep[i], kThreadWindow);
+        if (d == kUndecided) queue[atomicAdd(&qn, 1u)] = i;
       }
+      hk[i] = d;
     }
     __syncthreads();
     for (uint32_t q = threadIdx.x / kWave; q < qn; q += NT / kWave) {
       const uint32_t i = queue[q];
-      const uint32_t L = sub[i];
-      const uint32_t d = kv.wave_first_diff(node[i], node[L], dep[i] + kThreadWindow);
-      if (__lane_id() == 0 && d != kNoDiff) atomicMin(&fdm[L], d);
+      const uint32_t d = kv.wave_first_diff(node[i], node[sub[i]], dep[i] + kThreadWindow);
+      if (__lane_id() == 0) hk[i] = d;
     }
     __syncthreads();
+
+    // (b) sort keys: (side, distance of the first difference, digits there)
     bool open = false;
     for (uint32_t i = threadIdx.x; i < m; i += NT) {
-      if (!res[i]) {
-        const uint32_t d = fdm[sub[i]];
-        if (d == kNoDiff) {
-          res[i] = 1;  // identical signatures (or a single member)
-          dig[i] = 0;
-        } else {
-          open = true;
-          dig[i] = kv.digits(node[i], d, width);
-          dep[i] = d + width;
-        }
-      } else {
+      if (res[i]) {
+        hk[i] = 0;
         dig[i] = 0;
+        continue;
+      }
+      const uint32_t d = uint32_t(hk[i]);
+      if (d == kNoDiff) {
+        hk[i] = side_key(1, 0);
+        dig[i] = 0;
+      } else {
+        const uint32_t L = sub[i];
+        const uint64_t da = kv.digit(node[i], d), dl = kv.digit(node[L], d);
+        hk[i] = side_key(da < dl ? 0u : 2u, d - dep[i]);
+        dig[i] = kv.digits(node[i], d, width);
+        dep[i] = d + width;
+        open = true;
       }
     }
-    if (!__syncthreads_or(open)) break;
+    if (!__syncthreads_or(open)) {
+      // every open subgroup consists of copies of its pivot: one class each
+      for (uint32_t i = threadIdx.x; i < m; i += NT) res[i] = 1;
+      __syncthreads();
+      break;
+    }
 
-    // (b) sort by (subgroup, digit); subgroups keep their position ranges
+    // (c) sort by (subgroup, side key, digits); subgroups keep their ranges
     for (uint32_t size = 2; size <= P; size <<= 1) {
       for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
         for (uint32_t i = threadIdx.x; i < P / 2; i += NT) {
           const uint32_t lo = 2 * i - (i & (stride - 1));
           const uint32_t hi = lo + stride;
           const bool up = (lo & size) == 0;
-          const bool gt = sub[lo] != sub[hi] ? sub[lo] > sub[hi] : dig[lo] > dig[hi];
+          const bool gt = sub[lo] != sub[hi] ? sub[lo] > sub[hi]
+                          : hk[lo] != hk[hi] ? hk[lo] > hk[hi]
+                                             : dig[lo] > dig[hi];
           if (gt == up) {
             uint32_t tu = sub[lo]; sub[lo] = sub[hi]; sub[hi] = tu;
             tu = node[lo]; node[lo] = node[hi]; node[hi] = tu;
             tu = dep[lo]; dep[lo] = dep[hi]; dep[hi] = tu;
-            const uint64_t td = dig[lo]; dig[lo] = dig[hi]; dig[hi] = td;
+            uint64_t td = hk[lo]; hk[lo] = hk[hi]; hk[hi] = td;
+            td = dig[lo]; dig[lo] = dig[hi]; dig[hi] = td;
             const uint8_t tr = res[lo]; res[lo] = res[hi]; res[hi] = tr;
           }
         }
@@ -259,9 +284,10 @@ __global__ __launch_bounds__(NT) void resolve_k(const uint32_t* __restrict__ gst
       }
     }
 
-    // (c) split where the digit changes; close ended and single subgroups
+    // (d) split where the key changes; close copies of the pivot, ended
+    // sequences and single members
     for (uint32_t i = threadIdx.x; i < m; i += NT)
-      mark[i] = (i == 0 || sub[i] != sub[i - 1] || dig[i] != dig[i - 1]) ? 1 : 0;
+      mark[i] = (i == 0 || sub[i] != sub[i - 1] || hk[i] != hk[i - 1] || dig[i] != dig[i - 1]) ? 1 : 0;
     __syncthreads();
     uint32_t carry = 0;
     for (uint32_t base = 0; base < m; base += NT) {
@@ -278,7 +304,8 @@ __global__ __launch_bounds__(NT) void resolve_k(const uint32_t* __restrict__ gst
       if (mark[i] && i > 0) flag[s + i] = 1;
       if (!res[i]) {
         const bool single = mark[i] && (i + 1 == m || mark[i + 1]);
-        if ((dig[i] & kv.last_digit_mask()) == 0 || single) res[i] = 1;
+        const bool copies = (hk[i] >> 32) == 1;
+        if (copies || (dig[i] & kv.last_digit_mask()) == 0 || single) res[i] = 1;
       }
     }
     __syncthreads();
@@ -306,12 +333,19 @@ __global__ void blocks_as_segments_k(const uint32_t* __restrict__ bstart, uint32
 // Open segments of up to kSmallCap members go to the wave resolver, up to
 // medium_cap (<= kMediumCap) to the workgroup resolver, the rest to the
 // global pass.
+// nseg is an upper bound; when nseg_dev is given, segments at or past
+// *nseg_dev get no class.
 __global__ void classify_segments_k(const uint32_t* __restrict__ seg_size,
                                     const uint8_t* __restrict__ seg_done, uint32_t nseg,
-                                    uint32_t medium_cap, uint32_t* __restrict__ c_small,
-                                    uint32_t* __restrict__ c_medium, uint32_t* __restrict__ c_large) {
+                                    const uint32_t* __restrict__ nseg_dev, uint32_t medium_cap,
+                                    uint32_t* __restrict__ c_small, uint32_t* __restrict__ c_medium,
+                                    uint32_t* __restrict__ c_large) {
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= nseg) return;
+  if (nseg_dev && j >= *nseg_dev) {
+    c_small[j] = c_medium[j] = c_large[j] = 0;
+    return;
+  }
   const uint32_t z = seg_size[j];
   const bool done = seg_done[j] || z <= 1;
   c_small[j] = !done && z <= kSmallCap;
@@ -354,49 +388,34 @@ __device__ __forceinline__ uint32_t group_of_item(const uint32_t* ioff, uint32_t
   return lo;
 }
 
-// split[g] = min over members of the first difference with the leader.
-// Each thread compares one member over a short window; members that still
-// agree are appended to `longq` for large_split_pos_wave_k.
+// fdv[i] = first difference of item i's sequence with its group leader's
+// (kNoDiff for the leader and its copies). Each thread compares one item
+// over a short window; items that still agree are appended to `longq` for
+// large_fd_wave_k.
 template <typename KeyT>
-__global__ __launch_bounds__(256) void large_split_pos_k(
+__global__ __launch_bounds__(256) void large_fd_k(
     const uint32_t* __restrict__ gstart, const uint32_t* __restrict__ gdepth, const uint32_t* __restrict__ ioff,
-    uint32_t ng, uint32_t nitems, const uint32_t* __restrict__ ord, uint32_t* __restrict__ split,
+    uint32_t ng, uint32_t nitems, const uint32_t* __restrict__ ord, uint32_t* __restrict__ fdv,
     uint32_t* __restrict__ longq, uint32_t* __restrict__ nlong, KeyView<KeyT> kv) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool in = i < nitems;
-  uint32_t g = 0, d = kNoDiff;
-  if (in) {
-    g = group_of_item(ioff, ng, i);
-    const uint32_t a = ord[gstart[g] + (i - ioff[g])];
-    const uint32_t b = ord[gstart[g]];
-    if (a != b) {
-      d = kv.first_diff_window(a, b, gdepth[g], kThreadWindow);
-      if (d == kUndecided) {
-        longq[atomicAdd(nlong, 1u)] = i;
-        d = kNoDiff;
-      }
-    }
+  if (i >= nitems) return;
+  const uint32_t g = group_of_item(ioff, ng, i);
+  const uint32_t a = ord[gstart[g] + (i - ioff[g])];
+  const uint32_t b = ord[gstart[g]];
+  uint32_t d = kNoDiff;
+  if (a != b) {
+    d = kv.first_diff_window(a, b, gdepth[g], kThreadWindow);
+    if (d == kUndecided) longq[atomicAdd(nlong, 1u)] = i;
   }
-  // Members of one group are contiguous, so a wave usually covers a single
-  // group: reduce there and issue one atomic, and only when it can lower the
-  // stored minimum (huge groups would otherwise serialise on one address).
-  const uint32_t g0 = __shfl(g, 0, kWave);
-  const bool uniform = __ballot(in && g != g0) == 0;
-  if (uniform) {
-    const uint32_t dm = wave_min(d);
-    if (__lane_id() == 0 && dm != kNoDiff && dm < split[g0]) atomicMin(&split[g0], dm);
-  } else if (in && d != kNoDiff && d < split[g]) {
-    atomicMin(&split[g], d);
-  }
+  fdv[i] = d;
 }
 
-// One wave per queued member, grid-stride over the queue length in *nlong.
+// One wave per queued item, grid-stride over the queue length in *nlong.
 template <typename KeyT>
-__global__ void large_split_pos_wave_k(const uint32_t* __restrict__ gstart, const uint32_t* __restrict__ gdepth,
-                                       const uint32_t* __restrict__ ioff, uint32_t ng,
-                                       const uint32_t* __restrict__ ord, uint32_t* __restrict__ split,
-                                       const uint32_t* __restrict__ longq, const uint32_t* __restrict__ nlong,
-                                       KeyView<KeyT> kv) {
+__global__ void large_fd_wave_k(const uint32_t* __restrict__ gstart, const uint32_t* __restrict__ gdepth,
+                                const uint32_t* __restrict__ ioff, uint32_t ng, const uint32_t* __restrict__ ord,
+                                uint32_t* __restrict__ fdv, const uint32_t* __restrict__ longq,
+                                const uint32_t* __restrict__ nlong, KeyView<KeyT> kv) {
   const uint32_t nq = *nlong;
   const uint32_t waves = gridDim.x * (blockDim.x / kWave);
   for (uint32_t q = (blockIdx.x * blockDim.x + threadIdx.x) / kWave; q < nq; q += waves) {
@@ -405,81 +424,131 @@ __global__ void large_split_pos_wave_k(const uint32_t* __restrict__ gstart, cons
     const uint32_t a = ord[gstart[g] + (i - ioff[g])];
     const uint32_t b = ord[gstart[g]];
     const uint32_t d = kv.wave_first_diff(a, b, gdepth[g] + kThreadWindow);
-    if (__lane_id() == 0 && d != kNoDiff) atomicMin(&split[g], d);
+    if (__lane_id() == 0) fdv[i] = d;
   }
 }
 
-__global__ void open_flags_k(const uint32_t* __restrict__ split, uint32_t n, uint32_t* __restrict__ out) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = split[i] != kNoDiff;
-}
+// Layout of the global sort key of an item of group g (see side_key):
+//   hi = g << (2 + fd_bits) | side << fd_bits | fdkey
+//   lo = `width` packed digits from the first difference on
+// fdkey = distance of the first difference from the group depth (below),
+// or its complement in fd_bits (above). Packed into one word as
+// hi << dig_bits | lo when it fits, else kept as two words.
+struct LargeKey {
+  int fd_bits;
+  int dig_bits;   // width * dbits
+  uint32_t width;
+  bool packed;
+  __device__ __forceinline__ uint64_t hi_of(const uint64_t* ka, const uint64_t* kb, uint32_t i) const {
+    return packed ? (dig_bits >= 64 ? 0ull : ka[i] >> dig_bits) : ka[i];
+  }
+  __device__ __forceinline__ uint64_t lo_of(const uint64_t* ka, const uint64_t* kb, uint32_t i) const {
+    return packed ? (dig_bits >= 64 ? ka[i] : (ka[i] & ((1ull << dig_bits) - 1))) : kb[i];
+  }
+};
 
-// Sort keys of the open large groups: (group << dig_bits) | the `width`
-// packed digits from split[g] on (dig_bits = width * kv.dbits). Items are
-// numbered from item_base (ioff holds absolute item offsets).
 template <typename KeyT>
-__global__ void large_gather_k(const uint32_t* __restrict__ gstart, const uint32_t* __restrict__ gpos,
+__global__ void large_gather_k(const uint32_t* __restrict__ gstart, const uint32_t* __restrict__ gdepth,
                                const uint32_t* __restrict__ ioff, uint32_t ng, uint32_t nitems,
-                               uint32_t item_base, const uint32_t* __restrict__ ord, int dig_bits,
-                               uint32_t width, uint64_t* __restrict__ key, uint32_t* __restrict__ val,
+                               const uint32_t* __restrict__ ord, const uint32_t* __restrict__ fdv, LargeKey lk,
+                               uint64_t* __restrict__ ka, uint64_t* __restrict__ kb, uint32_t* __restrict__ val,
                                KeyView<KeyT> kv) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nitems) return;
-  const uint32_t ia = item_base + i;
-  const uint32_t g = group_of_item(ioff, ng, ia);
-  const uint32_t node = ord[gstart[g] + (ia - ioff[g])];
-  const uint64_t hi = dig_bits >= 64 ? 0ull : (uint64_t(g) << dig_bits);
-  key[i] = hi | kv.digits(node, gpos[g], width);
+  const uint32_t g = group_of_item(ioff, ng, i);
+  const uint32_t node = ord[gstart[g] + (i - ioff[g])];
+  const uint32_t d = fdv[i];
+  uint64_t side = 1, fdkey = 0, lo = 0;
+  if (d != kNoDiff) {
+    const uint32_t leader = ord[gstart[g]];
+    const uint64_t fdmask = (1ull << lk.fd_bits) - 1;
+    const uint64_t rel = d - gdepth[g];
+    side = kv.digit(node, d) < kv.digit(leader, d) ? 0 : 2;
+    fdkey = side == 0 ? rel : (fdmask - rel);
+    lo = kv.digits(node, d, lk.width);
+  }
+  const uint64_t hi = (uint64_t(g) << (2 + lk.fd_bits)) | (side << lk.fd_bits) | fdkey;
+  if (lk.packed) {
+    ka[i] = (lk.dig_bits >= 64 ? 0ull : (hi << lk.dig_bits)) | lo;
+  } else {
+    ka[i] = hi;
+    kb[i] = lo;
+  }
   val[i] = node;
 }
 
 // After the sort: write members back to ord, flag class starts, and mark the
 // first item of every subgroup.
 __global__ void large_write_k(const uint32_t* __restrict__ gstart, const uint32_t* __restrict__ ioff,
-                              uint32_t nitems, uint32_t item_base, const uint64_t* __restrict__ key,
-                              const uint32_t* __restrict__ val, int dig_bits,
-                              uint32_t* __restrict__ ord, uint8_t* __restrict__ flag,
-                              uint32_t* __restrict__ start_flag, uint32_t* __restrict__ item_pos) {
+                              uint32_t nitems, const uint64_t* __restrict__ ka, const uint64_t* __restrict__ kb,
+                              const uint32_t* __restrict__ val, LargeKey lk, uint32_t* __restrict__ ord,
+                              uint8_t* __restrict__ flag, uint32_t* __restrict__ start_flag,
+                              uint32_t* __restrict__ item_pos) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nitems) return;
-  const uint32_t ia = item_base + i;
-  const uint32_t g = dig_bits >= 64 ? 0u : uint32_t(key[i] >> dig_bits);
-  const uint32_t p = gstart[g] + (ia - ioff[g]);
+  const uint64_t hi = lk.hi_of(ka, kb, i), lo = lk.lo_of(ka, kb, i);
+  const uint32_t g = uint32_t(hi >> (2 + lk.fd_bits));
+  const uint32_t p = gstart[g] + (i - ioff[g]);
   ord[p] = val[i];
   item_pos[i] = p;
-  const bool st = (ia == ioff[g]) || key[i] != key[i - 1];
+  const bool st = (i == ioff[g]) || hi != lk.hi_of(ka, kb, i - 1) || lo != lk.lo_of(ka, kb, i - 1);
   start_flag[i] = st;
-  if (st && ia != ioff[g]) flag[p] = 1;
+  if (st && i != ioff[g]) flag[p] = 1;
 }
 
-// Subgroup j starts at item S[j] (S = compacted start flags); its depth is
-// `width` past the split position of its group; it is closed when its
-// sequences ended inside the digits (last packed digit zero).
+// Subgroup j starts at item S[j] (S = compacted start flags). Its depth is
+// `width` past its first difference with the pivot; it is closed when it
+// holds copies of the pivot or its sequences ended inside the digits.
 __global__ void large_subgroups_k(const uint32_t* __restrict__ start_flag,
                                   const uint32_t* __restrict__ start_off, uint32_t nitems,
-                                  const uint32_t* __restrict__ item_pos, const uint64_t* __restrict__ key,
-                                  int dig_bits, uint32_t width, uint64_t last_mask,
-                                  const uint32_t* __restrict__ gpos, uint32_t* __restrict__ sub_item,
+                                  const uint32_t* __restrict__ item_pos, const uint64_t* __restrict__ ka,
+                                  const uint64_t* __restrict__ kb, LargeKey lk, uint64_t last_mask,
+                                  const uint32_t* __restrict__ gdepth, uint32_t* __restrict__ sub_item,
                                   uint32_t* __restrict__ seg_start, uint32_t* __restrict__ seg_depth,
                                   uint8_t* __restrict__ seg_done) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nitems) return;
   if (start_flag[i]) {
     const uint32_t j = start_off[i];
-    const uint32_t g = dig_bits >= 64 ? 0u : uint32_t(key[i] >> dig_bits);
+    const uint64_t hi = lk.hi_of(ka, kb, i), lo = lk.lo_of(ka, kb, i);
+    const uint64_t fdmask = (1ull << lk.fd_bits) - 1;
+    const uint32_t g = uint32_t(hi >> (2 + lk.fd_bits));
+    const uint32_t side = uint32_t(hi >> lk.fd_bits) & 3u;
+    const uint64_t fdkey = hi & fdmask;
+    const uint64_t rel = side == 0 ? fdkey : (fdmask - fdkey);
     sub_item[j] = i;
     seg_start[j] = item_pos[i];
-    seg_depth[j] = gpos[g] + width;
-    seg_done[j] = (key[i] & last_mask) == 0;
+    seg_depth[j] = side == 1 ? 0u : uint32_t(gdepth[g] + rel + lk.width);
+    seg_done[j] = side == 1 || (lo & last_mask) == 0;
   }
 }
 
-__global__ void subgroup_sizes_k(const uint32_t* __restrict__ sub_item, uint32_t ns, uint32_t nitems,
-                                 uint32_t* __restrict__ seg_size) {
+// ns_dev: number of subgroups (device); at most nitems.
+__global__ void subgroup_sizes_k(const uint32_t* __restrict__ sub_item, const uint32_t* __restrict__ ns_dev,
+                                 uint32_t nitems, uint32_t* __restrict__ seg_size) {
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t ns = *ns_dev;
   if (j >= ns) return;
   const uint32_t end = (j + 1 < ns) ? sub_item[j + 1] : nitems;
   seg_size[j] = end - sub_item[j];
+}
+
+// Two-word sort support: out[i] = in[idx[i]].
+__global__ void gather_u64_k(const uint64_t* __restrict__ in, const uint32_t* __restrict__ idx, uint32_t n,
+                             uint64_t* __restrict__ out) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = in[idx[i]];
+}
+
+// Final two-word order: lo_out[i] = lo[perm[i]], val_out[i] = val[idx1[perm[i]]].
+__global__ void two_word_finish_k(const uint64_t* __restrict__ lo, const uint32_t* __restrict__ idx1,
+                                  const uint32_t* __restrict__ perm, const uint32_t* __restrict__ val, uint32_t n,
+                                  uint64_t* __restrict__ lo_out, uint32_t* __restrict__ val_out) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t p = perm[i];
+  lo_out[i] = lo[p];
+  val_out[i] = val[idx1[p]];
 }
 
 // ---------------------------------------------------------------------------

@@ -138,41 +138,83 @@ __device__ __forceinline__ uint64_t match_digit8(uint32_t d, uint64_t valid_mask
   return m;
 }
 
-template <typename K, bool kHasVal>
+// Scatter of one 4096-item tile. Wave w owns the contiguous sub-tile
+// [w*1024, (w+1)*1024) and keeps its 16 rows of 64 items in registers.
+// The tile is first sorted by digit into LDS (per-wave digit counts give
+// every wave its local offsets; each wave places its rows in order with
+// wave-local counters, one LDS read and one write per row, which a wave
+// completes in order). Then consecutive threads copy consecutive LDS items
+// to their global positions, so each digit's run is written contiguously.
+// Stable: tile order = wave order, row order, lane order.
+template <typename K, typename V, bool kHasVal>
 __global__ __launch_bounds__(kRadixNT) void radix_scatter_k(
-    const K* __restrict__ kin, const uint32_t* __restrict__ vin, K* __restrict__ kout,
-    uint32_t* __restrict__ vout, uint64_t n, int shift, const uint32_t* __restrict__ hist_scan,
+    const K* __restrict__ kin, const V* __restrict__ vin, K* __restrict__ kout,
+    V* __restrict__ vout, uint64_t n, int shift, const uint32_t* __restrict__ hist_scan,
     uint32_t nblocks) {
-  __shared__ uint32_t base_d[256];
-  __shared__ uint32_t wcnt[kRadixNW][256];
-  for (int d = threadIdx.x; d < 256; d += kRadixNT) base_d[d] = hist_scan[uint64_t(d) * nblocks + blockIdx.x];
+  constexpr int kRows = kRadixIPT;
+  __shared__ uint32_t wh[kRadixNW][256];   // per-wave counts, then running local offsets
+  __shared__ uint32_t gdelta[256];         // global position - local position, per digit
+  __shared__ K sk[kRadixTile];
+  __shared__ V sv[kHasVal ? kRadixTile : 1];
+  for (int j = threadIdx.x; j < kRadixNW * 256; j += kRadixNT) (&wh[0][0])[j] = 0;
+  __syncthreads();
   const int w = threadIdx.x / kWave;
+  const int lane = __lane_id();
   const uint64_t tile = uint64_t(blockIdx.x) * kRadixTile;
-  for (int r = 0; r < kRadixIPT; ++r) {
-    for (int j = threadIdx.x; j < kRadixNW * 256; j += kRadixNT) (&wcnt[0][0])[j] = 0;
-    __syncthreads();
-    const uint64_t idx = tile + uint64_t(r) * kRadixNT + threadIdx.x;
+  const uint64_t sub = tile + uint64_t(w) * (kRows * kWave);
+  const uint32_t tile_n = uint32_t(n - tile < uint64_t(kRadixTile) ? n - tile : uint64_t(kRadixTile));
+  K key[kRows];
+  V val[kRows];
+  uint32_t dg[kRows];
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) {
+    const uint64_t idx = sub + uint64_t(r) * kWave + lane;
     const bool valid = idx < n;
-    const K key = valid ? kin[idx] : K(0);
-    const uint32_t d = valid ? (uint32_t(key >> shift) & 255u) : 0u;
+    key[r] = valid ? kin[idx] : K(0);
+    if (kHasVal) val[r] = valid ? vin[idx] : V(0);
+    dg[r] = valid ? (uint32_t(key[r] >> shift) & 255u) : 256u;
+  }
+#pragma unroll
+  for (int r = 0; r < kRows; ++r)
+    if (dg[r] < 256u) atomicAdd(&wh[w][dg[r]], 1u);
+  __syncthreads();
+  {
+    // local exclusive prefix over (digit, wave), and the global shift per digit
+    const int d = threadIdx.x;  // kRadixNT == 256: one digit per thread
+    uint32_t tot = 0;
+#pragma unroll
+    for (int q = 0; q < kRadixNW; ++q) tot += wh[q][d];
+    __shared__ uint32_t shs[kRadixNW];
+    uint32_t all;
+    uint32_t local = block_exclusive_scan<kRadixNT>(tot, shs, &all);
+    gdelta[d] = hist_scan[uint64_t(d) * nblocks + blockIdx.x] - local;
+#pragma unroll
+    for (int q = 0; q < kRadixNW; ++q) {
+      const uint32_t c = wh[q][d];
+      wh[q][d] = local;
+      local += c;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) {
+    const bool valid = dg[r] < 256u;
+    const uint32_t d = valid ? dg[r] : 0u;
     const uint64_t m = match_digit8(d, __ballot(valid));
     const uint32_t rank = __popcll(m & lanemask_lt());
-    if (valid && rank == 0) wcnt[w][d] = __popcll(m);
-    __syncthreads();
+    const uint32_t pos = wh[w][d] + rank;
     if (valid) {
-      uint32_t off = base_d[d] + rank;
-      for (int q = 0; q < w; ++q) off += wcnt[q][d];
-      kout[off] = key;
-      if (kHasVal) vout[off] = vin[idx];
+      sk[pos] = key[r];
+      if (kHasVal) sv[pos] = val[r];
     }
-    __syncthreads();
-    for (int dd = threadIdx.x; dd < 256; dd += kRadixNT) {
-      uint32_t s = 0;
-#pragma unroll
-      for (int q = 0; q < kRadixNW; ++q) s += wcnt[q][dd];
-      base_d[dd] += s;
-    }
-    __syncthreads();
+    if (valid && rank == 0) wh[w][d] = pos + __popcll(m);
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < tile_n; i += kRadixNT) {
+    const K k = sk[i];
+    const uint32_t pos = gdelta[uint32_t(k >> shift) & 255u] + i;
+    kout[pos] = k;
+    if (kHasVal) vout[pos] = sv[i];
   }
 }
 
@@ -186,8 +228,8 @@ inline size_t radix_scratch_words(uint64_t n) {
 // Sorts (keys, vals) of length n by bits [begin_bit, end_bit) of the key,
 // stably. Ping-pongs between (k0,v0) and (k1,v1); returns true when the
 // result ends in (k1,v1). vals may be null (keys only).
-template <typename K>
-bool radix_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, uint64_t n, int begin_bit, int end_bit,
+template <typename K, typename V = uint32_t>
+bool radix_sort(K* k0, V* v0, K* k1, V* v1, uint64_t n, int begin_bit, int end_bit,
                 uint32_t* scratch, hipStream_t s) {
   if (n <= 1 || end_bit <= begin_bit) return false;
   const uint32_t nb = radix_blocks(n);
@@ -197,15 +239,15 @@ bool radix_sort(K* k0, uint32_t* v0, K* k1, uint32_t* v1, uint64_t n, int begin_
   for (int shift = begin_bit; shift < end_bit; shift += 8) {
     const K* ki = flip ? k1 : k0;
     K* ko = flip ? k0 : k1;
-    const uint32_t* vi = flip ? v1 : v0;
-    uint32_t* vo = flip ? v0 : v1;
+    const V* vi = flip ? v1 : v0;
+    V* vo = flip ? v0 : v1;
     radix_hist_k<K><<<nb, kRadixNT, 0, s>>>(ki, n, shift, hist, nb);
     KB_LAUNCH_CHECK();
     scan<uint32_t, uint32_t, false>(hist, hist, uint64_t(nb) * 256, part, s);
     if (v0 != nullptr)
-      radix_scatter_k<K, true><<<nb, kRadixNT, 0, s>>>(ki, vi, ko, vo, n, shift, hist, nb);
+      radix_scatter_k<K, V, true><<<nb, kRadixNT, 0, s>>>(ki, vi, ko, vo, n, shift, hist, nb);
     else
-      radix_scatter_k<K, false><<<nb, kRadixNT, 0, s>>>(ki, nullptr, ko, nullptr, n, shift, hist, nb);
+      radix_scatter_k<K, V, false><<<nb, kRadixNT, 0, s>>>(ki, nullptr, ko, nullptr, n, shift, hist, nb);
     KB_LAUNCH_CHECK();
     flip = !flip;
   }

@@ -217,3 +217,14 @@ def test_key_width_exactly_32():
     node_label = rng.integers(0, 4, size=n).astype(np.int32)
     g = synth.Graph(n, node_label, src, lab, dst, name="key32")
     check_parity(g, 2)
+
+
+def test_large_label_values():
+    """Label values up to 2^31 - 1 (ranked by sorting instead of a table)."""
+    rng = np.random.default_rng(29)
+    n, e = 5000, 30000
+    vals = np.array([0, 7, 1 << 24, (1 << 31) - 1, 123456789], np.int32)
+    g = synth.Graph(n, vals[rng.integers(0, 5, size=n)], rng.integers(0, n, size=e).astype(np.int32),
+                    vals[rng.integers(0, 5, size=e)], rng.integers(0, n, size=e).astype(np.int32),
+                    name="biglabels")
+    check_parity(g, 5)
