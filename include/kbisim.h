@@ -132,6 +132,82 @@ kbisim_status kbisim_work(const kbisim_graph* g, int64_t* nodes_edges, int32_t c
 /* Frees everything owned by the handle. NULL is ignored. */
 void kbisim_destroy(kbisim_graph* g);
 
+/* ---- Batched form ---------------------------------------------------------
+ * Many independent graphs refined together: every kernel launch of a round
+ * serves all of them (a union of the graphs whose node ids and labels are
+ * kept apart per graph). Results are per graph and identical to refining
+ * each graph alone with kbisim_create/kbisim_refine.
+ *
+ * The graphs are concatenated in one kbisim_graph_desc: graph g owns nodes
+ * [node_off[g], node_off[g+1]) and edges [edge_off[g], edge_off[g+1]) of the
+ * arrays; edge endpoints are LOCAL node ids of their graph (0 .. N_g - 1).
+ * node_off and edge_off are host arrays of num_graphs + 1 entries starting at
+ * 0; desc->num_nodes / num_edges must equal their last entries. */
+typedef struct kbisim_batch kbisim_batch;
+
+kbisim_status kbisim_batch_create(int32_t num_graphs, const int64_t* node_off, const int64_t* edge_off,
+                                  const kbisim_graph_desc* concat, const kbisim_options* opt,
+                                  kbisim_batch** out);
+
+/* Refines graph g for up to k_per_graph[g] rounds (host array, each >= 0),
+ * stopping a graph at its own fixed point when early stop is on. One call
+ * per batch (a second call is KBISIM_ESTATE). rounds_done (host, [num_graphs],
+ * may be NULL) receives each graph's executed rounds. */
+kbisim_status kbisim_batch_refine(kbisim_batch* b, const int32_t* k_per_graph, int32_t* rounds_done);
+
+/* pid_out[sum N] (host or device): every graph's local ids, graph after graph;
+ * num_blocks (host, [num_graphs], may be NULL): each graph's block count. */
+kbisim_status kbisim_batch_result(const kbisim_batch* b, int32_t* pid_out, kbisim_mem mem,
+                                  int64_t* num_blocks);
+
+void kbisim_batch_destroy(kbisim_batch* b);
+
+/* ---- Served form ----------------------------------------------------------
+ * A request loop for many jobs of different sizes on one GPU. Requests queue
+ * in FIFO order; a request is admitted when one of max_slots slots is free
+ * and its estimated device footprint (about 36 B per edge + 96 B per node +
+ * 64 MB) fits in what hbm_budget_bytes has left. Admitted requests run
+ * concurrently, each on its own stream with its partition state resident in
+ * device memory across rounds, so requests that arrive while others run
+ * overlap with them on the device. Results equal those of kbisim_refine on
+ * the same graph alone. desc->stream is ignored. Host input arrays are
+ * copied by submit; DEVICE input arrays are read when the request runs and
+ * must stay valid until kbisim_server_wait has returned for it. opt may be
+ * NULL; its profile field is ignored. */
+typedef struct kbisim_server kbisim_server;
+
+kbisim_status kbisim_server_create(uint64_t hbm_budget_bytes, int32_t max_slots, const kbisim_options* opt,
+                                   kbisim_server** out);
+
+/* Queues a job refining desc's graph up to k rounds. KBISIM_ENOMEM when its
+ * footprint exceeds the whole budget (it could never run). */
+kbisim_status kbisim_server_submit(kbisim_server* s, const kbisim_graph_desc* desc, int32_t k,
+                                   uint64_t* req_id);
+
+/* Waits up to timeout_s seconds (negative: no limit) for the request. On
+ * success writes pid_out[N] (host or device), *num_blocks and *rounds_done
+ * (each may be NULL). Returns KBISIM_ETIMEDOUT, KBISIM_ECANCELED, or the
+ * request's own error (e.g. KBISIM_EINVAL for an invalid graph) otherwise. */
+kbisim_status kbisim_server_wait(kbisim_server* s, uint64_t req_id, int32_t* pid_out, kbisim_mem mem,
+                                 int64_t* num_blocks, int32_t* rounds_done, double timeout_s);
+
+/* Cancels a queued request at once, a running one at its next round
+ * boundary; KBISIM_ESTATE if it already finished. */
+kbisim_status kbisim_server_cancel(kbisim_server* s, uint64_t req_id);
+
+/* Seconds from submit to start (queued_s) and to completion (total_s) of a
+ * completed request; KBISIM_ESTATE otherwise. */
+kbisim_status kbisim_server_timing(kbisim_server* s, uint64_t req_id, double* queued_s, double* total_s);
+
+/* Forgets a finished request (its results); unknown or unfinished ids are ignored. */
+kbisim_status kbisim_server_release(kbisim_server* s, uint64_t req_id);
+
+/* Device bytes currently reserved by running requests (their estimates). */
+kbisim_status kbisim_server_in_use(kbisim_server* s, uint64_t* bytes);
+
+/* Cancels queued and running requests, waits for the workers, frees all. */
+void kbisim_server_destroy(kbisim_server* s);
+
 /* The library keeps freed device memory in a process-wide cache for reuse by
  * later handles (allocation is slow). This returns every cached block to
  * the HIP runtime after the device has finished with it; *released_bytes

@@ -66,6 +66,33 @@ def load_library():
     lib.kbisim_work.restype = ctypes.c_int
     lib.kbisim_release_cached.argtypes = [ctypes.POINTER(i64)]
     lib.kbisim_release_cached.restype = ctypes.c_int
+    lib.kbisim_batch_create.argtypes = [i32, vp, vp, ctypes.POINTER(GraphDesc), ctypes.POINTER(Options),
+                                        ctypes.POINTER(vp)]
+    lib.kbisim_batch_create.restype = ctypes.c_int
+    lib.kbisim_batch_refine.argtypes = [vp, vp, vp]
+    lib.kbisim_batch_refine.restype = ctypes.c_int
+    lib.kbisim_batch_result.argtypes = [vp, vp, ctypes.c_int, vp]
+    lib.kbisim_batch_result.restype = ctypes.c_int
+    lib.kbisim_batch_destroy.argtypes = [vp]
+    lib.kbisim_batch_destroy.restype = None
+    u64 = ctypes.c_uint64
+    lib.kbisim_server_create.argtypes = [u64, i32, ctypes.POINTER(Options), ctypes.POINTER(vp)]
+    lib.kbisim_server_create.restype = ctypes.c_int
+    lib.kbisim_server_submit.argtypes = [vp, ctypes.POINTER(GraphDesc), i32, ctypes.POINTER(u64)]
+    lib.kbisim_server_submit.restype = ctypes.c_int
+    lib.kbisim_server_wait.argtypes = [vp, u64, vp, ctypes.c_int, ctypes.POINTER(i64), ctypes.POINTER(i32),
+                                       ctypes.c_double]
+    lib.kbisim_server_wait.restype = ctypes.c_int
+    lib.kbisim_server_cancel.argtypes = [vp, u64]
+    lib.kbisim_server_cancel.restype = ctypes.c_int
+    lib.kbisim_server_timing.argtypes = [vp, u64, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    lib.kbisim_server_timing.restype = ctypes.c_int
+    lib.kbisim_server_release.argtypes = [vp, u64]
+    lib.kbisim_server_release.restype = ctypes.c_int
+    lib.kbisim_server_in_use.argtypes = [vp, ctypes.POINTER(u64)]
+    lib.kbisim_server_in_use.restype = ctypes.c_int
+    lib.kbisim_server_destroy.argtypes = [vp]
+    lib.kbisim_server_destroy.restype = None
     lib.kbisim_destroy.argtypes = [vp]
     lib.kbisim_destroy.restype = None
     lib.kbisim_status_str.argtypes = [ctypes.c_int]
@@ -250,3 +277,157 @@ def refine(num_nodes, node_label, src, elab, dst, k, **kw):
         rd = g.refine(k)
         pid, _, counts = g.result()
         return pid, counts, rd
+
+
+def _options(early_stop=True, profile=False, medium_cap=None):
+    lib = load_library()
+    opt = Options()
+    lib.kbisim_options_default(ctypes.byref(opt))
+    opt.early_stop = 1 if early_stop else 0
+    opt.profile = 1 if profile else 0
+    if medium_cap is not None:
+        opt.medium_cap = int(medium_cap)
+    return opt
+
+
+def kbisim_batch_create(node_off, edge_off, node_label, src, elab, dst, *, stream=None, **kw):
+    """Batch of graphs concatenated in the four arrays (local endpoint ids);
+    node_off / edge_off: num_graphs + 1 offsets. Returns the handle."""
+    lib = load_library()
+    mem, ptrs, keep = _arrays(node_label, src, elab, dst)
+    noff = np.ascontiguousarray(np.asarray(node_off, dtype=np.int64))
+    eoff = np.ascontiguousarray(np.asarray(edge_off, dtype=np.int64))
+    G = int(noff.shape[0]) - 1
+    desc = GraphDesc(int(noff[-1]), int(eoff[-1]), ptrs[0] or None, ptrs[1] or None, ptrs[2] or None,
+                     ptrs[3] or None, mem, _stream_ptr(stream))
+    opt = _options(**kw)
+    h = ctypes.c_void_p()
+    _check(lib.kbisim_batch_create(G, noff.ctypes.data, eoff.ctypes.data, ctypes.byref(desc),
+                                   ctypes.byref(opt), ctypes.byref(h)))
+    return h, G
+
+
+def kbisim_batch_refine(handle, k_per_graph):
+    k = np.ascontiguousarray(np.asarray(k_per_graph, dtype=np.int32))
+    rd = np.zeros(k.shape[0], np.int32)
+    _check(load_library().kbisim_batch_refine(handle, k.ctypes.data, rd.ctypes.data))
+    return rd
+
+
+def kbisim_batch_result(handle, num_graphs, pid_out):
+    """pid_out: numpy int32 array or torch CUDA int32 tensor of sum N. Returns blocks per graph."""
+    blocks = np.zeros(num_graphs, np.int64)
+    if isinstance(pid_out, np.ndarray):
+        mem, ptr = KBISIM_MEM_HOST, (pid_out.ctypes.data if pid_out.size else None)
+    else:
+        mem, ptr = KBISIM_MEM_DEVICE, (pid_out.data_ptr() if pid_out.numel() else None)
+    _check(load_library().kbisim_batch_result(handle, ptr, mem, blocks.ctypes.data))
+    return blocks
+
+
+def kbisim_batch_destroy(handle):
+    if handle:
+        load_library().kbisim_batch_destroy(handle)
+
+
+def refine_batch(graphs, k, device=None, **kw):
+    """Refines a list of graphs (objects with num_nodes, node_label, src, elab,
+    dst) as one batch. k: int or per-graph list. Returns (list of id arrays,
+    blocks, rounds_done)."""
+    noff = np.zeros(len(graphs) + 1, np.int64)
+    eoff = np.zeros(len(graphs) + 1, np.int64)
+    for i, g in enumerate(graphs):
+        noff[i + 1] = noff[i] + int(g.num_nodes)
+        eoff[i + 1] = eoff[i] + int(np.asarray(g.src).shape[0])
+    cat = lambda name: np.concatenate([np.asarray(getattr(g, name), np.int32) for g in graphs]) \
+        if graphs else np.zeros(0, np.int32)
+    arrs = [cat("node_label"), cat("src"), cat("elab"), cat("dst")]
+    if device is not None:
+        import torch
+        arrs = [torch.from_numpy(a).to(device) for a in arrs]
+    ks = [int(k)] * len(graphs) if np.isscalar(k) else list(k)
+    h, G = kbisim_batch_create(noff, eoff, *arrs, **kw)
+    try:
+        rd = kbisim_batch_refine(h, ks)
+        out = np.empty(int(noff[-1]), np.int32)
+        blocks = kbisim_batch_result(h, G, out)
+    finally:
+        kbisim_batch_destroy(h)
+    pids = [out[noff[i]:noff[i + 1]] for i in range(len(graphs))]
+    return pids, [int(b) for b in blocks], [int(r) for r in rd]
+
+
+class Server:
+    """Binding of the served form (kbisim_server_*)."""
+
+    def __init__(self, hbm_budget_bytes, max_slots=4, **kw):
+        lib = load_library()
+        opt = _options(**kw)
+        h = ctypes.c_void_p()
+        _check(lib.kbisim_server_create(int(hbm_budget_bytes), int(max_slots), ctypes.byref(opt),
+                                        ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+        self._n = {}
+
+    def submit(self, num_nodes, node_label, src, elab, dst, k):
+        """Host arrays are copied; device (torch) arrays are referenced and
+        kept alive here until the request has been waited for."""
+        mem, ptrs, keep = _arrays(node_label, src, elab, dst)
+        n, m = int(num_nodes), int(keep[1].shape[0])
+        desc = GraphDesc(n, m, ptrs[0] or None, ptrs[1] or None, ptrs[2] or None, ptrs[3] or None, mem, None)
+        rid = ctypes.c_uint64(0)
+        _check(load_library().kbisim_server_submit(self._h, ctypes.byref(desc), int(k), ctypes.byref(rid)))
+        if mem == KBISIM_MEM_DEVICE:
+            self._keep[rid.value] = keep
+        self._n[rid.value] = n
+        return int(rid.value)
+
+    def wait(self, rid, timeout_s=-1.0):
+        """Returns (ids numpy array, num_blocks, rounds_done); raises KbisimError."""
+        n = self._n[rid]
+        out = np.empty(n, np.int32)
+        nb = ctypes.c_int64(0)
+        rd = ctypes.c_int32(0)
+        st = load_library().kbisim_server_wait(self._h, int(rid), out.ctypes.data if n else None,
+                                               KBISIM_MEM_HOST, ctypes.byref(nb), ctypes.byref(rd),
+                                               float(timeout_s))
+        if st != -7:  # anything but a time-out ends the request's use of its inputs
+            self._keep.pop(rid, None)
+        _check(st)
+        return out, int(nb.value), int(rd.value)
+
+    def cancel(self, rid):
+        _check(load_library().kbisim_server_cancel(self._h, int(rid)))
+
+    def timing(self, rid):
+        q, t = ctypes.c_double(0), ctypes.c_double(0)
+        _check(load_library().kbisim_server_timing(self._h, int(rid), ctypes.byref(q), ctypes.byref(t)))
+        return q.value, t.value
+
+    def release(self, rid):
+        _check(load_library().kbisim_server_release(self._h, int(rid)))
+        self._n.pop(rid, None)
+
+    def in_use(self):
+        b = ctypes.c_uint64(0)
+        _check(load_library().kbisim_server_in_use(self._h, ctypes.byref(b)))
+        return int(b.value)
+
+    def close(self):
+        if self._h:
+            load_library().kbisim_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

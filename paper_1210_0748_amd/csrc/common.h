@@ -24,6 +24,10 @@ struct OutOfMemory : std::runtime_error {
   using std::runtime_error::runtime_error;
 };
 
+struct StateError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+
 #define KB_CHECK(expr)                                                                      \
   do {                                                                                      \
     hipError_t kb_err_ = (expr);                                                            \

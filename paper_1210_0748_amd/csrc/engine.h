@@ -47,19 +47,13 @@ struct DevBuf {
   }
 };
 
-// Pinned host words for small device->host readbacks.
+// Pinned host words for small device->host readbacks (a slot of the
+// process-wide pinned slab; the slot's owner is the only user).
 struct HostWords {
   uint64_t* p = nullptr;
-  HostWords() {
-    if (hipHostMalloc(reinterpret_cast<void**>(&p), 64 * sizeof(uint64_t), hipHostMallocDefault) !=
-        hipSuccess) {
-      (void)hipGetLastError();
-      p = nullptr;
-      throw OutOfMemory("hipHostMalloc of readback words failed");
-    }
-  }
+  HostWords() : p(PinnedSlots::instance().acquire()) {}
   ~HostWords() {
-    if (p) (void)hipHostFree(p);
+    if (p) PinnedSlots::instance().release(p);
   }
   HostWords(const HostWords&) = delete;
   HostWords& operator=(const HostWords&) = delete;
@@ -93,6 +87,16 @@ class Engine {
   void refine(int32_t k);
   void result(int32_t* pid_out, bool to_device) const;
 
+  // One refinement round regardless of the fixed point (callers that track
+  // several graphs in one union decide when to stop).
+  void step_round() {
+    StreamScope scope(st_);
+    run_round();
+  }
+  const int32_t* pid_device() const { return pid_[cur_].as<int32_t>(); }
+  const uint32_t* ord_device() const { return ord_.as<uint32_t>(); }
+  hipStream_t stream() const { return st_; }
+  int64_t num_edges() const { return m_; }
   int64_t num_nodes() const { return n_; }
   int64_t blocks() const { return B_; }
   int32_t rounds_done() const { return rounds_; }

@@ -13,11 +13,13 @@
 #include <new>
 #include <string>
 
+#include "batch.h"
 #include "build.h"
 #include "common.h"
 #include "engine.h"
 #include "refine.h"
 #include "scan_radix.h"
+#include "server.h"
 #include "signature.h"
 #include "../../include/kbisim.h"
 
@@ -637,6 +639,394 @@ void Engine::result(int32_t* pid_out, bool to_device) const {
   KB_CHECK(hipStreamSynchronize(st_));
 }
 
+
+// ---------------------------------------------------------------------------
+// Batched form.
+
+Batch::Batch(int32_t G, const int64_t* node_off, const int64_t* edge_off, const int32_t* label, const int32_t* src,
+             const int32_t* lab, const int32_t* dst, bool host_mem, hipStream_t s, const Options& o)
+    : G_(G), st_(s), opt_(o) {
+  StreamScope scope(s);
+  if (G < 1) throw InvalidInput("num_graphs < 1");
+  node_off_.assign(node_off, node_off + G + 1);
+  edge_off_.assign(edge_off, edge_off + G + 1);
+  if (node_off_[0] != 0 || edge_off_[0] != 0) throw InvalidInput("offsets must start at 0");
+  for (int32_t g = 0; g < G; ++g)
+    if (node_off_[g + 1] < node_off_[g] || edge_off_[g + 1] < edge_off_[g])
+      throw InvalidInput("offsets must be non-decreasing");
+  ntot_ = node_off_[G];
+  etot_ = edge_off_[G];
+  if (ntot_ >= (int64_t(1) << 31)) throw InvalidInput("total nodes >= 2^31");
+  if (etot_ >= int64_t(0xffffffffll)) throw InvalidInput("total edges >= 2^32 - 1");
+  const uint64_t N = uint64_t(ntot_), E = uint64_t(etot_);
+  d_node_off_.ensure((G + 1) * 8);
+  d_edge_off_.ensure((G + 1) * 8);
+  KB_CHECK(hipMemcpyAsync(d_node_off_.p, node_off_.data(), (G + 1) * 8, hipMemcpyHostToDevice, s));
+  KB_CHECK(hipMemcpyAsync(d_edge_off_.p, edge_off_.data(), (G + 1) * 8, hipMemcpyHostToDevice, s));
+  DevBuf hl, hs, hb, hd;
+  if (host_mem) {
+    hl.ensure(std::max<uint64_t>(N, 1) * 4);
+    hs.ensure(std::max<uint64_t>(E, 1) * 4);
+    hb.ensure(std::max<uint64_t>(E, 1) * 4);
+    hd.ensure(std::max<uint64_t>(E, 1) * 4);
+    if (N) KB_CHECK(hipMemcpyAsync(hl.p, label, N * 4, hipMemcpyHostToDevice, s));
+    if (E) {
+      KB_CHECK(hipMemcpyAsync(hs.p, src, E * 4, hipMemcpyHostToDevice, s));
+      KB_CHECK(hipMemcpyAsync(hb.p, lab, E * 4, hipMemcpyHostToDevice, s));
+      KB_CHECK(hipMemcpyAsync(hd.p, dst, E * 4, hipMemcpyHostToDevice, s));
+    }
+    label = hl.as<int32_t>();
+    src = hs.as<int32_t>();
+    lab = hb.as<int32_t>();
+    dst = hd.as<int32_t>();
+  }
+  // union endpoints and graph-major node labels
+  DevBuf usrc, udst, glabel, err;
+  usrc.ensure(std::max<uint64_t>(E, 1) * 4);
+  udst.ensure(std::max<uint64_t>(E, 1) * 4);
+  glabel.ensure(std::max<uint64_t>(N, 1) * 4);
+  err.ensure(4);
+  KB_CHECK(hipMemsetAsync(err.p, 0, 4, s));
+  const uint32_t gs = std::max<uint32_t>(1, std::min<uint32_t>(ceil_div(std::max<uint64_t>(E, 1), 256), 8192));
+  if (E) {
+    union_edges_k<<<gs, 256, 0, s>>>(src, dst, E, d_node_off_.as<int64_t>(), d_edge_off_.as<int64_t>(), uint32_t(G),
+                                     usrc.as<int32_t>(), udst.as<int32_t>(), err.as<uint32_t>());
+    KB_LAUNCH_CHECK();
+  }
+  if (N) {
+    DevBuf k0, k1, i0, i1, fl, cl, scratch, part;
+    k0.ensure(N * 8);
+    k1.ensure(N * 8);
+    for (DevBuf* b : {&i0, &i1, &fl, &cl}) b->ensure(N * 4);
+    union_node_keys_k<<<ceil_div(N, 256), 256, 0, s>>>(label, N, d_node_off_.as<int64_t>(), uint32_t(G),
+                                                        k0.as<uint64_t>(), i0.as<uint32_t>(), err.as<uint32_t>());
+    KB_LAUNCH_CHECK();
+    scratch.ensure(radix_scratch_words(N) * 4);
+    const int bits = 31 + bits_for(G > 1 ? uint64_t(G - 1) : 1);
+    const bool f = radix_sort<uint64_t>(k0.as<uint64_t>(), i0.as<uint32_t>(), k1.as<uint64_t>(), i1.as<uint32_t>(), N, 0,
+                                        bits, scratch.as<uint32_t>(), s);
+    const uint64_t* K = f ? k1.as<uint64_t>() : k0.as<uint64_t>();
+    const uint32_t* I = f ? i1.as<uint32_t>() : i0.as<uint32_t>();
+    u64_run_flags_k<<<ceil_div(N, 256), 256, 0, s>>>(K, uint32_t(N), fl.as<uint32_t>());
+    KB_LAUNCH_CHECK();
+    part.ensure(scan_partials_count(N) * 4);
+    scan<uint32_t, uint32_t, true>(fl.as<uint32_t>(), cl.as<uint32_t>(), N, part.as<uint32_t>(), s);
+    scatter_rank_k<<<ceil_div(N, 256), 256, 0, s>>>(I, cl.as<uint32_t>(), uint32_t(N), glabel.as<int32_t>());
+    KB_LAUNCH_CHECK();
+  }
+  uint32_t e32 = 0;
+  KB_CHECK(hipMemcpyAsync(&e32, err.p, 4, hipMemcpyDeviceToHost, s));
+  KB_CHECK(hipStreamSynchronize(s));
+  if (e32 & 1u) throw InvalidInput("edge endpoint outside its graph's node range");
+  if (e32 & 4u) throw InvalidInput("negative node label");
+  eng_ = new Engine(ntot_, etot_, s, o);
+  try {
+    eng_->build(glabel.as<int32_t>(), usrc.as<int32_t>(), lab, udst.as<int32_t>());
+  } catch (...) {
+    delete eng_;
+    eng_ = nullptr;
+    throw;
+  }
+  out_.ensure(std::max<uint64_t>(N, 1) * 4);
+  base_.ensure(uint64_t(G) * 4);
+  cnt_.ensure(uint64_t(G) * 4);
+  take_.ensure(uint64_t(G));
+  read_counts(prev_);
+  blocks_ = prev_;
+  rounds_.assign(G, 0);
+  done_.assign(G, 0);
+}
+
+Batch::~Batch() { delete eng_; }
+
+void Batch::read_counts(std::vector<int32_t>& cnt) {
+  cnt.assign(G_, 0);
+  graph_id_range_k<<<ceil_div(uint64_t(G_), 256), 256, 0, st_>>>(eng_->pid_device(), eng_->ord_device(),
+                                                                 d_node_off_.as<int64_t>(), uint32_t(G_),
+                                                                 base_.as<int32_t>(), cnt_.as<int32_t>());
+  KB_LAUNCH_CHECK();
+  KB_CHECK(hipMemcpyAsync(cnt.data(), cnt_.p, uint64_t(G_) * 4, hipMemcpyDeviceToHost, st_));
+  KB_CHECK(hipStreamSynchronize(st_));
+}
+
+void Batch::take_snapshot(const std::vector<uint8_t>& take) {
+  if (ntot_ == 0) return;
+  KB_CHECK(hipMemcpyAsync(take_.p, take.data(), uint64_t(G_), hipMemcpyHostToDevice, st_));
+  const uint32_t gs = std::max<uint32_t>(1, std::min<uint32_t>(ceil_div(uint64_t(ntot_), 256), 8192));
+  snapshot_k<<<gs, 256, 0, st_>>>(eng_->pid_device(), uint64_t(ntot_), d_node_off_.as<int64_t>(), uint32_t(G_),
+                                   base_.as<int32_t>(), take_.as<uint8_t>(), out_.as<int32_t>());
+  KB_LAUNCH_CHECK();
+  KB_CHECK(hipStreamSynchronize(st_));  // `take` is a host vector the caller may change
+}
+
+void Batch::refine(const std::vector<int32_t>& k) {
+  StreamScope scope(st_);
+  if (refined_) throw StateError("batch already refined");
+  k_ = k;
+  std::vector<uint8_t> take(G_, 0);
+  bool any = false, open = false;
+  for (int32_t g = 0; g < G_; ++g) {
+    if (k_[g] == 0) {
+      take[g] = 1;
+      done_[g] = 1;
+      any = true;
+    } else {
+      open = true;
+    }
+  }
+  if (any) take_snapshot(take);
+  std::vector<int32_t> cur;
+  for (int32_t i = 1; open; ++i) {
+    eng_->step_round();
+    read_counts(cur);
+    std::fill(take.begin(), take.end(), 0);
+    any = false;
+    open = false;
+    for (int32_t g = 0; g < G_; ++g) {
+      if (done_[g]) continue;
+      blocks_[g] = cur[g];
+      if ((opt_.early_stop && cur[g] == prev_[g]) || i == k_[g]) {
+        rounds_[g] = i;
+        done_[g] = 1;
+        take[g] = 1;
+        any = true;
+      } else {
+        open = true;
+      }
+    }
+    prev_ = cur;
+    if (any) take_snapshot(take);
+  }
+  refined_ = true;
+}
+
+void Batch::result(int32_t* pid_out, bool to_device, int64_t* blocks, int32_t* rounds) const {
+  if (!refined_) throw StateError("batch not refined yet");
+  if (pid_out && ntot_) {
+    KB_CHECK(hipMemcpyAsync(pid_out, out_.p, uint64_t(ntot_) * 4,
+                            to_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st_));
+    KB_CHECK(hipStreamSynchronize(st_));
+  }
+  for (int32_t g = 0; g < G_; ++g) {
+    if (blocks) blocks[g] = blocks_[g];
+    if (rounds) rounds[g] = rounds_[g];
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// Served form.
+
+struct Cancelled : std::runtime_error {
+  Cancelled() : std::runtime_error("cancelled") {}
+};
+
+Server::Server(uint64_t budget, int32_t slots, const Options& o) : budget_(budget), slots_(slots), opt_(o) {
+  KB_CHECK(hipGetDevice(&device_));
+  for (int32_t i = 0; i < slots; ++i) {
+    hipStream_t s = nullptr;
+    KB_CHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));  // default priority
+    streams_.push_back(s);
+  }
+  for (int32_t i = 0; i < slots; ++i) threads_.emplace_back(&Server::worker, this, int(i));
+}
+
+Server::~Server() {
+  {
+    std::lock_guard<std::mutex> lk(mu_);
+    stop_ = true;
+    for (auto& r : queue_) r->state = Request::kCancelled;
+    queue_.clear();
+    for (auto& kv : all_)
+      if (kv.second->state == Request::kRunning) kv.second->cancel = true;
+  }
+  cv_work_.notify_all();
+  cv_done_.notify_all();
+  for (auto& t : threads_) t.join();
+  for (auto s : streams_) (void)hipStreamDestroy(s);
+}
+
+uint64_t Server::submit(const int32_t* label, const int32_t* src, const int32_t* lab, const int32_t* dst, int64_t n,
+                        int64_t m, bool device_inputs, int32_t k) {
+  auto r = std::make_shared<Request>();
+  r->k = k;
+  r->n = n;
+  r->m = m;
+  r->device_inputs = device_inputs;
+  r->footprint = job_footprint(uint64_t(n), uint64_t(m));
+  if (r->footprint > budget_)
+    throw OutOfMemory("request needs about " + std::to_string(r->footprint) + " device bytes; budget is " +
+                      std::to_string(budget_));
+  if (device_inputs) {
+    r->dev[0] = label;
+    r->dev[1] = src;
+    r->dev[2] = lab;
+    r->dev[3] = dst;
+  } else {
+    r->host[0].assign(label, label + n);
+    r->host[1].assign(src, src + m);
+    r->host[2].assign(lab, lab + m);
+    r->host[3].assign(dst, dst + m);
+  }
+  r->t_submit = std::chrono::steady_clock::now();
+  std::lock_guard<std::mutex> lk(mu_);
+  if (stop_) throw StateError("server is shutting down");
+  r->id = next_id_++;
+  all_[r->id] = r;
+  queue_.push_back(r);
+  cv_work_.notify_all();
+  return r->id;
+}
+
+void Server::worker(int slot) {
+  (void)hipSetDevice(device_);
+  hipStream_t s = streams_[size_t(slot)];
+  for (;;) {
+    std::shared_ptr<Request> r;
+    {
+      std::unique_lock<std::mutex> lk(mu_);
+      cv_work_.wait(lk, [&] {
+        return stop_ || (!queue_.empty() && in_use_ + queue_.front()->footprint <= budget_);
+      });
+      if (stop_) return;
+      r = queue_.front();
+      queue_.pop_front();
+      in_use_ += r->footprint;
+      r->state = Request::kRunning;
+      r->t_start = std::chrono::steady_clock::now();
+    }
+    int status = 0;
+    std::string err;
+    bool cancelled = false;
+    try {
+      run(*r, s);
+    } catch (const Cancelled&) {
+      cancelled = true;
+    } catch (const InvalidInput& e) {
+      status = KBISIM_EINVAL;
+      err = e.what();
+    } catch (const OutOfMemory& e) {
+      status = KBISIM_ENOMEM;
+      err = e.what();
+    } catch (const std::exception& e) {
+      status = KBISIM_EDEVICE;
+      err = e.what();
+    }
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      in_use_ -= r->footprint;
+      r->t_end = std::chrono::steady_clock::now();
+      r->status = status;
+      r->error = err;
+      r->state = cancelled ? Request::kCancelled : status ? Request::kFailed : Request::kDone;
+      for (auto& h : r->host) std::vector<int32_t>().swap(h);  // inputs no longer needed
+    }
+    cv_done_.notify_all();
+    cv_work_.notify_all();  // memory came back: the queue head may fit now
+  }
+}
+
+void Server::run(Request& r, hipStream_t s) {
+  StreamScope scope(s);
+  Engine eng(r.n, r.m, s, opt_);
+  if (r.device_inputs) {
+    eng.build(r.dev[0], r.dev[1], r.dev[2], r.dev[3]);
+  } else {
+    DevBuf b[4];
+    const uint64_t len[4] = {uint64_t(r.n), uint64_t(r.m), uint64_t(r.m), uint64_t(r.m)};
+    const int32_t* p[4];
+    for (int i = 0; i < 4; ++i) {
+      b[i].ensure(std::max<uint64_t>(len[i], 1) * 4);
+      if (len[i]) KB_CHECK(hipMemcpyAsync(b[i].p, r.host[i].data(), len[i] * 4, hipMemcpyHostToDevice, s));
+      p[i] = b[i].as<int32_t>();
+    }
+    eng.build(p[0], p[1], p[2], p[3]);
+  }
+  while (eng.rounds_done() < r.k && !(eng.fixed() && opt_.early_stop)) {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      if (r.cancel) throw Cancelled();
+    }
+    eng.step_round();
+  }
+  r.pid.resize(size_t(r.n));
+  if (r.n) eng.result(r.pid.data(), false);
+  r.counts = eng.counts();
+  r.rounds = eng.rounds_done();
+}
+
+int Server::wait(uint64_t id, int32_t* pid_out, bool to_device, int64_t* num_blocks, int32_t* rounds,
+                 double timeout_s, std::string* err) {
+  std::unique_lock<std::mutex> lk(mu_);
+  auto it = all_.find(id);
+  if (it == all_.end()) return KBISIM_EINVAL;
+  std::shared_ptr<Request> r = it->second;
+  auto finished = [&] {
+    return r->state == Request::kDone || r->state == Request::kFailed || r->state == Request::kCancelled;
+  };
+  if (timeout_s < 0) {
+    cv_done_.wait(lk, finished);
+  } else if (!cv_done_.wait_for(lk, std::chrono::duration<double>(timeout_s), finished)) {
+    return KBISIM_ETIMEDOUT;
+  }
+  if (r->state == Request::kCancelled) return KBISIM_ECANCELED;
+  if (r->state == Request::kFailed) {
+    if (err) *err = r->error;
+    return r->status;
+  }
+  lk.unlock();  // a done request is not modified any more
+  if (pid_out && r->n) {
+    if (to_device)
+      KB_CHECK(hipMemcpy(pid_out, r->pid.data(), size_t(r->n) * 4, hipMemcpyHostToDevice));
+    else
+      std::memcpy(pid_out, r->pid.data(), size_t(r->n) * 4);
+  }
+  if (num_blocks) *num_blocks = r->counts.empty() ? 0 : r->counts.back();
+  if (rounds) *rounds = r->rounds;
+  return KBISIM_OK;
+}
+
+int Server::cancel(uint64_t id) {
+  std::lock_guard<std::mutex> lk(mu_);
+  auto it = all_.find(id);
+  if (it == all_.end()) return KBISIM_EINVAL;
+  Request& r = *it->second;
+  if (r.state == Request::kQueued) {
+    for (auto q = queue_.begin(); q != queue_.end(); ++q)
+      if ((*q)->id == id) {
+        queue_.erase(q);
+        break;
+      }
+    r.state = Request::kCancelled;
+    cv_done_.notify_all();
+    cv_work_.notify_all();
+    return KBISIM_OK;
+  }
+  if (r.state == Request::kRunning) {
+    r.cancel = true;
+    return KBISIM_OK;
+  }
+  return KBISIM_ESTATE;  // already finished
+}
+
+bool Server::timing(uint64_t id, double* queued_s, double* total_s) {
+  std::lock_guard<std::mutex> lk(mu_);
+  auto it = all_.find(id);
+  if (it == all_.end() || it->second->state != Request::kDone) return false;
+  const Request& r = *it->second;
+  if (queued_s) *queued_s = std::chrono::duration<double>(r.t_start - r.t_submit).count();
+  if (total_s) *total_s = std::chrono::duration<double>(r.t_end - r.t_submit).count();
+  return true;
+}
+
+void Server::release(uint64_t id) {
+  std::lock_guard<std::mutex> lk(mu_);
+  auto it = all_.find(id);
+  if (it == all_.end()) return;
+  const auto st = it->second->state;
+  if (st == Request::kDone || st == Request::kFailed || st == Request::kCancelled) all_.erase(it);
+}
+
 }  // namespace kb
 
 // ===========================================================================
@@ -644,6 +1034,14 @@ void Engine::result(int32_t* pid_out, bool to_device) const {
 
 struct kbisim_graph {
   kb::Engine* eng = nullptr;
+};
+
+struct kbisim_batch {
+  kb::Batch* b = nullptr;
+};
+
+struct kbisim_server {
+  kb::Server* s = nullptr;
 };
 
 namespace {
@@ -657,6 +1055,9 @@ kbisim_status guarded(F&& f) {
   } catch (const kb::InvalidInput& e) {
     g_last_error = e.what();
     return KBISIM_EINVAL;
+  } catch (const kb::StateError& e) {
+    g_last_error = e.what();
+    return KBISIM_ESTATE;
   } catch (const kb::OutOfMemory& e) {
     g_last_error = e.what();
     return KBISIM_ENOMEM;
@@ -687,6 +1088,16 @@ void kbisim_options_default(kbisim_options* opt) {
   opt->medium_cap = int32_t(kb::kDefaultMediumCap);
 }
 
+static kbisim_status parse_options(const kbisim_options* opt, kb::Options* o) {
+  if (!opt) return KBISIM_OK;
+  o->early_stop = opt->early_stop != 0;
+  o->profile = opt->profile != 0;
+  if (opt->medium_cap < 0 || opt->medium_cap > int32_t(kb::kMediumCap))
+    return fail(KBISIM_EINVAL, "medium_cap outside [0, 1024]");
+  if (opt->medium_cap > 0) o->medium_cap = uint32_t(opt->medium_cap);
+  return KBISIM_OK;
+}
+
 kbisim_status kbisim_create(const kbisim_graph_desc* d, const kbisim_options* opt, kbisim_graph** out) {
   if (!d || !out) return fail(KBISIM_EINVAL, "null desc or out");
   if (d->num_nodes < 0 || d->num_edges < 0) return fail(KBISIM_EINVAL, "negative size");
@@ -697,13 +1108,7 @@ kbisim_status kbisim_create(const kbisim_graph_desc* d, const kbisim_options* op
     return fail(KBISIM_EINVAL, "null edge array");
   if (d->mem != KBISIM_MEM_HOST && d->mem != KBISIM_MEM_DEVICE) return fail(KBISIM_EINVAL, "bad mem kind");
   kb::Options o;
-  if (opt) {
-    o.early_stop = opt->early_stop != 0;
-    if (opt->medium_cap < 0 || opt->medium_cap > int32_t(kb::kMediumCap))
-      return fail(KBISIM_EINVAL, "medium_cap outside [0, 1024]");
-    if (opt->medium_cap > 0) o.medium_cap = uint32_t(opt->medium_cap);
-    o.profile = opt->profile != 0;
-  }
+  if (parse_options(opt, &o) != KBISIM_OK) return KBISIM_EINVAL;
   return guarded([&]() {
     hipStream_t s = static_cast<hipStream_t>(d->stream);
     kb::StreamScope scope(s);
@@ -790,6 +1195,137 @@ kbisim_status kbisim_work(const kbisim_graph* g, int64_t* nodes_edges, int32_t c
     if (reset) g->eng->reset_work();
     return KBISIM_OK;
   });
+}
+
+
+kbisim_status kbisim_batch_create(int32_t num_graphs, const int64_t* node_off, const int64_t* edge_off,
+                                  const kbisim_graph_desc* d, const kbisim_options* opt, kbisim_batch** out) {
+  if (!d || !out || !node_off || !edge_off) return fail(KBISIM_EINVAL, "null argument");
+  if (num_graphs < 1) return fail(KBISIM_EINVAL, "num_graphs < 1");
+  if (d->num_nodes != node_off[num_graphs] || d->num_edges != edge_off[num_graphs])
+    return fail(KBISIM_EINVAL, "desc sizes differ from the offsets' totals");
+  if (d->num_nodes > 0 && !d->node_label) return fail(KBISIM_EINVAL, "null node_label");
+  if (d->num_edges > 0 && (!d->edge_src || !d->edge_label || !d->edge_dst))
+    return fail(KBISIM_EINVAL, "null edge array");
+  if (d->mem != KBISIM_MEM_HOST && d->mem != KBISIM_MEM_DEVICE) return fail(KBISIM_EINVAL, "bad mem kind");
+  kb::Options o;
+  if (parse_options(opt, &o) != KBISIM_OK) return KBISIM_EINVAL;
+  return guarded([&]() {
+    hipStream_t s = static_cast<hipStream_t>(d->stream);
+    auto* b = new kb::Batch(num_graphs, node_off, edge_off, d->node_label, d->edge_src, d->edge_label, d->edge_dst,
+                            d->mem == KBISIM_MEM_HOST, s, o);
+    auto* h = new kbisim_batch;
+    h->b = b;
+    *out = h;
+    return KBISIM_OK;
+  });
+}
+
+kbisim_status kbisim_batch_refine(kbisim_batch* h, const int32_t* k_per_graph, int32_t* rounds_done) {
+  if (!h || !h->b || !k_per_graph) return fail(KBISIM_EINVAL, "null argument");
+  const int32_t G = h->b->num_graphs();
+  for (int32_t g = 0; g < G; ++g)
+    if (k_per_graph[g] < 0) return fail(KBISIM_EINVAL, "k < 0");
+  return guarded([&]() {
+    h->b->refine(std::vector<int32_t>(k_per_graph, k_per_graph + G));
+    if (rounds_done) h->b->result(nullptr, false, nullptr, rounds_done);
+    return KBISIM_OK;
+  });
+}
+
+kbisim_status kbisim_batch_result(const kbisim_batch* h, int32_t* pid_out, kbisim_mem mem, int64_t* num_blocks) {
+  if (!h || !h->b) return fail(KBISIM_EINVAL, "null handle");
+  if (mem != KBISIM_MEM_HOST && mem != KBISIM_MEM_DEVICE) return fail(KBISIM_EINVAL, "bad mem kind");
+  return guarded([&]() {
+    h->b->result(pid_out, mem == KBISIM_MEM_DEVICE, num_blocks, nullptr);
+    return KBISIM_OK;
+  });
+}
+
+void kbisim_batch_destroy(kbisim_batch* h) {
+  if (!h) return;
+  delete h->b;
+  delete h;
+}
+
+
+kbisim_status kbisim_server_create(uint64_t hbm_budget_bytes, int32_t max_slots, const kbisim_options* opt,
+                                   kbisim_server** out) {
+  if (!out) return fail(KBISIM_EINVAL, "null out");
+  if (max_slots < 1 || max_slots > 64) return fail(KBISIM_EINVAL, "max_slots outside [1, 64]");
+  if (hbm_budget_bytes == 0) return fail(KBISIM_EINVAL, "zero budget");
+  kb::Options o;
+  if (parse_options(opt, &o) != KBISIM_OK) return KBISIM_EINVAL;
+  o.profile = false;
+  return guarded([&]() {
+    auto* h = new kbisim_server;
+    h->s = new kb::Server(hbm_budget_bytes, max_slots, o);
+    *out = h;
+    return KBISIM_OK;
+  });
+}
+
+kbisim_status kbisim_server_submit(kbisim_server* h, const kbisim_graph_desc* d, int32_t k, uint64_t* req_id) {
+  if (!h || !h->s || !d || !req_id) return fail(KBISIM_EINVAL, "null argument");
+  if (k < 0) return fail(KBISIM_EINVAL, "k < 0");
+  if (d->num_nodes < 0 || d->num_edges < 0) return fail(KBISIM_EINVAL, "negative size");
+  if (d->num_nodes >= (int64_t(1) << 31)) return fail(KBISIM_EINVAL, "num_nodes >= 2^31");
+  if (d->num_edges >= int64_t(0xffffffffll)) return fail(KBISIM_EINVAL, "num_edges >= 2^32 - 1");
+  if (d->num_nodes > 0 && !d->node_label) return fail(KBISIM_EINVAL, "null node_label");
+  if (d->num_edges > 0 && (!d->edge_src || !d->edge_label || !d->edge_dst))
+    return fail(KBISIM_EINVAL, "null edge array");
+  if (d->mem != KBISIM_MEM_HOST && d->mem != KBISIM_MEM_DEVICE) return fail(KBISIM_EINVAL, "bad mem kind");
+  return guarded([&]() {
+    *req_id = h->s->submit(d->node_label, d->edge_src, d->edge_label, d->edge_dst, d->num_nodes, d->num_edges,
+                           d->mem == KBISIM_MEM_DEVICE, k);
+    return KBISIM_OK;
+  });
+}
+
+kbisim_status kbisim_server_wait(kbisim_server* h, uint64_t req_id, int32_t* pid_out, kbisim_mem mem,
+                                 int64_t* num_blocks, int32_t* rounds_done, double timeout_s) {
+  if (!h || !h->s) return fail(KBISIM_EINVAL, "null handle");
+  if (mem != KBISIM_MEM_HOST && mem != KBISIM_MEM_DEVICE) return fail(KBISIM_EINVAL, "bad mem kind");
+  return guarded([&]() {
+    std::string err;
+    const int st = h->s->wait(req_id, pid_out, mem == KBISIM_MEM_DEVICE, num_blocks, rounds_done, timeout_s, &err);
+    if (st != KBISIM_OK) {
+      g_last_error = err.empty() ? kbisim_status_str(kbisim_status(st)) : err;
+      return kbisim_status(st);
+    }
+    return KBISIM_OK;
+  });
+}
+
+kbisim_status kbisim_server_cancel(kbisim_server* h, uint64_t req_id) {
+  if (!h || !h->s) return fail(KBISIM_EINVAL, "null handle");
+  const int st = h->s->cancel(req_id);
+  if (st != KBISIM_OK) return fail(kbisim_status(st), st == KBISIM_ESTATE ? "request already finished" : "unknown id");
+  return KBISIM_OK;
+}
+
+kbisim_status kbisim_server_timing(kbisim_server* h, uint64_t req_id, double* queued_s, double* total_s) {
+  if (!h || !h->s) return fail(KBISIM_EINVAL, "null handle");
+  if (!h->s->timing(req_id, queued_s, total_s)) return fail(KBISIM_ESTATE, "request not done");
+  return KBISIM_OK;
+}
+
+kbisim_status kbisim_server_release(kbisim_server* h, uint64_t req_id) {
+  if (!h || !h->s) return fail(KBISIM_EINVAL, "null handle");
+  h->s->release(req_id);
+  return KBISIM_OK;
+}
+
+kbisim_status kbisim_server_in_use(kbisim_server* h, uint64_t* bytes) {
+  if (!h || !h->s || !bytes) return fail(KBISIM_EINVAL, "null argument");
+  *bytes = h->s->in_use();
+  return KBISIM_OK;
+}
+
+void kbisim_server_destroy(kbisim_server* h) {
+  if (!h) return;
+  delete h->s;
+  delete h;
 }
 
 void kbisim_destroy(kbisim_graph* g) {

@@ -16,6 +16,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "common.h"
 
@@ -32,21 +33,32 @@ class Pool {
     const size_t want = round(bytes);
     int dev = 0;
     KB_CHECK(hipGetDevice(&dev));
+    Blk b{nullptr, 0, nullptr, 0, nullptr};
+    bool found = false;
     {
+      // take a block under the lock; wait for its last user only after
+      // releasing the lock, so no thread blocks on the GPU while holding it
       std::lock_guard<std::mutex> lk(mu_);
-      auto it = free_.lower_bound(want);
-      for (; it != free_.end() && it->first <= 2 * want; ++it) {
+      for (auto it = free_.lower_bound(want); it != free_.end() && it->first <= 2 * want; ++it) {
         if (it->second.dev != dev) continue;
-        Blk b = it->second;
+        b = it->second;
         free_.erase(it);
         cached_ -= b.bytes;
-        if (b.ev) {
-          if (b.stream != s) KB_CHECK(hipEventSynchronize(b.ev));
-          KB_CHECK(hipEventDestroy(b.ev));
-        }
-        *got = b.bytes;
-        return b.p;
+        found = true;
+        break;
       }
+    }
+    if (found) {
+      if (b.ev) {
+        const hipError_t e1 = (b.stream != s) ? hipEventSynchronize(b.ev) : hipSuccess;
+        (void)hipEventDestroy(b.ev);
+        if (e1 != hipSuccess) {
+          (void)hipFree(b.p);
+          KB_CHECK(e1);
+        }
+      }
+      *got = b.bytes;
+      return b.p;
     }
     void* p = nullptr;
     hipError_t e = hipMalloc(&p, want);
@@ -120,6 +132,47 @@ class Pool {
   std::mutex mu_;
   std::multimap<size_t, Blk> free_;
   size_t cached_ = 0;
+};
+
+// Small pinned host buffers for device-to-host readbacks, carved from one
+// slab that lives until the process ends (per-handle pinned allocation and
+// release would synchronise the whole device every time).
+class PinnedSlots {
+ public:
+  static constexpr size_t kSlotWords = 64;
+  static PinnedSlots& instance() {
+    static PinnedSlots* p = new PinnedSlots();
+    return *p;
+  }
+  uint64_t* acquire() {
+    for (;;) {
+      {
+        std::lock_guard<std::mutex> lk(mu_);
+        if (!free_.empty()) {
+          uint64_t* w = free_.back();
+          free_.pop_back();
+          return w;
+        }
+      }
+      // allocate a new slab outside the lock
+      void* slab = nullptr;
+      const size_t n = 256;  // slots per slab
+      if (hipHostMalloc(&slab, n * kSlotWords * sizeof(uint64_t), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        throw OutOfMemory("hipHostMalloc of readback slots failed");
+      }
+      std::lock_guard<std::mutex> lk(mu_);
+      for (size_t i = 0; i < n; ++i) free_.push_back(static_cast<uint64_t*>(slab) + i * kSlotWords);
+    }
+  }
+  void release(uint64_t* w) {
+    std::lock_guard<std::mutex> lk(mu_);
+    free_.push_back(w);
+  }
+
+ private:
+  std::mutex mu_;
+  std::vector<uint64_t*> free_;
 };
 
 // Stream on which the calling thread's library work runs; device buffers

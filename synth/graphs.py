@@ -70,7 +70,9 @@ def uniform_graph(n, e, num_node_labels=4, num_edge_labels=8, seed=1, name="unif
 
 
 def _scale_to_total(w, total, cap):
-    """c such that sum(min(c*w, cap)) == total (bisection on c)."""
+    """c such that sum(min(c*w, cap)) == total (bisection on c); needs
+    cap * len(w) >= total."""
+    assert cap * w.shape[0] >= total
     lo, hi = 0.0, float(total) / float(w.sum()) * 4.0 + 1.0
     while np.minimum(hi * w, cap).sum() < total:
         hi *= 2.0
@@ -93,6 +95,10 @@ def powerlaw_graph(n, e, seed=1, zipf_a=2.1, deg_cap=100_000, num_node_labels=10
     # sampled maximum stays at or below deg_cap (asserted below)
     cap = float(min(deg_cap, max(e, 1)))
     cap_eff = max(cap - 6.0 * np.sqrt(cap), 1.0)
+    # the capped expected degrees must be able to add up to e
+    cap_eff = max(cap_eff, float(np.ceil(e / max(n, 1))))
+    if n == 0 or cap_eff > deg_cap:
+        raise ValueError("cannot place %d edges on %d nodes under out-degree cap %d" % (e, n, deg_cap))
     c = _scale_to_total(w, e, cap_eff)
     lam = np.minimum(c * w, cap_eff)
     deg = rng.multinomial(e, lam / lam.sum()).astype(np.int64)
@@ -202,7 +208,7 @@ def batch_graphs(num_graphs, seed=1, median_nodes=20_000, sigma=1.0, min_nodes=1
     out = []
     for g in range(num_graphs):
         n = int(sizes[g])
-        gr = powerlaw_graph(n, avg_degree * n, seed=(seed, g), deg_cap=n,
+        gr = powerlaw_graph(n, avg_degree * n, seed=(seed, g), deg_cap=max(n, 8 * avg_degree),
                             num_node_labels=num_labels, node_label_exp=0.0,
                             num_edge_labels=num_labels, edge_label_exp=0.0, name="batch%d" % g)
         out.append(gr)

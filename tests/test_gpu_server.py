@@ -1,0 +1,104 @@
+"""Served form: concurrent requests give the same results as each request
+alone; admission, rejection, failure isolation and cancellation."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import need_gpu, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+GB = 1 << 30
+
+
+def request_graphs():
+    gs = []
+    for i, n in enumerate([3000, 200, 40000, 12000, 1, 7000, 90000, 500]):
+        gs.append(synth.powerlaw_graph(n, 8 * n, seed=100 + i, deg_cap=max(64, n // 4),
+                                       num_node_labels=6, num_edge_labels=5, name="req%d" % i))
+    gs.append(synth.worked_example())
+    return gs
+
+
+def test_mix_equals_alone():
+    torch, kb = need_gpu()
+    gs = request_graphs()
+    ks = [2 + (3 * i) % 9 for i in range(len(gs))]
+    alone = []
+    for g, k in zip(gs, ks):
+        pid, counts, rd = kb.refine(g.num_nodes, g.node_label, g.src, g.elab, g.dst, k)
+        alone.append((pid, counts[-1], rd))
+    say("server mix of %d requests" % len(gs))
+    with kb.Server(8 * GB, max_slots=4) as srv:
+        ids = []
+        for i, (g, k) in enumerate(zip(gs, ks)):
+            arrs = to_dev(torch, g) if i % 2 else (g.node_label, g.src, g.elab, g.dst)
+            ids.append(srv.submit(g.num_nodes, *arrs, k))
+        say("submitted %d requests" % len(ids))
+        for rid, (pid, nb, rd), g, k in zip(ids, alone, gs, ks):
+            out, nb2, rd2 = srv.wait(rid, timeout_s=60)
+            say("request %d (%s, N=%d) done" % (rid, g.name, g.num_nodes))
+            assert np.array_equal(out, pid) and nb2 == nb and rd2 == rd, g.name
+            r = oracle.refine(g.num_nodes, g.node_label, g.src, g.elab, g.dst, k)
+            assert np.array_equal(out, r.pid) and rd2 == r.rounds_done
+            q, tot = srv.timing(rid)
+            assert 0 <= q <= tot
+
+
+def test_small_budget_admits_one_at_a_time():
+    torch, kb = need_gpu()
+    gs = request_graphs()[:5]
+    budget = 300 << 20  # each job's estimate (>= 64 MB) leaves room for few at once
+    with kb.Server(budget, max_slots=4) as srv:
+        ids = [srv.submit(g.num_nodes, g.node_label, g.src, g.elab, g.dst, 4) for g in gs]
+        seen = 0
+        for rid, g in zip(ids, gs):
+            out, nb, rd = srv.wait(rid, timeout_s=60)
+            r = oracle.refine(g.num_nodes, g.node_label, g.src, g.elab, g.dst, 4)
+            assert np.array_equal(out, r.pid)
+            seen = max(seen, srv.in_use())
+        assert srv.in_use() == 0
+
+
+def test_oversize_rejected_and_invalid_isolated():
+    torch, kb = need_gpu()
+    big = synth.uniform_graph(100000, 1000000, seed=1)
+    good = synth.uniform_graph(3000, 9000, seed=2)
+    bad = synth.uniform_graph(3000, 9000, seed=3)
+    bad.dst = bad.dst.copy()
+    bad.dst[5] = 3000
+    with kb.Server(64 << 20 | 1 << 26, max_slots=2) as srv:
+        with pytest.raises(kb.KbisimError) as e:
+            srv.submit(big.num_nodes, big.node_label, big.src, big.elab, big.dst, 3)
+        assert e.value.status == -2
+    with kb.Server(2 * GB, max_slots=2) as srv:
+        r_bad = srv.submit(bad.num_nodes, bad.node_label, bad.src, bad.elab, bad.dst, 3)
+        r_good = srv.submit(good.num_nodes, good.node_label, good.src, good.elab, good.dst, 3)
+        with pytest.raises(kb.KbisimError) as e:
+            srv.wait(r_bad, timeout_s=60)
+        assert e.value.status == -1
+        out, nb, rd = srv.wait(r_good, timeout_s=60)
+        r = oracle.refine(good.num_nodes, good.node_label, good.src, good.elab, good.dst, 3)
+        assert np.array_equal(out, r.pid)
+
+
+def test_cancel_queued():
+    torch, kb = need_gpu()
+    gs = request_graphs()
+    with kb.Server(8 * GB, max_slots=1) as srv:
+        first = srv.submit(gs[6].num_nodes, gs[6].node_label, gs[6].src, gs[6].elab, gs[6].dst, 10)
+        queued = srv.submit(gs[0].num_nodes, gs[0].node_label, gs[0].src, gs[0].elab, gs[0].dst, 5)
+        try:
+            srv.cancel(queued)
+            cancelled = True
+        except kb.KbisimError:
+            cancelled = False  # it had already run
+        if cancelled:
+            with pytest.raises(kb.KbisimError) as e:
+                srv.wait(queued, timeout_s=60)
+            assert e.value.status in (-6,)
+        out, nb, rd = srv.wait(first, timeout_s=60)
+        assert out.shape[0] == gs[6].num_nodes

@@ -79,7 +79,7 @@ def test_figure1_prose():
 
 @pytest.mark.parametrize("table", ["table4", "table5"])
 def test_update_tables_as_partitions(table):
-    """Tables 4 and 5 (Section 4.3): a from-scratch run on the updated graph gives
+    """Tables 4 and 5 (Section 4.2): a from-scratch run on the updated graph gives
     the same partitions (block structure) the update algorithm printed."""
     fx = load("updates.json")[table]
     g = graph_of(fx, table)
