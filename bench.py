@@ -12,6 +12,8 @@ Prints one JSON line (rank 0). Options:
   --warmup W      untimed steps first (default 1)
   --workload W    synth.CONFIGS name (default powerlaw-10M-100M)
   --no-cpu-baseline   skip timing the oracle on the host
+  --form F        plain (default), batched or served: the two system forms
+                  print their own JSON line (see bench_batched / bench_served)
 """
 from __future__ import annotations
 
@@ -56,7 +58,8 @@ def load_traffic(kernel_class):
         t = json.load(f)
     if t.get("source_digest") != kernel_source_digest():
         return None
-    return t.get("kernels", {}).get(kernel_class)
+    k = t.get("kernels", {}).get(kernel_class)
+    return None if k is None else k.get("bytes_per_launch")
 
 
 def cpu_baseline(seed=1):
@@ -85,6 +88,11 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--medium-cap", type=int, default=None)
+    ap.add_argument("--form", choices=["plain", "batched", "served"], default="plain")
+    ap.add_argument("--graphs", type=int, default=512, help="batched: number of graphs")
+    ap.add_argument("--requests", type=int, default=300, help="served: number of requests")
+    ap.add_argument("--max-nodes", type=int, default=2_000_000, help="served: largest request")
+    ap.add_argument("--slots", type=int, default=4, help="served: concurrent slots")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -100,6 +108,10 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     dev = torch.device("cuda:0")
+    if args.form == "batched":
+        return bench_batched(args, torch, kb, dev)
+    if args.form == "served":
+        return bench_served(args, torch, kb, dev)
 
     t0 = time.perf_counter()
     g, k_default = synth.make_config(args.workload, seed=args.seed)
@@ -181,6 +193,166 @@ def main():
     if not args.no_cpu_baseline:
         log("timing the oracle on the host ...")
         line["cpu_baseline"] = cpu_baseline(args.seed)
+    print(json.dumps(line), flush=True)
+
+
+def pct(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs), q)) if len(xs) else None
+
+
+def bench_batched(args, torch, kb, dev):
+    """Batched form: many graphs of log-normal size (median 20k nodes, sigma
+    1, 1k..1M nodes, mean out-degree 8, 16 node and 16 edge labels), k = 5,
+    refined as one batch (medium_cap from the autotuner) vs the per-graph
+    plain refine loop on the same GPU; results must be identical."""
+    import numpy as np
+    import synth
+    from paper_1210_0748_amd import autotune
+    k = 5
+    t0 = time.perf_counter()
+    graphs = synth.batch_graphs(args.graphs, seed=args.seed)
+    noff = np.zeros(len(graphs) + 1, np.int64)
+    eoff = np.zeros(len(graphs) + 1, np.int64)
+    for i, g in enumerate(graphs):
+        noff[i + 1] = noff[i] + g.num_nodes
+        eoff[i + 1] = eoff[i] + g.num_edges
+    cat = lambda name: np.concatenate([getattr(g, name) for g in graphs])
+    arrs = [torch.from_numpy(cat(nm)).to(dev) for nm in ("node_label", "src", "elab", "dst")]
+    log("generated %d graphs: N=%d E=%d in %.1f s" % (len(graphs), noff[-1], eoff[-1], time.perf_counter() - t0))
+    cap, tune_times = autotune.tune_medium_cap(graphs, k, use_cache=False)
+    log("autotuned medium_cap=%d %s" % (cap, tune_times))
+    out = torch.empty(int(noff[-1]), dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def batched():
+        h, G = kb.kbisim_batch_create(noff, eoff, *arrs, stream=stream, medium_cap=cap)
+        try:
+            rd = kb.kbisim_batch_refine(h, [k] * G)
+            kb.kbisim_batch_result(h, G, out)
+        finally:
+            kb.kbisim_batch_destroy(h)
+        return rd
+
+    for _ in range(args.warmup):
+        batched()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rd = batched()
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / max(args.steps, 1)
+    edge_rounds = float(np.sum((eoff[1:] - eoff[:-1]) * rd))
+    got = out.cpu().numpy()
+
+    # per-graph plain refine loop (same device-resident inputs, one pass)
+    loop_out = torch.empty_like(out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i, g in enumerate(graphs):
+        a, b = int(noff[i]), int(noff[i + 1])
+        c, d = int(eoff[i]), int(eoff[i + 1])
+        h = kb.kbisim_create(b - a, arrs[0][a:b], arrs[1][c:d], arrs[2][c:d], arrs[3][c:d], stream=stream,
+                             medium_cap=cap)
+        try:
+            kb.kbisim_refine(h, k)
+            kb.kbisim_result(h, loop_out[a:b])
+        finally:
+            kb.kbisim_destroy(h)
+    torch.cuda.synchronize()
+    t_loop = time.perf_counter() - t0
+    same = bool(np.array_equal(got, loop_out.cpu().numpy()))
+    line = {
+        "metric": "batched edge-rounds/s (sum over graphs of |E|*rounds / time)",
+        "value": edge_rounds / t_batch, "unit": "edge-rounds/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": t_batch * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "batched-%d-graphs" % len(graphs), "graphs": len(graphs),
+                   "total_nodes": int(noff[-1]), "total_edges": int(eoff[-1]), "k": k,
+                   "median_nodes": 20000, "sigma": 1.0, "avg_degree": 8, "labels": 16},
+        "medium_cap": cap, "tune_seconds": tune_times,
+        "per_graph_loop": {"ms": t_loop * 1e3, "edge_rounds_per_s": edge_rounds / t_loop},
+        "speedup_vs_loop": t_loop / t_batch, "identical_to_loop": same,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_served(args, torch, kb, dev):
+    """Served form: Poisson arrivals (rate 200/s) of k-bisimulation requests;
+    sizes log-uniform between 10k nodes and --max-nodes, |E| = 10 |N| with a
+    power-law out-degree, 32 edge labels, k uniform in 2..10. Requests refer
+    to a device-resident pool of graphs (24 sizes, generated and uploaded
+    once). The server (HBM budget 200 GB) runs them concurrently; the
+    baseline solves them one after another in arrival order on one stream.
+    Latency = completion - arrival."""
+    import numpy as np
+    import synth
+    rng = np.random.Generator(np.random.PCG64(args.seed))
+    sizes = np.unique(np.round(np.geomspace(10_000, args.max_nodes, 24)).astype(np.int64))
+    t0 = time.perf_counter()
+    pool = []
+    for i, n in enumerate(sizes):
+        g = synth.powerlaw_graph(int(n), int(10 * n), seed=(args.seed, 1000 + i), deg_cap=max(64, int(n) // 10))
+        pool.append((g.num_nodes, [torch.from_numpy(a).to(dev) for a in (g.node_label, g.src, g.elab, g.dst)],
+                     g.num_edges))
+    log("request pool: %d graphs, %d..%d nodes, %.1f s" % (len(pool), sizes[0], sizes[-1], time.perf_counter() - t0))
+    reqs = synth.serving_stream(args.requests, seed=args.seed, rate=200.0, max_nodes=args.max_nodes)
+    logs = np.log(sizes)
+    for r in reqs:
+        r["pool"] = int(np.argmin(np.abs(logs - np.log(r["num_nodes"]))))
+    torch.cuda.synchronize()
+
+    # served: submit each request at its arrival time
+    lat, results = [], {}
+    with kb.Server(200 << 30, max_slots=args.slots) as srv:
+        ids = []
+        t_start = time.perf_counter()
+        for r in reqs:
+            now = time.perf_counter() - t_start
+            if r["arrival"] > now:
+                time.sleep(r["arrival"] - now)
+            n, a, _ = pool[r["pool"]]
+            ids.append((srv.submit(n, *a, r["k"]), time.perf_counter() - t_start))
+        done_at = []
+        for (rid, t_sub), r in zip(ids, reqs):
+            pid, nb, rd = srv.wait(rid, timeout_s=600)
+            q, tot = srv.timing(rid)
+            done_at.append(t_sub + tot)
+            lat.append(t_sub + tot - r["arrival"])
+            results[rid] = (pid, rd)
+            srv.release(rid)
+        makespan = max(done_at) if done_at else 0.0
+
+    # serial plain solves in arrival order on one stream
+    lat_s, same = [], True
+    stream = torch.cuda.current_stream()
+    t_start = time.perf_counter()
+    for (rid, _), r in zip(ids, reqs):
+        now = time.perf_counter() - t_start
+        if r["arrival"] > now:
+            time.sleep(r["arrival"] - now)
+        n, a, _ = pool[r["pool"]]
+        with kb.Graph(n, *a, stream=stream) as h:
+            rd = h.refine(r["k"])
+            pid, nb, counts = h.result()
+        lat_s.append(time.perf_counter() - t_start - r["arrival"])
+        same = same and rd == results[rid][1] and np.array_equal(pid, results[rid][0])
+    makespan_s = time.perf_counter() - t_start
+    er = float(sum(pool[r["pool"]][2] * results[rid][1] for (rid, _), r in zip(ids, reqs)))
+    line = {
+        "metric": "served requests/s with p50/p99 latency (Poisson arrivals, 200/s)",
+        "value": len(reqs) / makespan, "unit": "req/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": makespan * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": "served-poisson-200", "requests": len(reqs), "min_nodes": 10000,
+                   "max_nodes": args.max_nodes, "avg_degree": 10, "edge_labels": 32, "k": "uniform 2..10",
+                   "hbm_budget_gb": 200, "slots": args.slots, "pool_graphs": len(pool)},
+        "latency_s": {"p50": pct(lat, 50), "p99": pct(lat, 99), "max": max(lat) if lat else None},
+        "edge_rounds_per_s": er / makespan,
+        "serial_baseline": {"req_per_s": len(reqs) / makespan_s, "p50": pct(lat_s, 50), "p99": pct(lat_s, 99),
+                            "edge_rounds_per_s": er / makespan_s},
+        "identical_to_serial": bool(same),
+    }
     print(json.dumps(line), flush=True)
 
 
