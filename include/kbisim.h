@@ -74,10 +74,10 @@ typedef struct {
   int32_t early_stop; /* 1 (default): stop at the first round with B_i == B_{i-1} */
   int32_t profile;    /* 1: time each kernel class with HIP events (kbisim_profile) and
                          count the work of the signature kernels (kbisim_work) */
-  int32_t medium_cap; /* tuning: blocks of 65..medium_cap members are ordered by one
-                         workgroup in LDS, larger ones by global radix passes; 64..1024,
-                         values <= 64 send every block above 64 members to the global
-                         passes; 0 = library default. Ids do not depend on it. */
+  int32_t medium_cap; /* tuning: groups of 65..medium_cap members are ordered by one
+                         workgroup in LDS, larger ones by global radix passes; 0..4096,
+                         values <= 64 send every group above 64 members to the global
+                         passes; 0 = library default (4096). Ids do not depend on it. */
 } kbisim_options;
 
 /* Fills *opt with the defaults above. */

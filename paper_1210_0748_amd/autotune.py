@@ -14,7 +14,7 @@ import math
 import os
 import time
 
-CANDIDATES = (64, 256, 512, 1024)
+CANDIDATES = (64, 512, 1024, 4096)
 
 
 def _cache_path():

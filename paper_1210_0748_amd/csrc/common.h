@@ -61,6 +61,19 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
+// Wave-aggregated append: each active lane with `want` receives a distinct
+// slot counted from *counter (one atomic per wave). Every active lane of the
+// wave must call it; the return value is meaningful only where `want` holds.
+__device__ __forceinline__ uint32_t wave_append(bool want, uint32_t* counter) {
+  const uint64_t b = __ballot(want);
+  if (!b) return 0;
+  const int leader = __ffsll((unsigned long long)b) - 1;
+  uint32_t base = 0;
+  if (__lane_id() == leader) base = atomicAdd(counter, uint32_t(__popcll(b)));
+  base = __shfl(base, leader, kWave);
+  return base + uint32_t(__popcll(b & lanemask_lt()));
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll

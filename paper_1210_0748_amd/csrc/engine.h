@@ -59,21 +59,26 @@ struct HostWords {
   HostWords& operator=(const HostWords&) = delete;
 };
 
-constexpr uint32_t kDefaultMediumCap = 512;
+constexpr uint32_t kDefaultMediumCap = 4096;
 
 struct Options {
   bool early_stop = true;
   bool profile = false;
-  uint32_t medium_cap = kDefaultMediumCap;  // groups above this size use the global pass
+  uint32_t medium_cap = kDefaultMediumCap;  // groups above this size use the global passes
 };
 
 constexpr int kProfClasses = 7;
 
-// Segment lists produced by classification: small (one wave), medium (one
-// workgroup), large (global passes).
+// Work lists produced by classifying open segments by size: lane groups
+// (four widths), medium and big groups (one workgroup each) and large groups
+// (global passes). All lists share one set of arrays; list c is the range
+// [off[c], off[c] + cnt[c]).
+constexpr int kNumSegLists = 7;
 struct SegLists {
-  DevBuf s_start, s_size, s_depth, m_start, m_size, m_depth, l_start, l_size, l_depth;
-  uint32_t ns = 0, nm = 0, nl = 0;
+  DevBuf start, size, depth;
+  uint32_t cnt[kNumSegLists] = {};
+  uint32_t off[kNumSegLists] = {};
+  uint32_t count(int c) const { return cnt[c]; }
 };
 
 class Engine {
@@ -156,10 +161,10 @@ class Engine {
   bool fixed_ = false;
   std::vector<int64_t> counts_;
   // round scratch
-  DevBuf ukey_, ucnt_, cls_, scanpart_, radix_;
-  DevBuf seg_start_, seg_size_, seg_depth_, seg_done_, cf_small_, cf_medium_, cf_large_, off_;
+  DevBuf ukey_, ucnt_, cls_, scanpart_, radix_, bm_, bmslot_;
+  DevBuf seg_start_, seg_size_, seg_depth_, seg_done_, cls_part_, cls_meta_;
   SegLists lists_a_, lists_b_;
-  DevBuf l_ioff_, l_fd_, l_long_, l_open_;
+  DevBuf l_ioff_, l_lcp_, l_long_, l_open_;
   DevBuf k0_, k1_, k2_, k3_, k4_, v0_, v1_, v2_, v3_, v4_, sflag_, soff_, ipos_, sub_item_;
   DevBuf next_l_start_[2], next_l_size_[2], next_l_depth_[2];
 

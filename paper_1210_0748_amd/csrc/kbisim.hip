@@ -330,70 +330,68 @@ void Engine::assign_ids_into(int32_t* pid_out) {
 
 void Engine::make_lists(const uint32_t* seg_start, const uint32_t* seg_size, const uint32_t* seg_depth,
                         const uint8_t* seg_done, uint32_t nseg, SegLists& out, const uint32_t* nseg_dev) {
-  out.ns = out.nm = out.nl = 0;
+  static_assert(kNumSegLists == kSegClasses, "list count");
+  for (int c = 0; c < kNumSegLists; ++c) out.cnt[c] = out.off[c] = 0;
   if (nseg == 0) return;
-  const uint64_t n1 = uint64_t(nseg) + 1;
-  for (DevBuf* b : {&cf_small_, &cf_medium_, &cf_large_}) b->ensure(n1 * 4);
-  off_.ensure(3 * n1 * 4);
-  classify_segments_k<<<grid_for(nseg), kNT, 0, st_>>>(seg_size, seg_done, nseg, nseg_dev, opt_.medium_cap,
-                                                       cf_small_.as<uint32_t>(),
-                                                       cf_medium_.as<uint32_t>(), cf_large_.as<uint32_t>());
+  const uint32_t ntiles = ceil_div(nseg, kClassTile);
+  const uint32_t big_cap = opt_.medium_cap;
+  const uint32_t med_cap = std::min(opt_.medium_cap, kMediumCapSmall);
+  cls_part_.ensure(uint64_t(ntiles) * kSegClasses * 4);
+  cls_meta_.ensure(2 * kSegClasses * 4);
+  for (DevBuf* b : {&out.start, &out.size, &out.depth}) b->ensure(uint64_t(nseg) * 4);
+  class_count_k<<<ntiles, 256, 0, st_>>>(seg_size, seg_done, nseg, nseg_dev, med_cap, big_cap,
+                                         cls_part_.as<uint32_t>());
   KB_LAUNCH_CHECK();
-  // exclusive scans over nseg + 1 entries: entry nseg is the list length
-  // (the flag at index nseg is never read into it)
-  uint32_t* o = off_.as<uint32_t>();
-  scan_dev<uint32_t, uint32_t, false>(cf_small_.as<uint32_t>(), o, n1);
-  scan_dev<uint32_t, uint32_t, false>(cf_medium_.as<uint32_t>(), o + n1, n1);
-  scan_dev<uint32_t, uint32_t, false>(cf_large_.as<uint32_t>(), o + 2 * n1, n1);
+  class_offsets_k<<<1, 1024, 0, st_>>>(cls_part_.as<uint32_t>(), ntiles, cls_meta_.as<uint32_t>());
+  KB_LAUNCH_CHECK();
+  class_scatter_k<<<ntiles, 256, 0, st_>>>(seg_start, seg_size, seg_depth, seg_done, nseg, nseg_dev, med_cap,
+                                           big_cap, cls_part_.as<uint32_t>(), cls_meta_.as<uint32_t>(),
+                                           out.start.as<uint32_t>(), out.size.as<uint32_t>(),
+                                           out.depth.as<uint32_t>());
+  KB_LAUNCH_CHECK();
   uint32_t* hw32 = reinterpret_cast<uint32_t*>(hw_.p);
-  hw32[0] = hw32[1] = hw32[2] = 0;
-  KB_CHECK(hipMemcpyAsync(hw32 + 0, o + nseg, 4, hipMemcpyDeviceToHost, st_));
-  KB_CHECK(hipMemcpyAsync(hw32 + 1, o + n1 + nseg, 4, hipMemcpyDeviceToHost, st_));
-  KB_CHECK(hipMemcpyAsync(hw32 + 2, o + 2 * n1 + nseg, 4, hipMemcpyDeviceToHost, st_));
+  for (int c = 0; c < 2 * kSegClasses; ++c) hw32[c] = 0;  // before the copy is queued
+  KB_CHECK(hipMemcpyAsync(hw32, cls_meta_.p, 2 * kSegClasses * 4, hipMemcpyDeviceToHost, st_));
   KB_CHECK(hipStreamSynchronize(st_));
-  out.ns = hw32[0];
-  out.nm = hw32[1];
-  out.nl = hw32[2];
-  struct {
-    DevBuf *st, *sz, *dp;
-    uint32_t cnt;
-    const uint32_t* f;
-    const uint32_t* off;
-  } parts[3] = {{&out.s_start, &out.s_size, &out.s_depth, out.ns, cf_small_.as<uint32_t>(), o},
-                {&out.m_start, &out.m_size, &out.m_depth, out.nm, cf_medium_.as<uint32_t>(), o + n1},
-                {&out.l_start, &out.l_size, &out.l_depth, out.nl, cf_large_.as<uint32_t>(), o + 2 * n1}};
-  for (auto& pp : parts) {
-    if (!pp.cnt) continue;
-    pp.st->ensure(uint64_t(pp.cnt) * 4);
-    pp.sz->ensure(uint64_t(pp.cnt) * 4);
-    pp.dp->ensure(uint64_t(pp.cnt) * 4);
-    scatter_segments_k<<<grid_for(nseg), kNT, 0, st_>>>(seg_start, seg_size, seg_depth, nseg, pp.f, pp.off,
-                                                        pp.st->as<uint32_t>(), pp.sz->as<uint32_t>(),
-                                                        pp.dp->as<uint32_t>());
-    KB_LAUNCH_CHECK();
+  for (int c = 0; c < kSegClasses; ++c) {
+    out.cnt[c] = hw32[c];
+    out.off[c] = hw32[kSegClasses + c];
   }
+}
+
+template <int W, typename KeyT>
+static void launch_lanes(const SegLists& L, int c, uint32_t* ord, uint8_t* flag, const KeyView<KeyT>& kv,
+                         hipStream_t st) {
+  const uint32_t n = L.cnt[c];
+  if (!n) return;
+  const uint32_t o = L.off[c];
+  const uint32_t per_block = 256 / W;
+  resolve_lanes_k<W, KeyT><<<ceil_div(n, per_block), 256, 0, st>>>(
+      L.start.as<uint32_t>() + o, L.size.as<uint32_t>() + o, L.depth.as<uint32_t>() + o, n, ord, flag, kv);
+  KB_LAUNCH_CHECK();
 }
 
 template <typename KeyT>
 void Engine::resolve_lists(SegLists& L, const void* kvp) {
   const KeyView<KeyT>& kv = *static_cast<const KeyView<KeyT>*>(kvp);
-  if (L.ns) {
-    resolve_k<64, kSmallCap, KeyT><<<L.ns, 64, 0, st_>>>(L.s_start.as<uint32_t>(), L.s_size.as<uint32_t>(),
-                                                        L.s_depth.as<uint32_t>(), ord_.as<uint32_t>(),
-                                                        flag_.as<uint8_t>(), kv);
+  uint32_t* ord = ord_.as<uint32_t>();
+  uint8_t* flag = flag_.as<uint8_t>();
+  launch_lanes<8, KeyT>(L, 0, ord, flag, kv, st_);
+  launch_lanes<16, KeyT>(L, 1, ord, flag, kv, st_);
+  launch_lanes<32, KeyT>(L, 2, ord, flag, kv, st_);
+  launch_lanes<64, KeyT>(L, 3, ord, flag, kv, st_);
+  const uint32_t nm = L.cnt[kMediumClass];
+  if (nm) {
+    const uint32_t o = L.off[kMediumClass];
+    resolve_k<kMediumNT, kMediumCapSmall, KeyT><<<nm, kMediumNT, 0, st_>>>(
+        L.start.as<uint32_t>() + o, L.size.as<uint32_t>() + o, L.depth.as<uint32_t>() + o, ord, flag, kv);
     KB_LAUNCH_CHECK();
   }
-  if (L.nm) {
-    // LDS is sized for the largest group the list can hold: smaller groups
-    // leave room for more resident workgroups per CU
-    if (opt_.medium_cap <= kMediumCapSmall)
-      resolve_k<kMediumNT, kMediumCapSmall, KeyT><<<L.nm, kMediumNT, 0, st_>>>(
-          L.m_start.as<uint32_t>(), L.m_size.as<uint32_t>(), L.m_depth.as<uint32_t>(), ord_.as<uint32_t>(),
-          flag_.as<uint8_t>(), kv);
-    else
-      resolve_k<kMediumNT, kMediumCap, KeyT><<<L.nm, kMediumNT, 0, st_>>>(
-          L.m_start.as<uint32_t>(), L.m_size.as<uint32_t>(), L.m_depth.as<uint32_t>(), ord_.as<uint32_t>(),
-          flag_.as<uint8_t>(), kv);
+  const uint32_t nbig = L.cnt[kBigClass];
+  if (nbig) {
+    const uint32_t o = L.off[kBigClass];
+    resolve_k<kBigNT, kBigCap, KeyT><<<nbig, kBigNT, 0, st_>>>(
+        L.start.as<uint32_t>() + o, L.size.as<uint32_t>() + o, L.depth.as<uint32_t>() + o, ord, flag, kv);
     KB_LAUNCH_CHECK();
   }
 }
@@ -404,26 +402,21 @@ void Engine::order_groups(int key_bits, const void* kvp) {
   const uint32_t B = uint32_t(B_);
   seg_start_.ensure(uint64_t(B) * 4 + 4);
   seg_size_.ensure(uint64_t(B) * 4 + 4);
-  seg_depth_.ensure(uint64_t(B) * 4 + 4);
-  seg_done_.ensure(uint64_t(B) + 1);
   blocks_as_segments_k<<<grid_for(B), kNT, 0, st_>>>(bstart_.as<uint32_t>(), B, seg_start_.as<uint32_t>(),
-                                                     seg_size_.as<uint32_t>(), seg_depth_.as<uint32_t>(),
-                                                     seg_done_.as<uint8_t>());
+                                                     seg_size_.as<uint32_t>());
   KB_LAUNCH_CHECK();
-  make_lists(seg_start_.as<uint32_t>(), seg_size_.as<uint32_t>(), seg_depth_.as<uint32_t>(),
-             seg_done_.as<uint8_t>(), B, lists_a_);
+  make_lists(seg_start_.as<uint32_t>(), seg_size_.as<uint32_t>(), nullptr, nullptr, B, lists_a_);
   resolve_lists<KeyT>(lists_a_, kvp);
 
-  // Large groups: global passes, each splitting every group around its
-  // first member as a pivot.
-  const uint32_t* Ls = lists_a_.l_start.as<uint32_t>();
-  const uint32_t* Lz = lists_a_.l_size.as<uint32_t>();
-  const uint32_t* Ld = lists_a_.l_depth.as<uint32_t>();
-  uint32_t nl = lists_a_.nl;
+  // Large groups: global passes, each sorting every group by the digits
+  // after its common prefix.
+  uint32_t nl = lists_a_.cnt[kLargeClass];
+  const uint32_t* Ls = lists_a_.start.as<uint32_t>() + lists_a_.off[kLargeClass];
+  const uint32_t* Lz = lists_a_.size.as<uint32_t>() + lists_a_.off[kLargeClass];
+  const uint32_t* Ld = lists_a_.depth.as<uint32_t>() + lists_a_.off[kLargeClass];
   int nx = 0;
   const int dbits = key_bits + 1;
   const uint64_t last_mask = dbits >= 64 ? ~0ull : ((1ull << dbits) - 1);
-  const int fd_bits = bits_for(maxdeg_ > 0 ? maxdeg_ : 1);
   while (nl > 0) {
     // item offsets of the large groups (sizes with a trailing zero)
     l_ioff_.ensure((uint64_t(nl) + 1) * 4);
@@ -434,26 +427,25 @@ void Engine::order_groups(int key_bits, const void* kvp) {
     const uint32_t M = uint32_t(read_word(l_ioff_.as<uint32_t>() + nl, 4));
     const uint32_t* gio = l_ioff_.as<uint32_t>();
 
-    // first difference of every item with its group's pivot
-    l_fd_.ensure(uint64_t(M) * 4);
+    // end of every group's common prefix
+    l_lcp_.ensure(uint64_t(nl) * 4);
     l_long_.ensure((uint64_t(M) + 1) * 4);
+    KB_CHECK(hipMemsetAsync(l_lcp_.p, 0xff, uint64_t(nl) * 4, st_));
     KB_CHECK(hipMemsetAsync(l_long_.as<uint32_t>() + M, 0, 4, st_));
-    large_fd_k<KeyT><<<grid_for(M), kNT, 0, st_>>>(Ls, Ld, gio, nl, M, ord_.as<uint32_t>(), l_fd_.as<uint32_t>(),
-                                                  l_long_.as<uint32_t>(), l_long_.as<uint32_t>() + M, kv);
+    large_lcp_k<KeyT><<<grid_for(M), kNT, 0, st_>>>(Ls, Ld, gio, nl, M, ord_.as<uint32_t>(), l_lcp_.as<uint32_t>(),
+                                                   l_long_.as<uint32_t>(), l_long_.as<uint32_t>() + M, kv);
     KB_LAUNCH_CHECK();
-    large_fd_wave_k<KeyT><<<std::min<uint32_t>(grid_for(uint64_t(M) * kWave), 4096), kNT, 0, st_>>>(
-        Ls, Ld, gio, nl, ord_.as<uint32_t>(), l_fd_.as<uint32_t>(), l_long_.as<uint32_t>(),
+    large_lcp_wave_k<KeyT><<<std::min<uint32_t>(grid_for(uint64_t(M) * kWave), 4096), kNT, 0, st_>>>(
+        Ls, Ld, gio, nl, ord_.as<uint32_t>(), l_lcp_.as<uint32_t>(), l_long_.as<uint32_t>(),
         l_long_.as<uint32_t>() + M, kv);
     KB_LAUNCH_CHECK();
 
-    // sort key layout: one word when (group, side, distance, >= 1 digit) fit
+    // sort key layout: one word when (group, >= 1 digit) fit
     const int g_bits = nl > 1 ? bits_for(nl - 1) : 0;
-    const int hi_bits = g_bits + 2 + fd_bits;
     LargeKey lk;
-    lk.fd_bits = fd_bits;
-    if (hi_bits + dbits <= 64) {
+    if (g_bits + dbits <= 64) {
       lk.packed = true;
-      lk.width = uint32_t((64 - hi_bits) / dbits);
+      lk.width = uint32_t((64 - g_bits) / dbits);
     } else {
       lk.packed = false;
       lk.width = dbits >= 64 ? 1u : uint32_t(64 / dbits);
@@ -466,19 +458,19 @@ void Engine::order_groups(int key_bits, const void* kvp) {
     const uint64_t* KB = nullptr;
     const uint32_t* V;
     if (lk.packed) {
-      large_gather_k<KeyT><<<grid_for(M), kNT, 0, st_>>>(Ls, Ld, gio, nl, M, ord_.as<uint32_t>(), l_fd_.as<uint32_t>(),
+      large_gather_k<KeyT><<<grid_for(M), kNT, 0, st_>>>(Ls, gio, nl, M, ord_.as<uint32_t>(), l_lcp_.as<uint32_t>(),
                                                         lk, k0_.as<uint64_t>(), nullptr, v0_.as<uint32_t>(), kv);
       KB_LAUNCH_CHECK();
       const bool f = radix_sort<uint64_t>(k0_.as<uint64_t>(), v0_.as<uint32_t>(), k1_.as<uint64_t>(),
-                                          v1_.as<uint32_t>(), M, 0, hi_bits + lk.dig_bits, radix_scratch(M), st_);
+                                          v1_.as<uint32_t>(), M, 0, g_bits + lk.dig_bits, radix_scratch(M), st_);
       KA = f ? k1_.as<uint64_t>() : k0_.as<uint64_t>();
       V = f ? v1_.as<uint32_t>() : v0_.as<uint32_t>();
     } else {
       // two words: sort by lo (digits) carrying the item index, then stably
-      // by hi; the final order follows the second permutation
+      // by the group; the final order follows the second permutation
       for (DevBuf* b : {&k2_, &k3_, &k4_}) b->ensure(uint64_t(M) * 8);
       for (DevBuf* b : {&v2_, &v3_, &v4_}) b->ensure(uint64_t(M) * 4);
-      large_gather_k<KeyT><<<grid_for(M), kNT, 0, st_>>>(Ls, Ld, gio, nl, M, ord_.as<uint32_t>(), l_fd_.as<uint32_t>(),
+      large_gather_k<KeyT><<<grid_for(M), kNT, 0, st_>>>(Ls, gio, nl, M, ord_.as<uint32_t>(), l_lcp_.as<uint32_t>(),
                                                         lk, k2_.as<uint64_t>(), k0_.as<uint64_t>(),
                                                         v4_.as<uint32_t>(), kv);
       iota_k<<<grid_for(M), kNT, 0, st_>>>(v0_.as<uint32_t>(), M);
@@ -491,7 +483,7 @@ void Engine::order_groups(int key_bits, const void* kvp) {
       iota_k<<<grid_for(M), kNT, 0, st_>>>(v2_.as<uint32_t>(), M);
       KB_LAUNCH_CHECK();
       const bool f2 = radix_sort<uint64_t>(k3_.as<uint64_t>(), v2_.as<uint32_t>(), k4_.as<uint64_t>(),
-                                           v3_.as<uint32_t>(), M, 0, hi_bits, radix_scratch(M), st_);
+                                           v3_.as<uint32_t>(), M, 0, std::max(g_bits, 1), radix_scratch(M), st_);
       KA = f2 ? k4_.as<uint64_t>() : k3_.as<uint64_t>();
       const uint32_t* PS = f2 ? v3_.as<uint32_t>() : v2_.as<uint32_t>();
       uint64_t* lo_out = (L1 == k0_.as<uint64_t>()) ? k1_.as<uint64_t>() : k0_.as<uint64_t>();
@@ -512,9 +504,10 @@ void Engine::order_groups(int key_bits, const void* kvp) {
     seg_depth_.ensure(uint64_t(M) * 4 + 4);
     seg_done_.ensure(uint64_t(M) + 1);
     large_subgroups_k<<<grid_for(M), kNT, 0, st_>>>(sflag_.as<uint32_t>(), soff_.as<uint32_t>(), M,
-                                                    ipos_.as<uint32_t>(), KA, KB, lk, last_mask, Ld,
-                                                    sub_item_.as<uint32_t>(), seg_start_.as<uint32_t>(),
-                                                    seg_depth_.as<uint32_t>(), seg_done_.as<uint8_t>());
+                                                    ipos_.as<uint32_t>(), KA, KB, lk, last_mask,
+                                                    l_lcp_.as<uint32_t>(), sub_item_.as<uint32_t>(),
+                                                    seg_start_.as<uint32_t>(), seg_depth_.as<uint32_t>(),
+                                                    seg_done_.as<uint8_t>());
     subgroup_sizes_k<<<grid_for(M), kNT, 0, st_>>>(sub_item_.as<uint32_t>(), ns_dev, M, seg_size_.as<uint32_t>());
     KB_LAUNCH_CHECK();
     make_lists(seg_start_.as<uint32_t>(), seg_size_.as<uint32_t>(), seg_depth_.as<uint32_t>(),
@@ -522,13 +515,17 @@ void Engine::order_groups(int key_bits, const void* kvp) {
     resolve_lists<KeyT>(lists_b_, kvp);
     // the next pass works on the large subgroups (lists_b_ is reused below)
     const int nxt = nx ^ 1;
-    nl = lists_b_.nl;
+    nl = lists_b_.cnt[kLargeClass];
     if (nl) {
       const uint64_t bytes = uint64_t(nl) * 4;
+      const uint32_t o = lists_b_.off[kLargeClass];
       for (DevBuf* b : {&next_l_start_[nxt], &next_l_size_[nxt], &next_l_depth_[nxt]}) b->ensure(bytes);
-      KB_CHECK(hipMemcpyAsync(next_l_start_[nxt].p, lists_b_.l_start.p, bytes, hipMemcpyDeviceToDevice, st_));
-      KB_CHECK(hipMemcpyAsync(next_l_size_[nxt].p, lists_b_.l_size.p, bytes, hipMemcpyDeviceToDevice, st_));
-      KB_CHECK(hipMemcpyAsync(next_l_depth_[nxt].p, lists_b_.l_depth.p, bytes, hipMemcpyDeviceToDevice, st_));
+      KB_CHECK(hipMemcpyAsync(next_l_start_[nxt].p, lists_b_.start.as<uint32_t>() + o, bytes,
+                              hipMemcpyDeviceToDevice, st_));
+      KB_CHECK(hipMemcpyAsync(next_l_size_[nxt].p, lists_b_.size.as<uint32_t>() + o, bytes,
+                              hipMemcpyDeviceToDevice, st_));
+      KB_CHECK(hipMemcpyAsync(next_l_depth_[nxt].p, lists_b_.depth.as<uint32_t>() + o, bytes,
+                              hipMemcpyDeviceToDevice, st_));
     }
     Ls = next_l_start_[nxt].as<uint32_t>();
     Lz = next_l_size_[nxt].as<uint32_t>();
@@ -570,21 +567,44 @@ void Engine::round_impl() {
     KB_LAUNCH_CHECK();
     ev_end(ev);
   }
+  // small key universe: block and hub nodes de-duplicate through bitmaps,
+  // which the ordering then uses for first-difference searches
+  const bool use_bm = key_bits <= kBmKeyBits && (nb_ + nh_) > 0;
+  uint32_t bm_words = 0;
+  if (use_bm) {
+    bm_words = std::max<uint32_t>((1u << key_bits) / 32u, 4u);
+    bm_.ensure(uint64_t(nb_ + nh_) * bm_words * 4);
+    bmslot_.ensure(std::max<uint64_t>(N, 1) * 4);
+  }
   if (nb_) {
     ev = ev_begin(2);
-    sig_block_k<AdjT, KeyT><<<nb_, kSigBlockNT, 0, st_>>>(a, blist_.as<uint32_t>(), nb_);
+    if (use_bm)
+      sig_bitmap_k<AdjT, KeyT, kSigBlockNT><<<nb_, kSigBlockNT, 0, st_>>>(
+          a, blist_.as<uint32_t>(), BmOut{bm_.as<uint32_t>(), bmslot_.as<uint32_t>(), bm_words, 0u});
+    else
+      sig_block_k<AdjT, KeyT><<<nb_, kSigBlockNT, 0, st_>>>(a, blist_.as<uint32_t>(), nb_);
     KB_LAUNCH_CHECK();
     ev_end(ev);
   }
   if (nh_) {
     ev = ev_begin(3);
-    sig_hub_k<AdjT, KeyT><<<nh_, kHubNT, 0, st_>>>(a, hlist_.as<uint32_t>(), hub_off_.as<uint32_t>(),
-                                                   hub_tmp_.as<KeyT>(), key_bits);
+    if (use_bm)
+      sig_bitmap_k<AdjT, KeyT, 1024><<<nh_, 1024, 0, st_>>>(
+          a, hlist_.as<uint32_t>(), BmOut{bm_.as<uint32_t>(), bmslot_.as<uint32_t>(), bm_words, nb_});
+    else
+      sig_hub_k<AdjT, KeyT><<<nh_, kHubNT, 0, st_>>>(a, hlist_.as<uint32_t>(), hub_off_.as<uint32_t>(),
+                                                     hub_tmp_.as<KeyT>(), key_bits);
     KB_LAUNCH_CHECK();
     ev_end(ev);
   }
 
   KeyView<KeyT> kv{rowptr_.as<uint32_t>(), ukey_.as<KeyT>(), ucnt_.as<uint32_t>(), key_bits + 1};
+  if (use_bm) {
+    kv.bm = bm_.as<uint64_t>();
+    kv.bmslot = bmslot_.as<uint32_t>();
+    kv.bm_words64 = bm_words / 2;
+    kv.bm_min_deg = kWaveMaxDeg;
+  }
   const int evo = ev_begin(4);
   order_groups<KeyT>(key_bits, &kv);
   ev_end(evo);
@@ -1092,8 +1112,8 @@ static kbisim_status parse_options(const kbisim_options* opt, kb::Options* o) {
   if (!opt) return KBISIM_OK;
   o->early_stop = opt->early_stop != 0;
   o->profile = opt->profile != 0;
-  if (opt->medium_cap < 0 || opt->medium_cap > int32_t(kb::kMediumCap))
-    return fail(KBISIM_EINVAL, "medium_cap outside [0, 1024]");
+  if (opt->medium_cap < 0 || opt->medium_cap > int32_t(kb::kBigCap))
+    return fail(KBISIM_EINVAL, "medium_cap outside [0, 4096]");
   if (opt->medium_cap > 0) o->medium_cap = uint32_t(opt->medium_cap);
   return KBISIM_OK;
 }

@@ -4,8 +4,8 @@
 // each time costs milliseconds and an implicit device synchronisation. Freed
 // blocks are kept per device and handed out again (best fit, at most twice
 // the requested size). A block remembers the stream of its last user through
-// an event: a later user on another stream first waits for that event, so
-// reuse is ordered after every kernel that touched the block. When hipMalloc
+// an event: a later user on another stream makes its stream wait for that
+// event, so reuse is ordered after every kernel that touched the block. When hipMalloc
 // fails, all cached blocks are released and the allocation is retried.
 #pragma once
 
@@ -50,12 +50,17 @@ class Pool {
     }
     if (found) {
       if (b.ev) {
-        const hipError_t e1 = (b.stream != s) ? hipEventSynchronize(b.ev) : hipSuccess;
-        (void)hipEventDestroy(b.ev);
+        // order the new user's stream after the last user's work on the
+        // device; the host does not wait
+        const hipError_t e1 = (b.stream != s) ? hipStreamWaitEvent(s, b.ev, 0) : hipSuccess;
         if (e1 != hipSuccess) {
+          (void)hipGetLastError();
+          (void)hipEventSynchronize(b.ev);
+          (void)hipEventDestroy(b.ev);
           (void)hipFree(b.p);
           KB_CHECK(e1);
         }
+        (void)hipEventDestroy(b.ev);
       }
       *got = b.bytes;
       return b.p;

@@ -5,26 +5,31 @@
 // Canonical ids are lexicographic ranks of the signatures
 // [pid_prev(u), k1, k2, ...] (k = unique keys in ascending order, a proper
 // prefix is smaller). Because pid_prev(u) leads the signature, the new order
-// refines the old one block by block: the array `ord` holds the nodes sorted by
-// pid_prev (blocks contiguous, block b starting at bstart[b]), and only blocks
-// with two or more members need their members ordered by the key sequence.
+// refines the old one class by class: the array `ord` holds the nodes sorted
+// by class (classes contiguous), and only classes with two or more members
+// need their members ordered by the key sequence.
 //
-// Ordering a group is a most-significant-digit refinement with common-prefix
-// skipping. Every open subgroup S has a depth t(S): all members agree on the
-// keys before t(S). Each member finds the first position >= t(S) where its
-// sequence differs from that of the subgroup's first member (the leader); the
-// minimum d over the members is where S splits. If no member differs, S is a
-// set of identical signatures and closes. Otherwise the members are sorted by
-// digit(d) = key[d] + 1 (0 once the sequence has ended), split where the digit
-// changes, and every new subgroup gets depth d + 1. A subgroup whose sequences
-// ended at d, or that has one member, closes. When keys are narrow, several
-// consecutive digits are packed into one 64-bit sort digit (most significant
-// first), which consumes that many positions per iteration. Each iteration splits every
-// open subgroup, so the number of iterations does not depend on how long the
-// shared prefixes are. All comparisons are exact.
+// A group (a class, or a part of one whose members agree on all keys before
+// the group's depth t) is ordered by most-significant-digit refinement, with
+// digit(t) = key[t] + 1 (0 once the sequence has ended, so a proper prefix
+// sorts first). Two schemes split a group:
+//  * groups of up to a few hundred members (resolve_lanes_k, resolve_k) split
+//    around their first member (the pivot): each member finds the first
+//    position d where it differs from the pivot, and members are ordered by
+//    (below/equal/above the pivot at d, d, digits from d on); members that tie
+//    agree on everything before d + width and form the next subgroups;
+//  * larger groups go through global passes (large_*_k): the group's common
+//    prefix ends at the smallest such d over its members; all members are
+//    sorted by the digits from there with one device-wide radix sort, and
+//    runs of equal digits become the next groups.
+// When keys are narrow, several consecutive digits are packed into one
+// 64-bit sort digit (most significant first), which consumes that many
+// positions per step. A subgroup whose sequences ended inside the packed
+// digits, or that holds copies of one sequence, or a single member, closes.
+// All comparisons are exact.
 //
 // flag[p] = 1 marks the first position of every class (distinct signature) in
-// `ord`; an inclusive scan of flag then yields the new dense ids.
+// `ord`.
 #pragma once
 
 #include "common.h"
@@ -33,9 +38,10 @@
 namespace kb {
 
 constexpr uint32_t kSmallCap = 64;     // groups handled by one wave
-constexpr uint32_t kMediumCap = 1024;  // largest group one workgroup can order in LDS
-constexpr uint32_t kMediumCapSmall = 512;  // LDS size class for medium_cap <= 512
+constexpr uint32_t kMediumCapSmall = 512;  // groups one 256-thread workgroup orders in LDS
+constexpr uint32_t kBigCap = 4096;         // groups one 1024-thread workgroup orders in LDS
 constexpr int kMediumNT = 256;
+constexpr int kBigNT = 1024;
 constexpr uint32_t kNoDiff = 0xffffffffu;
 constexpr uint32_t kUndecided = 0xfffffffeu;
 constexpr uint32_t kThreadWindow = 32;  // keys one thread compares before asking its wave
@@ -46,6 +52,33 @@ struct KeyView {
   const KeyT* ukey;
   const uint32_t* ucnt;
   int dbits;  // bits of one digit: key bits + 1
+  // Optional key-set bitmaps (bm_words64 > 0) of every node with more than
+  // bm_min_deg edges: bitmap of node u at bm + bmslot[u] * bm_words64.
+  const uint64_t* bm = nullptr;
+  const uint32_t* bmslot = nullptr;
+  uint32_t bm_words64 = 0;
+  uint32_t bm_min_deg = 0;
+
+  __device__ __forceinline__ bool has_bm(uint32_t node) const {
+    return bm_words64 && rowptr[node + 1] - rowptr[node] > bm_min_deg;
+  }
+  // First difference of two key sets given as bitmaps: the smallest key x in
+  // exactly one of them; both sequences hold the same keys below x, so they
+  // first differ at the position equal to the number of those keys.
+  __device__ __forceinline__ uint32_t first_diff_bm(uint32_t a, uint32_t b) const {
+    const uint64_t* A = bm + size_t(bmslot[a]) * bm_words64;
+    const uint64_t* B = bm + size_t(bmslot[b]) * bm_words64;
+    uint32_t below = 0;
+    for (uint32_t w = 0; w < bm_words64; w += 2) {
+      const uint64_t a0 = A[w], a1 = A[w + 1], b0 = B[w], b1 = B[w + 1];
+      const uint64_t x0 = a0 ^ b0, x1 = a1 ^ b1;
+      if (x0) return below + uint32_t(__popcll(a0 & ((x0 & (~x0 + 1)) - 1)));
+      below += uint32_t(__popcll(a0));
+      if (x1) return below + uint32_t(__popcll(a1 & ((x1 & (~x1 + 1)) - 1)));
+      below += uint32_t(__popcll(a1));
+    }
+    return kNoDiff;
+  }
 
   __device__ __forceinline__ uint64_t digit(uint32_t node, uint32_t t) const {
     return t < ucnt[node] ? uint64_t(ukey[rowptr[node] + t]) + 1ull : 0ull;
@@ -92,6 +125,7 @@ struct KeyView {
   // kUndecided when the sequences agree on the whole window and continue.
   __device__ __forceinline__ uint32_t first_diff_window(uint32_t a, uint32_t b, uint32_t t,
                                                         uint32_t window) const {
+    if (has_bm(a) && has_bm(b)) return first_diff_bm(a, b);
     const uint32_t ca = ucnt[a], cb = ucnt[b];
     const uint32_t n = ca < cb ? ca : cb;
     const uint32_t stop = n > t ? ((n - t > window) ? t + window : n) : t;
@@ -176,21 +210,30 @@ __device__ __forceinline__ uint64_t side_key(uint32_t side, uint32_t rel) {
 // all agreeing on keys before gdepth) lexicographically and sets flag[] at
 // the first position of every class inside the group (the group's own first
 // position is already flagged). Each iteration splits every open subgroup
-// around its first member as a pivot (see side_key).
+// around its first member as a pivot (see side_key). Only members of open
+// subgroups take part in an iteration: their positions are listed in order
+// (an open subgroup is a contiguous range), the list is sorted by (subgroup,
+// side key, digits) through a permutation of positions, and the members are
+// then moved once to their new places.
 template <int NT, int CAP, typename KeyT>
 __global__ __launch_bounds__(NT) void resolve_k(const uint32_t* __restrict__ gstart,
                                                 const uint32_t* __restrict__ gsize,
                                                 const uint32_t* __restrict__ gdepth,
                                                 uint32_t* __restrict__ ord, uint8_t* __restrict__ flag,
                                                 KeyView<KeyT> kv) {
+  static_assert(CAP < 65535 && CAP % NT == 0, "positions are 16-bit");
+  constexpr uint16_t kPad = 0xffffu;
+  constexpr int kPer = CAP / NT;
   __shared__ uint32_t node[CAP];
-  __shared__ uint32_t sub[CAP];    // index of the subgroup's first member (the pivot)
-  __shared__ uint32_t dep[CAP];    // depth of the member's subgroup
+  __shared__ uint32_t dep[CAP];
+  __shared__ uint32_t sub[CAP];    // position of the member's subgroup pivot
   __shared__ uint64_t hk[CAP];     // first difference with the pivot, then side_key
   __shared__ uint64_t dig[CAP];    // packed digits from the first difference on
+  __shared__ uint16_t opos[CAP];   // positions of the open members, ascending
+  __shared__ uint16_t perm[CAP];   // sorted order of the open members (positions)
+  __shared__ uint16_t queue[CAP];  // members whose comparison needs a whole wave
   __shared__ uint8_t res[CAP];     // member's subgroup is closed
-  __shared__ uint8_t mark[CAP];
-  __shared__ uint32_t queue[CAP];  // members whose comparison needs a whole wave
+  __shared__ uint8_t mark[CAP];    // open-list entry starts a new subgroup
   __shared__ uint32_t qn;
   __shared__ uint32_t shm[NT / kWave > 0 ? NT / kWave : 1];
 
@@ -198,30 +241,39 @@ __global__ __launch_bounds__(NT) void resolve_k(const uint32_t* __restrict__ gst
   const uint32_t m = gsize[blockIdx.x];
   const uint32_t d0 = gdepth[blockIdx.x];
   const uint32_t width = kv.dbits >= 64 ? 1u : uint32_t(64 / kv.dbits);  // positions per digit
-  uint32_t P = 2;
-  while (P < m) P <<= 1;
-  for (uint32_t i = threadIdx.x; i < P; i += NT) {
-    const bool in = i < m;
-    node[i] = in ? ord[s + i] : 0xffffffffu;
-    sub[i] = in ? 0u : 0xffffffffu;
+  const uint64_t last_mask = kv.last_digit_mask();
+  for (uint32_t i = threadIdx.x; i < m; i += NT) {
+    node[i] = ord[s + i];
+    sub[i] = 0;
     dep[i] = d0;
-    res[i] = in ? 0 : 1;
-    hk[i] = in ? 0ull : ~0ull;
-    dig[i] = in ? 0ull : ~0ull;
+    res[i] = 0;
   }
   __syncthreads();
 
   for (;;) {
-    // (a) first difference of every open member with its pivot: a short
-    // window per thread, then whole waves (64 positions per step)
+    // (a) list the open members
+    uint32_t n = 0;
+    for (uint32_t base = 0; base < m; base += NT) {
+      const uint32_t i = base + threadIdx.x;
+      const bool f = i < m && !res[i];
+      uint32_t tot;
+      const uint32_t ex = block_exclusive_scan<NT>(uint32_t(f), shm, &tot);
+      if (f) opos[n + ex] = uint16_t(i);
+      n += tot;
+    }
+    if (n == 0) break;
     if (threadIdx.x == 0) qn = 0;
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < m; i += NT) {
-      uint32_t d = kNoDiff;
+
+    // (b) first difference with the pivot: a short window per thread, then
+    // whole waves (64 positions per step)
+    for (uint32_t k = threadIdx.x; k < n; k += NT) {
+      const uint32_t i = opos[k];
       const uint32_t L = sub[i];
-      if (!res[i] && i != L) {
+      uint32_t d = kNoDiff;
+      if (i != L) {
         d = kv.first_diff_window(node[i], node[L], dep[i], kThreadWindow);
-        if (d == kUndecided) queue[atomicAdd(&qn, 1u)] = i;
+        if (d == kUndecided) queue[atomicAdd(&qn, 1u)] = uint16_t(i);
       }
       hk[i] = d;
     }
@@ -233,14 +285,10 @@ __global__ __launch_bounds__(NT) void resolve_k(const uint32_t* __restrict__ gst
     }
     __syncthreads();
 
-    // (b) sort keys: (side, distance of the first difference, digits there)
+    // (c) sort keys: (side, distance of the first difference, digits there)
     bool open = false;
-    for (uint32_t i = threadIdx.x; i < m; i += NT) {
-      if (res[i]) {
-        hk[i] = 0;
-        dig[i] = 0;
-        continue;
-      }
+    for (uint32_t k = threadIdx.x; k < n; k += NT) {
+      const uint32_t i = opos[k];
       const uint32_t d = uint32_t(hk[i]);
       if (d == kNoDiff) {
         hk[i] = side_key(1, 0);
@@ -254,120 +302,344 @@ __global__ __launch_bounds__(NT) void resolve_k(const uint32_t* __restrict__ gst
         open = true;
       }
     }
-    if (!__syncthreads_or(open)) {
-      // every open subgroup consists of copies of its pivot: one class each
-      for (uint32_t i = threadIdx.x; i < m; i += NT) res[i] = 1;
-      __syncthreads();
-      break;
-    }
+    uint32_t P = 2;
+    while (P < n) P <<= 1;
+    for (uint32_t k = threadIdx.x; k < P; k += NT) perm[k] = k < n ? opos[k] : kPad;
+    if (!__syncthreads_or(open)) break;  // what is still open consists of copies of its pivot
 
-    // (c) sort by (subgroup, side key, digits); subgroups keep their ranges
+    // (d) bitonic sort of the open list by (subgroup, side key, digits);
+    // padding sorts last
     for (uint32_t size = 2; size <= P; size <<= 1) {
       for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-        for (uint32_t i = threadIdx.x; i < P / 2; i += NT) {
-          const uint32_t lo = 2 * i - (i & (stride - 1));
+        for (uint32_t t = threadIdx.x; t < P / 2; t += NT) {
+          const uint32_t lo = 2 * t - (t & (stride - 1));
           const uint32_t hi = lo + stride;
           const bool up = (lo & size) == 0;
-          const bool gt = sub[lo] != sub[hi] ? sub[lo] > sub[hi]
-                          : hk[lo] != hk[hi] ? hk[lo] > hk[hi]
-                                             : dig[lo] > dig[hi];
+          const uint32_t a = perm[lo], b = perm[hi];
+          bool gt;
+          if (a == kPad || b == kPad) {
+            gt = a == kPad && b != kPad;
+          } else {
+            gt = sub[a] != sub[b] ? sub[a] > sub[b] : hk[a] != hk[b] ? hk[a] > hk[b] : dig[a] > dig[b];
+          }
           if (gt == up) {
-            uint32_t tu = sub[lo]; sub[lo] = sub[hi]; sub[hi] = tu;
-            tu = node[lo]; node[lo] = node[hi]; node[hi] = tu;
-            tu = dep[lo]; dep[lo] = dep[hi]; dep[hi] = tu;
-            uint64_t td = hk[lo]; hk[lo] = hk[hi]; hk[hi] = td;
-            td = dig[lo]; dig[lo] = dig[hi]; dig[hi] = td;
-            const uint8_t tr = res[lo]; res[lo] = res[hi]; res[hi] = tr;
+            perm[lo] = uint16_t(b);
+            perm[hi] = uint16_t(a);
           }
         }
         __syncthreads();
       }
     }
 
-    // (d) split where the key changes; close copies of the pivot, ended
-    // sequences and single members
-    for (uint32_t i = threadIdx.x; i < m; i += NT)
-      mark[i] = (i == 0 || sub[i] != sub[i - 1] || hk[i] != hk[i - 1] || dig[i] != dig[i - 1]) ? 1 : 0;
-    __syncthreads();
-    uint32_t carry = 0;
-    for (uint32_t base = 0; base < m; base += NT) {
-      const uint32_t i = base + threadIdx.x;
-      const uint32_t v = (i < m && mark[i]) ? i : 0u;
-      uint32_t tot;
-      uint32_t r = block_inclusive_max<NT>(v, shm, &tot);
-      r = r > carry ? r : carry;
-      if (i < m) sub[i] = r;
-      carry = tot > carry ? tot : carry;
-    }
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < m; i += NT) {
-      if (mark[i] && i > 0) flag[s + i] = 1;
-      if (!res[i]) {
-        const bool single = mark[i] && (i + 1 == m || mark[i + 1]);
-        const bool copies = (hk[i] >> 32) == 1;
-        if (copies || (dig[i] & kv.last_digit_mask()) == 0 || single) res[i] = 1;
+    // (e) move: the k-th open position receives the k-th member in order
+    uint32_t tn[kPer], td[kPer];
+    uint64_t th[kPer], tg[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const uint32_t k = uint32_t(j) * NT + threadIdx.x;
+      if (k < n) {
+        const uint32_t src = perm[k];
+        tn[j] = node[src];
+        td[j] = dep[src];
+        th[j] = hk[src];
+        tg[j] = dig[src];
       }
     }
     __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const uint32_t k = uint32_t(j) * NT + threadIdx.x;
+      if (k < n) {
+        const uint32_t dst = opos[k];
+        node[dst] = tn[j];
+        dep[dst] = td[j];
+        hk[dst] = th[j];
+        dig[dst] = tg[j];
+      }
+    }
+    __syncthreads();
+
+    // (f) split where the key changes; close copies of the pivot, ended
+    // sequences and single members
+    for (uint32_t k = threadIdx.x; k < n; k += NT) {
+      const uint32_t i = opos[k];
+      bool mk = k == 0;
+      if (!mk) {
+        const uint32_t p = opos[k - 1];
+        mk = sub[i] != sub[p] || hk[i] != hk[p] || dig[i] != dig[p];
+      }
+      mark[k] = mk ? 1 : 0;
+    }
+    __syncthreads();
+    uint32_t carry = 0;
+    for (uint32_t base = 0; base < n; base += NT) {
+      const uint32_t k = base + threadIdx.x;
+      const uint32_t i = k < n ? opos[k] : 0u;
+      const uint32_t v = (k < n && mark[k]) ? i : 0u;
+      uint32_t tot;
+      uint32_t r = block_inclusive_max<NT>(v, shm, &tot);
+      r = r > carry ? r : carry;
+      if (k < n) {
+        if (mark[k] && i > 0) flag[s + i] = 1;
+        const bool single = mark[k] && (k + 1 == n || mark[k + 1]);
+        const bool copies = (hk[i] >> 32) == 1;
+        if (copies || (dig[i] & last_mask) == 0 || single) res[i] = 1;
+        sub[i] = r;
+      }
+      carry = tot > carry ? tot : carry;
+    }
+    __syncthreads();
   }
+  __syncthreads();
   for (uint32_t i = threadIdx.x; i < m; i += NT) ord[s + i] = node[i];
 }
 
+// Orders groups of at most W members (W a power of two <= 64), W lanes per
+// group and 256 / W groups per workgroup, with the same pivot splitting as
+// resolve_k: the members live in registers and are sorted by a bitonic
+// network over the group's lanes. Lanes past a group's size, and whole groups
+// past `ngroups`, are padding that sorts last and writes nothing.
+template <int W, typename KeyT>
+__global__ __launch_bounds__(256) void resolve_lanes_k(const uint32_t* __restrict__ gstart,
+                                                       const uint32_t* __restrict__ gsize,
+                                                       const uint32_t* __restrict__ gdepth, uint32_t ngroups,
+                                                       uint32_t* __restrict__ ord, uint8_t* __restrict__ flag,
+                                                       KeyView<KeyT> kv) {
+  static_assert(W >= 2 && W <= kWave && (W & (W - 1)) == 0, "W must be a power of two <= 64");
+  const uint32_t t = blockIdx.x * 256u + threadIdx.x;
+  const uint32_t gi = t / W;
+  const uint32_t l = t % W;
+  uint32_t s = 0, m = 0, d0 = 0;
+  if (gi < ngroups) {
+    s = gstart[gi];
+    m = gsize[gi];
+    d0 = gdepth[gi];
+  }
+  const bool in = l < m;
+  const uint32_t width = kv.dbits >= 64 ? 1u : uint32_t(64 / kv.dbits);
+  const uint64_t last_mask = kv.last_digit_mask();
+  uint32_t node = in ? ord[s + l] : 0xffffffffu;
+  uint32_t sub = in ? 0u : 0xffffffffu;  // lane of the subgroup's pivot
+  uint32_t dep = d0;
+  bool res = !in;
+  uint64_t hk = in ? 0ull : ~0ull, dig = in ? 0ull : ~0ull;
+
+  for (;;) {
+    // (a) first difference with the pivot: a short window per lane, then
+    // the whole wave for every lane whose window agreed
+    const uint32_t lead = __shfl(node, in ? sub : l, W);
+    uint32_t d = kNoDiff;
+    if (!res && l != sub) d = kv.first_diff_window(node, lead, dep, kThreadWindow);
+    for (uint64_t pend = __ballot(d == kUndecided); pend; pend &= pend - 1) {
+      const int q = __ffsll((unsigned long long)pend) - 1;
+      const uint32_t qa = __shfl(node, q, kWave), qb = __shfl(lead, q, kWave), qt = __shfl(dep, q, kWave);
+      const uint32_t r = kv.wave_first_diff(qa, qb, qt + kThreadWindow);
+      if (__lane_id() == q) d = r;
+    }
+    // (b) sort keys
+    bool open = false;
+    if (res) {
+      hk = in ? 0ull : ~0ull;
+      dig = in ? 0ull : ~0ull;
+    } else if (d == kNoDiff) {
+      hk = side_key(1, 0);
+      dig = 0;
+    } else {
+      const uint64_t da = kv.digit(node, d), dl = kv.digit(lead, d);
+      hk = side_key(da < dl ? 0u : 2u, d - dep);
+      dig = kv.digits(node, d, width);
+      dep = d + width;
+      open = true;
+    }
+    if (!__any(open)) break;  // what is still open consists of copies of its pivot
+    // (c) bitonic sort over the group's lanes by (sub, hk, dig)
+#pragma unroll
+    for (int size = 2; size <= W; size <<= 1) {
+#pragma unroll
+      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+        const uint32_t o_sub = __shfl_xor(sub, stride, W);
+        const uint64_t o_hk = __shfl_xor(hk, stride, W);
+        const uint64_t o_dig = __shfl_xor(dig, stride, W);
+        const uint32_t o_node = __shfl_xor(node, stride, W);
+        const uint32_t o_dep = __shfl_xor(dep, stride, W);
+        const int o_res = __shfl_xor(int(res), stride, W);
+        const bool o_less = o_sub != sub ? o_sub < sub : o_hk != hk ? o_hk < hk : o_dig < dig;
+        const bool o_more = o_sub != sub ? o_sub > sub : o_hk != hk ? o_hk > hk : o_dig > dig;
+        const bool keep_min = ((l & size) == 0) == ((l & stride) == 0);
+        if (keep_min ? o_less : o_more) {
+          sub = o_sub;
+          hk = o_hk;
+          dig = o_dig;
+          node = o_node;
+          dep = o_dep;
+          res = o_res != 0;
+        }
+      }
+    }
+    // (d) split where the key changes; close copies of the pivot, ended
+    // sequences and single members
+    const uint32_t p_sub = __shfl_up(sub, 1, W);
+    const uint64_t p_hk = __shfl_up(hk, 1, W);
+    const uint64_t p_dig = __shfl_up(dig, 1, W);
+    const bool mark = in && (l == 0 || p_sub != sub || p_hk != hk || p_dig != dig);
+    uint32_t v = mark ? l : 0u;
+#pragma unroll
+    for (int o = 1; o < W; o <<= 1) {
+      const uint32_t u = __shfl_up(v, o, W);
+      if (l >= uint32_t(o)) v = u > v ? u : v;
+    }
+    const bool next_mark = __shfl_down(int(mark), 1, W) != 0;
+    if (in) {
+      if (mark && l > 0) flag[s + l] = 1;
+      if (!res) {
+        const bool single = mark && (l + 1 == m || next_mark);
+        const bool copies = (hk >> 32) == 1;
+        if (copies || (dig & last_mask) == 0 || single) res = true;
+      }
+      sub = v;
+    }
+  }
+  if (in) ord[s + l] = node;
+}
+
 // ---------------------------------------------------------------------------
-// Segments (blocks of the previous round, or subgroups after a global split)
-// and their classification into work lists by size.
+// Segments (open groups) and their classification into work lists by size.
+//
+// Classes 0-3 hold groups of at most 8, 16, 32, 64 members (resolve_lanes_k
+// with that many lanes per group); kMediumClass groups of up to medium_cap
+// (<= kMediumCapSmall) members (resolve_k, 256 threads); kBigClass groups of
+// up to big_cap (<= kBigCap) members (resolve_k, 1024 threads); kLargeClass
+// the rest (global passes). The lists share one set of arrays: list c
+// occupies [off[c], off[c] + cnt[c]). Every group is ordered on its own.
 
 // Segment j of the previous partition: block j with start bstart[j], depth 0.
 __global__ void blocks_as_segments_k(const uint32_t* __restrict__ bstart, uint32_t nblocks,
-                                     uint32_t* __restrict__ seg_start, uint32_t* __restrict__ seg_size,
-                                     uint32_t* __restrict__ seg_depth, uint8_t* __restrict__ seg_done) {
+                                     uint32_t* __restrict__ seg_start, uint32_t* __restrict__ seg_size) {
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= nblocks) return;
   const uint32_t a = bstart[j], b = bstart[j + 1];
   seg_start[j] = a;
   seg_size[j] = b - a;
-  seg_depth[j] = 0;
-  seg_done[j] = (b - a) <= 1;
 }
 
-// Open segments of up to kSmallCap members go to the wave resolver, up to
-// medium_cap (<= kMediumCap) to the workgroup resolver, the rest to the
-// global pass.
-// nseg is an upper bound; when nseg_dev is given, segments at or past
-// *nseg_dev get no class.
-__global__ void classify_segments_k(const uint32_t* __restrict__ seg_size,
-                                    const uint8_t* __restrict__ seg_done, uint32_t nseg,
-                                    const uint32_t* __restrict__ nseg_dev, uint32_t medium_cap,
-                                    uint32_t* __restrict__ c_small, uint32_t* __restrict__ c_medium,
-                                    uint32_t* __restrict__ c_large) {
-  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= nseg) return;
-  if (nseg_dev && j >= *nseg_dev) {
-    c_small[j] = c_medium[j] = c_large[j] = 0;
-    return;
-  }
+constexpr int kLaneClasses = 4;
+constexpr int kMediumClass = kLaneClasses;
+constexpr int kBigClass = kLaneClasses + 1;
+constexpr int kLargeClass = kLaneClasses + 2;
+constexpr int kSegClasses = kLaneClasses + 3;
+
+// medium_cap <= kMediumCapSmall <= big_cap; a group above big_cap is large.
+__device__ __forceinline__ int seg_class(uint32_t z, uint32_t medium_cap, uint32_t big_cap) {
+  return z <= 8 ? 0 : z <= 16 ? 1 : z <= 32 ? 2 : z <= kSmallCap ? 3 : z <= medium_cap ? kMediumClass
+         : z <= big_cap ? kBigClass : kLargeClass;
+}
+
+// Classification is a three-kernel scan over tiles of kClassTile segments:
+// per-tile counts of every class, an exclusive scan of those counts per class
+// (one workgroup), and a scatter that ranks every open segment inside its
+// tile. Segment j is open when it has two or more members and is not done;
+// nseg is an upper bound and, when nseg_dev is given, only j < *nseg_dev exist.
+constexpr int kClassIPT = 8;
+constexpr int kClassTile = 256 * kClassIPT;
+
+__device__ __forceinline__ int open_class(const uint32_t* seg_size, const uint8_t* seg_done, uint32_t n,
+                                          uint32_t j, uint32_t medium_cap, uint32_t big_cap) {
+  if (j >= n) return -1;
   const uint32_t z = seg_size[j];
-  const bool done = seg_done[j] || z <= 1;
-  c_small[j] = !done && z <= kSmallCap;
-  c_medium[j] = !done && z > kSmallCap && z <= medium_cap;
-  c_large[j] = !done && z > kSmallCap && z > medium_cap;
+  if (z <= 1 || (seg_done && seg_done[j])) return -1;
+  return seg_class(z, medium_cap, big_cap);
 }
 
-// Scatters segment j to list position off[j] when its class flag is set
-// (off = exclusive scan of the flags).
-__global__ void scatter_segments_k(const uint32_t* __restrict__ seg_start,
-                                   const uint32_t* __restrict__ seg_size,
-                                   const uint32_t* __restrict__ seg_depth, uint32_t nseg,
-                                   const uint32_t* __restrict__ cflag, const uint32_t* __restrict__ off,
-                                   uint32_t* __restrict__ out_start, uint32_t* __restrict__ out_size,
-                                   uint32_t* __restrict__ out_depth) {
-  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= nseg) return;
-  if (cflag[j]) {
-    const uint32_t o = off[j];
+// Per-thread class counts packed 16 bits per class (a tile has at most
+// 2048 segments): classes 0-3 in lo, 4.. in hi.
+__device__ __forceinline__ void add_class(int c, uint64_t& lo, uint64_t& hi) {
+  if (c < 0) return;
+  if (c < 4)
+    lo += 1ull << (16 * c);
+  else
+    hi += 1ull << (16 * (c - 4));
+}
+__device__ __forceinline__ uint32_t class_field(int c, uint64_t lo, uint64_t hi) {
+  return uint32_t(((c < 4 ? lo : hi) >> (16 * (c & 3))) & 0xffffu);
+}
+
+// part[c * ntiles + tile] = number of open segments of class c in the tile.
+__global__ __launch_bounds__(256) void class_count_k(const uint32_t* __restrict__ seg_size,
+                                                     const uint8_t* __restrict__ seg_done, uint32_t nseg,
+                                                     const uint32_t* __restrict__ nseg_dev, uint32_t medium_cap,
+                                                     uint32_t big_cap, uint32_t* __restrict__ part) {
+  __shared__ uint64_t sh[256 / kWave];
+  const uint32_t n = nseg_dev ? min(nseg, *nseg_dev) : nseg;
+  const uint32_t base = blockIdx.x * uint32_t(kClassTile);
+  uint64_t lo = 0, hi = 0;
+#pragma unroll
+  for (int q = 0; q < kClassIPT; ++q)
+    add_class(open_class(seg_size, seg_done, n, base + q * 256u + threadIdx.x, medium_cap, big_cap), lo, hi);
+  uint64_t tl, th;
+  block_exclusive_scan<256>(lo, sh, &tl);
+  block_exclusive_scan<256>(hi, sh, &th);
+  if (threadIdx.x < kSegClasses) part[threadIdx.x * gridDim.x + blockIdx.x] = class_field(threadIdx.x, tl, th);
+}
+
+// In place: part[c * ntiles + t] = exclusive prefix over tiles; meta[c] =
+// count of class c, meta[kSegClasses + c] = offset of list c.
+__global__ __launch_bounds__(1024) void class_offsets_k(uint32_t* __restrict__ part, uint32_t ntiles,
+                                                        uint32_t* __restrict__ meta) {
+  __shared__ uint32_t sh[1024 / kWave];
+  __shared__ uint32_t tot_c[kSegClasses];
+  for (int c = 0; c < kSegClasses; ++c) {
+    uint32_t* p = part + size_t(c) * ntiles;
+    uint32_t carry = 0;
+    for (uint32_t b = 0; b < ntiles; b += 1024) {
+      const uint32_t i = b + threadIdx.x;
+      const uint32_t v = i < ntiles ? p[i] : 0u;
+      uint32_t tot;
+      const uint32_t ex = block_exclusive_scan<1024>(v, sh, &tot);
+      if (i < ntiles) p[i] = carry + ex;
+      carry += tot;
+    }
+    if (threadIdx.x == 0) tot_c[c] = carry;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t off = 0;
+    for (int c = 0; c < kSegClasses; ++c) {
+      meta[c] = tot_c[c];
+      meta[kSegClasses + c] = off;
+      off += tot_c[c];
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void class_scatter_k(
+    const uint32_t* __restrict__ seg_start, const uint32_t* __restrict__ seg_size,
+    const uint32_t* __restrict__ seg_depth, const uint8_t* __restrict__ seg_done, uint32_t nseg,
+    const uint32_t* __restrict__ nseg_dev, uint32_t medium_cap, uint32_t big_cap,
+    const uint32_t* __restrict__ part, const uint32_t* __restrict__ meta, uint32_t* __restrict__ out_start,
+    uint32_t* __restrict__ out_size, uint32_t* __restrict__ out_depth) {
+  __shared__ uint64_t sh[256 / kWave];
+  const uint32_t n = nseg_dev ? min(nseg, *nseg_dev) : nseg;
+  const uint32_t base = blockIdx.x * uint32_t(kClassTile);
+  int cls[kClassIPT];
+  uint64_t lo = 0, hi = 0;
+#pragma unroll
+  for (int q = 0; q < kClassIPT; ++q) {
+    cls[q] = open_class(seg_size, seg_done, n, base + q * 256u + threadIdx.x, medium_cap, big_cap);
+    add_class(cls[q], lo, hi);
+  }
+  uint64_t tl, th;
+  uint64_t el = block_exclusive_scan<256>(lo, sh, &tl);
+  uint64_t eh = block_exclusive_scan<256>(hi, sh, &th);
+#pragma unroll
+  for (int q = 0; q < kClassIPT; ++q) {
+    const int c = cls[q];
+    if (c < 0) continue;
+    const uint32_t j = base + q * 256u + threadIdx.x;
+    const uint32_t o = meta[kSegClasses + c] + part[c * gridDim.x + blockIdx.x] + class_field(c, el, eh);
+    add_class(c, el, eh);
     out_start[o] = seg_start[j];
     out_size[o] = seg_size[j];
-    out_depth[o] = seg_depth[j];
+    out_depth[o] = seg_depth ? seg_depth[j] : 0u;
   }
 }
 
@@ -388,34 +660,53 @@ __device__ __forceinline__ uint32_t group_of_item(const uint32_t* ioff, uint32_t
   return lo;
 }
 
-// fdv[i] = first difference of item i's sequence with its group leader's
-// (kNoDiff for the leader and its copies). Each thread compares one item
-// over a short window; items that still agree are appended to `longq` for
-// large_fd_wave_k.
-template <typename KeyT>
-__global__ __launch_bounds__(256) void large_fd_k(
-    const uint32_t* __restrict__ gstart, const uint32_t* __restrict__ gdepth, const uint32_t* __restrict__ ioff,
-    uint32_t ng, uint32_t nitems, const uint32_t* __restrict__ ord, uint32_t* __restrict__ fdv,
-    uint32_t* __restrict__ longq, uint32_t* __restrict__ nlong, KeyView<KeyT> kv) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nitems) return;
-  const uint32_t g = group_of_item(ioff, ng, i);
-  const uint32_t a = ord[gstart[g] + (i - ioff[g])];
-  const uint32_t b = ord[gstart[g]];
-  uint32_t d = kNoDiff;
-  if (a != b) {
-    d = kv.first_diff_window(a, b, gdepth[g], kThreadWindow);
-    if (d == kUndecided) longq[atomicAdd(nlong, 1u)] = i;
+// atomicMin(&lcp[g], d) for d != kNoDiff, with one atomic per wave when the
+// wave's lanes share one group (the common case: groups are long runs of
+// items), and none when lcp[g] is already at most d.
+__device__ __forceinline__ void lcp_update(uint32_t* lcp, uint32_t g, uint32_t d) {
+  const uint32_t g0 = __shfl(g, __ffsll((unsigned long long)__ballot(true)) - 1, kWave);
+  if (__all(g == g0)) {
+    const uint32_t m = wave_min(d);
+    const int first = __ffsll((unsigned long long)__ballot(true)) - 1;
+    if (__lane_id() == first && m != kNoDiff &&
+        m < __hip_atomic_load(&lcp[g0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicMin(&lcp[g0], m);
+  } else if (d != kNoDiff && d < __hip_atomic_load(&lcp[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+    atomicMin(&lcp[g], d);
   }
-  fdv[i] = d;
+}
+
+// lcp[g] = smallest first difference of a member of group g with the group's
+// first member (kNoDiff when all members are copies of it); lcp[] starts at
+// kNoDiff. Each thread compares one item over a short window; items that
+// still agree are appended to `longq` for large_lcp_wave_k.
+template <typename KeyT>
+__global__ __launch_bounds__(256) void large_lcp_k(const uint32_t* __restrict__ gstart,
+                                                   const uint32_t* __restrict__ gdepth,
+                                                   const uint32_t* __restrict__ ioff, uint32_t ng, uint32_t nitems,
+                                                   const uint32_t* __restrict__ ord, uint32_t* __restrict__ lcp,
+                                                   uint32_t* __restrict__ longq, uint32_t* __restrict__ nlong,
+                                                   KeyView<KeyT> kv) {
+  // no early exit: the wave-wide steps below need every lane
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t g = 0xffffffffu, d = kNoDiff;
+  if (i < nitems) {
+    g = group_of_item(ioff, ng, i);
+    const uint32_t a = ord[gstart[g] + (i - ioff[g])];
+    const uint32_t b = ord[gstart[g]];
+    if (a != b) d = kv.first_diff_window(a, b, gdepth[g], kThreadWindow);
+  }
+  const uint32_t slot = wave_append(d == kUndecided, nlong);
+  if (d == kUndecided) longq[slot] = i;
+  lcp_update(lcp, g, d == kUndecided ? kNoDiff : d);
 }
 
 // One wave per queued item, grid-stride over the queue length in *nlong.
 template <typename KeyT>
-__global__ void large_fd_wave_k(const uint32_t* __restrict__ gstart, const uint32_t* __restrict__ gdepth,
-                                const uint32_t* __restrict__ ioff, uint32_t ng, const uint32_t* __restrict__ ord,
-                                uint32_t* __restrict__ fdv, const uint32_t* __restrict__ longq,
-                                const uint32_t* __restrict__ nlong, KeyView<KeyT> kv) {
+__global__ void large_lcp_wave_k(const uint32_t* __restrict__ gstart, const uint32_t* __restrict__ gdepth,
+                                 const uint32_t* __restrict__ ioff, uint32_t ng, const uint32_t* __restrict__ ord,
+                                 uint32_t* __restrict__ lcp, const uint32_t* __restrict__ longq,
+                                 const uint32_t* __restrict__ nlong, KeyView<KeyT> kv) {
   const uint32_t nq = *nlong;
   const uint32_t waves = gridDim.x * (blockDim.x / kWave);
   for (uint32_t q = (blockIdx.x * blockDim.x + threadIdx.x) / kWave; q < nq; q += waves) {
@@ -424,23 +715,19 @@ __global__ void large_fd_wave_k(const uint32_t* __restrict__ gstart, const uint3
     const uint32_t a = ord[gstart[g] + (i - ioff[g])];
     const uint32_t b = ord[gstart[g]];
     const uint32_t d = kv.wave_first_diff(a, b, gdepth[g] + kThreadWindow);
-    if (__lane_id() == 0) fdv[i] = d;
+    if (__lane_id() == 0 && d != kNoDiff) atomicMin(&lcp[g], d);
   }
 }
 
-// Layout of the global sort key of an item of group g (see side_key):
-//   hi = g << (2 + fd_bits) | side << fd_bits | fdkey
-//   lo = `width` packed digits from the first difference on
-// fdkey = distance of the first difference from the group depth (below),
-// or its complement in fd_bits (above). Packed into one word as
-// hi << dig_bits | lo when it fits, else kept as two words.
+// Global sort key of an item of group g: the group index above `width`
+// digits taken from the group's common-prefix end lcp[g] on. Packed into one
+// word as g << dig_bits | digits when it fits, else kept as two words.
 struct LargeKey {
-  int fd_bits;
-  int dig_bits;   // width * dbits
+  int dig_bits;  // width * dbits
   uint32_t width;
   bool packed;
-  __device__ __forceinline__ uint64_t hi_of(const uint64_t* ka, const uint64_t* kb, uint32_t i) const {
-    return packed ? (dig_bits >= 64 ? 0ull : ka[i] >> dig_bits) : ka[i];
+  __device__ __forceinline__ uint32_t group_of(const uint64_t* ka, uint32_t i) const {
+    return uint32_t(packed ? (dig_bits >= 64 ? 0ull : ka[i] >> dig_bits) : ka[i]);
   }
   __device__ __forceinline__ uint64_t lo_of(const uint64_t* ka, const uint64_t* kb, uint32_t i) const {
     return packed ? (dig_bits >= 64 ? ka[i] : (ka[i] & ((1ull << dig_bits) - 1))) : kb[i];
@@ -448,30 +735,20 @@ struct LargeKey {
 };
 
 template <typename KeyT>
-__global__ void large_gather_k(const uint32_t* __restrict__ gstart, const uint32_t* __restrict__ gdepth,
-                               const uint32_t* __restrict__ ioff, uint32_t ng, uint32_t nitems,
-                               const uint32_t* __restrict__ ord, const uint32_t* __restrict__ fdv, LargeKey lk,
-                               uint64_t* __restrict__ ka, uint64_t* __restrict__ kb, uint32_t* __restrict__ val,
-                               KeyView<KeyT> kv) {
+__global__ void large_gather_k(const uint32_t* __restrict__ gstart, const uint32_t* __restrict__ ioff,
+                               uint32_t ng, uint32_t nitems, const uint32_t* __restrict__ ord,
+                               const uint32_t* __restrict__ lcp, LargeKey lk, uint64_t* __restrict__ ka,
+                               uint64_t* __restrict__ kb, uint32_t* __restrict__ val, KeyView<KeyT> kv) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nitems) return;
   const uint32_t g = group_of_item(ioff, ng, i);
   const uint32_t node = ord[gstart[g] + (i - ioff[g])];
-  const uint32_t d = fdv[i];
-  uint64_t side = 1, fdkey = 0, lo = 0;
-  if (d != kNoDiff) {
-    const uint32_t leader = ord[gstart[g]];
-    const uint64_t fdmask = (1ull << lk.fd_bits) - 1;
-    const uint64_t rel = d - gdepth[g];
-    side = kv.digit(node, d) < kv.digit(leader, d) ? 0 : 2;
-    fdkey = side == 0 ? rel : (fdmask - rel);
-    lo = kv.digits(node, d, lk.width);
-  }
-  const uint64_t hi = (uint64_t(g) << (2 + lk.fd_bits)) | (side << lk.fd_bits) | fdkey;
+  const uint32_t d = lcp[g];
+  const uint64_t lo = d == kNoDiff ? 0ull : kv.digits(node, d, lk.width);
   if (lk.packed) {
-    ka[i] = (lk.dig_bits >= 64 ? 0ull : (hi << lk.dig_bits)) | lo;
+    ka[i] = (lk.dig_bits >= 64 ? 0ull : (uint64_t(g) << lk.dig_bits)) | lo;
   } else {
-    ka[i] = hi;
+    ka[i] = g;
     kb[i] = lo;
   }
   val[i] = node;
@@ -486,40 +763,37 @@ __global__ void large_write_k(const uint32_t* __restrict__ gstart, const uint32_
                               uint32_t* __restrict__ item_pos) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nitems) return;
-  const uint64_t hi = lk.hi_of(ka, kb, i), lo = lk.lo_of(ka, kb, i);
-  const uint32_t g = uint32_t(hi >> (2 + lk.fd_bits));
+  const uint32_t g = lk.group_of(ka, i);
+  const uint64_t lo = lk.lo_of(ka, kb, i);
   const uint32_t p = gstart[g] + (i - ioff[g]);
   ord[p] = val[i];
   item_pos[i] = p;
-  const bool st = (i == ioff[g]) || hi != lk.hi_of(ka, kb, i - 1) || lo != lk.lo_of(ka, kb, i - 1);
+  const bool st = (i == ioff[g]) || lo != lk.lo_of(ka, kb, i - 1);
   start_flag[i] = st;
   if (st && i != ioff[g]) flag[p] = 1;
 }
 
 // Subgroup j starts at item S[j] (S = compacted start flags). Its depth is
-// `width` past its first difference with the pivot; it is closed when it
-// holds copies of the pivot or its sequences ended inside the digits.
+// `width` past its group's common prefix; it is closed when the group held
+// copies of one sequence or its sequences ended inside the digits.
 __global__ void large_subgroups_k(const uint32_t* __restrict__ start_flag,
                                   const uint32_t* __restrict__ start_off, uint32_t nitems,
                                   const uint32_t* __restrict__ item_pos, const uint64_t* __restrict__ ka,
                                   const uint64_t* __restrict__ kb, LargeKey lk, uint64_t last_mask,
-                                  const uint32_t* __restrict__ gdepth, uint32_t* __restrict__ sub_item,
+                                  const uint32_t* __restrict__ lcp, uint32_t* __restrict__ sub_item,
                                   uint32_t* __restrict__ seg_start, uint32_t* __restrict__ seg_depth,
                                   uint8_t* __restrict__ seg_done) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nitems) return;
   if (start_flag[i]) {
     const uint32_t j = start_off[i];
-    const uint64_t hi = lk.hi_of(ka, kb, i), lo = lk.lo_of(ka, kb, i);
-    const uint64_t fdmask = (1ull << lk.fd_bits) - 1;
-    const uint32_t g = uint32_t(hi >> (2 + lk.fd_bits));
-    const uint32_t side = uint32_t(hi >> lk.fd_bits) & 3u;
-    const uint64_t fdkey = hi & fdmask;
-    const uint64_t rel = side == 0 ? fdkey : (fdmask - fdkey);
+    const uint32_t g = lk.group_of(ka, i);
+    const uint64_t lo = lk.lo_of(ka, kb, i);
+    const uint32_t d = lcp[g];
     sub_item[j] = i;
     seg_start[j] = item_pos[i];
-    seg_depth[j] = side == 1 ? 0u : uint32_t(gdepth[g] + rel + lk.width);
-    seg_done[j] = side == 1 || (lo & last_mask) == 0;
+    seg_depth[j] = d == kNoDiff ? 0u : d + lk.width;
+    seg_done[j] = d == kNoDiff || (lo & last_mask) == 0;
   }
 }
 

@@ -285,6 +285,76 @@ __global__ __launch_bounds__(kHubNT) void sig_hub_k(SigArgs<AdjT, KeyT> a, const
   }
 }
 
+// ---- small key universes: bitmap de-duplication -----------------------------
+// When every key is below 2^kBmKeyBits, a node's unique keys are the set bits
+// of a bitmap of `words` 32-bit words: the workgroup ORs the node's keys into
+// LDS, then lists the set bits in ascending order (a block scan of the word
+// popcounts gives each word's first output slot). The bitmap itself is kept
+// in bm[slot * words ...] for later first-difference searches, and
+// bmslot[n] = slot. Used for nodes with more than kWaveMaxDeg edges: list
+// entry i gets slot slot0 + i.
+constexpr int kBmKeyBits = 12;
+constexpr uint32_t kBmMaxWords = (1u << kBmKeyBits) / 32;
+
+struct BmOut {
+  uint32_t* bm;      // [slots * words]
+  uint32_t* bmslot;  // [N]
+  uint32_t words;    // 32-bit words per bitmap (>= 2)
+  uint32_t slot0;
+};
+
+template <typename AdjT, typename KeyT, int NT>
+__global__ __launch_bounds__(NT) void sig_bitmap_k(SigArgs<AdjT, KeyT> a, const uint32_t* __restrict__ list,
+                                                   BmOut o) {
+  __shared__ uint32_t w[kBmMaxWords];
+  __shared__ uint32_t shs[NT / kWave];
+  const uint32_t n = list[blockIdx.x];
+  if (!a.active(n)) return;
+  const uint32_t nw = o.words;
+  for (uint32_t i = threadIdx.x; i < nw; i += NT) w[i] = 0;
+  __syncthreads();
+  const uint32_t beg = a.rowptr[n];
+  const uint32_t deg = a.rowptr[n + 1] - beg;
+  // four edges in flight per thread
+  uint32_t i = threadIdx.x;
+  for (; i + 3 * NT < deg; i += 4 * NT) {
+    const AdjT e0 = a.adj[beg + i], e1 = a.adj[beg + i + NT];
+    const AdjT e2 = a.adj[beg + i + 2 * NT], e3 = a.adj[beg + i + 3 * NT];
+    const uint32_t k0 = uint32_t(a.key_of(e0)), k1 = uint32_t(a.key_of(e1));
+    const uint32_t k2 = uint32_t(a.key_of(e2)), k3 = uint32_t(a.key_of(e3));
+    atomicOr(&w[k0 >> 5], 1u << (k0 & 31));
+    atomicOr(&w[k1 >> 5], 1u << (k1 & 31));
+    atomicOr(&w[k2 >> 5], 1u << (k2 & 31));
+    atomicOr(&w[k3 >> 5], 1u << (k3 & 31));
+  }
+  for (; i < deg; i += NT) {
+    const uint32_t k = uint32_t(a.key_of(a.adj[beg + i]));
+    atomicOr(&w[k >> 5], 1u << (k & 31));
+  }
+  __syncthreads();
+  const uint32_t slot = o.slot0 + blockIdx.x;
+  uint32_t* out = o.bm + size_t(slot) * nw;
+  KeyT* uk = a.ukey + beg;
+  uint32_t carry = 0;
+  for (uint32_t base = 0; base < nw; base += NT) {
+    const uint32_t j = base + threadIdx.x;
+    uint32_t v = j < nw ? w[j] : 0u;
+    if (j < nw) out[j] = v;
+    uint32_t tot;
+    uint32_t r = carry + block_exclusive_scan<NT>(uint32_t(__popc(v)), shs, &tot);
+    while (v) {
+      const uint32_t b = uint32_t(__ffs(v) - 1);
+      uk[r++] = KeyT(j * 32u + b);
+      v &= v - 1;
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    a.ucnt[n] = carry;
+    o.bmslot[n] = slot;
+  }
+}
+
 // Work of the signature kernels (profiling only, launched separately so the
 // timed kernels carry no counters): per bucket, active nodes and their edges.
 __global__ __launch_bounds__(256) void work_count_k(const uint32_t* __restrict__ rowptr,

@@ -79,7 +79,7 @@ def test_degree_buckets():
     check_parity(g, 6)
 
 
-@pytest.mark.parametrize("medium_cap", [None, 64, 300])
+@pytest.mark.parametrize("medium_cap", [None, 64, 300, 1000])
 def test_powerlaw_mid(medium_cap):
     """Power-law graph with hubs and large blocks; the split between the
     workgroup resolver and the global passes must not change any id."""
