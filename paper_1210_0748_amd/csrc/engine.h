@@ -161,7 +161,7 @@ class Engine {
   bool fixed_ = false;
   std::vector<int64_t> counts_;
   // round scratch
-  DevBuf ukey_, ucnt_, cls_, scanpart_, radix_, bm_, bmslot_;
+  DevBuf ukey_, ucnt_, head_, cls_, scanpart_, radix_, bm_, bmslot_;
   DevBuf seg_start_, seg_size_, seg_depth_, seg_done_, cls_part_, cls_meta_;
   SegLists lists_a_, lists_b_;
   DevBuf l_ioff_, l_lcp_, l_long_, l_open_;

@@ -415,6 +415,7 @@ void Engine::order_groups(int key_bits, const void* kvp) {
   const uint32_t* Lz = lists_a_.size.as<uint32_t>() + lists_a_.off[kLargeClass];
   const uint32_t* Ld = lists_a_.depth.as<uint32_t>() + lists_a_.off[kLargeClass];
   int nx = 0;
+  bool first_pass = true;
   const int dbits = key_bits + 1;
   const uint64_t last_mask = dbits >= 64 ? ~0ull : ((1ull << dbits) - 1);
   while (nl > 0) {
@@ -427,18 +428,28 @@ void Engine::order_groups(int key_bits, const void* kvp) {
     const uint32_t M = uint32_t(read_word(l_ioff_.as<uint32_t>() + nl, 4));
     const uint32_t* gio = l_ioff_.as<uint32_t>();
 
-    // end of every group's common prefix
+    // end of every group's common prefix; the first pass works on whole
+    // classes at depth 0 and sorts by their first digits directly (a class
+    // whose members share them all comes back as one subgroup and has its
+    // common prefix measured in the next pass)
     l_lcp_.ensure(uint64_t(nl) * 4);
-    l_long_.ensure((uint64_t(M) + 1) * 4);
-    KB_CHECK(hipMemsetAsync(l_lcp_.p, 0xff, uint64_t(nl) * 4, st_));
-    KB_CHECK(hipMemsetAsync(l_long_.as<uint32_t>() + M, 0, 4, st_));
-    large_lcp_k<KeyT><<<grid_for(M), kNT, 0, st_>>>(Ls, Ld, gio, nl, M, ord_.as<uint32_t>(), l_lcp_.as<uint32_t>(),
-                                                   l_long_.as<uint32_t>(), l_long_.as<uint32_t>() + M, kv);
-    KB_LAUNCH_CHECK();
-    large_lcp_wave_k<KeyT><<<std::min<uint32_t>(grid_for(uint64_t(M) * kWave), 4096), kNT, 0, st_>>>(
-        Ls, Ld, gio, nl, ord_.as<uint32_t>(), l_lcp_.as<uint32_t>(), l_long_.as<uint32_t>(),
-        l_long_.as<uint32_t>() + M, kv);
-    KB_LAUNCH_CHECK();
+    if (first_pass) {
+      KB_CHECK(hipMemsetAsync(l_lcp_.p, 0, uint64_t(nl) * 4, st_));
+    } else {
+      l_long_.ensure((uint64_t(M) + 1) * 4);
+      KB_CHECK(hipMemsetAsync(l_lcp_.p, 0xff, uint64_t(nl) * 4, st_));
+      KB_CHECK(hipMemsetAsync(l_long_.as<uint32_t>() + M, 0, 4, st_));
+      large_lcp_k<KeyT><<<grid_for(M), kNT, 0, st_>>>(Ls, Ld, gio, nl, M, ord_.as<uint32_t>(),
+                                                     l_lcp_.as<uint32_t>(), l_long_.as<uint32_t>(),
+                                                     l_long_.as<uint32_t>() + M, kv);
+      KB_LAUNCH_CHECK();
+      large_lcp_wave_k<KeyT><<<std::min<uint32_t>(grid_for(uint64_t(M) * kWave), 4096), kNT, 0, st_>>>(
+          Ls, Ld, gio, nl, ord_.as<uint32_t>(), l_lcp_.as<uint32_t>(), l_long_.as<uint32_t>(),
+          l_long_.as<uint32_t>() + M, kv);
+      KB_LAUNCH_CHECK();
+    }
+    const uint64_t* head = first_pass ? head_.as<uint64_t>() : nullptr;
+    const uint32_t head_w = dbits >= 64 ? 1u : uint32_t(64 / dbits);
 
     // sort key layout: one word when (group, >= 1 digit) fit
     const int g_bits = nl > 1 ? bits_for(nl - 1) : 0;
@@ -459,7 +470,8 @@ void Engine::order_groups(int key_bits, const void* kvp) {
     const uint32_t* V;
     if (lk.packed) {
       large_gather_k<KeyT><<<grid_for(M), kNT, 0, st_>>>(Ls, gio, nl, M, ord_.as<uint32_t>(), l_lcp_.as<uint32_t>(),
-                                                        lk, k0_.as<uint64_t>(), nullptr, v0_.as<uint32_t>(), kv);
+                                                        lk, k0_.as<uint64_t>(), nullptr, v0_.as<uint32_t>(), kv,
+                                                        head, head_w);
       KB_LAUNCH_CHECK();
       const bool f = radix_sort<uint64_t>(k0_.as<uint64_t>(), v0_.as<uint32_t>(), k1_.as<uint64_t>(),
                                           v1_.as<uint32_t>(), M, 0, g_bits + lk.dig_bits, radix_scratch(M), st_);
@@ -472,7 +484,7 @@ void Engine::order_groups(int key_bits, const void* kvp) {
       for (DevBuf* b : {&v2_, &v3_, &v4_}) b->ensure(uint64_t(M) * 4);
       large_gather_k<KeyT><<<grid_for(M), kNT, 0, st_>>>(Ls, gio, nl, M, ord_.as<uint32_t>(), l_lcp_.as<uint32_t>(),
                                                         lk, k2_.as<uint64_t>(), k0_.as<uint64_t>(),
-                                                        v4_.as<uint32_t>(), kv);
+                                                        v4_.as<uint32_t>(), kv, head, head_w);
       iota_k<<<grid_for(M), kNT, 0, st_>>>(v0_.as<uint32_t>(), M);
       KB_LAUNCH_CHECK();
       const bool f1 = radix_sort<uint64_t>(k0_.as<uint64_t>(), v0_.as<uint32_t>(), k1_.as<uint64_t>(),
@@ -531,6 +543,7 @@ void Engine::order_groups(int key_bits, const void* kvp) {
     Lz = next_l_size_[nxt].as<uint32_t>();
     Ld = next_l_depth_[nxt].as<uint32_t>();
     nx = nxt;
+    first_pass = false;
   }
 }
 
@@ -548,6 +561,10 @@ void Engine::round_impl() {
   a.ucnt = ucnt_.as<uint32_t>();
   a.dst_bits = dst_bits_;
   a.pid_bits = pid_bits;
+  a.hdbits = key_bits + 1;
+  a.hw = a.hdbits >= 64 ? 1u : uint32_t(64 / a.hdbits);
+  head_.ensure(std::max<uint64_t>(N, 1) * 8);
+  a.head = head_.as<uint64_t>();
   if (opt_.profile) {
     if (!work_.p) {
       work_.ensure(8 * sizeof(unsigned long long));

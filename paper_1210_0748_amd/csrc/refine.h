@@ -734,17 +734,26 @@ struct LargeKey {
   }
 };
 
+// head (optional, only when every group is at depth 0 with lcp 0): the
+// first head_w digits of every node, packed as by KeyView::digits.
 template <typename KeyT>
 __global__ void large_gather_k(const uint32_t* __restrict__ gstart, const uint32_t* __restrict__ ioff,
                                uint32_t ng, uint32_t nitems, const uint32_t* __restrict__ ord,
                                const uint32_t* __restrict__ lcp, LargeKey lk, uint64_t* __restrict__ ka,
-                               uint64_t* __restrict__ kb, uint32_t* __restrict__ val, KeyView<KeyT> kv) {
+                               uint64_t* __restrict__ kb, uint32_t* __restrict__ val, KeyView<KeyT> kv,
+                               const uint64_t* __restrict__ head, uint32_t head_w) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nitems) return;
   const uint32_t g = group_of_item(ioff, ng, i);
   const uint32_t node = ord[gstart[g] + (i - ioff[g])];
   const uint32_t d = lcp[g];
-  const uint64_t lo = d == kNoDiff ? 0ull : kv.digits(node, d, lk.width);
+  uint64_t lo;
+  if (head) {
+    const uint32_t drop = (head_w - lk.width) * uint32_t(kv.dbits);
+    lo = drop >= 64 ? 0ull : head[node] >> drop;
+  } else {
+    lo = d == kNoDiff ? 0ull : kv.digits(node, d, lk.width);
+  }
   if (lk.packed) {
     ka[i] = (lk.dig_bits >= 64 ? 0ull : (uint64_t(g) << lk.dig_bits)) | lo;
   } else {

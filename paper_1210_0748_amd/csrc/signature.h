@@ -37,8 +37,18 @@ struct SigArgs {
   const uint32_t* bstart;  // [B+1] block start positions (block sizes)
   KeyT* ukey;              // [E] unique keys per node at rowptr offsets
   uint32_t* ucnt;          // [N]
+  uint64_t* head;          // [N] first hw digits (key + 1, 0 past the end), most significant first
   int dst_bits;
   int pid_bits;
+  int hdbits;              // bits of one digit: key bits + 1
+  uint32_t hw;             // digits per head word: 64 / hdbits
+
+  __device__ __forceinline__ uint64_t head_of(const KeyT* k, uint32_t c) const {
+    if (hdbits >= 64) return c ? uint64_t(k[0]) + 1ull : 0ull;
+    uint64_t v = 0;
+    for (uint32_t j = 0; j < hw; ++j) v = (v << hdbits) | (j < c ? uint64_t(k[j]) + 1ull : 0ull);
+    return v;
+  }
 
   __device__ __forceinline__ KeyT key_of(AdjT a) const {
     const uint32_t dst = uint32_t(a & ((AdjT(1) << dst_bits) - 1));
@@ -95,6 +105,7 @@ __global__ __launch_bounds__(256) void sig_thread_k(SigArgs<AdjT, KeyT> a, uint3
       }
     }
     a.ucnt[n] = c;
+    a.head[n] = a.head_of(a.ukey + beg, c);
   }
 }
 
@@ -132,9 +143,16 @@ __global__ __launch_bounds__(256) void sig_wave_k(SigArgs<AdjT, KeyT> a, const u
   const KeyT prev = __shfl_up(k, 1, kWave);
   const bool f = uint32_t(lane) < deg && (lane == 0 || k != prev);
   const uint64_t b = __ballot(f);
-  if (f) a.ukey[beg + __popcll(b & lanemask_lt())] = k;
+  const uint32_t r = uint32_t(__popcll(b & lanemask_lt()));
+  if (f) a.ukey[beg + r] = k;
+  // head word: the first hw unique keys, OR-reduced over the wave
+  uint64_t hv = 0;
+  if (f && r < a.hw) hv = a.hdbits >= 64 ? uint64_t(k) + 1ull : (uint64_t(k) + 1ull) << ((a.hw - 1 - r) * a.hdbits);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) hv |= __shfl_xor(hv, o, kWave);
   if (lane == 0) {
     a.ucnt[n] = __popcll(b);
+    a.head[n] = hv;
   }
 }
 
@@ -191,8 +209,10 @@ __global__ __launch_bounds__(kSigBlockNT) void sig_block_k(SigArgs<AdjT, KeyT> a
   __syncthreads();
   block_bitonic(s, P);
   const uint32_t c = block_unique_write<kSigBlockNT>(s, deg, a.ukey + beg);
+  __syncthreads();
   if (threadIdx.x == 0) {
     a.ucnt[n] = c;
+    a.head[n] = a.head_of(a.ukey + beg, c);
   }
 }
 
@@ -282,6 +302,7 @@ __global__ __launch_bounds__(kHubNT) void sig_hub_k(SigArgs<AdjT, KeyT> a, const
   }
   if (threadIdx.x == 0) {
     a.ucnt[n] = carry;
+    a.head[n] = a.head_of(A, carry);
   }
 }
 
@@ -349,8 +370,10 @@ __global__ __launch_bounds__(NT) void sig_bitmap_k(SigArgs<AdjT, KeyT> a, const 
     }
     carry += tot;
   }
+  __syncthreads();
   if (threadIdx.x == 0) {
     a.ucnt[n] = carry;
+    a.head[n] = a.head_of(uk, carry);
     o.bmslot[n] = slot;
   }
 }
