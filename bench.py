@@ -28,9 +28,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Algorithmic bytes per unit of the signature kernels: each processed edge
-# reads its (label, dst) table entry (4 + 4 B in a plain table layout) and
-# gathers pid_prev[dst] (4 B); each processed node reads row_ptr (4 B) and
+# Algorithmic bytes per unit of the signature launch: each edge of an active
+# node reads its (label, dst) table entry (4 + 4 B in a plain table layout)
+# and gathers pid_prev[dst] (4 B); each active node reads row_ptr (4 B) and
 # pid_prev (4 B) and its id write is 4 B.
 BYTES_PER_EDGE = 12
 BYTES_PER_NODE = 12
@@ -155,13 +155,12 @@ def main():
     assert counts_p == counts
     log("profile: " + json.dumps(prof))
     log("work: " + json.dumps(work))
-    classes = ["sig_thread", "sig_wave", "sig_block", "sig_hub"]
-    dom = max(classes, key=lambda c: prof[c][0])
+    # dominant kernel: the signature launch (one per round, all degree buckets)
+    dom = "signature"
     ms_total, launches = prof[dom]
-    nodes, edges = work[dom]
-    # the thread-per-node kernel also reads row_ptr and pid of every node
-    scanned_nodes = g.num_nodes * launches if dom == "sig_thread" else nodes
-    algo_bytes_per_launch = (BYTES_PER_EDGE * edges + BYTES_PER_NODE * scanned_nodes) / max(launches, 1)
+    nodes = sum(v[0] for v in work.values())
+    edges = sum(v[1] for v in work.values())
+    algo_bytes_per_launch = (BYTES_PER_EDGE * edges + BYTES_PER_NODE * nodes) / max(launches, 1)
     avg_ms = ms_total / max(launches, 1)
     achieved = algo_bytes_per_launch / (avg_ms / 1e3) / 1e9
     traffic = load_traffic(dom)
@@ -184,7 +183,7 @@ def main():
         "rounds_only": {"ms": rounds_only_ms,
                         "edge_rounds_per_s": g.num_edges * rd / (rounds_only_ms / 1e3),
                         "note": "sum of per-round event times of the profiled step (no create)"},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+        "roofline": {"bound": "hbm", "kernel": "signature_k", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic,
                      "launch_avg_ms": avg_ms, "algo_bytes_per_launch": algo_bytes_per_launch},

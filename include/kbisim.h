@@ -106,15 +106,21 @@ kbisim_status kbisim_result(const kbisim_graph* g, int32_t* pid_out, kbisim_mem 
 
 /* Kernel classes timed when options.profile = 1. */
 typedef enum {
-  KBISIM_PROF_SIG_THREAD = 0, /* signatures, out-degree <= 16 (one thread per node) */
-  KBISIM_PROF_SIG_WAVE = 1,   /* signatures, out-degree <= 64 (one wave per node) */
-  KBISIM_PROF_SIG_BLOCK = 2,  /* signatures, out-degree <= 4096 (one workgroup per node) */
-  KBISIM_PROF_SIG_HUB = 3,    /* signatures, larger out-degree */
-  KBISIM_PROF_ORDER = 4,      /* ordering signatures inside blocks (all kernels) */
-  KBISIM_PROF_ASSIGN = 5,     /* scan + id assignment */
-  KBISIM_PROF_ROUND = 6,      /* one whole round */
-  KBISIM_PROF_COUNT = 7
+  KBISIM_PROF_SIGNATURE = 0, /* the signature launch of a round (all out-degree buckets) */
+  KBISIM_PROF_ORDER = 1,     /* ordering signatures inside classes (all kernels) */
+  KBISIM_PROF_ASSIGN = 2,    /* ids of the round and the next round's active set */
+  KBISIM_PROF_ROUND = 3,     /* one whole round */
+  KBISIM_PROF_COUNT = 4
 } kbisim_prof_class;
+
+/* Signature work buckets (kbisim_work), by out-degree. */
+typedef enum {
+  KBISIM_BUCKET_THREAD = 0, /* <= 16 edges: one thread per node */
+  KBISIM_BUCKET_WAVE = 1,   /* <= 64 edges: one wave per node */
+  KBISIM_BUCKET_BLOCK = 2,  /* <= 4096 edges: one workgroup per node */
+  KBISIM_BUCKET_HUB = 3,    /* more edges: one workgroup per node */
+  KBISIM_BUCKET_COUNT = 4
+} kbisim_bucket;
 
 /* Timings collected when options.profile = 1 with HIP events recorded on the
  * handle's stream around each launch of class c: ms[c] = summed milliseconds,
@@ -123,10 +129,10 @@ typedef enum {
 kbisim_status kbisim_profile(const kbisim_graph* g, double* ms, int64_t* launches, int32_t cap,
                              int32_t reset);
 
-/* Work done by the signature kernels when options.profile = 1, summed over
- * rounds: nodes_edges[2c] = nodes processed by bucket c (KBISIM_PROF_SIG_*,
- * c = 0..3) and nodes_edges[2c+1] = their out-edges. Nodes alone in their
- * block are skipped by every bucket and not counted. cap = entries (8). */
+/* Work done by the signature launches when options.profile = 1, summed over
+ * rounds: nodes_edges[2c] = nodes of bucket c (kbisim_bucket) and
+ * nodes_edges[2c+1] = their out-edges. Only active nodes (members of classes
+ * with two or more members) are processed and counted. cap = entries (8). */
 kbisim_status kbisim_work(const kbisim_graph* g, int64_t* nodes_edges, int32_t cap, int32_t reset);
 
 /* Frees everything owned by the handle. NULL is ignored. */
@@ -165,7 +171,7 @@ void kbisim_batch_destroy(kbisim_batch* b);
 /* ---- Served form ----------------------------------------------------------
  * A request loop for many jobs of different sizes on one GPU. Requests queue
  * in FIFO order; a request is admitted when one of max_slots slots is free
- * and its estimated device footprint (about 36 B per edge + 96 B per node +
+ * and its estimated device footprint (about 36 B per edge + 160 B per node +
  * 64 MB) fits in what hbm_budget_bytes has left. Admitted requests run
  * concurrently, each on its own stream with its partition state resident in
  * device memory across rounds, so requests that arrive while others run

@@ -11,7 +11,8 @@ _LIB_PATH = os.path.join(_HERE, "libkbisim.so")
 
 KBISIM_MEM_HOST = 0
 KBISIM_MEM_DEVICE = 1
-PROF_CLASSES = ["sig_thread", "sig_wave", "sig_block", "sig_hub", "order", "assign", "round"]
+PROF_CLASSES = ["signature", "order", "assign", "round"]
+WORK_BUCKETS = ["thread", "wave", "block", "hub"]
 
 STATUS = {0: "KBISIM_OK", -1: "KBISIM_EINVAL", -2: "KBISIM_ENOMEM", -3: "KBISIM_EDEVICE",
           -4: "KBISIM_ESTATE", -5: "KBISIM_EBUSY", -6: "KBISIM_ECANCELED", -7: "KBISIM_ETIMEDOUT"}
@@ -208,7 +209,7 @@ def kbisim_work(handle, reset=False):
     """Per signature bucket: (active nodes, their edges), summed over rounds."""
     w = np.zeros(8, np.int64)
     _check(load_library().kbisim_work(handle, w.ctypes.data, 8, 1 if reset else 0))
-    return {PROF_CLASSES[c]: (int(w[2 * c]), int(w[2 * c + 1])) for c in range(4)}
+    return {WORK_BUCKETS[c]: (int(w[2 * c]), int(w[2 * c + 1])) for c in range(4)}
 
 
 def kbisim_release_cached():

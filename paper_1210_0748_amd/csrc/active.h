@@ -1,0 +1,181 @@
+// The active set of a refinement round and the id assignment that ends it.
+//
+// Refinement never merges classes (Proposition 1), so a class with a single
+// member stays alone and keeps its place in `ord`. A round therefore only
+// works on the active segments: the classes of the previous round with two
+// or more members. Ids are kept as class-start positions: the id of node u
+// is the position in `ord` of the first member of u's class. These ids order
+// the classes exactly as the dense ids do (both increase along `ord`), so
+// they serve as pId_{i-1} inside signatures, and a node of an untouched class
+// keeps its id from round to round. Dense 0-based ids are a scan of the
+// class-start flags, computed only when ids are read out.
+#pragma once
+
+#include "common.h"
+#include "compact.h"
+#include "refine.h"
+
+namespace kb {
+
+// Words of the per-round summary the host reads back in one copy.
+constexpr int kInfoSeg = 0;                          // next segments: counts, list starts, total
+constexpr int kInfoBucket = 2 * kSegClasses + 1;     // degree buckets: counts, list starts, total
+constexpr int kNumBuckets = 3;                       // wave, block, hub lists
+constexpr int kInfoClasses = kInfoBucket + 2 * kNumBuckets + 1;  // classes among the active positions
+constexpr int kInfoItems = kInfoClasses + 1;         // positions of the next active segments
+constexpr int kInfoWords = kInfoItems + 1;
+
+// apos[j] = position of active item j, anode[j] = ord[apos[j]]; segment t of
+// the list covers positions [seg_s[t], seg_s[t] + size), soff is the
+// exclusive scan of the sizes (soff[S] = number of items), S = *s_dev.
+// Thread 0 also records the number of items in info.
+// actr[anode[j]] = tag marks the active nodes of the round.
+__global__ void expand_k(const uint32_t* __restrict__ seg_s, const uint32_t* __restrict__ soff,
+                         const uint32_t* __restrict__ s_dev, uint32_t m_cap, const uint32_t* __restrict__ ord,
+                         uint32_t* __restrict__ apos, uint32_t* __restrict__ anode, uint32_t* __restrict__ actr,
+                         uint32_t tag, uint32_t* __restrict__ info) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t S = *s_dev;
+  const uint32_t M = soff[S];
+  if (j == 0) info[kInfoItems] = M;
+  if (j >= m_cap || j >= M) return;
+  uint32_t lo = 0, hi = S;  // last t with soff[t] <= j
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (soff[mid] <= j)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  const uint32_t p = seg_s[lo] + (j - soff[lo]);
+  const uint32_t u = ord[p];
+  apos[j] = p;
+  anode[j] = u;
+  actr[u] = tag;
+}
+
+// Out-degree bucket of an active node for the signature kernel: wave (17..64
+// edges), block (65..4096) or hub; nodes with at most 16 edges need no list.
+struct NodeBucketOf {
+  const uint32_t* anode;
+  const uint32_t* rowptr;
+  uint32_t thread_max, wave_max, block_max;
+  __device__ __forceinline__ int operator()(uint32_t j) const {
+    const uint32_t n = anode[j];
+    const uint32_t d = rowptr[n + 1] - rowptr[n];
+    return d <= thread_max ? -1 : d <= wave_max ? 0 : d <= block_max ? 1 : 2;
+  }
+};
+struct NodeWrite {
+  const uint32_t* anode;
+  uint32_t* list;
+  __device__ __forceinline__ void operator()(uint32_t j, int, uint32_t o) const { list[o] = anode[j]; }
+};
+// The same over all nodes in id order (lists in node order: neighbouring
+// nodes have neighbouring rows), for rounds where most nodes are active.
+struct NodeBucketDenseOf {
+  const uint32_t* actr;
+  uint32_t tag;
+  const uint32_t* rowptr;
+  uint32_t thread_max, wave_max, block_max;
+  __device__ __forceinline__ int operator()(uint32_t n) const {
+    if (actr[n] != tag) return -1;
+    const uint32_t d = rowptr[n + 1] - rowptr[n];
+    return d <= thread_max ? -1 : d <= wave_max ? 0 : d <= block_max ? 1 : 2;
+  }
+};
+struct NodeWriteDense {
+  uint32_t* list;
+  __device__ __forceinline__ void operator()(uint32_t n, int, uint32_t o) const { list[o] = n; }
+};
+
+// Initial segments: the blocks of pId_0 (block b spans [bstart[b], bstart[b+1])).
+struct BlockSegOf {
+  const uint32_t* bstart;
+  uint32_t medium_cap, big_cap;
+  __device__ __forceinline__ int operator()(uint32_t b) const {
+    const uint32_t z = bstart[b + 1] - bstart[b];
+    return z >= 2 ? seg_class(z, medium_cap, big_cap) : -1;
+  }
+};
+struct BlockSegWrite {
+  const uint32_t* bstart;
+  uint32_t *o_start, *o_size, *o_depth;
+  __device__ __forceinline__ void operator()(uint32_t b, int, uint32_t o) const {
+    o_start[o] = bstart[b];
+    o_size[o] = bstart[b + 1] - bstart[b];
+    o_depth[o] = 0;
+  }
+};
+
+// ---- assignment over the active positions -----------------------------------
+
+__global__ void act_flags_k(const uint32_t* __restrict__ apos, const uint8_t* __restrict__ flag, uint32_t m,
+                            uint32_t* __restrict__ fl) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < m) fl[j] = flag[apos[j]];
+}
+
+// cls = inclusive scan of fl: class c (0-based, in position order) of the
+// active positions starts at item first[c]. info[kInfoClasses] = classes.
+__global__ void class_first_k(const uint32_t* __restrict__ fl, const uint32_t* __restrict__ cls, uint32_t m,
+                              uint32_t* __restrict__ first, uint32_t* __restrict__ info) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  if (fl[j]) first[cls[j] - 1] = j;
+  if (j == m - 1) info[kInfoClasses] = cls[j];
+}
+
+// pid[u] = position of the first member of u's class, for every active u.
+__global__ void assign_pos_k(const uint32_t* __restrict__ apos, const uint32_t* __restrict__ cls,
+                             const uint32_t* __restrict__ first, const uint32_t* __restrict__ ord, uint32_t m,
+                             int32_t* __restrict__ pid) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  pid[ord[apos[j]]] = int32_t(apos[first[cls[j] - 1]]);
+}
+
+// Classes of the active positions with two or more members become the next
+// round's segments (class c spans items first[c] .. first[c+1]).
+struct NextSegOf {
+  const uint32_t* first;
+  const uint32_t* nclass;  // device count of classes
+  uint32_t m;
+  uint32_t medium_cap, big_cap;
+  __device__ __forceinline__ uint32_t size(uint32_t c) const {
+    const uint32_t C = *nclass;
+    return (c + 1 < C ? first[c + 1] : m) - first[c];
+  }
+  __device__ __forceinline__ int operator()(uint32_t c) const {
+    const uint32_t z = size(c);
+    return z >= 2 ? seg_class(z, medium_cap, big_cap) : -1;
+  }
+};
+struct NextSegWrite {
+  NextSegOf of;
+  const uint32_t* apos;
+  uint32_t *o_start, *o_size, *o_depth;
+  __device__ __forceinline__ void operator()(uint32_t c, int, uint32_t o) const {
+    o_start[o] = apos[of.first[c]];
+    o_size[o] = of.size(c);
+    o_depth[o] = 0;
+  }
+};
+
+// ---- ids ---------------------------------------------------------------------
+
+// cls = inclusive scan of flag over all positions: dense[ord[p]] = cls[p] - 1.
+__global__ void dense_ids_k(const uint32_t* __restrict__ ord, const uint32_t* __restrict__ cls, uint32_t n,
+                            int32_t* __restrict__ dense) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) dense[ord[p]] = int32_t(cls[p] - 1);
+}
+
+// Class-start position ids from dense block starts: pid[ord[p]] = bstart[cls[p] - 1].
+__global__ void pos_ids_k(const uint32_t* __restrict__ ord, const uint32_t* __restrict__ cls,
+                          const uint32_t* __restrict__ bstart, uint32_t n, int32_t* __restrict__ pid) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) pid[ord[p]] = int32_t(bstart[cls[p] - 1]);
+}
+
+}  // namespace kb

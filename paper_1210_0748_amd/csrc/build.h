@@ -74,39 +74,14 @@ __global__ void rank_scatter_k(const uint32_t* __restrict__ val, const uint32_t*
   if (p < n) rank[val[p]] = cls[p] - 1;
 }
 
-// Degree buckets: 0 thread (<=16), 1 wave (<=64), 2 block (<=4096), 3 hub.
-__global__ void bucket_flags_k(const uint32_t* __restrict__ rowptr, uint32_t n, uint32_t t_max,
-                               uint32_t w_max, uint32_t b_max, uint32_t* __restrict__ fw,
-                               uint32_t* __restrict__ fb, uint32_t* __restrict__ fh,
-                               uint32_t* __restrict__ hub_deg) {
+// hub_deg[v] = out-degree of v when above b_max (a hub), else 0; an
+// exclusive scan of it places every hub's radix-sort space.
+__global__ void hub_degree_k(const uint32_t* __restrict__ rowptr, uint32_t n, uint32_t b_max,
+                             uint32_t* __restrict__ hub_deg) {
   const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= n) return;
   const uint32_t d = rowptr[v + 1] - rowptr[v];
-  fw[v] = d > t_max && d <= w_max;
-  fb[v] = d > w_max && d <= b_max;
-  fh[v] = d > b_max;
   hub_deg[v] = d > b_max ? d : 0u;
-}
-
-// *mx = max of v[0..n) by one block.
-__global__ __launch_bounds__(1024) void max_u32_k(const uint32_t* __restrict__ v, uint32_t n,
-                                                  uint32_t* __restrict__ mx) {
-  uint32_t m = 0;
-  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) m = v[i] > m ? v[i] : m;
-  m = wave_max(m);
-  if (__lane_id() == 0) atomicMax(mx, m);
-}
-
-__global__ void compact_index_k(const uint32_t* __restrict__ f, const uint32_t* __restrict__ off,
-                                uint32_t n, uint32_t* __restrict__ out) {
-  const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n && f[v]) out[off[v]] = v;
-}
-
-__global__ void gather_u32_k(const uint32_t* __restrict__ src, const uint32_t* __restrict__ idx,
-                             uint32_t n, uint32_t* __restrict__ out) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = src[idx[i]];
 }
 
 // Label values below this bound are ranked through a presence table; larger

@@ -67,7 +67,7 @@ struct Options {
   uint32_t medium_cap = kDefaultMediumCap;  // groups above this size use the global passes
 };
 
-constexpr int kProfClasses = 7;
+constexpr int kProfClasses = 4;  // signature launch, ordering, assignment, whole round
 
 // Work lists produced by classifying open segments by size: lane groups
 // (four widths), medium and big groups (one workgroup each) and large groups
@@ -78,7 +78,11 @@ struct SegLists {
   DevBuf start, size, depth;
   uint32_t cnt[kNumSegLists] = {};
   uint32_t off[kNumSegLists] = {};
-  uint32_t count(int c) const { return cnt[c]; }
+  uint32_t total() const {
+    uint32_t t = 0;
+    for (uint32_t c : cnt) t += c;
+    return t;
+  }
 };
 
 class Engine {
@@ -90,7 +94,8 @@ class Engine {
   void build(const int32_t* node_label, const int32_t* src, const int32_t* lab, const int32_t* dst);
   // Runs rounds until `k` rounds are done or the fixed point is hit.
   void refine(int32_t k);
-  void result(int32_t* pid_out, bool to_device) const;
+  // Dense ids of the current partition (pId of the last round done).
+  void result(int32_t* pid_out, bool to_device);
 
   // One refinement round regardless of the fixed point (callers that track
   // several graphs in one union decide when to stop).
@@ -98,7 +103,11 @@ class Engine {
     StreamScope scope(st_);
     run_round();
   }
-  const int32_t* pid_device() const { return pid_[cur_].as<int32_t>(); }
+  // Dense ids on the device (computed when the partition changed since the
+  // last call) and the cumulative class counts: cls[p] = number of classes
+  // starting at positions <= p of ord.
+  const int32_t* dense_pid();
+  const uint32_t* class_scan() { dense_pid(); return cls_.as<uint32_t>(); }
   const uint32_t* ord_device() const { return ord_.as<uint32_t>(); }
   hipStream_t stream() const { return st_; }
   int64_t num_edges() const { return m_; }
@@ -129,12 +138,15 @@ class Engine {
   void resolve_lists(SegLists& L, const void* kv);
   void make_lists(const uint32_t* seg_start, const uint32_t* seg_size, const uint32_t* seg_depth,
                   const uint8_t* seg_done, uint32_t nseg, SegLists& out, const uint32_t* nseg_dev = nullptr);
+  void assign_round();
+  void prepare_active(uint32_t seg_items, uint32_t m_cap, uint32_t tag);
   void run_round();
-  void assign_ids_into(int32_t* pid_out);
   uint64_t read_word(const void* dev, int bytes);
   template <typename Tin, typename Tout, bool kIncl>
   void scan_dev(const Tin* in, Tout* out, uint64_t n);
   uint32_t* radix_scratch(uint64_t n);
+  uint32_t* compact_scratch(uint64_t words);
+  uint32_t medium_cap() const;
 
   int ev_begin(int cls);  // returns a slot for ev_end, or -1 when not profiling
   void ev_end(int slot);
@@ -148,24 +160,34 @@ class Engine {
   bool adj64_ = false, key64_ = false;
   int dst_bits_ = 1, lab_bits_ = 0;
   uint32_t n_elab_ = 0;
+  uint32_t b0_ = 0;  // blocks of pId_0
 
   // graph
-  DevBuf rowptr_, adj_, wlist_, blist_, hlist_, hub_off_, hub_tmp_;
-  uint32_t nw_ = 0, nb_ = 0, nh_ = 0;
-  uint32_t maxdeg_ = 0;
-  // partition state
-  DevBuf pid_[2], ord_, flag_, bstart_;
-  int cur_ = 0;
+  DevBuf rowptr_, adj_, hub_toff_, hub_tmp_;
+  uint64_t hub_edges_ = 0;
+  // partition state: ord, class-start flags, class-start position ids, and
+  // the dense pId_0 used by the first round's keys
+  DevBuf pid_, pid0_, ord_, flag_;
   int64_t B_ = 0;
   int32_t rounds_ = 0;
   bool fixed_ = false;
   std::vector<int64_t> counts_;
+  // active set: segments (size classes), their positions and nodes, and the
+  // signature work lists (wave, block, hub)
+  SegLists act_;
+  uint32_t S_act_ = 0, M_act_ = 0;
+  DevBuf soff_, apos_, anode_, actr_, blists_, info_;
+  bool act_dense_ = false;  // work lists in node order (see prepare_active)
+  uint32_t bcnt_[3] = {}, boff_[3] = {};
+  // dense ids
+  DevBuf dense_;
+  int32_t dense_round_ = -1;
   // round scratch
-  DevBuf ukey_, ucnt_, head_, cls_, scanpart_, radix_, bm_, bmslot_;
-  DevBuf seg_start_, seg_size_, seg_depth_, seg_done_, cls_part_, cls_meta_;
-  SegLists lists_a_, lists_b_;
+  DevBuf ukey_, ucnt_, head_, cls_, fl_, first_, scanpart_, radix_, part_, bm_, bmslot_;
+  DevBuf seg_start_, seg_size_, seg_depth_, seg_done_, cls_meta_;
+  SegLists lists_b_;
   DevBuf l_ioff_, l_lcp_, l_long_, l_open_;
-  DevBuf k0_, k1_, k2_, k3_, k4_, v0_, v1_, v2_, v3_, v4_, sflag_, soff_, ipos_, sub_item_;
+  DevBuf k0_, k1_, k2_, k3_, k4_, v0_, v1_, v2_, v3_, v4_, sflag_, soff2_, ipos_, sub_item_;
   DevBuf next_l_start_[2], next_l_size_[2], next_l_depth_[2];
 
   // profiling

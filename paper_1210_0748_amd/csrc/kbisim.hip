@@ -13,6 +13,7 @@
 #include <new>
 #include <string>
 
+#include "active.h"
 #include "batch.h"
 #include "build.h"
 #include "common.h"
@@ -131,59 +132,16 @@ void Engine::build_adj(const int32_t* src, const int32_t* lab, const int32_t* ds
     adj_.ensure(sizeof(AdjT));
     KB_CHECK(hipMemsetAsync(rowptr_.p, 0, (N + 1) * 4, st_));
   }
-  // degree buckets
+  // hubs: radix-sort space for rounds whose keys are too wide for bitmaps
   if (N) {
-    DevBuf fw, fb, fh, hd, ow, ob, oh;
-    for (DevBuf* b : {&fw, &fb, &fh, &hd, &ow, &ob, &oh}) b->ensure((N + 1) * sizeof(uint32_t));
-    for (DevBuf* b : {&fw, &fb, &fh, &hd})
-      KB_CHECK(hipMemsetAsync(b->p, 0, (N + 1) * sizeof(uint32_t), st_));
-    bucket_flags_k<<<grid_for(N), kNT, 0, st_>>>(rowptr_.as<uint32_t>(), uint32_t(N), kThreadMaxDeg,
-                                                 kWaveMaxDeg, kBlockMaxDeg, fw.as<uint32_t>(),
-                                                 fb.as<uint32_t>(), fh.as<uint32_t>(), hd.as<uint32_t>());
+    DevBuf hd;
+    hd.ensure((N + 1) * sizeof(uint32_t));
+    hub_toff_.ensure((N + 1) * sizeof(uint32_t));
+    KB_CHECK(hipMemsetAsync(hd.as<uint32_t>() + N, 0, 4, st_));
+    hub_degree_k<<<grid_for(N), kNT, 0, st_>>>(rowptr_.as<uint32_t>(), uint32_t(N), kBlockMaxDeg, hd.as<uint32_t>());
     KB_LAUNCH_CHECK();
-
-    scan_dev<uint32_t, uint32_t, false>(fw.as<uint32_t>(), ow.as<uint32_t>(), N + 1);
-    scan_dev<uint32_t, uint32_t, false>(fb.as<uint32_t>(), ob.as<uint32_t>(), N + 1);
-    scan_dev<uint32_t, uint32_t, false>(fh.as<uint32_t>(), oh.as<uint32_t>(), N + 1);
-    hw_.p[1] = hw_.p[2] = hw_.p[3] = 0;  // before the copies are queued
-    KB_CHECK(hipMemcpyAsync(&hw_.p[1], ow.as<uint32_t>() + N, 4, hipMemcpyDeviceToHost, st_));
-    KB_CHECK(hipMemcpyAsync(&hw_.p[2], ob.as<uint32_t>() + N, 4, hipMemcpyDeviceToHost, st_));
-    KB_CHECK(hipMemcpyAsync(&hw_.p[3], oh.as<uint32_t>() + N, 4, hipMemcpyDeviceToHost, st_));
-    KB_CHECK(hipStreamSynchronize(st_));
-    nw_ = uint32_t(hw_.p[1]);
-    nb_ = uint32_t(hw_.p[2]);
-    nh_ = uint32_t(hw_.p[3]);
-    wlist_.ensure(std::max<uint32_t>(nw_, 1) * sizeof(uint32_t));
-    blist_.ensure(std::max<uint32_t>(nb_, 1) * sizeof(uint32_t));
-    hlist_.ensure(std::max<uint32_t>(nh_, 1) * sizeof(uint32_t));
-    compact_index_k<<<grid_for(N), kNT, 0, st_>>>(fw.as<uint32_t>(), ow.as<uint32_t>(), uint32_t(N),
-                                                  wlist_.as<uint32_t>());
-    compact_index_k<<<grid_for(N), kNT, 0, st_>>>(fb.as<uint32_t>(), ob.as<uint32_t>(), uint32_t(N),
-                                                  blist_.as<uint32_t>());
-    compact_index_k<<<grid_for(N), kNT, 0, st_>>>(fh.as<uint32_t>(), oh.as<uint32_t>(), uint32_t(N),
-                                                  hlist_.as<uint32_t>());
-    KB_LAUNCH_CHECK();
-    hub_off_.ensure((nh_ + 1) * sizeof(uint32_t));
-    if (nh_) {
-      DevBuf hdl;
-      hdl.ensure((nh_ + 1) * sizeof(uint32_t));
-      KB_CHECK(hipMemsetAsync(hdl.p, 0, (nh_ + 1) * sizeof(uint32_t), st_));
-      gather_u32_k<<<grid_for(nh_), kNT, 0, st_>>>(hd.as<uint32_t>(), hlist_.as<uint32_t>(), nh_,
-                                                   hdl.as<uint32_t>());
-      KB_LAUNCH_CHECK();
-      DevBuf mx;
-      mx.ensure(4);
-      KB_CHECK(hipMemsetAsync(mx.p, 0, 4, st_));
-      max_u32_k<<<1, 1024, 0, st_>>>(hdl.as<uint32_t>(), nh_, mx.as<uint32_t>());
-      KB_LAUNCH_CHECK();
-      scan_dev<uint32_t, uint32_t, false>(hdl.as<uint32_t>(), hub_off_.as<uint32_t>(), nh_ + 1);
-      const uint64_t tot = read_word(hub_off_.as<uint32_t>() + nh_, 4);
-      hub_tmp_.ensure(std::max<uint64_t>(tot, 1) * (key64_ ? 8 : 4));
-      maxdeg_ = uint32_t(read_word(mx.p, 4));
-    } else {
-      maxdeg_ = kBlockMaxDeg;  // bound: no node has more edges than a block-bucket node
-    }
-    KB_CHECK(hipStreamSynchronize(st_));  // temporaries are freed on return
+    scan_dev<uint32_t, uint32_t, false>(hd.as<uint32_t>(), hub_toff_.as<uint32_t>(), N + 1);
+    hub_edges_ = read_word(hub_toff_.as<uint32_t>() + N, 4);  // synchronises: `hd` may be freed
   }
 }
 
@@ -248,19 +206,25 @@ void Engine::build(const int32_t* node_label, const int32_t* src, const int32_t*
   if (words[0] & 4u) throw InvalidInput("negative node label");
   const uint32_t max_nlab = words[1], max_elab = words[2];
 
-  pid_[0].ensure(std::max<uint64_t>(N, 1) * 4);
-  pid_[1].ensure(std::max<uint64_t>(N, 1) * 4);
-  ord_.ensure(std::max<uint64_t>(N, 1) * 4);
-  flag_.ensure(std::max<uint64_t>(N, 1));
-  bstart_.ensure((N + 1) * 4);
-  cls_.ensure(std::max<uint64_t>(N, 1) * 4);
-  cur_ = 0;
+  const uint64_t N1 = std::max<uint64_t>(N, 1);
+  pid_.ensure(N1 * 4);
+  pid0_.ensure(N1 * 4);
+  ord_.ensure(N1 * 4);
+  flag_.ensure(N1);
+  cls_.ensure(N1 * 4);
+  info_.ensure(kInfoWords * 4);
+  for (DevBuf* b : {&act_.start, &act_.size, &act_.depth, &soff_}) b->ensure((N + 1) * 4);
+  for (DevBuf* b : {&apos_, &anode_, &blists_, &fl_, &first_, &actr_}) b->ensure(N1 * 4);
+  KB_CHECK(hipMemsetAsync(actr_.p, 0, N1 * 4, st_));
 
   // pId_0: the rank of the node label; nodes sorted by it give `ord` and the
   // blocks (Section 3.1, k = 0: sort by label, a new id per new label)
+  DevBuf bstart;
+  bstart.ensure((N + 1) * 4);
+  B_ = 0;
   if (N) {
     DevBuf table, rank, ka, kb2, va, vb;
-    const uint32_t b0 = label_ranks(node_label, N, max_nlab, table, rank);
+    const uint32_t nl = label_ranks(node_label, N, max_nlab, table, rank);
     for (DevBuf* b : {&ka, &kb2, &va, &vb}) b->ensure(N * 4);
     if (table.p) {
       lookup_rank_k<<<grid_for(N), kNT, 0, st_>>>(node_label, table.as<uint32_t>(), uint32_t(N),
@@ -271,20 +235,30 @@ void Engine::build(const int32_t* node_label, const int32_t* src, const int32_t*
     }
     KB_LAUNCH_CHECK();
     const bool f = radix_sort<uint32_t>(ka.as<uint32_t>(), va.as<uint32_t>(), kb2.as<uint32_t>(),
-                                        vb.as<uint32_t>(), N, 0, bits_for(b0 > 1 ? b0 - 1 : 1),
+                                        vb.as<uint32_t>(), N, 0, bits_for(nl > 1 ? nl - 1 : 1),
                                         radix_scratch(N), st_);
     const uint32_t* keys = f ? kb2.as<uint32_t>() : ka.as<uint32_t>();
     const uint32_t* vals = f ? vb.as<uint32_t>() : va.as<uint32_t>();
     KB_CHECK(hipMemcpyAsync(ord_.p, vals, N * 4, hipMemcpyDeviceToDevice, st_));
     run_start_flags_k<<<grid_for(N), kNT, 0, st_>>>(keys, uint32_t(N), flag_.as<uint8_t>(), nullptr);
     KB_LAUNCH_CHECK();
-    assign_ids_into(pid_[0].as<int32_t>());  // synchronises before the temporaries go
-  } else {
-    assign_ids_into(pid_[0].as<int32_t>());
+    // dense pId_0, block starts, and class-start position ids
+    scan_dev<uint8_t, uint32_t, true>(flag_.as<uint8_t>(), cls_.as<uint32_t>(), N);
+    assign_k<<<grid_for(N), kNT, 0, st_>>>(ord_.as<uint32_t>(), flag_.as<uint8_t>(), cls_.as<uint32_t>(),
+                                           uint32_t(N), pid0_.as<int32_t>(), bstart.as<uint32_t>());
+    KB_LAUNCH_CHECK();
+    B_ = int64_t(read_word(cls_.as<uint32_t>() + (N - 1), 4));
+    set_u32_k<<<1, 1, 0, st_>>>(bstart.as<uint32_t>() + B_, uint32_t(N));
+    KB_LAUNCH_CHECK();
+    pos_ids_k<<<grid_for(N), kNT, 0, st_>>>(ord_.as<uint32_t>(), cls_.as<uint32_t>(), bstart.as<uint32_t>(),
+                                            uint32_t(N), pid_.as<int32_t>());
+    KB_LAUNCH_CHECK();
   }
+  b0_ = uint32_t(B_);
   counts_.assign(1, B_);
   rounds_ = 0;
   fixed_ = false;
+  dense_round_ = -1;
 
   // edge labels: dense ascending ranks
   DevBuf etable, erank;
@@ -302,27 +276,98 @@ void Engine::build(const int32_t* node_label, const int32_t* src, const int32_t*
 
   // per-round buffers
   ukey_.ensure(std::max<uint64_t>(E, 1) * (key64_ ? 8 : 4));
-  ucnt_.ensure(std::max<uint64_t>(N, 1) * 4);
+  ucnt_.ensure(N1 * 4);
+  head_.ensure(N1 * 8);
+
+  // the first round's segments: the blocks of pId_0 with two or more members
+  if (N) {
+    const uint32_t med = std::min(medium_cap(), kMediumCapSmall), big = medium_cap();
+    KB_CHECK(hipMemsetAsync(act_.size.p, 0, (uint64_t(B_) + 1) * 4, st_));
+    compact<kSegClasses>(BlockSegOf{bstart.as<uint32_t>(), med, big},
+                         BlockSegWrite{bstart.as<uint32_t>(), act_.start.as<uint32_t>(), act_.size.as<uint32_t>(),
+                                       act_.depth.as<uint32_t>()},
+                         uint32_t(B_), nullptr, compact_scratch(compact_part_words<kSegClasses>(B_)),
+                         info_.as<uint32_t>() + kInfoSeg, st_);
+    prepare_active(uint32_t(B_), uint32_t(N), 1u);
+  }
   KB_CHECK(hipStreamSynchronize(st_));
 }
 
-// cls = inclusive scan of flag; pid[ord[p]] = cls[p]-1; bstart at class starts.
-void Engine::assign_ids_into(int32_t* pid_out) {
-  const uint64_t N = uint64_t(n_);
-  if (N == 0) {
-    set_u32_k<<<1, 1, 0, st_>>>(bstart_.as<uint32_t>(), 0u);
-    KB_LAUNCH_CHECK();
-    B_ = 0;
-    return;
+uint32_t Engine::medium_cap() const { return opt_.medium_cap; }
+
+uint32_t* Engine::compact_scratch(uint64_t words) {
+  part_.ensure(std::max<uint64_t>(words, 1) * 4);
+  return part_.as<uint32_t>();
+}
+
+// After the segment lists of the coming round are in act_ (their summary in
+// info_): item offsets of the segments, the active positions and nodes, the
+// signature work lists, and one read-back of the summary. seg_items bounds the
+// number of segments (act_.size must be zero from the last segment up to
+// seg_items), m_cap the number of active positions, tag the number of the
+// round being prepared (1 for the first), which marks its nodes in actr_.
+void Engine::prepare_active(uint32_t seg_items, uint32_t m_cap, uint32_t tag) {
+  uint32_t* info = info_.as<uint32_t>();
+  scan_dev<uint32_t, uint32_t, false>(act_.size.as<uint32_t>(), soff_.as<uint32_t>(), uint64_t(seg_items) + 1);
+  expand_k<<<grid_for(m_cap), kNT, 0, st_>>>(act_.start.as<uint32_t>(), soff_.as<uint32_t>(),
+                                             info + kInfoSeg + 2 * kSegClasses, m_cap, ord_.as<uint32_t>(),
+                                             apos_.as<uint32_t>(), anode_.as<uint32_t>(), actr_.as<uint32_t>(),
+                                             tag, info);
+  KB_LAUNCH_CHECK();
+  // when many nodes may be active, the work lists and the thread part go
+  // over node ids in order (neighbouring rows), else over the active list
+  act_dense_ = uint64_t(m_cap) * 8 >= uint64_t(n_);
+  if (act_dense_) {
+    compact<kNumBuckets>(NodeBucketDenseOf{actr_.as<uint32_t>(), tag, rowptr_.as<uint32_t>(), kThreadMaxDeg,
+                                           kWaveMaxDeg, kBlockMaxDeg},
+                         NodeWriteDense{blists_.as<uint32_t>()}, uint32_t(n_), nullptr,
+                         compact_scratch(compact_part_words<kNumBuckets>(uint64_t(n_))), info + kInfoBucket, st_);
+  } else {
+    compact<kNumBuckets>(NodeBucketOf{anode_.as<uint32_t>(), rowptr_.as<uint32_t>(), kThreadMaxDeg, kWaveMaxDeg,
+                                      kBlockMaxDeg},
+                         NodeWrite{anode_.as<uint32_t>(), blists_.as<uint32_t>()}, m_cap, info + kInfoItems,
+                         compact_scratch(compact_part_words<kNumBuckets>(m_cap)), info + kInfoBucket, st_);
   }
-  scan_dev<uint8_t, uint32_t, true>(flag_.as<uint8_t>(), cls_.as<uint32_t>(), N);
-  assign_k<<<grid_for(N), kNT, 0, st_>>>(ord_.as<uint32_t>(), flag_.as<uint8_t>(), cls_.as<uint32_t>(),
-                                         uint32_t(N), pid_out, bstart_.as<uint32_t>());
+  uint32_t* h = reinterpret_cast<uint32_t*>(hw_.p);
+  static_assert(kInfoWords <= 2 * PinnedSlots::kSlotWords, "read-back slot too small");
+  for (int i = 0; i < kInfoWords; ++i) h[i] = 0;  // before the copy is queued
+  KB_CHECK(hipMemcpyAsync(h, info, kInfoWords * 4, hipMemcpyDeviceToHost, st_));
+  KB_CHECK(hipStreamSynchronize(st_));
+  for (int c = 0; c < kSegClasses; ++c) {
+    act_.cnt[c] = h[kInfoSeg + c];
+    act_.off[c] = h[kInfoSeg + kSegClasses + c];
+  }
+  S_act_ = h[kInfoSeg + 2 * kSegClasses];
+  M_act_ = h[kInfoItems];
+  for (int c = 0; c < kNumBuckets; ++c) {
+    bcnt_[c] = h[kInfoBucket + c];
+    boff_[c] = h[kInfoBucket + kNumBuckets + c];
+  }
+}
+
+// Ids for the active positions after ordering: every class of the round gets
+// the position of its first member as id; classes with two or more members
+// become the next round's segments. Returns with the next active set ready.
+void Engine::assign_round() {
+  const uint32_t M = M_act_;
+  uint32_t* info = info_.as<uint32_t>();
+  act_flags_k<<<grid_for(M), kNT, 0, st_>>>(apos_.as<uint32_t>(), flag_.as<uint8_t>(), M, fl_.as<uint32_t>());
   KB_LAUNCH_CHECK();
-  const uint64_t b = read_word(cls_.as<uint32_t>() + (N - 1), 4);
-  set_u32_k<<<1, 1, 0, st_>>>(bstart_.as<uint32_t>() + b, uint32_t(N));
+  scan_dev<uint32_t, uint32_t, true>(fl_.as<uint32_t>(), cls_.as<uint32_t>(), M);
+  class_first_k<<<grid_for(M), kNT, 0, st_>>>(fl_.as<uint32_t>(), cls_.as<uint32_t>(), M, first_.as<uint32_t>(),
+                                              info);
   KB_LAUNCH_CHECK();
-  B_ = int64_t(b);
+  assign_pos_k<<<grid_for(M), kNT, 0, st_>>>(apos_.as<uint32_t>(), cls_.as<uint32_t>(), first_.as<uint32_t>(),
+                                             ord_.as<uint32_t>(), M, pid_.as<int32_t>());
+  KB_LAUNCH_CHECK();
+  const uint32_t med = std::min(medium_cap(), kMediumCapSmall), big = medium_cap();
+  KB_CHECK(hipMemsetAsync(act_.size.p, 0, (uint64_t(M) + 1) * 4, st_));
+  NextSegOf of{first_.as<uint32_t>(), info + kInfoClasses, M, med, big};
+  compact<kSegClasses>(of, NextSegWrite{of, apos_.as<uint32_t>(), act_.start.as<uint32_t>(),
+                                        act_.size.as<uint32_t>(), act_.depth.as<uint32_t>()},
+                       M, info + kInfoClasses, compact_scratch(compact_part_words<kSegClasses>(M)),
+                       info + kInfoSeg, st_);
+  prepare_active(M, M, uint32_t(rounds_) + 2);  // runs inside round rounds_ + 1
 }
 
 // ---------------------------------------------------------------------------
@@ -333,22 +378,14 @@ void Engine::make_lists(const uint32_t* seg_start, const uint32_t* seg_size, con
   static_assert(kNumSegLists == kSegClasses, "list count");
   for (int c = 0; c < kNumSegLists; ++c) out.cnt[c] = out.off[c] = 0;
   if (nseg == 0) return;
-  const uint32_t ntiles = ceil_div(nseg, kClassTile);
-  const uint32_t big_cap = opt_.medium_cap;
-  const uint32_t med_cap = std::min(opt_.medium_cap, kMediumCapSmall);
-  cls_part_.ensure(uint64_t(ntiles) * kSegClasses * 4);
-  cls_meta_.ensure(2 * kSegClasses * 4);
+  const uint32_t med = std::min(medium_cap(), kMediumCapSmall), big = medium_cap();
+  cls_meta_.ensure((2 * kSegClasses + 1) * 4);
   for (DevBuf* b : {&out.start, &out.size, &out.depth}) b->ensure(uint64_t(nseg) * 4);
-  class_count_k<<<ntiles, 256, 0, st_>>>(seg_size, seg_done, nseg, nseg_dev, med_cap, big_cap,
-                                         cls_part_.as<uint32_t>());
-  KB_LAUNCH_CHECK();
-  class_offsets_k<<<1, 1024, 0, st_>>>(cls_part_.as<uint32_t>(), ntiles, cls_meta_.as<uint32_t>());
-  KB_LAUNCH_CHECK();
-  class_scatter_k<<<ntiles, 256, 0, st_>>>(seg_start, seg_size, seg_depth, seg_done, nseg, nseg_dev, med_cap,
-                                           big_cap, cls_part_.as<uint32_t>(), cls_meta_.as<uint32_t>(),
-                                           out.start.as<uint32_t>(), out.size.as<uint32_t>(),
-                                           out.depth.as<uint32_t>());
-  KB_LAUNCH_CHECK();
+  compact<kSegClasses>(SegClassOf{seg_size, seg_done, med, big},
+                       SegCopy{seg_start, seg_size, seg_depth, out.start.as<uint32_t>(), out.size.as<uint32_t>(),
+                               out.depth.as<uint32_t>()},
+                       nseg, nseg_dev, compact_scratch(compact_part_words<kSegClasses>(nseg)),
+                       cls_meta_.as<uint32_t>(), st_);
   uint32_t* hw32 = reinterpret_cast<uint32_t*>(hw_.p);
   for (int c = 0; c < 2 * kSegClasses; ++c) hw32[c] = 0;  // before the copy is queued
   KB_CHECK(hipMemcpyAsync(hw32, cls_meta_.p, 2 * kSegClasses * 4, hipMemcpyDeviceToHost, st_));
@@ -398,22 +435,16 @@ void Engine::resolve_lists(SegLists& L, const void* kvp) {
 
 template <typename KeyT>
 void Engine::order_groups(int key_bits, const void* kvp) {
-  const KeyView<KeyT>& kv = *static_cast<const KeyView<KeyT>*>(kvp);
-  const uint32_t B = uint32_t(B_);
-  seg_start_.ensure(uint64_t(B) * 4 + 4);
-  seg_size_.ensure(uint64_t(B) * 4 + 4);
-  blocks_as_segments_k<<<grid_for(B), kNT, 0, st_>>>(bstart_.as<uint32_t>(), B, seg_start_.as<uint32_t>(),
-                                                     seg_size_.as<uint32_t>());
-  KB_LAUNCH_CHECK();
-  make_lists(seg_start_.as<uint32_t>(), seg_size_.as<uint32_t>(), nullptr, nullptr, B, lists_a_);
-  resolve_lists<KeyT>(lists_a_, kvp);
+  // the round's segments are already classified by size (act_)
+  resolve_lists<KeyT>(act_, kvp);
 
   // Large groups: global passes, each sorting every group by the digits
   // after its common prefix.
-  uint32_t nl = lists_a_.cnt[kLargeClass];
-  const uint32_t* Ls = lists_a_.start.as<uint32_t>() + lists_a_.off[kLargeClass];
-  const uint32_t* Lz = lists_a_.size.as<uint32_t>() + lists_a_.off[kLargeClass];
-  const uint32_t* Ld = lists_a_.depth.as<uint32_t>() + lists_a_.off[kLargeClass];
+  const KeyView<KeyT>& kv = *static_cast<const KeyView<KeyT>*>(kvp);
+  uint32_t nl = act_.cnt[kLargeClass];
+  const uint32_t* Ls = act_.start.as<uint32_t>() + act_.off[kLargeClass];
+  const uint32_t* Lz = act_.size.as<uint32_t>() + act_.off[kLargeClass];
+  const uint32_t* Ld = act_.depth.as<uint32_t>() + act_.off[kLargeClass];
   int nx = 0;
   bool first_pass = true;
   const int dbits = key_bits + 1;
@@ -464,7 +495,7 @@ void Engine::order_groups(int key_bits, const void* kvp) {
     lk.dig_bits = int(lk.width) * dbits;
     for (DevBuf* b : {&k0_, &k1_}) b->ensure(uint64_t(M) * 8);
     for (DevBuf* b : {&v0_, &v1_, &ipos_, &sub_item_}) b->ensure(uint64_t(M) * 4);
-    for (DevBuf* b : {&sflag_, &soff_}) b->ensure((uint64_t(M) + 1) * 4);
+    for (DevBuf* b : {&sflag_, &soff2_}) b->ensure((uint64_t(M) + 1) * 4);
     const uint64_t* KA;
     const uint64_t* KB = nullptr;
     const uint32_t* V;
@@ -509,13 +540,13 @@ void Engine::order_groups(int key_bits, const void* kvp) {
                                                 sflag_.as<uint32_t>(), ipos_.as<uint32_t>());
     KB_LAUNCH_CHECK();
     KB_CHECK(hipMemsetAsync(sflag_.as<uint32_t>() + M, 0, 4, st_));
-    scan_dev<uint32_t, uint32_t, false>(sflag_.as<uint32_t>(), soff_.as<uint32_t>(), uint64_t(M) + 1);
-    const uint32_t* ns_dev = soff_.as<uint32_t>() + M;  // number of subgroups, kept on the device
+    scan_dev<uint32_t, uint32_t, false>(sflag_.as<uint32_t>(), soff2_.as<uint32_t>(), uint64_t(M) + 1);
+    const uint32_t* ns_dev = soff2_.as<uint32_t>() + M;  // number of subgroups, kept on the device
     seg_start_.ensure(uint64_t(M) * 4 + 4);
     seg_size_.ensure(uint64_t(M) * 4 + 4);
     seg_depth_.ensure(uint64_t(M) * 4 + 4);
     seg_done_.ensure(uint64_t(M) + 1);
-    large_subgroups_k<<<grid_for(M), kNT, 0, st_>>>(sflag_.as<uint32_t>(), soff_.as<uint32_t>(), M,
+    large_subgroups_k<<<grid_for(M), kNT, 0, st_>>>(sflag_.as<uint32_t>(), soff2_.as<uint32_t>(), M,
                                                     ipos_.as<uint32_t>(), KA, KB, lk, last_mask,
                                                     l_lcp_.as<uint32_t>(), sub_item_.as<uint32_t>(),
                                                     seg_start_.as<uint32_t>(), seg_depth_.as<uint32_t>(),
@@ -550,98 +581,95 @@ void Engine::order_groups(int key_bits, const void* kvp) {
 template <typename AdjT, typename KeyT>
 void Engine::round_impl() {
   const uint32_t N = uint32_t(n_);
-  const int pid_bits = bits_for(B_ > 1 ? uint64_t(B_ - 1) : 1);
+  // round 1 keys use the dense pId_0 (narrow when there are few labels);
+  // later rounds use class-start positions
+  const bool first = rounds_ == 0;
+  const uint64_t id_max = first ? (b0_ > 1 ? b0_ - 1 : 1) : (N > 1 ? N - 1 : 1);
+  const int pid_bits = bits_for(id_max);
   const int key_bits = lab_bits_ + pid_bits;
   SigArgs<AdjT, KeyT> a;
   a.rowptr = rowptr_.as<uint32_t>();
   a.adj = adj_.as<AdjT>();
-  a.pid = pid_[cur_].as<int32_t>();
-  a.bstart = bstart_.as<uint32_t>();
+  a.pid = first ? pid0_.as<int32_t>() : pid_.as<int32_t>();
   a.ukey = ukey_.as<KeyT>();
   a.ucnt = ucnt_.as<uint32_t>();
+  a.head = head_.as<uint64_t>();
   a.dst_bits = dst_bits_;
   a.pid_bits = pid_bits;
   a.hdbits = key_bits + 1;
   a.hw = a.hdbits >= 64 ? 1u : uint32_t(64 / a.hdbits);
-  head_.ensure(std::max<uint64_t>(N, 1) * 8);
-  a.head = head_.as<uint64_t>();
+
+  SigWork w{};
+  const uint32_t* lists = blists_.as<uint32_t>();
+  w.anode = anode_.as<uint32_t>();
+  w.nact = M_act_;
+  w.actr = actr_.as<uint32_t>();
+  w.tag = uint32_t(rounds_) + 1;
+  w.n_nodes = N;
+  w.dense = act_dense_;
+  w.wl = lists + boff_[0];
+  w.nw = bcnt_[0];
+  w.bl = lists + boff_[1];
+  w.nb = bcnt_[1];
+  w.hl = lists + boff_[2];
+  w.nh = bcnt_[2];
+  w.key_bits = key_bits;
+  // small key universe: workgroup nodes de-duplicate through bitmaps, which
+  // the ordering then uses for first-difference searches
+  const bool use_bm = key_bits <= kBmKeyBits && (w.nb + w.nh) > 0;
+  if (use_bm) {
+    w.words = std::max<uint32_t>((1u << key_bits) / 32u, 4u);
+    bm_.ensure(uint64_t(w.nb + w.nh) * w.words * 4);
+    bmslot_.ensure(std::max<uint64_t>(N, 1) * 4);
+    w.bm = bm_.as<uint32_t>();
+    w.bmslot = bmslot_.as<uint32_t>();
+  } else if (w.nh) {
+    hub_tmp_.ensure(std::max<uint64_t>(hub_edges_, 1) * sizeof(KeyT));
+    w.hub_tmp = hub_tmp_.p;
+    w.hub_toff = hub_toff_.as<uint32_t>();
+  }
   if (opt_.profile) {
     if (!work_.p) {
       work_.ensure(8 * sizeof(unsigned long long));
       KB_CHECK(hipMemsetAsync(work_.p, 0, 8 * sizeof(unsigned long long), st_));
     }
-    work_count_k<<<grid_for(N), kNT, 0, st_>>>(a.rowptr, a.pid, a.bstart, N, work_.as<unsigned long long>());
+    work_count_k<<<grid_for(M_act_), kNT, 0, st_>>>(w.anode, a.rowptr, M_act_, work_.as<unsigned long long>());
     KB_LAUNCH_CHECK();
   }
-
-  int ev = ev_begin(0);
-  sig_thread_k<AdjT, KeyT><<<grid_for(N), kNT, 0, st_>>>(a, N);
+  const int ev = ev_begin(0);
+  signature_k<AdjT, KeyT><<<w.grid(), kSigNT, 0, st_>>>(a, w);
   KB_LAUNCH_CHECK();
   ev_end(ev);
-  if (nw_) {
-    ev = ev_begin(1);
-    sig_wave_k<AdjT, KeyT><<<grid_for(uint64_t(nw_) * kWave), kNT, 0, st_>>>(a, wlist_.as<uint32_t>(), nw_);
-    KB_LAUNCH_CHECK();
-    ev_end(ev);
-  }
-  // small key universe: block and hub nodes de-duplicate through bitmaps,
-  // which the ordering then uses for first-difference searches
-  const bool use_bm = key_bits <= kBmKeyBits && (nb_ + nh_) > 0;
-  uint32_t bm_words = 0;
-  if (use_bm) {
-    bm_words = std::max<uint32_t>((1u << key_bits) / 32u, 4u);
-    bm_.ensure(uint64_t(nb_ + nh_) * bm_words * 4);
-    bmslot_.ensure(std::max<uint64_t>(N, 1) * 4);
-  }
-  if (nb_) {
-    ev = ev_begin(2);
-    if (use_bm)
-      sig_bitmap_k<AdjT, KeyT, kSigBlockNT><<<nb_, kSigBlockNT, 0, st_>>>(
-          a, blist_.as<uint32_t>(), BmOut{bm_.as<uint32_t>(), bmslot_.as<uint32_t>(), bm_words, 0u});
-    else
-      sig_block_k<AdjT, KeyT><<<nb_, kSigBlockNT, 0, st_>>>(a, blist_.as<uint32_t>(), nb_);
-    KB_LAUNCH_CHECK();
-    ev_end(ev);
-  }
-  if (nh_) {
-    ev = ev_begin(3);
-    if (use_bm)
-      sig_bitmap_k<AdjT, KeyT, 1024><<<nh_, 1024, 0, st_>>>(
-          a, hlist_.as<uint32_t>(), BmOut{bm_.as<uint32_t>(), bmslot_.as<uint32_t>(), bm_words, nb_});
-    else
-      sig_hub_k<AdjT, KeyT><<<nh_, kHubNT, 0, st_>>>(a, hlist_.as<uint32_t>(), hub_off_.as<uint32_t>(),
-                                                     hub_tmp_.as<KeyT>(), key_bits);
-    KB_LAUNCH_CHECK();
-    ev_end(ev);
-  }
 
   KeyView<KeyT> kv{rowptr_.as<uint32_t>(), ukey_.as<KeyT>(), ucnt_.as<uint32_t>(), key_bits + 1};
   if (use_bm) {
     kv.bm = bm_.as<uint64_t>();
     kv.bmslot = bmslot_.as<uint32_t>();
-    kv.bm_words64 = bm_words / 2;
+    kv.bm_words64 = w.words / 2;
     kv.bm_min_deg = kWaveMaxDeg;
   }
-  const int evo = ev_begin(4);
+  const int evo = ev_begin(1);
   order_groups<KeyT>(key_bits, &kv);
   ev_end(evo);
 }
 
 void Engine::run_round() {
   const int64_t B_old = B_;
-  const int evr = ev_begin(6);
-  if (n_ > 0) {
+  const int evr = ev_begin(3);
+  if (M_act_ > 0) {
     if (adj64_) {
       if (key64_) round_impl<uint64_t, uint64_t>(); else round_impl<uint64_t, uint32_t>();
     } else {
       if (key64_) round_impl<uint32_t, uint64_t>(); else round_impl<uint32_t, uint32_t>();
     }
+    const uint32_t S_old = S_act_;
+    const int eva = ev_begin(2);
+    assign_round();  // reads back the classes of this round and the next active set
+    ev_end(eva);
+    const uint32_t C = reinterpret_cast<const uint32_t*>(hw_.p)[kInfoClasses];
+    B_ = B_old + int64_t(C) - int64_t(S_old);
   }
-  const int eva = ev_begin(5);
-  assign_ids_into(pid_[cur_ ^ 1].as<int32_t>());
-  ev_end(eva);
   ev_end(evr);
-  cur_ ^= 1;
   ++rounds_;
   counts_.push_back(B_);
   fixed_ = (B_ == B_old);
@@ -669,10 +697,25 @@ void Engine::refine(int32_t k) {
   KB_CHECK(hipStreamSynchronize(st_));
 }
 
-void Engine::result(int32_t* pid_out, bool to_device) const {
+const int32_t* Engine::dense_pid() {
+  StreamScope scope(st_);
+  const uint64_t N = uint64_t(n_);
+  dense_.ensure(std::max<uint64_t>(N, 1) * 4);
+  if (N && dense_round_ != rounds_) {
+    scan_dev<uint8_t, uint32_t, true>(flag_.as<uint8_t>(), cls_.as<uint32_t>(), N);
+    dense_ids_k<<<grid_for(N), kNT, 0, st_>>>(ord_.as<uint32_t>(), cls_.as<uint32_t>(), uint32_t(N),
+                                              dense_.as<int32_t>());
+    KB_LAUNCH_CHECK();
+    dense_round_ = rounds_;
+  }
+  return dense_.as<int32_t>();
+}
+
+void Engine::result(int32_t* pid_out, bool to_device) {
   if (n_ == 0) return;
-  KB_CHECK(hipMemcpyAsync(pid_out, pid_[cur_].p, uint64_t(n_) * 4,
-                          to_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st_));
+  const int32_t* d = dense_pid();
+  KB_CHECK(hipMemcpyAsync(pid_out, d, uint64_t(n_) * 4, to_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                          st_));
   KB_CHECK(hipStreamSynchronize(st_));
 }
 
@@ -778,7 +821,7 @@ Batch::~Batch() { delete eng_; }
 
 void Batch::read_counts(std::vector<int32_t>& cnt) {
   cnt.assign(G_, 0);
-  graph_id_range_k<<<ceil_div(uint64_t(G_), 256), 256, 0, st_>>>(eng_->pid_device(), eng_->ord_device(),
+  graph_id_range_k<<<ceil_div(uint64_t(G_), 256), 256, 0, st_>>>(eng_->dense_pid(), eng_->ord_device(),
                                                                  d_node_off_.as<int64_t>(), uint32_t(G_),
                                                                  base_.as<int32_t>(), cnt_.as<int32_t>());
   KB_LAUNCH_CHECK();
@@ -790,7 +833,7 @@ void Batch::take_snapshot(const std::vector<uint8_t>& take) {
   if (ntot_ == 0) return;
   KB_CHECK(hipMemcpyAsync(take_.p, take.data(), uint64_t(G_), hipMemcpyHostToDevice, st_));
   const uint32_t gs = std::max<uint32_t>(1, std::min<uint32_t>(ceil_div(uint64_t(ntot_), 256), 8192));
-  snapshot_k<<<gs, 256, 0, st_>>>(eng_->pid_device(), uint64_t(ntot_), d_node_off_.as<int64_t>(), uint32_t(G_),
+  snapshot_k<<<gs, 256, 0, st_>>>(eng_->dense_pid(), uint64_t(ntot_), d_node_off_.as<int64_t>(), uint32_t(G_),
                                    base_.as<int32_t>(), take_.as<uint8_t>(), out_.as<int32_t>());
   KB_LAUNCH_CHECK();
   KB_CHECK(hipStreamSynchronize(st_));  // `take` is a host vector the caller may change

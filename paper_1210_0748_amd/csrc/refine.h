@@ -33,6 +33,7 @@
 #pragma once
 
 #include "common.h"
+#include "compact.h"
 #include "scan_radix.h"
 
 namespace kb {
@@ -512,16 +513,6 @@ __global__ __launch_bounds__(256) void resolve_lanes_k(const uint32_t* __restric
 // the rest (global passes). The lists share one set of arrays: list c
 // occupies [off[c], off[c] + cnt[c]). Every group is ordered on its own.
 
-// Segment j of the previous partition: block j with start bstart[j], depth 0.
-__global__ void blocks_as_segments_k(const uint32_t* __restrict__ bstart, uint32_t nblocks,
-                                     uint32_t* __restrict__ seg_start, uint32_t* __restrict__ seg_size) {
-  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= nblocks) return;
-  const uint32_t a = bstart[j], b = bstart[j + 1];
-  seg_start[j] = a;
-  seg_size[j] = b - a;
-}
-
 constexpr int kLaneClasses = 4;
 constexpr int kMediumClass = kLaneClasses;
 constexpr int kBigClass = kLaneClasses + 1;
@@ -534,114 +525,31 @@ __device__ __forceinline__ int seg_class(uint32_t z, uint32_t medium_cap, uint32
          : z <= big_cap ? kBigClass : kLargeClass;
 }
 
-// Classification is a three-kernel scan over tiles of kClassTile segments:
-// per-tile counts of every class, an exclusive scan of those counts per class
-// (one workgroup), and a scatter that ranks every open segment inside its
-// tile. Segment j is open when it has two or more members and is not done;
-// nseg is an upper bound and, when nseg_dev is given, only j < *nseg_dev exist.
-constexpr int kClassIPT = 8;
-constexpr int kClassTile = 256 * kClassIPT;
-
-__device__ __forceinline__ int open_class(const uint32_t* seg_size, const uint8_t* seg_done, uint32_t n,
-                                          uint32_t j, uint32_t medium_cap, uint32_t big_cap) {
-  if (j >= n) return -1;
-  const uint32_t z = seg_size[j];
-  if (z <= 1 || (seg_done && seg_done[j])) return -1;
-  return seg_class(z, medium_cap, big_cap);
-}
-
-// Per-thread class counts packed 16 bits per class (a tile has at most
-// 2048 segments): classes 0-3 in lo, 4.. in hi.
-__device__ __forceinline__ void add_class(int c, uint64_t& lo, uint64_t& hi) {
-  if (c < 0) return;
-  if (c < 4)
-    lo += 1ull << (16 * c);
-  else
-    hi += 1ull << (16 * (c - 4));
-}
-__device__ __forceinline__ uint32_t class_field(int c, uint64_t lo, uint64_t hi) {
-  return uint32_t(((c < 4 ? lo : hi) >> (16 * (c & 3))) & 0xffffu);
-}
-
-// part[c * ntiles + tile] = number of open segments of class c in the tile.
-__global__ __launch_bounds__(256) void class_count_k(const uint32_t* __restrict__ seg_size,
-                                                     const uint8_t* __restrict__ seg_done, uint32_t nseg,
-                                                     const uint32_t* __restrict__ nseg_dev, uint32_t medium_cap,
-                                                     uint32_t big_cap, uint32_t* __restrict__ part) {
-  __shared__ uint64_t sh[256 / kWave];
-  const uint32_t n = nseg_dev ? min(nseg, *nseg_dev) : nseg;
-  const uint32_t base = blockIdx.x * uint32_t(kClassTile);
-  uint64_t lo = 0, hi = 0;
-#pragma unroll
-  for (int q = 0; q < kClassIPT; ++q)
-    add_class(open_class(seg_size, seg_done, n, base + q * 256u + threadIdx.x, medium_cap, big_cap), lo, hi);
-  uint64_t tl, th;
-  block_exclusive_scan<256>(lo, sh, &tl);
-  block_exclusive_scan<256>(hi, sh, &th);
-  if (threadIdx.x < kSegClasses) part[threadIdx.x * gridDim.x + blockIdx.x] = class_field(threadIdx.x, tl, th);
-}
-
-// In place: part[c * ntiles + t] = exclusive prefix over tiles; meta[c] =
-// count of class c, meta[kSegClasses + c] = offset of list c.
-__global__ __launch_bounds__(1024) void class_offsets_k(uint32_t* __restrict__ part, uint32_t ntiles,
-                                                        uint32_t* __restrict__ meta) {
-  __shared__ uint32_t sh[1024 / kWave];
-  __shared__ uint32_t tot_c[kSegClasses];
-  for (int c = 0; c < kSegClasses; ++c) {
-    uint32_t* p = part + size_t(c) * ntiles;
-    uint32_t carry = 0;
-    for (uint32_t b = 0; b < ntiles; b += 1024) {
-      const uint32_t i = b + threadIdx.x;
-      const uint32_t v = i < ntiles ? p[i] : 0u;
-      uint32_t tot;
-      const uint32_t ex = block_exclusive_scan<1024>(v, sh, &tot);
-      if (i < ntiles) p[i] = carry + ex;
-      carry += tot;
-    }
-    if (threadIdx.x == 0) tot_c[c] = carry;
+// Open segment j (two or more members, not done) -> its size class, for the
+// tile compaction (compact.h) that builds the work lists.
+struct SegClassOf {
+  const uint32_t* size;
+  const uint8_t* done;  // optional
+  uint32_t medium_cap, big_cap;
+  __device__ __forceinline__ int operator()(uint32_t j) const {
+    const uint32_t z = size[j];
+    if (z <= 1 || (done && done[j])) return -1;
+    return seg_class(z, medium_cap, big_cap);
   }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t off = 0;
-    for (int c = 0; c < kSegClasses; ++c) {
-      meta[c] = tot_c[c];
-      meta[kSegClasses + c] = off;
-      off += tot_c[c];
-    }
+};
+struct SegCopy {
+  const uint32_t* start;
+  const uint32_t* size;
+  const uint32_t* depth;  // optional: depth 0
+  uint32_t* o_start;
+  uint32_t* o_size;
+  uint32_t* o_depth;
+  __device__ __forceinline__ void operator()(uint32_t j, int, uint32_t o) const {
+    o_start[o] = start[j];
+    o_size[o] = size[j];
+    o_depth[o] = depth ? depth[j] : 0u;
   }
-}
-
-__global__ __launch_bounds__(256) void class_scatter_k(
-    const uint32_t* __restrict__ seg_start, const uint32_t* __restrict__ seg_size,
-    const uint32_t* __restrict__ seg_depth, const uint8_t* __restrict__ seg_done, uint32_t nseg,
-    const uint32_t* __restrict__ nseg_dev, uint32_t medium_cap, uint32_t big_cap,
-    const uint32_t* __restrict__ part, const uint32_t* __restrict__ meta, uint32_t* __restrict__ out_start,
-    uint32_t* __restrict__ out_size, uint32_t* __restrict__ out_depth) {
-  __shared__ uint64_t sh[256 / kWave];
-  const uint32_t n = nseg_dev ? min(nseg, *nseg_dev) : nseg;
-  const uint32_t base = blockIdx.x * uint32_t(kClassTile);
-  int cls[kClassIPT];
-  uint64_t lo = 0, hi = 0;
-#pragma unroll
-  for (int q = 0; q < kClassIPT; ++q) {
-    cls[q] = open_class(seg_size, seg_done, n, base + q * 256u + threadIdx.x, medium_cap, big_cap);
-    add_class(cls[q], lo, hi);
-  }
-  uint64_t tl, th;
-  uint64_t el = block_exclusive_scan<256>(lo, sh, &tl);
-  uint64_t eh = block_exclusive_scan<256>(hi, sh, &th);
-#pragma unroll
-  for (int q = 0; q < kClassIPT; ++q) {
-    const int c = cls[q];
-    if (c < 0) continue;
-    const uint32_t j = base + q * 256u + threadIdx.x;
-    const uint32_t o = meta[kSegClasses + c] + part[c * gridDim.x + blockIdx.x] + class_field(c, el, eh);
-    add_class(c, el, eh);
-    out_start[o] = seg_start[j];
-    out_size[o] = seg_size[j];
-    out_depth[o] = seg_depth ? seg_depth[j] : 0u;
-  }
-}
+};
 
 // ---------------------------------------------------------------------------
 // Global pass for groups too large for the resolvers. Items are the members of

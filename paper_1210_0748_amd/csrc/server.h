@@ -30,9 +30,9 @@ namespace kb {
 
 // Device bytes a job of n nodes and m edges may hold at its peak: inputs
 // (12 m), the CSR sort's key and value buffers (16 m), the adjacency and the
-// per-round keys (8 m), per-node state and the global ordering passes
-// (~96 n), plus slack for the caching allocator's rounding.
-inline uint64_t job_footprint(uint64_t n, uint64_t m) { return 36 * m + 96 * n + (uint64_t(64) << 20); }
+// per-round keys (8 m), per-node state, the active set and the global
+// ordering passes (~160 n), plus slack for the caching allocator's rounding.
+inline uint64_t job_footprint(uint64_t n, uint64_t m) { return 36 * m + 160 * n + (uint64_t(64) << 20); }
 
 struct Request {
   enum State { kQueued, kRunning, kDone, kFailed, kCancelled };

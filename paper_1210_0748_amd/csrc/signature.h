@@ -2,20 +2,23 @@
 // the join that fills pId_old(tId), the projection/sort/de-duplication that
 // builds F, and the per-node signature string).
 //
-// For every node u whose current block has at least two members, the kernels
-// gather key(e) = (edge label rank << pid_bits) | pid_prev[dst(e)] over u's
-// out-edges, sort the keys of u ascending, drop duplicates and write the
-// unique keys to ukey[rowptr[u] ...] and their number to ucnt[u]. The key
-// order equals the order of the pairs (label, pid) because the label occupies
-// the high bits.
+// For every active node u (a member of a class with two or more members) the
+// kernel gathers key(e) = (edge label rank << pid_bits) | pid_prev[dst(e)]
+// over u's out-edges, sorts the keys of u ascending, drops duplicates and
+// writes the unique keys to ukey[rowptr[u] ...] and their number to ucnt[u].
+// The key order equals the order of the pairs (label, pid) because the label
+// occupies the high bits.
 //
-// Nodes alone in their block are skipped: a refinement never merges blocks
-// (Proposition 1), so such a node stays alone and its signature cannot
-// change its rank inside the block.
+// Nodes alone in their class are skipped: a refinement never merges classes
+// (Proposition 1), so such a node stays alone whatever its signature.
 //
-// Work is bucketed by out-degree: one thread (<= 16 keys, register sorting
-// network), one wave (<= 64 keys, shuffle bitonic), one workgroup (<= 4096
-// keys, LDS bitonic) or one workgroup with a global-memory radix sort (hubs).
+// One launch covers all active nodes. Work is split by out-degree: one thread
+// (<= 16 keys, register sorting network), one wave (<= 64 keys, shuffle
+// bitonic), one workgroup (<= 4096 keys, LDS bitonic) or one workgroup with a
+// global-memory radix sort (hubs). When every key is below 2^kBmKeyBits the
+// workgroup nodes de-duplicate through an LDS bitmap instead, and keep the
+// bitmap for the ordering's first-difference searches. Workgroups are laid out
+// hubs first, so the longest ones start first.
 #pragma once
 
 #include "common.h"
@@ -26,15 +29,15 @@ namespace kb {
 constexpr uint32_t kThreadMaxDeg = 16;
 constexpr uint32_t kWaveMaxDeg = 64;
 constexpr uint32_t kBlockMaxDeg = 4096;
-constexpr int kSigBlockNT = 256;
-constexpr int kHubNT = 256;
+constexpr int kSigNT = 256;
+constexpr int kBmKeyBits = 12;
+constexpr uint32_t kBmMaxWords = (1u << kBmKeyBits) / 32;
 
 template <typename AdjT, typename KeyT>
 struct SigArgs {
   const uint32_t* rowptr;  // [N+1]
   const AdjT* adj;         // [E] (label rank << dst_bits) | dst, CSR order
   const int32_t* pid;      // [N] previous-round ids
-  const uint32_t* bstart;  // [B+1] block start positions (block sizes)
   KeyT* ukey;              // [E] unique keys per node at rowptr offsets
   uint32_t* ucnt;          // [N]
   uint64_t* head;          // [N] first hw digits (key + 1, 0 past the end), most significant first
@@ -43,22 +46,40 @@ struct SigArgs {
   int hdbits;              // bits of one digit: key bits + 1
   uint32_t hw;             // digits per head word: 64 / hdbits
 
+  __device__ __forceinline__ KeyT key_of(AdjT a) const {
+    const uint32_t dst = uint32_t(a & ((AdjT(1) << dst_bits) - 1));
+    const uint64_t lab = uint64_t(a >> dst_bits);
+    return KeyT((lab << pid_bits) | uint64_t(uint32_t(pid[dst])));
+  }
   __device__ __forceinline__ uint64_t head_of(const KeyT* k, uint32_t c) const {
     if (hdbits >= 64) return c ? uint64_t(k[0]) + 1ull : 0ull;
     uint64_t v = 0;
     for (uint32_t j = 0; j < hw; ++j) v = (v << hdbits) | (j < c ? uint64_t(k[j]) + 1ull : 0ull);
     return v;
   }
+};
 
-  __device__ __forceinline__ KeyT key_of(AdjT a) const {
-    const uint32_t dst = uint32_t(a & ((AdjT(1) << dst_bits) - 1));
-    const uint64_t lab = uint64_t(a >> dst_bits);
-    return KeyT((lab << pid_bits) | uint64_t(uint32_t(pid[dst])));
-  }
-  __device__ __forceinline__ bool active(uint32_t n) const {
-    const int32_t p = pid[n];
-    return bstart[p + 1] - bstart[p] > 1;
-  }
+// Work of one launch. Lists hold node ids; bitmaps (when bm != nullptr) go to
+// slot b for block-list entry b and nb + h for hub-list entry h.
+struct SigWork {
+  const uint32_t* anode;  // all active nodes (the thread part skips those above kThreadMaxDeg)
+  const uint32_t* actr;   // dense thread part: node n is active when actr[n] == tag
+  uint32_t tag, n_nodes;
+  bool dense;             // thread part over all node ids (in order) instead of anode
+  const uint32_t* wl;     // wave list
+  const uint32_t* bl;     // block list
+  const uint32_t* hl;     // hub list
+  uint32_t nact, nw, nb, nh;
+  uint32_t* bm;           // bitmaps, `words` 32-bit words each, or nullptr
+  uint32_t* bmslot;       // [N]
+  uint32_t words;
+  void* hub_tmp;          // radix ping-pong space of the hubs (KeyT)
+  const uint32_t* hub_toff;  // [N] offset of a hub's space in hub_tmp
+  int key_bits;
+
+  __host__ __device__ uint32_t wave_units() const { return (nw + kSigNT / kWave - 1) / (kSigNT / kWave); }
+  __host__ __device__ uint32_t thread_units() const { return ((dense ? n_nodes : nact) + kSigNT - 1) / kSigNT; }
+  __host__ __device__ uint32_t grid() const { return nh + nb + wave_units() + thread_units(); }
 };
 
 template <typename KeyT>
@@ -69,47 +90,41 @@ __device__ __forceinline__ void cas_up(KeyT& a, KeyT& b, bool up) {
   b = up ? hi : lo;
 }
 
-// ---- bucket 1: one thread per node, out-degree <= 16 ------------------------
+// ---- one thread per node, out-degree <= 16 ------------------------------------
 template <typename AdjT, typename KeyT>
-__global__ __launch_bounds__(256) void sig_thread_k(SigArgs<AdjT, KeyT> a, uint32_t n_nodes) {
-  const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
-  uint32_t beg = 0, deg = 0;
-  bool act = false;
-  if (n < n_nodes) {
-    beg = a.rowptr[n];
-    deg = a.rowptr[n + 1] - beg;
-    act = deg <= kThreadMaxDeg && a.active(n);
-  }
-  if (act) {
-    constexpr int M = kThreadMaxDeg;
-    KeyT k[M];
+__device__ __forceinline__ void sig_thread_node(const SigArgs<AdjT, KeyT>& a, uint32_t n, uint32_t beg,
+                                                uint32_t deg) {
+  constexpr int M = kThreadMaxDeg;
+  KeyT k[M];
 #pragma unroll
-    for (int j = 0; j < M; ++j) k[j] = (uint32_t(j) < deg) ? a.key_of(a.adj[beg + j]) : ~KeyT(0);
+  for (int j = 0; j < M; ++j) k[j] = (uint32_t(j) < deg) ? a.key_of(a.adj[beg + j]) : ~KeyT(0);
 #pragma unroll
-    for (int size = 2; size <= M; size <<= 1) {
+  for (int size = 2; size <= M; size <<= 1) {
 #pragma unroll
-      for (int stride = size >> 1; stride > 0; stride >>= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
 #pragma unroll
-        for (int i = 0; i < M; ++i) {
-          const int j = i ^ stride;
-          if (j > i) cas_up(k[i], k[j], (i & size) == 0);
-        }
+      for (int i = 0; i < M; ++i) {
+        const int j = i ^ stride;
+        if (j > i) cas_up(k[i], k[j], (i & size) == 0);
       }
     }
-    uint32_t c = 0;
-#pragma unroll
-    for (int j = 0; j < M; ++j) {
-      if (uint32_t(j) < deg && (j == 0 || k[j] != k[j - 1])) {
-        a.ukey[beg + c] = k[j];
-        ++c;
-      }
-    }
-    a.ucnt[n] = c;
-    a.head[n] = a.head_of(a.ukey + beg, c);
   }
+  uint32_t c = 0;
+  uint64_t hv = 0;
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    if (uint32_t(j) < deg && (j == 0 || k[j] != k[j - 1])) {
+      a.ukey[beg + c] = k[j];
+      if (c < a.hw) hv = a.hdbits >= 64 ? uint64_t(k[j]) + 1ull : (hv << a.hdbits) | (uint64_t(k[j]) + 1ull);
+      ++c;
+    }
+  }
+  if (a.hdbits < 64 && c < a.hw) hv <<= (a.hw - c) * a.hdbits;
+  a.ucnt[n] = c;
+  a.head[n] = hv;
 }
 
-// ---- bucket 2: one wave per node, 16 < out-degree <= 64 ----------------------
+// ---- one wave per node, 16 < out-degree <= 64 ---------------------------------
 template <typename KeyT>
 __device__ __forceinline__ KeyT wave_bitonic64(KeyT k) {
   const int lane = __lane_id();
@@ -128,13 +143,9 @@ __device__ __forceinline__ KeyT wave_bitonic64(KeyT k) {
   return k;
 }
 
+// Every lane of the wave calls it with the same n.
 template <typename AdjT, typename KeyT>
-__global__ __launch_bounds__(256) void sig_wave_k(SigArgs<AdjT, KeyT> a, const uint32_t* __restrict__ list,
-                                                  uint32_t count) {
-  const uint32_t w = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-  if (w >= count) return;
-  const uint32_t n = list[w];
-  if (!a.active(n)) return;
+__device__ __forceinline__ void sig_wave_node(const SigArgs<AdjT, KeyT>& a, uint32_t n) {
   const int lane = __lane_id();
   const uint32_t beg = a.rowptr[n];
   const uint32_t deg = a.rowptr[n + 1] - beg;
@@ -156,12 +167,12 @@ __global__ __launch_bounds__(256) void sig_wave_k(SigArgs<AdjT, KeyT> a, const u
   }
 }
 
-// ---- bucket 3: one workgroup per node, 64 < out-degree <= 4096 --------------
+// ---- one workgroup per node, 64 < out-degree <= 4096 ----------------------------
 template <typename KeyT>
 __device__ __forceinline__ void block_bitonic(KeyT* s, uint32_t P) {
   for (uint32_t size = 2; size <= P; size <<= 1) {
     for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-      for (uint32_t i = threadIdx.x; i < P / 2; i += blockDim.x) {
+      for (uint32_t i = threadIdx.x; i < P / 2; i += kSigNT) {
         const uint32_t lo = 2 * i - (i & (stride - 1));
         const uint32_t hi = lo + stride;
         const bool up = (lo & size) == 0;
@@ -176,193 +187,71 @@ __device__ __forceinline__ void block_bitonic(KeyT* s, uint32_t P) {
   }
 }
 
-// Writes the unique keys of the sorted array s[0..deg) to out[0..) and
-// returns their number to every thread.
-template <int NT, typename KeyT>
-__device__ __forceinline__ uint32_t block_unique_write(const KeyT* s, uint32_t deg, KeyT* out) {
-  __shared__ uint32_t shc[NT / kWave];
-  uint32_t carry = 0;
-  for (uint32_t base = 0; base < deg; base += NT) {
-    const uint32_t i = base + threadIdx.x;
-    const bool f = i < deg && (i == 0 || s[i] != s[i - 1]);
-    uint32_t tot;
-    const uint32_t ex = block_exclusive_scan<NT>(uint32_t(f), shc, &tot);
-    if (f) out[carry + ex] = s[i];
-    carry += tot;
-  }
-  return carry;
-}
-
 template <typename AdjT, typename KeyT>
-__global__ __launch_bounds__(kSigBlockNT) void sig_block_k(SigArgs<AdjT, KeyT> a,
-                                                           const uint32_t* __restrict__ list,
-                                                           uint32_t count) {
-  __shared__ KeyT s[kBlockMaxDeg];
-  const uint32_t n = list[blockIdx.x];
-  if (!a.active(n)) return;
+__device__ __forceinline__ void sig_block_node(const SigArgs<AdjT, KeyT>& a, uint32_t n, KeyT* s, uint32_t* shc) {
   const uint32_t beg = a.rowptr[n];
   const uint32_t deg = a.rowptr[n + 1] - beg;
   uint32_t P = 128;
   while (P < deg) P <<= 1;
-  for (uint32_t i = threadIdx.x; i < P; i += kSigBlockNT)
-    s[i] = i < deg ? a.key_of(a.adj[beg + i]) : ~KeyT(0);
+  for (uint32_t i = threadIdx.x; i < P; i += kSigNT) s[i] = i < deg ? a.key_of(a.adj[beg + i]) : ~KeyT(0);
   __syncthreads();
   block_bitonic(s, P);
-  const uint32_t c = block_unique_write<kSigBlockNT>(s, deg, a.ukey + beg);
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    a.ucnt[n] = c;
-    a.head[n] = a.head_of(a.ukey + beg, c);
-  }
-}
-
-// ---- bucket 4: hubs, out-degree > 4096 -----------------------------------------
-// One workgroup sorts the node's keys with an LSD radix sort (8-bit digits)
-// that ping-pongs between ukey[beg..] and tmp[hoff..], then writes the
-// unique keys to ukey[beg..].
-template <typename AdjT, typename KeyT>
-__global__ __launch_bounds__(kHubNT) void sig_hub_k(SigArgs<AdjT, KeyT> a, const uint32_t* __restrict__ list,
-                                                    const uint32_t* __restrict__ hub_off, KeyT* __restrict__ tmp,
-                                                    int key_bits) {
-  constexpr int NW = kHubNT / kWave;
-  __shared__ uint32_t cnt[256];
-  __shared__ uint32_t base_d[256];
-  __shared__ uint32_t wcnt[NW][256];
-  __shared__ uint32_t shs[NW];
-  const uint32_t n = list[blockIdx.x];
-  if (!a.active(n)) return;
-  const uint32_t beg = a.rowptr[n];
-  const uint32_t deg = a.rowptr[n + 1] - beg;
-  KeyT* A = a.ukey + beg;
-  KeyT* B = tmp + hub_off[blockIdx.x];
-  for (uint32_t i = threadIdx.x; i < deg; i += kHubNT) A[i] = a.key_of(a.adj[beg + i]);
-  __syncthreads();
-  const int w = threadIdx.x / kWave;
-  KeyT* src = A;
-  KeyT* dst = B;
-  for (int shift = 0; shift < key_bits; shift += 8) {
-    for (int d = threadIdx.x; d < 256; d += kHubNT) cnt[d] = 0;
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < deg; i += kHubNT)
-      atomicAdd(&cnt[uint32_t(src[i] >> shift) & 255u], 1u);
-    __syncthreads();
-    {
-      uint32_t tot;
-      const uint32_t v = threadIdx.x < 256 ? cnt[threadIdx.x] : 0u;
-      const uint32_t ex = block_exclusive_scan<kHubNT>(v, shs, &tot);
-      if (threadIdx.x < 256) base_d[threadIdx.x] = ex;
-    }
-    __syncthreads();
-    for (uint32_t row = 0; row < deg; row += kHubNT) {
-      for (int j = threadIdx.x; j < NW * 256; j += kHubNT) (&wcnt[0][0])[j] = 0;
-      __syncthreads();
-      const uint32_t i = row + threadIdx.x;
-      const bool valid = i < deg;
-      const KeyT key = valid ? src[i] : KeyT(0);
-      const uint32_t d = valid ? (uint32_t(key >> shift) & 255u) : 0u;
-      const uint64_t m = match_digit8(d, __ballot(valid));
-      const uint32_t rank = __popcll(m & lanemask_lt());
-      if (valid && rank == 0) wcnt[w][d] = __popcll(m);
-      __syncthreads();
-      if (valid) {
-        uint32_t off = base_d[d] + rank;
-        for (int q = 0; q < w; ++q) off += wcnt[q][d];
-        dst[off] = key;
-      }
-      __syncthreads();
-      for (int dd = threadIdx.x; dd < 256; dd += kHubNT) {
-        uint32_t s2 = 0;
-#pragma unroll
-        for (int q = 0; q < NW; ++q) s2 += wcnt[q][dd];
-        base_d[dd] += s2;
-      }
-      __syncthreads();
-    }
-    KeyT* t = src;
-    src = dst;
-    dst = t;
-  }
-  // unique pass: read src (sorted), write A; in place when src == A, so each
-  // chunk is read completely before any of it is written.
-  __shared__ uint32_t shc[NW];
+  KeyT* out = a.ukey + beg;
   uint32_t carry = 0;
-  for (uint32_t base = 0; base < deg; base += kHubNT) {
+  for (uint32_t base = 0; base < deg; base += kSigNT) {
     const uint32_t i = base + threadIdx.x;
-    KeyT cur = 0;
-    bool f = false;
-    if (i < deg) {
-      cur = src[i];
-      f = (i == 0) || cur != src[i - 1];
-    }
+    const bool f = i < deg && (i == 0 || s[i] != s[i - 1]);
     uint32_t tot;
-    const uint32_t ex = block_exclusive_scan<kHubNT>(uint32_t(f), shc, &tot);  // has barriers
-    if (f) A[carry + ex] = cur;
+    const uint32_t ex = block_exclusive_scan<kSigNT>(uint32_t(f), shc, &tot);
+    if (f) out[carry + ex] = s[i];
     carry += tot;
-    __syncthreads();
   }
+  __syncthreads();
   if (threadIdx.x == 0) {
     a.ucnt[n] = carry;
-    a.head[n] = a.head_of(A, carry);
+    a.head[n] = a.head_of(out, carry);
   }
 }
 
-// ---- small key universes: bitmap de-duplication -----------------------------
-// When every key is below 2^kBmKeyBits, a node's unique keys are the set bits
-// of a bitmap of `words` 32-bit words: the workgroup ORs the node's keys into
-// LDS, then lists the set bits in ascending order (a block scan of the word
+// ---- small key universes: bitmap de-duplication ---------------------------------
+// The workgroup ORs the node's keys into an LDS bitmap of `words` 32-bit
+// words, then lists the set bits in ascending order (a block scan of the word
 // popcounts gives each word's first output slot). The bitmap itself is kept
-// in bm[slot * words ...] for later first-difference searches, and
-// bmslot[n] = slot. Used for nodes with more than kWaveMaxDeg edges: list
-// entry i gets slot slot0 + i.
-constexpr int kBmKeyBits = 12;
-constexpr uint32_t kBmMaxWords = (1u << kBmKeyBits) / 32;
-
-struct BmOut {
-  uint32_t* bm;      // [slots * words]
-  uint32_t* bmslot;  // [N]
-  uint32_t words;    // 32-bit words per bitmap (>= 2)
-  uint32_t slot0;
-};
-
-template <typename AdjT, typename KeyT, int NT>
-__global__ __launch_bounds__(NT) void sig_bitmap_k(SigArgs<AdjT, KeyT> a, const uint32_t* __restrict__ list,
-                                                   BmOut o) {
-  __shared__ uint32_t w[kBmMaxWords];
-  __shared__ uint32_t shs[NT / kWave];
-  const uint32_t n = list[blockIdx.x];
-  if (!a.active(n)) return;
-  const uint32_t nw = o.words;
-  for (uint32_t i = threadIdx.x; i < nw; i += NT) w[i] = 0;
+// in bm[slot * words ...] for first-difference searches, and bmslot[n] = slot.
+template <typename AdjT, typename KeyT>
+__device__ __forceinline__ void sig_bitmap_node(const SigArgs<AdjT, KeyT>& a, uint32_t n, const SigWork& w,
+                                                uint32_t slot, uint32_t* bits, uint32_t* shs) {
+  const uint32_t nw = w.words;
+  for (uint32_t i = threadIdx.x; i < nw; i += kSigNT) bits[i] = 0;
   __syncthreads();
   const uint32_t beg = a.rowptr[n];
   const uint32_t deg = a.rowptr[n + 1] - beg;
   // four edges in flight per thread
   uint32_t i = threadIdx.x;
-  for (; i + 3 * NT < deg; i += 4 * NT) {
-    const AdjT e0 = a.adj[beg + i], e1 = a.adj[beg + i + NT];
-    const AdjT e2 = a.adj[beg + i + 2 * NT], e3 = a.adj[beg + i + 3 * NT];
+  for (; i + 3 * kSigNT < deg; i += 4 * kSigNT) {
+    const AdjT e0 = a.adj[beg + i], e1 = a.adj[beg + i + kSigNT];
+    const AdjT e2 = a.adj[beg + i + 2 * kSigNT], e3 = a.adj[beg + i + 3 * kSigNT];
     const uint32_t k0 = uint32_t(a.key_of(e0)), k1 = uint32_t(a.key_of(e1));
     const uint32_t k2 = uint32_t(a.key_of(e2)), k3 = uint32_t(a.key_of(e3));
-    atomicOr(&w[k0 >> 5], 1u << (k0 & 31));
-    atomicOr(&w[k1 >> 5], 1u << (k1 & 31));
-    atomicOr(&w[k2 >> 5], 1u << (k2 & 31));
-    atomicOr(&w[k3 >> 5], 1u << (k3 & 31));
+    atomicOr(&bits[k0 >> 5], 1u << (k0 & 31));
+    atomicOr(&bits[k1 >> 5], 1u << (k1 & 31));
+    atomicOr(&bits[k2 >> 5], 1u << (k2 & 31));
+    atomicOr(&bits[k3 >> 5], 1u << (k3 & 31));
   }
-  for (; i < deg; i += NT) {
+  for (; i < deg; i += kSigNT) {
     const uint32_t k = uint32_t(a.key_of(a.adj[beg + i]));
-    atomicOr(&w[k >> 5], 1u << (k & 31));
+    atomicOr(&bits[k >> 5], 1u << (k & 31));
   }
   __syncthreads();
-  const uint32_t slot = o.slot0 + blockIdx.x;
-  uint32_t* out = o.bm + size_t(slot) * nw;
+  uint32_t* out = w.bm + size_t(slot) * nw;
   KeyT* uk = a.ukey + beg;
   uint32_t carry = 0;
-  for (uint32_t base = 0; base < nw; base += NT) {
+  for (uint32_t base = 0; base < nw; base += kSigNT) {
     const uint32_t j = base + threadIdx.x;
-    uint32_t v = j < nw ? w[j] : 0u;
+    uint32_t v = j < nw ? bits[j] : 0u;
     if (j < nw) out[j] = v;
     uint32_t tot;
-    uint32_t r = carry + block_exclusive_scan<NT>(uint32_t(__popc(v)), shs, &tot);
+    uint32_t r = carry + block_exclusive_scan<kSigNT>(uint32_t(__popc(v)), shs, &tot);
     while (v) {
       const uint32_t b = uint32_t(__ffs(v) - 1);
       uk[r++] = KeyT(j * 32u + b);
@@ -374,31 +263,174 @@ __global__ __launch_bounds__(NT) void sig_bitmap_k(SigArgs<AdjT, KeyT> a, const 
   if (threadIdx.x == 0) {
     a.ucnt[n] = carry;
     a.head[n] = a.head_of(uk, carry);
-    o.bmslot[n] = slot;
+    w.bmslot[n] = slot;
   }
 }
 
-// Work of the signature kernels (profiling only, launched separately so the
-// timed kernels carry no counters): per bucket, active nodes and their edges.
-__global__ __launch_bounds__(256) void work_count_k(const uint32_t* __restrict__ rowptr,
-                                                    const int32_t* __restrict__ pid,
-                                                    const uint32_t* __restrict__ bstart, uint32_t n,
-                                                    unsigned long long* __restrict__ work) {
-  __shared__ unsigned long long acc[8];
-  if (threadIdx.x < 8) acc[threadIdx.x] = 0;
+// ---- hubs, out-degree > 4096 -------------------------------------------------------
+// One workgroup sorts the node's keys with an LSD radix sort (8-bit digits)
+// that ping-pongs between ukey[beg..] and tmp[0..deg), then writes the unique
+// keys to ukey[beg..].
+struct HubLds {
+  uint32_t cnt[256];
+  uint32_t base_d[256];
+  uint32_t wcnt[kSigNT / kWave][256];
+  uint32_t shs[kSigNT / kWave];
+};
+
+template <typename AdjT, typename KeyT>
+__device__ __forceinline__ void sig_hub_node(const SigArgs<AdjT, KeyT>& a, uint32_t n, KeyT* tmp, int key_bits,
+                                             HubLds& L) {
+  constexpr int NW = kSigNT / kWave;
+  const uint32_t beg = a.rowptr[n];
+  const uint32_t deg = a.rowptr[n + 1] - beg;
+  KeyT* A = a.ukey + beg;
+  KeyT* B = tmp;
+  for (uint32_t i = threadIdx.x; i < deg; i += kSigNT) A[i] = a.key_of(a.adj[beg + i]);
   __syncthreads();
-  const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n) {
-    const int32_t p = pid[v];
-    if (bstart[p + 1] - bstart[p] > 1) {
-      const uint32_t d = rowptr[v + 1] - rowptr[v];
-      const int b = d <= kThreadMaxDeg ? 0 : d <= kWaveMaxDeg ? 1 : d <= kBlockMaxDeg ? 2 : 3;
-      atomicAdd(&acc[2 * b], 1ull);
-      atomicAdd(&acc[2 * b + 1], (unsigned long long)d);
+  const int w = threadIdx.x / kWave;
+  KeyT* src = A;
+  KeyT* dst = B;
+  for (int shift = 0; shift < key_bits; shift += 8) {
+    for (int d = threadIdx.x; d < 256; d += kSigNT) L.cnt[d] = 0;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < deg; i += kSigNT) atomicAdd(&L.cnt[uint32_t(src[i] >> shift) & 255u], 1u);
+    __syncthreads();
+    {
+      uint32_t tot;
+      const uint32_t v = threadIdx.x < 256 ? L.cnt[threadIdx.x] : 0u;
+      const uint32_t ex = block_exclusive_scan<kSigNT>(v, L.shs, &tot);
+      if (threadIdx.x < 256) L.base_d[threadIdx.x] = ex;
+    }
+    __syncthreads();
+    for (uint32_t row = 0; row < deg; row += kSigNT) {
+      for (int j = threadIdx.x; j < NW * 256; j += kSigNT) (&L.wcnt[0][0])[j] = 0;
+      __syncthreads();
+      const uint32_t i = row + threadIdx.x;
+      const bool valid = i < deg;
+      const KeyT key = valid ? src[i] : KeyT(0);
+      const uint32_t d = valid ? (uint32_t(key >> shift) & 255u) : 0u;
+      const uint64_t m = match_digit8(d, __ballot(valid));
+      const uint32_t rank = __popcll(m & lanemask_lt());
+      if (valid && rank == 0) L.wcnt[w][d] = __popcll(m);
+      __syncthreads();
+      if (valid) {
+        uint32_t off = L.base_d[d] + rank;
+        for (int q = 0; q < w; ++q) off += L.wcnt[q][d];
+        dst[off] = key;
+      }
+      __syncthreads();
+      for (int dd = threadIdx.x; dd < 256; dd += kSigNT) {
+        uint32_t s2 = 0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) s2 += L.wcnt[q][dd];
+        L.base_d[dd] += s2;
+      }
+      __syncthreads();
+    }
+    KeyT* t = src;
+    src = dst;
+    dst = t;
+  }
+  // unique pass: read src (sorted), write A; in place when src == A, so each
+  // chunk is read completely before any of it is written.
+  uint32_t carry = 0;
+  for (uint32_t base = 0; base < deg; base += kSigNT) {
+    const uint32_t i = base + threadIdx.x;
+    KeyT cur = 0;
+    bool f = false;
+    if (i < deg) {
+      cur = src[i];
+      f = (i == 0) || cur != src[i - 1];
+    }
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan<kSigNT>(uint32_t(f), L.shs, &tot);  // has barriers
+    if (f) A[carry + ex] = cur;
+    carry += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    a.ucnt[n] = carry;
+    a.head[n] = a.head_of(A, carry);
+  }
+}
+
+// ---- the launch ----------------------------------------------------------------------
+template <typename KeyT>
+union SigLds {
+  KeyT block[kBlockMaxDeg];
+  HubLds hub;
+  struct {
+    uint32_t bits[kBmMaxWords];
+    uint32_t shs[kSigNT / kWave];
+  } bm;
+};
+
+template <typename AdjT, typename KeyT>
+__global__ __launch_bounds__(kSigNT) void signature_k(SigArgs<AdjT, KeyT> a, SigWork w) {
+  __shared__ SigLds<KeyT> lds;
+  __shared__ uint32_t shc[kSigNT / kWave];
+  uint32_t b = blockIdx.x;
+  if (b < w.nh) {
+    const uint32_t n = w.hl[b];
+    if (w.bm)
+      sig_bitmap_node(a, n, w, w.nb + b, lds.bm.bits, lds.bm.shs);
+    else
+      sig_hub_node(a, n, static_cast<KeyT*>(w.hub_tmp) + w.hub_toff[n], w.key_bits, lds.hub);
+    return;
+  }
+  b -= w.nh;
+  if (b < w.nb) {
+    const uint32_t n = w.bl[b];
+    if (w.bm)
+      sig_bitmap_node(a, n, w, b, lds.bm.bits, lds.bm.shs);
+    else
+      sig_block_node(a, n, lds.block, shc);
+    return;
+  }
+  b -= w.nb;
+  if (b < w.wave_units()) {
+    const uint32_t wi = b * (kSigNT / kWave) + threadIdx.x / kWave;
+    if (wi < w.nw) sig_wave_node(a, w.wl[wi]);
+    return;
+  }
+  b -= w.wave_units();
+  const uint32_t j = b * kSigNT + threadIdx.x;
+  uint32_t n = 0xffffffffu;
+  if (w.dense) {
+    if (j < w.n_nodes && w.actr[j] == w.tag) n = j;
+  } else if (j < w.nact) {
+    n = w.anode[j];
+  }
+  if (n != 0xffffffffu) {
+    const uint32_t beg = a.rowptr[n];
+    const uint32_t deg = a.rowptr[n + 1] - beg;
+    if (deg <= kThreadMaxDeg) sig_thread_node(a, n, beg, deg);
+  }
+}
+
+// Work of the signature launch (profiling only): per bucket (thread, wave,
+// block, hub) the active nodes and their edges.
+__global__ void work_count_k(const uint32_t* __restrict__ anode, const uint32_t* __restrict__ rowptr, uint32_t m,
+                             unsigned long long* __restrict__ acc) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  uint64_t ne[4] = {0, 0, 0, 0};
+  uint64_t nn[4] = {0, 0, 0, 0};
+  if (j < m) {
+    const uint32_t n = anode[j];
+    const uint32_t d = rowptr[n + 1] - rowptr[n];
+    const int c = d <= kThreadMaxDeg ? 0 : d <= kWaveMaxDeg ? 1 : d <= kBlockMaxDeg ? 2 : 3;
+    nn[c] = 1;
+    ne[c] = d;
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const uint64_t sn = wave_sum(nn[c]), se = wave_sum(ne[c]);
+    if (__lane_id() == 0 && (sn || se)) {
+      atomicAdd(&acc[2 * c], (unsigned long long)sn);
+      atomicAdd(&acc[2 * c + 1], (unsigned long long)se);
     }
   }
-  __syncthreads();
-  if (threadIdx.x < 8 && acc[threadIdx.x]) atomicAdd(&work[threadIdx.x], acc[threadIdx.x]);
 }
 
 }  // namespace kb

@@ -187,7 +187,7 @@ def test_profile_mode_same_ids():
         prof = h.profile()
         work = h.work()
     assert rd == r.rounds_done and counts == r.counts and np.array_equal(pid, r.pid)
-    assert prof["round"][1] == rd and prof["sig_thread"][1] == rd
+    assert prof["round"][1] == rd and prof["signature"][1] == rd
     assert sum(v[0] for v in work.values()) > 0
 
 
