@@ -84,6 +84,17 @@ __global__ void hub_degree_k(const uint32_t* __restrict__ rowptr, uint32_t n, ui
   hub_deg[v] = d > b_max ? d : 0u;
 }
 
+// *mx = largest out-degree (grid-stride; one atomic per wave at most).
+__global__ void max_degree_k(const uint32_t* __restrict__ rowptr, uint32_t n, uint32_t* __restrict__ mx) {
+  uint32_t m = 0;
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    const uint32_t d = rowptr[v + 1] - rowptr[v];
+    m = d > m ? d : m;
+  }
+  m = wave_max(m);
+  if (__lane_id() == 0 && m > __hip_atomic_load(mx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(mx, m);
+}
+
 // Label values below this bound are ranked through a presence table; larger
 // values through a sort.
 constexpr uint32_t kRankTableMax = 1u << 24;

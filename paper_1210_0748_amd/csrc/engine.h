@@ -165,6 +165,7 @@ class Engine {
   // graph
   DevBuf rowptr_, adj_, hub_toff_, hub_tmp_;
   uint64_t hub_edges_ = 0;
+  uint32_t maxdeg_ = 0;  // largest out-degree
   // partition state: ord, class-start flags, class-start position ids, and
   // the dense pId_0 used by the first round's keys
   DevBuf pid_, pid0_, ord_, flag_;
@@ -186,7 +187,7 @@ class Engine {
   DevBuf ukey_, ucnt_, head_, cls_, fl_, first_, scanpart_, radix_, part_, bm_, bmslot_;
   DevBuf seg_start_, seg_size_, seg_depth_, seg_done_, cls_meta_;
   SegLists lists_b_;
-  DevBuf l_ioff_, l_lcp_, l_long_, l_open_;
+  DevBuf l_ioff_, l_fd_, l_long_, l_open_;
   DevBuf k0_, k1_, k2_, k3_, k4_, v0_, v1_, v2_, v3_, v4_, sflag_, soff2_, ipos_, sub_item_;
   DevBuf next_l_start_[2], next_l_size_[2], next_l_depth_[2];
 

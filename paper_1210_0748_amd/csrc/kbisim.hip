@@ -141,7 +141,12 @@ void Engine::build_adj(const int32_t* src, const int32_t* lab, const int32_t* ds
     hub_degree_k<<<grid_for(N), kNT, 0, st_>>>(rowptr_.as<uint32_t>(), uint32_t(N), kBlockMaxDeg, hd.as<uint32_t>());
     KB_LAUNCH_CHECK();
     scan_dev<uint32_t, uint32_t, false>(hd.as<uint32_t>(), hub_toff_.as<uint32_t>(), N + 1);
-    hub_edges_ = read_word(hub_toff_.as<uint32_t>() + N, 4);  // synchronises: `hd` may be freed
+    KB_CHECK(hipMemsetAsync(hd.p, 0, 4, st_));
+    max_degree_k<<<std::min<uint32_t>(grid_for(N), 1024), kNT, 0, st_>>>(rowptr_.as<uint32_t>(), uint32_t(N),
+                                                                       hd.as<uint32_t>());
+    KB_LAUNCH_CHECK();
+    hub_edges_ = read_word(hub_toff_.as<uint32_t>() + N, 4);
+    maxdeg_ = uint32_t(read_word(hd.p, 4));  // synchronises: `hd` may be freed
   }
 }
 
@@ -438,8 +443,8 @@ void Engine::order_groups(int key_bits, const void* kvp) {
   // the round's segments are already classified by size (act_)
   resolve_lists<KeyT>(act_, kvp);
 
-  // Large groups: global passes, each sorting every group by the digits
-  // after its common prefix.
+  // Large groups: global passes. The first sorts whole classes by their
+  // leading digits; later ones split every group around its pivot.
   const KeyView<KeyT>& kv = *static_cast<const KeyView<KeyT>*>(kvp);
   uint32_t nl = act_.cnt[kLargeClass];
   const uint32_t* Ls = act_.start.as<uint32_t>() + act_.off[kLargeClass];
@@ -449,6 +454,8 @@ void Engine::order_groups(int key_bits, const void* kvp) {
   bool first_pass = true;
   const int dbits = key_bits + 1;
   const uint64_t last_mask = dbits >= 64 ? ~0ull : ((1ull << dbits) - 1);
+  const uint32_t head_w = dbits >= 64 ? 1u : uint32_t(64 / dbits);
+  const int fd_bits = bits_for(maxdeg_ > 0 ? maxdeg_ : 1);  // first differences are below the longest sequence
   while (nl > 0) {
     // item offsets of the large groups (sizes with a trailing zero)
     l_ioff_.ensure((uint64_t(nl) + 1) * 4);
@@ -459,38 +466,33 @@ void Engine::order_groups(int key_bits, const void* kvp) {
     const uint32_t M = uint32_t(read_word(l_ioff_.as<uint32_t>() + nl, 4));
     const uint32_t* gio = l_ioff_.as<uint32_t>();
 
-    // end of every group's common prefix; the first pass works on whole
-    // classes at depth 0 and sorts by their first digits directly (a class
-    // whose members share them all comes back as one subgroup and has its
-    // common prefix measured in the next pass)
-    l_lcp_.ensure(uint64_t(nl) * 4);
-    if (first_pass) {
-      KB_CHECK(hipMemsetAsync(l_lcp_.p, 0, uint64_t(nl) * 4, st_));
-    } else {
+    // pivot passes: every item's first difference with its group's pivot
+    if (!first_pass) {
+      l_fd_.ensure(uint64_t(M) * 4);
       l_long_.ensure((uint64_t(M) + 1) * 4);
-      KB_CHECK(hipMemsetAsync(l_lcp_.p, 0xff, uint64_t(nl) * 4, st_));
       KB_CHECK(hipMemsetAsync(l_long_.as<uint32_t>() + M, 0, 4, st_));
-      large_lcp_k<KeyT><<<grid_for(M), kNT, 0, st_>>>(Ls, Ld, gio, nl, M, ord_.as<uint32_t>(),
-                                                     l_lcp_.as<uint32_t>(), l_long_.as<uint32_t>(),
-                                                     l_long_.as<uint32_t>() + M, kv);
+      large_fd_k<KeyT><<<grid_for(M), kNT, 0, st_>>>(Ls, Ld, gio, nl, M, ord_.as<uint32_t>(), l_fd_.as<uint32_t>(),
+                                                    l_long_.as<uint32_t>(), l_long_.as<uint32_t>() + M, kv);
       KB_LAUNCH_CHECK();
-      large_lcp_wave_k<KeyT><<<std::min<uint32_t>(grid_for(uint64_t(M) * kWave), 4096), kNT, 0, st_>>>(
-          Ls, Ld, gio, nl, ord_.as<uint32_t>(), l_lcp_.as<uint32_t>(), l_long_.as<uint32_t>(),
+      large_fd_wave_k<KeyT><<<std::min<uint32_t>(grid_for(uint64_t(M) * kWave), 4096), kNT, 0, st_>>>(
+          Ls, Ld, gio, nl, ord_.as<uint32_t>(), l_fd_.as<uint32_t>(), l_long_.as<uint32_t>(),
           l_long_.as<uint32_t>() + M, kv);
       KB_LAUNCH_CHECK();
     }
     const uint64_t* head = first_pass ? head_.as<uint64_t>() : nullptr;
-    const uint32_t head_w = dbits >= 64 ? 1u : uint32_t(64 / dbits);
+    const uint32_t* fdv = first_pass ? nullptr : l_fd_.as<uint32_t>();
 
-    // sort key layout: one word when (group, >= 1 digit) fit
+    // sort key layout: one word when (high part, >= 1 digit) fit
     const int g_bits = nl > 1 ? bits_for(nl - 1) : 0;
     LargeKey lk;
-    if (g_bits + dbits <= 64) {
+    lk.fd_bits = first_pass ? 0 : fd_bits;
+    const int hi_bits = first_pass ? g_bits : g_bits + 2 + fd_bits;
+    if (hi_bits + dbits <= 64) {
       lk.packed = true;
-      lk.width = uint32_t((64 - g_bits) / dbits);
+      lk.width = std::min<uint32_t>(uint32_t((64 - hi_bits) / dbits), head_w);
     } else {
       lk.packed = false;
-      lk.width = dbits >= 64 ? 1u : uint32_t(64 / dbits);
+      lk.width = head_w;
     }
     lk.dig_bits = int(lk.width) * dbits;
     for (DevBuf* b : {&k0_, &k1_}) b->ensure(uint64_t(M) * 8);
@@ -500,22 +502,22 @@ void Engine::order_groups(int key_bits, const void* kvp) {
     const uint64_t* KB = nullptr;
     const uint32_t* V;
     if (lk.packed) {
-      large_gather_k<KeyT><<<grid_for(M), kNT, 0, st_>>>(Ls, gio, nl, M, ord_.as<uint32_t>(), l_lcp_.as<uint32_t>(),
-                                                        lk, k0_.as<uint64_t>(), nullptr, v0_.as<uint32_t>(), kv,
-                                                        head, head_w);
+      large_gather_k<KeyT><<<grid_for(M), kNT, 0, st_>>>(Ls, Ld, gio, nl, M, ord_.as<uint32_t>(), fdv, lk,
+                                                        k0_.as<uint64_t>(), nullptr, v0_.as<uint32_t>(), kv, head,
+                                                        head_w);
       KB_LAUNCH_CHECK();
       const bool f = radix_sort<uint64_t>(k0_.as<uint64_t>(), v0_.as<uint32_t>(), k1_.as<uint64_t>(),
-                                          v1_.as<uint32_t>(), M, 0, g_bits + lk.dig_bits, radix_scratch(M), st_);
+                                          v1_.as<uint32_t>(), M, 0, hi_bits + lk.dig_bits, radix_scratch(M), st_);
       KA = f ? k1_.as<uint64_t>() : k0_.as<uint64_t>();
       V = f ? v1_.as<uint32_t>() : v0_.as<uint32_t>();
     } else {
       // two words: sort by lo (digits) carrying the item index, then stably
-      // by the group; the final order follows the second permutation
+      // by hi; the final order follows the second permutation
       for (DevBuf* b : {&k2_, &k3_, &k4_}) b->ensure(uint64_t(M) * 8);
       for (DevBuf* b : {&v2_, &v3_, &v4_}) b->ensure(uint64_t(M) * 4);
-      large_gather_k<KeyT><<<grid_for(M), kNT, 0, st_>>>(Ls, gio, nl, M, ord_.as<uint32_t>(), l_lcp_.as<uint32_t>(),
-                                                        lk, k2_.as<uint64_t>(), k0_.as<uint64_t>(),
-                                                        v4_.as<uint32_t>(), kv, head, head_w);
+      large_gather_k<KeyT><<<grid_for(M), kNT, 0, st_>>>(Ls, Ld, gio, nl, M, ord_.as<uint32_t>(), fdv, lk,
+                                                        k2_.as<uint64_t>(), k0_.as<uint64_t>(), v4_.as<uint32_t>(),
+                                                        kv, head, head_w);
       iota_k<<<grid_for(M), kNT, 0, st_>>>(v0_.as<uint32_t>(), M);
       KB_LAUNCH_CHECK();
       const bool f1 = radix_sort<uint64_t>(k0_.as<uint64_t>(), v0_.as<uint32_t>(), k1_.as<uint64_t>(),
@@ -526,7 +528,7 @@ void Engine::order_groups(int key_bits, const void* kvp) {
       iota_k<<<grid_for(M), kNT, 0, st_>>>(v2_.as<uint32_t>(), M);
       KB_LAUNCH_CHECK();
       const bool f2 = radix_sort<uint64_t>(k3_.as<uint64_t>(), v2_.as<uint32_t>(), k4_.as<uint64_t>(),
-                                           v3_.as<uint32_t>(), M, 0, std::max(g_bits, 1), radix_scratch(M), st_);
+                                           v3_.as<uint32_t>(), M, 0, std::max(hi_bits, 1), radix_scratch(M), st_);
       KA = f2 ? k4_.as<uint64_t>() : k3_.as<uint64_t>();
       const uint32_t* PS = f2 ? v3_.as<uint32_t>() : v2_.as<uint32_t>();
       uint64_t* lo_out = (L1 == k0_.as<uint64_t>()) ? k1_.as<uint64_t>() : k0_.as<uint64_t>();
@@ -547,8 +549,8 @@ void Engine::order_groups(int key_bits, const void* kvp) {
     seg_depth_.ensure(uint64_t(M) * 4 + 4);
     seg_done_.ensure(uint64_t(M) + 1);
     large_subgroups_k<<<grid_for(M), kNT, 0, st_>>>(sflag_.as<uint32_t>(), soff2_.as<uint32_t>(), M,
-                                                    ipos_.as<uint32_t>(), KA, KB, lk, last_mask,
-                                                    l_lcp_.as<uint32_t>(), sub_item_.as<uint32_t>(),
+                                                    ipos_.as<uint32_t>(), KA, KB, lk, last_mask, Ld,
+                                                    sub_item_.as<uint32_t>(),
                                                     seg_start_.as<uint32_t>(), seg_depth_.as<uint32_t>(),
                                                     seg_done_.as<uint8_t>());
     subgroup_sizes_k<<<grid_for(M), kNT, 0, st_>>>(sub_item_.as<uint32_t>(), ns_dev, M, seg_size_.as<uint32_t>());

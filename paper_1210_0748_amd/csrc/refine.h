@@ -12,16 +12,16 @@
 // A group (a class, or a part of one whose members agree on all keys before
 // the group's depth t) is ordered by most-significant-digit refinement, with
 // digit(t) = key[t] + 1 (0 once the sequence has ended, so a proper prefix
-// sorts first). Two schemes split a group:
-//  * groups of up to a few hundred members (resolve_lanes_k, resolve_k) split
-//    around their first member (the pivot): each member finds the first
-//    position d where it differs from the pivot, and members are ordered by
-//    (below/equal/above the pivot at d, d, digits from d on); members that tie
-//    agree on everything before d + width and form the next subgroups;
-//  * larger groups go through global passes (large_*_k): the group's common
-//    prefix ends at the smallest such d over its members; all members are
-//    sorted by the digits from there with one device-wide radix sort, and
-//    runs of equal digits become the next groups.
+// sorts first). A group splits around its first member (the pivot): each
+// member finds the first position d where it differs from the pivot, and
+// members are ordered by (below/equal/above the pivot at d, d, digits from d
+// on); members that tie agree on everything before d + width and form the
+// next subgroups. Groups of up to a few thousand members do this in registers
+// or LDS (resolve_lanes_k, resolve_k); larger ones in global passes
+// (large_*_k) that sort the members of all large groups with one device-wide
+// radix sort. The first global pass of a round works on whole classes at
+// depth 0 and sorts by the leading digits only (no pivot), which every node's
+// signature kernel wrote out.
 // When keys are narrow, several consecutive digits are packed into one
 // 64-bit sort digit (most significant first), which consumes that many
 // positions per step. A subgroup whose sequences ended inside the packed
@@ -70,17 +70,29 @@ struct KeyView {
     const uint64_t* A = bm + size_t(bmslot[a]) * bm_words64;
     const uint64_t* B = bm + size_t(bmslot[b]) * bm_words64;
     uint32_t below = 0;
-    for (uint32_t w = 0; w < bm_words64; w += 2) {
-      const uint64_t a0 = A[w], a1 = A[w + 1], b0 = B[w], b1 = B[w + 1];
-      const uint64_t x0 = a0 ^ b0, x1 = a1 ^ b1;
-      if (x0) return below + uint32_t(__popcll(a0 & ((x0 & (~x0 + 1)) - 1)));
-      below += uint32_t(__popcll(a0));
-      if (x1) return below + uint32_t(__popcll(a1 & ((x1 & (~x1 + 1)) - 1)));
-      below += uint32_t(__popcll(a1));
+    // eight words of each bitmap in flight per step
+    uint32_t w = 0;
+    for (; w + 8 <= bm_words64; w += 8) {
+      uint64_t va[8], vb[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        va[q] = A[w + q];
+        vb[q] = B[w + q];
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const uint64_t x = va[q] ^ vb[q];
+        if (x) return below + uint32_t(__popcll(va[q] & ((x & (~x + 1)) - 1)));
+        below += uint32_t(__popcll(va[q]));
+      }
+    }
+    for (; w < bm_words64; ++w) {
+      const uint64_t x = A[w] ^ B[w];
+      if (x) return below + uint32_t(__popcll(A[w] & ((x & (~x + 1)) - 1)));
+      below += uint32_t(__popcll(A[w]));
     }
     return kNoDiff;
   }
-
   __device__ __forceinline__ uint64_t digit(uint32_t node, uint32_t t) const {
     return t < ucnt[node] ? uint64_t(ukey[rowptr[node] + t]) + 1ull : 0ull;
   }
@@ -133,13 +145,16 @@ struct KeyView {
     const KeyT* ka = ukey + rowptr[a];
     const KeyT* kb_ = ukey + rowptr[b];
     uint32_t j = t;
-    for (; j + 4 <= stop; j += 4) {
-      const KeyT a0 = ka[j], a1 = ka[j + 1], a2 = ka[j + 2], a3 = ka[j + 3];
-      const KeyT b0 = kb_[j], b1 = kb_[j + 1], b2 = kb_[j + 2], b3 = kb_[j + 3];
-      if (a0 != b0) return j;
-      if (a1 != b1) return j + 1;
-      if (a2 != b2) return j + 2;
-      if (a3 != b3) return j + 3;
+    for (; j + 8 <= stop; j += 8) {
+      KeyT va[8], vb[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        va[q] = ka[j + q];
+        vb[q] = kb_[j + q];
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (va[q] != vb[q]) return j + q;
     }
     for (; j < stop; ++j)
       if (ka[j] != kb_[j]) return j;
@@ -568,53 +583,37 @@ __device__ __forceinline__ uint32_t group_of_item(const uint32_t* ioff, uint32_t
   return lo;
 }
 
-// atomicMin(&lcp[g], d) for d != kNoDiff, with one atomic per wave when the
-// wave's lanes share one group (the common case: groups are long runs of
-// items), and none when lcp[g] is already at most d.
-__device__ __forceinline__ void lcp_update(uint32_t* lcp, uint32_t g, uint32_t d) {
-  const uint32_t g0 = __shfl(g, __ffsll((unsigned long long)__ballot(true)) - 1, kWave);
-  if (__all(g == g0)) {
-    const uint32_t m = wave_min(d);
-    const int first = __ffsll((unsigned long long)__ballot(true)) - 1;
-    if (__lane_id() == first && m != kNoDiff &&
-        m < __hip_atomic_load(&lcp[g0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-      atomicMin(&lcp[g0], m);
-  } else if (d != kNoDiff && d < __hip_atomic_load(&lcp[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-    atomicMin(&lcp[g], d);
-  }
-}
-
-// lcp[g] = smallest first difference of a member of group g with the group's
-// first member (kNoDiff when all members are copies of it); lcp[] starts at
-// kNoDiff. Each thread compares one item over a short window; items that
-// still agree are appended to `longq` for large_lcp_wave_k.
+// fdv[i] = first difference of item i's sequence with its group's first
+// member, the pivot (kNoDiff for the pivot and its copies). Each thread
+// compares one item over a short window; items that still agree are appended
+// to `longq` for large_fd_wave_k.
 template <typename KeyT>
-__global__ __launch_bounds__(256) void large_lcp_k(const uint32_t* __restrict__ gstart,
-                                                   const uint32_t* __restrict__ gdepth,
-                                                   const uint32_t* __restrict__ ioff, uint32_t ng, uint32_t nitems,
-                                                   const uint32_t* __restrict__ ord, uint32_t* __restrict__ lcp,
-                                                   uint32_t* __restrict__ longq, uint32_t* __restrict__ nlong,
-                                                   KeyView<KeyT> kv) {
-  // no early exit: the wave-wide steps below need every lane
+__global__ __launch_bounds__(256) void large_fd_k(const uint32_t* __restrict__ gstart,
+                                                  const uint32_t* __restrict__ gdepth,
+                                                  const uint32_t* __restrict__ ioff, uint32_t ng, uint32_t nitems,
+                                                  const uint32_t* __restrict__ ord, uint32_t* __restrict__ fdv,
+                                                  uint32_t* __restrict__ longq, uint32_t* __restrict__ nlong,
+                                                  KeyView<KeyT> kv) {
+  // no early exit: wave_append needs every lane
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  uint32_t g = 0xffffffffu, d = kNoDiff;
+  uint32_t d = kNoDiff;
   if (i < nitems) {
-    g = group_of_item(ioff, ng, i);
+    const uint32_t g = group_of_item(ioff, ng, i);
     const uint32_t a = ord[gstart[g] + (i - ioff[g])];
     const uint32_t b = ord[gstart[g]];
     if (a != b) d = kv.first_diff_window(a, b, gdepth[g], kThreadWindow);
+    fdv[i] = d;
   }
   const uint32_t slot = wave_append(d == kUndecided, nlong);
   if (d == kUndecided) longq[slot] = i;
-  lcp_update(lcp, g, d == kUndecided ? kNoDiff : d);
 }
 
 // One wave per queued item, grid-stride over the queue length in *nlong.
 template <typename KeyT>
-__global__ void large_lcp_wave_k(const uint32_t* __restrict__ gstart, const uint32_t* __restrict__ gdepth,
-                                 const uint32_t* __restrict__ ioff, uint32_t ng, const uint32_t* __restrict__ ord,
-                                 uint32_t* __restrict__ lcp, const uint32_t* __restrict__ longq,
-                                 const uint32_t* __restrict__ nlong, KeyView<KeyT> kv) {
+__global__ void large_fd_wave_k(const uint32_t* __restrict__ gstart, const uint32_t* __restrict__ gdepth,
+                                const uint32_t* __restrict__ ioff, uint32_t ng, const uint32_t* __restrict__ ord,
+                                uint32_t* __restrict__ fdv, const uint32_t* __restrict__ longq,
+                                const uint32_t* __restrict__ nlong, KeyView<KeyT> kv) {
   const uint32_t nq = *nlong;
   const uint32_t waves = gridDim.x * (blockDim.x / kWave);
   for (uint32_t q = (blockIdx.x * blockDim.x + threadIdx.x) / kWave; q < nq; q += waves) {
@@ -623,49 +622,70 @@ __global__ void large_lcp_wave_k(const uint32_t* __restrict__ gstart, const uint
     const uint32_t a = ord[gstart[g] + (i - ioff[g])];
     const uint32_t b = ord[gstart[g]];
     const uint32_t d = kv.wave_first_diff(a, b, gdepth[g] + kThreadWindow);
-    if (__lane_id() == 0 && d != kNoDiff) atomicMin(&lcp[g], d);
+    if (__lane_id() == 0) fdv[i] = d;
   }
 }
 
-// Global sort key of an item of group g: the group index above `width`
-// digits taken from the group's common-prefix end lcp[g] on. Packed into one
-// word as g << dig_bits | digits when it fits, else kept as two words.
+// Global sort key of an item of group g, hi above lo:
+//  * head pass (groups are whole classes at depth 0): hi = g, lo = the first
+//    `width` digits of the sequence;
+//  * pivot pass: hi = g << (2 + fd_bits) | side << fd_bits | fdkey, lo =
+//    `width` digits from the item's first difference d with the pivot on,
+//    where side says whether the item is below, equal to or above the pivot
+//    at d, and fdkey = d - depth (below) or its complement in fd_bits
+//    (above), as in side_key.
+// Packed into one word as hi << dig_bits | lo when that fits, else two words.
 struct LargeKey {
+  int fd_bits;   // 0 in the head pass
   int dig_bits;  // width * dbits
   uint32_t width;
   bool packed;
-  __device__ __forceinline__ uint32_t group_of(const uint64_t* ka, uint32_t i) const {
-    return uint32_t(packed ? (dig_bits >= 64 ? 0ull : ka[i] >> dig_bits) : ka[i]);
+  __device__ __forceinline__ uint64_t hi_of(const uint64_t* ka, uint32_t i) const {
+    return packed ? (dig_bits >= 64 ? 0ull : ka[i] >> dig_bits) : ka[i];
   }
   __device__ __forceinline__ uint64_t lo_of(const uint64_t* ka, const uint64_t* kb, uint32_t i) const {
     return packed ? (dig_bits >= 64 ? ka[i] : (ka[i] & ((1ull << dig_bits) - 1))) : kb[i];
   }
+  __device__ __forceinline__ uint32_t group_of(uint64_t hi) const {
+    return uint32_t(fd_bits ? hi >> (2 + fd_bits) : hi);
+  }
 };
 
-// head (optional, only when every group is at depth 0 with lcp 0): the
-// first head_w digits of every node, packed as by KeyView::digits.
+// head (head pass only): the first head_w digits of every node, packed as by
+// KeyView::digits; fdv (pivot pass only): first differences with the pivots.
 template <typename KeyT>
-__global__ void large_gather_k(const uint32_t* __restrict__ gstart, const uint32_t* __restrict__ ioff,
-                               uint32_t ng, uint32_t nitems, const uint32_t* __restrict__ ord,
-                               const uint32_t* __restrict__ lcp, LargeKey lk, uint64_t* __restrict__ ka,
-                               uint64_t* __restrict__ kb, uint32_t* __restrict__ val, KeyView<KeyT> kv,
-                               const uint64_t* __restrict__ head, uint32_t head_w) {
+__global__ void large_gather_k(const uint32_t* __restrict__ gstart, const uint32_t* __restrict__ gdepth,
+                               const uint32_t* __restrict__ ioff, uint32_t ng, uint32_t nitems,
+                               const uint32_t* __restrict__ ord, const uint32_t* __restrict__ fdv, LargeKey lk,
+                               uint64_t* __restrict__ ka, uint64_t* __restrict__ kb, uint32_t* __restrict__ val,
+                               KeyView<KeyT> kv, const uint64_t* __restrict__ head, uint32_t head_w) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nitems) return;
   const uint32_t g = group_of_item(ioff, ng, i);
   const uint32_t node = ord[gstart[g] + (i - ioff[g])];
-  const uint32_t d = lcp[g];
-  uint64_t lo;
-  if (head) {
+  uint64_t hi, lo;
+  if (!lk.fd_bits) {
     const uint32_t drop = (head_w - lk.width) * uint32_t(kv.dbits);
     lo = drop >= 64 ? 0ull : head[node] >> drop;
+    hi = g;
   } else {
-    lo = d == kNoDiff ? 0ull : kv.digits(node, d, lk.width);
+    const uint32_t d = fdv[i];
+    uint64_t side = 1, fdkey = 0;
+    lo = 0;
+    if (d != kNoDiff) {
+      const uint32_t leader = ord[gstart[g]];
+      const uint64_t fdmask = (1ull << lk.fd_bits) - 1;
+      const uint64_t rel = d - gdepth[g];
+      side = kv.digit(node, d) < kv.digit(leader, d) ? 0 : 2;
+      fdkey = side == 0 ? rel : (fdmask - rel);
+      lo = kv.digits(node, d, lk.width);
+    }
+    hi = (uint64_t(g) << (2 + lk.fd_bits)) | (side << lk.fd_bits) | fdkey;
   }
   if (lk.packed) {
-    ka[i] = (lk.dig_bits >= 64 ? 0ull : (uint64_t(g) << lk.dig_bits)) | lo;
+    ka[i] = (lk.dig_bits >= 64 ? 0ull : (hi << lk.dig_bits)) | lo;
   } else {
-    ka[i] = g;
+    ka[i] = hi;
     kb[i] = lo;
   }
   val[i] = node;
@@ -680,37 +700,47 @@ __global__ void large_write_k(const uint32_t* __restrict__ gstart, const uint32_
                               uint32_t* __restrict__ item_pos) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nitems) return;
-  const uint32_t g = lk.group_of(ka, i);
-  const uint64_t lo = lk.lo_of(ka, kb, i);
+  const uint64_t hi = lk.hi_of(ka, i), lo = lk.lo_of(ka, kb, i);
+  const uint32_t g = lk.group_of(hi);
   const uint32_t p = gstart[g] + (i - ioff[g]);
   ord[p] = val[i];
   item_pos[i] = p;
-  const bool st = (i == ioff[g]) || lo != lk.lo_of(ka, kb, i - 1);
+  const bool st = (i == ioff[g]) || hi != lk.hi_of(ka, i - 1) || lo != lk.lo_of(ka, kb, i - 1);
   start_flag[i] = st;
   if (st && i != ioff[g]) flag[p] = 1;
 }
 
-// Subgroup j starts at item S[j] (S = compacted start flags). Its depth is
-// `width` past its group's common prefix; it is closed when the group held
-// copies of one sequence or its sequences ended inside the digits.
+// Subgroup j starts at item S[j] (S = compacted start flags). Head pass: its
+// depth is `width`; pivot pass: `width` past its first difference with the
+// pivot. It is closed when it holds copies of the pivot or its sequences
+// ended inside the digits.
 __global__ void large_subgroups_k(const uint32_t* __restrict__ start_flag,
                                   const uint32_t* __restrict__ start_off, uint32_t nitems,
                                   const uint32_t* __restrict__ item_pos, const uint64_t* __restrict__ ka,
                                   const uint64_t* __restrict__ kb, LargeKey lk, uint64_t last_mask,
-                                  const uint32_t* __restrict__ lcp, uint32_t* __restrict__ sub_item,
+                                  const uint32_t* __restrict__ gdepth, uint32_t* __restrict__ sub_item,
                                   uint32_t* __restrict__ seg_start, uint32_t* __restrict__ seg_depth,
                                   uint8_t* __restrict__ seg_done) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nitems) return;
   if (start_flag[i]) {
     const uint32_t j = start_off[i];
-    const uint32_t g = lk.group_of(ka, i);
-    const uint64_t lo = lk.lo_of(ka, kb, i);
-    const uint32_t d = lcp[g];
+    const uint64_t hi = lk.hi_of(ka, i), lo = lk.lo_of(ka, kb, i);
+    const uint32_t g = lk.group_of(hi);
+    bool copies = false;
+    uint32_t depth = lk.width;
+    if (lk.fd_bits) {
+      const uint64_t fdmask = (1ull << lk.fd_bits) - 1;
+      const uint32_t side = uint32_t(hi >> lk.fd_bits) & 3u;
+      const uint64_t fdkey = hi & fdmask;
+      const uint64_t rel = side == 0 ? fdkey : (fdmask - fdkey);
+      copies = side == 1;
+      depth = copies ? 0u : uint32_t(gdepth[g] + rel + lk.width);
+    }
     sub_item[j] = i;
     seg_start[j] = item_pos[i];
-    seg_depth[j] = d == kNoDiff ? 0u : d + lk.width;
-    seg_done[j] = d == kNoDiff || (lo & last_mask) == 0;
+    seg_depth[j] = depth;
+    seg_done[j] = copies || (lo & last_mask) == 0;
   }
 }
 
