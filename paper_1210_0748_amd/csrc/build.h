@@ -23,9 +23,13 @@ __global__ void validate_edges_k(const int32_t* __restrict__ src, const int32_t*
     else
       mx = uint32_t(l) > mx ? uint32_t(l) : mx;
   }
-  if (e_bits) atomicOr(err, e_bits);
+  // one atomic per wave at most: skipped when nothing new is to be reported
+  e_bits = wave_or(e_bits);
   mx = wave_max(mx);
-  if (__lane_id() == 0) atomicMax(&maxv[1], mx);
+  if (__lane_id() == 0) {
+    if (e_bits) atomicOr(err, e_bits);
+    if (mx > __hip_atomic_load(&maxv[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(&maxv[1], mx);
+  }
 }
 
 __global__ void validate_nodes_k(const int32_t* __restrict__ label, uint64_t n,
@@ -39,9 +43,12 @@ __global__ void validate_nodes_k(const int32_t* __restrict__ label, uint64_t n,
     else
       mx = uint32_t(l) > mx ? uint32_t(l) : mx;
   }
-  if (bad) atomicOr(err, bad);
+  bad = wave_or(bad);
   mx = wave_max(mx);
-  if (__lane_id() == 0) atomicMax(&maxv[0], mx);
+  if (__lane_id() == 0) {
+    if (bad) atomicOr(err, bad);
+    if (mx > __hip_atomic_load(&maxv[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(&maxv[0], mx);
+  }
 }
 
 __global__ void to_u32_iota_k(const int32_t* __restrict__ in, uint32_t* __restrict__ key,
@@ -99,10 +106,15 @@ __global__ void max_degree_k(const uint32_t* __restrict__ rowptr, uint32_t n, ui
 // values through a sort.
 constexpr uint32_t kRankTableMax = 1u << 24;
 
+// present[v] = 1 for every value v in val[0..n); a value already marked is
+// not stored again (few distinct values would otherwise take one store per
+// element on the same few addresses).
 __global__ void mark_present_k(const int32_t* __restrict__ val, uint64_t n, uint32_t* __restrict__ present) {
   for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-       i += uint64_t(gridDim.x) * blockDim.x)
-    present[uint32_t(val[i])] = 1u;
+       i += uint64_t(gridDim.x) * blockDim.x) {
+    uint32_t* p = &present[uint32_t(val[i])];
+    if (*p == 0u) *p = 1u;  // a stale 0 only costs a repeated store
+  }
 }
 
 __global__ void lookup_rank_k(const int32_t* __restrict__ val, const uint32_t* __restrict__ rank,

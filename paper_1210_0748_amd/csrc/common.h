@@ -82,6 +82,13 @@ __device__ __forceinline__ T wave_sum(T v) {
 }
 
 template <typename T>
+__device__ __forceinline__ T wave_or(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, kWave);
+  return v;
+}
+
+template <typename T>
 __device__ __forceinline__ T wave_min(T v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) {

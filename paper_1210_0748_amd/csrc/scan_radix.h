@@ -146,7 +146,10 @@ __device__ __forceinline__ uint64_t match_digit8(uint32_t d, uint64_t valid_mask
 // completes in order). Then consecutive threads copy consecutive LDS items
 // to their global positions, so each digit's run is written contiguously.
 // Stable: tile order = wave order, row order, lane order.
-template <typename K, typename V, bool kHasVal>
+// kFused: `hist` holds the raw per-tile counts (digit-major) and every
+// workgroup derives its own global offsets from them (for few tiles); else
+// it holds their exclusive scan.
+template <typename K, typename V, bool kHasVal, bool kFused>
 __global__ __launch_bounds__(kRadixNT) void radix_scatter_k(
     const K* __restrict__ kin, const V* __restrict__ vin, K* __restrict__ kout,
     V* __restrict__ vout, uint64_t n, int shift, const uint32_t* __restrict__ hist_scan,
@@ -187,7 +190,22 @@ __global__ __launch_bounds__(kRadixNT) void radix_scatter_k(
     __shared__ uint32_t shs[kRadixNW];
     uint32_t all;
     uint32_t local = block_exclusive_scan<kRadixNT>(tot, shs, &all);
-    gdelta[d] = hist_scan[uint64_t(d) * nblocks + blockIdx.x] - local;
+    uint32_t gpos;
+    if (kFused) {
+      // items of digit d in earlier tiles, and in all tiles
+      const uint32_t* h = hist_scan + uint64_t(d) * nblocks;
+      uint32_t before = 0, total = 0;
+      for (uint32_t t = 0; t < nblocks; ++t) {
+        const uint32_t c = h[t];
+        before += t < blockIdx.x ? c : 0u;
+        total += c;
+      }
+      uint32_t alld;
+      gpos = block_exclusive_scan<kRadixNT>(total, shs, &alld) + before;
+    } else {
+      gpos = hist_scan[uint64_t(d) * nblocks + blockIdx.x];
+    }
+    gdelta[d] = gpos - local;
 #pragma unroll
     for (int q = 0; q < kRadixNW; ++q) {
       const uint32_t c = wh[q][d];
@@ -219,6 +237,9 @@ __global__ __launch_bounds__(kRadixNT) void radix_scatter_k(
 }
 
 inline uint32_t radix_blocks(uint64_t n) { return ceil_div(n, kRadixTile); }
+// Up to this many tiles the scatter derives its offsets from the raw
+// histogram itself, which saves the scan's three launches per digit.
+constexpr uint32_t kRadixFusedTiles = 64;
 // Scratch (uint32 words) radix_sort needs for the histograms and their scan.
 inline size_t radix_scratch_words(uint64_t n) {
   const size_t h = size_t(radix_blocks(n)) * 256;
@@ -243,11 +264,18 @@ bool radix_sort(K* k0, V* v0, K* k1, V* v1, uint64_t n, int begin_bit, int end_b
     V* vo = flip ? v0 : v1;
     radix_hist_k<K><<<nb, kRadixNT, 0, s>>>(ki, n, shift, hist, nb);
     KB_LAUNCH_CHECK();
-    scan<uint32_t, uint32_t, false>(hist, hist, uint64_t(nb) * 256, part, s);
-    if (v0 != nullptr)
-      radix_scatter_k<K, V, true><<<nb, kRadixNT, 0, s>>>(ki, vi, ko, vo, n, shift, hist, nb);
-    else
-      radix_scatter_k<K, V, false><<<nb, kRadixNT, 0, s>>>(ki, nullptr, ko, nullptr, n, shift, hist, nb);
+    if (nb <= kRadixFusedTiles) {
+      if (v0 != nullptr)
+        radix_scatter_k<K, V, true, true><<<nb, kRadixNT, 0, s>>>(ki, vi, ko, vo, n, shift, hist, nb);
+      else
+        radix_scatter_k<K, V, false, true><<<nb, kRadixNT, 0, s>>>(ki, nullptr, ko, nullptr, n, shift, hist, nb);
+    } else {
+      scan<uint32_t, uint32_t, false>(hist, hist, uint64_t(nb) * 256, part, s);
+      if (v0 != nullptr)
+        radix_scatter_k<K, V, true, false><<<nb, kRadixNT, 0, s>>>(ki, vi, ko, vo, n, shift, hist, nb);
+      else
+        radix_scatter_k<K, V, false, false><<<nb, kRadixNT, 0, s>>>(ki, nullptr, ko, nullptr, n, shift, hist, nb);
+    }
     KB_LAUNCH_CHECK();
     flip = !flip;
   }
