@@ -5,8 +5,12 @@
 #pragma once
 
 #include "common.h"
+#include "scan_radix.h"
 
 namespace kb {
+
+// Streaming kernels keep this many elements per thread in flight.
+constexpr int kStreamUnroll = 4;
 
 // err bit 1: src/dst outside [0, N); bit 2: negative edge label;
 // bit 4: negative node label. maxv[0] = max node label, maxv[1] = max edge label.
@@ -14,14 +18,25 @@ __global__ void validate_edges_k(const int32_t* __restrict__ src, const int32_t*
                                  const int32_t* __restrict__ dst, uint64_t m, int64_t n,
                                  uint32_t* __restrict__ err, uint32_t* __restrict__ maxv) {
   uint32_t e_bits = 0, mx = 0;
-  for (uint64_t e = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < m;
-       e += uint64_t(gridDim.x) * blockDim.x) {
-    const int32_t s = src[e], d = dst[e], l = lab[e];
-    if (s < 0 || s >= n || d < 0 || d >= n) e_bits |= 1u;
-    if (l < 0)
-      e_bits |= 2u;
-    else
-      mx = uint32_t(l) > mx ? uint32_t(l) : mx;
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t b = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; b < m; b += kStreamUnroll * stride) {
+    int32_t s[kStreamUnroll], d[kStreamUnroll], l[kStreamUnroll];
+#pragma unroll
+    for (int q = 0; q < kStreamUnroll; ++q) {  // all loads in flight before any test
+      const uint64_t e = b + q * stride;
+      const bool ok = e < m;
+      s[q] = ok ? src[e] : 0;
+      d[q] = ok ? dst[e] : 0;
+      l[q] = ok ? lab[e] : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < kStreamUnroll; ++q) {
+      if (s[q] < 0 || s[q] >= n || d[q] < 0 || d[q] >= n) e_bits |= 1u;
+      if (l[q] < 0)
+        e_bits |= 2u;
+      else
+        mx = uint32_t(l[q]) > mx ? uint32_t(l[q]) : mx;
+    }
   }
   // one atomic per wave at most: skipped when nothing new is to be reported
   e_bits = wave_or(e_bits);
@@ -35,13 +50,18 @@ __global__ void validate_edges_k(const int32_t* __restrict__ src, const int32_t*
 __global__ void validate_nodes_k(const int32_t* __restrict__ label, uint64_t n,
                                  uint32_t* __restrict__ err, uint32_t* __restrict__ maxv) {
   uint32_t bad = 0, mx = 0;
-  for (uint64_t v = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < n;
-       v += uint64_t(gridDim.x) * blockDim.x) {
-    const int32_t l = label[v];
-    if (l < 0)
-      bad = 4u;
-    else
-      mx = uint32_t(l) > mx ? uint32_t(l) : mx;
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t b = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; b < n; b += kStreamUnroll * stride) {
+    int32_t l[kStreamUnroll];
+#pragma unroll
+    for (int q = 0; q < kStreamUnroll; ++q) l[q] = b + q * stride < n ? label[b + q * stride] : 0;
+#pragma unroll
+    for (int q = 0; q < kStreamUnroll; ++q) {
+      if (l[q] < 0)
+        bad = 4u;
+      else
+        mx = uint32_t(l[q]) > mx ? uint32_t(l[q]) : mx;
+    }
   }
   bad = wave_or(bad);
   mx = wave_max(mx);
@@ -49,6 +69,12 @@ __global__ void validate_nodes_k(const int32_t* __restrict__ label, uint64_t n,
     if (bad) atomicOr(err, bad);
     if (mx > __hip_atomic_load(&maxv[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(&maxv[0], mx);
   }
+}
+
+// Grid for the validation kernels: a few workgroups per CU (each wave
+// reports once).
+inline uint32_t validate_blocks(uint64_t n) {
+  return std::max<uint32_t>(1, std::min<uint32_t>(ceil_div(n, 256), 2048));
 }
 
 __global__ void to_u32_iota_k(const int32_t* __restrict__ in, uint32_t* __restrict__ key,
@@ -106,14 +132,34 @@ __global__ void max_degree_k(const uint32_t* __restrict__ rowptr, uint32_t n, ui
 // values through a sort.
 constexpr uint32_t kRankTableMax = 1u << 24;
 
-// present[v] = 1 for every value v in val[0..n); a value already marked is
-// not stored again (few distinct values would otherwise take one store per
-// element on the same few addresses).
+// present[v] = 1 for every value v in val[0..n). Values below 64 are
+// collected in a register mask per thread and stored once per wave; larger
+// ones are stored only when not yet marked (few distinct values would
+// otherwise take one store per element on the same few addresses).
 __global__ void mark_present_k(const int32_t* __restrict__ val, uint64_t n, uint32_t* __restrict__ present) {
-  for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
-       i += uint64_t(gridDim.x) * blockDim.x) {
-    uint32_t* p = &present[uint32_t(val[i])];
-    if (*p == 0u) *p = 1u;  // a stale 0 only costs a repeated store
+  uint64_t low = 0;
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t b = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; b < n; b += kStreamUnroll * stride) {
+    uint32_t v[kStreamUnroll];
+#pragma unroll
+    for (int q = 0; q < kStreamUnroll; ++q) v[q] = b + q * stride < n ? uint32_t(val[b + q * stride]) : 0u;
+#pragma unroll
+    for (int q = 0; q < kStreamUnroll; ++q) {
+      if (v[q] < 64) {
+        low |= 1ull << v[q];
+      } else {
+        uint32_t* p = &present[v[q]];
+        if (*p == 0u) *p = 1u;  // a stale 0 only costs a repeated store
+      }
+    }
+  }
+  low = wave_or(low);
+  if (__lane_id() == 0) {
+    while (low) {
+      const uint32_t b = uint32_t(__ffsll((unsigned long long)low) - 1);
+      if (present[b] == 0u) present[b] = 1u;
+      low &= low - 1;
+    }
   }
 }
 
@@ -133,30 +179,73 @@ __global__ void pack_edges_k(const int32_t* __restrict__ src, const int32_t* __r
                              const int32_t* __restrict__ dst, uint64_t m, const uint32_t* __restrict__ erank,
                              const uint32_t* __restrict__ rank_table, int dst_bits, uint32_t* __restrict__ key,
                              AdjT* __restrict__ val) {
-  for (uint64_t e = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < m;
-       e += uint64_t(gridDim.x) * blockDim.x) {
-    const uint32_t r = erank ? erank[e] : rank_table[uint32_t(lab[e])];
-    key[e] = uint32_t(src[e]);
-    val[e] = (AdjT(r) << dst_bits) | AdjT(uint32_t(dst[e]));
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t b = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; b < m; b += kStreamUnroll * stride) {
+    uint32_t s[kStreamUnroll], d[kStreamUnroll], l[kStreamUnroll];
+#pragma unroll
+    for (int q = 0; q < kStreamUnroll; ++q) {
+      const uint64_t e = b + q * stride;
+      const bool ok = e < m;
+      s[q] = ok ? uint32_t(src[e]) : 0u;
+      d[q] = ok ? uint32_t(dst[e]) : 0u;
+      l[q] = ok ? (erank ? erank[e] : uint32_t(lab[e])) : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < kStreamUnroll; ++q) {
+      const uint64_t e = b + q * stride;
+      if (e < m) {
+        const uint32_t r = erank ? l[q] : rank_table[l[q]];
+        key[e] = s[q];
+        val[e] = (AdjT(r) << dst_bits) | AdjT(d[q]);
+      }
+    }
   }
 }
 
-// Degrees from edges sorted by source: the first and one-past-last position
-// of every run of equal sources (end stays 0 for nodes without edges).
-__global__ void run_bounds_k(const uint32_t* __restrict__ skey, uint64_t m, uint32_t* __restrict__ run_start,
-                             uint32_t* __restrict__ run_end) {
-  for (uint64_t p = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < m;
-       p += uint64_t(gridDim.x) * blockDim.x) {
-    const uint32_t k = skey[p];
-    if (p == 0 || skey[p - 1] != k) run_start[k] = uint32_t(p);
-    if (p + 1 == m || skey[p + 1] != k) run_end[k] = uint32_t(p + 1);
+// Row offsets of the CSR from the edges sorted by source: rowptr[v] = first
+// position whose source is >= v (v <= n). The thread at a position where the
+// source changes from u to v writes rowptr[u+1 .. v] (nodes without edges in
+// between share the offset); position 0 and the end cover the two borders,
+// so every entry is written exactly once. Ranges longer than kRowGap are
+// queued for csr_rowptr_gaps_k instead (gaps[3i..3i+2] = first, last, value).
+constexpr uint32_t kRowGap = 64;
+__global__ void csr_rowptr_k(const uint32_t* __restrict__ skey, uint64_t m, uint32_t n,
+                             uint32_t* __restrict__ rowptr, uint32_t* __restrict__ gaps,
+                             uint32_t* __restrict__ ngaps) {
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t b = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; b <= m; b += kStreamUnroll * stride) {
+    uint32_t cur[kStreamUnroll], prev[kStreamUnroll];
+#pragma unroll
+    for (int q = 0; q < kStreamUnroll; ++q) {
+      const uint64_t p = b + q * stride;
+      cur[q] = p < m ? skey[p] : n;                   // past the end: source n
+      prev[q] = (p > 0 && p <= m) ? skey[p - 1] : 0u;  // before the start: no source
+    }
+#pragma unroll
+    for (int q = 0; q < kStreamUnroll; ++q) {
+      const uint64_t p = b + q * stride;
+      if (p > m || (p > 0 && cur[q] == prev[q])) continue;
+      const uint32_t from = p == 0 ? 0u : prev[q] + 1, to = cur[q];
+      if (to - from < kRowGap) {
+        for (uint32_t w = from; w <= to; ++w) rowptr[w] = uint32_t(p);
+      } else {
+        const uint32_t slot = atomicAdd(ngaps, 1u);
+        gaps[3 * slot] = from;
+        gaps[3 * slot + 1] = to;
+        gaps[3 * slot + 2] = uint32_t(p);
+      }
+    }
   }
 }
 
-__global__ void degree_from_runs_k(const uint32_t* __restrict__ run_start, const uint32_t* __restrict__ run_end,
-                                   uint32_t n, uint32_t* __restrict__ deg) {
-  const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < n) deg[v] = run_end[v] ? run_end[v] - run_start[v] : 0u;
+// The long ranges: one workgroup per queued range (grid-stride).
+__global__ void csr_rowptr_gaps_k(const uint32_t* __restrict__ gaps, const uint32_t* __restrict__ ngaps,
+                                  uint32_t* __restrict__ rowptr) {
+  const uint32_t ng = *ngaps;
+  for (uint32_t i = blockIdx.x; i < ng; i += gridDim.x) {
+    const uint32_t from = gaps[3 * i], to = gaps[3 * i + 1], v = gaps[3 * i + 2];
+    for (uint32_t w = from + threadIdx.x; w <= to; w += blockDim.x) rowptr[w] = v;
+  }
 }
 
 }  // namespace kb

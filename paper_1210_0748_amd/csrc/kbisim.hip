@@ -101,7 +101,8 @@ void Engine::build_adj(const int32_t* src, const int32_t* lab, const int32_t* ds
   const uint64_t N = uint64_t(n_), E = uint64_t(m_);
   rowptr_.ensure((N + 1) * sizeof(uint32_t));
   if (E) {
-    // sort the packed edges by source: CSR order without atomics
+    // sort the packed edges by source (CSR order without atomics); row
+    // offsets by binary search in the sorted sources
     DevBuf ka, kb2, vb;
     ka.ensure(E * 4);
     kb2.ensure(E * 4);
@@ -115,18 +116,16 @@ void Engine::build_adj(const int32_t* src, const int32_t* lab, const int32_t* ds
                                               radix_scratch(E), st_);
     if (f) adj_.swap(vb);
     const uint32_t* skey = f ? kb2.as<uint32_t>() : ka.as<uint32_t>();
-    DevBuf rs, re, deg;
-    rs.ensure(N * 4);
-    re.ensure(N * 4);
-    deg.ensure((N + 1) * 4);
-    KB_CHECK(hipMemsetAsync(re.p, 0, N * 4, st_));
-    KB_CHECK(hipMemsetAsync(deg.as<uint32_t>() + N, 0, 4, st_));
-    run_bounds_k<<<grid_stride_blocks(E), kNT, 0, st_>>>(skey, E, rs.as<uint32_t>(), re.as<uint32_t>());
+    // long runs of nodes without edges: at most N / kRowGap + 1 of them
+    DevBuf gaps;
+    gaps.ensure((3 * (N / kRowGap + 2) + 1) * 4);
+    uint32_t* ng = gaps.as<uint32_t>() + 3 * (N / kRowGap + 2);
+    KB_CHECK(hipMemsetAsync(ng, 0, 4, st_));
+    csr_rowptr_k<<<grid_stride_blocks(E + 1), kNT, 0, st_>>>(skey, E, uint32_t(N), rowptr_.as<uint32_t>(),
+                                                            gaps.as<uint32_t>(), ng);
     KB_LAUNCH_CHECK();
-    degree_from_runs_k<<<grid_for(N), kNT, 0, st_>>>(rs.as<uint32_t>(), re.as<uint32_t>(), uint32_t(N),
-                                                     deg.as<uint32_t>());
+    csr_rowptr_gaps_k<<<256, kNT, 0, st_>>>(gaps.as<uint32_t>(), ng, rowptr_.as<uint32_t>());
     KB_LAUNCH_CHECK();
-    scan_dev<uint32_t, uint32_t, false>(deg.as<uint32_t>(), rowptr_.as<uint32_t>(), N + 1);
     KB_CHECK(hipStreamSynchronize(st_));  // temporaries are freed on return
   } else {
     adj_.ensure(sizeof(AdjT));
@@ -195,11 +194,11 @@ void Engine::build(const int32_t* node_label, const int32_t* src, const int32_t*
   KB_CHECK(hipMemsetAsync(errb.p, 0, 4 * sizeof(uint32_t), st_));
   uint32_t* err = errb.as<uint32_t>();
   if (N) {
-    validate_nodes_k<<<grid_stride_blocks(N), kNT, 0, st_>>>(node_label, N, err, err + 1);
+    validate_nodes_k<<<validate_blocks(N), kNT, 0, st_>>>(node_label, N, err, err + 1);
     KB_LAUNCH_CHECK();
   }
   if (E) {
-    validate_edges_k<<<grid_stride_blocks(E), kNT, 0, st_>>>(src, lab, dst, E, n_, err, err + 1);
+    validate_edges_k<<<validate_blocks(E), kNT, 0, st_>>>(src, lab, dst, E, n_, err, err + 1);
     KB_LAUNCH_CHECK();
   }
   KB_CHECK(hipMemcpyAsync(hw_.p, err, 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, st_));

@@ -79,6 +79,17 @@ def test_degree_buckets():
     check_parity(g, 6)
 
 
+def test_long_runs_without_edges():
+    """Sources only at both ends of the id range: the CSR has long runs of
+    empty rows (shorter and longer than the row-offset kernel's inline range)."""
+    degs = [3] * 10 + [0] * 5000 + [2] * 7 + [0] * 40 + [5] * 4 + [0] * 70 + [1] * 3
+    g = synth.degree_graph(degs, num_node_labels=3, num_edge_labels=2, seed=11, name="sparse-rows")
+    check_parity(g, 5)
+    # all edges from the last node only
+    g2 = synth.degree_graph([0] * 3000 + [9], num_node_labels=2, num_edge_labels=2, seed=12, name="one-source")
+    check_parity(g2, 3)
+
+
 @pytest.mark.parametrize("medium_cap", [None, 64, 300, 1000])
 def test_powerlaw_mid(medium_cap):
     """Power-law graph with hubs and large blocks; the split between the
