@@ -135,7 +135,8 @@ class Engine {
   template <typename KeyT>
   void order_groups(int key_bits, const void* kv);
   template <typename KeyT>
-  void resolve_lists(SegLists& L, const void* kv);
+  void resolve_lists(SegLists& L, const void* kv, hipStream_t s);
+  hipStream_t side_stream();
   void make_lists(const uint32_t* seg_start, const uint32_t* seg_size, const uint32_t* seg_depth,
                   const uint8_t* seg_done, uint32_t nseg, SegLists& out, const uint32_t* nseg_dev = nullptr);
   void assign_round();
@@ -186,10 +187,13 @@ class Engine {
   // round scratch
   DevBuf ukey_, ucnt_, head_, cls_, fl_, first_, scanpart_, radix_, part_, bm_, bmslot_;
   DevBuf seg_start_, seg_size_, seg_depth_, seg_done_, cls_meta_;
-  SegLists lists_b_;
+  SegLists lists_b_[2];  // subgroup lists of alternate global passes
   DevBuf l_ioff_, l_fd_, l_long_, l_open_;
   DevBuf k0_, k1_, k2_, k3_, k4_, v0_, v1_, v2_, v3_, v4_, sflag_, soff2_, ipos_, sub_item_;
-  DevBuf next_l_start_[2], next_l_size_[2], next_l_depth_[2];
+
+  // the resolvers run on a second stream, overlapping the global passes
+  hipStream_t side_ = nullptr;
+  hipEvent_t ev_side_[2] = {nullptr, nullptr}, ev_main_ = nullptr, ev_join_ = nullptr;
 
   // profiling
   struct EvPair {

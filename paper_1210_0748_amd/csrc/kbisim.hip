@@ -41,6 +41,23 @@ Engine::~Engine() {
     (void)hipEventDestroy(e.a);
     (void)hipEventDestroy(e.b);
   }
+  if (side_) {
+    (void)hipStreamSynchronize(side_);
+    (void)hipStreamDestroy(side_);
+  }
+  for (hipEvent_t e : {ev_side_[0], ev_side_[1], ev_main_, ev_join_})
+    if (e) (void)hipEventDestroy(e);
+}
+
+// Second stream for the resolvers (default priority, does not synchronise
+// with the null stream) and the events that order it against the handle's.
+hipStream_t Engine::side_stream() {
+  if (!side_) {
+    KB_CHECK(hipStreamCreateWithFlags(&side_, hipStreamNonBlocking));
+    for (hipEvent_t* e : {&ev_side_[0], &ev_side_[1], &ev_main_, &ev_join_})
+      KB_CHECK(hipEventCreateWithFlags(e, hipEventDisableTiming));
+  }
+  return side_;
 }
 
 uint64_t Engine::read_word(const void* dev, int bytes) {
@@ -413,25 +430,25 @@ static void launch_lanes(const SegLists& L, int c, uint32_t* ord, uint8_t* flag,
 }
 
 template <typename KeyT>
-void Engine::resolve_lists(SegLists& L, const void* kvp) {
+void Engine::resolve_lists(SegLists& L, const void* kvp, hipStream_t st) {
   const KeyView<KeyT>& kv = *static_cast<const KeyView<KeyT>*>(kvp);
   uint32_t* ord = ord_.as<uint32_t>();
   uint8_t* flag = flag_.as<uint8_t>();
-  launch_lanes<8, KeyT>(L, 0, ord, flag, kv, st_);
-  launch_lanes<16, KeyT>(L, 1, ord, flag, kv, st_);
-  launch_lanes<32, KeyT>(L, 2, ord, flag, kv, st_);
-  launch_lanes<64, KeyT>(L, 3, ord, flag, kv, st_);
+  launch_lanes<8, KeyT>(L, 0, ord, flag, kv, st);
+  launch_lanes<16, KeyT>(L, 1, ord, flag, kv, st);
+  launch_lanes<32, KeyT>(L, 2, ord, flag, kv, st);
+  launch_lanes<64, KeyT>(L, 3, ord, flag, kv, st);
   const uint32_t nm = L.cnt[kMediumClass];
   if (nm) {
     const uint32_t o = L.off[kMediumClass];
-    resolve_k<kMediumNT, kMediumCapSmall, KeyT><<<nm, kMediumNT, 0, st_>>>(
+    resolve_k<kMediumNT, kMediumCapSmall, KeyT><<<nm, kMediumNT, 0, st>>>(
         L.start.as<uint32_t>() + o, L.size.as<uint32_t>() + o, L.depth.as<uint32_t>() + o, ord, flag, kv);
     KB_LAUNCH_CHECK();
   }
   const uint32_t nbig = L.cnt[kBigClass];
   if (nbig) {
     const uint32_t o = L.off[kBigClass];
-    resolve_k<kBigNT, kBigCap, KeyT><<<nbig, kBigNT, 0, st_>>>(
+    resolve_k<kBigNT, kBigCap, KeyT><<<nbig, kBigNT, 0, st>>>(
         L.start.as<uint32_t>() + o, L.size.as<uint32_t>() + o, L.depth.as<uint32_t>() + o, ord, flag, kv);
     KB_LAUNCH_CHECK();
   }
@@ -439,8 +456,15 @@ void Engine::resolve_lists(SegLists& L, const void* kvp) {
 
 template <typename KeyT>
 void Engine::order_groups(int key_bits, const void* kvp) {
-  // the round's segments are already classified by size (act_)
-  resolve_lists<KeyT>(act_, kvp);
+  // The round's segments are already classified by size (act_). Groups small
+  // enough for one workgroup are resolved on the side stream while the main
+  // stream runs the global passes over the large ones: they touch disjoint
+  // ranges of ord and flag, and both only read the signatures.
+  hipStream_t side = side_stream();
+  KB_CHECK(hipEventRecord(ev_main_, st_));
+  KB_CHECK(hipStreamWaitEvent(side, ev_main_, 0));
+  resolve_lists<KeyT>(act_, kvp, side);
+  bool side_pending[2] = {false, false};
 
   // Large groups: global passes. The first sorts whole classes by their
   // leading digits; later ones split every group around its pivot.
@@ -554,29 +578,29 @@ void Engine::order_groups(int key_bits, const void* kvp) {
                                                     seg_done_.as<uint8_t>());
     subgroup_sizes_k<<<grid_for(M), kNT, 0, st_>>>(sub_item_.as<uint32_t>(), ns_dev, M, seg_size_.as<uint32_t>());
     KB_LAUNCH_CHECK();
+    // subgroup lists alternate between two buffers: the one written now was
+    // last read by the resolvers of two passes ago (side stream) and by the
+    // global pass before this one (this stream)
+    SegLists& out = lists_b_[nx];
+    if (side_pending[nx]) KB_CHECK(hipStreamWaitEvent(st_, ev_side_[nx], 0));
     make_lists(seg_start_.as<uint32_t>(), seg_size_.as<uint32_t>(), seg_depth_.as<uint32_t>(),
-               seg_done_.as<uint8_t>(), M, lists_b_, ns_dev);
-    resolve_lists<KeyT>(lists_b_, kvp);
-    // the next pass works on the large subgroups (lists_b_ is reused below)
-    const int nxt = nx ^ 1;
-    nl = lists_b_.cnt[kLargeClass];
-    if (nl) {
-      const uint64_t bytes = uint64_t(nl) * 4;
-      const uint32_t o = lists_b_.off[kLargeClass];
-      for (DevBuf* b : {&next_l_start_[nxt], &next_l_size_[nxt], &next_l_depth_[nxt]}) b->ensure(bytes);
-      KB_CHECK(hipMemcpyAsync(next_l_start_[nxt].p, lists_b_.start.as<uint32_t>() + o, bytes,
-                              hipMemcpyDeviceToDevice, st_));
-      KB_CHECK(hipMemcpyAsync(next_l_size_[nxt].p, lists_b_.size.as<uint32_t>() + o, bytes,
-                              hipMemcpyDeviceToDevice, st_));
-      KB_CHECK(hipMemcpyAsync(next_l_depth_[nxt].p, lists_b_.depth.as<uint32_t>() + o, bytes,
-                              hipMemcpyDeviceToDevice, st_));
-    }
-    Ls = next_l_start_[nxt].as<uint32_t>();
-    Lz = next_l_size_[nxt].as<uint32_t>();
-    Ld = next_l_depth_[nxt].as<uint32_t>();
-    nx = nxt;
+               seg_done_.as<uint8_t>(), M, out, ns_dev);
+    KB_CHECK(hipEventRecord(ev_main_, st_));
+    KB_CHECK(hipStreamWaitEvent(side, ev_main_, 0));
+    resolve_lists<KeyT>(out, kvp, side);
+    KB_CHECK(hipEventRecord(ev_side_[nx], side));
+    side_pending[nx] = true;
+    // the next pass works on the large subgroups, read from `out`
+    nl = out.cnt[kLargeClass];
+    Ls = out.start.as<uint32_t>() + out.off[kLargeClass];
+    Lz = out.size.as<uint32_t>() + out.off[kLargeClass];
+    Ld = out.depth.as<uint32_t>() + out.off[kLargeClass];
+    nx ^= 1;
     first_pass = false;
   }
+  // everything the side stream did comes before what follows on this stream
+  KB_CHECK(hipEventRecord(ev_join_, side));
+  KB_CHECK(hipStreamWaitEvent(st_, ev_join_, 0));
 }
 
 template <typename AdjT, typename KeyT>
