@@ -178,4 +178,12 @@ __global__ void pos_ids_k(const uint32_t* __restrict__ ord, const uint32_t* __re
   if (p < n) pid[ord[p]] = int32_t(bstart[cls[p] - 1]);
 }
 
+// Narrow copy of ids below 2^16 (the first round's keys gather pId_0 for
+// every edge; a smaller table keeps more of it in cache).
+template <typename T>
+__global__ void narrow_ids_k(const int32_t* __restrict__ in, uint32_t n, T* __restrict__ out) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = T(in[i]);
+}
+
 }  // namespace kb

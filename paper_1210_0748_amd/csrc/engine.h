@@ -162,6 +162,7 @@ class Engine {
   int dst_bits_ = 1, lab_bits_ = 0;
   uint32_t n_elab_ = 0;
   uint32_t b0_ = 0;  // blocks of pId_0
+  int pid0_bytes_ = 4;  // bytes per entry of pid0_
 
   // graph
   DevBuf rowptr_, adj_, hub_toff_, hub_tmp_;

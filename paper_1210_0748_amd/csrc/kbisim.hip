@@ -276,6 +276,19 @@ void Engine::build(const int32_t* node_label, const int32_t* src, const int32_t*
     KB_LAUNCH_CHECK();
   }
   b0_ = uint32_t(B_);
+  // pId_0 in the narrowest type that holds it
+  pid0_bytes_ = 4;
+  if (N && b0_ <= (1u << 16)) {
+    DevBuf narrow;
+    pid0_bytes_ = b0_ <= 256 ? 1 : 2;
+    narrow.ensure(N * pid0_bytes_);
+    if (pid0_bytes_ == 1)
+      narrow_ids_k<uint8_t><<<grid_for(N), kNT, 0, st_>>>(pid0_.as<int32_t>(), uint32_t(N), narrow.as<uint8_t>());
+    else
+      narrow_ids_k<uint16_t><<<grid_for(N), kNT, 0, st_>>>(pid0_.as<int32_t>(), uint32_t(N), narrow.as<uint16_t>());
+    KB_LAUNCH_CHECK();
+    pid0_.swap(narrow);  // the int32 copy goes back to the pool (after the kernel, by stream order)
+  }
   counts_.assign(1, B_);
   rounds_ = 0;
   fixed_ = false;
@@ -615,7 +628,13 @@ void Engine::round_impl() {
   SigArgs<AdjT, KeyT> a;
   a.rowptr = rowptr_.as<uint32_t>();
   a.adj = adj_.as<AdjT>();
-  a.pid = first ? pid0_.as<int32_t>() : pid_.as<int32_t>();
+  if (first) {
+    a.pid = pid0_.p;
+    a.pid_bytes = pid0_bytes_;
+  } else {
+    a.pid = pid_.p;
+    a.pid_bytes = 4;
+  }
   a.ukey = ukey_.as<KeyT>();
   a.ucnt = ucnt_.as<uint32_t>();
   a.head = head_.as<uint64_t>();

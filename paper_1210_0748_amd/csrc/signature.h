@@ -37,7 +37,8 @@ template <typename AdjT, typename KeyT>
 struct SigArgs {
   const uint32_t* rowptr;  // [N+1]
   const AdjT* adj;         // [E] (label rank << dst_bits) | dst, CSR order
-  const int32_t* pid;      // [N] previous-round ids
+  const void* pid;         // [N] previous-round ids, pid_bytes (1, 2 or 4) each
+  int pid_bytes;
   KeyT* ukey;              // [E] unique keys per node at rowptr offsets
   uint32_t* ucnt;          // [N]
   uint64_t* head;          // [N] first hw digits (key + 1, 0 past the end), most significant first
@@ -49,7 +50,10 @@ struct SigArgs {
   __device__ __forceinline__ KeyT key_of(AdjT a) const {
     const uint32_t dst = uint32_t(a & ((AdjT(1) << dst_bits) - 1));
     const uint64_t lab = uint64_t(a >> dst_bits);
-    return KeyT((lab << pid_bits) | uint64_t(uint32_t(pid[dst])));
+    const uint32_t p = pid_bytes == 4   ? static_cast<const uint32_t*>(pid)[dst]
+                       : pid_bytes == 2 ? uint32_t(static_cast<const uint16_t*>(pid)[dst])
+                                        : uint32_t(static_cast<const uint8_t*>(pid)[dst]);
+    return KeyT((lab << pid_bits) | uint64_t(p));
   }
   __device__ __forceinline__ uint64_t head_of(const KeyT* k, uint32_t c) const {
     if (hdbits >= 64) return c ? uint64_t(k[0]) + 1ull : 0ull;
