@@ -133,7 +133,7 @@ class Engine {
   template <typename AdjT, typename KeyT>
   void round_impl();
   template <typename KeyT>
-  void order_groups(int key_bits, const void* kv);
+  void order_groups(const void* kv);
   template <typename KeyT>
   void resolve_lists(SegLists& L, const void* kv, hipStream_t s);
   hipStream_t side_stream();

@@ -468,7 +468,7 @@ void Engine::resolve_lists(SegLists& L, const void* kvp, hipStream_t st) {
 }
 
 template <typename KeyT>
-void Engine::order_groups(int key_bits, const void* kvp) {
+void Engine::order_groups(const void* kvp) {
   // The round's segments are already classified by size (act_). Groups small
   // enough for one workgroup are resolved on the side stream while the main
   // stream runs the global passes over the large ones: they touch disjoint
@@ -488,7 +488,7 @@ void Engine::order_groups(int key_bits, const void* kvp) {
   const uint32_t* Ld = act_.depth.as<uint32_t>() + act_.off[kLargeClass];
   int nx = 0;
   bool first_pass = true;
-  const int dbits = key_bits + 1;
+  const int dbits = kv.dbits;
   const uint64_t last_mask = dbits >= 64 ? ~0ull : ((1ull << dbits) - 1);
   const uint32_t head_w = dbits >= 64 ? 1u : uint32_t(64 / dbits);
   const int fd_bits = bits_for(maxdeg_ > 0 ? maxdeg_ : 1);  // first differences are below the longest sequence
@@ -625,6 +625,10 @@ void Engine::round_impl() {
   const uint64_t id_max = first ? (b0_ > 1 ? b0_ - 1 : 1) : (N > 1 ? N - 1 : 1);
   const int pid_bits = bits_for(id_max);
   const int key_bits = lab_bits_ + pid_bits;
+  // a digit is key + 1 (0 marks the end of a sequence): as many bits as the
+  // largest key + 1 needs
+  const uint64_t max_key = (uint64_t(n_elab_ > 0 ? n_elab_ - 1 : 0) << pid_bits) | id_max;
+  const int digit_bits = bits_for(max_key + 1);
   SigArgs<AdjT, KeyT> a;
   a.rowptr = rowptr_.as<uint32_t>();
   a.adj = adj_.as<AdjT>();
@@ -640,7 +644,7 @@ void Engine::round_impl() {
   a.head = head_.as<uint64_t>();
   a.dst_bits = dst_bits_;
   a.pid_bits = pid_bits;
-  a.hdbits = key_bits + 1;
+  a.hdbits = digit_bits;
   a.hw = a.hdbits >= 64 ? 1u : uint32_t(64 / a.hdbits);
 
   SigWork w{};
@@ -685,7 +689,7 @@ void Engine::round_impl() {
   KB_LAUNCH_CHECK();
   ev_end(ev);
 
-  KeyView<KeyT> kv{rowptr_.as<uint32_t>(), ukey_.as<KeyT>(), ucnt_.as<uint32_t>(), key_bits + 1};
+  KeyView<KeyT> kv{rowptr_.as<uint32_t>(), ukey_.as<KeyT>(), ucnt_.as<uint32_t>(), digit_bits};
   if (use_bm) {
     kv.bm = bm_.as<uint64_t>();
     kv.bmslot = bmslot_.as<uint32_t>();
@@ -693,7 +697,7 @@ void Engine::round_impl() {
     kv.bm_min_deg = kWaveMaxDeg;
   }
   const int evo = ev_begin(1);
-  order_groups<KeyT>(key_bits, &kv);
+  order_groups<KeyT>(&kv);
   ev_end(evo);
 }
 
