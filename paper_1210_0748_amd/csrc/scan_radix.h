@@ -74,14 +74,38 @@ __global__ __launch_bounds__(kScanNT) void scan_apply_k(const Tin* __restrict__ 
   }
 }
 
+// Scan of up to kScanSmall elements by one workgroup, 1024 elements per step
+// with a running carry. partial[0] receives the total.
+constexpr uint32_t kScanSmall = 8192;
+template <typename Tin, typename Tout, bool kInclusive>
+__global__ __launch_bounds__(1024) void scan_small_k(const Tin* __restrict__ in, Tout* __restrict__ out,
+                                                     uint32_t n, Tout* __restrict__ partial) {
+  __shared__ Tout sh[1024 / kWave];
+  Tout carry = 0;
+  for (uint32_t base = 0; base < n; base += 1024) {
+    const uint32_t i = base + threadIdx.x;
+    const Tout v = i < n ? Tout(in[i]) : Tout(0);
+    Tout tot;
+    const Tout ex = block_exclusive_scan<1024>(v, sh, &tot);  // reads all of the step before writes
+    if (i < n) out[i] = carry + (kInclusive ? ex + v : ex);
+    carry += tot;
+  }
+  if (threadIdx.x == 0) partial[0] = carry;
+}
+
 // Scratch words needed by scan(): one partial per tile plus the total.
 inline size_t scan_partials_count(uint64_t n) { return size_t(ceil_div(n, kScanTile)) + 1; }
 
 // out[i] = sum(in[0..i)) (or ..i] when inclusive). partial must hold
-// scan_partials_count(n) entries; partial[#tiles] receives the total.
-// `out` may alias `in`.
+// scan_partials_count(n) entries of scratch. `out` may alias `in`. Up to
+// kScanSmall elements one workgroup does it all; beyond, three kernels.
 template <typename Tin, typename Tout, bool kInclusive = false>
 void scan(const Tin* in, Tout* out, uint64_t n, Tout* partial, hipStream_t s) {
+  if (n <= kScanSmall) {
+    scan_small_k<Tin, Tout, kInclusive><<<1, 1024, 0, s>>>(in, out, uint32_t(n), partial);
+    KB_LAUNCH_CHECK();
+    return;
+  }
   const uint32_t nb = ceil_div(n, kScanTile);
   if (nb > 0) {
     scan_reduce_k<Tin, Tout><<<nb, kScanNT, 0, s>>>(in, n, partial);
