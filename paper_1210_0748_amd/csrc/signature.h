@@ -83,7 +83,11 @@ struct SigWork {
 
   __host__ __device__ uint32_t wave_units() const { return (nw + kSigNT / kWave - 1) / (kSigNT / kWave); }
   __host__ __device__ uint32_t thread_units() const { return ((dense ? n_nodes : nact) + kSigNT - 1) / kSigNT; }
-  __host__ __device__ uint32_t grid() const { return nh + nb + wave_units() + thread_units(); }
+  // bitmap rounds: one wave per block-list node, else one workgroup
+  __host__ __device__ uint32_t block_units() const {
+    return bm ? (nb + kSigNT / kWave - 1) / (kSigNT / kWave) : nb;
+  }
+  __host__ __device__ uint32_t grid() const { return nh + block_units() + wave_units() + thread_units(); }
 };
 
 template <typename KeyT>
@@ -222,6 +226,75 @@ __device__ __forceinline__ void sig_block_node(const SigArgs<AdjT, KeyT>& a, uin
 // words, then lists the set bits in ascending order (a block scan of the word
 // popcounts gives each word's first output slot). The bitmap itself is kept
 // in bm[slot * words ...] for first-difference searches, and bmslot[n] = slot.
+// Head word (first hw keys) of a key set held as a bitmap in LDS.
+template <typename AdjT, typename KeyT>
+__device__ __forceinline__ uint64_t head_of_bits(const SigArgs<AdjT, KeyT>& a, const uint32_t* bits, uint32_t nw) {
+  uint64_t v = 0;
+  uint32_t c = 0;
+  for (uint32_t j = 0; j < nw && c < a.hw; ++j) {
+    uint32_t x = bits[j];
+    while (x && c < a.hw) {
+      const uint32_t key = j * 32u + uint32_t(__ffs(x) - 1);
+      v = a.hdbits >= 64 ? uint64_t(key) + 1ull : (v << a.hdbits) | (uint64_t(key) + 1ull);
+      ++c;
+      x &= x - 1;
+    }
+  }
+  if (a.hdbits < 64 && c < a.hw) v <<= (a.hw - c) * a.hdbits;
+  return v;
+}
+
+// The same for one wave per node (out-degree <= 4096), each wave with its
+// own LDS bitmap: all 64 lanes call it with the same n; LDS operations of
+// one wave are performed in order, so no barrier is needed between its steps.
+template <typename AdjT, typename KeyT>
+__device__ __forceinline__ void sig_bitmap_wave_node(const SigArgs<AdjT, KeyT>& a, uint32_t n, const SigWork& w,
+                                                     uint32_t slot, uint32_t* bits) {
+  const uint32_t lane = __lane_id();
+  const uint32_t nw = w.words;
+  for (uint32_t i = lane; i < nw; i += kWave) bits[i] = 0;
+  __builtin_amdgcn_wave_barrier();
+  const uint32_t beg = a.rowptr[n];
+  const uint32_t deg = a.rowptr[n + 1] - beg;
+  uint32_t i = lane;
+  for (; i + 3 * kWave < deg; i += 4 * kWave) {
+    const AdjT e0 = a.adj[beg + i], e1 = a.adj[beg + i + kWave];
+    const AdjT e2 = a.adj[beg + i + 2 * kWave], e3 = a.adj[beg + i + 3 * kWave];
+    const uint32_t k0 = uint32_t(a.key_of(e0)), k1 = uint32_t(a.key_of(e1));
+    const uint32_t k2 = uint32_t(a.key_of(e2)), k3 = uint32_t(a.key_of(e3));
+    atomicOr(&bits[k0 >> 5], 1u << (k0 & 31));
+    atomicOr(&bits[k1 >> 5], 1u << (k1 & 31));
+    atomicOr(&bits[k2 >> 5], 1u << (k2 & 31));
+    atomicOr(&bits[k3 >> 5], 1u << (k3 & 31));
+  }
+  for (; i < deg; i += kWave) {
+    const uint32_t k = uint32_t(a.key_of(a.adj[beg + i]));
+    atomicOr(&bits[k >> 5], 1u << (k & 31));
+  }
+  __builtin_amdgcn_wave_barrier();
+  uint32_t* out = w.bm + size_t(slot) * nw;
+  KeyT* uk = a.ukey + beg;
+  uint32_t carry = 0;
+  for (uint32_t base = 0; base < nw; base += kWave) {
+    const uint32_t j = base + lane;
+    uint32_t v = j < nw ? bits[j] : 0u;
+    if (j < nw) out[j] = v;
+    const uint32_t pc = uint32_t(__popc(v));
+    const uint32_t incl = wave_inclusive_scan(pc);
+    uint32_t r = carry + incl - pc;
+    while (v) {
+      uk[r++] = KeyT(j * 32u + uint32_t(__ffs(v) - 1));
+      v &= v - 1;
+    }
+    carry += __shfl(incl, kWave - 1, kWave);
+  }
+  if (lane == 0) {
+    a.ucnt[n] = carry;
+    a.head[n] = head_of_bits(a, bits, nw);
+    w.bmslot[n] = slot;
+  }
+}
+
 template <typename AdjT, typename KeyT>
 __device__ __forceinline__ void sig_bitmap_node(const SigArgs<AdjT, KeyT>& a, uint32_t n, const SigWork& w,
                                                 uint32_t slot, uint32_t* bits, uint32_t* shs) {
@@ -263,10 +336,9 @@ __device__ __forceinline__ void sig_bitmap_node(const SigArgs<AdjT, KeyT>& a, ui
     }
     carry += tot;
   }
-  __syncthreads();
   if (threadIdx.x == 0) {
     a.ucnt[n] = carry;
-    a.head[n] = a.head_of(uk, carry);
+    a.head[n] = head_of_bits(a, bits, nw);
     w.bmslot[n] = slot;
   }
 }
@@ -365,7 +437,7 @@ union SigLds {
   KeyT block[kBlockMaxDeg];
   HubLds hub;
   struct {
-    uint32_t bits[kBmMaxWords];
+    uint32_t bits[kSigNT / kWave][kBmMaxWords];  // one per wave (the workgroup path uses the first)
     uint32_t shs[kSigNT / kWave];
   } bm;
 };
@@ -378,21 +450,22 @@ __global__ __launch_bounds__(kSigNT) void signature_k(SigArgs<AdjT, KeyT> a, Sig
   if (b < w.nh) {
     const uint32_t n = w.hl[b];
     if (w.bm)
-      sig_bitmap_node(a, n, w, w.nb + b, lds.bm.bits, lds.bm.shs);
+      sig_bitmap_node(a, n, w, w.nb + b, lds.bm.bits[0], lds.bm.shs);
     else
       sig_hub_node(a, n, static_cast<KeyT*>(w.hub_tmp) + w.hub_toff[n], w.key_bits, lds.hub);
     return;
   }
   b -= w.nh;
-  if (b < w.nb) {
-    const uint32_t n = w.bl[b];
-    if (w.bm)
-      sig_bitmap_node(a, n, w, b, lds.bm.bits, lds.bm.shs);
-    else
-      sig_block_node(a, n, lds.block, shc);
+  if (b < w.block_units()) {
+    if (w.bm) {
+      const uint32_t bi = b * (kSigNT / kWave) + threadIdx.x / kWave;
+      if (bi < w.nb) sig_bitmap_wave_node(a, w.bl[bi], w, bi, lds.bm.bits[threadIdx.x / kWave]);
+    } else {
+      sig_block_node(a, w.bl[b], lds.block, shc);
+    }
     return;
   }
-  b -= w.nb;
+  b -= w.block_units();
   if (b < w.wave_units()) {
     const uint32_t wi = b * (kSigNT / kWave) + threadIdx.x / kWave;
     if (wi < w.nw) sig_wave_node(a, w.wl[wi]);
