@@ -665,12 +665,22 @@ void Engine::round_impl() {
   // small key universe: workgroup nodes de-duplicate through bitmaps, which
   // the ordering then uses for first-difference searches
   const bool use_bm = key_bits <= kBmKeyBits && (w.nb + w.nh) > 0;
+  w.hub_units = 1;
+  w.hub_chunk = 0;
   if (use_bm) {
     w.words = std::max<uint32_t>((1u << key_bits) / 32u, 4u);
     bm_.ensure(uint64_t(w.nb + w.nh) * w.words * 4);
     bmslot_.ensure(std::max<uint64_t>(N, 1) * 4);
     w.bm = bm_.as<uint32_t>();
     w.bmslot = bmslot_.as<uint32_t>();
+    if (w.nh) {
+      // hubs in units of at least kHubChunk edges, at most kHubUnits per hub;
+      // their bitmaps start at zero
+      w.hub_chunk = std::max<uint32_t>(kHubChunk, ceil_div(maxdeg_, kHubUnits));
+      w.hub_units = std::max<uint32_t>(1, ceil_div(maxdeg_, w.hub_chunk));
+      if (w.hub_units > 1)
+        KB_CHECK(hipMemsetAsync(w.bm + uint64_t(w.nb) * w.words, 0, uint64_t(w.nh) * w.words * 4, st_));
+    }
   } else if (w.nh) {
     hub_tmp_.ensure(std::max<uint64_t>(hub_edges_, 1) * sizeof(KeyT));
     w.hub_tmp = hub_tmp_.p;
@@ -687,6 +697,10 @@ void Engine::round_impl() {
   const int ev = ev_begin(0);
   signature_k<AdjT, KeyT><<<w.grid(), kSigNT, 0, st_>>>(a, w);
   KB_LAUNCH_CHECK();
+  if (w.bm && w.nh && w.hub_units > 1) {
+    sig_hub_list_k<AdjT, KeyT><<<w.nh, kSigNT, 0, st_>>>(a, w);
+    KB_LAUNCH_CHECK();
+  }
   ev_end(ev);
 
   KeyView<KeyT> kv{rowptr_.as<uint32_t>(), ukey_.as<KeyT>(), ucnt_.as<uint32_t>(), digit_bits};

@@ -31,6 +31,8 @@ constexpr uint32_t kWaveMaxDeg = 64;
 constexpr uint32_t kBlockMaxDeg = 4096;
 constexpr int kSigNT = 256;
 constexpr int kBmKeyBits = 12;
+constexpr uint32_t kHubChunk = 8192;  // edges per hub unit in bitmap rounds (at least)
+constexpr uint32_t kHubUnits = 16;    // units per hub (at most)
 constexpr uint32_t kBmMaxWords = (1u << kBmKeyBits) / 32;
 
 template <typename AdjT, typename KeyT>
@@ -79,6 +81,8 @@ struct SigWork {
   uint32_t words;
   void* hub_tmp;          // radix ping-pong space of the hubs (KeyT)
   const uint32_t* hub_toff;  // [N] offset of a hub's space in hub_tmp
+  uint32_t hub_units;     // workgroups per hub (bitmap rounds; else 1)
+  uint32_t hub_chunk;     // edges per unit
   int key_bits;
 
   __host__ __device__ uint32_t wave_units() const { return (nw + kSigNT / kWave - 1) / (kSigNT / kWave); }
@@ -87,7 +91,7 @@ struct SigWork {
   __host__ __device__ uint32_t block_units() const {
     return bm ? (nb + kSigNT / kWave - 1) / (kSigNT / kWave) : nb;
   }
-  __host__ __device__ uint32_t grid() const { return nh + block_units() + wave_units() + thread_units(); }
+  __host__ __device__ uint32_t grid() const { return nh * hub_units + block_units() + wave_units() + thread_units(); }
 };
 
 template <typename KeyT>
@@ -295,17 +299,50 @@ __device__ __forceinline__ void sig_bitmap_wave_node(const SigArgs<AdjT, KeyT>& 
   }
 }
 
+// Lists the set bits of a bitmap in LDS in ascending order as the node's
+// unique keys (a block scan of the word popcounts gives each word's first
+// output slot) and writes its count and head word.
+template <typename AdjT, typename KeyT>
+__device__ __forceinline__ void list_bits(const SigArgs<AdjT, KeyT>& a, uint32_t n, const uint32_t* bits,
+                                          uint32_t nw, uint32_t* shs) {
+  KeyT* uk = a.ukey + a.rowptr[n];
+  uint32_t carry = 0;
+  for (uint32_t base = 0; base < nw; base += kSigNT) {
+    const uint32_t j = base + threadIdx.x;
+    uint32_t v = j < nw ? bits[j] : 0u;
+    uint32_t tot;
+    uint32_t r = carry + block_exclusive_scan<kSigNT>(uint32_t(__popc(v)), shs, &tot);
+    while (v) {
+      uk[r++] = KeyT(j * 32u + uint32_t(__ffs(v) - 1));
+      v &= v - 1;
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    a.ucnt[n] = carry;
+    a.head[n] = head_of_bits(a, bits, nw);
+  }
+}
+
+// Workgroup bitmap node. Hubs in bitmap rounds are split into `units` chunks
+// of hub_chunk edges, one workgroup each, which OR their LDS bitmaps into the
+// hub's bitmap in global memory (zeroed before the launch); sig_hub_list_k
+// lists the keys after the launch. With one unit the workgroup lists them.
 template <typename AdjT, typename KeyT>
 __device__ __forceinline__ void sig_bitmap_node(const SigArgs<AdjT, KeyT>& a, uint32_t n, const SigWork& w,
-                                                uint32_t slot, uint32_t* bits, uint32_t* shs) {
+                                                uint32_t slot, uint32_t unit, uint32_t units, uint32_t* bits,
+                                                uint32_t* shs) {
   const uint32_t nw = w.words;
   for (uint32_t i = threadIdx.x; i < nw; i += kSigNT) bits[i] = 0;
   __syncthreads();
   const uint32_t beg = a.rowptr[n];
   const uint32_t deg = a.rowptr[n + 1] - beg;
+  const uint32_t lo = units == 1 ? 0u : min(deg, unit * w.hub_chunk);
+  const uint32_t hi = units == 1 ? deg : min(deg, lo + w.hub_chunk);
+  if (lo >= hi) return;  // nothing of this hub in this unit (uniform over the workgroup)
   // four edges in flight per thread
-  uint32_t i = threadIdx.x;
-  for (; i + 3 * kSigNT < deg; i += 4 * kSigNT) {
+  uint32_t i = lo + threadIdx.x;
+  for (; i + 3 * kSigNT < hi; i += 4 * kSigNT) {
     const AdjT e0 = a.adj[beg + i], e1 = a.adj[beg + i + kSigNT];
     const AdjT e2 = a.adj[beg + i + 2 * kSigNT], e3 = a.adj[beg + i + 3 * kSigNT];
     const uint32_t k0 = uint32_t(a.key_of(e0)), k1 = uint32_t(a.key_of(e1));
@@ -315,32 +352,36 @@ __device__ __forceinline__ void sig_bitmap_node(const SigArgs<AdjT, KeyT>& a, ui
     atomicOr(&bits[k2 >> 5], 1u << (k2 & 31));
     atomicOr(&bits[k3 >> 5], 1u << (k3 & 31));
   }
-  for (; i < deg; i += kSigNT) {
+  for (; i < hi; i += kSigNT) {
     const uint32_t k = uint32_t(a.key_of(a.adj[beg + i]));
     atomicOr(&bits[k >> 5], 1u << (k & 31));
   }
   __syncthreads();
   uint32_t* out = w.bm + size_t(slot) * nw;
-  KeyT* uk = a.ukey + beg;
-  uint32_t carry = 0;
-  for (uint32_t base = 0; base < nw; base += kSigNT) {
-    const uint32_t j = base + threadIdx.x;
-    uint32_t v = j < nw ? bits[j] : 0u;
-    if (j < nw) out[j] = v;
-    uint32_t tot;
-    uint32_t r = carry + block_exclusive_scan<kSigNT>(uint32_t(__popc(v)), shs, &tot);
-    while (v) {
-      const uint32_t b = uint32_t(__ffs(v) - 1);
-      uk[r++] = KeyT(j * 32u + b);
-      v &= v - 1;
-    }
-    carry += tot;
+  if (units > 1) {
+    for (uint32_t j = threadIdx.x; j < nw; j += kSigNT)
+      if (bits[j]) atomicOr(&out[j], bits[j]);
+    return;
   }
-  if (threadIdx.x == 0) {
-    a.ucnt[n] = carry;
-    a.head[n] = head_of_bits(a, bits, nw);
-    w.bmslot[n] = slot;
-  }
+  for (uint32_t j = threadIdx.x; j < nw; j += kSigNT) out[j] = bits[j];
+  list_bits(a, n, bits, nw, shs);
+  if (threadIdx.x == 0) w.bmslot[n] = slot;
+}
+
+// After a launch with chunked hubs: one workgroup per hub lists the keys of
+// its merged bitmap.
+template <typename AdjT, typename KeyT>
+__global__ __launch_bounds__(kSigNT) void sig_hub_list_k(SigArgs<AdjT, KeyT> a, SigWork w) {
+  __shared__ uint32_t bits[kBmMaxWords];
+  __shared__ uint32_t shs[kSigNT / kWave];
+  const uint32_t h = blockIdx.x;
+  const uint32_t n = w.hl[h];
+  const uint32_t slot = w.nb + h;
+  const uint32_t* src = w.bm + size_t(slot) * w.words;
+  for (uint32_t j = threadIdx.x; j < w.words; j += kSigNT) bits[j] = src[j];
+  __syncthreads();
+  list_bits(a, n, bits, w.words, shs);
+  if (threadIdx.x == 0) w.bmslot[n] = slot;
 }
 
 // ---- hubs, out-degree > 4096 -------------------------------------------------------
@@ -447,15 +488,16 @@ __global__ __launch_bounds__(kSigNT) void signature_k(SigArgs<AdjT, KeyT> a, Sig
   __shared__ SigLds<KeyT> lds;
   __shared__ uint32_t shc[kSigNT / kWave];
   uint32_t b = blockIdx.x;
-  if (b < w.nh) {
-    const uint32_t n = w.hl[b];
+  if (b < w.nh * w.hub_units) {
+    const uint32_t h = b / w.hub_units;
+    const uint32_t n = w.hl[h];
     if (w.bm)
-      sig_bitmap_node(a, n, w, w.nb + b, lds.bm.bits[0], lds.bm.shs);
+      sig_bitmap_node(a, n, w, w.nb + h, b % w.hub_units, w.hub_units, lds.bm.bits[0], lds.bm.shs);
     else
       sig_hub_node(a, n, static_cast<KeyT*>(w.hub_tmp) + w.hub_toff[n], w.key_bits, lds.hub);
     return;
   }
-  b -= w.nh;
+  b -= w.nh * w.hub_units;
   if (b < w.block_units()) {
     if (w.bm) {
       const uint32_t bi = b * (kSigNT / kWave) + threadIdx.x / kWave;
