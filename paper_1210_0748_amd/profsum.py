@@ -3,8 +3,13 @@
   python -m paper_1210_0748_amd.profsum stats   <kernel_stats.csv> [--top N]
   python -m paper_1210_0748_amd.profsum rounds  <kernel_trace.csv>
   python -m paper_1210_0748_amd.profsum counters <counter_collection.csv> --kernel SUBSTR
+  python -m paper_1210_0748_amd.profsum traffic <fetch.csv> --write W.csv --cal-fetch CF.csv
+         --cal-write CW.csv --kernel SUBSTR --name NAME --out profiles/traffic.json
 
-`stats` lists kernels by total time; `rounds` splits a kernel trace into
+`traffic` turns FETCH_SIZE / WRITE_SIZE runs of a command and of the 1 GiB
+copy probe (paper_1210_0748_amd.copyprobe) into bytes per launch of one
+kernel, stamped with a digest of the kernel sources (bench.py reports the
+figure only while the digest matches). `stats` lists kernels by total time; `rounds` splits a kernel trace into
 refinement rounds (at each launch of the thread-bucket signature kernel) and
 reports busy time, span and launch counts; `counters` averages the PMC
 values (e.g. FETCH_SIZE, WRITE_SIZE in KiB) per dispatch of the kernels whose
@@ -60,19 +65,76 @@ def cmd_counters(path, kernel):
         print("%-14s dispatches %5d  mean %14.1f  max %14.1f" % (name, len(vals), sum(vals) / len(vals), max(vals)))
 
 
+def _values(path, kernel):
+    rows = list(csv.DictReader(open(path)))
+    return [float(r["Counter_Value"]) for r in rows if kernel in r.get("Kernel_Name", "")]
+
+
+def source_digest():
+    import hashlib
+    import os
+    d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def cmd_traffic(a):
+    import json
+    import os
+    copy_bytes = float(1 << 30)
+    # the copy probe moves 1 GiB each way; counters are in KiB
+    cal_f = max(_values(a.cal_fetch, "copyBuffer") or _values(a.cal_fetch, ""))
+    cal_w = max(_values(a.cal_write, "copyBuffer") or _values(a.cal_write, ""))
+    fscale = copy_bytes / (cal_f * 1024.0)
+    wscale = copy_bytes / (cal_w * 1024.0)
+    f = _values(a.csv, a.kernel)
+    w = _values(a.write, a.kernel)
+    fb = sum(f) * 1024.0 * fscale / len(f)
+    wb = sum(w) * 1024.0 * wscale / len(w)
+    t = {}
+    if os.path.exists(a.out):
+        with open(a.out) as fh:
+            t = json.load(fh)
+    if t.get("source_digest") != source_digest():
+        t = {"kernels": {}}
+    t["source_digest"] = source_digest()
+    t["fetch_scale"] = fscale
+    t["write_scale"] = wscale
+    t["note"] = ("rocprofv3 FETCH_SIZE / WRITE_SIZE (KiB per dispatch), averaged over the dispatches of "
+                 "the kernel, scaled by the readings of a 1 GiB device copy")
+    t.setdefault("kernels", {})[a.name] = {
+        "kernel": a.kernel, "launches": len(f),
+        "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb, "bytes_per_launch": fb + wb,
+        "fetch_bytes_per_dispatch": [x * 1024.0 * fscale for x in f],
+        "write_bytes_per_dispatch": [x * 1024.0 * wscale for x in w]}
+    with open(a.out, "w") as fh:
+        json.dump(t, fh, indent=1)
+    print("%s: %.3g B fetched + %.3g B written per launch (%d launches)" % (a.name, fb, wb, len(f)))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["stats", "rounds", "counters"])
+    ap.add_argument("mode", choices=["stats", "rounds", "counters", "traffic"])
     ap.add_argument("csv")
     ap.add_argument("--top", type=int, default=25)
     ap.add_argument("--kernel", default="")
+    ap.add_argument("--write", default=None)
+    ap.add_argument("--cal-fetch", default=None)
+    ap.add_argument("--cal-write", default=None)
+    ap.add_argument("--name", default=None)
+    ap.add_argument("--out", default="profiles/traffic.json")
     a = ap.parse_args(argv)
     if a.mode == "stats":
         cmd_stats(a.csv, a.top)
     elif a.mode == "rounds":
         cmd_rounds(a.csv)
-    else:
+    elif a.mode == "counters":
         cmd_counters(a.csv, a.kernel)
+    else:
+        cmd_traffic(a)
 
 
 if __name__ == "__main__":
