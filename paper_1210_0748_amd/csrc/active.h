@@ -136,19 +136,27 @@ __global__ void assign_pos_k(const uint32_t* __restrict__ apos, const uint32_t* 
 }
 
 // Classes of the active positions with two or more members become the next
-// round's segments (class c spans items first[c] .. first[c+1]).
+// round's segments (class c spans items first[c] .. first[c+1]), except
+// classes of nodes without out-edges: all members of a class share this
+// round's signature, so when the first member's is empty they all have no
+// edges, their signatures stay empty in every later round, and the class
+// never splits.
 struct NextSegOf {
   const uint32_t* first;
   const uint32_t* nclass;  // device count of classes
   uint32_t m;
   uint32_t medium_cap, big_cap;
+  const uint32_t* apos;
+  const uint32_t* ord;
+  const uint32_t* ucnt;
   __device__ __forceinline__ uint32_t size(uint32_t c) const {
     const uint32_t C = *nclass;
     return (c + 1 < C ? first[c + 1] : m) - first[c];
   }
   __device__ __forceinline__ int operator()(uint32_t c) const {
     const uint32_t z = size(c);
-    return z >= 2 ? seg_class(z, medium_cap, big_cap) : -1;
+    if (z < 2 || ucnt[ord[apos[first[c]]]] == 0) return -1;
+    return seg_class(z, medium_cap, big_cap);
   }
 };
 struct NextSegWrite {

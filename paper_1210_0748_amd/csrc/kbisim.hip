@@ -396,7 +396,8 @@ void Engine::assign_round() {
   KB_LAUNCH_CHECK();
   const uint32_t med = std::min(medium_cap(), kMediumCapSmall), big = medium_cap();
   KB_CHECK(hipMemsetAsync(act_.size.p, 0, (uint64_t(M) + 1) * 4, st_));
-  NextSegOf of{first_.as<uint32_t>(), info + kInfoClasses, M, med, big};
+  NextSegOf of{first_.as<uint32_t>(), info + kInfoClasses, M, med, big, apos_.as<uint32_t>(), ord_.as<uint32_t>(),
+               ucnt_.as<uint32_t>()};
   compact<kSegClasses>(of, NextSegWrite{of, apos_.as<uint32_t>(), act_.start.as<uint32_t>(),
                                         act_.size.as<uint32_t>(), act_.depth.as<uint32_t>()},
                        M, info + kInfoClasses, compact_scratch(compact_part_words<kSegClasses>(M)),
