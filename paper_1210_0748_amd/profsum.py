@@ -10,7 +10,7 @@
 copy probe (paper_1210_0748_amd.copyprobe) into bytes per launch of one
 kernel, stamped with a digest of the kernel sources (bench.py reports the
 figure only while the digest matches). `stats` lists kernels by total time; `rounds` splits a kernel trace into
-refinement rounds (at each launch of the thread-bucket signature kernel) and
+refinement rounds (at each launch of the signature kernel) and
 reports busy time, span and launch counts; `counters` averages the PMC
 values (e.g. FETCH_SIZE, WRITE_SIZE in KiB) per dispatch of the kernels whose
 name contains SUBSTR.
@@ -46,7 +46,7 @@ def cmd_stats(path, top):
 def cmd_rounds(path):
     rows = list(csv.DictReader(open(path)))
     rows.sort(key=lambda r: int(r["Start_Timestamp"]))
-    marks = [i for i, r in enumerate(rows) if "sig_thread_k" in r["Kernel_Name"] or "signature_k" in r["Kernel_Name"]]
+    marks = [i for i, r in enumerate(rows) if "signature_k" in r["Kernel_Name"]]
     print("%5s %10s %10s %10s" % ("round", "launches", "busy_ms", "span_ms"))
     for j, (a, b) in enumerate(zip(marks, marks[1:] + [len(rows)])):
         seg = rows[a:b]
