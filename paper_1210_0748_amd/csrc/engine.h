@@ -135,7 +135,7 @@ class Engine {
   template <typename KeyT>
   void order_groups(const void* kv);
   template <typename KeyT>
-  void resolve_lists(SegLists& L, const void* kv, hipStream_t s);
+  void resolve_lists(SegLists& L, const void* kv, hipStream_t s_small, hipStream_t s_big);
   hipStream_t side_stream();
   void make_lists(const uint32_t* seg_start, const uint32_t* seg_size, const uint32_t* seg_depth,
                   const uint8_t* seg_done, uint32_t nseg, SegLists& out, const uint32_t* nseg_dev = nullptr);
@@ -192,9 +192,12 @@ class Engine {
   DevBuf l_ioff_, l_fd_, l_long_, l_open_;
   DevBuf k0_, k1_, k2_, k3_, k4_, v0_, v1_, v2_, v3_, v4_, sflag_, soff2_, ipos_, sub_item_;
 
-  // the resolvers run on a second stream, overlapping the global passes
-  hipStream_t side_ = nullptr;
-  hipEvent_t ev_side_[2] = {nullptr, nullptr}, ev_main_ = nullptr, ev_join_ = nullptr;
+  // the resolvers run on two more streams, overlapping the global passes and
+  // each other: groups of one workgroup of 1024 threads on side_big_, all
+  // smaller ones on side_
+  hipStream_t side_ = nullptr, side_big_ = nullptr;
+  hipEvent_t ev_side_[2] = {nullptr, nullptr}, ev_big_[2] = {nullptr, nullptr};
+  hipEvent_t ev_main_ = nullptr, ev_join_ = nullptr, ev_join_big_ = nullptr;
 
   // profiling
   struct EvPair {

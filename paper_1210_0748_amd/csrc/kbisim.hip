@@ -41,20 +41,22 @@ Engine::~Engine() {
     (void)hipEventDestroy(e.a);
     (void)hipEventDestroy(e.b);
   }
-  if (side_) {
-    (void)hipStreamSynchronize(side_);
-    (void)hipStreamDestroy(side_);
+  for (hipStream_t q : {side_, side_big_}) {
+    if (!q) continue;
+    (void)hipStreamSynchronize(q);
+    (void)hipStreamDestroy(q);
   }
-  for (hipEvent_t e : {ev_side_[0], ev_side_[1], ev_main_, ev_join_})
+  for (hipEvent_t e : {ev_side_[0], ev_side_[1], ev_big_[0], ev_big_[1], ev_main_, ev_join_, ev_join_big_})
     if (e) (void)hipEventDestroy(e);
 }
 
-// Second stream for the resolvers (default priority, does not synchronise
-// with the null stream) and the events that order it against the handle's.
+// Streams for the resolvers (default priority, not synchronising with the
+// null stream) and the events that order them against the handle's.
 hipStream_t Engine::side_stream() {
   if (!side_) {
     KB_CHECK(hipStreamCreateWithFlags(&side_, hipStreamNonBlocking));
-    for (hipEvent_t* e : {&ev_side_[0], &ev_side_[1], &ev_main_, &ev_join_})
+    KB_CHECK(hipStreamCreateWithFlags(&side_big_, hipStreamNonBlocking));
+    for (hipEvent_t* e : {&ev_side_[0], &ev_side_[1], &ev_big_[0], &ev_big_[1], &ev_main_, &ev_join_, &ev_join_big_})
       KB_CHECK(hipEventCreateWithFlags(e, hipEventDisableTiming));
   }
   return side_;
@@ -444,7 +446,7 @@ static void launch_lanes(const SegLists& L, int c, uint32_t* ord, uint8_t* flag,
 }
 
 template <typename KeyT>
-void Engine::resolve_lists(SegLists& L, const void* kvp, hipStream_t st) {
+void Engine::resolve_lists(SegLists& L, const void* kvp, hipStream_t st, hipStream_t st_big) {
   const KeyView<KeyT>& kv = *static_cast<const KeyView<KeyT>*>(kvp);
   uint32_t* ord = ord_.as<uint32_t>();
   uint8_t* flag = flag_.as<uint8_t>();
@@ -462,7 +464,7 @@ void Engine::resolve_lists(SegLists& L, const void* kvp, hipStream_t st) {
   const uint32_t nbig = L.cnt[kBigClass];
   if (nbig) {
     const uint32_t o = L.off[kBigClass];
-    resolve_k<kBigNT, kBigCap, KeyT><<<nbig, kBigNT, 0, st>>>(
+    resolve_k<kBigNT, kBigCap, KeyT><<<nbig, kBigNT, 0, st_big>>>(
         L.start.as<uint32_t>() + o, L.size.as<uint32_t>() + o, L.depth.as<uint32_t>() + o, ord, flag, kv);
     KB_LAUNCH_CHECK();
   }
@@ -475,9 +477,11 @@ void Engine::order_groups(const void* kvp) {
   // stream runs the global passes over the large ones: they touch disjoint
   // ranges of ord and flag, and both only read the signatures.
   hipStream_t side = side_stream();
+  hipStream_t big = side_big_;
   KB_CHECK(hipEventRecord(ev_main_, st_));
   KB_CHECK(hipStreamWaitEvent(side, ev_main_, 0));
-  resolve_lists<KeyT>(act_, kvp, side);
+  KB_CHECK(hipStreamWaitEvent(big, ev_main_, 0));
+  resolve_lists<KeyT>(act_, kvp, side, big);
   bool side_pending[2] = {false, false};
 
   // Large groups: global passes. The first sorts whole classes by their
@@ -596,13 +600,18 @@ void Engine::order_groups(const void* kvp) {
     // last read by the resolvers of two passes ago (side stream) and by the
     // global pass before this one (this stream)
     SegLists& out = lists_b_[nx];
-    if (side_pending[nx]) KB_CHECK(hipStreamWaitEvent(st_, ev_side_[nx], 0));
+    if (side_pending[nx]) {
+      KB_CHECK(hipStreamWaitEvent(st_, ev_side_[nx], 0));
+      KB_CHECK(hipStreamWaitEvent(st_, ev_big_[nx], 0));
+    }
     make_lists(seg_start_.as<uint32_t>(), seg_size_.as<uint32_t>(), seg_depth_.as<uint32_t>(),
                seg_done_.as<uint8_t>(), M, out, ns_dev);
     KB_CHECK(hipEventRecord(ev_main_, st_));
     KB_CHECK(hipStreamWaitEvent(side, ev_main_, 0));
-    resolve_lists<KeyT>(out, kvp, side);
+    KB_CHECK(hipStreamWaitEvent(big, ev_main_, 0));
+    resolve_lists<KeyT>(out, kvp, side, big);
     KB_CHECK(hipEventRecord(ev_side_[nx], side));
+    KB_CHECK(hipEventRecord(ev_big_[nx], big));
     side_pending[nx] = true;
     // the next pass works on the large subgroups, read from `out`
     nl = out.cnt[kLargeClass];
@@ -612,9 +621,11 @@ void Engine::order_groups(const void* kvp) {
     nx ^= 1;
     first_pass = false;
   }
-  // everything the side stream did comes before what follows on this stream
+  // everything the resolver streams did comes before what follows on this one
   KB_CHECK(hipEventRecord(ev_join_, side));
+  KB_CHECK(hipEventRecord(ev_join_big_, big));
   KB_CHECK(hipStreamWaitEvent(st_, ev_join_, 0));
+  KB_CHECK(hipStreamWaitEvent(st_, ev_join_big_, 0));
 }
 
 template <typename AdjT, typename KeyT>
