@@ -12,44 +12,118 @@ namespace kb {
 // Streaming kernels keep this many elements per thread in flight.
 constexpr int kStreamUnroll = 4;
 
-// err bit 1: src/dst outside [0, N); bit 2: negative edge label;
-// bit 4: negative node label. maxv[0] = max node label, maxv[1] = max edge label.
-__global__ void validate_edges_k(const int32_t* __restrict__ src, const int32_t* __restrict__ lab,
-                                 const int32_t* __restrict__ dst, uint64_t m, int64_t n,
-                                 uint32_t* __restrict__ err, uint32_t* __restrict__ maxv) {
-  uint32_t e_bits = 0, mx = 0;
-  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
-  for (uint64_t b = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; b < m; b += kStreamUnroll * stride) {
-    int32_t s[kStreamUnroll], d[kStreamUnroll], l[kStreamUnroll];
+// Presence of the label values below kMaskLabels, as four 64-bit words held
+// in registers (never indexed dynamically, so they stay out of scratch).
+constexpr uint32_t kMaskLabels = 256;
+struct LabelMask {
+  uint64_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
+  __device__ __forceinline__ void add(uint32_t v) {
+    const uint64_t bit = 1ull << (v & 63u);
+    const uint32_t q = v >> 6;
+    w0 |= q == 0 ? bit : 0ull;
+    w1 |= q == 1 ? bit : 0ull;
+    w2 |= q == 2 ? bit : 0ull;
+    w3 |= q == 3 ? bit : 0ull;
+  }
+  // OR over the wave; lane 0 then adds what is new to out[0..3]
+  __device__ __forceinline__ void publish(unsigned long long* out) {
+    const uint64_t v[4] = {wave_or(w0), wave_or(w1), wave_or(w2), wave_or(w3)};
+    if (__lane_id() != 0) return;
 #pragma unroll
-    for (int q = 0; q < kStreamUnroll; ++q) {  // all loads in flight before any test
-      const uint64_t e = b + q * stride;
-      const bool ok = e < m;
-      s[q] = ok ? src[e] : 0;
-      d[q] = ok ? dst[e] : 0;
-      l[q] = ok ? lab[e] : 0;
-    }
-#pragma unroll
-    for (int q = 0; q < kStreamUnroll; ++q) {
-      if (s[q] < 0 || s[q] >= n || d[q] < 0 || d[q] >= n) e_bits |= 1u;
-      if (l[q] < 0)
-        e_bits |= 2u;
-      else
-        mx = uint32_t(l[q]) > mx ? uint32_t(l[q]) : mx;
+    for (int q = 0; q < 4; ++q) {
+      const uint64_t cur = __hip_atomic_load(&out[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (v[q] & ~cur) atomicOr(&out[q], (unsigned long long)v[q]);
     }
   }
-  // one atomic per wave at most: skipped when nothing new is to be reported
+};
+
+// Errors and label maxima of one wave, reported with one atomic each at
+// most (skipped when nothing new is to be reported).
+__device__ __forceinline__ void report(uint32_t e_bits, uint32_t mx, uint32_t* err, uint32_t* maxv) {
   e_bits = wave_or(e_bits);
   mx = wave_max(mx);
   if (__lane_id() == 0) {
     if (e_bits) atomicOr(err, e_bits);
-    if (mx > __hip_atomic_load(&maxv[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(&maxv[1], mx);
+    if (mx > __hip_atomic_load(maxv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(maxv, mx);
   }
 }
 
-__global__ void validate_nodes_k(const int32_t* __restrict__ label, uint64_t n,
-                                 uint32_t* __restrict__ err, uint32_t* __restrict__ maxv) {
+// One pass over the edge table (src, lab, dst), grid-stride over the radix
+// tiles of the edges in input order:
+//   err bit 1: src/dst outside [0, N); bit 2: negative edge label;
+//   *maxv = largest edge label; lmask = presence of edge labels < 256;
+//   hist[d * nb + t] = edges of tile t whose source has lowest byte d (the
+//   first pass of the sort by source).
+__global__ __launch_bounds__(kRadixNT) void edge_scan_k(const int32_t* __restrict__ src,
+                                                        const int32_t* __restrict__ lab,
+                                                        const int32_t* __restrict__ dst, uint64_t m, int64_t n,
+                                                        uint32_t* __restrict__ err, uint32_t* __restrict__ maxv,
+                                                        unsigned long long* __restrict__ lmask,
+                                                        uint32_t* __restrict__ hist, uint32_t nb) {
+  __shared__ uint32_t cnt[kRadixNW][256];
+  const int w = threadIdx.x / kWave;
+  uint32_t e_bits = 0, mx = 0;
+  LabelMask mk;
+  const bool vec = ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(lab) |
+                     reinterpret_cast<uintptr_t>(dst)) & 15u) == 0;
+  auto check = [&](int32_t s, int32_t l, int32_t d) {
+    if (s < 0 || s >= n || d < 0 || d >= n) e_bits |= 1u;
+    if (l < 0) {
+      e_bits |= 2u;
+    } else {
+      mx = uint32_t(l) > mx ? uint32_t(l) : mx;
+      if (uint32_t(l) < kMaskLabels) mk.add(uint32_t(l));
+    }
+    atomicAdd(&cnt[w][uint32_t(s) & 255u], 1u);
+  };
+  for (uint32_t t = blockIdx.x; t < nb; t += gridDim.x) {
+    for (int j = threadIdx.x; j < kRadixNW * 256; j += kRadixNT) (&cnt[0][0])[j] = 0;
+    __syncthreads();
+    const uint64_t base = uint64_t(t) * kRadixTile;
+    if (vec && base + kRadixTile <= m) {
+      constexpr int kVecs = kRadixIPT / 4;
+      const uint4* vs = reinterpret_cast<const uint4*>(src + base);
+      const uint4* vl = reinterpret_cast<const uint4*>(lab + base);
+      const uint4* vd = reinterpret_cast<const uint4*>(dst + base);
+      uint4 rs[kVecs], rl[kVecs], rd[kVecs];
+#pragma unroll
+      for (int i = 0; i < kVecs; ++i) {
+        rs[i] = vs[i * kRadixNT + threadIdx.x];
+        rl[i] = vl[i * kRadixNT + threadIdx.x];
+        rd[i] = vd[i * kRadixNT + threadIdx.x];
+      }
+#pragma unroll
+      for (int i = 0; i < kVecs; ++i) {
+        check(int32_t(rs[i].x), int32_t(rl[i].x), int32_t(rd[i].x));
+        check(int32_t(rs[i].y), int32_t(rl[i].y), int32_t(rd[i].y));
+        check(int32_t(rs[i].z), int32_t(rl[i].z), int32_t(rd[i].z));
+        check(int32_t(rs[i].w), int32_t(rl[i].w), int32_t(rd[i].w));
+      }
+    } else {
+      for (int i = 0; i < kRadixIPT; ++i) {
+        const uint64_t e = base + uint64_t(i) * kRadixNT + threadIdx.x;
+        if (e < m) check(src[e], lab[e], dst[e]);
+      }
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < 256; d += kRadixNT) {
+      uint32_t c = 0;
+#pragma unroll
+      for (int q = 0; q < kRadixNW; ++q) c += cnt[q][d];
+      hist[uint64_t(d) * nb + t] = c;
+    }
+    __syncthreads();
+  }
+  report(e_bits, mx, err, maxv);
+  mk.publish(lmask);
+}
+
+// err bit 4: negative node label; *maxv = largest node label; lmask =
+// presence of node labels < 256.
+__global__ void validate_nodes_k(const int32_t* __restrict__ label, uint64_t n, uint32_t* __restrict__ err,
+                                 uint32_t* __restrict__ maxv, unsigned long long* __restrict__ lmask) {
   uint32_t bad = 0, mx = 0;
+  LabelMask mk;
   const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
   for (uint64_t b = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; b < n; b += kStreamUnroll * stride) {
     int32_t l[kStreamUnroll];
@@ -57,17 +131,34 @@ __global__ void validate_nodes_k(const int32_t* __restrict__ label, uint64_t n,
     for (int q = 0; q < kStreamUnroll; ++q) l[q] = b + q * stride < n ? label[b + q * stride] : 0;
 #pragma unroll
     for (int q = 0; q < kStreamUnroll; ++q) {
-      if (l[q] < 0)
+      if (b + q * stride >= n) continue;
+      if (l[q] < 0) {
         bad = 4u;
-      else
+      } else {
         mx = uint32_t(l[q]) > mx ? uint32_t(l[q]) : mx;
+        if (uint32_t(l[q]) < kMaskLabels) mk.add(uint32_t(l[q]));
+      }
     }
   }
-  bad = wave_or(bad);
-  mx = wave_max(mx);
-  if (__lane_id() == 0) {
-    if (bad) atomicOr(err, bad);
-    if (mx > __hip_atomic_load(&maxv[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(&maxv[0], mx);
+  report(bad, mx, err, maxv);
+  mk.publish(lmask);
+}
+
+// Rank table of label values below kMaskLabels from their presence mask:
+// table[v] = number of present values below v, for v < t (t = max + 2, so
+// table[t - 1] is the number of distinct values).
+__global__ void mask_ranks_k(const unsigned long long* __restrict__ lmask, uint32_t t, uint32_t* __restrict__ table) {
+  for (uint32_t v = threadIdx.x; v < t; v += blockDim.x) {
+    uint32_t c = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < 4; ++q) {
+      const uint32_t lo = q * 64u;
+      if (v >= lo + 64u)
+        c += uint32_t(__popcll(lmask[q]));
+      else if (v > lo)
+        c += uint32_t(__popcll(lmask[q] & ((1ull << (v - lo)) - 1ull)));
+    }
+    table[v] = c;
   }
 }
 
@@ -171,35 +262,31 @@ __global__ void lookup_rank_k(const int32_t* __restrict__ val, const uint32_t* _
   if (out_idx) out_idx[i] = i;
 }
 
-// Sort input for the CSR build: key = source node, value = packed
-// (label rank << dst_bits) | dst. `erank` (per edge) or `rank_table` (per
-// label value) gives the label rank.
+// Items of the first pass of the sort by source, read from the edge table
+// itself: key = source node, value = packed (label rank << dst_bits) | dst.
+// `erank` (per edge) or `rank_table` (per label value) gives the label rank.
 template <typename AdjT>
-__global__ void pack_edges_k(const int32_t* __restrict__ src, const int32_t* __restrict__ lab,
-                             const int32_t* __restrict__ dst, uint64_t m, const uint32_t* __restrict__ erank,
-                             const uint32_t* __restrict__ rank_table, int dst_bits, uint32_t* __restrict__ key,
-                             AdjT* __restrict__ val) {
-  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
-  for (uint64_t b = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; b < m; b += kStreamUnroll * stride) {
-    uint32_t s[kStreamUnroll], d[kStreamUnroll], l[kStreamUnroll];
-#pragma unroll
-    for (int q = 0; q < kStreamUnroll; ++q) {
-      const uint64_t e = b + q * stride;
-      const bool ok = e < m;
-      s[q] = ok ? uint32_t(src[e]) : 0u;
-      d[q] = ok ? uint32_t(dst[e]) : 0u;
-      l[q] = ok ? (erank ? erank[e] : uint32_t(lab[e])) : 0u;
-    }
-#pragma unroll
-    for (int q = 0; q < kStreamUnroll; ++q) {
-      const uint64_t e = b + q * stride;
-      if (e < m) {
-        const uint32_t r = erank ? l[q] : rank_table[l[q]];
-        key[e] = s[q];
-        val[e] = (AdjT(r) << dst_bits) | AdjT(d[q]);
-      }
-    }
+struct EdgePackLoad {
+  const int32_t* __restrict__ src;
+  const int32_t* __restrict__ lab;
+  const int32_t* __restrict__ dst;
+  const uint32_t* __restrict__ erank;
+  const uint32_t* __restrict__ rank_table;
+  int dst_bits;
+  __device__ __forceinline__ void operator()(uint64_t e, uint32_t& key, AdjT& val) const {
+    const uint32_t r = erank ? erank[e] : rank_table[uint32_t(lab[e])];
+    key = uint32_t(src[e]);
+    val = (AdjT(r) << dst_bits) | AdjT(uint32_t(dst[e]));
   }
+};
+
+// First pass of the sort by source straight from the edge table (the
+// per-tile counts come from edge_scan_k).
+template <typename AdjT, bool kFused>
+__global__ __launch_bounds__(kRadixNT) void pack_scatter_k(EdgePackLoad<AdjT> load, uint32_t* __restrict__ kout,
+                                                           AdjT* __restrict__ vout, uint64_t m,
+                                                           const uint32_t* __restrict__ hist, uint32_t nb) {
+  radix_scatter_tile<uint32_t, AdjT, true, kFused>(load, kout, vout, m, 0, hist, nb);
 }
 
 // Row offsets of the CSR from the edges sorted by source: rowptr[v] = first

@@ -128,8 +128,9 @@ class Engine {
  private:
   template <typename AdjT>
   void build_adj(const int32_t* src, const int32_t* lab, const int32_t* dst, const uint32_t* erank,
-                 const uint32_t* rank_table);
-  uint32_t label_ranks(const int32_t* val, uint64_t n, uint32_t maxv, DevBuf& rank_table, DevBuf& rank);
+                 const uint32_t* rank_table, uint32_t* hist0);
+  uint32_t label_ranks(const int32_t* val, uint64_t n, uint32_t maxv, const unsigned long long* mask_dev,
+                       const uint64_t* mask_host, DevBuf& rank_table, DevBuf& rank);
   template <typename AdjT, typename KeyT>
   void round_impl();
   template <typename KeyT>

@@ -116,22 +116,30 @@ void Engine::ev_collect() {
 
 template <typename AdjT>
 void Engine::build_adj(const int32_t* src, const int32_t* lab, const int32_t* dst, const uint32_t* erank,
-                       const uint32_t* rank_table) {
+                       const uint32_t* rank_table, uint32_t* hist0) {
   const uint64_t N = uint64_t(n_), E = uint64_t(m_);
   rowptr_.ensure((N + 1) * sizeof(uint32_t));
   if (E) {
     // sort the packed edges by source (CSR order without atomics); row
-    // offsets by binary search in the sorted sources
+    // offsets by binary search in the sorted sources. The first pass reads
+    // the edge table itself and packs while it scatters; its per-tile counts
+    // came with the validation pass.
     DevBuf ka, kb2, vb;
     ka.ensure(E * 4);
     kb2.ensure(E * 4);
     adj_.ensure(E * sizeof(AdjT));
     vb.ensure(E * sizeof(AdjT));
-    pack_edges_k<AdjT><<<grid_stride_blocks(E), kNT, 0, st_>>>(src, lab, dst, E, erank, rank_table, dst_bits_,
-                                                             ka.as<uint32_t>(), adj_.as<AdjT>());
+    const uint32_t nb = radix_blocks(E);
+    const EdgePackLoad<AdjT> load{src, lab, dst, erank, rank_table, dst_bits_};
+    if (nb <= kRadixFusedTiles) {
+      pack_scatter_k<AdjT, true><<<nb, kRadixNT, 0, st_>>>(load, ka.as<uint32_t>(), adj_.as<AdjT>(), E, hist0, nb);
+    } else {
+      scan_dev<uint32_t, uint32_t, false>(hist0, hist0, uint64_t(nb) * 256);
+      pack_scatter_k<AdjT, false><<<nb, kRadixNT, 0, st_>>>(load, ka.as<uint32_t>(), adj_.as<AdjT>(), E, hist0, nb);
+    }
     KB_LAUNCH_CHECK();
     const bool f = radix_sort<uint32_t, AdjT>(ka.as<uint32_t>(), adj_.as<AdjT>(), kb2.as<uint32_t>(),
-                                              vb.as<AdjT>(), E, 0, bits_for(N > 1 ? N - 1 : 1),
+                                              vb.as<AdjT>(), E, 8, bits_for(N > 1 ? N - 1 : 1),
                                               radix_scratch(E), st_);
     if (f) adj_.swap(vb);
     const uint32_t* skey = f ? kb2.as<uint32_t>() : ka.as<uint32_t>();
@@ -170,10 +178,23 @@ void Engine::build_adj(const int32_t* src, const int32_t* lab, const int32_t* ds
 
 // Dense ascending ranks of the label values `val[0..n)` (all >= 0, max
 // `maxv`): for small values through a presence table (rank_table[v] = rank
-// of value v), otherwise through a sort (rank[i] per element). Returns the
-// number of distinct values. Exactly one of the two outputs is filled.
-uint32_t Engine::label_ranks(const int32_t* val, uint64_t n, uint32_t maxv, DevBuf& rank_table, DevBuf& rank) {
+// of value v; below kMaskLabels built from the presence mask of the
+// validation pass, else by marking), otherwise through a sort (rank[i] per
+// element). Returns the number of distinct values. Exactly one of the two
+// outputs is filled.
+uint32_t Engine::label_ranks(const int32_t* val, uint64_t n, uint32_t maxv, const unsigned long long* mask_dev,
+                             const uint64_t* mask_host, DevBuf& rank_table, DevBuf& rank) {
   if (n == 0) return 0;
+  if (maxv < kMaskLabels) {
+    // all values are in the presence mask the validation pass collected
+    const uint32_t t = maxv + 2;
+    rank_table.ensure(uint64_t(t) * 4);
+    mask_ranks_k<<<1, 256, 0, st_>>>(mask_dev, t, rank_table.as<uint32_t>());
+    KB_LAUNCH_CHECK();
+    uint32_t d = 0;
+    for (int q = 0; q < 4; ++q) d += uint32_t(__builtin_popcountll(mask_host[q]));
+    return d;
+  }
   if (maxv < kRankTableMax) {
     const uint64_t t = uint64_t(maxv) + 2;
     DevBuf present;
@@ -208,22 +229,32 @@ uint32_t Engine::label_ranks(const int32_t* val, uint64_t n, uint32_t maxv, DevB
 void Engine::build(const int32_t* node_label, const int32_t* src, const int32_t* lab, const int32_t* dst) {
   StreamScope scope(st_);
   const uint64_t N = uint64_t(n_), E = uint64_t(m_);
+  // error word, label maxima, and the presence masks of node and edge labels
+  // below kMaskLabels (4 words each, from byte 16)
+  constexpr size_t kErrBytes = 16 + 8 * sizeof(uint64_t);
   DevBuf errb;
-  errb.ensure(4 * sizeof(uint32_t));
-  KB_CHECK(hipMemsetAsync(errb.p, 0, 4 * sizeof(uint32_t), st_));
+  errb.ensure(kErrBytes);
+  KB_CHECK(hipMemsetAsync(errb.p, 0, kErrBytes, st_));
   uint32_t* err = errb.as<uint32_t>();
+  unsigned long long* masks = reinterpret_cast<unsigned long long*>(errb.as<uint8_t>() + 16);
+  DevBuf hist0;  // per-tile source counts for the first pass of the sort by source
+  const uint32_t enb = E ? radix_blocks(E) : 0u;
   if (N) {
-    validate_nodes_k<<<validate_blocks(N), kNT, 0, st_>>>(node_label, N, err, err + 1);
+    validate_nodes_k<<<validate_blocks(N), kNT, 0, st_>>>(node_label, N, err, err + 1, masks);
     KB_LAUNCH_CHECK();
   }
   if (E) {
-    validate_edges_k<<<validate_blocks(E), kNT, 0, st_>>>(src, lab, dst, E, n_, err, err + 1);
+    hist0.ensure(uint64_t(enb) * 256 * 4);
+    edge_scan_k<<<std::min<uint32_t>(enb, 2048), kRadixNT, 0, st_>>>(src, lab, dst, E, n_, err, err + 2, masks + 4,
+                                                                     hist0.as<uint32_t>(), enb);
     KB_LAUNCH_CHECK();
   }
-  KB_CHECK(hipMemcpyAsync(hw_.p, err, 3 * sizeof(uint32_t), hipMemcpyDeviceToHost, st_));
+  KB_CHECK(hipMemcpyAsync(hw_.p, errb.p, kErrBytes, hipMemcpyDeviceToHost, st_));
   KB_CHECK(hipStreamSynchronize(st_));
   uint32_t words[3];
+  uint64_t mask_host[8];
   std::memcpy(words, hw_.p, sizeof(words));
+  std::memcpy(mask_host, hw_.p + 2, sizeof(mask_host));
   if (words[0] & 1u) throw InvalidInput("edge endpoint outside [0, num_nodes)");
   if (words[0] & 2u) throw InvalidInput("negative edge label");
   if (words[0] & 4u) throw InvalidInput("negative node label");
@@ -247,7 +278,7 @@ void Engine::build(const int32_t* node_label, const int32_t* src, const int32_t*
   B_ = 0;
   if (N) {
     DevBuf table, rank, ka, kb2, va, vb;
-    const uint32_t nl = label_ranks(node_label, N, max_nlab, table, rank);
+    const uint32_t nl = label_ranks(node_label, N, max_nlab, masks, mask_host, table, rank);
     for (DevBuf* b : {&ka, &kb2, &va, &vb}) b->ensure(N * 4);
     if (table.p) {
       lookup_rank_k<<<grid_for(N), kNT, 0, st_>>>(node_label, table.as<uint32_t>(), uint32_t(N),
@@ -298,7 +329,7 @@ void Engine::build(const int32_t* node_label, const int32_t* src, const int32_t*
 
   // edge labels: dense ascending ranks
   DevBuf etable, erank;
-  n_elab_ = label_ranks(lab, E, max_elab, etable, erank);
+  n_elab_ = label_ranks(lab, E, max_elab, masks + 4, mask_host + 4, etable, erank);
   lab_bits_ = n_elab_ > 1 ? bits_for(n_elab_ - 1) : 0;
   dst_bits_ = bits_for(N > 1 ? N - 1 : 1);
   adj64_ = dst_bits_ + lab_bits_ > 32;
@@ -306,9 +337,9 @@ void Engine::build(const int32_t* node_label, const int32_t* src, const int32_t*
   const uint32_t* er = erank.p ? erank.as<uint32_t>() : nullptr;
   const uint32_t* et = etable.p ? etable.as<uint32_t>() : nullptr;
   if (adj64_)
-    build_adj<uint64_t>(src, lab, dst, er, et);
+    build_adj<uint64_t>(src, lab, dst, er, et, hist0.as<uint32_t>());
   else
-    build_adj<uint32_t>(src, lab, dst, er, et);
+    build_adj<uint32_t>(src, lab, dst, er, et, hist0.as<uint32_t>());
 
   // per-round buffers
   ukey_.ensure(std::max<uint64_t>(E, 1) * (key64_ ? 8 : 4));

@@ -127,6 +127,9 @@ constexpr int kRadixIPT = 16;
 constexpr int kRadixTile = kRadixNT * kRadixIPT;
 constexpr int kRadixNW = kRadixNT / kWave;
 
+// Per-tile digit counts, digit-major: hist[d * nblocks + tile]. A full
+// tile whose start is 16-byte aligned is read with 16-byte loads (more
+// bytes in flight per thread); others element by element.
 template <typename K>
 __global__ __launch_bounds__(kRadixNT) void radix_hist_k(const K* __restrict__ keys, uint64_t n,
                                                          int shift, uint32_t* __restrict__ hist,
@@ -136,10 +139,25 @@ __global__ __launch_bounds__(kRadixNT) void radix_hist_k(const K* __restrict__ k
   __syncthreads();
   const int w = threadIdx.x / kWave;
   const uint64_t base = uint64_t(blockIdx.x) * kRadixTile;
+  constexpr int kPerVec = 16 / sizeof(K);
+  constexpr int kVecs = kRadixIPT / kPerVec;
+  if (base + kRadixTile <= n && (reinterpret_cast<uintptr_t>(keys) & 15u) == 0) {
+    const uint4* v = reinterpret_cast<const uint4*>(keys + base);
+    uint4 r[kVecs];
+#pragma unroll
+    for (int i = 0; i < kVecs; ++i) r[i] = v[i * kRadixNT + threadIdx.x];
+#pragma unroll
+    for (int i = 0; i < kVecs; ++i) {
+      const K* e = reinterpret_cast<const K*>(&r[i]);
+#pragma unroll
+      for (int q = 0; q < kPerVec; ++q) atomicAdd(&cnt[w][uint32_t(e[q] >> shift) & 255u], 1u);
+    }
+  } else {
 #pragma unroll 4
-  for (int i = 0; i < kRadixIPT; ++i) {
-    const uint64_t idx = base + uint64_t(i) * kRadixNT + threadIdx.x;
-    if (idx < n) atomicAdd(&cnt[w][uint32_t(keys[idx] >> shift) & 255u], 1u);
+    for (int i = 0; i < kRadixIPT; ++i) {
+      const uint64_t idx = base + uint64_t(i) * kRadixNT + threadIdx.x;
+      if (idx < n) atomicAdd(&cnt[w][uint32_t(keys[idx] >> shift) & 255u], 1u);
+    }
   }
   __syncthreads();
   for (int d = threadIdx.x; d < 256; d += kRadixNT) {
@@ -162,22 +180,32 @@ __device__ __forceinline__ uint64_t match_digit8(uint32_t d, uint64_t valid_mask
   return m;
 }
 
-// Scatter of one 4096-item tile. Wave w owns the contiguous sub-tile
-// [w*1024, (w+1)*1024) and keeps its 16 rows of 64 items in registers.
-// The tile is first sorted by digit into LDS (per-wave digit counts give
-// every wave its local offsets; each wave places its rows in order with
-// wave-local counters, one LDS read and one write per row, which a wave
-// completes in order). Then consecutive threads copy consecutive LDS items
-// to their global positions, so each digit's run is written contiguously.
-// Stable: tile order = wave order, row order, lane order.
+// Key and value of item i of a radix pass, read from two arrays.
+template <typename K, typename V, bool kHasVal>
+struct KVLoad {
+  const K* __restrict__ k;
+  const V* __restrict__ v;
+  __device__ __forceinline__ void operator()(uint64_t i, K& key, V& val) const {
+    key = k[i];
+    if (kHasVal) val = v[i];
+  }
+};
+
+// Scatter of one 4096-item tile (blockIdx.x). Wave w owns the contiguous
+// sub-tile [w*1024, (w+1)*1024) and keeps its 16 rows of 64 items in
+// registers. The tile is first sorted by digit into LDS (per-wave digit
+// counts give every wave its local offsets; each wave places its rows in
+// order with wave-local counters, one LDS read and one write per row, which
+// a wave completes in order). Then consecutive threads copy consecutive LDS
+// items to their global positions, so each digit's run is written
+// contiguously. Stable: tile order = wave order, row order, lane order.
 // kFused: `hist` holds the raw per-tile counts (digit-major) and every
 // workgroup derives its own global offsets from them (for few tiles); else
-// it holds their exclusive scan.
-template <typename K, typename V, bool kHasVal, bool kFused>
-__global__ __launch_bounds__(kRadixNT) void radix_scatter_k(
-    const K* __restrict__ kin, const V* __restrict__ vin, K* __restrict__ kout,
-    V* __restrict__ vout, uint64_t n, int shift, const uint32_t* __restrict__ hist_scan,
-    uint32_t nblocks) {
+// it holds their exclusive scan. `load(i, key, val)` reads item i < n.
+template <typename K, typename V, bool kHasVal, bool kFused, typename Load>
+__device__ __forceinline__ void radix_scatter_tile(const Load& load, K* __restrict__ kout, V* __restrict__ vout,
+                                                   uint64_t n, int shift, const uint32_t* __restrict__ hist_scan,
+                                                   uint32_t nblocks) {
   constexpr int kRows = kRadixIPT;
   __shared__ uint32_t wh[kRadixNW][256];   // per-wave counts, then running local offsets
   __shared__ uint32_t gdelta[256];         // global position - local position, per digit
@@ -197,8 +225,9 @@ __global__ __launch_bounds__(kRadixNT) void radix_scatter_k(
   for (int r = 0; r < kRows; ++r) {
     const uint64_t idx = sub + uint64_t(r) * kWave + lane;
     const bool valid = idx < n;
-    key[r] = valid ? kin[idx] : K(0);
-    if (kHasVal) val[r] = valid ? vin[idx] : V(0);
+    key[r] = K(0);
+    val[r] = V(0);
+    if (valid) load(idx, key[r], val[r]);
     dg[r] = valid ? (uint32_t(key[r] >> shift) & 255u) : 256u;
   }
 #pragma unroll
@@ -258,6 +287,15 @@ __global__ __launch_bounds__(kRadixNT) void radix_scatter_k(
     kout[pos] = k;
     if (kHasVal) vout[pos] = sv[i];
   }
+}
+
+template <typename K, typename V, bool kHasVal, bool kFused>
+__global__ __launch_bounds__(kRadixNT) void radix_scatter_k(
+    const K* __restrict__ kin, const V* __restrict__ vin, K* __restrict__ kout,
+    V* __restrict__ vout, uint64_t n, int shift, const uint32_t* __restrict__ hist_scan,
+    uint32_t nblocks) {
+  radix_scatter_tile<K, V, kHasVal, kFused>(KVLoad<K, V, kHasVal>{kin, vin}, kout, vout, n, shift, hist_scan,
+                                            nblocks);
 }
 
 inline uint32_t radix_blocks(uint64_t n) { return ceil_div(n, kRadixTile); }

@@ -230,6 +230,20 @@ def test_key_width_exactly_32():
     check_parity(g, 2)
 
 
+@pytest.mark.parametrize("top", [255, 256])
+def test_label_values_near_mask_limit(top):
+    """Label values around 256: below it the ranks come from the presence
+    mask of the validation pass, from 256 on from the marking table."""
+    rng = np.random.default_rng(31 + top)
+    n, e = 4000, 24000
+    nvals = np.array([0, 63, 64, 200, top], np.int32)
+    evals = np.array([1, 64, 128, 191, top], np.int32)
+    g = synth.Graph(n, nvals[rng.integers(0, 5, size=n)], rng.integers(0, n, size=e).astype(np.int32),
+                    evals[rng.integers(0, 5, size=e)], rng.integers(0, n, size=e).astype(np.int32),
+                    name="labels%d" % top)
+    check_parity(g, 5)
+
+
 def test_large_label_values():
     """Label values up to 2^31 - 1 (ranked by sorting instead of a table)."""
     rng = np.random.default_rng(29)
