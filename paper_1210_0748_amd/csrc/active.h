@@ -29,7 +29,8 @@ constexpr int kInfoWords = kInfoItems + 1;
 // the list covers positions [seg_s[t], seg_s[t] + size), soff is the
 // exclusive scan of the sizes (soff[S] = number of items), S = *s_dev.
 // Thread 0 also records the number of items in info.
-// actr[anode[j]] = tag marks the active nodes of the round.
+// actr[anode[j]] = tag marks the active nodes of the round (unless actr is
+// null: marked by the caller).
 __global__ void expand_k(const uint32_t* __restrict__ seg_s, const uint32_t* __restrict__ soff,
                          const uint32_t* __restrict__ s_dev, uint32_t m_cap, const uint32_t* __restrict__ ord,
                          uint32_t* __restrict__ apos, uint32_t* __restrict__ anode, uint32_t* __restrict__ actr,
@@ -51,7 +52,7 @@ __global__ void expand_k(const uint32_t* __restrict__ seg_s, const uint32_t* __r
   const uint32_t u = ord[p];
   apos[j] = p;
   anode[j] = u;
-  actr[u] = tag;
+  if (actr) actr[u] = tag;
 }
 
 // Out-degree bucket of an active node for the signature kernel: wave (17..64
@@ -172,24 +173,41 @@ struct NextSegWrite {
 
 // ---- ids ---------------------------------------------------------------------
 
-// cls = inclusive scan of flag over all positions: dense[ord[p]] = cls[p] - 1.
-__global__ void dense_ids_k(const uint32_t* __restrict__ ord, const uint32_t* __restrict__ cls, uint32_t n,
+// Dense ids in node order: pid[v] is the position of the first member of
+// v's class and cls (inclusive scan of the class-start flags) numbers the
+// classes along ord, so v's dense id is cls[pid[v]] - 1.
+__global__ void dense_ids_k(const int32_t* __restrict__ pid, const uint32_t* __restrict__ cls, uint32_t n,
                             int32_t* __restrict__ dense) {
-  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < n) dense[ord[p]] = int32_t(cls[p] - 1);
+  const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) dense[v] = int32_t(cls[uint32_t(pid[v])] - 1);
 }
 
-// Class-start position ids from dense block starts: pid[ord[p]] = bstart[cls[p] - 1].
-__global__ void pos_ids_k(const uint32_t* __restrict__ ord, const uint32_t* __restrict__ cls,
-                          const uint32_t* __restrict__ bstart, uint32_t n, int32_t* __restrict__ pid) {
+// Start position of every block of pId_0: bstart[cls[p] - 1] = p at the
+// first position p of each block (cls = inclusive scan of the flags).
+__global__ void block_starts_k(const uint8_t* __restrict__ flag, const uint32_t* __restrict__ cls, uint32_t n,
+                               uint32_t* __restrict__ bstart) {
   const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < n) pid[ord[p]] = int32_t(bstart[cls[p] - 1]);
+  if (p < n && flag[p]) bstart[cls[p] - 1] = p;
+}
+
+// In node order: the class-start position id of node v (the start of its
+// block of pId_0, rank0[v] = its block) and its active mark (tag when the
+// block has two or more members, else 0).
+template <typename T>
+__global__ void node_ids0_k(const T* __restrict__ rank0, const uint32_t* __restrict__ bstart, uint32_t n,
+                            int32_t* __restrict__ pid, uint32_t* __restrict__ actr, uint32_t tag) {
+  const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  const uint32_t r = uint32_t(rank0[v]);
+  const uint32_t s = bstart[r];
+  pid[v] = int32_t(s);
+  actr[v] = bstart[r + 1] - s >= 2 ? tag : 0u;
 }
 
 // Narrow copy of ids below 2^16 (the first round's keys gather pId_0 for
 // every edge; a smaller table keeps more of it in cache).
 template <typename T>
-__global__ void narrow_ids_k(const int32_t* __restrict__ in, uint32_t n, T* __restrict__ out) {
+__global__ void narrow_ids_k(const uint32_t* __restrict__ in, uint32_t n, T* __restrict__ out) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = T(in[i]);
 }

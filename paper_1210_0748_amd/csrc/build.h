@@ -254,12 +254,17 @@ __global__ void mark_present_k(const int32_t* __restrict__ val, uint64_t n, uint
   }
 }
 
-__global__ void lookup_rank_k(const int32_t* __restrict__ val, const uint32_t* __restrict__ rank,
-                              uint32_t n, uint32_t* __restrict__ out_key, uint32_t* __restrict__ out_idx) {
+// Label rank of every node: the sort input (key = rank, value = node) and
+// the rank itself in the narrow id type.
+template <typename T>
+__global__ void lookup_rank_k(const int32_t* __restrict__ val, const uint32_t* __restrict__ rank, uint32_t n,
+                              uint32_t* __restrict__ out_key, uint32_t* __restrict__ out_idx, T* __restrict__ narrow) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  out_key[i] = rank[uint32_t(val[i])];
-  if (out_idx) out_idx[i] = i;
+  const uint32_t r = rank[uint32_t(val[i])];
+  out_key[i] = r;
+  out_idx[i] = i;
+  narrow[i] = T(r);
 }
 
 // Items of the first pass of the sort by source, read from the edge table

@@ -141,7 +141,8 @@ class Engine {
   void make_lists(const uint32_t* seg_start, const uint32_t* seg_size, const uint32_t* seg_depth,
                   const uint8_t* seg_done, uint32_t nseg, SegLists& out, const uint32_t* nseg_dev = nullptr);
   void assign_round();
-  void prepare_active(uint32_t seg_items, uint32_t m_cap, uint32_t tag);
+  // mark: set actr[node] = tag for the active nodes (else already done)
+  void prepare_active(uint32_t seg_items, uint32_t m_cap, uint32_t tag, bool mark);
   void run_round();
   uint64_t read_word(const void* dev, int bytes);
   template <typename Tin, typename Tout, bool kIncl>

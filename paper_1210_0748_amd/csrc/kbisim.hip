@@ -262,30 +262,49 @@ void Engine::build(const int32_t* node_label, const int32_t* src, const int32_t*
 
   const uint64_t N1 = std::max<uint64_t>(N, 1);
   pid_.ensure(N1 * 4);
-  pid0_.ensure(N1 * 4);
   ord_.ensure(N1 * 4);
   flag_.ensure(N1);
   cls_.ensure(N1 * 4);
   info_.ensure(kInfoWords * 4);
   for (DevBuf* b : {&act_.start, &act_.size, &act_.depth, &soff_}) b->ensure((N + 1) * 4);
   for (DevBuf* b : {&apos_, &anode_, &blists_, &fl_, &first_, &actr_}) b->ensure(N1 * 4);
-  KB_CHECK(hipMemsetAsync(actr_.p, 0, N1 * 4, st_));
 
   // pId_0: the rank of the node label; nodes sorted by it give `ord` and the
-  // blocks (Section 3.1, k = 0: sort by label, a new id per new label)
+  // blocks (Section 3.1, k = 0: sort by label, a new id per new label).
+  // pId_0 is kept in the narrowest type that holds it (the first round
+  // gathers it for every edge); ids and the first round's active marks are
+  // written in node order.
   DevBuf bstart;
   bstart.ensure((N + 1) * 4);
   B_ = 0;
+  pid0_bytes_ = 4;
   if (N) {
     DevBuf table, rank, ka, kb2, va, vb;
     const uint32_t nl = label_ranks(node_label, N, max_nlab, masks, mask_host, table, rank);
+    pid0_bytes_ = nl <= 256 ? 1 : nl <= 65536 ? 2 : 4;
+    pid0_.ensure(N * pid0_bytes_);
     for (DevBuf* b : {&ka, &kb2, &va, &vb}) b->ensure(N * 4);
+    const uint32_t n32 = uint32_t(N);
     if (table.p) {
-      lookup_rank_k<<<grid_for(N), kNT, 0, st_>>>(node_label, table.as<uint32_t>(), uint32_t(N),
-                                                  ka.as<uint32_t>(), va.as<uint32_t>());
+      const uint32_t* t = table.as<uint32_t>();
+      if (pid0_bytes_ == 1)
+        lookup_rank_k<uint8_t><<<grid_for(N), kNT, 0, st_>>>(node_label, t, n32, ka.as<uint32_t>(),
+                                                             va.as<uint32_t>(), pid0_.as<uint8_t>());
+      else if (pid0_bytes_ == 2)
+        lookup_rank_k<uint16_t><<<grid_for(N), kNT, 0, st_>>>(node_label, t, n32, ka.as<uint32_t>(),
+                                                              va.as<uint32_t>(), pid0_.as<uint16_t>());
+      else
+        lookup_rank_k<uint32_t><<<grid_for(N), kNT, 0, st_>>>(node_label, t, n32, ka.as<uint32_t>(),
+                                                              va.as<uint32_t>(), pid0_.as<uint32_t>());
     } else {
       KB_CHECK(hipMemcpyAsync(ka.p, rank.p, N * 4, hipMemcpyDeviceToDevice, st_));
-      iota_k<<<grid_for(N), kNT, 0, st_>>>(va.as<uint32_t>(), uint32_t(N));
+      iota_k<<<grid_for(N), kNT, 0, st_>>>(va.as<uint32_t>(), n32);
+      if (pid0_bytes_ == 1)
+        narrow_ids_k<uint8_t><<<grid_for(N), kNT, 0, st_>>>(rank.as<uint32_t>(), n32, pid0_.as<uint8_t>());
+      else if (pid0_bytes_ == 2)
+        narrow_ids_k<uint16_t><<<grid_for(N), kNT, 0, st_>>>(rank.as<uint32_t>(), n32, pid0_.as<uint16_t>());
+      else
+        KB_CHECK(hipMemcpyAsync(pid0_.p, rank.p, N * 4, hipMemcpyDeviceToDevice, st_));
     }
     KB_LAUNCH_CHECK();
     const bool f = radix_sort<uint32_t>(ka.as<uint32_t>(), va.as<uint32_t>(), kb2.as<uint32_t>(),
@@ -294,34 +313,29 @@ void Engine::build(const int32_t* node_label, const int32_t* src, const int32_t*
     const uint32_t* keys = f ? kb2.as<uint32_t>() : ka.as<uint32_t>();
     const uint32_t* vals = f ? vb.as<uint32_t>() : va.as<uint32_t>();
     KB_CHECK(hipMemcpyAsync(ord_.p, vals, N * 4, hipMemcpyDeviceToDevice, st_));
-    run_start_flags_k<<<grid_for(N), kNT, 0, st_>>>(keys, uint32_t(N), flag_.as<uint8_t>(), nullptr);
+    run_start_flags_k<<<grid_for(N), kNT, 0, st_>>>(keys, n32, flag_.as<uint8_t>(), nullptr);
     KB_LAUNCH_CHECK();
-    // dense pId_0, block starts, and class-start position ids
+    // block starts (the ranks are dense: nl blocks), then per node its
+    // block's start position and whether the block has two or more members
     scan_dev<uint8_t, uint32_t, true>(flag_.as<uint8_t>(), cls_.as<uint32_t>(), N);
-    assign_k<<<grid_for(N), kNT, 0, st_>>>(ord_.as<uint32_t>(), flag_.as<uint8_t>(), cls_.as<uint32_t>(),
-                                           uint32_t(N), pid0_.as<int32_t>(), bstart.as<uint32_t>());
+    block_starts_k<<<grid_for(N), kNT, 0, st_>>>(flag_.as<uint8_t>(), cls_.as<uint32_t>(), n32,
+                                                 bstart.as<uint32_t>());
     KB_LAUNCH_CHECK();
-    B_ = int64_t(read_word(cls_.as<uint32_t>() + (N - 1), 4));
-    set_u32_k<<<1, 1, 0, st_>>>(bstart.as<uint32_t>() + B_, uint32_t(N));
+    B_ = int64_t(nl);
+    set_u32_k<<<1, 1, 0, st_>>>(bstart.as<uint32_t>() + B_, n32);
     KB_LAUNCH_CHECK();
-    pos_ids_k<<<grid_for(N), kNT, 0, st_>>>(ord_.as<uint32_t>(), cls_.as<uint32_t>(), bstart.as<uint32_t>(),
-                                            uint32_t(N), pid_.as<int32_t>());
+    if (pid0_bytes_ == 1)
+      node_ids0_k<uint8_t><<<grid_for(N), kNT, 0, st_>>>(pid0_.as<uint8_t>(), bstart.as<uint32_t>(), n32,
+                                                         pid_.as<int32_t>(), actr_.as<uint32_t>(), 1u);
+    else if (pid0_bytes_ == 2)
+      node_ids0_k<uint16_t><<<grid_for(N), kNT, 0, st_>>>(pid0_.as<uint16_t>(), bstart.as<uint32_t>(), n32,
+                                                          pid_.as<int32_t>(), actr_.as<uint32_t>(), 1u);
+    else
+      node_ids0_k<uint32_t><<<grid_for(N), kNT, 0, st_>>>(pid0_.as<uint32_t>(), bstart.as<uint32_t>(), n32,
+                                                          pid_.as<int32_t>(), actr_.as<uint32_t>(), 1u);
     KB_LAUNCH_CHECK();
   }
   b0_ = uint32_t(B_);
-  // pId_0 in the narrowest type that holds it
-  pid0_bytes_ = 4;
-  if (N && b0_ <= (1u << 16)) {
-    DevBuf narrow;
-    pid0_bytes_ = b0_ <= 256 ? 1 : 2;
-    narrow.ensure(N * pid0_bytes_);
-    if (pid0_bytes_ == 1)
-      narrow_ids_k<uint8_t><<<grid_for(N), kNT, 0, st_>>>(pid0_.as<int32_t>(), uint32_t(N), narrow.as<uint8_t>());
-    else
-      narrow_ids_k<uint16_t><<<grid_for(N), kNT, 0, st_>>>(pid0_.as<int32_t>(), uint32_t(N), narrow.as<uint16_t>());
-    KB_LAUNCH_CHECK();
-    pid0_.swap(narrow);  // the int32 copy goes back to the pool (after the kernel, by stream order)
-  }
   counts_.assign(1, B_);
   rounds_ = 0;
   fixed_ = false;
@@ -355,7 +369,7 @@ void Engine::build(const int32_t* node_label, const int32_t* src, const int32_t*
                                        act_.depth.as<uint32_t>()},
                          uint32_t(B_), nullptr, compact_scratch(compact_part_words<kSegClasses>(B_)),
                          info_.as<uint32_t>() + kInfoSeg, st_);
-    prepare_active(uint32_t(B_), uint32_t(N), 1u);
+    prepare_active(uint32_t(B_), uint32_t(N), 1u, false);  // active marks written above
   }
   KB_CHECK(hipStreamSynchronize(st_));
 }
@@ -373,13 +387,13 @@ uint32_t* Engine::compact_scratch(uint64_t words) {
 // number of segments (act_.size must be zero from the last segment up to
 // seg_items), m_cap the number of active positions, tag the number of the
 // round being prepared (1 for the first), which marks its nodes in actr_.
-void Engine::prepare_active(uint32_t seg_items, uint32_t m_cap, uint32_t tag) {
+void Engine::prepare_active(uint32_t seg_items, uint32_t m_cap, uint32_t tag, bool mark) {
   uint32_t* info = info_.as<uint32_t>();
   scan_dev<uint32_t, uint32_t, false>(act_.size.as<uint32_t>(), soff_.as<uint32_t>(), uint64_t(seg_items) + 1);
   expand_k<<<grid_for(m_cap), kNT, 0, st_>>>(act_.start.as<uint32_t>(), soff_.as<uint32_t>(),
                                              info + kInfoSeg + 2 * kSegClasses, m_cap, ord_.as<uint32_t>(),
-                                             apos_.as<uint32_t>(), anode_.as<uint32_t>(), actr_.as<uint32_t>(),
-                                             tag, info);
+                                             apos_.as<uint32_t>(), anode_.as<uint32_t>(),
+                                             mark ? actr_.as<uint32_t>() : nullptr, tag, info);
   KB_LAUNCH_CHECK();
   // when many nodes may be active, the work lists and the thread part go
   // over node ids in order (neighbouring rows), else over the active list
@@ -435,7 +449,7 @@ void Engine::assign_round() {
                                         act_.size.as<uint32_t>(), act_.depth.as<uint32_t>()},
                        M, info + kInfoClasses, compact_scratch(compact_part_words<kSegClasses>(M)),
                        info + kInfoSeg, st_);
-  prepare_active(M, M, uint32_t(rounds_) + 2);  // runs inside round rounds_ + 1
+  prepare_active(M, M, uint32_t(rounds_) + 2, true);  // runs inside round rounds_ + 1
 }
 
 // ---------------------------------------------------------------------------
@@ -808,7 +822,7 @@ const int32_t* Engine::dense_pid() {
   dense_.ensure(std::max<uint64_t>(N, 1) * 4);
   if (N && dense_round_ != rounds_) {
     scan_dev<uint8_t, uint32_t, true>(flag_.as<uint8_t>(), cls_.as<uint32_t>(), N);
-    dense_ids_k<<<grid_for(N), kNT, 0, st_>>>(ord_.as<uint32_t>(), cls_.as<uint32_t>(), uint32_t(N),
+    dense_ids_k<<<grid_for(N), kNT, 0, st_>>>(pid_.as<int32_t>(), cls_.as<uint32_t>(), uint32_t(N),
                                               dense_.as<int32_t>());
     KB_LAUNCH_CHECK();
     dense_round_ = rounds_;

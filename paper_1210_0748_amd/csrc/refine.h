@@ -772,19 +772,6 @@ __global__ void two_word_finish_k(const uint64_t* __restrict__ lo, const uint32_
   val_out[i] = val[idx1[p]];
 }
 
-// ---------------------------------------------------------------------------
-// New ids: cls = inclusive scan of flag; pid_next[ord[p]] = cls[p] - 1 and
-// bstart[cls[p] - 1] = p at class starts.
-__global__ void assign_k(const uint32_t* __restrict__ ord, const uint8_t* __restrict__ flag,
-                         const uint32_t* __restrict__ cls, uint32_t n, int32_t* __restrict__ pid_next,
-                         uint32_t* __restrict__ bstart) {
-  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  const uint32_t c = cls[p];
-  pid_next[ord[p]] = int32_t(c - 1);
-  if (flag[p]) bstart[c - 1] = p;
-}
-
 __global__ void set_u32_k(uint32_t* __restrict__ dst, uint32_t v) { *dst = v; }
 
 }  // namespace kb
