@@ -23,7 +23,8 @@ constexpr int kInfoBucket = 2 * kSegClasses + 1;     // degree buckets: counts, 
 constexpr int kNumBuckets = 3;                       // wave, block, hub lists
 constexpr int kInfoClasses = kInfoBucket + 2 * kNumBuckets + 1;  // classes among the active positions
 constexpr int kInfoItems = kInfoClasses + 1;         // positions of the next active segments
-constexpr int kInfoWords = kInfoItems + 1;
+constexpr int kInfoHubEdges = kInfoItems + 1;        // edges of the hubs in the hub list
+constexpr int kInfoWords = kInfoHubEdges + 1;
 
 // apos[j] = position of active item j, anode[j] = ord[apos[j]]; segment t of
 // the list covers positions [seg_s[t], seg_s[t] + size), soff is the
@@ -89,6 +90,36 @@ struct NodeWriteDense {
   uint32_t* list;
   __device__ __forceinline__ void operator()(uint32_t n, int, uint32_t o) const { list[o] = n; }
 };
+
+// hoff[h] = exclusive scan of the out-degrees of the hub list (*nh_dev
+// entries from lists + *start_dev), hoff[nh] = *total = their sum. One
+// workgroup of 1024 threads.
+__global__ __launch_bounds__(1024) void hub_offsets_k(const uint32_t* __restrict__ rowptr,
+                                                      const uint32_t* __restrict__ lists,
+                                                      const uint32_t* __restrict__ nh_dev,
+                                                      const uint32_t* __restrict__ start_dev,
+                                                      uint32_t* __restrict__ hoff, uint32_t* __restrict__ total) {
+  __shared__ uint32_t sh[1024 / kWave];
+  const uint32_t nh = *nh_dev;
+  const uint32_t* hl = lists + *start_dev;
+  uint32_t carry = 0;
+  for (uint32_t base = 0; base < nh; base += 1024) {
+    const uint32_t h = base + threadIdx.x;
+    uint32_t d = 0;
+    if (h < nh) {
+      const uint32_t n = hl[h];
+      d = rowptr[n + 1] - rowptr[n];
+    }
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan<1024>(d, sh, &tot);
+    if (h < nh) hoff[h] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    hoff[nh] = carry;
+    *total = carry;
+  }
+}
 
 // Initial segments: the blocks of pId_0 (block b spans [bstart[b], bstart[b+1])).
 struct BlockSegOf {

@@ -25,26 +25,35 @@ struct LabelMask {
     w2 |= q == 2 ? bit : 0ull;
     w3 |= q == 3 ? bit : 0ull;
   }
-  // OR over the wave; lane 0 then adds what is new to out[0..3]
-  __device__ __forceinline__ void publish(unsigned long long* out) {
-    const uint64_t v[4] = {wave_or(w0), wave_or(w1), wave_or(w2), wave_or(w3)};
-    if (__lane_id() != 0) return;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const uint64_t cur = __hip_atomic_load(&out[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (v[q] & ~cur) atomicOr(&out[q], (unsigned long long)v[q]);
-    }
-  }
 };
 
-// Errors and label maxima of one wave, reported with one atomic each at
-// most (skipped when nothing new is to be reported).
-__device__ __forceinline__ void report(uint32_t e_bits, uint32_t mx, uint32_t* err, uint32_t* maxv) {
-  e_bits = wave_or(e_bits);
-  mx = wave_max(mx);
-  if (__lane_id() == 0) {
-    if (e_bits) atomicOr(err, e_bits);
-    if (mx > __hip_atomic_load(maxv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(maxv, mx);
+// Errors, label maximum and label mask of one workgroup (every thread calls
+// it), reduced over the workgroup and reported by thread 0 with one atomic
+// each at most (skipped when nothing new is to be reported).
+template <int NT>
+__device__ __forceinline__ void report(uint32_t e_bits, uint32_t mx, const LabelMask& mk, uint32_t* err,
+                                       uint32_t* maxv, unsigned long long* lmask) {
+  constexpr int NW = NT / kWave;
+  __shared__ uint64_t red[NW][6];
+  const int w = threadIdx.x / kWave;
+  const uint64_t v[6] = {wave_or(uint64_t(e_bits)), wave_max(uint64_t(mx)), wave_or(mk.w0),
+                         wave_or(mk.w1),            wave_or(mk.w2),          wave_or(mk.w3)};
+  if (__lane_id() == 0)
+    for (int q = 0; q < 6; ++q) red[w][q] = v[q];
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  uint64_t r[6] = {0, 0, 0, 0, 0, 0};
+  for (int i = 0; i < NW; ++i) {
+    r[0] |= red[i][0];
+    r[1] = red[i][1] > r[1] ? red[i][1] : r[1];
+    for (int q = 2; q < 6; ++q) r[q] |= red[i][q];
+  }
+  if (r[0]) atomicOr(err, uint32_t(r[0]));
+  if (uint32_t(r[1]) > __hip_atomic_load(maxv, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+    atomicMax(maxv, uint32_t(r[1]));
+  for (int q = 0; q < 4; ++q) {
+    const uint64_t cur = __hip_atomic_load(&lmask[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (r[q + 2] & ~cur) atomicOr(&lmask[q], (unsigned long long)r[q + 2]);
   }
 }
 
@@ -114,13 +123,13 @@ __global__ __launch_bounds__(kRadixNT) void edge_scan_k(const int32_t* __restric
     }
     __syncthreads();
   }
-  report(e_bits, mx, err, maxv);
-  mk.publish(lmask);
+  report<kRadixNT>(e_bits, mx, mk, err, maxv, lmask);
 }
 
 // err bit 4: negative node label; *maxv = largest node label; lmask =
 // presence of node labels < 256.
-__global__ void validate_nodes_k(const int32_t* __restrict__ label, uint64_t n, uint32_t* __restrict__ err,
+__global__ __launch_bounds__(kRadixNT) void validate_nodes_k(const int32_t* __restrict__ label, uint64_t n,
+                                                       uint32_t* __restrict__ err,
                                  uint32_t* __restrict__ maxv, unsigned long long* __restrict__ lmask) {
   uint32_t bad = 0, mx = 0;
   LabelMask mk;
@@ -140,8 +149,7 @@ __global__ void validate_nodes_k(const int32_t* __restrict__ label, uint64_t n, 
       }
     }
   }
-  report(bad, mx, err, maxv);
-  mk.publish(lmask);
+  report<kRadixNT>(bad, mx, mk, err, maxv, lmask);
 }
 
 // Rank table of label values below kMaskLabels from their presence mask:

@@ -133,6 +133,8 @@ class Engine {
                        const uint64_t* mask_host, DevBuf& rank_table, DevBuf& rank);
   template <typename AdjT, typename KeyT>
   void round_impl();
+  template <typename AdjT, typename KeyT, typename CompT>
+  void hub_sort(const void* sig_args, const uint32_t* hl, uint32_t nh, int key_bits);
   template <typename KeyT>
   void order_groups(const void* kv);
   template <typename KeyT>
@@ -168,6 +170,10 @@ class Engine {
 
   // graph
   DevBuf rowptr_, adj_, hub_toff_, hub_tmp_;
+  // hubs of the round sorted together (rounds with wide keys): offsets of
+  // their items, sort space, run ranks; edges of the listed hubs
+  DevBuf hub_off_, hub_k0_, hub_k1_, hub_fl_;
+  uint32_t hub_edges_act_ = 0;
   uint64_t hub_edges_ = 0;
   uint32_t maxdeg_ = 0;  // largest out-degree
   // partition state: ord, class-start flags, class-start position ids, and

@@ -240,7 +240,7 @@ void Engine::build(const int32_t* node_label, const int32_t* src, const int32_t*
   DevBuf hist0;  // per-tile source counts for the first pass of the sort by source
   const uint32_t enb = E ? radix_blocks(E) : 0u;
   if (N) {
-    validate_nodes_k<<<validate_blocks(N), kNT, 0, st_>>>(node_label, N, err, err + 1, masks);
+    validate_nodes_k<<<validate_blocks(N), kRadixNT, 0, st_>>>(node_label, N, err, err + 1, masks);
     KB_LAUNCH_CHECK();
   }
   if (E) {
@@ -356,6 +356,7 @@ void Engine::build(const int32_t* node_label, const int32_t* src, const int32_t*
     build_adj<uint32_t>(src, lab, dst, er, et, hist0.as<uint32_t>());
 
   // per-round buffers
+  hub_off_.ensure((E / (uint64_t(kBlockMaxDeg) + 1) + 2) * 4);
   ukey_.ensure(std::max<uint64_t>(E, 1) * (key64_ ? 8 : 4));
   ucnt_.ensure(N1 * 4);
   head_.ensure(N1 * 8);
@@ -409,6 +410,11 @@ void Engine::prepare_active(uint32_t seg_items, uint32_t m_cap, uint32_t tag, bo
                          NodeWrite{anode_.as<uint32_t>(), blists_.as<uint32_t>()}, m_cap, info + kInfoItems,
                          compact_scratch(compact_part_words<kNumBuckets>(m_cap)), info + kInfoBucket, st_);
   }
+  // offsets of the hubs' items for the device-wide hub sort
+  hub_offsets_k<<<1, 1024, 0, st_>>>(rowptr_.as<uint32_t>(), blists_.as<uint32_t>(), info + kInfoBucket + 2,
+                                     info + kInfoBucket + kNumBuckets + 2, hub_off_.as<uint32_t>(),
+                                     info + kInfoHubEdges);
+  KB_LAUNCH_CHECK();
   uint32_t* h = reinterpret_cast<uint32_t*>(hw_.p);
   static_assert(kInfoWords <= 2 * PinnedSlots::kSlotWords, "read-back slot too small");
   for (int i = 0; i < kInfoWords; ++i) h[i] = 0;  // before the copy is queued
@@ -420,6 +426,7 @@ void Engine::prepare_active(uint32_t seg_items, uint32_t m_cap, uint32_t tag, bo
   }
   S_act_ = h[kInfoSeg + 2 * kSegClasses];
   M_act_ = h[kInfoItems];
+  hub_edges_act_ = h[kInfoHubEdges];
   for (int c = 0; c < kNumBuckets; ++c) {
     bcnt_[c] = h[kInfoBucket + c];
     boff_[c] = h[kInfoBucket + kNumBuckets + c];
@@ -673,6 +680,34 @@ void Engine::order_groups(const void* kvp) {
   KB_CHECK(hipStreamWaitEvent(st_, ev_join_big_, 0));
 }
 
+// The round's hubs (list hl, nh entries, item offsets in hub_off_) sorted
+// together by (hub, key): unique keys, counts and head words of every hub.
+template <typename AdjT, typename KeyT, typename CompT>
+void Engine::hub_sort(const void* sig_args, const uint32_t* hl, uint32_t nh, int key_bits) {
+  const SigArgs<AdjT, KeyT>& a = *static_cast<const SigArgs<AdjT, KeyT>*>(sig_args);
+  const uint32_t H = hub_edges_act_;
+  const int hub_bits = bits_for(nh > 1 ? nh - 1 : 1);
+  const uint32_t* hoff = hub_off_.as<uint32_t>();
+  hub_k0_.ensure(uint64_t(H) * sizeof(CompT));
+  hub_k1_.ensure(uint64_t(H) * sizeof(CompT));
+  hub_fl_.ensure((uint64_t(H) + 1) * 4);
+  CompT* k0 = hub_k0_.as<CompT>();
+  CompT* k1 = hub_k1_.as<CompT>();
+  uint32_t* fl = hub_fl_.as<uint32_t>();
+  hub_keys_k<AdjT, KeyT, CompT><<<grid_for(H), kNT, 0, st_>>>(a, hl, hoff, nh, H, key_bits, k0);
+  KB_LAUNCH_CHECK();
+  const bool f = radix_sort<CompT>(k0, static_cast<uint32_t*>(nullptr), k1, static_cast<uint32_t*>(nullptr), H, 0,
+                                   hub_bits + key_bits, radix_scratch(H), st_);
+  const CompT* c = f ? k1 : k0;
+  hub_flags_k<CompT><<<grid_for(uint64_t(H) + 1), kNT, 0, st_>>>(c, H, fl);
+  KB_LAUNCH_CHECK();
+  scan_dev<uint32_t, uint32_t, false>(fl, fl, uint64_t(H) + 1);
+  hub_write_k<AdjT, KeyT, CompT><<<grid_for(H), kNT, 0, st_>>>(a, hl, hoff, c, fl, H, key_bits);
+  KB_LAUNCH_CHECK();
+  hub_finish_k<AdjT, KeyT><<<ceil_div(nh, kNT), kNT, 0, st_>>>(a, hl, hoff, fl, nh);
+  KB_LAUNCH_CHECK();
+}
+
 template <typename AdjT, typename KeyT>
 void Engine::round_impl() {
   const uint32_t N = uint32_t(n_);
@@ -739,9 +774,20 @@ void Engine::round_impl() {
         KB_CHECK(hipMemsetAsync(w.bm + uint64_t(w.nb) * w.words, 0, uint64_t(w.nh) * w.words * 4, st_));
     }
   } else if (w.nh) {
-    hub_tmp_.ensure(std::max<uint64_t>(hub_edges_, 1) * sizeof(KeyT));
-    w.hub_tmp = hub_tmp_.p;
-    w.hub_toff = hub_toff_.as<uint32_t>();
+    // wide keys: all hubs in one device-wide sort by (hub, key) when that
+    // fits 64 bits, else one workgroup per hub
+    const int hub_bits = bits_for(w.nh > 1 ? w.nh - 1 : 1);
+    if (hub_bits + key_bits <= 64) {
+      if (hub_bits + key_bits <= 32)
+        hub_sort<AdjT, KeyT, uint32_t>(&a, w.hl, w.nh, key_bits);
+      else
+        hub_sort<AdjT, KeyT, uint64_t>(&a, w.hl, w.nh, key_bits);
+      w.nh = 0;
+    } else {
+      hub_tmp_.ensure(std::max<uint64_t>(hub_edges_, 1) * sizeof(KeyT));
+      w.hub_tmp = hub_tmp_.p;
+      w.hub_toff = hub_toff_.as<uint32_t>();
+    }
   }
   if (opt_.profile) {
     if (!work_.p) {

@@ -528,10 +528,73 @@ __global__ __launch_bounds__(kSigNT) void signature_k(SigArgs<AdjT, KeyT> a, Sig
   }
 }
 
+// ---- hubs in rounds with wide keys: one device-wide sort ----------------------
+// A hub sorted by one workgroup gathers its keys one workgroup's worth at a
+// time, which for hubs of 10^5 edges and more takes milliseconds. Instead the
+// edges of all hubs of the round are sorted together by (hub, key) with the
+// device-wide radix sort: hub h of the hub list owns items [hoff[h],
+// hoff[h+1]) (exclusive scan of the hub out-degrees).
+
+// comp[i] = (h << key_bits) | key of item i.
+template <typename AdjT, typename KeyT, typename CompT>
+__global__ void hub_keys_k(SigArgs<AdjT, KeyT> a, const uint32_t* __restrict__ hl, const uint32_t* __restrict__ hoff,
+                           uint32_t nh, uint32_t n_items, int key_bits, CompT* __restrict__ comp) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_items) return;
+  uint32_t lo = 0, hi = nh;  // last h with hoff[h] <= i
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (hoff[mid] <= i)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  const uint32_t e = a.rowptr[hl[lo]] + (i - hoff[lo]);
+  comp[i] = (CompT(lo) << key_bits) | CompT(a.key_of(a.adj[e]));
+}
+
+// fl[i] = 1 where a run of equal (hub, key) starts; fl[n] = 0.
+template <typename CompT>
+__global__ void hub_flags_k(const CompT* __restrict__ comp, uint32_t n, uint32_t* __restrict__ fl) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) fl[i] = (i == 0 || comp[i] != comp[i - 1]) ? 1u : 0u;
+  if (i == n) fl[n] = 0u;
+}
+
+// rank = exclusive scan of the run flags: the unique key starting a run at
+// item i is key number rank[i] - rank[hoff[h]] of hub h.
+template <typename AdjT, typename KeyT, typename CompT>
+__global__ void hub_write_k(SigArgs<AdjT, KeyT> a, const uint32_t* __restrict__ hl, const uint32_t* __restrict__ hoff,
+                            const CompT* __restrict__ comp, const uint32_t* __restrict__ rank, uint32_t n,
+                            int key_bits) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const CompT c = comp[i];
+  if (i > 0 && comp[i - 1] == c) return;
+  const uint32_t h = uint32_t(c >> key_bits);
+  a.ukey[a.rowptr[hl[h]] + (rank[i] - rank[hoff[h]])] = KeyT(c & ((CompT(1) << key_bits) - 1));
+}
+
+// Per hub: number of unique keys and the head word.
+template <typename AdjT, typename KeyT>
+__global__ void hub_finish_k(SigArgs<AdjT, KeyT> a, const uint32_t* __restrict__ hl,
+                             const uint32_t* __restrict__ hoff, const uint32_t* __restrict__ rank, uint32_t nh) {
+  const uint32_t h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= nh) return;
+  const uint32_t n = hl[h];
+  const uint32_t c = rank[hoff[h + 1]] - rank[hoff[h]];
+  a.ucnt[n] = c;
+  a.head[n] = a.head_of(a.ukey + a.rowptr[n], c);
+}
+
 // Work of the signature launch (profiling only): per bucket (thread, wave,
 // block, hub) the active nodes and their edges.
-__global__ void work_count_k(const uint32_t* __restrict__ anode, const uint32_t* __restrict__ rowptr, uint32_t m,
-                             unsigned long long* __restrict__ acc) {
+__global__ __launch_bounds__(kSigNT) void work_count_k(const uint32_t* __restrict__ anode,
+                                                      const uint32_t* __restrict__ rowptr, uint32_t m,
+                                                      unsigned long long* __restrict__ acc) {
+  __shared__ unsigned long long red[8];
+  if (threadIdx.x < 8) red[threadIdx.x] = 0;
+  __syncthreads();
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   uint64_t ne[4] = {0, 0, 0, 0};
   uint64_t nn[4] = {0, 0, 0, 0};
@@ -546,10 +609,12 @@ __global__ void work_count_k(const uint32_t* __restrict__ anode, const uint32_t*
   for (int c = 0; c < 4; ++c) {
     const uint64_t sn = wave_sum(nn[c]), se = wave_sum(ne[c]);
     if (__lane_id() == 0 && (sn || se)) {
-      atomicAdd(&acc[2 * c], (unsigned long long)sn);
-      atomicAdd(&acc[2 * c + 1], (unsigned long long)se);
+      atomicAdd(&red[2 * c], (unsigned long long)sn);
+      atomicAdd(&red[2 * c + 1], (unsigned long long)se);
     }
   }
+  __syncthreads();
+  if (threadIdx.x < 8 && red[threadIdx.x]) atomicAdd(&acc[threadIdx.x], red[threadIdx.x]);
 }
 
 }  // namespace kb
