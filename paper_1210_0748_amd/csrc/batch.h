@@ -1,7 +1,9 @@
 // Batched form: many independent graphs refined together.
 //
 // The graphs become one disjoint union whose node labels are made
-// graph-major: a node's union label is the rank of (graph, label). Every
+// graph-major: a node's union label orders the pairs (graph, label)
+// lexicographically ((graph << b) | label, or their rank when that does not
+// fit 31 bits). Every
 // signature then starts with an id that orders graphs first, so each round
 // of the union keeps the graphs' blocks apart and, inside graph g, orders
 // signatures exactly as a run on g alone would (all of g's ids are shifted
@@ -18,6 +20,7 @@
 #include <vector>
 
 #include "common.h"
+#include "build.h"
 #include "engine.h"
 
 namespace kb {
@@ -34,19 +37,52 @@ __device__ __forceinline__ uint32_t bucket_of(const int64_t* off, uint32_t G, ui
   return lo;
 }
 
-// Union edge endpoints: local ids of graph g offset by node_off[g].
-// err bit 1: a local id outside [0, N_g).
-__global__ void union_edges_k(const int32_t* __restrict__ src, const int32_t* __restrict__ dst, uint64_t m,
-                              const int64_t* __restrict__ node_off, const int64_t* __restrict__ edge_off,
-                              uint32_t G, int32_t* __restrict__ usrc, int32_t* __restrict__ udst,
-                              uint32_t* __restrict__ err) {
-  for (uint64_t e = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < m;
-       e += uint64_t(gridDim.x) * blockDim.x) {
-    const uint32_t g = bucket_of(edge_off, G, e);
+// Items per workgroup of the union kernels: graphs are much larger than a
+// tile, so a tile mostly lies inside one graph, found once per tile.
+constexpr uint32_t kUnionTile = 4096;
+
+// Graphs owning the first and last items [t0, t1) of a tile, by binary
+// search in `off` (thread 0), shared with the workgroup.
+__device__ __forceinline__ void tile_graphs(const int64_t* off, uint32_t G, uint64_t t0, uint64_t t1, uint32_t* sh) {
+  if (threadIdx.x == 0) {
+    sh[0] = bucket_of(off, G, t0);
+    sh[1] = bucket_of(off, G, t1 - 1);
+  }
+  __syncthreads();
+}
+
+// Graph of item i of a tile whose items belong to graphs glo..ghi.
+__device__ __forceinline__ uint32_t graph_in(const int64_t* off, uint32_t glo, uint32_t ghi, uint64_t i) {
+  uint32_t lo = glo, hi = ghi + 1;  // last g in [glo, ghi] with off[g] <= i
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (uint64_t(off[mid]) <= i)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// Union edge endpoints: local ids of graph g offset by node_off[g]. One tile
+// of kUnionTile edges per workgroup. err bit 1: a local id outside [0, N_g).
+__global__ __launch_bounds__(256) void union_edges_k(const int32_t* __restrict__ src, const int32_t* __restrict__ dst,
+                                                     uint64_t m, const int64_t* __restrict__ node_off,
+                                                     const int64_t* __restrict__ edge_off, uint32_t G,
+                                                     int32_t* __restrict__ usrc, int32_t* __restrict__ udst,
+                                                     uint32_t* __restrict__ err) {
+  __shared__ uint32_t gr[2];
+  const uint64_t t0 = uint64_t(blockIdx.x) * kUnionTile;
+  const uint64_t t1 = t0 + kUnionTile < m ? t0 + kUnionTile : m;
+  tile_graphs(edge_off, G, t0, t1, gr);
+  const uint32_t glo = gr[0], ghi = gr[1];
+  uint32_t bad = 0;
+  for (uint64_t e = t0 + threadIdx.x; e < t1; e += blockDim.x) {
+    const uint32_t g = glo == ghi ? glo : graph_in(edge_off, glo, ghi, e);
     const int64_t base = node_off[g], n = node_off[g + 1] - base;
     const int32_t s = src[e], d = dst[e];
     if (s < 0 || s >= n || d < 0 || d >= n) {
-      atomicOr(err, 1u);
+      bad = 1u;
       usrc[e] = 0;
       udst[e] = 0;
     } else {
@@ -54,17 +90,32 @@ __global__ void union_edges_k(const int32_t* __restrict__ src, const int32_t* __
       udst[e] = int32_t(base + d);
     }
   }
+  bad = wave_or(bad);
+  if (__lane_id() == 0 && bad) atomicOr(err, 1u);
 }
 
-// Sort key (graph, label) of every union node; err bit 4: negative label.
+// Union label of every node: (graph << lbits) | label (labels already
+// validated, below 2^lbits). One tile of kUnionTile nodes per workgroup.
+__global__ __launch_bounds__(256) void union_labels_k(const int32_t* __restrict__ label, uint64_t n,
+                                                      const int64_t* __restrict__ node_off, uint32_t G, int lbits,
+                                                      int32_t* __restrict__ out) {
+  __shared__ uint32_t gr[2];
+  const uint64_t t0 = uint64_t(blockIdx.x) * kUnionTile;
+  const uint64_t t1 = t0 + kUnionTile < n ? t0 + kUnionTile : n;
+  tile_graphs(node_off, G, t0, t1, gr);
+  const uint32_t glo = gr[0], ghi = gr[1];
+  for (uint64_t v = t0 + threadIdx.x; v < t1; v += blockDim.x) {
+    const uint32_t g = glo == ghi ? glo : graph_in(node_off, glo, ghi, v);
+    out[v] = int32_t((g << lbits) | uint32_t(label[v]));
+  }
+}
+
+// Sort key (graph, label) of every union node (labels already validated).
 __global__ void union_node_keys_k(const int32_t* __restrict__ label, uint64_t n, const int64_t* __restrict__ node_off,
-                                  uint32_t G, uint64_t* __restrict__ key, uint32_t* __restrict__ idx,
-                                  uint32_t* __restrict__ err) {
+                                  uint32_t G, uint64_t* __restrict__ key, uint32_t* __restrict__ idx) {
   const uint64_t v = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (v >= n) return;
-  const int32_t l = label[v];
-  if (l < 0) atomicOr(err, 4u);
-  key[v] = (uint64_t(bucket_of(node_off, G, v)) << 31) | uint64_t(uint32_t(l) & 0x7fffffffu);
+  key[v] = (uint64_t(bucket_of(node_off, G, v)) << 31) | uint64_t(uint32_t(label[v]));
   idx[v] = uint32_t(v);
 }
 
@@ -79,10 +130,12 @@ __global__ void scatter_rank_k(const uint32_t* __restrict__ idx, const uint32_t*
   if (p < n) out[idx[p]] = int32_t(cls[p] - 1);
 }
 
-// Per graph: union id at its first and last sorted position.
-__global__ void graph_id_range_k(const int32_t* __restrict__ pid, const uint32_t* __restrict__ ord,
-                                 const int64_t* __restrict__ node_off, uint32_t G, int32_t* __restrict__ base,
-                                 int32_t* __restrict__ count) {
+// Per graph: dense union id of its first sorted position and its number of
+// classes, from the inclusive scan of the class-start flags (graph g holds
+// positions [node_off[g], node_off[g+1]), and a graph's first position
+// starts a class).
+__global__ void graph_id_range_k(const uint32_t* __restrict__ cls, const int64_t* __restrict__ node_off, uint32_t G,
+                                 int32_t* __restrict__ base, int32_t* __restrict__ count) {
   const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= G) return;
   const int64_t a = node_off[g], b = node_off[g + 1];
@@ -91,18 +144,23 @@ __global__ void graph_id_range_k(const int32_t* __restrict__ pid, const uint32_t
     count[g] = 0;
     return;
   }
-  const int32_t lo = pid[ord[a]], hi = pid[ord[b - 1]];
-  base[g] = lo;
-  count[g] = hi - lo + 1;
+  base[g] = int32_t(cls[a] - 1);
+  count[g] = int32_t(cls[b - 1] - cls[a] + 1);
 }
 
-// Local ids of the graphs marked in `take`.
-__global__ void snapshot_k(const int32_t* __restrict__ pid, uint64_t n, const int64_t* __restrict__ node_off,
-                           uint32_t G, const int32_t* __restrict__ base, const uint8_t* __restrict__ take,
-                           int32_t* __restrict__ out) {
-  for (uint64_t v = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; v < n;
-       v += uint64_t(gridDim.x) * blockDim.x) {
-    const uint32_t g = bucket_of(node_off, G, v);
+// Local ids of the graphs marked in `take`. One tile of kUnionTile nodes per
+// workgroup.
+__global__ __launch_bounds__(256) void snapshot_k(const int32_t* __restrict__ pid, uint64_t n,
+                                                  const int64_t* __restrict__ node_off, uint32_t G,
+                                                  const int32_t* __restrict__ base, const uint8_t* __restrict__ take,
+                                                  int32_t* __restrict__ out) {
+  __shared__ uint32_t gr[2];
+  const uint64_t t0 = uint64_t(blockIdx.x) * kUnionTile;
+  const uint64_t t1 = t0 + kUnionTile < n ? t0 + kUnionTile : n;
+  tile_graphs(node_off, G, t0, t1, gr);
+  const uint32_t glo = gr[0], ghi = gr[1];
+  for (uint64_t v = t0 + threadIdx.x; v < t1; v += blockDim.x) {
+    const uint32_t g = glo == ghi ? glo : graph_in(node_off, glo, ghi, v);
     if (take[g]) out[v] = pid[v] - base[g];
   }
 }

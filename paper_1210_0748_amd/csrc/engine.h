@@ -107,7 +107,7 @@ class Engine {
   // last call) and the cumulative class counts: cls[p] = number of classes
   // starting at positions <= p of ord.
   const int32_t* dense_pid();
-  const uint32_t* class_scan() { dense_pid(); return cls_.as<uint32_t>(); }
+  const uint32_t* class_scan();
   const uint32_t* ord_device() const { return ord_.as<uint32_t>(); }
   hipStream_t stream() const { return st_; }
   int64_t num_edges() const { return m_; }
@@ -193,6 +193,7 @@ class Engine {
   // dense ids
   DevBuf dense_;
   int32_t dense_round_ = -1;
+  int32_t cls_round_ = -1;  // round whose class scan cls_ holds (-1: none)
   // round scratch
   DevBuf ukey_, ucnt_, head_, cls_, fl_, first_, scanpart_, radix_, part_, bm_, bmslot_;
   DevBuf seg_start_, seg_size_, seg_depth_, seg_done_, cls_meta_;

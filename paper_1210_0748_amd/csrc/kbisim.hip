@@ -340,6 +340,7 @@ void Engine::build(const int32_t* node_label, const int32_t* src, const int32_t*
   rounds_ = 0;
   fixed_ = false;
   dense_round_ = -1;
+  cls_round_ = -1;
 
   // edge labels: dense ascending ranks
   DevBuf etable, erank;
@@ -441,6 +442,7 @@ void Engine::assign_round() {
   uint32_t* info = info_.as<uint32_t>();
   act_flags_k<<<grid_for(M), kNT, 0, st_>>>(apos_.as<uint32_t>(), flag_.as<uint8_t>(), M, fl_.as<uint32_t>());
   KB_LAUNCH_CHECK();
+  cls_round_ = -1;  // cls_ holds the scan over the active positions from here on
   scan_dev<uint32_t, uint32_t, true>(fl_.as<uint32_t>(), cls_.as<uint32_t>(), M);
   class_first_k<<<grid_for(M), kNT, 0, st_>>>(fl_.as<uint32_t>(), cls_.as<uint32_t>(), M, first_.as<uint32_t>(),
                                               info);
@@ -862,12 +864,21 @@ void Engine::refine(int32_t k) {
   KB_CHECK(hipStreamSynchronize(st_));
 }
 
+const uint32_t* Engine::class_scan() {
+  StreamScope scope(st_);
+  if (n_ && cls_round_ != rounds_) {
+    scan_dev<uint8_t, uint32_t, true>(flag_.as<uint8_t>(), cls_.as<uint32_t>(), uint64_t(n_));
+    cls_round_ = rounds_;
+  }
+  return cls_.as<uint32_t>();
+}
+
 const int32_t* Engine::dense_pid() {
   StreamScope scope(st_);
   const uint64_t N = uint64_t(n_);
   dense_.ensure(std::max<uint64_t>(N, 1) * 4);
   if (N && dense_round_ != rounds_) {
-    scan_dev<uint8_t, uint32_t, true>(flag_.as<uint8_t>(), cls_.as<uint32_t>(), N);
+    class_scan();
     dense_ids_k<<<grid_for(N), kNT, 0, st_>>>(pid_.as<int32_t>(), cls_.as<uint32_t>(), uint32_t(N),
                                               dense_.as<int32_t>());
     KB_LAUNCH_CHECK();
@@ -930,40 +941,57 @@ Batch::Batch(int32_t G, const int64_t* node_off, const int64_t* edge_off, const 
   usrc.ensure(std::max<uint64_t>(E, 1) * 4);
   udst.ensure(std::max<uint64_t>(E, 1) * 4);
   glabel.ensure(std::max<uint64_t>(N, 1) * 4);
-  err.ensure(4);
-  KB_CHECK(hipMemsetAsync(err.p, 0, 4, s));
-  const uint32_t gs = std::max<uint32_t>(1, std::min<uint32_t>(ceil_div(std::max<uint64_t>(E, 1), 256), 8192));
+  // err word, largest node label, label mask (unused here)
+  constexpr size_t kErrBytes = 16 + 4 * sizeof(uint64_t);
+  err.ensure(kErrBytes);
+  KB_CHECK(hipMemsetAsync(err.p, 0, kErrBytes, s));
+  uint32_t* errw = err.as<uint32_t>();
   if (E) {
-    union_edges_k<<<gs, 256, 0, s>>>(src, dst, E, d_node_off_.as<int64_t>(), d_edge_off_.as<int64_t>(), uint32_t(G),
-                                     usrc.as<int32_t>(), udst.as<int32_t>(), err.as<uint32_t>());
+    union_edges_k<<<ceil_div(E, kUnionTile), 256, 0, s>>>(src, dst, E, d_node_off_.as<int64_t>(),
+                                                          d_edge_off_.as<int64_t>(), uint32_t(G), usrc.as<int32_t>(),
+                                                          udst.as<int32_t>(), errw);
     KB_LAUNCH_CHECK();
   }
   if (N) {
-    DevBuf k0, k1, i0, i1, fl, cl, scratch, part;
-    k0.ensure(N * 8);
-    k1.ensure(N * 8);
-    for (DevBuf* b : {&i0, &i1, &fl, &cl}) b->ensure(N * 4);
-    union_node_keys_k<<<ceil_div(N, 256), 256, 0, s>>>(label, N, d_node_off_.as<int64_t>(), uint32_t(G),
-                                                        k0.as<uint64_t>(), i0.as<uint32_t>(), err.as<uint32_t>());
-    KB_LAUNCH_CHECK();
-    scratch.ensure(radix_scratch_words(N) * 4);
-    const int bits = 31 + bits_for(G > 1 ? uint64_t(G - 1) : 1);
-    const bool f = radix_sort<uint64_t>(k0.as<uint64_t>(), i0.as<uint32_t>(), k1.as<uint64_t>(), i1.as<uint32_t>(), N, 0,
-                                        bits, scratch.as<uint32_t>(), s);
-    const uint64_t* K = f ? k1.as<uint64_t>() : k0.as<uint64_t>();
-    const uint32_t* I = f ? i1.as<uint32_t>() : i0.as<uint32_t>();
-    u64_run_flags_k<<<ceil_div(N, 256), 256, 0, s>>>(K, uint32_t(N), fl.as<uint32_t>());
-    KB_LAUNCH_CHECK();
-    part.ensure(scan_partials_count(N) * 4);
-    scan<uint32_t, uint32_t, true>(fl.as<uint32_t>(), cl.as<uint32_t>(), N, part.as<uint32_t>(), s);
-    scatter_rank_k<<<ceil_div(N, 256), 256, 0, s>>>(I, cl.as<uint32_t>(), uint32_t(N), glabel.as<int32_t>());
+    validate_nodes_k<<<std::max<uint32_t>(1, std::min<uint32_t>(ceil_div(N, 256), 2048)), kRadixNT, 0, s>>>(
+        label, N, errw, errw + 1, reinterpret_cast<unsigned long long*>(err.as<uint8_t>() + 16));
     KB_LAUNCH_CHECK();
   }
-  uint32_t e32 = 0;
-  KB_CHECK(hipMemcpyAsync(&e32, err.p, 4, hipMemcpyDeviceToHost, s));
+  uint32_t ew[2] = {0, 0};
+  KB_CHECK(hipMemcpyAsync(ew, err.p, 8, hipMemcpyDeviceToHost, s));
   KB_CHECK(hipStreamSynchronize(s));
-  if (e32 & 1u) throw InvalidInput("edge endpoint outside its graph's node range");
-  if (e32 & 4u) throw InvalidInput("negative node label");
+  if (ew[0] & 1u) throw InvalidInput("edge endpoint outside its graph's node range");
+  if (ew[0] & 4u) throw InvalidInput("negative node label");
+  if (N) {
+    // union label (g << lbits) | label when that stays below 2^31; else the
+    // dense rank of (graph, label) through a sort
+    const int lbits = bits_for(ew[1] > 0 ? ew[1] : 1);
+    const int gbits = bits_for(G > 1 ? uint64_t(G - 1) : 1);
+    if (lbits + gbits <= 31) {
+      union_labels_k<<<ceil_div(N, kUnionTile), 256, 0, s>>>(label, N, d_node_off_.as<int64_t>(), uint32_t(G), lbits,
+                                                             glabel.as<int32_t>());
+      KB_LAUNCH_CHECK();
+    } else {
+      DevBuf k0, k1, i0, i1, fl, cl, scratch, part;
+      k0.ensure(N * 8);
+      k1.ensure(N * 8);
+      for (DevBuf* b : {&i0, &i1, &fl, &cl}) b->ensure(N * 4);
+      union_node_keys_k<<<ceil_div(N, 256), 256, 0, s>>>(label, N, d_node_off_.as<int64_t>(), uint32_t(G),
+                                                          k0.as<uint64_t>(), i0.as<uint32_t>());
+      KB_LAUNCH_CHECK();
+      scratch.ensure(radix_scratch_words(N) * 4);
+      const bool f = radix_sort<uint64_t>(k0.as<uint64_t>(), i0.as<uint32_t>(), k1.as<uint64_t>(), i1.as<uint32_t>(),
+                                          N, 0, 31 + gbits, scratch.as<uint32_t>(), s);
+      const uint64_t* K = f ? k1.as<uint64_t>() : k0.as<uint64_t>();
+      const uint32_t* I = f ? i1.as<uint32_t>() : i0.as<uint32_t>();
+      u64_run_flags_k<<<ceil_div(N, 256), 256, 0, s>>>(K, uint32_t(N), fl.as<uint32_t>());
+      KB_LAUNCH_CHECK();
+      part.ensure(scan_partials_count(N) * 4);
+      scan<uint32_t, uint32_t, true>(fl.as<uint32_t>(), cl.as<uint32_t>(), N, part.as<uint32_t>(), s);
+      scatter_rank_k<<<ceil_div(N, 256), 256, 0, s>>>(I, cl.as<uint32_t>(), uint32_t(N), glabel.as<int32_t>());
+      KB_LAUNCH_CHECK();
+    }
+  }
   eng_ = new Engine(ntot_, etot_, s, o);
   try {
     eng_->build(glabel.as<int32_t>(), usrc.as<int32_t>(), lab, udst.as<int32_t>());
@@ -986,9 +1014,9 @@ Batch::~Batch() { delete eng_; }
 
 void Batch::read_counts(std::vector<int32_t>& cnt) {
   cnt.assign(G_, 0);
-  graph_id_range_k<<<ceil_div(uint64_t(G_), 256), 256, 0, st_>>>(eng_->dense_pid(), eng_->ord_device(),
-                                                                 d_node_off_.as<int64_t>(), uint32_t(G_),
-                                                                 base_.as<int32_t>(), cnt_.as<int32_t>());
+  graph_id_range_k<<<ceil_div(uint64_t(G_), 256), 256, 0, st_>>>(eng_->class_scan(), d_node_off_.as<int64_t>(),
+                                                                 uint32_t(G_), base_.as<int32_t>(),
+                                                                 cnt_.as<int32_t>());
   KB_LAUNCH_CHECK();
   KB_CHECK(hipMemcpyAsync(cnt.data(), cnt_.p, uint64_t(G_) * 4, hipMemcpyDeviceToHost, st_));
   KB_CHECK(hipStreamSynchronize(st_));
@@ -997,8 +1025,7 @@ void Batch::read_counts(std::vector<int32_t>& cnt) {
 void Batch::take_snapshot(const std::vector<uint8_t>& take) {
   if (ntot_ == 0) return;
   KB_CHECK(hipMemcpyAsync(take_.p, take.data(), uint64_t(G_), hipMemcpyHostToDevice, st_));
-  const uint32_t gs = std::max<uint32_t>(1, std::min<uint32_t>(ceil_div(uint64_t(ntot_), 256), 8192));
-  snapshot_k<<<gs, 256, 0, st_>>>(eng_->dense_pid(), uint64_t(ntot_), d_node_off_.as<int64_t>(), uint32_t(G_),
+  snapshot_k<<<ceil_div(uint64_t(ntot_), kUnionTile), 256, 0, st_>>>(eng_->dense_pid(), uint64_t(ntot_), d_node_off_.as<int64_t>(), uint32_t(G_),
                                    base_.as<int32_t>(), take_.as<uint8_t>(), out_.as<int32_t>());
   KB_LAUNCH_CHECK();
   KB_CHECK(hipStreamSynchronize(st_));  // `take` is a host vector the caller may change
