@@ -14,13 +14,15 @@
 #include "common.h"
 #include "compact.h"
 #include "refine.h"
+#include "signature.h"
 
 namespace kb {
 
 // Words of the per-round summary the host reads back in one copy.
 constexpr int kInfoSeg = 0;                          // next segments: counts, list starts, total
 constexpr int kInfoBucket = 2 * kSegClasses + 1;     // degree buckets: counts, list starts, total
-constexpr int kNumBuckets = 3;                       // wave, block, hub lists
+constexpr int kNumBuckets = 4;                       // wave, mid, block, hub lists
+constexpr int kBucketWave = 0, kBucketMid = 1, kBucketBlock = 2, kBucketHub = 3;
 constexpr int kInfoClasses = kInfoBucket + 2 * kNumBuckets + 1;  // classes among the active positions
 constexpr int kInfoItems = kInfoClasses + 1;         // positions of the next active segments
 constexpr int kInfoHubEdges = kInfoItems + 1;        // edges of the hubs in the hub list
@@ -57,15 +59,21 @@ __global__ void expand_k(const uint32_t* __restrict__ seg_s, const uint32_t* __r
 }
 
 // Out-degree bucket of an active node for the signature kernel: wave (17..64
-// edges), block (65..4096) or hub; nodes with at most 16 edges need no list.
+// edges), mid (65..512), block (513..4096) or hub; nodes with at most 16
+// edges need no list.
+__device__ __forceinline__ int degree_bucket(uint32_t d) {
+  return d <= kThreadMaxDeg ? -1
+         : d <= kWaveMaxDeg ? kBucketWave
+         : d <= kMidMaxDeg  ? kBucketMid
+         : d <= kBlockMaxDeg ? kBucketBlock
+                             : kBucketHub;
+}
 struct NodeBucketOf {
   const uint32_t* anode;
   const uint32_t* rowptr;
-  uint32_t thread_max, wave_max, block_max;
   __device__ __forceinline__ int operator()(uint32_t j) const {
     const uint32_t n = anode[j];
-    const uint32_t d = rowptr[n + 1] - rowptr[n];
-    return d <= thread_max ? -1 : d <= wave_max ? 0 : d <= block_max ? 1 : 2;
+    return degree_bucket(rowptr[n + 1] - rowptr[n]);
   }
 };
 struct NodeWrite {
@@ -79,11 +87,9 @@ struct NodeBucketDenseOf {
   const uint32_t* actr;
   uint32_t tag;
   const uint32_t* rowptr;
-  uint32_t thread_max, wave_max, block_max;
   __device__ __forceinline__ int operator()(uint32_t n) const {
     if (actr[n] != tag) return -1;
-    const uint32_t d = rowptr[n + 1] - rowptr[n];
-    return d <= thread_max ? -1 : d <= wave_max ? 0 : d <= block_max ? 1 : 2;
+    return degree_bucket(rowptr[n + 1] - rowptr[n]);
   }
 };
 struct NodeWriteDense {

@@ -189,7 +189,7 @@ class Engine {
   uint32_t S_act_ = 0, M_act_ = 0;
   DevBuf soff_, apos_, anode_, actr_, blists_, info_;
   bool act_dense_ = false;  // work lists in node order (see prepare_active)
-  uint32_t bcnt_[3] = {}, boff_[3] = {};
+  uint32_t bcnt_[4] = {}, boff_[4] = {};  // per degree bucket: wave, mid, block, hub
   // dense ids
   DevBuf dense_;
   int32_t dense_round_ = -1;

@@ -401,19 +401,17 @@ void Engine::prepare_active(uint32_t seg_items, uint32_t m_cap, uint32_t tag, bo
   // over node ids in order (neighbouring rows), else over the active list
   act_dense_ = uint64_t(m_cap) * 8 >= uint64_t(n_);
   if (act_dense_) {
-    compact<kNumBuckets>(NodeBucketDenseOf{actr_.as<uint32_t>(), tag, rowptr_.as<uint32_t>(), kThreadMaxDeg,
-                                           kWaveMaxDeg, kBlockMaxDeg},
+    compact<kNumBuckets>(NodeBucketDenseOf{actr_.as<uint32_t>(), tag, rowptr_.as<uint32_t>()},
                          NodeWriteDense{blists_.as<uint32_t>()}, uint32_t(n_), nullptr,
                          compact_scratch(compact_part_words<kNumBuckets>(uint64_t(n_))), info + kInfoBucket, st_);
   } else {
-    compact<kNumBuckets>(NodeBucketOf{anode_.as<uint32_t>(), rowptr_.as<uint32_t>(), kThreadMaxDeg, kWaveMaxDeg,
-                                      kBlockMaxDeg},
+    compact<kNumBuckets>(NodeBucketOf{anode_.as<uint32_t>(), rowptr_.as<uint32_t>()},
                          NodeWrite{anode_.as<uint32_t>(), blists_.as<uint32_t>()}, m_cap, info + kInfoItems,
                          compact_scratch(compact_part_words<kNumBuckets>(m_cap)), info + kInfoBucket, st_);
   }
   // offsets of the hubs' items for the device-wide hub sort
-  hub_offsets_k<<<1, 1024, 0, st_>>>(rowptr_.as<uint32_t>(), blists_.as<uint32_t>(), info + kInfoBucket + 2,
-                                     info + kInfoBucket + kNumBuckets + 2, hub_off_.as<uint32_t>(),
+  hub_offsets_k<<<1, 1024, 0, st_>>>(rowptr_.as<uint32_t>(), blists_.as<uint32_t>(), info + kInfoBucket + kBucketHub,
+                                     info + kInfoBucket + kNumBuckets + kBucketHub, hub_off_.as<uint32_t>(),
                                      info + kInfoHubEdges);
   KB_LAUNCH_CHECK();
   uint32_t* h = reinterpret_cast<uint32_t*>(hw_.p);
@@ -749,21 +747,23 @@ void Engine::round_impl() {
   w.tag = uint32_t(rounds_) + 1;
   w.n_nodes = N;
   w.dense = act_dense_;
-  w.wl = lists + boff_[0];
-  w.nw = bcnt_[0];
-  w.bl = lists + boff_[1];
-  w.nb = bcnt_[1];
-  w.hl = lists + boff_[2];
-  w.nh = bcnt_[2];
+  w.wl = lists + boff_[kBucketWave];
+  w.nw = bcnt_[kBucketWave];
+  w.ml = lists + boff_[kBucketMid];
+  w.nm = bcnt_[kBucketMid];
+  w.bl = lists + boff_[kBucketBlock];
+  w.nb = bcnt_[kBucketBlock];
+  w.hl = lists + boff_[kBucketHub];
+  w.nh = bcnt_[kBucketHub];
   w.key_bits = key_bits;
   // small key universe: workgroup nodes de-duplicate through bitmaps, which
   // the ordering then uses for first-difference searches
-  const bool use_bm = key_bits <= kBmKeyBits && (w.nb + w.nh) > 0;
+  const bool use_bm = key_bits <= kBmKeyBits && (w.nm + w.nb + w.nh) > 0;
   w.hub_units = 1;
   w.hub_chunk = 0;
   if (use_bm) {
     w.words = std::max<uint32_t>((1u << key_bits) / 32u, 4u);
-    bm_.ensure(uint64_t(w.nb + w.nh) * w.words * 4);
+    bm_.ensure(uint64_t(w.nm + w.nb + w.nh) * w.words * 4);
     bmslot_.ensure(std::max<uint64_t>(N, 1) * 4);
     w.bm = bm_.as<uint32_t>();
     w.bmslot = bmslot_.as<uint32_t>();
@@ -773,7 +773,7 @@ void Engine::round_impl() {
       w.hub_chunk = std::max<uint32_t>(kHubChunk, ceil_div(maxdeg_, kHubUnits));
       w.hub_units = std::max<uint32_t>(1, ceil_div(maxdeg_, w.hub_chunk));
       if (w.hub_units > 1)
-        KB_CHECK(hipMemsetAsync(w.bm + uint64_t(w.nb) * w.words, 0, uint64_t(w.nh) * w.words * 4, st_));
+        KB_CHECK(hipMemsetAsync(w.bm + uint64_t(w.hub_slot0()) * w.words, 0, uint64_t(w.nh) * w.words * 4, st_));
     }
   } else if (w.nh) {
     // wide keys: all hubs in one device-wide sort by (hub, key) when that

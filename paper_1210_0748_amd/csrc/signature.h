@@ -14,11 +14,15 @@
 //
 // One launch covers all active nodes. Work is split by out-degree: one thread
 // (<= 16 keys, register sorting network), one wave (<= 64 keys, shuffle
-// bitonic), one workgroup (<= 4096 keys, LDS bitonic) or one workgroup with a
-// global-memory radix sort (hubs). When every key is below 2^kBmKeyBits the
-// workgroup nodes de-duplicate through an LDS bitmap instead, and keep the
-// bitmap for the ordering's first-difference searches. Workgroups are laid out
-// hubs first, so the longest ones start first.
+// bitonic; <= 512 keys, 2, 4 or 8 keys per lane in registers), one workgroup
+// (<= 4096 keys, LDS bitonic); hubs (more keys) are sorted by (hub, key)
+// together with the device-wide radix sort before the launch, or, when that
+// key does not fit 64 bits, by one workgroup each with a global-memory radix
+// sort. When every key is below 2^kBmKeyBits the nodes above 64 keys
+// de-duplicate through a bitmap instead (one wave per node, hubs in chunks of
+// one workgroup), and keep the bitmap for the ordering's first-difference
+// searches. Workgroups are laid out hubs first, so the longest ones start
+// first.
 #pragma once
 
 #include "common.h"
@@ -28,6 +32,7 @@ namespace kb {
 
 constexpr uint32_t kThreadMaxDeg = 16;
 constexpr uint32_t kWaveMaxDeg = 64;
+constexpr uint32_t kMidMaxDeg = 512;
 constexpr uint32_t kBlockMaxDeg = 4096;
 constexpr int kSigNT = 256;
 constexpr int kBmKeyBits = 12;
@@ -65,17 +70,21 @@ struct SigArgs {
   }
 };
 
-// Work of one launch. Lists hold node ids; bitmaps (when bm != nullptr) go to
-// slot b for block-list entry b and nb + h for hub-list entry h.
+// Work of one launch. Lists hold node ids by out-degree: wave (17..64), mid
+// (65..512), block (513..4096) and hub lists. With bitmaps (bm != nullptr)
+// mid and block nodes take one wave each (slot i for entry i of the mid list
+// followed by the block list) and hub h takes slot hub_slot0() + h; without,
+// a mid node takes one wave and a block node one workgroup.
 struct SigWork {
   const uint32_t* anode;  // all active nodes (the thread part skips those above kThreadMaxDeg)
   const uint32_t* actr;   // dense thread part: node n is active when actr[n] == tag
   uint32_t tag, n_nodes;
   bool dense;             // thread part over all node ids (in order) instead of anode
   const uint32_t* wl;     // wave list
+  const uint32_t* ml;     // mid list
   const uint32_t* bl;     // block list
   const uint32_t* hl;     // hub list
-  uint32_t nact, nw, nb, nh;
+  uint32_t nact, nw, nm, nb, nh;
   uint32_t* bm;           // bitmaps, `words` 32-bit words each, or nullptr
   uint32_t* bmslot;       // [N]
   uint32_t words;
@@ -85,13 +94,19 @@ struct SigWork {
   uint32_t hub_chunk;     // edges per unit
   int key_bits;
 
-  __host__ __device__ uint32_t wave_units() const { return (nw + kSigNT / kWave - 1) / (kSigNT / kWave); }
+  static constexpr uint32_t kWavesPerUnit = kSigNT / kWave;
+  __host__ __device__ uint32_t hub_slot0() const { return nm + nb; }
+  __host__ __device__ uint32_t wave_units() const { return (nw + kWavesPerUnit - 1) / kWavesPerUnit; }
   __host__ __device__ uint32_t thread_units() const { return ((dense ? n_nodes : nact) + kSigNT - 1) / kSigNT; }
-  // bitmap rounds: one wave per block-list node, else one workgroup
+  // bitmap rounds: one wave per mid or block node; else one workgroup per
+  // block node and one wave per mid node
   __host__ __device__ uint32_t block_units() const {
-    return bm ? (nb + kSigNT / kWave - 1) / (kSigNT / kWave) : nb;
+    return bm ? (nm + nb + kWavesPerUnit - 1) / kWavesPerUnit : nb;
   }
-  __host__ __device__ uint32_t grid() const { return nh * hub_units + block_units() + wave_units() + thread_units(); }
+  __host__ __device__ uint32_t mid_units() const { return bm ? 0u : (nm + kWavesPerUnit - 1) / kWavesPerUnit; }
+  __host__ __device__ uint32_t grid() const {
+    return nh * hub_units + block_units() + mid_units() + wave_units() + thread_units();
+  }
 };
 
 template <typename KeyT>
@@ -177,6 +192,93 @@ __device__ __forceinline__ void sig_wave_node(const SigArgs<AdjT, KeyT>& a, uint
     a.ucnt[n] = __popcll(b);
     a.head[n] = hv;
   }
+}
+
+// ---- one wave per node, K keys per lane, out-degree <= 64 K ----------------------
+// Bitonic sort of 64 K keys held in registers, element i = lane * K + q in
+// lane `lane`, register q: partners closer than K are in the same lane, the
+// others K-aligned in lane ^ (stride / K).
+template <int K, typename KeyT>
+__device__ __forceinline__ void wave_bitonic_k(KeyT (&k)[K]) {
+  const uint32_t lane = __lane_id();
+#pragma unroll
+  for (uint32_t size = 2; size <= kWave * K; size <<= 1) {
+#pragma unroll
+    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      if (stride < K) {
+#pragma unroll
+        for (uint32_t q = 0; q < K; ++q) {
+          const uint32_t p = q ^ stride;
+          if (p > q) cas_up(k[q], k[p], ((lane * K + q) & size) == 0);
+        }
+      } else {
+#pragma unroll
+        for (uint32_t q = 0; q < K; ++q) {
+          const uint32_t i = lane * K + q;
+          const KeyT o = __shfl_xor(k[q], int(stride / K), kWave);
+          const bool up = (i & size) == 0;
+          const bool lower = (i & stride) == 0;
+          const KeyT mn = k[q] < o ? k[q] : o;
+          const KeyT mx = k[q] < o ? o : k[q];
+          k[q] = (lower == up) ? mn : mx;
+        }
+      }
+    }
+  }
+}
+
+// Every lane of the wave calls it with the same n (out-degree <= 64 K).
+template <int K, typename AdjT, typename KeyT>
+__device__ __forceinline__ void sig_wave_multi_node(const SigArgs<AdjT, KeyT>& a, uint32_t n, uint32_t beg,
+                                                    uint32_t deg) {
+  const uint32_t lane = __lane_id();
+  KeyT k[K];
+#pragma unroll
+  for (uint32_t q = 0; q < K; ++q) {  // coalesced loads; the sort places them
+    const uint32_t j = q * kWave + lane;
+    k[q] = j < deg ? a.key_of(a.adj[beg + j]) : ~KeyT(0);
+  }
+  wave_bitonic_k<K>(k);
+  // first of each run of equal keys, in sorted order
+  const KeyT before = __shfl_up(k[K - 1], 1, kWave);
+  uint32_t first = 0;
+#pragma unroll
+  for (uint32_t q = 0; q < K; ++q) {
+    const uint32_t i = lane * K + q;
+    const KeyT pv = q == 0 ? before : k[q > 0 ? q - 1 : 0];
+    if (i < deg && (i == 0 || k[q] != pv)) first |= 1u << q;
+  }
+  const uint32_t c = uint32_t(__popc(first));
+  const uint32_t incl = wave_inclusive_scan(c);
+  uint32_t r = incl - c;
+  uint64_t hv = 0;
+#pragma unroll
+  for (uint32_t q = 0; q < K; ++q) {
+    if ((first >> q) & 1u) {
+      a.ukey[beg + r] = k[q];
+      if (r < a.hw)
+        hv |= a.hdbits >= 64 ? uint64_t(k[q]) + 1ull : (uint64_t(k[q]) + 1ull) << ((a.hw - 1 - r) * a.hdbits);
+      ++r;
+    }
+  }
+  hv = wave_or(hv);
+  const uint32_t total = __shfl(incl, kWave - 1, kWave);
+  if (lane == 0) {
+    a.ucnt[n] = total;
+    a.head[n] = hv;
+  }
+}
+
+template <typename AdjT, typename KeyT>
+__device__ __forceinline__ void sig_mid_node(const SigArgs<AdjT, KeyT>& a, uint32_t n) {
+  const uint32_t beg = a.rowptr[n];
+  const uint32_t deg = a.rowptr[n + 1] - beg;
+  if (deg <= 2 * kWave)
+    sig_wave_multi_node<2>(a, n, beg, deg);
+  else if (deg <= 4 * kWave)
+    sig_wave_multi_node<4>(a, n, beg, deg);
+  else
+    sig_wave_multi_node<8>(a, n, beg, deg);
 }
 
 // ---- one workgroup per node, 64 < out-degree <= 4096 ----------------------------
@@ -376,7 +478,7 @@ __global__ __launch_bounds__(kSigNT) void sig_hub_list_k(SigArgs<AdjT, KeyT> a, 
   __shared__ uint32_t shs[kSigNT / kWave];
   const uint32_t h = blockIdx.x;
   const uint32_t n = w.hl[h];
-  const uint32_t slot = w.nb + h;
+  const uint32_t slot = w.hub_slot0() + h;
   const uint32_t* src = w.bm + size_t(slot) * w.words;
   for (uint32_t j = threadIdx.x; j < w.words; j += kSigNT) bits[j] = src[j];
   __syncthreads();
@@ -492,7 +594,7 @@ __global__ __launch_bounds__(kSigNT) void signature_k(SigArgs<AdjT, KeyT> a, Sig
     const uint32_t h = b / w.hub_units;
     const uint32_t n = w.hl[h];
     if (w.bm)
-      sig_bitmap_node(a, n, w, w.nb + h, b % w.hub_units, w.hub_units, lds.bm.bits[0], lds.bm.shs);
+      sig_bitmap_node(a, n, w, w.hub_slot0() + h, b % w.hub_units, w.hub_units, lds.bm.bits[0], lds.bm.shs);
     else
       sig_hub_node(a, n, static_cast<KeyT*>(w.hub_tmp) + w.hub_toff[n], w.key_bits, lds.hub);
     return;
@@ -501,13 +603,20 @@ __global__ __launch_bounds__(kSigNT) void signature_k(SigArgs<AdjT, KeyT> a, Sig
   if (b < w.block_units()) {
     if (w.bm) {
       const uint32_t bi = b * (kSigNT / kWave) + threadIdx.x / kWave;
-      if (bi < w.nb) sig_bitmap_wave_node(a, w.bl[bi], w, bi, lds.bm.bits[threadIdx.x / kWave]);
+      if (bi < w.nm + w.nb)
+        sig_bitmap_wave_node(a, bi < w.nm ? w.ml[bi] : w.bl[bi - w.nm], w, bi, lds.bm.bits[threadIdx.x / kWave]);
     } else {
       sig_block_node(a, w.bl[b], lds.block, shc);
     }
     return;
   }
   b -= w.block_units();
+  if (b < w.mid_units()) {
+    const uint32_t mi = b * (kSigNT / kWave) + threadIdx.x / kWave;
+    if (mi < w.nm) sig_mid_node(a, w.ml[mi]);
+    return;
+  }
+  b -= w.mid_units();
   if (b < w.wave_units()) {
     const uint32_t wi = b * (kSigNT / kWave) + threadIdx.x / kWave;
     if (wi < w.nw) sig_wave_node(a, w.wl[wi]);

@@ -71,9 +71,9 @@ def test_host_inputs():
 
 
 def test_degree_buckets():
-    """Out-degrees at every bucket edge: 0, 1, 15..17, 63..65, 4095..4097 and a
-    20k hub, among 3k low-degree nodes."""
-    degs = [0, 1, 15, 16, 17, 63, 64, 65, 4095, 4096, 4097, 20000] * 2
+    """Out-degrees at every bucket edge: 0, 1, 15..17, 63..65, 128/129,
+    256/257, 512/513, 4095..4097 and a 20k hub, among 3k low-degree nodes."""
+    degs = [0, 1, 15, 16, 17, 63, 64, 65, 128, 129, 256, 257, 512, 513, 4095, 4096, 4097, 20000] * 2
     g = synth.degree_graph(degs + [2] * 3000, num_node_labels=2, num_edge_labels=3, seed=3,
                            name="degrees")
     check_parity(g, 6)
