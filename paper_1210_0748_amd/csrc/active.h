@@ -31,31 +31,48 @@ constexpr int kInfoWords = kInfoHubEdges + 1;
 // apos[j] = position of active item j, anode[j] = ord[apos[j]]; segment t of
 // the list covers positions [seg_s[t], seg_s[t] + size), soff is the
 // exclusive scan of the sizes (soff[S] = number of items), S = *s_dev.
-// Thread 0 also records the number of items in info.
+// Thread 0 of workgroup 0 also records the number of items in info.
 // actr[anode[j]] = tag marks the active nodes of the round (unless actr is
-// null: marked by the caller).
-__global__ void expand_k(const uint32_t* __restrict__ seg_s, const uint32_t* __restrict__ soff,
-                         const uint32_t* __restrict__ s_dev, uint32_t m_cap, const uint32_t* __restrict__ ord,
-                         uint32_t* __restrict__ apos, uint32_t* __restrict__ anode, uint32_t* __restrict__ actr,
-                         uint32_t tag, uint32_t* __restrict__ info) {
-  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t S = *s_dev;
-  const uint32_t M = soff[S];
-  if (j == 0) info[kInfoItems] = M;
-  if (j >= m_cap || j >= M) return;
-  uint32_t lo = 0, hi = S;  // last t with soff[t] <= j
-  while (hi - lo > 1) {
+// null: marked by the caller). One tile of kExpandTile items per workgroup:
+// the segments of the tile's first and last items are found once, items in
+// between search only that range.
+constexpr uint32_t kExpandTile = 2048;
+__device__ __forceinline__ uint32_t seg_of(const uint32_t* soff, uint32_t lo, uint32_t hi, uint32_t j) {
+  while (hi - lo > 1) {  // last t in [lo, hi) with soff[t] <= j
     const uint32_t mid = (lo + hi) >> 1;
     if (soff[mid] <= j)
       lo = mid;
     else
       hi = mid;
   }
-  const uint32_t p = seg_s[lo] + (j - soff[lo]);
-  const uint32_t u = ord[p];
-  apos[j] = p;
-  anode[j] = u;
-  if (actr) actr[u] = tag;
+  return lo;
+}
+__global__ __launch_bounds__(256) void expand_k(const uint32_t* __restrict__ seg_s, const uint32_t* __restrict__ soff,
+                                                const uint32_t* __restrict__ s_dev, uint32_t m_cap,
+                                                const uint32_t* __restrict__ ord, uint32_t* __restrict__ apos,
+                                                uint32_t* __restrict__ anode, uint32_t* __restrict__ actr,
+                                                uint32_t tag, uint32_t* __restrict__ info) {
+  __shared__ uint32_t range[2];
+  const uint32_t S = *s_dev;
+  const uint32_t M = soff[S] < m_cap ? soff[S] : m_cap;
+  if (blockIdx.x == 0 && threadIdx.x == 0) info[kInfoItems] = soff[S];
+  const uint32_t t0 = blockIdx.x * kExpandTile;
+  if (t0 >= M) return;  // uniform over the workgroup
+  const uint32_t t1 = t0 + kExpandTile < M ? t0 + kExpandTile : M;
+  if (threadIdx.x == 0) {
+    range[0] = seg_of(soff, 0, S, t0);
+    range[1] = seg_of(soff, 0, S, t1 - 1);
+  }
+  __syncthreads();
+  const uint32_t lo = range[0], hi = range[1];
+  for (uint32_t j = t0 + threadIdx.x; j < t1; j += blockDim.x) {
+    const uint32_t t = lo == hi ? lo : seg_of(soff, lo, hi + 1, j);
+    const uint32_t p = seg_s[t] + (j - soff[t]);
+    const uint32_t u = ord[p];
+    apos[j] = p;
+    anode[j] = u;
+    if (actr) actr[u] = tag;
+  }
 }
 
 // Out-degree bucket of an active node for the signature kernel: wave (17..64

@@ -392,7 +392,7 @@ uint32_t* Engine::compact_scratch(uint64_t words) {
 void Engine::prepare_active(uint32_t seg_items, uint32_t m_cap, uint32_t tag, bool mark) {
   uint32_t* info = info_.as<uint32_t>();
   scan_dev<uint32_t, uint32_t, false>(act_.size.as<uint32_t>(), soff_.as<uint32_t>(), uint64_t(seg_items) + 1);
-  expand_k<<<grid_for(m_cap), kNT, 0, st_>>>(act_.start.as<uint32_t>(), soff_.as<uint32_t>(),
+  expand_k<<<std::max<uint32_t>(1, ceil_div(m_cap, kExpandTile)), 256, 0, st_>>>(act_.start.as<uint32_t>(), soff_.as<uint32_t>(),
                                              info + kInfoSeg + 2 * kSegClasses, m_cap, ord_.as<uint32_t>(),
                                              apos_.as<uint32_t>(), anode_.as<uint32_t>(),
                                              mark ? actr_.as<uint32_t>() : nullptr, tag, info);
@@ -694,7 +694,7 @@ void Engine::hub_sort(const void* sig_args, const uint32_t* hl, uint32_t nh, int
   CompT* k0 = hub_k0_.as<CompT>();
   CompT* k1 = hub_k1_.as<CompT>();
   uint32_t* fl = hub_fl_.as<uint32_t>();
-  hub_keys_k<AdjT, KeyT, CompT><<<grid_for(H), kNT, 0, st_>>>(a, hl, hoff, nh, H, key_bits, k0);
+  hub_keys_k<AdjT, KeyT, CompT><<<ceil_div(H, kHubKeyTile), 256, 0, st_>>>(a, hl, hoff, nh, H, key_bits, k0);
   KB_LAUNCH_CHECK();
   const bool f = radix_sort<CompT>(k0, static_cast<uint32_t*>(nullptr), k1, static_cast<uint32_t*>(nullptr), H, 0,
                                    hub_bits + key_bits, radix_scratch(H), st_);

@@ -644,22 +644,37 @@ __global__ __launch_bounds__(kSigNT) void signature_k(SigArgs<AdjT, KeyT> a, Sig
 // device-wide radix sort: hub h of the hub list owns items [hoff[h],
 // hoff[h+1]) (exclusive scan of the hub out-degrees).
 
-// comp[i] = (h << key_bits) | key of item i.
-template <typename AdjT, typename KeyT, typename CompT>
-__global__ void hub_keys_k(SigArgs<AdjT, KeyT> a, const uint32_t* __restrict__ hl, const uint32_t* __restrict__ hoff,
-                           uint32_t nh, uint32_t n_items, int key_bits, CompT* __restrict__ comp) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_items) return;
-  uint32_t lo = 0, hi = nh;  // last h with hoff[h] <= i
-  while (hi - lo > 1) {
+// comp[i] = (h << key_bits) | key of item i. One tile of kHubKeyTile items
+// per workgroup: the hubs of its first and last items are found once.
+constexpr uint32_t kHubKeyTile = 2048;
+__device__ __forceinline__ uint32_t hub_of(const uint32_t* hoff, uint32_t lo, uint32_t hi, uint32_t i) {
+  while (hi - lo > 1) {  // last h in [lo, hi) with hoff[h] <= i
     const uint32_t mid = (lo + hi) >> 1;
     if (hoff[mid] <= i)
       lo = mid;
     else
       hi = mid;
   }
-  const uint32_t e = a.rowptr[hl[lo]] + (i - hoff[lo]);
-  comp[i] = (CompT(lo) << key_bits) | CompT(a.key_of(a.adj[e]));
+  return lo;
+}
+template <typename AdjT, typename KeyT, typename CompT>
+__global__ __launch_bounds__(256) void hub_keys_k(SigArgs<AdjT, KeyT> a, const uint32_t* __restrict__ hl,
+                                                  const uint32_t* __restrict__ hoff, uint32_t nh, uint32_t n_items,
+                                                  int key_bits, CompT* __restrict__ comp) {
+  __shared__ uint32_t range[2];
+  const uint32_t t0 = blockIdx.x * kHubKeyTile;
+  const uint32_t t1 = t0 + kHubKeyTile < n_items ? t0 + kHubKeyTile : n_items;
+  if (threadIdx.x == 0) {
+    range[0] = hub_of(hoff, 0, nh, t0);
+    range[1] = hub_of(hoff, 0, nh, t1 - 1);
+  }
+  __syncthreads();
+  const uint32_t lo = range[0], hi = range[1];
+  for (uint32_t i = t0 + threadIdx.x; i < t1; i += blockDim.x) {
+    const uint32_t h = lo == hi ? lo : hub_of(hoff, lo, hi + 1, i);
+    const uint32_t e = a.rowptr[hl[h]] + (i - hoff[h]);
+    comp[i] = (CompT(h) << key_bits) | CompT(a.key_of(a.adj[e]));
+  }
 }
 
 // fl[i] = 1 where a run of equal (hub, key) starts; fl[n] = 0.
