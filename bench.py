@@ -91,7 +91,7 @@ def main():
     ap.add_argument("--form", choices=["plain", "batched", "served"], default="plain")
     ap.add_argument("--graphs", type=int, default=512, help="batched: number of graphs")
     ap.add_argument("--requests", type=int, default=300, help="served: number of requests")
-    ap.add_argument("--max-nodes", type=int, default=2_000_000, help="served: largest request")
+    ap.add_argument("--max-nodes", type=int, default=10_000_000, help="served: largest request")
     ap.add_argument("--slots", type=int, default=4, help="served: concurrent slots")
     args = ap.parse_args()
     if args.gpus != 1:
