@@ -205,6 +205,7 @@ class Engine {
   // each other: groups of one workgroup of 1024 threads on side_big_, all
   // smaller ones on side_
   hipStream_t side_ = nullptr, side_big_ = nullptr;
+  int side_dev_ = 0;  // device of the resolver streams
   hipEvent_t ev_side_[2] = {nullptr, nullptr}, ev_big_[2] = {nullptr, nullptr};
   hipEvent_t ev_main_ = nullptr, ev_join_ = nullptr, ev_join_big_ = nullptr;
 

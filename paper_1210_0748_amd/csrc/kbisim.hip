@@ -43,19 +43,23 @@ Engine::~Engine() {
   }
   for (hipStream_t q : {side_, side_big_}) {
     if (!q) continue;
-    (void)hipStreamSynchronize(q);
-    (void)hipStreamDestroy(q);
+    if (hipStreamSynchronize(q) == hipSuccess)
+      StreamPool::instance().put(q, side_dev_);
+    else
+      (void)hipGetLastError();  // a stream in an error state is not reused
   }
   for (hipEvent_t e : {ev_side_[0], ev_side_[1], ev_big_[0], ev_big_[1], ev_main_, ev_join_, ev_join_big_})
     if (e) (void)hipEventDestroy(e);
 }
 
 // Streams for the resolvers (default priority, not synchronising with the
-// null stream) and the events that order them against the handle's.
+// null stream; from the process-wide pool) and the events that order them
+// against the handle's.
 hipStream_t Engine::side_stream() {
   if (!side_) {
-    KB_CHECK(hipStreamCreateWithFlags(&side_, hipStreamNonBlocking));
-    KB_CHECK(hipStreamCreateWithFlags(&side_big_, hipStreamNonBlocking));
+    KB_CHECK(hipGetDevice(&side_dev_));
+    side_ = StreamPool::instance().get();
+    side_big_ = StreamPool::instance().get();
     for (hipEvent_t* e : {&ev_side_[0], &ev_side_[1], &ev_big_[0], &ev_big_[1], &ev_main_, &ev_join_, &ev_join_big_})
       KB_CHECK(hipEventCreateWithFlags(e, hipEventDisableTiming));
   }
@@ -171,8 +175,14 @@ void Engine::build_adj(const int32_t* src, const int32_t* lab, const int32_t* ds
     max_degree_k<<<std::min<uint32_t>(grid_for(N), 1024), kNT, 0, st_>>>(rowptr_.as<uint32_t>(), uint32_t(N),
                                                                        hd.as<uint32_t>());
     KB_LAUNCH_CHECK();
-    hub_edges_ = read_word(hub_toff_.as<uint32_t>() + N, 4);
-    maxdeg_ = uint32_t(read_word(hd.p, 4));  // synchronises: `hd` may be freed
+    // both words in one read-back (synchronises: `hd` may be freed)
+    uint32_t* hw32 = reinterpret_cast<uint32_t*>(hw_.p);
+    hw32[0] = hw32[1] = 0;
+    KB_CHECK(hipMemcpyAsync(hw32, hub_toff_.as<uint32_t>() + N, 4, hipMemcpyDeviceToHost, st_));
+    KB_CHECK(hipMemcpyAsync(hw32 + 1, hd.p, 4, hipMemcpyDeviceToHost, st_));
+    KB_CHECK(hipStreamSynchronize(st_));
+    hub_edges_ = hw32[0];
+    maxdeg_ = hw32[1];
   }
 }
 

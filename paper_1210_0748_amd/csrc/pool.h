@@ -16,6 +16,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "common.h"
@@ -178,6 +179,42 @@ class PinnedSlots {
  private:
   std::mutex mu_;
   std::vector<uint64_t*> free_;
+};
+
+// Non-blocking streams of default priority for the resolvers of a graph
+// handle, kept per device for the life of the process: creating and
+// destroying two streams per job costs about 0.2 ms. A returned stream has
+// been synchronised by its user.
+class StreamPool {
+ public:
+  static StreamPool& instance() {
+    static StreamPool* p = new StreamPool();  // never destroyed, like the streams
+    return *p;
+  }
+  hipStream_t get() {
+    int dev = 0;
+    KB_CHECK(hipGetDevice(&dev));
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      for (size_t i = 0; i < free_.size(); ++i) {
+        if (free_[i].first != dev) continue;
+        const hipStream_t s = free_[i].second;
+        free_.erase(free_.begin() + long(i));
+        return s;
+      }
+    }
+    hipStream_t s = nullptr;
+    KB_CHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    return s;
+  }
+  void put(hipStream_t s, int dev) {
+    std::lock_guard<std::mutex> lk(mu_);
+    free_.emplace_back(dev, s);
+  }
+
+ private:
+  std::mutex mu_;
+  std::vector<std::pair<int, hipStream_t>> free_;
 };
 
 // Stream on which the calling thread's library work runs; device buffers
