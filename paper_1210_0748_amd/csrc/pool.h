@@ -61,7 +61,7 @@ class Pool {
           (void)hipFree(b.p);
           KB_CHECK(e1);
         }
-        (void)hipEventDestroy(b.ev);
+        put_event(b.ev, dev);  // the wait (if any) is queued: the event may be recorded again
       }
       *got = b.bytes;
       return b.p;
@@ -85,9 +85,8 @@ class Pool {
     if (!p) return;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) dev = 0;
-    Blk b{p, bytes, s, dev, nullptr};
-    if (hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) != hipSuccess ||
-        hipEventRecord(b.ev, s) != hipSuccess) {
+    Blk b{p, bytes, s, dev, get_event(dev)};
+    if (!b.ev || hipEventRecord(b.ev, s) != hipSuccess) {
       // cannot order a later reuse: give the block back to the runtime
       (void)hipGetLastError();
       if (b.ev) (void)hipEventDestroy(b.ev);
@@ -130,6 +129,29 @@ class Pool {
     int dev;
     hipEvent_t ev;
   };
+  // Events of the current device are reused (a create and destroy per block
+  // and job add up); nullptr when none can be created.
+  hipEvent_t get_event(int dev) {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      for (size_t i = free_ev_.size(); i-- > 0;) {
+        if (free_ev_[i].first != dev) continue;
+        const hipEvent_t e = free_ev_[i].second;
+        free_ev_.erase(free_ev_.begin() + long(i));
+        return e;
+      }
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    return e;
+  }
+  void put_event(hipEvent_t e, int dev) {
+    std::lock_guard<std::mutex> lk(mu_);
+    free_ev_.emplace_back(dev, e);
+  }
   static size_t round(size_t b) {
     if (b == 0) b = 1;
     const size_t g = b >= (size_t(1) << 20) ? (size_t(1) << 20) : 256;
@@ -137,6 +159,7 @@ class Pool {
   }
   std::mutex mu_;
   std::multimap<size_t, Blk> free_;
+  std::vector<std::pair<int, hipEvent_t>> free_ev_;
   size_t cached_ = 0;
 };
 
