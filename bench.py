@@ -114,7 +114,7 @@ def main():
         return bench_served(args, torch, kb, dev)
 
     t0 = time.perf_counter()
-    g, k_default = synth.make_config(args.workload, seed=args.seed)
+    g, k_default = synth.make_config(args.workload, seed=args.seed, progress=log)
     k = args.k if args.k is not None else k_default
     log("generated %s: N=%d E=%d in %.1f s" % (args.workload, g.num_nodes, g.num_edges,
                                                 time.perf_counter() - t0))
@@ -130,7 +130,7 @@ def main():
             rd = kb.kbisim_refine(h, k)
             nb, counts = kb.kbisim_result(h, out, counts_cap=k + 1)
             prof = kb.kbisim_profile(h) if profile else None
-            work = kb.kbisim_work(h) if profile else None
+            work = (kb.kbisim_work(h), kb.kbisim_round_profile(h)) if profile else None
         finally:
             kb.kbisim_destroy(h)
         return rd, counts, prof, work
@@ -167,7 +167,7 @@ def main():
 
     # One extra profiled step (HIP events on the library's stream around each
     # launch) for the per-kernel roofline; not part of the timed region.
-    rd_p, counts_p, prof, work = step(True)
+    rd_p, counts_p, prof, (work, per_round) = step(True)
     assert counts_p == counts
     log("profile: " + json.dumps(prof))
     log("work: " + json.dumps(work))
@@ -181,7 +181,9 @@ def main():
     achieved = algo_bytes_per_launch / (avg_ms / 1e3) / 1e9
     traffic = load_traffic(dom)
     line = {
-        "metric": "edge-rounds/s (|E|*rounds/time), 10M-node/100M-edge power-law graph to fixed point",
+        "metric": ("edge-rounds/s (|E|*rounds/time), 10M-node/100M-edge power-law graph to fixed point"
+                   if args.workload == "powerlaw-10M-100M" else
+                   "edge-rounds/s (|E|*rounds/time), %s to fixed point (cap k)" % args.workload),
         "value": value,
         "unit": "edge-rounds/s",
         "n_gpus": 1,
@@ -201,6 +203,12 @@ def main():
                      "traffic": traffic,
                      "launch_avg_ms": avg_ms, "algo_bytes_per_launch": algo_bytes_per_launch},
         "kernel_ms": {c: prof[c][0] for c in prof},
+        # round by round: the signature launch's algorithmic GB/s and the round's time
+        "rounds": [{"round": r + 1, "active_nodes": x["active_nodes"], "active_edges": x["active_edges"],
+                    "signature_ms": x["signature_ms"], "round_ms": x["round_ms"],
+                    "signature_gbs": (BYTES_PER_EDGE * x["active_edges"] + BYTES_PER_NODE * x["active_nodes"])
+                    / max(x["signature_ms"], 1e-9) / 1e6}
+                   for r, x in enumerate(per_round)],
     }
     if not args.no_cpu_baseline:
         log("timing the oracle on the host ...")

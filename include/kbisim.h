@@ -117,8 +117,10 @@ typedef enum {
 typedef enum {
   KBISIM_BUCKET_THREAD = 0, /* <= 16 edges: one thread per node */
   KBISIM_BUCKET_WAVE = 1,   /* <= 64 edges: one wave per node */
-  KBISIM_BUCKET_BLOCK = 2,  /* <= 4096 edges: one workgroup per node */
-  KBISIM_BUCKET_HUB = 3,    /* more edges: one workgroup per node */
+  KBISIM_BUCKET_BLOCK = 2,  /* <= 4096 edges: one wave (<= 512 edges, or key-set bitmaps) or
+                               one workgroup per node */
+  KBISIM_BUCKET_HUB = 3,    /* more edges: all hubs of a round in one device-wide sort (or
+                               in chunks of one workgroup each with key-set bitmaps) */
   KBISIM_BUCKET_COUNT = 4
 } kbisim_bucket;
 
@@ -134,6 +136,22 @@ kbisim_status kbisim_profile(const kbisim_graph* g, double* ms, int64_t* launche
  * nodes_edges[2c+1] = their out-edges. Only active nodes (members of classes
  * with two or more members) are processed and counted. cap = entries (8). */
 kbisim_status kbisim_work(const kbisim_graph* g, int64_t* nodes_edges, int32_t cap, int32_t reset);
+
+/* One refinement round as recorded when options.profile = 1. */
+typedef struct {
+  double signature_ms; /* the signature launch(es) of the round (HIP events) */
+  double round_ms;     /* the whole round: signatures, ordering, id assignment */
+  int64_t active_nodes; /* nodes whose signature the round computed */
+  int64_t active_edges; /* their out-edges */
+} kbisim_round_stat;
+
+/* Per-round profile when options.profile = 1 (round-by-round rates of the
+ * signature launch, Algorithm 1's iterations): stats[r-1] for round r of the
+ * rounds computed since create or the last reset; *n (may be NULL) receives
+ * their number, of which min(*n, cap) are written. Counts of rounds past the
+ * 64th accumulate in the 64th entry. reset != 0 clears after reading. */
+kbisim_status kbisim_round_profile(const kbisim_graph* g, kbisim_round_stat* stats, int32_t cap, int32_t* n,
+                                   int32_t reset);
 
 /* Frees everything owned by the handle. NULL is ignored. */
 void kbisim_destroy(kbisim_graph* g);

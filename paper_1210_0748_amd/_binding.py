@@ -65,6 +65,8 @@ def load_library():
     lib.kbisim_profile.restype = ctypes.c_int
     lib.kbisim_work.argtypes = [vp, vp, i32, i32]
     lib.kbisim_work.restype = ctypes.c_int
+    lib.kbisim_round_profile.argtypes = [vp, ctypes.POINTER(RoundStat), i32, ctypes.POINTER(i32), i32]
+    lib.kbisim_round_profile.restype = ctypes.c_int
     lib.kbisim_release_cached.argtypes = [ctypes.POINTER(i64)]
     lib.kbisim_release_cached.restype = ctypes.c_int
     lib.kbisim_batch_create.argtypes = [i32, vp, vp, ctypes.POINTER(GraphDesc), ctypes.POINTER(Options),
@@ -212,6 +214,20 @@ def kbisim_work(handle, reset=False):
     return {WORK_BUCKETS[c]: (int(w[2 * c]), int(w[2 * c + 1])) for c in range(4)}
 
 
+class RoundStat(ctypes.Structure):
+    _fields_ = [("signature_ms", ctypes.c_double), ("round_ms", ctypes.c_double),
+                ("active_nodes", ctypes.c_int64), ("active_edges", ctypes.c_int64)]
+
+
+def kbisim_round_profile(handle, reset=False, cap=64):
+    """Per round (profile mode): dicts with signature_ms, round_ms,
+    active_nodes, active_edges."""
+    buf = (RoundStat * cap)()
+    n = ctypes.c_int32(0)
+    _check(load_library().kbisim_round_profile(handle, buf, cap, ctypes.byref(n), 1 if reset else 0))
+    return [{f: getattr(buf[r], f) for f, _ in RoundStat._fields_} for r in range(min(n.value, cap))]
+
+
 def kbisim_release_cached():
     """Frees the library's cache of device memory; returns the bytes released."""
     b = ctypes.c_int64(0)
@@ -253,6 +269,9 @@ class Graph:
 
     def work(self, reset=False):
         return kbisim_work(self._h, reset)
+
+    def round_profile(self, reset=False):
+        return kbisim_round_profile(self._h, reset)
 
     def close(self):
         if self._h:

@@ -26,7 +26,8 @@ constexpr int kBucketWave = 0, kBucketMid = 1, kBucketBlock = 2, kBucketHub = 3;
 constexpr int kInfoClasses = kInfoBucket + 2 * kNumBuckets + 1;  // classes among the active positions
 constexpr int kInfoItems = kInfoClasses + 1;         // positions of the next active segments
 constexpr int kInfoHubEdges = kInfoItems + 1;        // edges of the hubs in the hub list
-constexpr int kInfoWords = kInfoHubEdges + 1;
+constexpr int kInfoLargeItems = kInfoHubEdges + 1;   // items in the large segments
+constexpr int kInfoWords = kInfoLargeItems + 1;
 
 // apos[j] = position of active item j, anode[j] = ord[apos[j]]; segment t of
 // the list covers positions [seg_s[t], seg_s[t] + size), soff is the

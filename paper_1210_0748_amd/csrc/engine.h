@@ -76,6 +76,8 @@ constexpr int kProfClasses = 4;  // signature launch, ordering, assignment, whol
 constexpr int kNumSegLists = 7;
 struct SegLists {
   DevBuf start, size, depth;
+  DevBuf ioff;               // item offsets of the large groups (exclusive scan of their sizes)
+  uint32_t large_items = 0;  // items in the large groups
   uint32_t cnt[kNumSegLists] = {};
   uint32_t off[kNumSegLists] = {};
   uint32_t total() const {
@@ -121,6 +123,15 @@ class Engine {
   // per signature bucket: active nodes and their edges, summed over rounds
   void work_counts(uint64_t* out8);
   void reset_work();
+  // per round (profiling): signature and round milliseconds, active nodes
+  // and edges; rounds past kRoundSlots share the last slot's counts
+  struct RoundStat {
+    double sig_ms = 0, round_ms = 0;
+    uint64_t nodes = 0, edges = 0;
+  };
+  static constexpr int kRoundSlots = 64;
+  std::vector<RoundStat> round_stats();
+  void reset_round_stats();
   int adj_bytes() const { return adj64_ ? 8 : 4; }
   int key_bytes() const { return key64_ ? 8 : 4; }
   uint32_t num_edge_labels() const { return n_elab_; }
@@ -140,6 +151,7 @@ class Engine {
   template <typename KeyT>
   void resolve_lists(SegLists& L, const void* kv, hipStream_t s_small, hipStream_t s_big);
   hipStream_t side_stream();
+  void large_offsets(SegLists& L, const uint32_t* meta, uint32_t* total, uint64_t items);
   void make_lists(const uint32_t* seg_start, const uint32_t* seg_size, const uint32_t* seg_depth,
                   const uint8_t* seg_done, uint32_t nseg, SegLists& out, const uint32_t* nseg_dev = nullptr);
   void assign_round();
@@ -198,7 +210,7 @@ class Engine {
   DevBuf ukey_, ucnt_, head_, cls_, fl_, first_, scanpart_, radix_, part_, bm_, bmslot_;
   DevBuf seg_start_, seg_size_, seg_depth_, seg_done_, cls_meta_;
   SegLists lists_b_[2];  // subgroup lists of alternate global passes
-  DevBuf l_ioff_, l_fd_, l_long_, l_open_;
+  DevBuf l_fd_, l_long_;
   DevBuf k0_, k1_, k2_, k3_, k4_, v0_, v1_, v2_, v3_, v4_, sflag_, soff2_, ipos_, sub_item_;
 
   // the resolvers run on two more streams, overlapping the global passes and
@@ -213,9 +225,12 @@ class Engine {
   struct EvPair {
     hipEvent_t a, b;
     int cls;
+    int round;  // round being computed when recorded (1-based)
   };
   std::vector<EvPair> ev_pool_;
-  DevBuf work_;
+  std::vector<RoundStat> round_ms_;  // milliseconds per round (counts come from work_)
+  int32_t round_base_ = 0;           // rounds before the last reset of the round stats
+  DevBuf work_;                      // kRoundSlots x 8 counters (per round: 4 buckets x nodes, edges)
   size_t ev_used_ = 0;
 };
 

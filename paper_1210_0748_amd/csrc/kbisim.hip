@@ -94,6 +94,7 @@ int Engine::ev_begin(int cls) {
   }
   const int slot = int(ev_used_++);
   ev_pool_[slot].cls = cls;
+  ev_pool_[slot].round = rounds_ + 1;
   KB_CHECK(hipEventRecord(ev_pool_[slot].a, st_));
   return slot;
 }
@@ -111,6 +112,11 @@ void Engine::ev_collect() {
     KB_CHECK(hipEventElapsedTime(&ms, ev_pool_[i].a, ev_pool_[i].b));
     prof_ms[ev_pool_[i].cls] += ms;
     prof_n[ev_pool_[i].cls] += 1;
+    const int r = ev_pool_[i].round - round_base_;
+    if (r >= 1 && (ev_pool_[i].cls == 0 || ev_pool_[i].cls == 3)) {
+      if (round_ms_.size() < size_t(r)) round_ms_.resize(size_t(r));
+      (ev_pool_[i].cls == 0 ? round_ms_[size_t(r) - 1].sig_ms : round_ms_[size_t(r) - 1].round_ms) += ms;
+    }
   }
   ev_used_ = 0;
 }
@@ -381,6 +387,7 @@ void Engine::build(const int32_t* node_label, const int32_t* src, const int32_t*
                                        act_.depth.as<uint32_t>()},
                          uint32_t(B_), nullptr, compact_scratch(compact_part_words<kSegClasses>(B_)),
                          info_.as<uint32_t>() + kInfoSeg, st_);
+    large_offsets(act_, info_.as<uint32_t>() + kInfoSeg, info_.as<uint32_t>() + kInfoLargeItems, N);
     prepare_active(uint32_t(B_), uint32_t(N), 1u, false);  // active marks written above
   }
   KB_CHECK(hipStreamSynchronize(st_));
@@ -436,6 +443,7 @@ void Engine::prepare_active(uint32_t seg_items, uint32_t m_cap, uint32_t tag, bo
   S_act_ = h[kInfoSeg + 2 * kSegClasses];
   M_act_ = h[kInfoItems];
   hub_edges_act_ = h[kInfoHubEdges];
+  act_.large_items = h[kInfoLargeItems];
   for (int c = 0; c < kNumBuckets; ++c) {
     bcnt_[c] = h[kInfoBucket + c];
     boff_[c] = h[kInfoBucket + kNumBuckets + c];
@@ -466,6 +474,7 @@ void Engine::assign_round() {
                                         act_.size.as<uint32_t>(), act_.depth.as<uint32_t>()},
                        M, info + kInfoClasses, compact_scratch(compact_part_words<kSegClasses>(M)),
                        info + kInfoSeg, st_);
+  large_offsets(act_, info + kInfoSeg, info + kInfoLargeItems, M);
   prepare_active(M, M, uint32_t(rounds_) + 2, true);  // runs inside round rounds_ + 1
 }
 
@@ -476,23 +485,35 @@ void Engine::make_lists(const uint32_t* seg_start, const uint32_t* seg_size, con
                         const uint8_t* seg_done, uint32_t nseg, SegLists& out, const uint32_t* nseg_dev) {
   static_assert(kNumSegLists == kSegClasses, "list count");
   for (int c = 0; c < kNumSegLists; ++c) out.cnt[c] = out.off[c] = 0;
+  out.large_items = 0;
   if (nseg == 0) return;
   const uint32_t med = std::min(medium_cap(), kMediumCapSmall), big = medium_cap();
-  cls_meta_.ensure((2 * kSegClasses + 1) * 4);
+  cls_meta_.ensure((2 * kSegClasses + 2) * 4);
   for (DevBuf* b : {&out.start, &out.size, &out.depth}) b->ensure(uint64_t(nseg) * 4);
   compact<kSegClasses>(SegClassOf{seg_size, seg_done, med, big},
                        SegCopy{seg_start, seg_size, seg_depth, out.start.as<uint32_t>(), out.size.as<uint32_t>(),
                                out.depth.as<uint32_t>()},
                        nseg, nseg_dev, compact_scratch(compact_part_words<kSegClasses>(nseg)),
                        cls_meta_.as<uint32_t>(), st_);
+  large_offsets(out, cls_meta_.as<uint32_t>(), cls_meta_.as<uint32_t>() + 2 * kSegClasses + 1, nseg);
   uint32_t* hw32 = reinterpret_cast<uint32_t*>(hw_.p);
-  for (int c = 0; c < 2 * kSegClasses; ++c) hw32[c] = 0;  // before the copy is queued
-  KB_CHECK(hipMemcpyAsync(hw32, cls_meta_.p, 2 * kSegClasses * 4, hipMemcpyDeviceToHost, st_));
+  for (int c = 0; c < 2 * kSegClasses + 2; ++c) hw32[c] = 0;  // before the copy is queued
+  KB_CHECK(hipMemcpyAsync(hw32, cls_meta_.p, (2 * kSegClasses + 2) * 4, hipMemcpyDeviceToHost, st_));
   KB_CHECK(hipStreamSynchronize(st_));
   for (int c = 0; c < kSegClasses; ++c) {
     out.cnt[c] = hw32[c];
     out.off[c] = hw32[kSegClasses + c];
   }
+  out.large_items = hw32[2 * kSegClasses + 1];
+}
+
+// Item offsets of the large groups of a list just classified (meta on the
+// device), and their total into *total; `items` bounds the list's items.
+// Large groups have more than 64 members, so at most items / 65 + 1 of them.
+void Engine::large_offsets(SegLists& L, const uint32_t* meta, uint32_t* total, uint64_t items) {
+  L.ioff.ensure((items / 65 + 2) * 4);
+  large_offsets_k<<<1, 1024, 0, st_>>>(L.size.as<uint32_t>(), meta, L.ioff.as<uint32_t>(), total);
+  KB_LAUNCH_CHECK();
 }
 
 template <int W, typename KeyT>
@@ -551,8 +572,9 @@ void Engine::order_groups(const void* kvp) {
   const KeyView<KeyT>& kv = *static_cast<const KeyView<KeyT>*>(kvp);
   uint32_t nl = act_.cnt[kLargeClass];
   const uint32_t* Ls = act_.start.as<uint32_t>() + act_.off[kLargeClass];
-  const uint32_t* Lz = act_.size.as<uint32_t>() + act_.off[kLargeClass];
   const uint32_t* Ld = act_.depth.as<uint32_t>() + act_.off[kLargeClass];
+  uint32_t M = act_.large_items;         // items of the large groups
+  const uint32_t* gio = act_.ioff.as<uint32_t>();  // and their offsets
   int nx = 0;
   bool first_pass = true;
   const int dbits = kv.dbits;
@@ -560,14 +582,6 @@ void Engine::order_groups(const void* kvp) {
   const uint32_t head_w = dbits >= 64 ? 1u : uint32_t(64 / dbits);
   const int fd_bits = bits_for(maxdeg_ > 0 ? maxdeg_ : 1);  // first differences are below the longest sequence
   while (nl > 0) {
-    // item offsets of the large groups (sizes with a trailing zero)
-    l_ioff_.ensure((uint64_t(nl) + 1) * 4);
-    l_open_.ensure((uint64_t(nl) + 1) * 4);
-    KB_CHECK(hipMemcpyAsync(l_open_.p, Lz, uint64_t(nl) * 4, hipMemcpyDeviceToDevice, st_));
-    KB_CHECK(hipMemsetAsync(l_open_.as<uint32_t>() + nl, 0, 4, st_));
-    scan_dev<uint32_t, uint32_t, false>(l_open_.as<uint32_t>(), l_ioff_.as<uint32_t>(), uint64_t(nl) + 1);
-    const uint32_t M = uint32_t(read_word(l_ioff_.as<uint32_t>() + nl, 4));
-    const uint32_t* gio = l_ioff_.as<uint32_t>();
 
     // pivot passes: every item's first difference with its group's pivot
     if (!first_pass) {
@@ -678,8 +692,9 @@ void Engine::order_groups(const void* kvp) {
     // the next pass works on the large subgroups, read from `out`
     nl = out.cnt[kLargeClass];
     Ls = out.start.as<uint32_t>() + out.off[kLargeClass];
-    Lz = out.size.as<uint32_t>() + out.off[kLargeClass];
     Ld = out.depth.as<uint32_t>() + out.off[kLargeClass];
+    M = out.large_items;
+    gio = out.ioff.as<uint32_t>();
     nx ^= 1;
     first_pass = false;
   }
@@ -803,10 +818,12 @@ void Engine::round_impl() {
   }
   if (opt_.profile) {
     if (!work_.p) {
-      work_.ensure(8 * sizeof(unsigned long long));
-      KB_CHECK(hipMemsetAsync(work_.p, 0, 8 * sizeof(unsigned long long), st_));
+      work_.ensure(kRoundSlots * 8 * sizeof(unsigned long long));
+      KB_CHECK(hipMemsetAsync(work_.p, 0, kRoundSlots * 8 * sizeof(unsigned long long), st_));
     }
-    work_count_k<<<grid_for(M_act_), kNT, 0, st_>>>(w.anode, a.rowptr, M_act_, work_.as<unsigned long long>());
+    const int slot = std::min<int>(rounds_ - round_base_, kRoundSlots - 1);
+    work_count_k<<<grid_for(M_act_), kNT, 0, st_>>>(w.anode, a.rowptr, M_act_,
+                                                    work_.as<unsigned long long>() + 8 * std::max(slot, 0));
     KB_LAUNCH_CHECK();
   }
   const int ev = ev_begin(0);
@@ -857,12 +874,39 @@ void Engine::work_counts(uint64_t* out8) {
   StreamScope scope(st_);
   for (int i = 0; i < 8; ++i) out8[i] = 0;
   if (!work_.p) return;
-  KB_CHECK(hipMemcpyAsync(out8, work_.p, 8 * sizeof(uint64_t), hipMemcpyDeviceToHost, st_));
+  std::vector<uint64_t> all(size_t(kRoundSlots) * 8);
+  KB_CHECK(hipMemcpyAsync(all.data(), work_.p, all.size() * sizeof(uint64_t), hipMemcpyDeviceToHost, st_));
   KB_CHECK(hipStreamSynchronize(st_));
+  for (size_t r = 0; r < size_t(kRoundSlots); ++r)
+    for (int i = 0; i < 8; ++i) out8[i] += all[r * 8 + size_t(i)];
 }
 
 void Engine::reset_work() {
-  if (work_.p) KB_CHECK(hipMemsetAsync(work_.p, 0, 8 * sizeof(unsigned long long), st_));
+  if (work_.p) KB_CHECK(hipMemsetAsync(work_.p, 0, kRoundSlots * 8 * sizeof(unsigned long long), st_));
+}
+
+std::vector<Engine::RoundStat> Engine::round_stats() {
+  StreamScope scope(st_);
+  std::vector<RoundStat> out(round_ms_);
+  if (out.empty() || !work_.p) return out;
+  std::vector<uint64_t> all(size_t(kRoundSlots) * 8);
+  KB_CHECK(hipMemcpyAsync(all.data(), work_.p, all.size() * sizeof(uint64_t), hipMemcpyDeviceToHost, st_));
+  KB_CHECK(hipStreamSynchronize(st_));
+  for (size_t r = 0; r < out.size(); ++r) {
+    const size_t slot = std::min<size_t>(r, size_t(kRoundSlots) - 1);
+    for (int c = 0; c < 4; ++c) {
+      out[r].nodes += all[slot * 8 + size_t(2 * c)];
+      out[r].edges += all[slot * 8 + size_t(2 * c + 1)];
+    }
+  }
+  return out;
+}
+
+// The per-round counters restart at the next round (shared with kbisim_work).
+void Engine::reset_round_stats() {
+  round_ms_.clear();
+  round_base_ = rounds_;
+  reset_work();
 }
 
 void Engine::refine(int32_t k) {
@@ -1465,6 +1509,24 @@ kbisim_status kbisim_profile(const kbisim_graph* g, double* ms, int64_t* launche
     g->eng->prof_n.fill(0);
   }
   return KBISIM_OK;
+}
+
+kbisim_status kbisim_round_profile(const kbisim_graph* g, kbisim_round_stat* stats, int32_t cap, int32_t* n,
+                                   int32_t reset) {
+  if (!g || !g->eng) return fail(KBISIM_EINVAL, "null handle");
+  if (cap < 0 || (cap > 0 && !stats)) return fail(KBISIM_EINVAL, "bad stats buffer");
+  return guarded([&]() {
+    const std::vector<kb::Engine::RoundStat> rs = g->eng->round_stats();
+    if (n) *n = int32_t(rs.size());
+    for (size_t r = 0; r < std::min<size_t>(rs.size(), size_t(cap)); ++r) {
+      stats[r].signature_ms = rs[r].sig_ms;
+      stats[r].round_ms = rs[r].round_ms;
+      stats[r].active_nodes = int64_t(rs[r].nodes);
+      stats[r].active_edges = int64_t(rs[r].edges);
+    }
+    if (reset) g->eng->reset_round_stats();
+    return KBISIM_OK;
+  });
 }
 
 kbisim_status kbisim_work(const kbisim_graph* g, int64_t* nodes_edges, int32_t cap, int32_t reset) {

@@ -162,6 +162,61 @@ struct KeyView {
     if (ca == cb) return kNoDiff;
     return n > t ? n : t;
   }
+  // Member a against pivot b from position t, with the rows and counts of
+  // both loaded once: the first difference d (kUndecided when a window of
+  // `window` keys agrees and both continue, kNoDiff when equal) and, when d
+  // is decided, the digits of both at d (da, dl: side) and a's packed digits
+  // from d on (width positions). Saves reloading the rows for the keys.
+  struct Cmp {
+    uint32_t d;
+    uint64_t da, dl, dig;
+  };
+  __device__ __forceinline__ Cmp compare(uint32_t a, uint32_t b, uint32_t t, uint32_t window,
+                                         uint32_t width) const {
+    const uint32_t ra = rowptr[a], rb = rowptr[b];
+    const uint32_t ea = rowptr[a + 1], eb = rowptr[b + 1];
+    const uint32_t ca = ucnt[a], cb = ucnt[b];
+    const KeyT* ka = ukey + ra;
+    const KeyT* kb_ = ukey + rb;
+    Cmp c{kNoDiff, 0, 0, 0};
+    if (bm_words64 && ea - ra > bm_min_deg && eb - rb > bm_min_deg) {
+      c.d = first_diff_bm(a, b);
+    } else {
+      const uint32_t n = ca < cb ? ca : cb;
+      const uint32_t stop = n > t ? ((n - t > window) ? t + window : n) : t;
+      uint32_t j = t, d = kNoDiff;
+      for (; j + 8 <= stop && d == kNoDiff; j += 8) {
+        KeyT va[8], vb[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          va[q] = ka[j + q];
+          vb[q] = kb_[j + q];
+        }
+#pragma unroll
+        for (int q = 7; q >= 0; --q)
+          if (va[q] != vb[q]) d = j + uint32_t(q);
+      }
+      for (; j < stop && d == kNoDiff; ++j)
+        if (ka[j] != kb_[j]) d = j;
+      if (d == kNoDiff) {
+        if (stop < n) d = kUndecided;
+        else if (ca != cb) d = n > t ? n : t;
+      }
+      c.d = d;
+    }
+    if (c.d == kNoDiff || c.d == kUndecided) return c;
+    const uint32_t d = c.d;
+    c.da = d < ca ? uint64_t(ka[d]) + 1ull : 0ull;
+    c.dl = d < cb ? uint64_t(kb_[d]) + 1ull : 0ull;
+    if (width == 1 || dbits >= 64) {
+      c.dig = c.da;
+    } else {
+      uint64_t v = 0;
+      for (uint32_t q = 0; q < width; ++q) v = (v << dbits) | (d + q < ca ? uint64_t(ka[d + q]) + 1ull : 0ull);
+      c.dig = v;
+    }
+    return c;
+  }
   // first_diff computed by a whole wave, 64 positions per step; every lane
   // of the wave must call it with the same arguments.
   __device__ __forceinline__ uint32_t wave_first_diff(uint32_t a, uint32_t b, uint32_t t) const {
@@ -281,41 +336,48 @@ __global__ __launch_bounds__(NT) void resolve_k(const uint32_t* __restrict__ gst
     if (threadIdx.x == 0) qn = 0;
     __syncthreads();
 
-    // (b) first difference with the pivot: a short window per thread, then
-    // whole waves (64 positions per step)
+    // (b) first difference with the pivot and the sort key there: (side,
+    // distance of the first difference, digits from it on). A short window
+    // per thread; members whose window agreed go to whole waves (64
+    // positions per step) and get their key after.
+    bool open = false;
     for (uint32_t k = threadIdx.x; k < n; k += NT) {
       const uint32_t i = opos[k];
       const uint32_t L = sub[i];
-      uint32_t d = kNoDiff;
-      if (i != L) {
-        d = kv.first_diff_window(node[i], node[L], dep[i], kThreadWindow);
-        if (d == kUndecided) queue[atomicAdd(&qn, 1u)] = uint16_t(i);
+      if (i == L) {
+        hk[i] = side_key(1, 0);
+        dig[i] = 0;
+        continue;
       }
-      hk[i] = d;
+      const typename KeyView<KeyT>::Cmp c = kv.compare(node[i], node[L], dep[i], kThreadWindow, width);
+      if (c.d == kUndecided) {
+        queue[atomicAdd(&qn, 1u)] = uint16_t(i);
+      } else if (c.d == kNoDiff) {
+        hk[i] = side_key(1, 0);
+        dig[i] = 0;
+      } else {
+        hk[i] = side_key(c.da < c.dl ? 0u : 2u, c.d - dep[i]);
+        dig[i] = c.dig;
+        dep[i] = c.d + width;
+        open = true;
+      }
     }
     __syncthreads();
     for (uint32_t q = threadIdx.x / kWave; q < qn; q += NT / kWave) {
       const uint32_t i = queue[q];
-      const uint32_t d = kv.wave_first_diff(node[i], node[sub[i]], dep[i] + kThreadWindow);
-      if (__lane_id() == 0) hk[i] = d;
-    }
-    __syncthreads();
-
-    // (c) sort keys: (side, distance of the first difference, digits there)
-    bool open = false;
-    for (uint32_t k = threadIdx.x; k < n; k += NT) {
-      const uint32_t i = opos[k];
-      const uint32_t d = uint32_t(hk[i]);
-      if (d == kNoDiff) {
-        hk[i] = side_key(1, 0);
-        dig[i] = 0;
-      } else {
-        const uint32_t L = sub[i];
-        const uint64_t da = kv.digit(node[i], d), dl = kv.digit(node[L], d);
-        hk[i] = side_key(da < dl ? 0u : 2u, d - dep[i]);
-        dig[i] = kv.digits(node[i], d, width);
-        dep[i] = d + width;
-        open = true;
+      const uint32_t L = sub[i];
+      const uint32_t d = kv.wave_first_diff(node[i], node[L], dep[i] + kThreadWindow);
+      if (__lane_id() == 0) {
+        if (d == kNoDiff) {
+          hk[i] = side_key(1, 0);
+          dig[i] = 0;
+        } else {
+          const uint64_t da = kv.digit(node[i], d), dl = kv.digit(node[L], d);
+          hk[i] = side_key(da < dl ? 0u : 2u, d - dep[i]);
+          dig[i] = kv.digits(node[i], d, width);
+          dep[i] = d + width;
+          open = true;
+        }
       }
     }
     uint32_t P = 2;
@@ -444,14 +506,19 @@ __global__ __launch_bounds__(256) void resolve_lanes_k(const uint32_t* __restric
     // (a) first difference with the pivot: a short window per lane, then
     // the whole wave for every lane whose window agreed
     const uint32_t lead = __shfl(node, in ? sub : l, W);
-    uint32_t d = kNoDiff;
-    if (!res && l != sub) d = kv.first_diff_window(node, lead, dep, kThreadWindow);
-    for (uint64_t pend = __ballot(d == kUndecided); pend; pend &= pend - 1) {
+    typename KeyView<KeyT>::Cmp c{kNoDiff, 0, 0, 0};
+    if (!res && l != sub) c = kv.compare(node, lead, dep, kThreadWindow, width);
+    bool late = false;  // decided by the whole wave: keys still to fetch
+    for (uint64_t pend = __ballot(c.d == kUndecided); pend; pend &= pend - 1) {
       const int q = __ffsll((unsigned long long)pend) - 1;
       const uint32_t qa = __shfl(node, q, kWave), qb = __shfl(lead, q, kWave), qt = __shfl(dep, q, kWave);
       const uint32_t r = kv.wave_first_diff(qa, qb, qt + kThreadWindow);
-      if (__lane_id() == q) d = r;
+      if (__lane_id() == q) {
+        c.d = r;
+        late = true;
+      }
     }
+    const uint32_t d = c.d;
     // (b) sort keys
     bool open = false;
     if (res) {
@@ -461,9 +528,9 @@ __global__ __launch_bounds__(256) void resolve_lanes_k(const uint32_t* __restric
       hk = side_key(1, 0);
       dig = 0;
     } else {
-      const uint64_t da = kv.digit(node, d), dl = kv.digit(lead, d);
+      const uint64_t da = late ? kv.digit(node, d) : c.da, dl = late ? kv.digit(lead, d) : c.dl;
       hk = side_key(da < dl ? 0u : 2u, d - dep);
-      dig = kv.digits(node, d, width);
+      dig = late ? kv.digits(node, d, width) : c.dig;
       dep = d + width;
       open = true;
     }
@@ -570,6 +637,32 @@ struct SegCopy {
 // Global pass for groups too large for the resolvers. Items are the members of
 // the large groups laid out group after group; ioff[g] is the absolute index
 // of the first item of group g.
+
+// Item offsets of the large groups of a classified list: ioff[g] =
+// exclusive scan of the sizes of the meta[kLargeClass] groups listed from
+// meta[kSegClasses + kLargeClass], ioff[ng] = *total = their items. One
+// workgroup of 1024 threads (computed with the lists, so the host learns the
+// total with the list counts).
+__global__ __launch_bounds__(1024) void large_offsets_k(const uint32_t* __restrict__ size,
+                                                        const uint32_t* __restrict__ meta,
+                                                        uint32_t* __restrict__ ioff, uint32_t* __restrict__ total) {
+  __shared__ uint32_t sh[1024 / kWave];
+  const uint32_t ng = meta[kLargeClass];
+  const uint32_t* z = size + meta[kSegClasses + kLargeClass];
+  uint32_t carry = 0;
+  for (uint32_t base = 0; base < ng; base += 1024) {
+    const uint32_t g = base + threadIdx.x;
+    const uint32_t v = g < ng ? z[g] : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan<1024>(v, sh, &tot);
+    if (g < ng) ioff[g] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    ioff[ng] = carry;
+    *total = carry;
+  }
+}
 
 __device__ __forceinline__ uint32_t group_of_item(const uint32_t* ioff, uint32_t ng, uint32_t i) {
   uint32_t lo = 0, hi = ng;  // last g with ioff[g] <= i

@@ -87,8 +87,11 @@ def _scale_to_total(w, total, cap):
 
 def powerlaw_graph(n, e, seed=1, zipf_a=2.1, deg_cap=100_000, num_node_labels=100,
                    node_label_exp=1.2, num_edge_labels=32, edge_label_exp=1.1, name="powerlaw",
-                   shuffle=True):
-    """Power-law out-degree graph; see the module docstring for the recipe."""
+                   shuffle=True, progress=None):
+    """Power-law out-degree graph; see the module docstring for the recipe.
+    progress(msg), when given, is called between the generation steps (large
+    graphs take minutes)."""
+    say = progress or (lambda msg: None)
     rng = _rng(seed)
     w = rng.zipf(zipf_a, size=n).astype(np.float64)
     # expected degrees are held six standard deviations under the cap, so the
@@ -102,17 +105,22 @@ def powerlaw_graph(n, e, seed=1, zipf_a=2.1, deg_cap=100_000, num_node_labels=10
     c = _scale_to_total(w, e, cap_eff)
     lam = np.minimum(c * w, cap_eff)
     deg = rng.multinomial(e, lam / lam.sum()).astype(np.int64)
+    say("out-degrees drawn")
     assert int(deg.sum()) == e
     assert int(deg.max(initial=0)) <= deg_cap, "out-degree above the cap"
     indeg = rng.multinomial(e, (deg + 1.0) / float((deg + 1).sum())).astype(np.int64)
     src = np.repeat(np.arange(n, dtype=np.int32), deg)
     dst = np.repeat(np.arange(n, dtype=np.int32), indeg)
     dst = rng.permutation(dst)  # i.i.d. draws == multinomial counts in random order
+    say("targets drawn")
     elab = _zipf_labels(rng, e, num_edge_labels, edge_label_exp)
     node_label = _zipf_labels(rng, n, num_node_labels, node_label_exp)
+    say("labels drawn")
     if shuffle and e > 0:
         perm = rng.permutation(e)
+        say("edge order drawn")
         src, dst, elab = src[perm], dst[perm], elab[perm]
+        del perm
     return Graph(n, _i32(node_label), _i32(src), _i32(elab), _i32(dst), name=name,
                  meta=dict(kind="powerlaw", seed=seed, zipf_a=zipf_a, deg_cap=deg_cap,
                            node_labels=num_node_labels, edge_labels=num_edge_labels))
@@ -240,10 +248,10 @@ CONFIGS = {
 }
 
 
-def make_config(name, seed=1):
+def make_config(name, seed=1, progress=None):
     cfg = CONFIGS[name]
     if cfg["maker"] == "uniform":
         g = uniform_graph(cfg["n"], cfg["e"], seed=seed, name=name)
     else:
-        g = powerlaw_graph(cfg["n"], cfg["e"], seed=seed, name=name)
+        g = powerlaw_graph(cfg["n"], cfg["e"], seed=seed, name=name, progress=progress)
     return g, cfg["k"]

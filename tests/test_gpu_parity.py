@@ -197,9 +197,19 @@ def test_profile_mode_same_ids():
         pid, nb, counts = h.result()
         prof = h.profile()
         work = h.work()
+        per_round = h.round_profile()
     assert rd == r.rounds_done and counts == r.counts and np.array_equal(pid, r.pid)
     assert prof["round"][1] == rd and prof["signature"][1] == rd
     assert sum(v[0] for v in work.values()) > 0
+    # per round: the same work split by round, times of every round
+    assert len(per_round) == rd
+    assert sum(x["active_nodes"] for x in per_round) == sum(v[0] for v in work.values())
+    assert sum(x["active_edges"] for x in per_round) == sum(v[1] for v in work.values())
+    _, lab_rank, lab_count = np.unique(g.node_label, return_inverse=True, return_counts=True)
+    assert per_round[0]["active_nodes"] == int(np.sum(lab_count[lab_rank] >= 2))  # round 1: label blocks of 2+
+    for x in per_round:
+        assert 0 < x["signature_ms"] <= x["round_ms"]
+    assert abs(sum(x["round_ms"] for x in per_round) - prof["round"][0]) < 1e-6 * max(1.0, prof["round"][0])
 
 
 def test_wide_keys():
