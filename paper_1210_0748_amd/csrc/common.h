@@ -47,15 +47,6 @@ inline int bits_for(uint64_t v) {
   return b;
 }
 
-// SplitMix64 output function (Steele, Lea, Flood: "Fast splittable
-// pseudorandom number generators", OOPSLA 2014). Used only to group equal
-// signatures; never to decide an id.
-__device__ __forceinline__ uint64_t mix64(uint64_t z) {
-  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
-  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
-  return z ^ (z >> 31);
-}
-
 __device__ __forceinline__ uint64_t lanemask_lt() {
   const int lane = __lane_id();
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));

@@ -55,31 +55,51 @@ __global__ __launch_bounds__(256) void tile_count_k(F f, uint32_t n, const uint3
   if (threadIdx.x < NC) part[threadIdx.x * gridDim.x + blockIdx.x] = tot.get(threadIdx.x);
 }
 
+// One workgroup: per class, the exclusive scan of the per-tile counts (in
+// place) and the class totals. All classes of a chunk of 1024 tiles are
+// scanned together (their loads in flight at once, one pair of barriers per
+// chunk), so the cost does not grow with the number of classes.
 template <int NC>
 __global__ __launch_bounds__(1024) void tile_offsets_k(uint32_t* __restrict__ part, uint32_t ntiles,
                                                        uint32_t* __restrict__ meta) {
-  __shared__ uint32_t sh[1024 / kWave];
-  __shared__ uint32_t tot_c[NC];
-  for (int c = 0; c < NC; ++c) {
-    uint32_t* p = part + size_t(c) * ntiles;
-    uint32_t carry = 0;
-    for (uint32_t b = 0; b < ntiles; b += 1024) {
-      const uint32_t i = b + threadIdx.x;
-      const uint32_t v = i < ntiles ? p[i] : 0u;
-      uint32_t tot;
-      const uint32_t ex = block_exclusive_scan<1024>(v, sh, &tot);
-      if (i < ntiles) p[i] = carry + ex;
-      carry += tot;
+  constexpr int NW = 1024 / kWave;
+  __shared__ uint32_t sh[NW][NC];
+  const int lane = __lane_id();
+  const int w = threadIdx.x / kWave;
+  uint32_t carry[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) carry[c] = 0;
+  for (uint32_t b = 0; b < ntiles; b += 1024) {
+    const uint32_t i = b + threadIdx.x;
+    uint32_t v[NC], inc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) v[c] = i < ntiles ? part[size_t(c) * ntiles + i] : 0u;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      inc[c] = wave_inclusive_scan(v[c]);
+      if (lane == kWave - 1) sh[w][c] = inc[c];
     }
-    if (threadIdx.x == 0) tot_c[c] = carry;
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      uint32_t before = 0, tot = 0;
+#pragma unroll
+      for (int q = 0; q < NW; ++q) {
+        const uint32_t x = sh[q][c];
+        before += q < w ? x : 0u;
+        tot += x;
+      }
+      if (i < ntiles) part[size_t(c) * ntiles + i] = carry[c] + before + inc[c] - v[c];
+      carry[c] += tot;
+    }
+    __syncthreads();
   }
-  __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t off = 0;
     for (int c = 0; c < NC; ++c) {
-      meta[c] = tot_c[c];
+      meta[c] = carry[c];
       meta[NC + c] = off;
-      off += tot_c[c];
+      off += carry[c];
     }
     meta[2 * NC] = off;
   }

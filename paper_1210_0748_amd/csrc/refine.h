@@ -114,28 +114,9 @@ struct KeyView {
     return dbits >= 64 ? ~0ull : ((1ull << dbits) - 1);
   }
   // First position >= t where the key sequences of a and b differ (one of
-  // them ending counts as a difference), or kNoDiff if they are equal.
-  __device__ __forceinline__ uint32_t first_diff(uint32_t a, uint32_t b, uint32_t t) const {
-    const uint32_t ca = ucnt[a], cb = ucnt[b];
-    const uint32_t n = ca < cb ? ca : cb;
-    const KeyT* ka = ukey + rowptr[a];
-    const KeyT* kb_ = ukey + rowptr[b];
-    uint32_t j = t;
-    for (; j + 4 <= n; j += 4) {
-      const KeyT a0 = ka[j], a1 = ka[j + 1], a2 = ka[j + 2], a3 = ka[j + 3];
-      const KeyT b0 = kb_[j], b1 = kb_[j + 1], b2 = kb_[j + 2], b3 = kb_[j + 3];
-      if (a0 != b0) return j;
-      if (a1 != b1) return j + 1;
-      if (a2 != b2) return j + 2;
-      if (a3 != b3) return j + 3;
-    }
-    for (; j < n; ++j)
-      if (ka[j] != kb_[j]) return j;
-    if (ca == cb) return kNoDiff;
-    return n > t ? n : t;
-  }
-  // As first_diff, but looks at most at `window` positions from t; returns
-  // kUndecided when the sequences agree on the whole window and continue.
+  // them ending counts as a difference; kNoDiff if they are equal), looking
+  // at most at `window` positions from t: kUndecided when the sequences agree
+  // on the whole window and continue.
   __device__ __forceinline__ uint32_t first_diff_window(uint32_t a, uint32_t b, uint32_t t,
                                                         uint32_t window) const {
     if (has_bm(a) && has_bm(b)) return first_diff_bm(a, b);
@@ -217,7 +198,7 @@ struct KeyView {
     }
     return c;
   }
-  // first_diff computed by a whole wave, 64 positions per step; every lane
+  // The first difference computed by a whole wave, 64 positions per step; every lane
   // of the wave must call it with the same arguments.
   __device__ __forceinline__ uint32_t wave_first_diff(uint32_t a, uint32_t b, uint32_t t) const {
     const uint32_t ca = ucnt[a], cb = ucnt[b];
