@@ -5,7 +5,7 @@ They restate properties proved in the paper's appendix:
 * Proposition 1 (each round refines the previous one),
 * the stop-condition propositions (a round with an unchanged block count is a
   fixed point; it is reached within |N| rounds),
-plus the properties of the canonical numbering chosen for this build (dense
+plus the properties of the canonical numbering used here (dense
 0-based lexicographic ranks whose first key is the previous id).
 """
 from __future__ import annotations
