@@ -9,7 +9,7 @@
 // Section 2.2 realised as an ordered dictionary (Section 3.2, "Data structures
 // for S": a dictionary is one of the admissible set-equality structures).
 //
-// Readings taken where the paper leaves a choice (all listed in the design doc):
+// Readings taken where the paper leaves a choice:
 //  * node labels and edge labels are int32 >= 0 and ordered numerically;
 //  * the input is any multiset of (src, label, dst) triples; set semantics of
 //    the signature (Definition 3) make duplicates irrelevant;
