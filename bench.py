@@ -87,6 +87,8 @@ def main():
     ap.add_argument("--k", type=int, default=None)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-early-stop", action="store_true",
+                    help="plain form: run all k rounds even past the fixed point")
     ap.add_argument("--medium-cap", type=int, default=None)
     ap.add_argument("--form", choices=["plain", "batched", "served"], default="plain")
     ap.add_argument("--graphs", type=int, default=512, help="batched: number of graphs")
@@ -121,11 +123,12 @@ def main():
     arrs = [torch.from_numpy(a).to(dev) for a in (g.node_label, g.src, g.elab, g.dst)]
     out = torch.empty(g.num_nodes, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
+    early_stop = not args.no_early_stop
     torch.cuda.synchronize()
 
     def step(profile):
         h = kb.kbisim_create(g.num_nodes, *arrs, stream=stream, profile=profile,
-                             medium_cap=args.medium_cap)
+                             medium_cap=args.medium_cap, early_stop=early_stop)
         try:
             rd = kb.kbisim_refine(h, k)
             nb, counts = kb.kbisim_result(h, out, counts_cap=k + 1)
@@ -152,7 +155,8 @@ def main():
     # Phases of one more (untimed) step, each closed by a device sync.
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    h = kb.kbisim_create(g.num_nodes, *arrs, stream=stream, medium_cap=args.medium_cap)
+    h = kb.kbisim_create(g.num_nodes, *arrs, stream=stream, medium_cap=args.medium_cap,
+                         early_stop=early_stop)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kb.kbisim_refine(h, k)
@@ -181,9 +185,10 @@ def main():
     achieved = algo_bytes_per_launch / (avg_ms / 1e3) / 1e9
     traffic = load_traffic(dom)
     line = {
-        "metric": ("edge-rounds/s (|E|*rounds/time), 10M-node/100M-edge power-law graph to fixed point"
-                   if args.workload == "powerlaw-10M-100M" else
-                   "edge-rounds/s (|E|*rounds/time), %s to fixed point (cap k)" % args.workload),
+        "metric": ("edge-rounds/s (|E|*rounds/time), %s %s" % (
+            "10M-node/100M-edge power-law graph" if args.workload == "powerlaw-10M-100M" else args.workload,
+            ("to fixed point" if args.workload == "powerlaw-10M-100M" else "to fixed point (cap k)")
+            if early_stop else "all k rounds, no early stop")),
         "value": value,
         "unit": "edge-rounds/s",
         "n_gpus": 1,
@@ -196,7 +201,7 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": args.workload, "num_nodes": g.num_nodes, "num_edges": g.num_edges,
-                   "k_cap": k, "rounds": rd, "counts": counts, "seed": args.seed},
+                   "k_cap": k, "early_stop": early_stop, "rounds": rd, "counts": counts, "seed": args.seed},
         "phases": dict(phases, note="one untimed step, each phase closed by a device sync"),
         "roofline": {"bound": "hbm", "kernel": "signature_k", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
@@ -204,7 +209,10 @@ def main():
                      "launch_avg_ms": avg_ms, "algo_bytes_per_launch": algo_bytes_per_launch},
         "kernel_ms": {c: prof[c][0] for c in prof},
         # round by round: the signature launch's algorithmic GB/s and the round's time
-        "rounds": [{"round": r + 1, "active_nodes": x["active_nodes"], "active_edges": x["active_edges"],
+        # (max_sig_ints: the longest signature as integers, the old id plus a (label, id) pair per key)
+        "rounds": [{"round": r + 1, "blocks": counts[r + 1] if r + 1 < len(counts) else None,
+                    "max_sig_ints": 1 + 2 * x["max_keys"],
+                    "active_nodes": x["active_nodes"], "active_edges": x["active_edges"],
                     "signature_ms": x["signature_ms"], "round_ms": x["round_ms"],
                     "signature_gbs": (BYTES_PER_EDGE * x["active_edges"] + BYTES_PER_NODE * x["active_nodes"])
                     / max(x["signature_ms"], 1e-9) / 1e6}

@@ -143,6 +143,7 @@ typedef struct {
   double round_ms;     /* the whole round: signatures, ordering, id assignment */
   int64_t active_nodes; /* nodes whose signature the round computed */
   int64_t active_edges; /* their out-edges */
+  int64_t max_keys;     /* longest signature: unique (label, id) pairs of one node */
 } kbisim_round_stat;
 
 /* Per-round profile when options.profile = 1 (round-by-round rates of the

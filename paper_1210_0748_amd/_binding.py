@@ -216,12 +216,13 @@ def kbisim_work(handle, reset=False):
 
 class RoundStat(ctypes.Structure):
     _fields_ = [("signature_ms", ctypes.c_double), ("round_ms", ctypes.c_double),
-                ("active_nodes", ctypes.c_int64), ("active_edges", ctypes.c_int64)]
+                ("active_nodes", ctypes.c_int64), ("active_edges", ctypes.c_int64),
+                ("max_keys", ctypes.c_int64)]
 
 
 def kbisim_round_profile(handle, reset=False, cap=64):
     """Per round (profile mode): dicts with signature_ms, round_ms,
-    active_nodes, active_edges."""
+    active_nodes, active_edges, max_keys."""
     buf = (RoundStat * cap)()
     n = ctypes.c_int32(0)
     _check(load_library().kbisim_round_profile(handle, buf, cap, ctypes.byref(n), 1 if reset else 0))

@@ -127,9 +127,10 @@ class Engine {
   // and edges; rounds past kRoundSlots share the last slot's counts
   struct RoundStat {
     double sig_ms = 0, round_ms = 0;
-    uint64_t nodes = 0, edges = 0;
+    uint64_t nodes = 0, edges = 0, max_keys = 0;
   };
   static constexpr int kRoundSlots = 64;
+  static constexpr int kWorkWords = 16;  // per round: 4 buckets x (nodes, edges), longest key list
   std::vector<RoundStat> round_stats();
   void reset_round_stats();
   int adj_bytes() const { return adj64_ ? 8 : 4; }
@@ -230,7 +231,7 @@ class Engine {
   std::vector<EvPair> ev_pool_;
   std::vector<RoundStat> round_ms_;  // milliseconds per round (counts come from work_)
   int32_t round_base_ = 0;           // rounds before the last reset of the round stats
-  DevBuf work_;                      // kRoundSlots x 8 counters (per round: 4 buckets x nodes, edges)
+  DevBuf work_;                      // kRoundSlots x kWorkWords counters
   size_t ev_used_ = 0;
 };
 

@@ -818,12 +818,12 @@ void Engine::round_impl() {
   }
   if (opt_.profile) {
     if (!work_.p) {
-      work_.ensure(kRoundSlots * 8 * sizeof(unsigned long long));
-      KB_CHECK(hipMemsetAsync(work_.p, 0, kRoundSlots * 8 * sizeof(unsigned long long), st_));
+      work_.ensure(kRoundSlots * kWorkWords * sizeof(unsigned long long));
+      KB_CHECK(hipMemsetAsync(work_.p, 0, kRoundSlots * kWorkWords * sizeof(unsigned long long), st_));
     }
     const int slot = std::min<int>(rounds_ - round_base_, kRoundSlots - 1);
     work_count_k<<<grid_for(M_act_), kNT, 0, st_>>>(w.anode, a.rowptr, M_act_,
-                                                    work_.as<unsigned long long>() + 8 * std::max(slot, 0));
+                                                    work_.as<unsigned long long>() + kWorkWords * std::max(slot, 0));
     KB_LAUNCH_CHECK();
   }
   const int ev = ev_begin(0);
@@ -834,6 +834,12 @@ void Engine::round_impl() {
     KB_LAUNCH_CHECK();
   }
   ev_end(ev);
+  if (opt_.profile) {  // longest signature of the round (unique keys)
+    const int slot = std::min<int>(rounds_ - round_base_, kRoundSlots - 1);
+    max_ucnt_k<<<grid_for(M_act_), kNT, 0, st_>>>(w.anode, a.ucnt, M_act_,
+                                                  work_.as<unsigned long long>() + kWorkWords * std::max(slot, 0) + 8);
+    KB_LAUNCH_CHECK();
+  }
 
   KeyView<KeyT> kv{rowptr_.as<uint32_t>(), ukey_.as<KeyT>(), ucnt_.as<uint32_t>(), digit_bits};
   if (use_bm) {
@@ -874,30 +880,31 @@ void Engine::work_counts(uint64_t* out8) {
   StreamScope scope(st_);
   for (int i = 0; i < 8; ++i) out8[i] = 0;
   if (!work_.p) return;
-  std::vector<uint64_t> all(size_t(kRoundSlots) * 8);
+  std::vector<uint64_t> all(size_t(kRoundSlots) * kWorkWords);
   KB_CHECK(hipMemcpyAsync(all.data(), work_.p, all.size() * sizeof(uint64_t), hipMemcpyDeviceToHost, st_));
   KB_CHECK(hipStreamSynchronize(st_));
   for (size_t r = 0; r < size_t(kRoundSlots); ++r)
-    for (int i = 0; i < 8; ++i) out8[i] += all[r * 8 + size_t(i)];
+    for (int i = 0; i < 8; ++i) out8[i] += all[r * kWorkWords + size_t(i)];
 }
 
 void Engine::reset_work() {
-  if (work_.p) KB_CHECK(hipMemsetAsync(work_.p, 0, kRoundSlots * 8 * sizeof(unsigned long long), st_));
+  if (work_.p) KB_CHECK(hipMemsetAsync(work_.p, 0, kRoundSlots * kWorkWords * sizeof(unsigned long long), st_));
 }
 
 std::vector<Engine::RoundStat> Engine::round_stats() {
   StreamScope scope(st_);
   std::vector<RoundStat> out(round_ms_);
   if (out.empty() || !work_.p) return out;
-  std::vector<uint64_t> all(size_t(kRoundSlots) * 8);
+  std::vector<uint64_t> all(size_t(kRoundSlots) * kWorkWords);
   KB_CHECK(hipMemcpyAsync(all.data(), work_.p, all.size() * sizeof(uint64_t), hipMemcpyDeviceToHost, st_));
   KB_CHECK(hipStreamSynchronize(st_));
   for (size_t r = 0; r < out.size(); ++r) {
     const size_t slot = std::min<size_t>(r, size_t(kRoundSlots) - 1);
     for (int c = 0; c < 4; ++c) {
-      out[r].nodes += all[slot * 8 + size_t(2 * c)];
-      out[r].edges += all[slot * 8 + size_t(2 * c + 1)];
+      out[r].nodes += all[slot * kWorkWords + size_t(2 * c)];
+      out[r].edges += all[slot * kWorkWords + size_t(2 * c + 1)];
     }
+    out[r].max_keys = all[slot * kWorkWords + 8];
   }
   return out;
 }
@@ -1523,6 +1530,7 @@ kbisim_status kbisim_round_profile(const kbisim_graph* g, kbisim_round_stat* sta
       stats[r].round_ms = rs[r].round_ms;
       stats[r].active_nodes = int64_t(rs[r].nodes);
       stats[r].active_edges = int64_t(rs[r].edges);
+      stats[r].max_keys = int64_t(rs[r].max_keys);
     }
     if (reset) g->eng->reset_round_stats();
     return KBISIM_OK;

@@ -711,6 +711,14 @@ __global__ void hub_finish_k(SigArgs<AdjT, KeyT> a, const uint32_t* __restrict__
   a.head[n] = a.head_of(a.ukey + a.rowptr[n], c);
 }
 
+// Largest number of unique keys among the active nodes (profiling only).
+__global__ void max_ucnt_k(const uint32_t* __restrict__ anode, const uint32_t* __restrict__ ucnt, uint32_t m,
+                           unsigned long long* __restrict__ mx) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t c = wave_max(uint64_t(j < m ? ucnt[anode[j]] : 0u));
+  if (__lane_id() == 0 && c > 0) atomicMax(mx, (unsigned long long)c);
+}
+
 // Work of the signature launch (profiling only): per bucket (thread, wave,
 // block, hub) the active nodes and their edges.
 __global__ __launch_bounds__(kSigNT) void work_count_k(const uint32_t* __restrict__ anode,

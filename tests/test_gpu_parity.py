@@ -209,6 +209,13 @@ def test_profile_mode_same_ids():
     assert per_round[0]["active_nodes"] == int(np.sum(lab_count[lab_rank] >= 2))  # round 1: label blocks of 2+
     for x in per_round:
         assert 0 < x["signature_ms"] <= x["round_ms"]
+    # round 1: longest signature = most distinct (edge label, label of target) pairs of an active node
+    act = lab_count[lab_rank] >= 2
+    keep = act[g.src]
+    pairs = np.unique(np.stack([g.src[keep].astype(np.int64), g.elab[keep].astype(np.int64),
+                                lab_rank[g.dst[keep]].astype(np.int64)]), axis=1)
+    assert per_round[0]["max_keys"] == int(np.bincount(pairs[0]).max())
+    assert all(0 <= x["max_keys"] <= int(np.bincount(g.src).max()) for x in per_round)
     assert abs(sum(x["round_ms"] for x in per_round) - prof["round"][0]) < 1e-6 * max(1.0, prof["round"][0])
 
 
