@@ -13,7 +13,8 @@
 // (Proposition 1), so such a node stays alone whatever its signature.
 //
 // One launch covers all active nodes. Work is split by out-degree: one thread
-// (<= 16 keys, register sorting network), one wave (<= 64 keys, shuffle
+// (<= 16 keys, register sorting network; the wave's rows staged in LDS so
+// that loads and stores are contiguous), one wave (<= 64 keys, shuffle
 // bitonic; <= 512 keys, 2, 4 or 8 keys per lane in registers), one workgroup
 // (<= 4096 keys, LDS bitonic); hubs (more keys) are sorted by (hub, key)
 // together with the device-wide radix sort before the launch, or, when that
@@ -118,13 +119,47 @@ __device__ __forceinline__ void cas_up(KeyT& a, KeyT& b, bool up) {
 }
 
 // ---- one thread per node, out-degree <= 16 ------------------------------------
+// Each lane sorts its node's keys with a 16-key sorting network in registers
+// and de-duplicates them. The rows pass through LDS: the wave lists the edges
+// of its 64 nodes one node after another, loads them (consecutive lanes read
+// consecutive edges of a row; a lane reading its own row would put the
+// wave's accesses 64 rows apart) and turns them into keys; each lane takes
+// its keys from the list and puts its unique keys back in place, and the
+// wave writes those out the same way. `n` is kNone for lanes without a node
+// (or whose node has more than kThreadMaxDeg edges). Every thread of the
+// workgroup calls it (three workgroup barriers).
+template <typename KeyT>
+struct ThreadLds {
+  static constexpr uint32_t kCap = kWave * kThreadMaxDeg;
+  KeyT key[kSigNT / kWave][kCap];
+  uint8_t own[kSigNT / kWave][kCap];      // lane of the node the listed edge belongs to
+  uint32_t delta[kSigNT / kWave][kWave];  // per lane: row start in adj minus list start
+  uint32_t lim[kSigNT / kWave][kWave];    // per lane: end of its unique keys in the list
+};
+constexpr uint32_t kNone = 0xffffffffu;
+
 template <typename AdjT, typename KeyT>
-__device__ __forceinline__ void sig_thread_node(const SigArgs<AdjT, KeyT>& a, uint32_t n, uint32_t beg,
-                                                uint32_t deg) {
+__device__ __forceinline__ void sig_thread_wave(const SigArgs<AdjT, KeyT>& a, uint32_t n, ThreadLds<KeyT>& t) {
   constexpr int M = kThreadMaxDeg;
+  const int wv = threadIdx.x / kWave;
+  const int lane = __lane_id();
+  uint32_t beg = 0, deg = 0;
+  if (n != kNone) {
+    beg = a.rowptr[n];
+    deg = a.rowptr[n + 1] - beg;
+    if (deg > kThreadMaxDeg) n = kNone, deg = 0;
+  }
+  const uint32_t incl = wave_inclusive_scan(deg);
+  const uint32_t o = incl - deg;  // this lane's first list position
+  const uint32_t total = __shfl(incl, kWave - 1, kWave);
+  t.delta[wv][lane] = beg - o;
+  for (uint32_t q = 0; q < deg; ++q) t.own[wv][o + q] = uint8_t(lane);
+  __syncthreads();
+  for (uint32_t i = lane; i < total; i += kWave) t.key[wv][i] = a.key_of(a.adj[t.delta[wv][t.own[wv][i]] + i]);
+  __syncthreads();
   KeyT k[M];
 #pragma unroll
-  for (int j = 0; j < M; ++j) k[j] = (uint32_t(j) < deg) ? a.key_of(a.adj[beg + j]) : ~KeyT(0);
+  for (int j = 0; j < M; ++j) k[j] = (uint32_t(j) < deg) ? t.key[wv][o + j] : ~KeyT(0);
 #pragma unroll
   for (int size = 2; size <= M; size <<= 1) {
 #pragma unroll
@@ -141,14 +176,22 @@ __device__ __forceinline__ void sig_thread_node(const SigArgs<AdjT, KeyT>& a, ui
 #pragma unroll
   for (int j = 0; j < M; ++j) {
     if (uint32_t(j) < deg && (j == 0 || k[j] != k[j - 1])) {
-      a.ukey[beg + c] = k[j];
+      t.key[wv][o + c] = k[j];
       if (c < a.hw) hv = a.hdbits >= 64 ? uint64_t(k[j]) + 1ull : (hv << a.hdbits) | (uint64_t(k[j]) + 1ull);
       ++c;
     }
   }
   if (a.hdbits < 64 && c < a.hw) hv <<= (a.hw - c) * a.hdbits;
-  a.ucnt[n] = c;
-  a.head[n] = hv;
+  t.lim[wv][lane] = o + c;
+  if (n != kNone) {
+    a.ucnt[n] = c;
+    a.head[n] = hv;
+  }
+  __syncthreads();
+  for (uint32_t i = lane; i < total; i += kWave) {
+    const uint32_t ow = t.own[wv][i];
+    if (i < t.lim[wv][ow]) a.ukey[t.delta[wv][ow] + i] = t.key[wv][i];
+  }
 }
 
 // ---- one wave per node, 16 < out-degree <= 64 ---------------------------------
@@ -578,6 +621,7 @@ __device__ __forceinline__ void sig_hub_node(const SigArgs<AdjT, KeyT>& a, uint3
 template <typename KeyT>
 union SigLds {
   KeyT block[kBlockMaxDeg];
+  ThreadLds<KeyT> th;
   HubLds hub;
   struct {
     uint32_t bits[kSigNT / kWave][kBmMaxWords];  // one per wave (the workgroup path uses the first)
@@ -624,17 +668,13 @@ __global__ __launch_bounds__(kSigNT) void signature_k(SigArgs<AdjT, KeyT> a, Sig
   }
   b -= w.wave_units();
   const uint32_t j = b * kSigNT + threadIdx.x;
-  uint32_t n = 0xffffffffu;
+  uint32_t n = kNone;
   if (w.dense) {
     if (j < w.n_nodes && w.actr[j] == w.tag) n = j;
   } else if (j < w.nact) {
     n = w.anode[j];
   }
-  if (n != 0xffffffffu) {
-    const uint32_t beg = a.rowptr[n];
-    const uint32_t deg = a.rowptr[n + 1] - beg;
-    if (deg <= kThreadMaxDeg) sig_thread_node(a, n, beg, deg);
-  }
+  sig_thread_wave(a, n, lds.th);
 }
 
 // ---- hubs in rounds with wide keys: one device-wide sort ----------------------
