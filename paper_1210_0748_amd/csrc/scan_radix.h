@@ -153,7 +153,16 @@ __global__ __launch_bounds__(kRadixNT) void radix_hist_k(const K* __restrict__ k
     for (int i = 0; i < kVecs; ++i) {
       const K* e = reinterpret_cast<const K*>(&r[i]);
 #pragma unroll
-      for (int q = 0; q < kPerVec; ++q) atomicAdd(&cnt[w][uint32_t(e[q] >> shift) & 255u], 1u);
+      for (int q = 0; q < kPerVec; ++q) {
+        // a digit shared by the whole wave is added once
+        const uint32_t d = uint32_t(e[q] >> shift) & 255u;
+        const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+        if (__ballot(d != d0) == 0) {
+          if (__lane_id() == 0) atomicAdd(&cnt[w][d0], uint32_t(kWave));
+        } else {
+          atomicAdd(&cnt[w][d], 1u);
+        }
+      }
     }
   } else {
 #pragma unroll 4
@@ -233,9 +242,17 @@ __device__ __forceinline__ void radix_scatter_tile(const Load& load, K* __restri
     if (valid) load(idx, key[r], val[r]);
     dg[r] = valid ? (uint32_t(key[r] >> shift) & 255u) : 256u;
   }
+  // lanes of the wave sharing each row's digit: one LDS add per distinct
+  // digit (equal digits in a row, common in the high digits, would
+  // otherwise serialise on one counter), reused for the ranks below
+  uint64_t peers[kRows];
 #pragma unroll
-  for (int r = 0; r < kRows; ++r)
-    if (dg[r] < 256u) atomicAdd(&wh[w][dg[r]], 1u);
+  for (int r = 0; r < kRows; ++r) {
+    const bool valid = dg[r] < 256u;
+    const uint32_t d = valid ? dg[r] : 0u;
+    peers[r] = match_digit8(d, __ballot(valid));
+    if (valid && (peers[r] & lanemask_lt()) == 0) atomicAdd(&wh[w][d], uint32_t(__popcll(peers[r])));
+  }
   __syncthreads();
   {
     // local exclusive prefix over (digit, wave), and the global shift per digit
@@ -274,7 +291,7 @@ __device__ __forceinline__ void radix_scatter_tile(const Load& load, K* __restri
   for (int r = 0; r < kRows; ++r) {
     const bool valid = dg[r] < 256u;
     const uint32_t d = valid ? dg[r] : 0u;
-    const uint64_t m = match_digit8(d, __ballot(valid));
+    const uint64_t m = peers[r];
     const uint32_t rank = __popcll(m & lanemask_lt());
     const uint32_t pos = wh[w][d] + rank;
     if (valid) {
