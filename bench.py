@@ -11,6 +11,8 @@ Prints one JSON line (rank 0). Options:
   --steps K       timed steps (default 3)
   --warmup W      untimed steps first (default 1)
   --workload W    synth.CONFIGS name (default powerlaw-10M-100M)
+  --k K           round cap (default: the workload's, 10)
+  --no-early-stop run all K rounds even past the fixed point
   --no-cpu-baseline   skip timing the oracle on the host
   --form F        plain (default), batched or served: the two system forms
                   print their own JSON line (see bench_batched / bench_served)
@@ -48,9 +50,11 @@ def kernel_source_digest():
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel_class):
+def load_traffic(kernel_class, workload, early_stop, k_cap):
     """HBM bytes per launch measured with rocprofv3 counters, if the committed
-    measurement was taken on the current kernel sources (else None)."""
+    measurement was taken on the current kernel sources and on this same job
+    (workload, early stop, k), else None: the average over a job's launches
+    depends on its rounds."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(p):
         return None
@@ -59,7 +63,9 @@ def load_traffic(kernel_class):
     if t.get("source_digest") != kernel_source_digest():
         return None
     k = t.get("kernels", {}).get(kernel_class)
-    return None if k is None else k.get("bytes_per_launch")
+    if k is None or (k.get("workload"), k.get("early_stop"), k.get("k_cap")) != (workload, early_stop, k_cap):
+        return None
+    return k.get("bytes_per_launch")
 
 
 def cpu_baseline(seed=1):
@@ -183,7 +189,7 @@ def main():
     algo_bytes_per_launch = (BYTES_PER_EDGE * edges + BYTES_PER_NODE * nodes) / max(launches, 1)
     avg_ms = ms_total / max(launches, 1)
     achieved = algo_bytes_per_launch / (avg_ms / 1e3) / 1e9
-    traffic = load_traffic(dom)
+    traffic = load_traffic(dom, args.workload, early_stop, k)
     line = {
         "metric": ("edge-rounds/s (|E|*rounds/time), %s %s" % (
             "10M-node/100M-edge power-law graph" if args.workload == "powerlaw-10M-100M" else args.workload,

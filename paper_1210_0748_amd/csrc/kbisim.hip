@@ -822,8 +822,8 @@ void Engine::round_impl() {
       KB_CHECK(hipMemsetAsync(work_.p, 0, kRoundSlots * kWorkWords * sizeof(unsigned long long), st_));
     }
     const int slot = std::min<int>(rounds_ - round_base_, kRoundSlots - 1);
-    work_count_k<<<grid_for(M_act_), kNT, 0, st_>>>(w.anode, a.rowptr, M_act_,
-                                                    work_.as<unsigned long long>() + kWorkWords * std::max(slot, 0));
+    work_count_k<<<std::min<uint32_t>(grid_for(M_act_), kProfGrid), kSigNT, 0, st_>>>(
+        w.anode, a.rowptr, M_act_, work_.as<unsigned long long>() + kWorkWords * std::max(slot, 0));
     KB_LAUNCH_CHECK();
   }
   const int ev = ev_begin(0);
@@ -836,8 +836,8 @@ void Engine::round_impl() {
   ev_end(ev);
   if (opt_.profile) {  // longest signature of the round (unique keys)
     const int slot = std::min<int>(rounds_ - round_base_, kRoundSlots - 1);
-    max_ucnt_k<<<grid_for(M_act_), kNT, 0, st_>>>(w.anode, a.ucnt, M_act_,
-                                                  work_.as<unsigned long long>() + kWorkWords * std::max(slot, 0) + 8);
+    max_ucnt_k<<<std::min<uint32_t>(grid_for(M_act_), kProfGrid), kSigNT, 0, st_>>>(
+        w.anode, a.ucnt, M_act_, work_.as<unsigned long long>() + kWorkWords * std::max(slot, 0) + 8);
     KB_LAUNCH_CHECK();
   }
 

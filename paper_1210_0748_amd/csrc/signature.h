@@ -751,31 +751,49 @@ __global__ void hub_finish_k(SigArgs<AdjT, KeyT> a, const uint32_t* __restrict__
   a.head[n] = a.head_of(a.ukey + a.rowptr[n], c);
 }
 
-// Largest number of unique keys among the active nodes (profiling only).
-__global__ void max_ucnt_k(const uint32_t* __restrict__ anode, const uint32_t* __restrict__ ucnt, uint32_t m,
-                           unsigned long long* __restrict__ mx) {
-  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t c = wave_max(uint64_t(j < m ? ucnt[anode[j]] : 0u));
-  if (__lane_id() == 0 && c > 0) atomicMax(mx, (unsigned long long)c);
+// Profiling reductions over the active list: grid-stride over at most
+// kProfGrid workgroups, one global atomic per workgroup and counter (one per
+// wave serialises on the counters: milliseconds at 10^7 nodes).
+constexpr uint32_t kProfGrid = 512;
+
+// Largest number of unique keys among the active nodes.
+__global__ __launch_bounds__(kSigNT) void max_ucnt_k(const uint32_t* __restrict__ anode,
+                                                    const uint32_t* __restrict__ ucnt, uint32_t m,
+                                                    unsigned long long* __restrict__ mx) {
+  __shared__ uint32_t sh[kSigNT / kWave];
+  uint32_t c = 0;
+  for (uint64_t j = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; j < m; j += uint64_t(gridDim.x) * blockDim.x) {
+    const uint32_t u = ucnt[anode[j]];
+    c = u > c ? u : c;
+  }
+  c = wave_max(c);
+  if (__lane_id() == 0) sh[threadIdx.x / kWave] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < kSigNT / kWave; ++q) c = sh[q] > c ? sh[q] : c;
+    if (c > 0) atomicMax(mx, (unsigned long long)c);
+  }
 }
 
-// Work of the signature launch (profiling only): per bucket (thread, wave,
-// block, hub) the active nodes and their edges.
+// Work of the signature launch: per bucket (thread, wave, block, hub) the
+// active nodes and their edges.
 __global__ __launch_bounds__(kSigNT) void work_count_k(const uint32_t* __restrict__ anode,
                                                       const uint32_t* __restrict__ rowptr, uint32_t m,
                                                       unsigned long long* __restrict__ acc) {
   __shared__ unsigned long long red[8];
   if (threadIdx.x < 8) red[threadIdx.x] = 0;
   __syncthreads();
-  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   uint64_t ne[4] = {0, 0, 0, 0};
   uint64_t nn[4] = {0, 0, 0, 0};
-  if (j < m) {
+  for (uint64_t j = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; j < m; j += uint64_t(gridDim.x) * blockDim.x) {
     const uint32_t n = anode[j];
     const uint32_t d = rowptr[n + 1] - rowptr[n];
     const int c = d <= kThreadMaxDeg ? 0 : d <= kWaveMaxDeg ? 1 : d <= kBlockMaxDeg ? 2 : 3;
-    nn[c] = 1;
-    ne[c] = d;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      nn[q] += q == c ? 1u : 0u;
+      ne[q] += q == c ? d : 0u;
+    }
   }
 #pragma unroll
   for (int c = 0; c < 4; ++c) {

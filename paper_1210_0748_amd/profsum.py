@@ -5,6 +5,7 @@
   python -m paper_1210_0748_amd.profsum counters <counter_collection.csv> --kernel SUBSTR
   python -m paper_1210_0748_amd.profsum traffic <fetch.csv> --write W.csv --cal-fetch CF.csv
          --cal-write CW.csv --kernel SUBSTR --name NAME --out profiles/traffic.json
+         [--workload W --k-cap K --no-early-stop]   (the bench job the counters ran)
 
 `traffic` turns FETCH_SIZE / WRITE_SIZE runs of a command and of the 1 GiB
 copy probe (paper_1210_0748_amd.copyprobe) into bytes per launch of one
@@ -107,6 +108,8 @@ def cmd_traffic(a):
                  "the kernel, scaled by the readings of a 1 GiB device copy")
     t.setdefault("kernels", {})[a.name] = {
         "kernel": a.kernel, "launches": len(f),
+        # the bench job the counters were read on
+        "workload": a.workload, "early_stop": not a.no_early_stop, "k_cap": a.k_cap,
         "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb, "bytes_per_launch": fb + wb,
         "fetch_bytes_per_dispatch": [x * 1024.0 * fscale for x in f],
         "write_bytes_per_dispatch": [x * 1024.0 * wscale for x in w]}
@@ -126,6 +129,9 @@ def main(argv=None):
     ap.add_argument("--cal-write", default=None)
     ap.add_argument("--name", default=None)
     ap.add_argument("--out", default="profiles/traffic.json")
+    ap.add_argument("--workload", default="powerlaw-10M-100M", help="traffic: the bench job's workload")
+    ap.add_argument("--k-cap", type=int, default=10, help="traffic: the bench job's k")
+    ap.add_argument("--no-early-stop", action="store_true", help="traffic: the bench job ran without early stop")
     a = ap.parse_args(argv)
     if a.mode == "stats":
         cmd_stats(a.csv, a.top)
