@@ -79,6 +79,27 @@ def test_degree_buckets():
     check_parity(g, 6)
 
 
+def test_thread_rows_at_list_capacity():
+    """Out-degree 16 (the one-thread limit) everywhere: every wave of 64 nodes
+    lists exactly 64 x 16 edges, the capacity of its LDS list. Then the same
+    with all 16 edges of a node on one (label, target) pair (one unique key
+    out of 16), and mixed with rows of 17 edges and empty rows, which the
+    thread part leaves to the wave part or writes as empty."""
+    g = synth.degree_graph([16] * 4096, num_node_labels=3, num_edge_labels=4, seed=31, name="deg16")
+    check_parity(g, 4)
+    rng = np.random.default_rng(32)
+    n = 2048
+    src = np.repeat(np.arange(n, dtype=np.int32), 16)
+    dst = np.repeat(rng.integers(0, n, size=n, dtype=np.int32), 16)
+    lab = np.repeat(rng.integers(0, 2, size=n, dtype=np.int32), 16)
+    perm = rng.permutation(src.shape[0])
+    node_label = rng.integers(0, 2, size=n, dtype=np.int32)
+    check_parity(synth.Graph(n, node_label, src[perm], lab[perm], dst[perm], name="deg16-copies"), 4)
+    g3 = synth.degree_graph([16, 17, 0, 16, 1] * 800, num_node_labels=2, num_edge_labels=3, seed=33,
+                            name="deg16-mixed")
+    check_parity(g3, 5)
+
+
 def test_long_runs_without_edges():
     """Sources only at both ends of the id range: the CSR has long runs of
     empty rows (shorter and longer than the row-offset kernel's inline range)."""
