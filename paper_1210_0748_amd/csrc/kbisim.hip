@@ -163,7 +163,8 @@ void Engine::build_adj(const int32_t* src, const int32_t* lab, const int32_t* ds
     KB_LAUNCH_CHECK();
     csr_rowptr_gaps_k<<<256, kNT, 0, st_>>>(gaps.as<uint32_t>(), ng, rowptr_.as<uint32_t>());
     KB_LAUNCH_CHECK();
-    KB_CHECK(hipStreamSynchronize(st_));  // temporaries are freed on return
+    // the temporaries go back to the pool with an event on this stream: a
+    // later user of a block is ordered after this work, no host wait here
   } else {
     adj_.ensure(sizeof(AdjT));
     KB_CHECK(hipMemsetAsync(rowptr_.p, 0, (N + 1) * 4, st_));

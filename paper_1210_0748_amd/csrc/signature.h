@@ -14,7 +14,8 @@
 //
 // One launch covers all active nodes. Work is split by out-degree: one thread
 // (<= 16 keys, register sorting network; the wave's rows staged in LDS so
-// that loads and stores are contiguous), one wave (<= 64 keys, shuffle
+// that loads and stores are contiguous), one wave (two nodes per wave when
+// both have <= 32 keys) (<= 64 keys, shuffle
 // bitonic; <= 512 keys, 2, 4 or 8 keys per lane in registers), one workgroup
 // (<= 4096 keys, LDS bitonic); hubs (more keys) are sorted by (hub, key)
 // together with the device-wide radix sort before the launch, or, when that
@@ -97,7 +98,8 @@ struct SigWork {
 
   static constexpr uint32_t kWavesPerUnit = kSigNT / kWave;
   __host__ __device__ uint32_t hub_slot0() const { return nm + nb; }
-  __host__ __device__ uint32_t wave_units() const { return (nw + kWavesPerUnit - 1) / kWavesPerUnit; }
+  // two wave-list entries per wave (sig_wave_pair)
+  __host__ __device__ uint32_t wave_units() const { return ((nw + 1) / 2 + kWavesPerUnit - 1) / kWavesPerUnit; }
   __host__ __device__ uint32_t thread_units() const { return ((dense ? n_nodes : nact) + kSigNT - 1) / kSigNT; }
   // bitmap rounds: one wave per mid or block node; else one workgroup per
   // block node and one wave per mid node
@@ -233,6 +235,60 @@ __device__ __forceinline__ void sig_wave_node(const SigArgs<AdjT, KeyT>& a, uint
   for (int o = 32; o > 0; o >>= 1) hv |= __shfl_xor(hv, o, kWave);
   if (lane == 0) {
     a.ucnt[n] = __popcll(b);
+    a.head[n] = hv;
+  }
+}
+
+// Two wave-list nodes per wave. When both have at most 32 edges (or the
+// second is kNone) each takes a half-wave: a 32-lane bitonic sort (15
+// stages instead of the full wave's 21, with a 32-wide shuffle network that
+// stays inside the half) and the same de-duplication over the half's lanes;
+// else the wave runs sig_wave_node for one node after the other. With one
+// node per wave, a node of 17..32 edges left half of the lanes idle.
+template <typename AdjT, typename KeyT>
+__device__ __forceinline__ void sig_wave_pair(const SigArgs<AdjT, KeyT>& a, uint32_t n0, uint32_t n1) {
+  const uint32_t b0 = a.rowptr[n0];
+  const uint32_t d0 = a.rowptr[n0 + 1] - b0;
+  uint32_t b1 = 0, d1 = 0;
+  if (n1 != kNone) {
+    b1 = a.rowptr[n1];
+    d1 = a.rowptr[n1 + 1] - b1;
+  }
+  if (d0 > kWave / 2 || d1 > kWave / 2) {
+    sig_wave_node(a, n0);
+    if (n1 != kNone) sig_wave_node(a, n1);
+    return;
+  }
+  const int lane = __lane_id();
+  const int half = lane >> 5;
+  const uint32_t l = uint32_t(lane & 31);
+  const uint32_t n = half ? n1 : n0;
+  const uint32_t beg = half ? b1 : b0;
+  const uint32_t deg = half ? d1 : d0;
+  KeyT k = l < deg ? a.key_of(a.adj[beg + l]) : ~KeyT(0);
+#pragma unroll
+  for (uint32_t size = 2; size <= 32; size <<= 1) {
+#pragma unroll
+    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      const KeyT o = __shfl_xor(k, int(stride), kWave);
+      const bool up = (l & size) == 0;  // size 32: both halves ascending
+      const bool lower = (l & stride) == 0;
+      const KeyT mn = k < o ? k : o;
+      const KeyT mx = k < o ? o : k;
+      k = (lower == up) ? mn : mx;
+    }
+  }
+  const KeyT prev = __shfl_up(k, 1, kWave);
+  const bool f = l < deg && (l == 0 || k != prev);
+  const uint32_t bh = uint32_t(__ballot(f) >> (32 * half));
+  const uint32_t r = uint32_t(__popc(bh & ((1u << l) - 1u)));
+  if (f) a.ukey[beg + r] = k;
+  uint64_t hv = 0;
+  if (f && r < a.hw) hv = a.hdbits >= 64 ? uint64_t(k) + 1ull : (uint64_t(k) + 1ull) << ((a.hw - 1 - r) * a.hdbits);
+#pragma unroll
+  for (int o = 16; o > 0; o >>= 1) hv |= __shfl_xor(hv, o, kWave);
+  if (l == 0 && n != kNone) {
+    a.ucnt[n] = uint32_t(__popc(bh));
     a.head[n] = hv;
   }
 }
@@ -662,8 +718,8 @@ __global__ __launch_bounds__(kSigNT) void signature_k(SigArgs<AdjT, KeyT> a, Sig
   }
   b -= w.mid_units();
   if (b < w.wave_units()) {
-    const uint32_t wi = b * (kSigNT / kWave) + threadIdx.x / kWave;
-    if (wi < w.nw) sig_wave_node(a, w.wl[wi]);
+    const uint32_t wi = 2 * (b * (kSigNT / kWave) + threadIdx.x / kWave);
+    if (wi < w.nw) sig_wave_pair(a, w.wl[wi], wi + 1 < w.nw ? w.wl[wi + 1] : kNone);
     return;
   }
   b -= w.wave_units();
