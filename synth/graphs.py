@@ -208,8 +208,9 @@ def complete_graph(n, extra_isolated=0):
 # --- batched and served workloads --------------------------------------------
 
 def batch_graphs(num_graphs, seed=1, median_nodes=20_000, sigma=1.0, min_nodes=1_000,
-                 max_nodes=1_000_000, avg_degree=8, num_labels=16):
-    """Independent graphs of log-normal size; graph g uses seed (seed, g)."""
+                 max_nodes=1_000_000, avg_degree=8, num_labels=16, progress=None):
+    """Independent graphs of log-normal size; graph g uses seed (seed, g).
+    `progress(msg)`, if given, is called every 256 graphs."""
     rng = _rng(seed)
     sizes = np.clip(np.round(median_nodes * np.exp(sigma * rng.standard_normal(num_graphs))),
                     min_nodes, max_nodes).astype(np.int64)
@@ -220,6 +221,8 @@ def batch_graphs(num_graphs, seed=1, median_nodes=20_000, sigma=1.0, min_nodes=1
                             num_node_labels=num_labels, node_label_exp=0.0,
                             num_edge_labels=num_labels, edge_label_exp=0.0, name="batch%d" % g)
         out.append(gr)
+        if progress is not None and (g + 1) % 256 == 0:
+            progress("batch graphs: %d of %d" % (g + 1, num_graphs))
     return out
 
 
