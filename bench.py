@@ -344,6 +344,7 @@ def bench_served(args, torch, kb, dev):
         g = synth.powerlaw_graph(int(n), int(10 * n), seed=(args.seed, 1000 + i), deg_cap=max(64, int(n) // 10))
         pool.append((g.num_nodes, [torch.from_numpy(a).to(dev) for a in (g.node_label, g.src, g.elab, g.dst)],
                      g.num_edges))
+        log("request pool: graph %d of %d (%d nodes) after %.1f s" % (i + 1, len(sizes), n, time.perf_counter() - t0))
     log("request pool: %d graphs, %d..%d nodes, %.1f s" % (len(pool), sizes[0], sizes[-1], time.perf_counter() - t0))
     reqs = synth.serving_stream(args.requests, seed=args.seed, rate=200.0, max_nodes=args.max_nodes)
     logs = np.log(sizes)
