@@ -116,7 +116,7 @@ typedef enum {
 /* Signature work buckets (kbisim_work), by out-degree. */
 typedef enum {
   KBISIM_BUCKET_THREAD = 0, /* <= 16 edges: one thread per node */
-  KBISIM_BUCKET_WAVE = 1,   /* <= 64 edges: one wave per node */
+  KBISIM_BUCKET_WAVE = 1,   /* <= 64 edges: one wave per node (two per wave when both <= 32) */
   KBISIM_BUCKET_BLOCK = 2,  /* <= 4096 edges: one wave (<= 512 edges, or key-set bitmaps) or
                                one workgroup per node */
   KBISIM_BUCKET_HUB = 3,    /* more edges: all hubs of a round in one device-wide sort (or
