@@ -6,6 +6,8 @@
   python -m paper_1210_0748_amd.profsum traffic <fetch.csv> --write W.csv --cal-fetch CF.csv
          --cal-write CW.csv --kernel SUBSTR --name NAME --out profiles/traffic.json
          [--workload W --k-cap K --no-early-stop]   (the bench job the counters ran)
+  python -m paper_1210_0748_amd.profsum gbs <kernel_stats.csv> --fetch F.csv --write W.csv
+         [--scales profiles/traffic.json] [--top N]
 
 `traffic` turns FETCH_SIZE / WRITE_SIZE runs of a command and of the 1 GiB
 copy probe (paper_1210_0748_amd.copyprobe) into bytes per launch of one
@@ -14,7 +16,10 @@ figure only while the digest matches). `stats` lists kernels by total time; `rou
 refinement rounds (at each launch of the signature kernel) and
 reports busy time, span and launch counts; `counters` averages the PMC
 values (e.g. FETCH_SIZE, WRITE_SIZE in KiB) per dispatch of the kernels whose
-name contains SUBSTR.
+name contains SUBSTR. `gbs` joins a kernel-statistics run with FETCH_SIZE and
+WRITE_SIZE runs of the same command: per kernel the measured HBM bytes per
+dispatch (scaled by the copy-probe factors of `--scales`) over its average
+duration, and that rate as a fraction of the 8 TB/s peak.
 """
 from __future__ import annotations
 
@@ -64,6 +69,35 @@ def cmd_counters(path, kernel):
             acc[r["Counter_Name"]].append(float(r["Counter_Value"]))
     for name, vals in sorted(acc.items()):
         print("%-14s dispatches %5d  mean %14.1f  max %14.1f" % (name, len(vals), sum(vals) / len(vals), max(vals)))
+
+
+def _per_kernel_mean(path):
+    acc = defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        acc[r["Kernel_Name"]].append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
+def cmd_gbs(stats_path, fetch_path, write_path, scales_path, top, peak_gbs=8000.0):
+    import json
+    with open(scales_path) as fh:
+        t = json.load(fh)
+    fs, ws = float(t["fetch_scale"]), float(t["write_scale"])
+    fetch, write = _per_kernel_mean(fetch_path), _per_kernel_mean(write_path)
+    rows = list(csv.DictReader(open(stats_path)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    print("%-60s %6s %9s %10s %10s %8s %6s" % ("kernel", "calls", "avg_us", "fetch_MB", "write_MB", "GB/s",
+                                                "of_8TB"))
+    for r in rows[:top] if top > 0 else rows:
+        name = r["Name"]
+        if name not in fetch or name not in write:
+            continue
+        fb = fetch[name] * 1024.0 * fs
+        wb = write[name] * 1024.0 * ws
+        avg_ns = float(r["AverageNs"])
+        gbs = (fb + wb) / avg_ns if avg_ns > 0 else 0.0
+        print("%-60s %6s %9.1f %10.2f %10.2f %8.0f %6.3f" % (short(name, 60), r["Calls"], avg_ns / 1e3, fb / 1e6,
+                                                             wb / 1e6, gbs, gbs / peak_gbs))
 
 
 def _values(path, kernel):
@@ -120,11 +154,13 @@ def cmd_traffic(a):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["stats", "rounds", "counters", "traffic"])
+    ap.add_argument("mode", choices=["stats", "rounds", "counters", "traffic", "gbs"])
     ap.add_argument("csv")
     ap.add_argument("--top", type=int, default=25)
     ap.add_argument("--kernel", default="")
     ap.add_argument("--write", default=None)
+    ap.add_argument("--fetch", default=None)
+    ap.add_argument("--scales", default="profiles/traffic.json")
     ap.add_argument("--cal-fetch", default=None)
     ap.add_argument("--cal-write", default=None)
     ap.add_argument("--name", default=None)
@@ -139,6 +175,8 @@ def main(argv=None):
         cmd_rounds(a.csv)
     elif a.mode == "counters":
         cmd_counters(a.csv, a.kernel)
+    elif a.mode == "gbs":
+        cmd_gbs(a.csv, a.fetch, a.write, a.scales, a.top if a.top != 25 else 0)
     else:
         cmd_traffic(a)
 
