@@ -16,6 +16,8 @@ Prints one JSON line (rank 0). Options:
   --no-cpu-baseline   skip timing the oracle on the host
   --form F        plain (default), batched or served: the two system forms
                   print their own JSON line (see bench_batched / bench_served)
+  --host-io M     plain job with host inputs and result (pinned or pageable):
+                  the PCIe-inclusive rate, on its own JSON line
 """
 from __future__ import annotations
 
@@ -116,6 +118,8 @@ def main():
     ap.add_argument("--requests", type=int, default=300, help="served: number of requests")
     ap.add_argument("--max-nodes", type=int, default=10_000_000, help="served: largest request")
     ap.add_argument("--slots", type=int, default=4, help="served: concurrent slots")
+    ap.add_argument("--host-io", choices=["pinned", "pageable"], default=None,
+                    help="plain form: inputs and result in host memory (PCIe included; its own JSON line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: there is no multi-GPU path "
@@ -135,6 +139,8 @@ def main():
         return bench_batched(args, torch, kb, dev)
     if args.form == "served":
         return bench_served(args, torch, kb, dev)
+    if args.host_io:
+        return bench_host_io(args, torch, kb)
 
     t0 = time.perf_counter()
     g, k_default = synth.make_config(args.workload, seed=args.seed, progress=log)
@@ -322,6 +328,55 @@ def bench_batched(args, torch, kb, dev):
         "medium_cap": cap, "tune_seconds": tune_times,
         "per_graph_loop": {"ms": t_loop * 1e3, "edge_rounds_per_s": edge_rounds / t_loop},
         "speedup_vs_loop": t_loop / t_batch, "identical_to_loop": same,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_host_io(args, torch, kb):
+    """The plain job with the edge table and labels in host memory and the
+    ids returned to host memory: create copies the inputs over PCIe, the
+    result copies the ids back. Pinned buffers come from torch's pinned
+    allocator; pageable ones are plain numpy arrays."""
+    import numpy as np
+    import synth
+    g, k_default = synth.make_config(args.workload, seed=args.seed, progress=log)
+    k = args.k if args.k is not None else k_default
+    if args.host_io == "pinned":
+        keep = [torch.from_numpy(a).pin_memory() for a in (g.node_label, g.src, g.elab, g.dst)]
+        inputs = [t.numpy() for t in keep]
+        keep.append(torch.empty(g.num_nodes, dtype=torch.int32).pin_memory())
+        out = keep[-1].numpy()
+    else:
+        inputs = [g.node_label, g.src, g.elab, g.dst]
+        out = np.empty(g.num_nodes, np.int32)
+
+    def job():
+        h = kb.kbisim_create(g.num_nodes, *inputs, early_stop=not args.no_early_stop)
+        try:
+            rd = kb.kbisim_refine(h, k)
+            _, counts = kb.kbisim_result(h, out, counts_cap=k + 1)
+        finally:
+            kb.kbisim_destroy(h)
+        return rd, counts
+
+    for _ in range(args.warmup):
+        job()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        rd, counts = job()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / max(args.steps, 1)
+    in_bytes = 4 * (g.num_nodes + 3 * g.num_edges)
+    line = {
+        "metric": "edge-rounds/s including the host-device copies (%s host memory), %s" % (args.host_io,
+                                                                                     args.workload),
+        "value": g.num_edges * rd / (ms / 1e3), "unit": "edge-rounds/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": args.workload, "num_nodes": g.num_nodes, "num_edges": g.num_edges, "k_cap": k,
+                   "rounds": rd, "counts": counts, "host_io": args.host_io,
+                   "bytes_in": in_bytes, "bytes_out": 4 * g.num_nodes},
     }
     print(json.dumps(line), flush=True)
 
