@@ -18,6 +18,9 @@ Prints one JSON line (rank 0). Options:
                   print their own JSON line (see bench_batched / bench_served)
   --host-io M     plain job with host inputs and result (pinned or pageable):
                   the PCIe-inclusive rate, on its own JSON line
+  --copy-probe    only a 1 GiB device-to-device copy (1 GiB read, 1 GiB
+                  written): the calibration run for rocprofv3 FETCH_SIZE /
+                  WRITE_SIZE readings of the library's kernels
 """
 from __future__ import annotations
 
@@ -120,6 +123,8 @@ def main():
     ap.add_argument("--slots", type=int, default=4, help="served: concurrent slots")
     ap.add_argument("--host-io", choices=["pinned", "pageable"], default=None,
                     help="plain form: inputs and result in host memory (PCIe included; its own JSON line)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only a 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: there is no multi-GPU path "
@@ -135,6 +140,8 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     dev = torch.device("cuda:0")
+    if args.copy_probe:
+        return copy_probe(torch, dev)
     if args.form == "batched":
         return bench_batched(args, torch, kb, dev)
     if args.form == "served":
@@ -249,6 +256,19 @@ def main():
         log("timing the oracle on the host ...")
         line["cpu_baseline"] = cpu_baseline(args.seed, g, k, early_stop)
     print(json.dumps(line), flush=True)
+
+
+def copy_probe(torch, dev):
+    """A device copy of known size (1 GiB read, 1 GiB written). Run under the
+    same rocprofv3 counter collection as the library, its FETCH_SIZE and
+    WRITE_SIZE readings turn the library's readings into bytes."""
+    n = 1 << 28  # int32 elements: 1 GiB
+    a = torch.ones(n, dtype=torch.int32, device=dev)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    log("copied %d bytes" % (4 * n))
 
 
 def pct(xs, q):

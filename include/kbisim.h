@@ -195,10 +195,11 @@ void kbisim_batch_destroy(kbisim_batch* b);
  * concurrently, each on its own stream with its partition state resident in
  * device memory across rounds, so requests that arrive while others run
  * overlap with them on the device. Results equal those of kbisim_refine on
- * the same graph alone. desc->stream is ignored. Host input arrays are
- * copied by submit; DEVICE input arrays are read when the request runs and
- * must stay valid until kbisim_server_wait has returned for it. opt may be
- * NULL; its profile field is ignored. */
+ * the same graph alone. Host input arrays are copied by submit. DEVICE
+ * input arrays are read when the request runs, after all work enqueued on
+ * desc->stream before the submit call (an event recorded there; NULL = the
+ * default stream), and must stay valid until kbisim_server_wait has
+ * returned for the request. opt may be NULL; its profile field is ignored. */
 typedef struct kbisim_server kbisim_server;
 
 kbisim_status kbisim_server_create(uint64_t hbm_budget_bytes, int32_t max_slots, const kbisim_options* opt,
@@ -229,6 +230,17 @@ kbisim_status kbisim_server_release(kbisim_server* s, uint64_t req_id);
 
 /* Device bytes currently reserved by running requests (their estimates). */
 kbisim_status kbisim_server_in_use(kbisim_server* s, uint64_t* bytes);
+
+/* Lifecycle state of a request (kbisim_request_state); KBISIM_EINVAL for an
+ * unknown or released id. */
+typedef enum {
+  KBISIM_REQ_QUEUED = 0,
+  KBISIM_REQ_RUNNING = 1,
+  KBISIM_REQ_DONE = 2,
+  KBISIM_REQ_FAILED = 3,
+  KBISIM_REQ_CANCELLED = 4
+} kbisim_request_state;
+kbisim_status kbisim_server_state(kbisim_server* s, uint64_t req_id, int32_t* state);
 
 /* Cancels queued and running requests, waits for the workers, frees all. */
 void kbisim_server_destroy(kbisim_server* s);

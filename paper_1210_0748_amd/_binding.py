@@ -14,6 +14,7 @@ KBISIM_MEM_DEVICE = 1
 PROF_CLASSES = ["signature", "order", "assign", "round"]
 WORK_BUCKETS = ["thread", "wave", "block", "hub"]
 
+REQUEST_STATES = ["queued", "running", "done", "failed", "cancelled"]
 STATUS = {0: "KBISIM_OK", -1: "KBISIM_EINVAL", -2: "KBISIM_ENOMEM", -3: "KBISIM_EDEVICE",
           -4: "KBISIM_ESTATE", -5: "KBISIM_EBUSY", -6: "KBISIM_ECANCELED", -7: "KBISIM_ETIMEDOUT"}
 
@@ -92,6 +93,8 @@ def load_library():
     lib.kbisim_server_timing.restype = ctypes.c_int
     lib.kbisim_server_release.argtypes = [vp, u64]
     lib.kbisim_server_release.restype = ctypes.c_int
+    lib.kbisim_server_state.argtypes = [vp, u64, ctypes.POINTER(i32)]
+    lib.kbisim_server_state.restype = ctypes.c_int
     lib.kbisim_server_in_use.argtypes = [vp, ctypes.POINTER(u64)]
     lib.kbisim_server_in_use.restype = ctypes.c_int
     lib.kbisim_server_destroy.argtypes = [vp]
@@ -396,7 +399,8 @@ class Server:
         kept alive here until the request has been waited for."""
         mem, ptrs, keep = _arrays(node_label, src, elab, dst)
         n, m = int(num_nodes), int(keep[1].shape[0])
-        desc = GraphDesc(n, m, ptrs[0] or None, ptrs[1] or None, ptrs[2] or None, ptrs[3] or None, mem, None)
+        stream = _stream_ptr(None) if mem == KBISIM_MEM_DEVICE else None
+        desc = GraphDesc(n, m, ptrs[0] or None, ptrs[1] or None, ptrs[2] or None, ptrs[3] or None, mem, stream)
         rid = ctypes.c_uint64(0)
         _check(load_library().kbisim_server_submit(self._h, ctypes.byref(desc), int(k), ctypes.byref(rid)))
         if mem == KBISIM_MEM_DEVICE:
@@ -429,6 +433,12 @@ class Server:
     def release(self, rid):
         _check(load_library().kbisim_server_release(self._h, int(rid)))
         self._n.pop(rid, None)
+
+    def state(self, rid):
+        """One of REQUEST_STATES (queued, running, done, failed, cancelled)."""
+        st = ctypes.c_int32(0)
+        _check(load_library().kbisim_server_state(self._h, int(rid), ctypes.byref(st)))
+        return REQUEST_STATES[st.value]
 
     def in_use(self):
         b = ctypes.c_uint64(0)

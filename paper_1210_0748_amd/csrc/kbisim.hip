@@ -1169,7 +1169,11 @@ Server::~Server() {
   {
     std::lock_guard<std::mutex> lk(mu_);
     stop_ = true;
-    for (auto& r : queue_) r->state = Request::kCancelled;
+    for (auto& r : queue_) {
+      r->state = Request::kCancelled;
+      if (r->ready) (void)hipEventDestroy(r->ready);
+      r->ready = nullptr;
+    }
     queue_.clear();
     for (auto& kv : all_)
       if (kv.second->state == Request::kRunning) kv.second->cancel = true;
@@ -1181,7 +1185,7 @@ Server::~Server() {
 }
 
 uint64_t Server::submit(const int32_t* label, const int32_t* src, const int32_t* lab, const int32_t* dst, int64_t n,
-                        int64_t m, bool device_inputs, int32_t k) {
+                        int64_t m, bool device_inputs, int32_t k, hipStream_t caller) {
   auto r = std::make_shared<Request>();
   r->k = k;
   r->n = n;
@@ -1196,6 +1200,15 @@ uint64_t Server::submit(const int32_t* label, const int32_t* src, const int32_t*
     r->dev[1] = src;
     r->dev[2] = lab;
     r->dev[3] = dst;
+    // the caller's kernels that write the inputs may still be in flight:
+    // the worker's stream waits for this point of the caller's stream
+    KB_CHECK(hipEventCreateWithFlags(&r->ready, hipEventDisableTiming));
+    const hipError_t e = hipEventRecord(r->ready, caller);
+    if (e != hipSuccess) {
+      (void)hipEventDestroy(r->ready);
+      r->ready = nullptr;
+      KB_CHECK(e);
+    }
   } else {
     r->host[0].assign(label, label + n);
     r->host[1].assign(src, src + m);
@@ -1204,7 +1217,10 @@ uint64_t Server::submit(const int32_t* label, const int32_t* src, const int32_t*
   }
   r->t_submit = std::chrono::steady_clock::now();
   std::lock_guard<std::mutex> lk(mu_);
-  if (stop_) throw StateError("server is shutting down");
+  if (stop_) {
+    if (r->ready) (void)hipEventDestroy(r->ready);
+    throw StateError("server is shutting down");
+  }
   r->id = next_id_++;
   all_[r->id] = r;
   queue_.push_back(r);
@@ -1254,6 +1270,10 @@ void Server::worker(int slot) {
       r->error = err;
       r->state = cancelled ? Request::kCancelled : status ? Request::kFailed : Request::kDone;
       for (auto& h : r->host) std::vector<int32_t>().swap(h);  // inputs no longer needed
+      if (r->ready) {
+        (void)hipEventDestroy(r->ready);
+        r->ready = nullptr;
+      }
     }
     cv_done_.notify_all();
     cv_work_.notify_all();  // memory came back: the queue head may fit now
@@ -1264,6 +1284,7 @@ void Server::run(Request& r, hipStream_t s) {
   StreamScope scope(s);
   Engine eng(r.n, r.m, s, opt_);
   if (r.device_inputs) {
+    KB_CHECK(hipStreamWaitEvent(s, r.ready, 0));
     eng.build(r.dev[0], r.dev[1], r.dev[2], r.dev[3]);
   } else {
     DevBuf b[4];
@@ -1332,6 +1353,8 @@ int Server::cancel(uint64_t id) {
         break;
       }
     r.state = Request::kCancelled;
+    if (r.ready) (void)hipEventDestroy(r.ready);
+    r.ready = nullptr;
     cv_done_.notify_all();
     cv_work_.notify_all();
     return KBISIM_OK;
@@ -1341,6 +1364,20 @@ int Server::cancel(uint64_t id) {
     return KBISIM_OK;
   }
   return KBISIM_ESTATE;  // already finished
+}
+
+int Server::state(uint64_t id, int32_t* st) {
+  std::lock_guard<std::mutex> lk(mu_);
+  auto it = all_.find(id);
+  if (it == all_.end()) return KBISIM_EINVAL;
+  switch (it->second->state) {
+    case Request::kQueued: *st = KBISIM_REQ_QUEUED; break;
+    case Request::kRunning: *st = KBISIM_REQ_RUNNING; break;
+    case Request::kDone: *st = KBISIM_REQ_DONE; break;
+    case Request::kFailed: *st = KBISIM_REQ_FAILED; break;
+    case Request::kCancelled: *st = KBISIM_REQ_CANCELLED; break;
+  }
+  return KBISIM_OK;
 }
 
 bool Server::timing(uint64_t id, double* queued_s, double* total_s) {
@@ -1630,7 +1667,7 @@ kbisim_status kbisim_server_submit(kbisim_server* h, const kbisim_graph_desc* d,
   if (d->mem != KBISIM_MEM_HOST && d->mem != KBISIM_MEM_DEVICE) return fail(KBISIM_EINVAL, "bad mem kind");
   return guarded([&]() {
     *req_id = h->s->submit(d->node_label, d->edge_src, d->edge_label, d->edge_dst, d->num_nodes, d->num_edges,
-                           d->mem == KBISIM_MEM_DEVICE, k);
+                           d->mem == KBISIM_MEM_DEVICE, k, static_cast<hipStream_t>(d->stream));
     return KBISIM_OK;
   });
 }
@@ -1666,6 +1703,12 @@ kbisim_status kbisim_server_timing(kbisim_server* h, uint64_t req_id, double* qu
 kbisim_status kbisim_server_release(kbisim_server* h, uint64_t req_id) {
   if (!h || !h->s) return fail(KBISIM_EINVAL, "null handle");
   h->s->release(req_id);
+  return KBISIM_OK;
+}
+
+kbisim_status kbisim_server_state(kbisim_server* h, uint64_t req_id, int32_t* state) {
+  if (!h || !h->s || !state) return fail(KBISIM_EINVAL, "null argument");
+  if (h->s->state(req_id, state) != KBISIM_OK) return fail(KBISIM_EINVAL, "unknown id");
   return KBISIM_OK;
 }
 

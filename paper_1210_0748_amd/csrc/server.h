@@ -41,6 +41,7 @@ struct Request {
   int64_t n = 0, m = 0;
   bool device_inputs = false;
   const int32_t* dev[4] = {nullptr, nullptr, nullptr, nullptr};  // caller-owned device arrays
+  hipEvent_t ready = nullptr;  // device inputs: recorded on the caller's stream at submit
   std::vector<int32_t> host[4];                                   // copies of host arrays
   uint64_t footprint = 0;
   State state = kQueued;
@@ -58,8 +59,10 @@ class Server {
   Server(uint64_t budget, int32_t slots, const Options& o);
   ~Server();
   // Returns the request id; throws InvalidInput / OutOfMemory (never fits).
+  // Device inputs are read after the work enqueued on `caller` before the
+  // call (an event recorded there at submit, waited for by the worker).
   uint64_t submit(const int32_t* label, const int32_t* src, const int32_t* lab, const int32_t* dst, int64_t n,
-                  int64_t m, bool device_inputs, int32_t k);
+                  int64_t m, bool device_inputs, int32_t k, hipStream_t caller);
   // Waits up to timeout_s (< 0: forever). Returns 0 when done and fills the
   // outputs; otherwise a negative status (failed/cancelled/timed out).
   int wait(uint64_t id, int32_t* pid_out, bool to_device, int64_t* num_blocks, int32_t* rounds,
@@ -68,6 +71,7 @@ class Server {
   // Seconds from submit to start and to completion (done requests).
   bool timing(uint64_t id, double* queued_s, double* total_s);
   void release(uint64_t id);  // forget a finished request
+  int state(uint64_t id, int32_t* st);  // KBISIM_EINVAL for an unknown id
   uint64_t in_use() {
     std::lock_guard<std::mutex> lk(mu_);
     return in_use_;

@@ -10,7 +10,7 @@
          [--scales profiles/traffic.json] [--top N]
 
 `traffic` turns FETCH_SIZE / WRITE_SIZE runs of a command and of the 1 GiB
-copy probe (paper_1210_0748_amd.copyprobe) into bytes per launch of one
+copy probe (`bench.py --copy-probe`) into bytes per launch of one
 kernel, stamped with a digest of the kernel sources (bench.py reports the
 figure only while the digest matches). `stats` lists kernels by total time; `rounds` splits a kernel trace into
 refinement rounds (at each launch of the signature kernel) and

@@ -102,3 +102,58 @@ def test_cancel_queued():
             assert e.value.status in (-6,)
         out, nb, rd = srv.wait(first, timeout_s=60)
         assert out.shape[0] == gs[6].num_nodes
+
+
+def test_device_inputs_written_by_pending_kernels():
+    """Device inputs still being written by kernels on the caller's stream
+    when submit is called (no synchronisation): the request must read them
+    after those kernels."""
+    torch, kb = need_gpu()
+    dev = torch.device("cuda:0")
+    n, m = 60000, 480000
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(11)
+    with kb.Server(4 * GB, max_slots=2) as srv:
+        say("queueing a long kernel ahead of the input writes")
+        if hasattr(torch.cuda, "_sleep"):
+            torch.cuda._sleep(200_000_000)
+        else:  # pragma: no cover
+            x = torch.ones(4096, 4096, device=dev)
+            for _ in range(8):
+                x = x @ x * 1e-4
+        lab = torch.randint(0, 7, (n,), device=dev, dtype=torch.int32, generator=gen)
+        src = torch.randint(0, n, (m,), device=dev, dtype=torch.int32, generator=gen)
+        elab = torch.randint(0, 5, (m,), device=dev, dtype=torch.int32, generator=gen)
+        dst = torch.randint(0, n, (m,), device=dev, dtype=torch.int32, generator=gen)
+        rid = srv.submit(n, lab, src, elab, dst, 6)
+        out, nb, rd = srv.wait(rid, timeout_s=60)
+    host = [t.cpu().numpy() for t in (lab, src, elab, dst)]
+    r = oracle.refine(n, *host, 6)
+    assert rd == r.rounds_done and nb == r.counts[-1]
+    assert np.array_equal(out, r.pid)
+
+
+def test_cancel_running_keeps_neighbours():
+    """A running request cancelled from the host stops at a round boundary
+    and reports ECANCELED; requests running beside it are unaffected."""
+    torch, kb = need_gpu()
+    long_g = synth.path_graph(3000)  # 3000 rounds to its fixed point
+    gs = request_graphs()[:4]
+    with kb.Server(8 * GB, max_slots=4) as srv:
+        rid_long = srv.submit(long_g.num_nodes, long_g.node_label, long_g.src, long_g.elab, long_g.dst, 3000)
+        ids = [srv.submit(g.num_nodes, g.node_label, g.src, g.elab, g.dst, 6) for g in gs]
+        t0 = time.perf_counter()
+        while srv.state(rid_long) == "queued" and time.perf_counter() - t0 < 30:
+            time.sleep(0.001)
+        assert srv.state(rid_long) == "running", srv.state(rid_long)
+        srv.cancel(rid_long)
+        say("cancelled the running request")
+        with pytest.raises(kb.KbisimError) as e:
+            srv.wait(rid_long, timeout_s=60)
+        assert e.value.status == -6
+        assert srv.state(rid_long) == "cancelled"
+        for rid, g in zip(ids, gs):
+            out, nb, rd = srv.wait(rid, timeout_s=60)
+            r = oracle.refine(g.num_nodes, g.node_label, g.src, g.elab, g.dst, 6)
+            assert np.array_equal(out, r.pid) and rd == r.rounds_done, g.name
+        assert srv.in_use() == 0
