@@ -10,8 +10,12 @@ Contents
 * ``refine``      -- Build_Bisim (Algorithm 1, Section 3) in plain C++17 with
                      S as an ordered dictionary; canonical ids are per-round
                      lexicographic signature ranks.
+* ``signature_lengths`` -- lengths of all signatures from given previous ids.
 * ``signatures``  -- Definition 3 signatures of sampled nodes from a given
                      previous-round id array (one-round checks at full size).
+* ``maintain``    -- the maintenance algorithms of Section 4 (Add_Nodes,
+                     Add_Edges, deletions) on a stored history, in the
+                     paper's numbering, and the updated graph by definition.
 * ``bruteforce``  -- pairwise bisimilarity from Definition 1, Kaushik's
                      definition and the Paige-Tarjan stable-partition
                      definition (Appendix, "Alternative definitions"), plus the
@@ -31,6 +35,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "kbisim_oracle.cpp")
+_SRCS = [_SRC, os.path.join(_HERE, "maintain_oracle.cpp")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 HEAD_PID0 = 1
@@ -40,9 +45,10 @@ NO_EARLY_STOP = 4
 
 def build(force: bool = False) -> str:
     """Compile the C++ oracle with g++ (one thread, -O2). Returns the .so path."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    newest = max(os.path.getmtime(f) for f in _SRCS)
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < newest:
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["g++", "-std=c++17", "-O2", "-fPIC", "-shared", "-o", tmp, _SRC])
+        subprocess.check_call(["g++", "-std=c++17", "-O2", "-fPIC", "-shared", "-o", tmp] + _SRCS)
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -60,6 +66,25 @@ def _load():
         lib.oracle_refine.argtypes = [i64, i64, p, p, p, p, i32, i32, p, p, p, p, p]
         lib.oracle_signatures.restype = i32
         lib.oracle_signatures.argtypes = [i64, i64, p, p, p, p, i64, p, p, p]
+        lib.oracle_signature_lengths.restype = i32
+        lib.oracle_signature_lengths.argtypes = [i64, i64, p, p, p, p, p]
+        lib.oracle_state_create.restype = p
+        lib.oracle_state_create.argtypes = [i64, p, i64, p, p, p, i32]
+        lib.oracle_state_destroy.restype = None
+        lib.oracle_state_destroy.argtypes = [p]
+        lib.oracle_state_num_nodes.restype = i64
+        lib.oracle_state_num_nodes.argtypes = [p]
+        lib.oracle_state_history.restype = None
+        lib.oracle_state_history.argtypes = [p, p]
+        lib.oracle_state_work.restype = None
+        lib.oracle_state_work.argtypes = [p, p, p]
+        lib.oracle_state_add_nodes.restype = i32
+        lib.oracle_state_add_nodes.argtypes = [p, i64, p]
+        for f in ("oracle_state_add_edges", "oracle_state_delete_edges"):
+            getattr(lib, f).restype = i32
+            getattr(lib, f).argtypes = [p, i64, p, p, p]
+        lib.oracle_state_delete_nodes.restype = i32
+        lib.oracle_state_delete_nodes.argtypes = [p, i64, p]
         _lib = lib
     return _lib
 
@@ -112,6 +137,30 @@ def refine(num_nodes, node_label, src, elab, dst, k, *, head_pid0=False,
     r = int(rd[0])
     return Result(pid=pid, counts=[int(c) for c in counts[: r + 1]],
                   max_sig_ints=[int(c) for c in msi[: r + 1]], rounds_done=r, history=hist)
+
+
+def signature_lengths(num_nodes, src, elab, dst, pid_prev):
+    """[N] int64: length (ints) of every node's signature from pid_prev."""
+    lib = _load()
+    n = int(num_nodes)
+    src, elab, dst, pid_prev = _i32(src), _i32(elab), _i32(dst), _i32(pid_prev)
+    out = np.empty(n, np.int64)
+    if lib.oracle_signature_lengths(n, int(src.shape[0]), _ptr(src), _ptr(elab), _ptr(dst), _ptr(pid_prev),
+                                    _ptr(out)) != 0:
+        raise OracleError("invalid input")
+    return out
+
+
+def longest_multi_member(lengths, pid_prev):
+    """Longest signature among the nodes whose class in the previous round
+    has two or more members (1 when there is none): nodes alone in their
+    class keep it in every later round whatever their signature."""
+    pid_prev = np.asarray(pid_prev)
+    if pid_prev.size == 0:
+        return 1
+    sizes = np.bincount(pid_prev)
+    multi = sizes[pid_prev] >= 2
+    return int(max(1, lengths[multi].max())) if multi.any() else 1
 
 
 def signatures(num_nodes, src, elab, dst, pid_prev, sample):

@@ -228,4 +228,19 @@ int32_t oracle_signatures(int64_t n, int64_t m, const int32_t* src, const int32_
   return ORACLE_OK;
 }
 
+// Length (as a count of ints, 1 + 2 * pairs) of every node's signature built
+// from a given previous-round id array; len_out[N]. Returns 0 or -1.
+int32_t oracle_signature_lengths(int64_t n, int64_t m, const int32_t* src, const int32_t* elab,
+                                 const int32_t* dst, const int32_t* pid_prev, int64_t* len_out) {
+  if (n < 0 || m < 0) return ORACLE_EINVAL;
+  std::vector<std::vector<std::pair<int32_t, int32_t>>> out(n);
+  for (int64_t e = 0; e < m; ++e) {
+    if (src[e] < 0 || src[e] >= n || dst[e] < 0 || dst[e] >= n) return ORACLE_EINVAL;
+    out[src[e]].emplace_back(elab[e], dst[e]);
+  }
+  std::vector<int32_t> prev(pid_prev, pid_prev + n);
+  for (int64_t v = 0; v < n; ++v) len_out[v] = int64_t(build_signature(prev[v], out[v], prev).size());
+  return ORACLE_OK;
+}
+
 }  // extern "C"

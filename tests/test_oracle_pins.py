@@ -245,3 +245,21 @@ def test_invalid_input_rejected():
         oracle.refine(2, [0, 0], [0], [-1], [1], 1)  # negative edge label
     with pytest.raises(oracle.OracleError):
         oracle.refine(2, [0, 0], z, z, z, -1)
+
+
+def test_signature_lengths_table1():
+    """Lengths of Table 1's signatures (sig_1 and sig_2 as printed) from the
+    previous round's ids; and the longest among nodes of non-singleton
+    classes (all of round 1's classes have two or more members)."""
+    fx = load("figure1.json")
+    g = graph_of(fx)
+    pn = fx["paper_numbering"]
+    for j, key in ((1, "sig1"), (2, "sig2")):
+        lengths = oracle.signature_lengths(g.num_nodes, g.src, g.elab, g.dst, pn["pid"][j - 1])
+        assert lengths.tolist() == [len(s) for s in pn[key]]
+    lengths = oracle.signature_lengths(g.num_nodes, g.src, g.elab, g.dst, pn["pid"][0])
+    assert oracle.longest_multi_member(lengths, np.asarray(pn["pid"][0]) - 1) == 5
+    # round 2: classes of pId_1 {1,2}, {3,5} have two members; 4 and 6 are alone
+    lengths = oracle.signature_lengths(g.num_nodes, g.src, g.elab, g.dst, pn["pid"][1])
+    assert oracle.longest_multi_member(lengths, np.asarray(pn["pid"][1]) - 3) == 5
+    assert oracle.longest_multi_member(np.array([7, 3, 5]), np.array([0, 1, 2])) == 1
