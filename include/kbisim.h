@@ -78,6 +78,12 @@ typedef struct {
                          workgroup in LDS, larger ones by global radix passes; 0..4096,
                          values <= 64 send every group above 64 members to the global
                          passes; 0 = library default (4096). Ids do not depend on it. */
+  int32_t history;    /* 1: keep the partition of every computed round (the node table
+                         with pId_0..pId_k of Section 4, Table 3) and the maintenance
+                         state (edges also by target, the label values), about
+                         8 B per node per round plus the edge table again; needed by
+                         kbisim_result_round for earlier rounds and by kbisim_update.
+                         0 (default): only the last round. */
 } kbisim_options;
 
 /* Fills *opt with the defaults above. */
@@ -103,6 +109,56 @@ kbisim_status kbisim_refine(kbisim_graph* g, int32_t k, int32_t* rounds_done);
  * B_0, B_1, ... . Any pointer may be NULL to skip that output. */
 kbisim_status kbisim_result(const kbisim_graph* g, int32_t* pid_out, kbisim_mem mem,
                             int64_t* num_blocks, int64_t* counts, int32_t counts_cap);
+
+/* Change of k (Section 4, "Change k"): the ids of round j (pId_j, canonical
+ * as above) and B_j, for j <= rounds done, read from the stored history
+ * without recomputing anything (a larger k is kbisim_refine). Rounds past an
+ * early stop equal the last round. Earlier rounds need options.history = 1
+ * (else KBISIM_ESTATE); a round not computed yet is KBISIM_ESTATE. pid_out
+ * [N] in host or device memory (device: on the handle's stream, then
+ * synchronised); either pointer may be NULL. */
+kbisim_status kbisim_result_round(const kbisim_graph* g, int32_t round, int32_t* pid_out, kbisim_mem mem,
+                                  int64_t* num_blocks);
+
+/* One change to the graph of a handle (Section 4, maintenance), applied in
+ * this order: new isolated nodes appended (Algorithm 2, Add_Nodes; ids N,
+ * N+1, ...), then deletions of edge triples (every copy of each triple goes;
+ * triples not in the graph are ignored), then additions of edge triples
+ * (Algorithm 3, Add_Edges; endpoints may be the new nodes). All arrays are
+ * in `mem` and read during the call. */
+typedef struct {
+  int64_t num_new_nodes;          /* >= 0 */
+  const int32_t* new_node_label;  /* [num_new_nodes], values >= 0 */
+  int64_t num_del_edges;          /* >= 0 */
+  const int32_t* del_src;         /* [num_del_edges] each */
+  const int32_t* del_label;
+  const int32_t* del_dst;
+  int64_t num_add_edges;          /* >= 0 */
+  const int32_t* add_src;         /* [num_add_edges] each */
+  const int32_t* add_label;
+  const int32_t* add_dst;
+  kbisim_mem mem;
+} kbisim_update_desc;
+
+/* Applies the update and brings every stored round up to date (Algorithm 3's
+ * level-by-level propagation: per round, the sources of changed edges, the
+ * nodes whose class changed in the round below and their sources are
+ * re-checked; classes holding none of them keep their stored split). When
+ * the update moves the fixed point, rounds continue up to the largest k
+ * given to kbisim_refine (or stop earlier at the new fixed point). Afterwards
+ * the handle holds exactly what kbisim_create on the updated graph followed
+ * by kbisim_refine(k) gives: every round's ids, counts and rounds done.
+ * Needs options.history = 1 (else KBISIM_ESTATE). Invalid input
+ * (an endpoint outside [0, N + num_new_nodes), a negative label) is
+ * KBISIM_EINVAL and leaves the handle unchanged. *rounds_done may be NULL. */
+kbisim_status kbisim_update(kbisim_graph* g, const kbisim_update_desc* u, int32_t* rounds_done);
+
+/* Work of the last kbisim_update: rounds brought up to date, nodes re-checked
+ * (the frontiers, summed over rounds), nodes whose signature was recomputed
+ * (members of the re-ordered classes) and nodes found changed. Any pointer
+ * may be NULL. */
+kbisim_status kbisim_update_stats(const kbisim_graph* g, int64_t* levels, int64_t* rechecked, int64_t* recomputed,
+                                  int64_t* changed);
 
 /* Kernel classes timed when options.profile = 1. */
 typedef enum {

@@ -236,7 +236,7 @@ int32_t oracle_signature_lengths(int64_t n, int64_t m, const int32_t* src, const
   std::vector<std::vector<std::pair<int32_t, int32_t>>> out(n);
   for (int64_t e = 0; e < m; ++e) {
     if (src[e] < 0 || src[e] >= n || dst[e] < 0 || dst[e] >= n) return ORACLE_EINVAL;
-    out[src[e]].emplace_back(elab[e], dst[e]);
+    out[size_t(src[e])].push_back({elab[e], dst[e]});
   }
   std::vector<int32_t> prev(pid_prev, pid_prev + n);
   for (int64_t v = 0; v < n; ++v) len_out[v] = int64_t(build_signature(prev[v], out[v], prev).size());

@@ -34,7 +34,16 @@ class GraphDesc(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("early_stop", ctypes.c_int32), ("profile", ctypes.c_int32),
-                ("medium_cap", ctypes.c_int32)]
+                ("medium_cap", ctypes.c_int32), ("history", ctypes.c_int32)]
+
+
+class UpdateDesc(ctypes.Structure):
+    _fields_ = [("num_new_nodes", ctypes.c_int64), ("new_node_label", ctypes.c_void_p),
+                ("num_del_edges", ctypes.c_int64), ("del_src", ctypes.c_void_p),
+                ("del_label", ctypes.c_void_p), ("del_dst", ctypes.c_void_p),
+                ("num_add_edges", ctypes.c_int64), ("add_src", ctypes.c_void_p),
+                ("add_label", ctypes.c_void_p), ("add_dst", ctypes.c_void_p),
+                ("mem", ctypes.c_int)]
 
 
 _lib = None
@@ -62,6 +71,13 @@ def load_library():
     lib.kbisim_refine.restype = ctypes.c_int
     lib.kbisim_result.argtypes = [vp, vp, ctypes.c_int, ctypes.POINTER(i64), vp, i32]
     lib.kbisim_result.restype = ctypes.c_int
+    lib.kbisim_result_round.argtypes = [vp, i32, vp, ctypes.c_int, ctypes.POINTER(i64)]
+    lib.kbisim_result_round.restype = ctypes.c_int
+    lib.kbisim_update.argtypes = [vp, ctypes.POINTER(UpdateDesc), ctypes.POINTER(i32)]
+    lib.kbisim_update.restype = ctypes.c_int
+    lib.kbisim_update_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                        ctypes.POINTER(i64)]
+    lib.kbisim_update_stats.restype = ctypes.c_int
     lib.kbisim_profile.argtypes = [vp, vp, vp, i32, i32]
     lib.kbisim_profile.restype = ctypes.c_int
     lib.kbisim_work.argtypes = [vp, vp, i32, i32]
@@ -157,7 +173,7 @@ def _arrays(node_label, src, elab, dst):
 
 
 def kbisim_create(num_nodes, node_label, src, elab, dst, *, stream=None, early_stop=True,
-                  profile=False, medium_cap=None):
+                  profile=False, medium_cap=None, history=False):
     """Creates a device-resident graph handle (see kbisim.h). Returns the handle."""
     lib = load_library()
     mem, ptrs, keep = _arrays(node_label, src, elab, dst)
@@ -170,6 +186,7 @@ def kbisim_create(num_nodes, node_label, src, elab, dst, *, stream=None, early_s
     lib.kbisim_options_default(ctypes.byref(opt))
     opt.early_stop = 1 if early_stop else 0
     opt.profile = 1 if profile else 0
+    opt.history = 1 if history else 0
     if medium_cap is not None:
         opt.medium_cap = int(medium_cap)
     h = ctypes.c_void_p()
@@ -200,6 +217,71 @@ def kbisim_result(handle, pid_out=None, counts_cap=0):
     _check(lib.kbisim_result(handle, ptr, mem, ctypes.byref(nb),
                              counts.ctypes.data if counts_cap else None, int(counts_cap)))
     return int(nb.value), [int(c) for c in counts]
+
+
+def _out_ptr(pid_out):
+    if pid_out is None:
+        return KBISIM_MEM_HOST, None
+    if isinstance(pid_out, np.ndarray):
+        assert pid_out.dtype == np.int32 and pid_out.flags.c_contiguous
+        return KBISIM_MEM_HOST, (pid_out.ctypes.data if pid_out.size else None)
+    assert pid_out.dtype.__repr__().endswith("int32") and pid_out.is_contiguous()
+    return KBISIM_MEM_DEVICE, (pid_out.data_ptr() if pid_out.numel() else None)
+
+
+def kbisim_result_round(handle, round_, pid_out=None):
+    """Ids of round `round_` (change of k) into pid_out; returns B of that round."""
+    mem, ptr = _out_ptr(pid_out)
+    nb = ctypes.c_int64(0)
+    _check(load_library().kbisim_result_round(handle, int(round_), ptr, mem, ctypes.byref(nb)))
+    return int(nb.value)
+
+
+def kbisim_update(handle, *, new_labels=None, delete=None, add=None):
+    """Applies one update (see kbisim.h): new_labels (new nodes), delete and
+    add as (src, label, dst) triples of arrays; numpy (host) or torch CUDA
+    int32 tensors (device), all of one kind. Returns rounds done."""
+    parts = []
+    for a in ([new_labels] if new_labels is not None else []) + list(delete or ()) + list(add or ()):
+        parts.append(a)
+    is_dev = False
+    try:
+        import torch
+        is_dev = any(isinstance(a, torch.Tensor) for a in parts)
+    except ImportError:  # pragma: no cover
+        pass
+    keep = []
+
+    def arr(a):
+        if a is None:
+            return 0, None
+        if is_dev:
+            if str(a.dtype) != "torch.int32" or not a.is_cuda:
+                raise TypeError("device update arrays must be int32 CUDA tensors")
+            t = a.contiguous()
+            keep.append(t)
+            return int(t.numel()), (t.data_ptr() if t.numel() else None)
+        x = np.ascontiguousarray(np.asarray(a), dtype=np.int32)
+        keep.append(x)
+        return int(x.shape[0]), (x.ctypes.data if x.size else None)
+
+    n_new, p_new = arr(new_labels)
+    d = [arr(x) for x in (delete if delete is not None else (None, None, None))]
+    a = [arr(x) for x in (add if add is not None else (None, None, None))]
+    if len({x[0] for x in d}) > 1 or len({x[0] for x in a}) > 1:
+        raise KbisimError(-1, "edge arrays of different lengths")
+    desc = UpdateDesc(n_new, p_new, d[0][0], d[0][1], d[1][1], d[2][1], a[0][0], a[0][1], a[1][1], a[2][1],
+                      KBISIM_MEM_DEVICE if is_dev else KBISIM_MEM_HOST)
+    rd = ctypes.c_int32(0)
+    _check(load_library().kbisim_update(handle, ctypes.byref(desc), ctypes.byref(rd)))
+    return int(rd.value)
+
+
+def kbisim_update_stats(handle):
+    """(levels, rechecked, recomputed, changed) of the last update."""
+    v = [ctypes.c_int64(0) for _ in range(4)]
+    _check(load_library().kbisim_update_stats(handle, *[ctypes.byref(x) for x in v]))
+    return tuple(int(x.value) for x in v)
 
 
 def kbisim_profile(handle, reset=False):
@@ -268,6 +350,27 @@ class Graph:
         nb, counts = kbisim_result(self._h, out if self.num_nodes else None, cap)
         return out, nb, counts
 
+    def result_round(self, round_, device=None):
+        """Ids of an earlier round (history option) or the current one:
+        (ids, num_blocks)."""
+        if device is not None:
+            import torch
+            out = torch.empty(self.num_nodes, dtype=torch.int32, device=device)
+        else:
+            out = np.empty(self.num_nodes, np.int32)
+        nb = kbisim_result_round(self._h, round_, out)
+        return out, nb
+
+    def update(self, *, new_labels=None, delete=None, add=None):
+        """Applies an update (history option); returns rounds done."""
+        self.rounds_done = kbisim_update(self._h, new_labels=new_labels, delete=delete, add=add)
+        if new_labels is not None:
+            self.num_nodes += int(len(new_labels))
+        return self.rounds_done
+
+    def update_stats(self):
+        return kbisim_update_stats(self._h)
+
     def profile(self, reset=False):
         return kbisim_profile(self._h, reset)
 
@@ -303,12 +406,13 @@ def refine(num_nodes, node_label, src, elab, dst, k, **kw):
         return pid, counts, rd
 
 
-def _options(early_stop=True, profile=False, medium_cap=None):
+def _options(early_stop=True, profile=False, medium_cap=None, history=False):
     lib = load_library()
     opt = Options()
     lib.kbisim_options_default(ctypes.byref(opt))
     opt.early_stop = 1 if early_stop else 0
     opt.profile = 1 if profile else 0
+    opt.history = 1 if history else 0
     if medium_cap is not None:
         opt.medium_cap = int(medium_cap)
     return opt

@@ -24,6 +24,21 @@ struct DevBuf {
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), s(o.s) {
+    o.p = nullptr;
+    o.bytes = 0;
+  }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) {
+      release();
+      p = o.p;
+      bytes = o.bytes;
+      s = o.s;
+      o.p = nullptr;
+      o.bytes = 0;
+    }
+    return *this;
+  }
   ~DevBuf() { release(); }
   void release() {
     if (p) Pool::instance().put(p, bytes, s);
@@ -64,7 +79,28 @@ constexpr uint32_t kDefaultMediumCap = 4096;
 struct Options {
   bool early_stop = true;
   bool profile = false;
+  bool history = false;  // keep pId_0..pId_rounds and the maintenance state (reverse CSR, label values)
   uint32_t medium_cap = kDefaultMediumCap;  // groups above this size use the global passes
+};
+
+// One change to a graph handle's graph (the maintenance of Section 4): new
+// isolated nodes appended, then edge triples deleted (every copy), then
+// edge triples added. All arrays are device pointers.
+struct UpdateArgs {
+  int64_t n_new = 0;
+  const int32_t* new_label = nullptr;
+  int64_t m_del = 0;
+  const int32_t *del_src = nullptr, *del_lab = nullptr, *del_dst = nullptr;
+  int64_t m_add = 0;
+  const int32_t *add_src = nullptr, *add_lab = nullptr, *add_dst = nullptr;
+};
+
+// Work of the last update: per level, nodes whose signature was recomputed
+// (members of the classes that had to be re-ordered), nodes re-checked
+// (the frontier) and nodes found changed.
+struct UpdateStat {
+  int32_t levels = 0;
+  uint64_t recomputed = 0, rechecked = 0, changed = 0;
 };
 
 constexpr int kProfClasses = 4;  // signature launch, ordering, assignment, whole round
@@ -105,6 +141,16 @@ class Engine {
     StreamScope scope(st_);
     run_round();
   }
+  // Ids of an earlier round j <= rounds_done from the stored history (or
+  // the current round); dense, written to pid_out (host or device).
+  void result_round(int32_t j, int32_t* pid_out, bool to_device, int64_t* blocks);
+  // Applies an update (new nodes, deleted and added edges) and brings every
+  // stored round up to date, then continues to the round target when the
+  // fixed point moved. Needs the history option.
+  void update(const UpdateArgs& u);
+  const UpdateStat& update_stat() const { return ustat_; }
+  bool history() const { return opt_.history; }
+  int32_t round_target() const { return k_target_; }
   // Dense ids on the device (computed when the partition changed since the
   // last call) and the cumulative class counts: cls[p] = number of classes
   // starting at positions <= p of ord.
@@ -142,9 +188,10 @@ class Engine {
   void build_adj(const int32_t* src, const int32_t* lab, const int32_t* dst, const uint32_t* erank,
                  const uint32_t* rank_table, uint32_t* hist0);
   uint32_t label_ranks(const int32_t* val, uint64_t n, uint32_t maxv, const unsigned long long* mask_dev,
-                       const uint64_t* mask_host, DevBuf& rank_table, DevBuf& rank);
+                       const uint64_t* mask_host, DevBuf& rank_table, DevBuf& rank,
+                       std::vector<int32_t>* values = nullptr);
   template <typename AdjT, typename KeyT>
-  void round_impl();
+  void round_impl(bool first);
   template <typename AdjT, typename KeyT, typename CompT>
   void hub_sort(const void* sig_args, const uint32_t* hl, uint32_t nh, int key_bits);
   template <typename KeyT>
@@ -156,6 +203,18 @@ class Engine {
   void make_lists(const uint32_t* seg_start, const uint32_t* seg_size, const uint32_t* seg_depth,
                   const uint8_t* seg_done, uint32_t nseg, SegLists& out, const uint32_t* nseg_dev = nullptr);
   void assign_round();
+  void assign_ids();  // ids of the active positions after ordering (first part of assign_round)
+  // maintenance
+  void save_level(int32_t j);
+  void load_level(int32_t j);
+  void build_reverse();
+  template <typename AdjT>
+  void update_graph(const UpdateArgs& u, uint32_t n_new_total, std::vector<uint32_t>& src_list_host);
+  template <typename AdjT, typename KeyT>
+  void update_levels();
+  void rebuild_active();
+  void grow_nodes(uint64_t n_new);
+  void graph_stats();
   // mark: set actr[node] = tag for the active nodes (else already done)
   void prepare_active(uint32_t seg_items, uint32_t m_cap, uint32_t tag, bool mark);
   void run_round();
@@ -174,6 +233,26 @@ class Engine {
   hipStream_t st_;
   Options opt_;
   HostWords hw_;
+  uint32_t tag_ = 1;       // marks the active nodes of the coming round in actr_
+  int32_t k_target_ = 0;   // largest k asked of refine
+
+  // history (options.history): per round j, ord and class-start position
+  // ids of that round's partition
+  struct Level {
+    DevBuf ord, pid;
+  };
+  std::vector<Level> hist_;
+  // maintenance state: reverse CSR (edges by target, words (label rank <<
+  // dst_bits) | source), sorted distinct label values, update scratch
+  DevBuf rrowptr_, radj_;
+  std::vector<int32_t> nlab_vals_, elab_vals_;
+  DevBuf d_nvals_, d_evals_;
+  DevBuf rtag_, ctag_, dtag_, cont_;
+  uint32_t utag_ = 0;
+  DevBuf src_list_, rlist_, clist_, dlist_, dsize_, ufirst_, keep_, kscan_, old_prev_pid_, old_ord_, old_pid_;
+  uint32_t n_src_ = 0;       // sources of changed edges and new nodes, checked at every level
+  uint32_t old_n_nodes_ = 0;  // nodes before the update in progress
+  UpdateStat ustat_;
 
   bool adj64_ = false, key64_ = false;
   int dst_bits_ = 1, lab_bits_ = 0;

@@ -18,6 +18,7 @@
 #include "build.h"
 #include "common.h"
 #include "engine.h"
+#include "maintain.h"
 #include "refine.h"
 #include "scan_radix.h"
 #include "server.h"
@@ -200,7 +201,9 @@ void Engine::build_adj(const int32_t* src, const int32_t* lab, const int32_t* ds
 // element). Returns the number of distinct values. Exactly one of the two
 // outputs is filled.
 uint32_t Engine::label_ranks(const int32_t* val, uint64_t n, uint32_t maxv, const unsigned long long* mask_dev,
-                             const uint64_t* mask_host, DevBuf& rank_table, DevBuf& rank) {
+                             const uint64_t* mask_host, DevBuf& rank_table, DevBuf& rank,
+                             std::vector<int32_t>* values) {
+  if (values) values->clear();
   if (n == 0) return 0;
   if (maxv < kMaskLabels) {
     // all values are in the presence mask the validation pass collected
@@ -210,6 +213,9 @@ uint32_t Engine::label_ranks(const int32_t* val, uint64_t n, uint32_t maxv, cons
     KB_LAUNCH_CHECK();
     uint32_t d = 0;
     for (int q = 0; q < 4; ++q) d += uint32_t(__builtin_popcountll(mask_host[q]));
+    if (values)
+      for (uint32_t v = 0; v < kMaskLabels; ++v)
+        if ((mask_host[v / 64] >> (v % 64)) & 1ull) values->push_back(int32_t(v));
     return d;
   }
   if (maxv < kRankTableMax) {
@@ -222,6 +228,13 @@ uint32_t Engine::label_ranks(const int32_t* val, uint64_t n, uint32_t maxv, cons
     KB_LAUNCH_CHECK();
     scan_dev<uint32_t, uint32_t, false>(present.as<uint32_t>(), rank_table.as<uint32_t>(), t);
     const uint32_t d = uint32_t(read_word(rank_table.as<uint32_t>() + (t - 1), 4));
+    if (values) {  // value v is present where the exclusive scan steps
+      std::vector<uint32_t> tab(t);
+      KB_CHECK(hipMemcpyAsync(tab.data(), rank_table.p, uint64_t(t) * 4, hipMemcpyDeviceToHost, st_));
+      KB_CHECK(hipStreamSynchronize(st_));
+      for (uint32_t v = 0; v + 1 < t; ++v)
+        if (tab[v + 1] != tab[v]) values->push_back(int32_t(v));
+    }
     return d;  // synchronised: `present` may be freed
   }
   DevBuf ka, kb2, va, vb;
@@ -240,7 +253,17 @@ uint32_t Engine::label_ranks(const int32_t* val, uint64_t n, uint32_t maxv, cons
   rank.ensure(n * 4);
   rank_scatter_k<<<grid_for(n), kNT, 0, st_>>>(vals, cl, uint32_t(n), rank.as<uint32_t>());
   KB_LAUNCH_CHECK();
-  return uint32_t(read_word(cl + (n - 1), 4));
+  const uint32_t d = uint32_t(read_word(cl + (n - 1), 4));
+  if (values && d) {
+    DevBuf dv;
+    dv.ensure(uint64_t(d) * 4);
+    distinct_values_k<<<grid_for(n), kNT, 0, st_>>>(keys, fl, cl, uint32_t(n), dv.as<int32_t>());
+    KB_LAUNCH_CHECK();
+    values->resize(d);
+    KB_CHECK(hipMemcpyAsync(values->data(), dv.p, uint64_t(d) * 4, hipMemcpyDeviceToHost, st_));
+    KB_CHECK(hipStreamSynchronize(st_));
+  }
+  return d;
 }
 
 void Engine::build(const int32_t* node_label, const int32_t* src, const int32_t* lab, const int32_t* dst) {
@@ -297,7 +320,8 @@ void Engine::build(const int32_t* node_label, const int32_t* src, const int32_t*
   pid0_bytes_ = 4;
   if (N) {
     DevBuf table, rank, ka, kb2, va, vb;
-    const uint32_t nl = label_ranks(node_label, N, max_nlab, masks, mask_host, table, rank);
+    const uint32_t nl = label_ranks(node_label, N, max_nlab, masks, mask_host, table, rank,
+                                    opt_.history ? &nlab_vals_ : nullptr);
     pid0_bytes_ = nl <= 256 ? 1 : nl <= 65536 ? 2 : 4;
     pid0_.ensure(N * pid0_bytes_);
     for (DevBuf* b : {&ka, &kb2, &va, &vb}) b->ensure(N * 4);
@@ -361,7 +385,8 @@ void Engine::build(const int32_t* node_label, const int32_t* src, const int32_t*
 
   // edge labels: dense ascending ranks
   DevBuf etable, erank;
-  n_elab_ = label_ranks(lab, E, max_elab, masks + 4, mask_host + 4, etable, erank);
+  n_elab_ = label_ranks(lab, E, max_elab, masks + 4, mask_host + 4, etable, erank,
+                        opt_.history ? &elab_vals_ : nullptr);
   lab_bits_ = n_elab_ > 1 ? bits_for(n_elab_ - 1) : 0;
   dst_bits_ = bits_for(N > 1 ? N - 1 : 1);
   adj64_ = dst_bits_ + lab_bits_ > 32;
@@ -391,6 +416,11 @@ void Engine::build(const int32_t* node_label, const int32_t* src, const int32_t*
     large_offsets(act_, info_.as<uint32_t>() + kInfoSeg, info_.as<uint32_t>() + kInfoLargeItems, N);
     prepare_active(uint32_t(B_), uint32_t(N), 1u, false);  // active marks written above
   }
+  if (opt_.history) {
+    hist_.clear();
+    save_level(0);
+    build_reverse();
+  }
   KB_CHECK(hipStreamSynchronize(st_));
 }
 
@@ -408,6 +438,7 @@ uint32_t* Engine::compact_scratch(uint64_t words) {
 // seg_items), m_cap the number of active positions, tag the number of the
 // round being prepared (1 for the first), which marks its nodes in actr_.
 void Engine::prepare_active(uint32_t seg_items, uint32_t m_cap, uint32_t tag, bool mark) {
+  tag_ = tag;
   uint32_t* info = info_.as<uint32_t>();
   scan_dev<uint32_t, uint32_t, false>(act_.size.as<uint32_t>(), soff_.as<uint32_t>(), uint64_t(seg_items) + 1);
   expand_k<<<std::max<uint32_t>(1, ceil_div(m_cap, kExpandTile)), 256, 0, st_>>>(act_.start.as<uint32_t>(), soff_.as<uint32_t>(),
@@ -454,7 +485,7 @@ void Engine::prepare_active(uint32_t seg_items, uint32_t m_cap, uint32_t tag, bo
 // Ids for the active positions after ordering: every class of the round gets
 // the position of its first member as id; classes with two or more members
 // become the next round's segments. Returns with the next active set ready.
-void Engine::assign_round() {
+void Engine::assign_ids() {
   const uint32_t M = M_act_;
   uint32_t* info = info_.as<uint32_t>();
   act_flags_k<<<grid_for(M), kNT, 0, st_>>>(apos_.as<uint32_t>(), flag_.as<uint8_t>(), M, fl_.as<uint32_t>());
@@ -467,6 +498,12 @@ void Engine::assign_round() {
   assign_pos_k<<<grid_for(M), kNT, 0, st_>>>(apos_.as<uint32_t>(), cls_.as<uint32_t>(), first_.as<uint32_t>(),
                                              ord_.as<uint32_t>(), M, pid_.as<int32_t>());
   KB_LAUNCH_CHECK();
+}
+
+void Engine::assign_round() {
+  const uint32_t M = M_act_;
+  uint32_t* info = info_.as<uint32_t>();
+  assign_ids();
   const uint32_t med = std::min(medium_cap(), kMediumCapSmall), big = medium_cap();
   KB_CHECK(hipMemsetAsync(act_.size.p, 0, (uint64_t(M) + 1) * 4, st_));
   NextSegOf of{first_.as<uint32_t>(), info + kInfoClasses, M, med, big, apos_.as<uint32_t>(), ord_.as<uint32_t>(),
@@ -476,7 +513,7 @@ void Engine::assign_round() {
                        M, info + kInfoClasses, compact_scratch(compact_part_words<kSegClasses>(M)),
                        info + kInfoSeg, st_);
   large_offsets(act_, info + kInfoSeg, info + kInfoLargeItems, M);
-  prepare_active(M, M, uint32_t(rounds_) + 2, true);  // runs inside round rounds_ + 1
+  prepare_active(M, M, tag_ + 1, true);  // runs inside round rounds_ + 1
 }
 
 // ---------------------------------------------------------------------------
@@ -735,11 +772,10 @@ void Engine::hub_sort(const void* sig_args, const uint32_t* hl, uint32_t nh, int
 }
 
 template <typename AdjT, typename KeyT>
-void Engine::round_impl() {
+void Engine::round_impl(bool first) {
   const uint32_t N = uint32_t(n_);
   // round 1 keys use the dense pId_0 (narrow when there are few labels);
-  // later rounds use class-start positions
-  const bool first = rounds_ == 0;
+  // later rounds (and the rounds of an update) use class-start positions
   const uint64_t id_max = first ? (b0_ > 1 ? b0_ - 1 : 1) : (N > 1 ? N - 1 : 1);
   const int pid_bits = bits_for(id_max);
   const int key_bits = lab_bits_ + pid_bits;
@@ -770,7 +806,7 @@ void Engine::round_impl() {
   w.anode = anode_.as<uint32_t>();
   w.nact = M_act_;
   w.actr = actr_.as<uint32_t>();
-  w.tag = uint32_t(rounds_) + 1;
+  w.tag = tag_;
   w.n_nodes = N;
   w.dense = act_dense_;
   w.wl = lists + boff_[kBucketWave];
@@ -858,10 +894,11 @@ void Engine::run_round() {
   const int64_t B_old = B_;
   const int evr = ev_begin(3);
   if (M_act_ > 0) {
+    const bool first = rounds_ == 0;
     if (adj64_) {
-      if (key64_) round_impl<uint64_t, uint64_t>(); else round_impl<uint64_t, uint32_t>();
+      if (key64_) round_impl<uint64_t, uint64_t>(first); else round_impl<uint64_t, uint32_t>(first);
     } else {
-      if (key64_) round_impl<uint32_t, uint64_t>(); else round_impl<uint32_t, uint32_t>();
+      if (key64_) round_impl<uint32_t, uint64_t>(first); else round_impl<uint32_t, uint32_t>(first);
     }
     const uint32_t S_old = S_act_;
     const int eva = ev_begin(2);
@@ -874,6 +911,7 @@ void Engine::run_round() {
   ++rounds_;
   counts_.push_back(B_);
   fixed_ = (B_ == B_old);
+  if (opt_.history) save_level(rounds_);
   ev_collect();
 }
 
@@ -919,6 +957,7 @@ void Engine::reset_round_stats() {
 
 void Engine::refine(int32_t k) {
   StreamScope scope(st_);
+  k_target_ = std::max(k_target_, k);
   while (rounds_ < k) {
     if (fixed_ && opt_.early_stop) break;
     run_round();
@@ -957,6 +996,8 @@ void Engine::result(int32_t* pid_out, bool to_device) {
   KB_CHECK(hipStreamSynchronize(st_));
 }
 
+
+#include "maintain_engine.h"
 
 // ---------------------------------------------------------------------------
 // Batched form.
@@ -1457,6 +1498,7 @@ void kbisim_options_default(kbisim_options* opt) {
   opt->early_stop = 1;
   opt->profile = 0;
   opt->medium_cap = int32_t(kb::kDefaultMediumCap);
+  opt->history = 0;
 }
 
 static kbisim_status parse_options(const kbisim_options* opt, kb::Options* o) {
@@ -1466,6 +1508,7 @@ static kbisim_status parse_options(const kbisim_options* opt, kb::Options* o) {
   if (opt->medium_cap < 0 || opt->medium_cap > int32_t(kb::kBigCap))
     return fail(KBISIM_EINVAL, "medium_cap outside [0, 4096]");
   if (opt->medium_cap > 0) o->medium_cap = uint32_t(opt->medium_cap);
+  o->history = opt->history != 0;
   return KBISIM_OK;
 }
 
@@ -1538,6 +1581,85 @@ kbisim_status kbisim_result(const kbisim_graph* g, int32_t* pid_out, kbisim_mem 
     }
     return KBISIM_OK;
   });
+}
+
+kbisim_status kbisim_result_round(const kbisim_graph* g, int32_t round, int32_t* pid_out, kbisim_mem mem,
+                                  int64_t* num_blocks) {
+  if (!g || !g->eng) return fail(KBISIM_EINVAL, "null handle");
+  if (mem != KBISIM_MEM_HOST && mem != KBISIM_MEM_DEVICE) return fail(KBISIM_EINVAL, "bad mem kind");
+  if (round < 0) return fail(KBISIM_EINVAL, "round < 0");
+  return guarded([&]() {
+    int64_t b = 0;
+    g->eng->result_round(round, pid_out, mem == KBISIM_MEM_DEVICE, &b);
+    if (num_blocks) *num_blocks = b;
+    return KBISIM_OK;
+  });
+}
+
+kbisim_status kbisim_update(kbisim_graph* g, const kbisim_update_desc* u, int32_t* rounds_done) {
+  if (!g || !g->eng || !u) return fail(KBISIM_EINVAL, "null argument");
+  if (u->num_new_nodes < 0 || u->num_del_edges < 0 || u->num_add_edges < 0)
+    return fail(KBISIM_EINVAL, "negative size");
+  if (u->num_new_nodes > 0 && !u->new_node_label) return fail(KBISIM_EINVAL, "null new_node_label");
+  if (u->num_del_edges > 0 && (!u->del_src || !u->del_label || !u->del_dst))
+    return fail(KBISIM_EINVAL, "null deleted edge array");
+  if (u->num_add_edges > 0 && (!u->add_src || !u->add_label || !u->add_dst))
+    return fail(KBISIM_EINVAL, "null added edge array");
+  if (u->mem != KBISIM_MEM_HOST && u->mem != KBISIM_MEM_DEVICE) return fail(KBISIM_EINVAL, "bad mem kind");
+  if (u->num_new_nodes >= (int64_t(1) << 31) || u->num_add_edges >= int64_t(0xffffffffll) ||
+      u->num_del_edges >= int64_t(0xffffffffll))
+    return fail(KBISIM_EINVAL, "update too large");
+  if (!g->eng->history()) return fail(KBISIM_ESTATE, "updates need options.history = 1");
+  return guarded([&]() {
+    kb::StreamScope scope(g->eng->stream());
+    kb::UpdateArgs a;
+    a.n_new = u->num_new_nodes;
+    a.m_del = u->num_del_edges;
+    a.m_add = u->num_add_edges;
+    kb::DevBuf b[7];
+    if (u->mem == KBISIM_MEM_HOST) {
+      const int32_t* src[7] = {u->new_node_label, u->del_src, u->del_label, u->del_dst,
+                               u->add_src, u->add_label, u->add_dst};
+      const uint64_t len[7] = {uint64_t(a.n_new), uint64_t(a.m_del), uint64_t(a.m_del), uint64_t(a.m_del),
+                               uint64_t(a.m_add), uint64_t(a.m_add), uint64_t(a.m_add)};
+      const int32_t* dev[7];
+      for (int i = 0; i < 7; ++i) {
+        b[i].ensure(std::max<uint64_t>(len[i], 1) * 4);
+        if (len[i])
+          KB_CHECK(hipMemcpyAsync(b[i].p, src[i], len[i] * 4, hipMemcpyHostToDevice, g->eng->stream()));
+        dev[i] = b[i].as<int32_t>();
+      }
+      a.new_label = dev[0];
+      a.del_src = dev[1];
+      a.del_lab = dev[2];
+      a.del_dst = dev[3];
+      a.add_src = dev[4];
+      a.add_lab = dev[5];
+      a.add_dst = dev[6];
+    } else {
+      a.new_label = u->new_node_label;
+      a.del_src = u->del_src;
+      a.del_lab = u->del_label;
+      a.del_dst = u->del_dst;
+      a.add_src = u->add_src;
+      a.add_lab = u->add_label;
+      a.add_dst = u->add_dst;
+    }
+    g->eng->update(a);
+    if (rounds_done) *rounds_done = g->eng->rounds_done();
+    return KBISIM_OK;
+  });
+}
+
+kbisim_status kbisim_update_stats(const kbisim_graph* g, int64_t* levels, int64_t* rechecked, int64_t* recomputed,
+                                  int64_t* changed) {
+  if (!g || !g->eng) return fail(KBISIM_EINVAL, "null handle");
+  const kb::UpdateStat& s = g->eng->update_stat();
+  if (levels) *levels = s.levels;
+  if (rechecked) *rechecked = int64_t(s.rechecked);
+  if (recomputed) *recomputed = int64_t(s.recomputed);
+  if (changed) *changed = int64_t(s.changed);
+  return KBISIM_OK;
 }
 
 kbisim_status kbisim_profile(const kbisim_graph* g, double* ms, int64_t* launches, int32_t cap,

@@ -1,0 +1,512 @@
+// Kernels of the maintenance of a k-bisimulation partition (Section 4 of the
+// paper: change of k, Add_Nodes, Add_Edges and deletions) on a handle that
+// keeps the history of every round.
+//
+// The paper keeps pId_0..pId_k per node (Table 3), the edge table sorted by
+// source and by target (E_st, E_ts) and the signature store S, and pushes
+// changes level by level through a priority queue (Algorithm 3). Here a
+// round's partition is stored as its node order `ord` (classes contiguous,
+// in canonical order) and class-start position ids; E_st and E_ts are two
+// CSR tables; the queue becomes one device frontier per level: the sources
+// of changed edges, the nodes whose class changed at the level below, and
+// their sources through the reverse table. Classes of the level below that
+// hold no frontier node keep their split of the old history (copied with a
+// scan over the old order); the others are re-ordered by signature with the
+// round kernels.
+#pragma once
+
+#include "common.h"
+#include "scan_radix.h"
+
+namespace kb {
+
+constexpr uint32_t kNoneU32 = 0xffffffffu;
+
+// flag[p] = 1 at the first position of every class of a stored round:
+// the class-start position id of the node at p is p itself.
+__global__ void flags_from_level_k(const uint32_t* __restrict__ ord, const int32_t* __restrict__ pid, uint32_t n,
+                                   uint8_t* __restrict__ flag) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) flag[p] = uint32_t(pid[ord[p]]) == p ? 1 : 0;
+}
+
+// Rank of value v among the sorted distinct values vals[0..nv), or kNoneU32.
+__device__ __forceinline__ uint32_t value_rank(const int32_t* vals, uint32_t nv, int32_t v) {
+  uint32_t lo = 0, hi = nv;
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (vals[mid] < v)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return (lo < nv && vals[lo] == v) ? lo : kNoneU32;
+}
+
+// Edges of an update: validation and packing into the words of both tables.
+// Forward: key = src, word = (label rank << bits) | dst; reverse: key = dst,
+// word = (label rank << bits) | src. err bits: 1 an endpoint outside [0, n),
+// 2 a negative label, 4 a label value not among vals. keep[e] = 1 for an
+// edge with neither.
+template <typename W>
+__global__ void pack_update_k(const int32_t* __restrict__ src, const int32_t* __restrict__ lab,
+                              const int32_t* __restrict__ dst, uint32_t m, uint32_t n,
+                              const int32_t* __restrict__ vals, uint32_t nv, int bits,
+                              uint32_t* __restrict__ fkey, W* __restrict__ fword, uint32_t* __restrict__ rkey,
+                              W* __restrict__ rword, uint32_t* __restrict__ keep, uint32_t* __restrict__ err) {
+  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m) return;
+  const int32_t s = src[e], l = lab[e], t = dst[e];
+  uint32_t bad = 0;
+  if (s < 0 || uint32_t(s) >= n || t < 0 || uint32_t(t) >= n) bad |= 1u;
+  if (l < 0) bad |= 2u;
+  const uint32_t r = bad ? kNoneU32 : value_rank(vals, nv, l);
+  if (!bad && r == kNoneU32) bad |= 4u;
+  if (bad) atomicOr(err, bad);
+  keep[e] = bad ? 0u : 1u;
+  fkey[e] = bad ? 0u : uint32_t(s);
+  rkey[e] = bad ? 0u : uint32_t(t);
+  fword[e] = bad ? W(0) : (W(r) << bits) | W(uint32_t(t));
+  rword[e] = bad ? W(0) : (W(r) << bits) | W(uint32_t(s));
+}
+
+// Node labels of new nodes: err bit 2 for a negative label, 4 for a value
+// not among vals; rank[i] otherwise.
+__global__ void rank_new_nodes_k(const int32_t* __restrict__ lab, uint32_t m, const int32_t* __restrict__ vals,
+                                 uint32_t nv, uint32_t* __restrict__ rank, uint32_t* __restrict__ err) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const int32_t l = lab[i];
+  uint32_t bad = l < 0 ? 2u : 0u;
+  const uint32_t r = bad ? kNoneU32 : value_rank(vals, nv, l);
+  if (!bad && r == kNoneU32) bad |= 4u;
+  if (bad) atomicOr(err, bad);
+  rank[i] = r;
+}
+
+// Old table words in the new encoding: label rank through lmap (or kept),
+// endpoint bits from bits_o to bits_n.
+template <typename Wo, typename Wn>
+struct Reencode {
+  const uint32_t* lmap;  // old rank -> new rank, or null
+  int bits_o, bits_n;
+  __device__ __forceinline__ Wn operator()(Wo w) const {
+    const Wo mask = (Wo(1) << bits_o) - 1;
+    const uint32_t end = uint32_t(w & mask);
+    uint32_t r = uint32_t(w >> bits_o);
+    if (lmap) r = lmap[r];
+    return (Wn(r) << bits_n) | Wn(end);
+  }
+};
+
+// Distinct values of a sorted key array: flags for a scan.
+__global__ void run_flags_k(const uint32_t* __restrict__ key, uint32_t m, uint32_t* __restrict__ fl) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) fl[i] = (i == 0 || key[i] != key[i - 1]) ? 1u : 0u;
+}
+__global__ void run_scatter_k(const uint32_t* __restrict__ key, const uint32_t* __restrict__ fl,
+                              const uint32_t* __restrict__ ex, uint32_t m, uint32_t* __restrict__ out,
+                              uint32_t* __restrict__ count) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  if (fl[i]) out[ex[i]] = key[i];
+  if (i == m - 1) *count = ex[i] + fl[i];
+}
+
+__device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* a, uint32_t lo, uint32_t hi, uint32_t v) {
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (a[mid] < v)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+__device__ __forceinline__ uint32_t upper_bound_u32(const uint32_t* a, uint32_t lo, uint32_t hi, uint32_t v) {
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (a[mid] <= v)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+// Whether v occurs in the sorted range a[lo, hi).
+template <typename W>
+__device__ __forceinline__ bool contains_sorted(const W* a, uint32_t lo, uint32_t hi, W v) {
+  uint32_t l = lo, h = hi;
+  while (l < h) {
+    const uint32_t mid = (l + h) >> 1;
+    if (a[mid] < v)
+      l = mid + 1;
+    else
+      h = mid;
+  }
+  return l < hi && a[l] == v;
+}
+
+// Rows touched by an update (sorted distinct row ids R[0..r)): their ranges
+// in the sorted added (a_row) and deleted (d_row) lists, old degree, and the
+// old row range (begs/ends, E_o for rows of new nodes).
+struct MergeRows {
+  const uint32_t* R;
+  const uint32_t* count;  // r on the device
+  uint32_t *a_lo, *a_hi, *d_lo, *d_hi, *begs, *ends;
+};
+__global__ void merge_rows_k(MergeRows mr, const uint32_t* __restrict__ a_row, uint32_t m_a,
+                             const uint32_t* __restrict__ d_row, uint32_t m_d, const uint32_t* __restrict__ rp_o,
+                             uint32_t n_o) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= *mr.count) return;
+  const uint32_t row = mr.R[i];
+  mr.a_lo[i] = lower_bound_u32(a_row, 0, m_a, row);
+  mr.a_hi[i] = upper_bound_u32(a_row, 0, m_a, row);
+  mr.d_lo[i] = lower_bound_u32(d_row, 0, m_d, row);
+  mr.d_hi[i] = upper_bound_u32(d_row, 0, m_d, row);
+  const uint32_t e_o = rp_o[n_o];
+  mr.begs[i] = row < n_o ? rp_o[row] : e_o;
+  mr.ends[i] = row < n_o ? rp_o[row + 1] : e_o;
+}
+
+// One wave per touched row: old edges that survive the deletions, new
+// degree and the change of degree.
+template <typename Wo, typename Wn>
+__global__ __launch_bounds__(256) void merge_count_k(MergeRows mr, const Wo* __restrict__ adj_o,
+                                                     const Wn* __restrict__ d_word, Reencode<Wo, Wn> re,
+                                                     uint32_t* __restrict__ newdeg,
+                                                     unsigned long long* __restrict__ delta) {
+  const uint32_t r = *mr.count;
+  const uint32_t lane = __lane_id();
+  for (uint32_t i = (blockIdx.x * blockDim.x + threadIdx.x) / kWave; i < r;
+       i += (gridDim.x * blockDim.x) / kWave) {
+    const uint32_t b = mr.begs[i], e = mr.ends[i], dl = mr.d_lo[i], dh = mr.d_hi[i];
+    uint32_t kept = 0;
+    for (uint32_t x = b + lane; x < e; x += kWave) {
+      const Wn w = re(adj_o[x]);
+      kept += contains_sorted(d_word, dl, dh, w) ? 0u : 1u;
+    }
+    kept = wave_sum(kept);
+    if (lane == 0) {
+      const uint32_t nd = kept + (mr.a_hi[i] - mr.a_lo[i]);
+      newdeg[i] = nd;
+      delta[i] = (unsigned long long)(int64_t(nd) - int64_t(e - b));
+    }
+  }
+}
+
+// Degrees of all rows of the new table (old degree, 0 for new nodes), then
+// the touched rows' new degrees.
+__global__ void old_degrees_k(const uint32_t* __restrict__ rp_o, uint32_t n_o, uint32_t n_n, uint32_t* __restrict__ deg) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s <= n_n) deg[s] = s < n_o ? rp_o[s + 1] - rp_o[s] : 0u;
+}
+__global__ void set_degrees_k(MergeRows mr, const uint32_t* __restrict__ newdeg, uint32_t* __restrict__ deg) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < *mr.count) deg[mr.R[i]] = newdeg[i];
+}
+
+// Edges of untouched rows move by the change of degree of the touched rows
+// before them: with ends[] non-decreasing, the touched rows before edge e
+// are those with ends <= e (t of them), and e lies in touched row t when
+// begs[t] <= e. One tile of kMergeTile edges per workgroup; the tile's range
+// of touched rows is found once.
+constexpr uint32_t kMergeTile = 4096;
+template <typename Wo, typename Wn>
+__global__ __launch_bounds__(256) void merge_copy_k(MergeRows mr, const uint32_t* __restrict__ r_old_dev,
+                                                    const unsigned long long* __restrict__ cum,
+                                                    const Wo* __restrict__ adj_o, uint64_t e_o,
+                                                    Reencode<Wo, Wn> re, Wn* __restrict__ adj_n) {
+  __shared__ uint32_t range[2];
+  const uint64_t t0 = uint64_t(blockIdx.x) * kMergeTile;
+  if (t0 >= e_o) return;
+  const uint64_t t1 = t0 + kMergeTile < e_o ? t0 + kMergeTile : e_o;
+  const uint32_t ro = *r_old_dev;
+  if (threadIdx.x == 0) {
+    range[0] = upper_bound_u32(mr.ends, 0, ro, uint32_t(t0));
+    range[1] = upper_bound_u32(mr.ends, 0, ro, uint32_t(t1 - 1));
+  }
+  __syncthreads();
+  const uint32_t lo = range[0], hi = range[1];
+  for (uint64_t e = t0 + threadIdx.x; e < t1; e += blockDim.x) {
+    const uint32_t i = lo == hi ? lo : upper_bound_u32(mr.ends, lo, hi, uint32_t(e));
+    if (i < ro && mr.begs[i] <= uint32_t(e)) continue;  // inside a touched row
+    adj_n[e + cum[i]] = re(adj_o[e]);
+  }
+}
+
+// One wave per touched row: surviving old edges in their order, then the
+// added ones.
+template <typename Wo, typename Wn>
+__global__ __launch_bounds__(256) void merge_rows_copy_k(MergeRows mr, const Wo* __restrict__ adj_o,
+                                                         const Wn* __restrict__ d_word,
+                                                         const Wn* __restrict__ a_word, Reencode<Wo, Wn> re,
+                                                         const uint32_t* __restrict__ rp_n, Wn* __restrict__ adj_n) {
+  const uint32_t r = *mr.count;
+  const uint32_t lane = __lane_id();
+  for (uint32_t i = (blockIdx.x * blockDim.x + threadIdx.x) / kWave; i < r;
+       i += (gridDim.x * blockDim.x) / kWave) {
+    const uint32_t b = mr.begs[i], e = mr.ends[i], dl = mr.d_lo[i], dh = mr.d_hi[i];
+    uint32_t base = rp_n[mr.R[i]];
+    for (uint32_t x0 = b; x0 < e; x0 += kWave) {
+      const uint32_t x = x0 + lane;
+      Wn w = 0;
+      bool keep = false;
+      if (x < e) {
+        w = re(adj_o[x]);
+        keep = !contains_sorted(d_word, dl, dh, w);
+      }
+      const uint64_t bal = __ballot(keep);
+      if (keep) adj_n[base + uint32_t(__popcll(bal & lanemask_lt()))] = w;
+      base += uint32_t(__popcll(bal));
+    }
+    const uint32_t al = mr.a_lo[i], ah = mr.a_hi[i];
+    for (uint32_t j = al + lane; j < ah; j += kWave) adj_n[base + (j - al)] = a_word[j];
+  }
+}
+
+// Reverse table items from the forward table: for every edge of row s with
+// word (r << bits) | t, key t and word (r << bits) | s. One tile of
+// kMergeTile edges per workgroup, rows found by binary search in rowptr.
+template <typename W>
+__global__ __launch_bounds__(256) void reverse_items_k(const uint32_t* __restrict__ rowptr, uint32_t n,
+                                                       const W* __restrict__ adj, uint64_t m, int bits,
+                                                       uint32_t* __restrict__ rkey, W* __restrict__ rword) {
+  __shared__ uint32_t range[2];
+  const uint64_t t0 = uint64_t(blockIdx.x) * kMergeTile;
+  if (t0 >= m) return;
+  const uint64_t t1 = t0 + kMergeTile < m ? t0 + kMergeTile : m;
+  if (threadIdx.x == 0) {  // rows containing the first and last edge
+    range[0] = upper_bound_u32(rowptr, 0, n + 1, uint32_t(t0)) - 1;
+    range[1] = upper_bound_u32(rowptr, 0, n + 1, uint32_t(t1 - 1)) - 1;
+  }
+  __syncthreads();
+  const uint32_t lo = range[0], hi = range[1];
+  const W mask = (W(1) << bits) - 1;
+  for (uint64_t e = t0 + threadIdx.x; e < t1; e += blockDim.x) {
+    const uint32_t s = lo == hi ? lo : upper_bound_u32(rowptr, lo, hi + 1, uint32_t(e)) - 1;
+    const W w = adj[e];
+    rkey[e] = uint32_t(w & mask);
+    rword[e] = ((w >> bits) << bits) | W(s);
+  }
+}
+
+// ---- level-wise propagation -------------------------------------------------
+
+// Marks node p for the frontier of this level (once per tag) and appends it.
+// Every lane of the wave calls it.
+__device__ __forceinline__ void frontier_mark(bool want, uint32_t p, uint32_t* __restrict__ rtag, uint32_t tag,
+                                              uint32_t* __restrict__ rlist, uint32_t* __restrict__ rcount) {
+  const bool fresh = want && atomicExch(&rtag[p], tag) != tag;
+  const uint32_t slot = wave_append(fresh, rcount);
+  if (fresh) rlist[slot] = p;
+}
+
+// Frontier of level j (Algorithm 3's queue at level j): every node of
+// `always` (sources of changed edges and new nodes, checked at every level),
+// and every node of `changed` (its class changed at level j - 1, so its own
+// head changed) with its sources through the reverse table. One wave per
+// listed node.
+template <typename W>
+__global__ __launch_bounds__(256) void frontier_k(const uint32_t* __restrict__ always, uint32_t n_always,
+                                                  const uint32_t* __restrict__ changed,
+                                                  const uint32_t* __restrict__ n_changed_dev,
+                                                  const uint32_t* __restrict__ rrowptr, const W* __restrict__ radj,
+                                                  int bits, uint32_t* __restrict__ rtag, uint32_t tag,
+                                                  uint32_t* __restrict__ rlist, uint32_t* __restrict__ rcount) {
+  const uint32_t n_changed = n_changed_dev ? *n_changed_dev : 0u;
+  const uint32_t total = n_always + n_changed;
+  const uint32_t lane = __lane_id();
+  const W mask = (W(1) << bits) - 1;
+  for (uint32_t i = (blockIdx.x * blockDim.x + threadIdx.x) / kWave; i < total;
+       i += (gridDim.x * blockDim.x) / kWave) {
+    const bool is_changed = i >= n_always;
+    const uint32_t u = is_changed ? changed[i - n_always] : always[i];
+    frontier_mark(lane == 0, u, rtag, tag, rlist, rcount);
+    if (!is_changed) continue;  // uniform over the wave
+    const uint32_t b = rrowptr[u], e = rrowptr[u + 1];
+    for (uint32_t x0 = b; x0 < e; x0 += kWave) {
+      const uint32_t x = x0 + lane;
+      const bool in = x < e;
+      frontier_mark(in, in ? uint32_t(radj[x] & mask) : 0u, rtag, tag, rlist, rcount);
+    }
+  }
+}
+
+// Classes of level j - 1 holding a frontier node (by class-start position).
+__global__ void dirty_classes_k(const uint32_t* __restrict__ rlist, const uint32_t* __restrict__ rcount,
+                                const int32_t* __restrict__ pid, uint32_t* __restrict__ dtag, uint32_t tag,
+                                uint32_t* __restrict__ dlist, uint32_t* __restrict__ dcount) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool in = i < *rcount;
+  const uint32_t c = in ? uint32_t(pid[rlist[i]]) : 0u;
+  const bool fresh = in && atomicExch(&dtag[c], tag) != tag;
+  const uint32_t slot = wave_append(fresh, dcount);
+  if (fresh) dlist[slot] = c;
+}
+
+// First position of every class (cls = inclusive scan of the class-start flags).
+__global__ void class_starts_k(const uint8_t* __restrict__ flag, const uint32_t* __restrict__ cls, uint32_t n,
+                               uint32_t* __restrict__ firstpos) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n && flag[p]) firstpos[cls[p] - 1] = p;
+}
+
+// Size of every listed class; members of those with two or more summed.
+__global__ void dirty_sizes_k(const uint32_t* __restrict__ dlist, const uint32_t* __restrict__ dcount,
+                              const uint32_t* __restrict__ cls, const uint32_t* __restrict__ firstpos, uint32_t n,
+                              uint32_t* __restrict__ dsize, uint32_t* __restrict__ members) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= *dcount) return;
+  const uint32_t c = dlist[i];
+  const uint32_t ci = cls[c] - 1, B = cls[n - 1];
+  const uint32_t next = ci + 1 < B ? firstpos[ci + 1] : n;
+  const uint32_t z = next - c;
+  dsize[i] = z;
+  if (z >= 2) atomicAdd(members, z);
+}
+
+// Old positions p of the stored round j whose node kept its class at level
+// j - 1 (not changed there): keep[p] = 1.
+__global__ void keep_flags_k(const uint32_t* __restrict__ old_ord, uint32_t n_o, const uint32_t* __restrict__ ctag,
+                             uint32_t tag_prev, uint32_t* __restrict__ keep) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n_o) keep[p] = ctag[old_ord[p]] != tag_prev ? 1u : 0u;
+}
+
+// Classes of level j - 1 without frontier nodes split as in the stored
+// round j: their members (exactly the kept members of one old class of
+// level j - 1, which starts at old_prev_pid[u] in the old order) keep their
+// old order, and the first kept member of each old class of level j starts
+// a class. ks = exclusive scan of keep over old positions.
+__global__ void copy_split_k(const uint32_t* __restrict__ old_ord, uint32_t n_o, const uint32_t* __restrict__ keep,
+                             const uint32_t* __restrict__ ks, const int32_t* __restrict__ old_prev_pid,
+                             const int32_t* __restrict__ old_pid, const uint32_t* __restrict__ dtag, uint32_t tag,
+                             uint32_t* __restrict__ ord, uint8_t* __restrict__ flag, int32_t* __restrict__ pid) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_o || !keep[p]) return;
+  const uint32_t u = old_ord[p];
+  const uint32_t c = uint32_t(pid[u]);
+  if (dtag[c] == tag) return;  // re-ordered by signature instead
+  const uint32_t base = ks[uint32_t(old_prev_pid[u])];
+  const uint32_t first = ks[uint32_t(old_pid[u])];
+  const uint32_t dest = c + (ks[p] - base);
+  ord[dest] = u;
+  flag[dest] = ks[p] == first ? 1 : 0;
+  pid[u] = int32_t(c + (first - base));
+}
+
+// Change detection in the re-ordered classes. A new class that holds a node
+// outside the frontier continues that node's old class (every such node of
+// one old class lands in one new class, and no two old classes share one);
+// cont[class start] = the old class (its old start position).
+__global__ void cont_reset_k(const uint32_t* __restrict__ apos, uint32_t m, uint32_t* __restrict__ cont) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) cont[apos[i]] = kNoneU32;
+}
+__global__ void cont_set_k(const uint32_t* __restrict__ apos, uint32_t m, const uint32_t* __restrict__ ord,
+                           const int32_t* __restrict__ pid, const uint32_t* __restrict__ rtag, uint32_t tag,
+                           uint32_t n_o, const int32_t* __restrict__ old_pid, uint32_t* __restrict__ cont) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const uint32_t u = ord[apos[i]];
+  if (rtag[u] == tag || u >= n_o) return;
+  cont[uint32_t(pid[u])] = uint32_t(old_pid[u]);
+}
+// A frontier node changed at level j unless it joined the continuation of
+// its own old class. Nodes of classes that were not re-ordered (alone at
+// level j - 1) and new nodes count as changed. Changed nodes are listed and
+// tagged for the next level.
+__global__ void changed_k(const uint32_t* __restrict__ rlist, const uint32_t* __restrict__ rcount,
+                          const uint32_t* __restrict__ actr, uint32_t act_tag, const int32_t* __restrict__ pid,
+                          const uint32_t* __restrict__ cont, uint32_t n_o, const int32_t* __restrict__ old_pid,
+                          uint32_t* __restrict__ ctag, uint32_t tag, uint32_t* __restrict__ clist,
+                          uint32_t* __restrict__ ccount) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  bool ch = false;
+  uint32_t u = 0;
+  if (i < *rcount) {
+    u = rlist[i];
+    ch = u >= n_o || actr[u] != act_tag || cont[uint32_t(pid[u])] != uint32_t(old_pid[u]);
+    if (ch) ctag[u] = tag;
+  }
+  const uint32_t slot = wave_append(ch, ccount);
+  if (ch) clist[slot] = u;
+}
+
+// Classes with two or more members whose members have out-edges (the
+// active segments of the coming round, from a full class scan).
+struct ClassSegOf {
+  const uint32_t* firstpos;
+  const uint32_t* nclass;
+  uint32_t n;
+  const uint32_t* ord;
+  const uint32_t* rowptr;
+  uint32_t medium_cap, big_cap;
+  bool skip_edgeless;  // members of a class of round >= 1 share their signature: all or none have edges
+  __device__ __forceinline__ uint32_t size(uint32_t c) const {
+    return (c + 1 < *nclass ? firstpos[c + 1] : n) - firstpos[c];
+  }
+  __device__ __forceinline__ int operator()(uint32_t c) const {
+    const uint32_t z = size(c);
+    if (z < 2) return -1;
+    const uint32_t u = ord[firstpos[c]];
+    if (skip_edgeless && rowptr[u + 1] == rowptr[u]) return -1;
+    return seg_class(z, medium_cap, big_cap);
+  }
+};
+struct ClassSegWrite {
+  ClassSegOf of;
+  uint32_t *o_start, *o_size, *o_depth;
+  __device__ __forceinline__ void operator()(uint32_t c, int, uint32_t o) const {
+    o_start[o] = of.firstpos[c];
+    o_size[o] = of.size(c);
+    o_depth[o] = 0;
+  }
+};
+
+// Re-ordered classes of level j - 1 (size >= 2) as segments.
+struct DirtySegOf {
+  const uint32_t* dlist;
+  const uint32_t* dsize;
+  uint32_t medium_cap, big_cap;
+  __device__ __forceinline__ int operator()(uint32_t i) const {
+    const uint32_t z = dsize[i];
+    return z >= 2 ? seg_class(z, medium_cap, big_cap) : -1;
+  }
+};
+struct DirtySegWrite {
+  const uint32_t* dlist;
+  const uint32_t* dsize;
+  uint32_t *o_start, *o_size, *o_depth;
+  __device__ __forceinline__ void operator()(uint32_t i, int, uint32_t o) const {
+    o_start[o] = dlist[i];
+    o_size[o] = dsize[i];
+    o_depth[o] = 0;
+  }
+};
+
+// Distinct values of a sorted array (run starts fl, cl = inclusive scan of fl).
+__global__ void distinct_values_k(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ fl,
+                                  const uint32_t* __restrict__ cl, uint32_t n, int32_t* __restrict__ vals) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && fl[i]) vals[cl[i] - 1] = int32_t(keys[i]);
+}
+
+// Level 0 after new nodes: every node's label rank (old nodes through the
+// map of old ranks to new ones), as sort items and in the narrow id type.
+template <typename Told, typename Tnew>
+__global__ void level0_ranks_k(const Told* __restrict__ old_rank, uint32_t n_o, const uint32_t* __restrict__ new_rank,
+                               uint32_t n_n, const uint32_t* __restrict__ rmap, uint32_t* __restrict__ key,
+                               uint32_t* __restrict__ idx, Tnew* __restrict__ narrow) {
+  const uint32_t u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= n_n) return;
+  uint32_t r = u < n_o ? uint32_t(old_rank[u]) : new_rank[u - n_o];
+  if (u < n_o && rmap) r = rmap[r];
+  key[u] = r;
+  idx[u] = u;
+  narrow[u] = Tnew(r);
+}
+
+}  // namespace kb

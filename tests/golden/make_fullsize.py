@@ -69,12 +69,20 @@ def main():
     print("oracle: rounds=%d counts=%s in %.1f s" % (r.rounds_done, r.counts, t_oracle), flush=True)
     sample = sample_of(g.num_nodes)
     rows = r.history[: r.rounds_done + 1]
+    # longest signature per round among nodes of classes with two or more
+    # members in the previous round (the nodes a round can still split)
+    multi = [1]
+    for j in range(1, r.rounds_done + 1):
+        lengths = oracle.signature_lengths(g.num_nodes, g.src, g.elab, g.dst, rows[j - 1])
+        multi.append(oracle.longest_multi_member(lengths, rows[j - 1]))
+        print("round %d: longest signature in a class of two or more: %d ints" % (j, multi[-1]), flush=True)
     out = {
         "source": "oracle/kbisim_oracle.cpp (Algorithm 1 with an ordered-dictionary S) on the seeded "
                   "synthetic workload; written by tests/golden/make_fullsize.py",
         "workload": args.workload, "seed": args.seed, "num_nodes": g.num_nodes, "num_edges": g.num_edges,
         "k": k, "early_stop": early_stop,
         "rounds_done": r.rounds_done, "counts": r.counts, "max_sig_ints": r.max_sig_ints,
+        "max_sig_ints_multi": multi,
         "digest": "sha256 of the int32 little-endian id array of each round, node order",
         "round_digests": [digest(rows[j]) for j in range(r.rounds_done + 1)],
         "sample_seed": SAMPLE_SEED, "sample_nodes": sample.tolist(),

@@ -1,11 +1,23 @@
-"""Parity at full size: the 10M-node / 100M-edge power-law graph that the
-bench times, with the bench's options, refined to the fixed point on the GPU.
-The whole oracle run is too slow for a test at this size, so every round is
-checked on sampled nodes against the oracle's signatures (computed from the
-GPU's previous-round ids, one sampled node at a time) and by properties that
-hold at any size: pId_0 is the label rank, ids are dense, every round refines
-the previous one with ids monotone in the previous ids, counts grow until the
-first repeated count, where the run stops."""
+"""Parity at full size.
+
+* The 10M-node / 100M-edge power-law graph that the bench times, refined to
+  the fixed point (cap 10) in the bench's launch configuration, compared
+  with the oracle's whole run element by element: the SHA-256 digest of
+  every round's id array (tests/golden/powerlaw-10M-100M.json, written by
+  tests/golden/make_fullsize.py from the oracle alone), the ids of a fixed
+  sample of nodes (to name a mismatch), the counts, the rounds done and the
+  longest signature per round among nodes of classes with two or more
+  members (the nodes a round can still split: the library computes only
+  their signatures).
+* The 100M-node / 1B-edge graph at k = 10 with early stop off (the paper ran
+  all ten rounds): too large for the whole oracle run, so every round is
+  checked on sampled nodes against the oracle's signatures built from the
+  previous round's ids, plus the properties that hold at any size. It takes
+  about ten minutes of host work and runs when KBISIM_FULL_1B=1.
+"""
+import hashlib
+import json
+import os
 import time
 
 import numpy as np
@@ -14,9 +26,61 @@ import pytest
 import oracle
 from oracle import checks
 import synth
-from gpu_util import gpu_rounds, need_gpu, say
+from gpu_util import need_gpu, say
 
 pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "powerlaw-10M-100M.json")
+
+
+def digest(ids):
+    return hashlib.sha256(np.ascontiguousarray(ids, dtype="<i4").tobytes()).hexdigest()
+
+
+def test_powerlaw_10M_100M_exact():
+    torch, kb = need_gpu()
+    with open(GOLDEN) as f:
+        want = json.load(f)
+    t0 = time.perf_counter()
+    g, k = synth.make_config("powerlaw-10M-100M", seed=want["seed"])
+    assert (g.num_nodes, g.num_edges, k) == (want["num_nodes"], want["num_edges"], want["k"])
+    say("generated N=%d E=%d in %.1f s" % (g.num_nodes, g.num_edges, time.perf_counter() - t0))
+    dev = torch.device("cuda:0")
+    arrs = [torch.from_numpy(a).to(dev) for a in (g.node_label, g.src, g.elab, g.dst)]
+    sample = np.asarray(want["sample_nodes"], np.int64)
+    rd_want = want["rounds_done"]
+
+    # the bench's launch configuration: create, refine(k), result to device
+    out = torch.empty(g.num_nodes, dtype=torch.int32, device=dev)
+    h = kb.kbisim_create(g.num_nodes, *arrs)
+    try:
+        rd = kb.kbisim_refine(h, k)
+        nb, counts = kb.kbisim_result(h, out, counts_cap=k + 1)
+    finally:
+        kb.kbisim_destroy(h)
+    last = out.cpu().numpy()
+    assert rd == rd_want and counts[: rd + 1] == want["counts"]
+    assert np.array_equal(last[sample], np.asarray(want["sample_ids"][rd_want], np.int32))
+    assert digest(last) == want["round_digests"][rd_want]
+    say("bench configuration: rounds=%d counts=%s, final ids match the oracle's digest" % (rd, counts[: rd + 1]))
+
+    # every round, read back from the stored history
+    with kb.Graph(g.num_nodes, *arrs, history=True) as hh:
+        hh.refine(k)
+        for j in range(rd_want + 1):
+            ids, nbj = hh.result_round(j)
+            assert nbj == want["counts"][j]
+            mism = np.flatnonzero(ids[sample] != np.asarray(want["sample_ids"][j], np.int32))
+            assert mism.size == 0, "round %d: sampled node %d differs" % (j, int(sample[mism[0]]))
+            assert digest(ids) == want["round_digests"][j], "round %d differs from the oracle" % j
+            say("round %d: all %d ids equal the oracle's" % (j, g.num_nodes))
+
+    # longest signature per round among the nodes a round can split
+    with kb.Graph(g.num_nodes, *arrs, profile=True) as hp:
+        hp.refine(k)
+        per_round = hp.round_profile()
+    got = [1] + [1 + 2 * int(x["max_keys"]) for x in per_round]
+    assert got == want["max_sig_ints_multi"], (got, want["max_sig_ints_multi"])
 
 
 def sample_nodes(rng, prev, n_random=1500, n_pairs=300):
@@ -30,26 +94,40 @@ def sample_nodes(rng, prev, n_random=1500, n_pairs=300):
     return np.unique(np.concatenate([picks, pairs])).astype(np.int32)
 
 
-def test_powerlaw_10M_100M_sampled():
+@pytest.mark.slow
+@pytest.mark.skipif(os.environ.get("KBISIM_FULL_1B") != "1", reason="about ten minutes; set KBISIM_FULL_1B=1")
+def test_powerlaw_100M_1B_k10_sampled():
     torch, kb = need_gpu()
     t0 = time.perf_counter()
-    g, k = synth.make_config("powerlaw-10M-100M")
-    say("generated %s N=%d E=%d in %.1f s" % (g.name, g.num_nodes, g.num_edges, time.perf_counter() - t0))
-    hist, counts, rd = gpu_rounds(torch, kb, g, k)
-    say("GPU: rounds=%d counts=%s" % (rd, counts[: rd + 1]))
+    g, _ = synth.make_config("powerlaw-100M-1B", progress=say)
+    k = 10
+    say("generated N=%d E=%d in %.1f s" % (g.num_nodes, g.num_edges, time.perf_counter() - t0))
+    dev = torch.device("cuda:0")
+    arrs = [torch.from_numpy(a).to(dev) for a in (g.node_label, g.src, g.elab, g.dst)]
     n = g.num_nodes
-    # stop rule: counts strictly increase until the first repeat, at round rd
-    c = counts[: rd + 1]
-    checks.check_counts(c, n)
-    assert rd >= 1 and c[rd] == c[rd - 1], "stopped before the fixed point"
-    assert all(c[i] < c[i + 1] for i in range(rd - 1)), "a repeated count did not stop the run"
-    checks.check_label_rank(g.node_label, hist[0])
-    rng = np.random.default_rng(2024)
-    for j in range(1, rd + 1):
-        prev, cur = hist[j - 1], hist[j]
-        checks.check_dense(cur, c[j])
-        checks.check_refines_monotone(prev, cur)
-        sample = sample_nodes(rng, prev)
-        sigs = oracle.signatures(n, g.src, g.elab, g.dst, prev, sample)
-        checks.check_lex_order(sigs, cur[sample].tolist())
-        say("round %d: %d blocks, %d sampled nodes agree with the oracle's signatures" % (j, c[j], sample.size))
+    rng = np.random.default_rng(2026)
+    with kb.Graph(n, *arrs, history=True, early_stop=False) as h:
+        rd = h.refine(k)
+        assert rd == k
+        _, _, counts = h.result()
+        say("GPU: rounds=%d counts=%s" % (rd, counts))
+        checks.check_counts(counts, n)
+        del arrs
+        prev, _ = h.result_round(0)
+        checks.check_label_rank(g.node_label, prev)
+        fixed = None
+        for j in range(1, k + 1):
+            cur, nb = h.result_round(j)
+            checks.check_dense(cur, counts[j])
+            checks.check_refines_monotone(prev, cur)
+            if counts[j] == counts[j - 1]:
+                fixed = j if fixed is None else fixed
+                assert np.array_equal(cur, prev), "round %d after the fixed point changed ids" % j
+            else:
+                assert fixed is None, "counts grew after a repeated count"
+                sample = sample_nodes(rng, prev)
+                sigs = oracle.signatures(n, g.src, g.elab, g.dst, prev, sample)
+                checks.check_lex_order(sigs, cur[sample].tolist())
+                say("round %d: %d blocks, %d sampled nodes agree with the oracle's signatures" %
+                    (j, counts[j], sample.size))
+            prev = cur
