@@ -103,6 +103,25 @@ kbisim_status kbisim_create(const kbisim_graph_desc* desc, const kbisim_options*
  * k < 0 is KBISIM_EINVAL. Synchronises the handle's stream. */
 kbisim_status kbisim_refine(kbisim_graph* g, int32_t k, int32_t* rounds_done);
 
+/* For callers that cannot allocate device memory (code that runs under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * kbisim_create + kbisim_refine(k) + kbisim_result + kbisim_destroy in one
+ * call that calls no hipMalloc, hipFree or allocating library routine. Every
+ * intermediate buffer is carved from a static device region of
+ * KBISIM_STATIC_SCRATCH_BYTES bytes (one per GPU, held until the process
+ * ends; it keeps the last call's contents, which no call relies on). Work
+ * runs on desc->stream only; the call returns after it has finished. Calls
+ * on one GPU are serialised by the library (they share the region).
+ * Inputs as for kbisim_create (host or device); pid_out[N] in out_mem;
+ * num_blocks and rounds_done may be NULL. Graphs whose estimated footprint
+ * (48 B per edge + 256 B per node + 1 MiB) exceeds the region are rejected
+ * with KBISIM_ENOMEM before any work; the region running out anyway is
+ * KBISIM_ENOMEM too. opt's profile and history fields are ignored. */
+#define KBISIM_STATIC_SCRATCH_BYTES (128u << 20)
+kbisim_status kbisim_refine_static(const kbisim_graph_desc* desc, int32_t k, const kbisim_options* opt,
+                                   int32_t* pid_out, kbisim_mem out_mem, int64_t* num_blocks,
+                                   int32_t* rounds_done);
+
 /* Writes the ids of the last computed round (pId_k) to pid_out[N] in host or
  * device memory (device: enqueued on the handle's stream, then synchronised),
  * *num_blocks = B of that round, and counts[0..min(counts_cap, rounds+1)) =

@@ -71,6 +71,9 @@ def load_library():
     lib.kbisim_refine.restype = ctypes.c_int
     lib.kbisim_result.argtypes = [vp, vp, ctypes.c_int, ctypes.POINTER(i64), vp, i32]
     lib.kbisim_result.restype = ctypes.c_int
+    lib.kbisim_refine_static.argtypes = [ctypes.POINTER(GraphDesc), i32, ctypes.POINTER(Options), vp, ctypes.c_int,
+                                         ctypes.POINTER(i64), ctypes.POINTER(i32)]
+    lib.kbisim_refine_static.restype = ctypes.c_int
     lib.kbisim_result_round.argtypes = [vp, i32, vp, ctypes.c_int, ctypes.POINTER(i64)]
     lib.kbisim_result_round.restype = ctypes.c_int
     lib.kbisim_update.argtypes = [vp, ctypes.POINTER(UpdateDesc), ctypes.POINTER(i32)]
@@ -275,6 +278,24 @@ def kbisim_update(handle, *, new_labels=None, delete=None, add=None):
     rd = ctypes.c_int32(0)
     _check(load_library().kbisim_update(handle, ctypes.byref(desc), ctypes.byref(rd)))
     return int(rd.value)
+
+
+def kbisim_refine_static(num_nodes, node_label, src, elab, dst, k, pid_out, *, stream=None, early_stop=True,
+                         medium_cap=None):
+    """The allocation-free one-shot refine (static scratch region): ids of
+    round k (or the fixed point) into pid_out (numpy or torch CUDA int32).
+    Returns (num_blocks, rounds_done)."""
+    lib = load_library()
+    mem, ptrs, keep = _arrays(node_label, src, elab, dst)
+    n, m = int(num_nodes), int(keep[1].shape[0])
+    desc = GraphDesc(n, m, ptrs[0] or None, ptrs[1] or None, ptrs[2] or None, ptrs[3] or None, mem,
+                     _stream_ptr(stream) if (mem == KBISIM_MEM_DEVICE or stream is not None) else None)
+    opt = _options(early_stop=early_stop, medium_cap=medium_cap)
+    out_mem, out_ptr = _out_ptr(pid_out)
+    nb, rd = ctypes.c_int64(0), ctypes.c_int32(0)
+    _check(lib.kbisim_refine_static(ctypes.byref(desc), int(k), ctypes.byref(opt), out_ptr, out_mem,
+                                    ctypes.byref(nb), ctypes.byref(rd)))
+    return int(nb.value), int(rd.value)
 
 
 def kbisim_update_stats(handle):

@@ -66,9 +66,18 @@ struct DevBuf {
 // process-wide pinned slab; the slot's owner is the only user).
 struct HostWords {
   uint64_t* p = nullptr;
-  HostWords() : p(PinnedSlots::instance().acquire()) {}
+  bool pinned = true;
+  HostWords() {
+    if (active_arena()) {  // allocation-free jobs read back into this thread's own words
+      static thread_local uint64_t words[2 * PinnedSlots::kSlotWords];
+      p = words;
+      pinned = false;
+    } else {
+      p = PinnedSlots::instance().acquire();
+    }
+  }
   ~HostWords() {
-    if (p) PinnedSlots::instance().release(p);
+    if (p && pinned) PinnedSlots::instance().release(p);
   }
   HostWords(const HostWords&) = delete;
   HostWords& operator=(const HostWords&) = delete;
@@ -297,6 +306,7 @@ class Engine {
   // each other: groups of one workgroup of 1024 threads on side_big_, all
   // smaller ones on side_
   hipStream_t side_ = nullptr, side_big_ = nullptr;
+  bool single_stream_ = false;  // all work on st_ (jobs inside a static scratch region)
   int side_dev_ = 0;  // device of the resolver streams
   hipEvent_t ev_side_[2] = {nullptr, nullptr}, ev_big_[2] = {nullptr, nullptr};
   hipEvent_t ev_main_ = nullptr, ev_join_ = nullptr, ev_join_big_ = nullptr;

@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -35,7 +36,8 @@ inline uint32_t grid_stride_blocks(uint64_t n) {
 }
 }  // namespace
 
-Engine::Engine(int64_t n, int64_t m, hipStream_t s, const Options& o) : n_(n), m_(m), st_(s), opt_(o) {}
+Engine::Engine(int64_t n, int64_t m, hipStream_t s, const Options& o)
+    : n_(n), m_(m), st_(s), opt_(o), single_stream_(active_arena() != nullptr) {}
 
 Engine::~Engine() {
   for (auto& e : ev_pool_) {
@@ -218,7 +220,7 @@ uint32_t Engine::label_ranks(const int32_t* val, uint64_t n, uint32_t maxv, cons
         if ((mask_host[v / 64] >> (v % 64)) & 1ull) values->push_back(int32_t(v));
     return d;
   }
-  if (maxv < kRankTableMax) {
+  if (maxv < kRankTableMax && !single_stream_) {  // (a table of maxv entries may not fit a static region)
     const uint64_t t = uint64_t(maxv) + 2;
     DevBuf present;
     present.ensure(t * 4);
@@ -597,11 +599,14 @@ void Engine::order_groups(const void* kvp) {
   // enough for one workgroup are resolved on the side stream while the main
   // stream runs the global passes over the large ones: they touch disjoint
   // ranges of ord and flag, and both only read the signatures.
-  hipStream_t side = side_stream();
-  hipStream_t big = side_big_;
-  KB_CHECK(hipEventRecord(ev_main_, st_));
-  KB_CHECK(hipStreamWaitEvent(side, ev_main_, 0));
-  KB_CHECK(hipStreamWaitEvent(big, ev_main_, 0));
+  const bool one = single_stream_;  // everything in stream order on st_, no events
+  hipStream_t side = one ? st_ : side_stream();
+  hipStream_t big = one ? st_ : side_big_;
+  if (!one) {
+    KB_CHECK(hipEventRecord(ev_main_, st_));
+    KB_CHECK(hipStreamWaitEvent(side, ev_main_, 0));
+    KB_CHECK(hipStreamWaitEvent(big, ev_main_, 0));
+  }
   resolve_lists<KeyT>(act_, kvp, side, big);
   bool side_pending[2] = {false, false};
 
@@ -714,18 +719,22 @@ void Engine::order_groups(const void* kvp) {
     // last read by the resolvers of two passes ago (side stream) and by the
     // global pass before this one (this stream)
     SegLists& out = lists_b_[nx];
-    if (side_pending[nx]) {
+    if (side_pending[nx] && !one) {
       KB_CHECK(hipStreamWaitEvent(st_, ev_side_[nx], 0));
       KB_CHECK(hipStreamWaitEvent(st_, ev_big_[nx], 0));
     }
     make_lists(seg_start_.as<uint32_t>(), seg_size_.as<uint32_t>(), seg_depth_.as<uint32_t>(),
                seg_done_.as<uint8_t>(), M, out, ns_dev);
-    KB_CHECK(hipEventRecord(ev_main_, st_));
-    KB_CHECK(hipStreamWaitEvent(side, ev_main_, 0));
-    KB_CHECK(hipStreamWaitEvent(big, ev_main_, 0));
+    if (!one) {
+      KB_CHECK(hipEventRecord(ev_main_, st_));
+      KB_CHECK(hipStreamWaitEvent(side, ev_main_, 0));
+      KB_CHECK(hipStreamWaitEvent(big, ev_main_, 0));
+    }
     resolve_lists<KeyT>(out, kvp, side, big);
-    KB_CHECK(hipEventRecord(ev_side_[nx], side));
-    KB_CHECK(hipEventRecord(ev_big_[nx], big));
+    if (!one) {
+      KB_CHECK(hipEventRecord(ev_side_[nx], side));
+      KB_CHECK(hipEventRecord(ev_big_[nx], big));
+    }
     side_pending[nx] = true;
     // the next pass works on the large subgroups, read from `out`
     nl = out.cnt[kLargeClass];
@@ -737,10 +746,12 @@ void Engine::order_groups(const void* kvp) {
     first_pass = false;
   }
   // everything the resolver streams did comes before what follows on this one
-  KB_CHECK(hipEventRecord(ev_join_, side));
-  KB_CHECK(hipEventRecord(ev_join_big_, big));
-  KB_CHECK(hipStreamWaitEvent(st_, ev_join_, 0));
-  KB_CHECK(hipStreamWaitEvent(st_, ev_join_big_, 0));
+  if (!one) {
+    KB_CHECK(hipEventRecord(ev_join_, side));
+    KB_CHECK(hipEventRecord(ev_join_big_, big));
+    KB_CHECK(hipStreamWaitEvent(st_, ev_join_, 0));
+    KB_CHECK(hipStreamWaitEvent(st_, ev_join_big_, 0));
+  }
 }
 
 // The round's hubs (list hl, nh entries, item offsets in hub_off_) sorted
@@ -1444,6 +1455,42 @@ void Server::release(uint64_t id) {
 // ===========================================================================
 // C ABI
 
+// The static scratch region of the allocation-free entry point: one copy per
+// GPU the library runs on, held until the process ends. Host code never uses
+// the symbol itself (a host-side stand-in): the device address comes from
+// hipGetSymbolAddress, once per device, with that device current.
+static __device__ __align__(256) unsigned char scratch[KBISIM_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_busy[kMaxDevices];  // one job at a time per device uses the region
+
+int current_device() {
+  int dev = 0;
+  KB_CHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) throw kb::DeviceError(hipErrorInvalidDevice, "device index out of range");
+  return dev;
+}
+
+// Device address of this device's scratch region (looked up on first use).
+void* scratch_region(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    KB_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw kb::DeviceError(hipErrorInvalidSymbol, "no device address for the scratch region");
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+
+// Upper bound on the region a job of n nodes and m edges may need (all its
+// buffers at their peak, with room for the first-fit arena's fragmentation).
+uint64_t static_footprint(uint64_t n, uint64_t m) { return 48 * m + 256 * n + (uint64_t(1) << 20); }
+}  // namespace
+
 struct kbisim_graph {
   kb::Engine* eng = nullptr;
 };
@@ -1552,6 +1599,55 @@ kbisim_status kbisim_create(const kbisim_graph_desc* d, const kbisim_options* op
     auto* h = new kbisim_graph;
     h->eng = eng;
     *out = h;
+    return KBISIM_OK;
+  });
+}
+
+kbisim_status kbisim_refine_static(const kbisim_graph_desc* d, int32_t k, const kbisim_options* opt,
+                                   int32_t* pid_out, kbisim_mem out_mem, int64_t* num_blocks,
+                                   int32_t* rounds_done) {
+  if (!d) return fail(KBISIM_EINVAL, "null desc");
+  if (d->num_nodes < 0 || d->num_edges < 0) return fail(KBISIM_EINVAL, "negative size");
+  if (k < 0) return fail(KBISIM_EINVAL, "k < 0");
+  if (d->num_nodes > 0 && !d->node_label) return fail(KBISIM_EINVAL, "null node_label");
+  if (d->num_edges > 0 && (!d->edge_src || !d->edge_label || !d->edge_dst))
+    return fail(KBISIM_EINVAL, "null edge array");
+  if (d->num_nodes > 0 && !pid_out) return fail(KBISIM_EINVAL, "null pid_out");
+  if (d->mem != KBISIM_MEM_HOST && d->mem != KBISIM_MEM_DEVICE) return fail(KBISIM_EINVAL, "bad mem kind");
+  if (out_mem != KBISIM_MEM_HOST && out_mem != KBISIM_MEM_DEVICE) return fail(KBISIM_EINVAL, "bad output mem kind");
+  if (d->num_nodes >= (int64_t(1) << 31) || d->num_edges >= int64_t(0xffffffffll) ||
+      static_footprint(uint64_t(d->num_nodes), uint64_t(d->num_edges)) > uint64_t(KBISIM_STATIC_SCRATCH_BYTES))
+    return fail(KBISIM_ENOMEM, "graph too large for the static scratch region (KBISIM_STATIC_SCRATCH_BYTES)");
+  kb::Options o;
+  if (parse_options(opt, &o) != KBISIM_OK) return KBISIM_EINVAL;
+  o.profile = false;
+  o.history = false;
+  return guarded([&]() {
+    const int dev = current_device();
+    void* region = scratch_region(dev);
+    std::lock_guard<std::mutex> busy(g_scratch_busy[dev]);
+    hipStream_t s = static_cast<hipStream_t>(d->stream);
+    kb::Arena arena(region, KBISIM_STATIC_SCRATCH_BYTES);
+    kb::ArenaScope as(&arena);
+    kb::StreamScope scope(s);
+    const uint64_t N = uint64_t(d->num_nodes), E = uint64_t(d->num_edges);
+    kb::Engine eng(d->num_nodes, d->num_edges, s, o);
+    if (d->mem == KBISIM_MEM_HOST) {
+      kb::DevBuf b[4];
+      const uint64_t len[4] = {N, E, E, E};
+      const int32_t* src[4] = {d->node_label, d->edge_src, d->edge_label, d->edge_dst};
+      for (int i = 0; i < 4; ++i) {
+        b[i].ensure(std::max<uint64_t>(len[i], 1) * 4);
+        if (len[i]) KB_CHECK(hipMemcpyAsync(b[i].p, src[i], len[i] * 4, hipMemcpyHostToDevice, s));
+      }
+      eng.build(b[0].as<int32_t>(), b[1].as<int32_t>(), b[2].as<int32_t>(), b[3].as<int32_t>());
+    } else {
+      eng.build(d->node_label, d->edge_src, d->edge_label, d->edge_dst);
+    }
+    eng.refine(k);
+    if (N) eng.result(pid_out, out_mem == KBISIM_MEM_DEVICE);
+    if (num_blocks) *num_blocks = eng.blocks();
+    if (rounds_done) *rounds_done = eng.rounds_done();
     return KBISIM_OK;
   });
 }

@@ -13,6 +13,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <iterator>
 #include <map>
 #include <mutex>
 #include <string>
@@ -23,6 +24,67 @@
 
 namespace kb {
 
+// A fixed device region that serves every allocation of the calling thread
+// while an ArenaScope is active (first fit, neighbours merged on free). The
+// library's allocation-free entry point runs a whole job inside one; all its
+// work is on one stream, so a block freed there can be reused by the next
+// allocation at once (later kernels are ordered after earlier ones).
+class Arena {
+ public:
+  Arena(void* base, size_t bytes) : base_(static_cast<char*>(base)), bytes_(bytes) { free_[0] = bytes; }
+  void* get(size_t want) {
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second < want) continue;
+      const size_t off = it->first, len = it->second;
+      free_.erase(it);
+      if (len > want) free_[off + want] = len - want;
+      used_ += want;
+      peak_ = used_ > peak_ ? used_ : peak_;
+      return base_ + off;
+    }
+    throw OutOfMemory("the static scratch region (" + std::to_string(bytes_) + " bytes) is exhausted");
+  }
+  bool owns(const void* p) const {
+    const char* c = static_cast<const char*>(p);
+    return c >= base_ && c < base_ + bytes_;
+  }
+  void put(void* p, size_t bytes) {
+    size_t off = size_t(static_cast<char*>(p) - base_), len = bytes;
+    used_ -= bytes;
+    auto next = free_.lower_bound(off);
+    if (next != free_.end() && off + len == next->first) {
+      len += next->second;
+      next = free_.erase(next);
+    }
+    if (next != free_.begin()) {
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == off) {
+        prev->second += len;
+        return;
+      }
+    }
+    free_[off] = len;
+  }
+  size_t peak() const { return peak_; }
+
+ private:
+  char* base_;
+  size_t bytes_;
+  std::map<size_t, size_t> free_;  // offset -> length
+  size_t used_ = 0, peak_ = 0;
+};
+
+inline Arena*& active_arena() {
+  static thread_local Arena* a = nullptr;
+  return a;
+}
+
+struct ArenaScope {
+  Arena* prev;
+  explicit ArenaScope(Arena* a) : prev(active_arena()) { active_arena() = a; }
+  ~ArenaScope() { active_arena() = prev; }
+};
+
 class Pool {
  public:
   static Pool& instance() {
@@ -32,6 +94,10 @@ class Pool {
 
   void* get(size_t bytes, hipStream_t s, size_t* got) {
     const size_t want = round(bytes);
+    if (Arena* a = active_arena()) {
+      *got = want;
+      return a->get(want);
+    }
     int dev = 0;
     KB_CHECK(hipGetDevice(&dev));
     Blk b{nullptr, 0, nullptr, 0, nullptr};
@@ -83,6 +149,12 @@ class Pool {
 
   void put(void* p, size_t bytes, hipStream_t s) {
     if (!p) return;
+    if (Arena* a = active_arena()) {
+      if (a->owns(p)) {
+        a->put(p, bytes);
+        return;
+      }
+    }
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) dev = 0;
     Blk b{p, bytes, s, dev, get_event(dev)};
@@ -154,7 +226,7 @@ class Pool {
   }
   static size_t round(size_t b) {
     if (b == 0) b = 1;
-    const size_t g = b >= (size_t(1) << 20) ? (size_t(1) << 20) : 256;
+    const size_t g = (b >= (size_t(1) << 20) && !active_arena()) ? (size_t(1) << 20) : 256;
     return (b + g - 1) / g * g;
   }
   std::mutex mu_;
