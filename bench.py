@@ -21,6 +21,11 @@ Prints one JSON line (rank 0). Options:
   --copy-probe    only a 1 GiB device-to-device copy (1 GiB read, 1 GiB
                   written): the calibration run for rocprofv3 FETCH_SIZE /
                   WRITE_SIZE readings of the library's kernels
+  --form update   maintenance (Section 5.3): m random edges of the graph are
+                  left out, the partition of the rest is computed with the
+                  history kept, then kbisim_update adds the m edges back;
+                  its time against a rebuild of the whole job, for
+                  m = 1, 10, ..., --max-batch (one JSON line)
 """
 from __future__ import annotations
 
@@ -116,7 +121,8 @@ def main():
     ap.add_argument("--no-early-stop", action="store_true",
                     help="plain form: run all k rounds even past the fixed point")
     ap.add_argument("--medium-cap", type=int, default=None)
-    ap.add_argument("--form", choices=["plain", "batched", "served"], default="plain")
+    ap.add_argument("--form", choices=["plain", "batched", "served", "update"], default="plain")
+    ap.add_argument("--max-batch", type=int, default=1_000_000, help="update: largest batch of added edges")
     ap.add_argument("--graphs", type=int, default=512, help="batched: number of graphs")
     ap.add_argument("--requests", type=int, default=300, help="served: number of requests")
     ap.add_argument("--max-nodes", type=int, default=10_000_000, help="served: largest request")
@@ -146,6 +152,8 @@ def main():
         return bench_batched(args, torch, kb, dev)
     if args.form == "served":
         return bench_served(args, torch, kb, dev)
+    if args.form == "update":
+        return bench_update(args, torch, kb, dev)
     if args.host_io:
         return bench_host_io(args, torch, kb)
 
@@ -348,6 +356,88 @@ def bench_batched(args, torch, kb, dev):
         "medium_cap": cap, "tune_seconds": tune_times,
         "per_graph_loop": {"ms": t_loop * 1e3, "edge_rounds_per_s": edge_rounds / t_loop},
         "speedup_vs_loop": t_loop / t_batch, "identical_to_loop": same,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_update(args, torch, kb, dev):
+    """Add_Edges against a rebuild (the paper's multiple-edge experiment,
+    Section 5.3): for each batch size m, m edges drawn at random from the
+    graph are left out, the job runs on the rest with the history kept, and
+    kbisim_update adds the m edges back. The updated ids must equal those of
+    the whole graph's job bit for bit. The rebuild is the plain job (create,
+    refine, result) on the whole graph, with and without the history."""
+    import numpy as np
+    import synth
+    g, k_default = synth.make_config(args.workload, seed=args.seed, progress=log)
+    k = args.k if args.k is not None else k_default
+    arrs = [torch.from_numpy(a).to(dev) for a in (g.node_label, g.src, g.elab, g.dst)]
+    stream = torch.cuda.current_stream()
+    ref = torch.empty(g.num_nodes, dtype=torch.int32, device=dev)
+
+    def job(history):
+        h = kb.kbisim_create(g.num_nodes, *arrs, stream=stream, history=history)
+        try:
+            rd = kb.kbisim_refine(h, k)
+            kb.kbisim_result(h, ref)
+        finally:
+            kb.kbisim_destroy(h)
+        return rd
+
+    rebuild = {}
+    for history in (False, True):
+        job(history)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(max(args.steps, 1)):
+            t0 = time.perf_counter()
+            rd = job(history)
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+        rebuild["history" if history else "plain"] = float(np.median(ts))
+    want = ref.cpu().numpy()
+    log("rebuild: %s ms, rounds=%d" % (rebuild, rd))
+    rng = np.random.Generator(np.random.PCG64(args.seed + 17))
+    rows = []
+    m = 1
+    out = torch.empty(g.num_nodes, dtype=torch.int32, device=dev)
+    while m <= min(args.max_batch, g.num_edges):
+        pick = np.sort(rng.choice(g.num_edges, size=m, replace=False))
+        keep = np.ones(g.num_edges, bool)
+        keep[pick] = False
+        keep_t = torch.from_numpy(keep).to(dev)
+        base = [arrs[0]] + [a[keep_t].contiguous() for a in arrs[1:]]
+        added = [a[torch.from_numpy(pick).to(dev)].contiguous() for a in arrs[1:]]
+        h = kb.kbisim_create(g.num_nodes, *base, stream=stream, history=True)
+        try:
+            rd0 = kb.kbisim_refine(h, k)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rd1 = kb.kbisim_update(h, add=tuple(added))
+            torch.cuda.synchronize()
+            t_upd = (time.perf_counter() - t0) * 1e3
+            levels, full_from, rechecked, recomputed, changed = kb.kbisim_update_stats(h)
+            kb.kbisim_result(h, out)
+        finally:
+            kb.kbisim_destroy(h)
+        same = bool(np.array_equal(out.cpu().numpy(), want)) and rd1 == rd
+        rows.append({"edges": m, "update_ms": t_upd, "speedup_vs_rebuild": rebuild["plain"] / t_upd,
+                     "rounds_before": rd0, "rounds_after": rd1, "full_rounds_from": full_from,
+                     "rechecked": rechecked, "recomputed": recomputed,
+                     "changed": changed, "identical_to_rebuild": same})
+        log("m=%d: update %.2f ms (rebuild %.2f ms), full rounds from %d, rechecked %d, recomputed %d, "
+            "identical %s" % (m, t_upd, rebuild["plain"], full_from, rechecked, recomputed, same))
+        del base, added, keep_t
+        m *= 10
+    line = {
+        "metric": "Add_Edges time vs rebuild (ms), %s, m random edges added back" % args.workload,
+        "value": rows[0]["update_ms"] if rows else None, "unit": "ms", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": rows[0]["update_ms"] if rows else None, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": args.workload, "num_nodes": g.num_nodes, "num_edges": g.num_edges, "k_cap": k,
+                   "rounds": rd},
+        "rebuild_ms": rebuild, "batches": rows,
+        "identical_to_rebuild": all(r["identical_to_rebuild"] for r in rows),
     }
     print(json.dumps(line), flush=True)
 

@@ -84,6 +84,12 @@ typedef struct {
                          8 B per node per round plus the edge table again; needed by
                          kbisim_result_round for earlier rounds and by kbisim_update.
                          0 (default): only the last round. */
+  int32_t update_mode; /* how kbisim_update brings the stored rounds up to date after
+                          the graph changed: 0 (default) per round by cost, level by
+                          level (Algorithm 3) while that is cheaper than a full round,
+                          then full rounds (Section 4, "When to switch back"); 1 level
+                          by level in every round; 2 full rounds from round 1. The
+                          result does not depend on it. */
 } kbisim_options;
 
 /* Fills *opt with the defaults above. */
@@ -164,7 +170,9 @@ typedef struct {
  * nodes whose class changed in the round below and their sources are
  * re-checked; classes holding none of them keep their stored split). When
  * the update moves the fixed point, rounds continue up to the largest k
- * given to kbisim_refine (or stop earlier at the new fixed point). Afterwards
+ * given to kbisim_refine (or stop earlier at the new fixed point). From a
+ * round whose frontier outgrows a full round, the remaining rounds run in
+ * full (Section 4, "When to switch back"). Afterwards
  * the handle holds exactly what kbisim_create on the updated graph followed
  * by kbisim_refine(k) gives: every round's ids, counts and rounds done.
  * Needs options.history = 1 (else KBISIM_ESTATE). Invalid input
@@ -172,12 +180,16 @@ typedef struct {
  * KBISIM_EINVAL and leaves the handle unchanged. *rounds_done may be NULL. */
 kbisim_status kbisim_update(kbisim_graph* g, const kbisim_update_desc* u, int32_t* rounds_done);
 
-/* Work of the last kbisim_update: rounds brought up to date, nodes re-checked
- * (the frontiers, summed over rounds), nodes whose signature was recomputed
+/* Work of the last kbisim_update: rounds brought up to date level by level,
+ * the first round recomputed in full instead (0 if none: when a round's
+ * frontier and the classes it touches hold more nodes than a full round
+ * re-orders, that round and the later ones run as in kbisim_refine, the
+ * switch back to Algorithm 1 that Section 4 suggests), nodes re-checked (the
+ * frontiers, summed over rounds), nodes whose signature was recomputed
  * (members of the re-ordered classes) and nodes found changed. Any pointer
  * may be NULL. */
-kbisim_status kbisim_update_stats(const kbisim_graph* g, int64_t* levels, int64_t* rechecked, int64_t* recomputed,
-                                  int64_t* changed);
+kbisim_status kbisim_update_stats(const kbisim_graph* g, int64_t* levels, int64_t* full_from, int64_t* rechecked,
+                                  int64_t* recomputed, int64_t* changed);
 
 /* Kernel classes timed when options.profile = 1. */
 typedef enum {

@@ -34,7 +34,8 @@ class GraphDesc(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("early_stop", ctypes.c_int32), ("profile", ctypes.c_int32),
-                ("medium_cap", ctypes.c_int32), ("history", ctypes.c_int32)]
+                ("medium_cap", ctypes.c_int32), ("history", ctypes.c_int32),
+                ("update_mode", ctypes.c_int32)]
 
 
 class UpdateDesc(ctypes.Structure):
@@ -79,7 +80,7 @@ def load_library():
     lib.kbisim_update.argtypes = [vp, ctypes.POINTER(UpdateDesc), ctypes.POINTER(i32)]
     lib.kbisim_update.restype = ctypes.c_int
     lib.kbisim_update_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
-                                        ctypes.POINTER(i64)]
+                                        ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.kbisim_update_stats.restype = ctypes.c_int
     lib.kbisim_profile.argtypes = [vp, vp, vp, i32, i32]
     lib.kbisim_profile.restype = ctypes.c_int
@@ -176,7 +177,7 @@ def _arrays(node_label, src, elab, dst):
 
 
 def kbisim_create(num_nodes, node_label, src, elab, dst, *, stream=None, early_stop=True,
-                  profile=False, medium_cap=None, history=False):
+                  profile=False, medium_cap=None, history=False, update_mode=0):
     """Creates a device-resident graph handle (see kbisim.h). Returns the handle."""
     lib = load_library()
     mem, ptrs, keep = _arrays(node_label, src, elab, dst)
@@ -190,6 +191,7 @@ def kbisim_create(num_nodes, node_label, src, elab, dst, *, stream=None, early_s
     opt.early_stop = 1 if early_stop else 0
     opt.profile = 1 if profile else 0
     opt.history = 1 if history else 0
+    opt.update_mode = int(update_mode)
     if medium_cap is not None:
         opt.medium_cap = int(medium_cap)
     h = ctypes.c_void_p()
@@ -299,8 +301,8 @@ def kbisim_refine_static(num_nodes, node_label, src, elab, dst, k, pid_out, *, s
 
 
 def kbisim_update_stats(handle):
-    """(levels, rechecked, recomputed, changed) of the last update."""
-    v = [ctypes.c_int64(0) for _ in range(4)]
+    """(levels, full_from, rechecked, recomputed, changed) of the last update."""
+    v = [ctypes.c_int64(0) for _ in range(5)]
     _check(load_library().kbisim_update_stats(handle, *[ctypes.byref(x) for x in v]))
     return tuple(int(x.value) for x in v)
 

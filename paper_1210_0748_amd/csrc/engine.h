@@ -89,6 +89,7 @@ struct Options {
   bool early_stop = true;
   bool profile = false;
   bool history = false;  // keep pId_0..pId_rounds and the maintenance state (reverse CSR, label values)
+  int update_mode = 0;   // rounds of an update: 0 chosen by cost, 1 level by level, 2 in full
   uint32_t medium_cap = kDefaultMediumCap;  // groups above this size use the global passes
 };
 
@@ -108,7 +109,8 @@ struct UpdateArgs {
 // (members of the classes that had to be re-ordered), nodes re-checked
 // (the frontier) and nodes found changed.
 struct UpdateStat {
-  int32_t levels = 0;
+  int32_t levels = 0;     // rounds brought up to date level by level
+  int32_t full_from = 0;  // first round recomputed in full instead (0: none)
   uint64_t recomputed = 0, rechecked = 0, changed = 0;
 };
 
@@ -259,6 +261,8 @@ class Engine {
   DevBuf rtag_, ctag_, dtag_, cont_;
   uint32_t utag_ = 0;
   DevBuf src_list_, rlist_, clist_, dlist_, dsize_, ufirst_, keep_, kscan_, old_prev_pid_, old_ord_, old_pid_;
+  DevBuf fill_, dszpos_, isize_, gw_, inode_, iflag_, w_, wscan_, inu_, kus_, oflag_, ocls_, ofirst_, xpos_, xflag_;
+  DevBuf chunk_;
   uint32_t n_src_ = 0;       // sources of changed edges and new nodes, checked at every level
   uint32_t old_n_nodes_ = 0;  // nodes before the update in progress
   UpdateStat ustat_;

@@ -1546,6 +1546,7 @@ void kbisim_options_default(kbisim_options* opt) {
   opt->profile = 0;
   opt->medium_cap = int32_t(kb::kDefaultMediumCap);
   opt->history = 0;
+  opt->update_mode = 0;
 }
 
 static kbisim_status parse_options(const kbisim_options* opt, kb::Options* o) {
@@ -1556,6 +1557,8 @@ static kbisim_status parse_options(const kbisim_options* opt, kb::Options* o) {
     return fail(KBISIM_EINVAL, "medium_cap outside [0, 4096]");
   if (opt->medium_cap > 0) o->medium_cap = uint32_t(opt->medium_cap);
   o->history = opt->history != 0;
+  if (opt->update_mode < 0 || opt->update_mode > 2) return fail(KBISIM_EINVAL, "update_mode outside [0, 2]");
+  o->update_mode = opt->update_mode;
   return KBISIM_OK;
 }
 
@@ -1747,11 +1750,12 @@ kbisim_status kbisim_update(kbisim_graph* g, const kbisim_update_desc* u, int32_
   });
 }
 
-kbisim_status kbisim_update_stats(const kbisim_graph* g, int64_t* levels, int64_t* rechecked, int64_t* recomputed,
-                                  int64_t* changed) {
+kbisim_status kbisim_update_stats(const kbisim_graph* g, int64_t* levels, int64_t* full_from, int64_t* rechecked,
+                                  int64_t* recomputed, int64_t* changed) {
   if (!g || !g->eng) return fail(KBISIM_EINVAL, "null handle");
   const kb::UpdateStat& s = g->eng->update_stat();
   if (levels) *levels = s.levels;
+  if (full_from) *full_from = s.full_from;
   if (rechecked) *rechecked = int64_t(s.rechecked);
   if (recomputed) *recomputed = int64_t(s.recomputed);
   if (changed) *changed = int64_t(s.changed);

@@ -306,44 +306,97 @@ __device__ __forceinline__ void frontier_mark(bool want, uint32_t p, uint32_t* _
 // Frontier of level j (Algorithm 3's queue at level j): every node of
 // `always` (sources of changed edges and new nodes, checked at every level),
 // and every node of `changed` (its class changed at level j - 1, so its own
-// head changed) with its sources through the reverse table. One wave per
-// listed node.
+// head changed) with its sources through the reverse table. Work items are
+// one listed node, or one chunk of kFrontierChunk sources of a changed node
+// (chunk_off = exclusive scan of the chunks per changed node), one wave each,
+// so a node with very many sources is spread over many waves.
+constexpr uint32_t kFrontierChunk = 2048;
+__global__ void frontier_chunks_k(const uint32_t* __restrict__ changed, const uint32_t* __restrict__ n_changed_dev,
+                                  const uint32_t* __restrict__ rrowptr, uint32_t* __restrict__ chunks) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t n = *n_changed_dev;
+  if (i > n) return;
+  if (i == n) {
+    chunks[i] = 0;
+    return;
+  }
+  const uint32_t u = changed[i];
+  chunks[i] = (rrowptr[u + 1] - rrowptr[u] + kFrontierChunk - 1) / kFrontierChunk;
+}
 template <typename W>
 __global__ __launch_bounds__(256) void frontier_k(const uint32_t* __restrict__ always, uint32_t n_always,
                                                   const uint32_t* __restrict__ changed,
                                                   const uint32_t* __restrict__ n_changed_dev,
+                                                  const uint32_t* __restrict__ chunk_off,
                                                   const uint32_t* __restrict__ rrowptr, const W* __restrict__ radj,
                                                   int bits, uint32_t* __restrict__ rtag, uint32_t tag,
                                                   uint32_t* __restrict__ rlist, uint32_t* __restrict__ rcount) {
-  const uint32_t n_changed = n_changed_dev ? *n_changed_dev : 0u;
-  const uint32_t total = n_always + n_changed;
+  const uint32_t n_changed = *n_changed_dev;
+  const uint32_t n_chunks = chunk_off[n_changed];
+  const uint32_t total = n_always + n_changed + n_chunks;
   const uint32_t lane = __lane_id();
   const W mask = (W(1) << bits) - 1;
   for (uint32_t i = (blockIdx.x * blockDim.x + threadIdx.x) / kWave; i < total;
        i += (gridDim.x * blockDim.x) / kWave) {
-    const bool is_changed = i >= n_always;
-    const uint32_t u = is_changed ? changed[i - n_always] : always[i];
-    frontier_mark(lane == 0, u, rtag, tag, rlist, rcount);
-    if (!is_changed) continue;  // uniform over the wave
-    const uint32_t b = rrowptr[u], e = rrowptr[u + 1];
-    for (uint32_t x0 = b; x0 < e; x0 += kWave) {
-      const uint32_t x = x0 + lane;
-      const bool in = x < e;
-      frontier_mark(in, in ? uint32_t(radj[x] & mask) : 0u, rtag, tag, rlist, rcount);
+    if (i < n_always + n_changed) {  // a listed node itself
+      const uint32_t u = i < n_always ? always[i] : changed[i - n_always];
+      frontier_mark(lane == 0, u, rtag, tag, rlist, rcount);
+      continue;
     }
+    // chunk q of the sources of changed node t (chunk_off[t] <= q < chunk_off[t + 1])
+    const uint32_t q = i - n_always - n_changed;
+    uint32_t lo = 0, hi = n_changed;  // last t with chunk_off[t] <= q
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (chunk_off[mid] <= q)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    const uint32_t u = changed[lo];
+    const uint32_t b = rrowptr[u] + (q - chunk_off[lo]) * kFrontierChunk;
+    const uint32_t e = min(b + kFrontierChunk, rrowptr[u + 1]);
+    // each lane marks its sources of the chunk, keeps the fresh ones, and
+    // the wave appends them with one atomic
+    constexpr int kPer = int(kFrontierChunk / kWave);
+    uint32_t fresh[kPer];
+    int nf = 0;
+#pragma unroll
+    for (int t = 0; t < kPer; ++t) {
+      const uint32_t x = b + uint32_t(t) * kWave + lane;
+      if (x < e) {
+        const uint32_t p = uint32_t(radj[x] & mask);
+        if (atomicExch(&rtag[p], tag) != tag) fresh[nf++] = p;
+      }
+    }
+    const uint32_t incl = wave_inclusive_scan(uint32_t(nf));
+    const uint32_t tot = __shfl(incl, kWave - 1, kWave);
+    uint32_t base = 0;
+    if (lane == 0 && tot) base = atomicAdd(rcount, tot);
+    base = __shfl(base, 0, kWave) + incl - uint32_t(nf);
+    for (int t = 0; t < nf; ++t) rlist[base + uint32_t(t)] = fresh[t];
   }
 }
 
 // Classes of level j - 1 holding a frontier node (by class-start position).
+// Kernels over device-sized lists run a capped grid; every wave steps
+// through the list together (wave_append needs all its lanes).
+#define KB_LIST_LOOP(i, n)                                                                        \
+  for (uint32_t kb_base = blockIdx.x * blockDim.x; kb_base < (n); kb_base += gridDim.x * blockDim.x) \
+    if (const uint32_t i = kb_base + threadIdx.x; true)
+constexpr uint32_t kListGrid = 1024;
+
 __global__ void dirty_classes_k(const uint32_t* __restrict__ rlist, const uint32_t* __restrict__ rcount,
                                 const int32_t* __restrict__ pid, uint32_t* __restrict__ dtag, uint32_t tag,
                                 uint32_t* __restrict__ dlist, uint32_t* __restrict__ dcount) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool in = i < *rcount;
-  const uint32_t c = in ? uint32_t(pid[rlist[i]]) : 0u;
-  const bool fresh = in && atomicExch(&dtag[c], tag) != tag;
-  const uint32_t slot = wave_append(fresh, dcount);
-  if (fresh) dlist[slot] = c;
+  const uint32_t n = *rcount;
+  KB_LIST_LOOP(i, n) {
+    const bool in = i < n;
+    const uint32_t c = in ? uint32_t(pid[rlist[i]]) : 0u;
+    const bool fresh = in && atomicExch(&dtag[c], tag) != tag;
+    const uint32_t slot = wave_append(fresh, dcount);
+    if (fresh) dlist[slot] = c;
+  }
 }
 
 // First position of every class (cls = inclusive scan of the class-start flags).
@@ -356,15 +409,211 @@ __global__ void class_starts_k(const uint8_t* __restrict__ flag, const uint32_t*
 // Size of every listed class; members of those with two or more summed.
 __global__ void dirty_sizes_k(const uint32_t* __restrict__ dlist, const uint32_t* __restrict__ dcount,
                               const uint32_t* __restrict__ cls, const uint32_t* __restrict__ firstpos, uint32_t n,
-                              uint32_t* __restrict__ dsize, uint32_t* __restrict__ members) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= *dcount) return;
-  const uint32_t c = dlist[i];
-  const uint32_t ci = cls[c] - 1, B = cls[n - 1];
-  const uint32_t next = ci + 1 < B ? firstpos[ci + 1] : n;
-  const uint32_t z = next - c;
-  dsize[i] = z;
-  if (z >= 2) atomicAdd(members, z);
+                              uint32_t* __restrict__ dsize, uint32_t* __restrict__ dsz_pos, uint32_t* __restrict__ fill,
+                              uint32_t* __restrict__ members) {
+  const uint32_t nd = *dcount, B = cls[n - 1];
+  KB_LIST_LOOP(i, nd) {
+    uint32_t z = 0;
+    if (i < nd) {
+      const uint32_t c = dlist[i];
+      const uint32_t ci = cls[c] - 1;
+      const uint32_t next = ci + 1 < B ? firstpos[ci + 1] : n;
+      z = next - c;
+      dsize[i] = z >= 2 ? z : 0u;
+      dsz_pos[c] = z;
+      fill[c] = 0;
+    }
+    z = wave_sum(z >= 2 ? z : 0u);
+    if (__lane_id() == 0 && z) atomicAdd(members, z);
+  }
+}
+
+// Members of the classes with two or more members (an upper bound on the
+// nodes a full round re-orders), from the class-start flags alone.
+__global__ __launch_bounds__(256) void multi_members_k(const uint8_t* __restrict__ flag, uint32_t n,
+                                                       unsigned long long* __restrict__ total) {
+  __shared__ uint32_t sh[256 / kWave];
+  uint32_t z = 0;
+  for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x)
+    z += (flag[p] && (p + 1 == n || flag[p + 1])) ? 0u : 1u;
+  z = block_sum<256>(z, sh);
+  if (threadIdx.x == 0 && z) atomicAdd(total, (unsigned long long)z);
+}
+
+// ---- re-ordered classes through representatives ----------------------------
+// A class of level j - 1 that holds frontier nodes (R) also holds nodes
+// outside the frontier (U); U nodes keep their level-j signature, so the U
+// nodes of one stored class X of round j stay together (one new class, the
+// continuation of X). Only one representative per such group (the first U
+// member of X in the stored order) and the R nodes are ordered by signature;
+// the groups are expanded to their members afterwards.
+
+// Slot of this lane among the lanes of its wave that add to the same
+// counter (one atomic per distinct counter in the wave, not per lane: the
+// items of one big class arrive together). Every lane of the wave calls it.
+__device__ __forceinline__ uint32_t wave_group_add(bool want, uint32_t key, uint32_t* __restrict__ counters) {
+  uint64_t pending = __ballot(want);
+  uint32_t slot = 0;
+  while (pending) {
+    const int leader = __ffsll((unsigned long long)pending) - 1;
+    const uint32_t k = __shfl(key, leader, kWave);
+    const uint64_t same = __ballot(want && key == k);
+    uint32_t base = 0;
+    if (__lane_id() == leader) base = atomicAdd(&counters[k], uint32_t(__popcll(same)));
+    base = __shfl(base, leader, kWave);
+    if (want && key == k) slot = base + uint32_t(__popcll(same & lanemask_lt()));
+    pending &= ~same;
+  }
+  return slot;
+}
+
+// Per old position p of the stored round j: inU[p] = the node is outside
+// the frontier; keep[p] = the node kept its class at level j - 1; oflag[p] =
+// p starts a stored class.
+__global__ void old_flags_k(const uint32_t* __restrict__ old_ord, const int32_t* __restrict__ old_pid, uint32_t n_o,
+                            const uint32_t* __restrict__ rtag, uint32_t tag, const uint32_t* __restrict__ ctag,
+                            uint32_t tag_prev, uint32_t* __restrict__ inU, uint32_t* __restrict__ keep,
+                            uint32_t* __restrict__ oflag) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_o) return;
+  const uint32_t u = old_ord[p];
+  inU[p] = rtag[u] != tag ? 1u : 0u;
+  keep[p] = ctag[u] != tag_prev ? 1u : 0u;
+  oflag[p] = uint32_t(old_pid[u]) == p ? 1u : 0u;
+}
+
+// Items of the re-ordered classes (dsz[class start] >= 2): the frontier
+// nodes and the representatives. With place = false only counted (per class
+// start, in fill), with place = true also written to ord from the class
+// start on (fill counted from zero again). gw[u] = the item's weight: the
+// size of its group for a representative, 1 for a frontier node.
+__global__ void items_frontier_k(const uint32_t* __restrict__ rlist, const uint32_t* __restrict__ rcount,
+                                 const int32_t* __restrict__ pid, const uint32_t* __restrict__ dsz,
+                                 uint32_t* __restrict__ fill, bool place, uint32_t* __restrict__ ord,
+                                 uint32_t* __restrict__ gw) {
+  const uint32_t n = *rcount;
+  KB_LIST_LOOP(i, n) {
+    bool want = false;
+    uint32_t u = 0, c = 0;
+    if (i < n) {
+      u = rlist[i];
+      c = uint32_t(pid[u]);
+      want = dsz[c] >= 2;
+    }
+    const uint32_t slot = wave_group_add(want, c, fill);
+    if (want && place) {
+      ord[c + slot] = u;
+      gw[u] = 1u;
+    }
+  }
+}
+__global__ void items_reps_k(const uint32_t* __restrict__ old_ord, const int32_t* __restrict__ old_pid, uint32_t n_o,
+                             const uint32_t* __restrict__ inU, const uint32_t* __restrict__ kus,
+                             const uint32_t* __restrict__ ocls, const uint32_t* __restrict__ ofirst,
+                             const int32_t* __restrict__ pid, const uint32_t* __restrict__ dtag, uint32_t tag,
+                             const uint32_t* __restrict__ dsz, uint32_t* __restrict__ fill, bool place,
+                             uint32_t* __restrict__ ord, uint32_t* __restrict__ gw) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  bool want = false;
+  uint32_t u = 0, c = 0, xs = 0;
+  if (p < n_o && inU[p]) {
+    u = old_ord[p];
+    c = uint32_t(pid[u]);
+    if (dtag[c] == tag && dsz[c] >= 2) {
+      xs = uint32_t(old_pid[u]);
+      want = kus[p] == kus[xs];  // the first U member of its stored class
+    }
+  }
+  const uint32_t slot = wave_group_add(want, c, fill);
+  if (!want || !place) return;
+  const uint32_t ci = ocls[xs] - 1, B = ocls[n_o - 1];
+  const uint32_t xe = ci + 1 < B ? ofirst[ci + 1] : n_o;
+  ord[c + slot] = u;
+  gw[u] = kus[xe] - kus[xs];
+}
+
+// Per re-ordered class: its item count becomes the segment size; fill is
+// cleared for the placing pass; the items are summed.
+__global__ void item_sizes_k(const uint32_t* __restrict__ dlist, const uint32_t* __restrict__ dcount,
+                             const uint32_t* __restrict__ dsz, uint32_t* __restrict__ fill,
+                             uint32_t* __restrict__ isize, uint32_t* __restrict__ total) {
+  const uint32_t nd = *dcount;
+  KB_LIST_LOOP(i, nd) {
+    uint32_t z = 0;
+    if (i < nd) {
+      const uint32_t c = dlist[i];
+      z = dsz[c] >= 2 ? fill[c] : 0u;
+      isize[i] = z;
+      fill[c] = 0;
+    }
+    z = wave_sum(z);
+    if (__lane_id() == 0 && z) atomicAdd(total, z);
+  }
+}
+
+// First position of every stored class (u32 flags, ocls inclusive scan).
+__global__ void old_starts_k(const uint32_t* __restrict__ oflag, const uint32_t* __restrict__ ocls, uint32_t n,
+                             uint32_t* __restrict__ ofirst) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n && oflag[p]) ofirst[ocls[p] - 1] = p;
+}
+
+// After the ordering: the items in their order, and their weights.
+__global__ void items_read_k(const uint32_t* __restrict__ apos, uint32_t m, const uint32_t* __restrict__ ord,
+                             const uint8_t* __restrict__ flag, const uint32_t* __restrict__ gw,
+                             uint32_t* __restrict__ inode, uint8_t* __restrict__ iflag, uint32_t* __restrict__ w) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j > m) return;
+  if (j == m) {
+    w[j] = 0;
+    return;
+  }
+  const uint32_t u = ord[apos[j]];
+  inode[j] = u;
+  iflag[j] = flag[apos[j]];
+  w[j] = gw[u];
+}
+// Final position of item j: its class start plus the weights of the items
+// before it in the class (W = exclusive scan of the weights; the first item
+// of j's class is j - (apos[j] - class start)). A frontier node goes there;
+// a representative leaves the position and its flag for its group.
+__global__ void items_place_k(const uint32_t* __restrict__ apos, uint32_t m, const uint32_t* __restrict__ inode,
+                              const uint8_t* __restrict__ iflag, const uint32_t* __restrict__ W,
+                              const int32_t* __restrict__ pid, const uint32_t* __restrict__ rtag, uint32_t tag,
+                              const int32_t* __restrict__ old_pid, uint32_t* __restrict__ ord,
+                              uint8_t* __restrict__ flag, uint32_t* __restrict__ xpos, uint8_t* __restrict__ xflag) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  const uint32_t u = inode[j];
+  const uint32_t c = uint32_t(pid[u]);
+  const uint32_t j0 = j - (apos[j] - c);
+  const uint32_t fp = c + (W[j] - W[j0]);
+  if (rtag[u] == tag) {
+    ord[fp] = u;
+    flag[fp] = iflag[j];
+  } else {
+    xpos[uint32_t(old_pid[u])] = fp;
+    xflag[uint32_t(old_pid[u])] = iflag[j];
+  }
+}
+// The groups: every U member of a re-ordered class at its representative's
+// position plus its rank in the group (stored order).
+__global__ void groups_place_k(const uint32_t* __restrict__ old_ord, const int32_t* __restrict__ old_pid, uint32_t n_o,
+                               const uint32_t* __restrict__ inU, const uint32_t* __restrict__ kus,
+                               const int32_t* __restrict__ pid, const uint32_t* __restrict__ dtag, uint32_t tag,
+                               const uint32_t* __restrict__ dsz, const uint32_t* __restrict__ xpos,
+                               const uint8_t* __restrict__ xflag, uint32_t* __restrict__ ord,
+                               uint8_t* __restrict__ flag) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_o || !inU[p]) return;
+  const uint32_t u = old_ord[p];
+  const uint32_t c = uint32_t(pid[u]);
+  if (dtag[c] != tag || dsz[c] < 2) return;
+  const uint32_t xs = uint32_t(old_pid[u]);
+  const uint32_t t = kus[p] - kus[xs];
+  const uint32_t dest = xpos[xs] + t;
+  ord[dest] = u;
+  flag[dest] = t == 0 ? xflag[xs] : 0;
 }
 
 // Old positions p of the stored round j whose node kept its class at level
@@ -423,16 +672,18 @@ __global__ void changed_k(const uint32_t* __restrict__ rlist, const uint32_t* __
                           const uint32_t* __restrict__ cont, uint32_t n_o, const int32_t* __restrict__ old_pid,
                           uint32_t* __restrict__ ctag, uint32_t tag, uint32_t* __restrict__ clist,
                           uint32_t* __restrict__ ccount) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  bool ch = false;
-  uint32_t u = 0;
-  if (i < *rcount) {
-    u = rlist[i];
-    ch = u >= n_o || actr[u] != act_tag || cont[uint32_t(pid[u])] != uint32_t(old_pid[u]);
-    if (ch) ctag[u] = tag;
+  const uint32_t n = *rcount;
+  KB_LIST_LOOP(i, n) {
+    bool ch = false;
+    uint32_t u = 0;
+    if (i < n) {
+      u = rlist[i];
+      ch = u >= n_o || actr[u] != act_tag || cont[uint32_t(pid[u])] != uint32_t(old_pid[u]);
+      if (ch) ctag[u] = tag;
+    }
+    const uint32_t slot = wave_append(ch, ccount);
+    if (ch) clist[slot] = u;
   }
-  const uint32_t slot = wave_append(ch, ccount);
-  if (ch) clist[slot] = u;
 }
 
 // Classes with two or more members whose members have out-edges (the
@@ -469,7 +720,7 @@ struct ClassSegWrite {
 // Re-ordered classes of level j - 1 (size >= 2) as segments.
 struct DirtySegOf {
   const uint32_t* dlist;
-  const uint32_t* dsize;
+  const uint32_t* dsize;  // 0 or 1: no segment
   uint32_t medium_cap, big_cap;
   __device__ __forceinline__ int operator()(uint32_t i) const {
     const uint32_t z = dsize[i];

@@ -668,7 +668,8 @@ void Engine::update_levels() {
   const int32_t K = rounds_;
   const uint32_t n_o = old_n_nodes_;
   uint32_t* hw = reinterpret_cast<uint32_t*>(hw_.p);
-  DevBuf cnt;  // [0] frontier, [1] classes, [2] members
+  // [0] frontier, [1] classes, [2] members, [3] items, [4..5] members of a full round (u64)
+  DevBuf cnt;
   cnt.ensure(32);
   uint32_t T_prev = utag_;
   // number of changed nodes of the level below, on the device; at level 0
@@ -678,71 +679,175 @@ void Engine::update_levels() {
   hw[0] = N - n_o;
   KB_CHECK(hipMemcpyAsync(nch.p, hw, 4, hipMemcpyHostToDevice, st_));
   KB_CHECK(hipStreamSynchronize(st_));
-  for (DevBuf* b : {&rlist_, &dlist_, &dsize_}) b->ensure(std::max<uint32_t>(N, 1) * 4);
-  kscan_.ensure((uint64_t(n_o) + 1) * 4);
-  keep_.ensure((uint64_t(n_o) + 1) * 4);
-  ufirst_.ensure(std::max<uint32_t>(N, 1) * 4);
+  const uint64_t N1 = std::max<uint32_t>(N, 1), O1 = uint64_t(n_o) + 1;
+  for (DevBuf* b : {&rlist_, &dlist_, &ufirst_, &fill_, &dszpos_, &gw_, &inode_}) b->ensure(N1 * 4);
+  for (DevBuf* b : {&dsize_, &isize_, &w_, &wscan_, &chunk_}) b->ensure((N1 + 1) * 4);
+  iflag_.ensure(N1);
+  for (DevBuf* b : {&keep_, &kscan_, &inu_, &kus_, &oflag_, &ocls_, &ofirst_, &xpos_}) b->ensure(O1 * 4);
+  xflag_.ensure(O1);
   const uint32_t med = std::min(medium_cap(), kMediumCapSmall), big = medium_cap();
   int32_t stop_at = -1;
+  bool switched = false;
   for (int32_t j = 1; j <= K; ++j) {
     const uint32_t T = ++utag_;
     KB_CHECK(hipMemsetAsync(cnt.p, 0, 32, st_));
     uint32_t* c = cnt.as<uint32_t>();
-    // frontier
-    const uint32_t waves = n_src_ + N;  // bound on listed nodes
-    if (adj64_)
-      frontier_k<uint64_t><<<std::min<uint32_t>(ceil_div(uint64_t(waves) * kWave, 256), 8192), 256, 0, st_>>>(
-          src_list_.as<uint32_t>(), n_src_, clist_.as<uint32_t>(), nch.as<uint32_t>(), rrowptr_.as<uint32_t>(),
-          radj_.as<uint64_t>(), dst_bits_, rtag_.as<uint32_t>(), T, rlist_.as<uint32_t>(), c);
-    else
-      frontier_k<uint32_t><<<std::min<uint32_t>(ceil_div(uint64_t(waves) * kWave, 256), 8192), 256, 0, st_>>>(
-          src_list_.as<uint32_t>(), n_src_, clist_.as<uint32_t>(), nch.as<uint32_t>(), rrowptr_.as<uint32_t>(),
-          radj_.as<uint32_t>(), dst_bits_, rtag_.as<uint32_t>(), T, rlist_.as<uint32_t>(), c);
+    // frontier: chunks of the changed nodes' sources, then one wave per item
+    frontier_chunks_k<<<grid_for(uint64_t(N) + 1), kNT, 0, st_>>>(clist_.as<uint32_t>(), nch.as<uint32_t>(),
+                                                                  rrowptr_.as<uint32_t>(), chunk_.as<uint32_t>());
     KB_LAUNCH_CHECK();
-    // classes of level j - 1
+    scan_dev<uint32_t, uint32_t, false>(chunk_.as<uint32_t>(), chunk_.as<uint32_t>(), uint64_t(N) + 1);
+    const uint32_t fgrid = 2048;
+    if (adj64_)
+      frontier_k<uint64_t><<<fgrid, 256, 0, st_>>>(src_list_.as<uint32_t>(), n_src_, clist_.as<uint32_t>(),
+                                                   nch.as<uint32_t>(), chunk_.as<uint32_t>(), rrowptr_.as<uint32_t>(),
+                                                   radj_.as<uint64_t>(), dst_bits_, rtag_.as<uint32_t>(), T,
+                                                   rlist_.as<uint32_t>(), c);
+    else
+      frontier_k<uint32_t><<<fgrid, 256, 0, st_>>>(src_list_.as<uint32_t>(), n_src_, clist_.as<uint32_t>(),
+                                                   nch.as<uint32_t>(), chunk_.as<uint32_t>(), rrowptr_.as<uint32_t>(),
+                                                   radj_.as<uint32_t>(), dst_bits_, rtag_.as<uint32_t>(), T,
+                                                   rlist_.as<uint32_t>(), c);
+    KB_LAUNCH_CHECK();
+    // classes of level j - 1 that hold the frontier
     class_scan();
     class_starts_k<<<grid_for(N), kNT, 0, st_>>>(flag_.as<uint8_t>(), cls_.as<uint32_t>(), N, ufirst_.as<uint32_t>());
     KB_LAUNCH_CHECK();
-    dirty_classes_k<<<grid_for(N), kNT, 0, st_>>>(rlist_.as<uint32_t>(), c, pid_.as<int32_t>(), dtag_.as<uint32_t>(), T,
+    dirty_classes_k<<<std::min<uint32_t>(grid_for(N), kListGrid), kNT, 0, st_>>>(rlist_.as<uint32_t>(), c, pid_.as<int32_t>(), dtag_.as<uint32_t>(), T,
                                                  dlist_.as<uint32_t>(), c + 1);
     KB_LAUNCH_CHECK();
-    dirty_sizes_k<<<grid_for(N), kNT, 0, st_>>>(dlist_.as<uint32_t>(), c + 1, cls_.as<uint32_t>(),
-                                               ufirst_.as<uint32_t>(), N, dsize_.as<uint32_t>(), c + 2);
+    dirty_sizes_k<<<std::min<uint32_t>(grid_for(N), kListGrid), kNT, 0, st_>>>(dlist_.as<uint32_t>(), c + 1, cls_.as<uint32_t>(),
+                                               ufirst_.as<uint32_t>(), N, dsize_.as<uint32_t>(),
+                                               dszpos_.as<uint32_t>(), fill_.as<uint32_t>(), c + 2);
     KB_LAUNCH_CHECK();
-    KB_CHECK(hipMemcpyAsync(hw, c, 16, hipMemcpyDeviceToHost, st_));
-    KB_CHECK(hipMemcpyAsync(hw + 4, cls_.as<uint32_t>() + (N - 1), 4, hipMemcpyDeviceToHost, st_));
-    KB_CHECK(hipMemcpyAsync(hw + 5, nch.p, 4, hipMemcpyDeviceToHost, st_));
+    multi_members_k<<<std::min<uint32_t>(grid_for(N), 2048), kNT, 0, st_>>>(flag_.as<uint8_t>(), N,
+                                                 reinterpret_cast<unsigned long long*>(c + 4));
+    KB_LAUNCH_CHECK();
+    KB_CHECK(hipMemcpyAsync(hw, c, 24, hipMemcpyDeviceToHost, st_));
+    KB_CHECK(hipMemcpyAsync(hw + 6, cls_.as<uint32_t>() + (N - 1), 4, hipMemcpyDeviceToHost, st_));
+    KB_CHECK(hipMemcpyAsync(hw + 7, nch.p, 4, hipMemcpyDeviceToHost, st_));
     KB_CHECK(hipStreamSynchronize(st_));
-    const uint32_t nr = hw[0], nd = hw[1], members = hw[2], B_prev = hw[4];
-    if (j > 1) ustat_.changed += hw[5];
+    const uint32_t nr = hw[0], nd = hw[1], members = hw[2], B_prev = hw[6];
+    uint64_t full_members = 0;
+    std::memcpy(&full_members, hw + 4, 8);
+    if (j > 1) ustat_.changed += hw[7];
     if (j - 1 >= 1) counts_.push_back(int64_t(B_prev));
     if (opt_.early_stop && j - 1 >= 1 && counts_[size_t(j - 1)] == counts_[size_t(j - 2)]) {
       stop_at = j - 1;
       break;
     }
-    ustat_.rechecked += nr;
-    ustat_.recomputed += members;
-    ustat_.levels = j;
-    // re-ordered classes
-    KB_CHECK(hipMemsetAsync(act_.size.p, 0, (uint64_t(nd) + 1) * 4, st_));
-    uint32_t* info = info_.as<uint32_t>();
-    compact<kSegClasses>(DirtySegOf{dlist_.as<uint32_t>(), dsize_.as<uint32_t>(), med, big},
-                         DirtySegWrite{dlist_.as<uint32_t>(), dsize_.as<uint32_t>(), act_.start.as<uint32_t>(),
-                                       act_.size.as<uint32_t>(), act_.depth.as<uint32_t>()},
-                         nd, nullptr, compact_scratch(compact_part_words<kSegClasses>(std::max<uint32_t>(nd, 1))),
-                         info + kInfoSeg, st_);
-    large_offsets(act_, info + kInfoSeg, info + kInfoLargeItems, members);
-    prepare_active(nd, members, tag_ + 1, true);
-    if (M_act_ > 0) round_impl<AdjT, KeyT>(false);
-    // the other classes split as stored
+    // Switch back to Algorithm 1 (Section 4, "When to switch back"): when
+    // the frontier, or below the frontier and the items to re-order, outnumber
+    // the nodes a full round would compute, the remaining rounds run in full
+    // from this level (checked first on the frontier alone, before the
+    // passes over the stored round).
+    // Cost model: a level by level round pays about 0.45 node-passes over
+    // all N nodes (the stored round's order, its scans and copies) plus about
+    // two node-costs per frontier node and per item; a full round pays one
+    // per member of a class with two or more members (measured on the
+    // 10M-node power-law graph: 1.8 ms of passes per level, 0.4 ns per node of
+    // a full round).
+    const uint64_t fixed_cost = uint64_t(N) * 9 / 20;
+    auto go_full = [&](uint64_t work) {
+      if (opt_.update_mode == 1) return false;
+      if (opt_.update_mode == 2) return true;
+      return fixed_cost + 2 * work > full_members;
+    };
+    if (go_full(nr)) {
+      stop_at = j - 1;
+      switched = true;
+      ustat_.full_from = j;
+      break;
+    }
+    // the stored round j: frontier membership, kept classes, class starts
     old_ord_.swap(hist_[size_t(j)].ord);
     old_pid_.swap(hist_[size_t(j)].pid);
     if (n_o) {
-      keep_flags_k<<<grid_for(n_o), kNT, 0, st_>>>(old_ord_.as<uint32_t>(), n_o, ctag_.as<uint32_t>(), T_prev,
-                                                   keep_.as<uint32_t>());
+      old_flags_k<<<grid_for(n_o), kNT, 0, st_>>>(old_ord_.as<uint32_t>(), old_pid_.as<int32_t>(), n_o,
+                                                  rtag_.as<uint32_t>(), T, ctag_.as<uint32_t>(), T_prev,
+                                                  inu_.as<uint32_t>(), keep_.as<uint32_t>(), oflag_.as<uint32_t>());
       KB_LAUNCH_CHECK();
+      KB_CHECK(hipMemsetAsync(inu_.as<uint32_t>() + n_o, 0, 4, st_));
       KB_CHECK(hipMemsetAsync(keep_.as<uint32_t>() + n_o, 0, 4, st_));
-      scan_dev<uint32_t, uint32_t, false>(keep_.as<uint32_t>(), kscan_.as<uint32_t>(), uint64_t(n_o) + 1);
+      scan_dev<uint32_t, uint32_t, false>(inu_.as<uint32_t>(), kus_.as<uint32_t>(), O1);
+      scan_dev<uint32_t, uint32_t, false>(keep_.as<uint32_t>(), kscan_.as<uint32_t>(), O1);
+      scan_dev<uint32_t, uint32_t, true>(oflag_.as<uint32_t>(), ocls_.as<uint32_t>(), n_o);
+      old_starts_k<<<grid_for(n_o), kNT, 0, st_>>>(oflag_.as<uint32_t>(), ocls_.as<uint32_t>(), n_o,
+                                                   ofirst_.as<uint32_t>());
+      KB_LAUNCH_CHECK();
+    }
+    // items of the re-ordered classes (counted only: the partition of level
+    // j - 1 stays intact until the choice below)
+    auto items = [&](bool place) {
+      items_frontier_k<<<std::min<uint32_t>(grid_for(N), kListGrid), kNT, 0, st_>>>(rlist_.as<uint32_t>(), c, pid_.as<int32_t>(),
+                                                    dszpos_.as<uint32_t>(), fill_.as<uint32_t>(), place,
+                                                    ord_.as<uint32_t>(), gw_.as<uint32_t>());
+      KB_LAUNCH_CHECK();
+      if (n_o) {
+        items_reps_k<<<grid_for(n_o), kNT, 0, st_>>>(old_ord_.as<uint32_t>(), old_pid_.as<int32_t>(), n_o,
+                                                     inu_.as<uint32_t>(), kus_.as<uint32_t>(), ocls_.as<uint32_t>(),
+                                                     ofirst_.as<uint32_t>(), pid_.as<int32_t>(), dtag_.as<uint32_t>(), T,
+                                                     dszpos_.as<uint32_t>(), fill_.as<uint32_t>(), place,
+                                                     ord_.as<uint32_t>(), gw_.as<uint32_t>());
+        KB_LAUNCH_CHECK();
+      }
+    };
+    items(false);
+    item_sizes_k<<<std::min<uint32_t>(grid_for(N), kListGrid), kNT, 0, st_>>>(dlist_.as<uint32_t>(), c + 1, dszpos_.as<uint32_t>(),
+                                              fill_.as<uint32_t>(), isize_.as<uint32_t>(), c + 3);
+    KB_LAUNCH_CHECK();
+    KB_CHECK(hipMemcpyAsync(hw, c + 3, 4, hipMemcpyDeviceToHost, st_));
+    KB_CHECK(hipStreamSynchronize(st_));
+    const uint32_t n_items = hw[0];
+    if (go_full(uint64_t(nr) + uint64_t(n_items))) {
+      stop_at = j - 1;
+      switched = true;
+      ustat_.full_from = j;
+      break;
+    }
+    ustat_.rechecked += nr;
+    ustat_.recomputed += n_items;
+    ustat_.levels = j;
+    // re-ordered classes: segments of their items
+    KB_CHECK(hipMemsetAsync(act_.size.p, 0, (uint64_t(nd) + 1) * 4, st_));
+    uint32_t* info = info_.as<uint32_t>();
+    compact<kSegClasses>(DirtySegOf{dlist_.as<uint32_t>(), isize_.as<uint32_t>(), med, big},
+                         DirtySegWrite{dlist_.as<uint32_t>(), isize_.as<uint32_t>(), act_.start.as<uint32_t>(),
+                                       act_.size.as<uint32_t>(), act_.depth.as<uint32_t>()},
+                         nd, nullptr, compact_scratch(compact_part_words<kSegClasses>(std::max<uint32_t>(nd, 1))),
+                         info + kInfoSeg, st_);
+    large_offsets(act_, info + kInfoSeg, info + kInfoLargeItems, n_items);
+    items(true);
+    prepare_active(nd, n_items, tag_ + 1, true);
+    const uint32_t M_items = M_act_;
+    if (M_items > 0) {
+      // level 1 keys from the dense label ranks (narrow, as in a first
+      // round: they order exactly as the level-0 class positions)
+      round_impl<AdjT, KeyT>(j == 1);
+      // expand: items to their final positions, groups behind their representatives
+      items_read_k<<<grid_for(uint64_t(M_items) + 1), kNT, 0, st_>>>(apos_.as<uint32_t>(), M_items, ord_.as<uint32_t>(),
+                                                                     flag_.as<uint8_t>(), gw_.as<uint32_t>(),
+                                                                     inode_.as<uint32_t>(), iflag_.as<uint8_t>(),
+                                                                     w_.as<uint32_t>());
+      KB_LAUNCH_CHECK();
+      scan_dev<uint32_t, uint32_t, false>(w_.as<uint32_t>(), wscan_.as<uint32_t>(), uint64_t(M_items) + 1);
+      items_place_k<<<grid_for(M_items), kNT, 0, st_>>>(apos_.as<uint32_t>(), M_items, inode_.as<uint32_t>(),
+                                                        iflag_.as<uint8_t>(), wscan_.as<uint32_t>(), pid_.as<int32_t>(),
+                                                        rtag_.as<uint32_t>(), T, old_pid_.as<int32_t>(),
+                                                        ord_.as<uint32_t>(), flag_.as<uint8_t>(), xpos_.as<uint32_t>(),
+                                                        xflag_.as<uint8_t>());
+      KB_LAUNCH_CHECK();
+      if (n_o) {
+        groups_place_k<<<grid_for(n_o), kNT, 0, st_>>>(old_ord_.as<uint32_t>(), old_pid_.as<int32_t>(), n_o,
+                                                       inu_.as<uint32_t>(), kus_.as<uint32_t>(), pid_.as<int32_t>(),
+                                                       dtag_.as<uint32_t>(), T, dszpos_.as<uint32_t>(),
+                                                       xpos_.as<uint32_t>(), xflag_.as<uint8_t>(), ord_.as<uint32_t>(),
+                                                       flag_.as<uint8_t>());
+        KB_LAUNCH_CHECK();
+      }
+    }
+    // the other classes split as stored
+    if (n_o) {
       copy_split_k<<<grid_for(n_o), kNT, 0, st_>>>(old_ord_.as<uint32_t>(), n_o, keep_.as<uint32_t>(),
                                                    kscan_.as<uint32_t>(), old_prev_pid_.as<int32_t>(),
                                                    old_pid_.as<int32_t>(), dtag_.as<uint32_t>(), T,
@@ -751,21 +856,28 @@ void Engine::update_levels() {
     }
     cls_round_ = -1;
     dense_round_ = -1;
-    // ids of the re-ordered classes and change detection
-    const uint32_t M = M_act_;
-    if (M > 0) {
-      assign_ids();
-      cont_reset_k<<<grid_for(M), kNT, 0, st_>>>(apos_.as<uint32_t>(), M, cont_.as<uint32_t>());
+    // ids of the re-ordered classes (all their positions) and change detection
+    if (members > 0) {
+      KB_CHECK(hipMemsetAsync(dsize_.as<uint32_t>() + nd, 0, 4, st_));
+      scan_dev<uint32_t, uint32_t, false>(dsize_.as<uint32_t>(), soff_.as<uint32_t>(), uint64_t(nd) + 1);
+      expand_k<<<std::max<uint32_t>(1, ceil_div(members, kExpandTile)), 256, 0, st_>>>(
+          dlist_.as<uint32_t>(), soff_.as<uint32_t>(), c + 1, members, ord_.as<uint32_t>(), apos_.as<uint32_t>(),
+          anode_.as<uint32_t>(), nullptr, 0u, info);
       KB_LAUNCH_CHECK();
-      cont_set_k<<<grid_for(M), kNT, 0, st_>>>(apos_.as<uint32_t>(), M, ord_.as<uint32_t>(), pid_.as<int32_t>(),
-                                               rtag_.as<uint32_t>(), T, n_o, old_pid_.as<int32_t>(),
-                                               cont_.as<uint32_t>());
+      M_act_ = members;
+      assign_ids();
+      cont_reset_k<<<grid_for(members), kNT, 0, st_>>>(apos_.as<uint32_t>(), members, cont_.as<uint32_t>());
+      KB_LAUNCH_CHECK();
+      cont_set_k<<<grid_for(members), kNT, 0, st_>>>(apos_.as<uint32_t>(), members, ord_.as<uint32_t>(),
+                                                     pid_.as<int32_t>(), rtag_.as<uint32_t>(), T, n_o,
+                                                     old_pid_.as<int32_t>(), cont_.as<uint32_t>());
       KB_LAUNCH_CHECK();
     }
     KB_CHECK(hipMemsetAsync(nch.p, 0, 4, st_));
-    changed_k<<<grid_for(std::max<uint32_t>(nr, 1)), kNT, 0, st_>>>(
-        rlist_.as<uint32_t>(), c, actr_.as<uint32_t>(), M > 0 ? tag_ : kNoneU32, pid_.as<int32_t>(), cont_.as<uint32_t>(),
-        n_o, old_pid_.as<int32_t>(), ctag_.as<uint32_t>(), T, clist_.as<uint32_t>(), nch.as<uint32_t>());
+    changed_k<<<std::min<uint32_t>(grid_for(std::max<uint32_t>(nr, 1)), kListGrid), kNT, 0, st_>>>(
+        rlist_.as<uint32_t>(), c, actr_.as<uint32_t>(), M_items > 0 ? tag_ : kNoneU32, pid_.as<int32_t>(),
+        cont_.as<uint32_t>(), n_o, old_pid_.as<int32_t>(), ctag_.as<uint32_t>(), T, clist_.as<uint32_t>(),
+        nch.as<uint32_t>());
     KB_LAUNCH_CHECK();
     save_level(j);
     old_prev_pid_.swap(old_pid_);
@@ -785,7 +897,7 @@ void Engine::update_levels() {
   hist_.resize(size_t(last) + 1);
   counts_.resize(size_t(last) + 1);
   B_ = counts_.back();
-  fixed_ = last >= 1 && counts_[size_t(last)] == counts_[size_t(last) - 1];
+  fixed_ = !switched && last >= 1 && counts_[size_t(last)] == counts_[size_t(last) - 1];
   cls_round_ = -1;
   dense_round_ = -1;
 }

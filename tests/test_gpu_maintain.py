@@ -73,14 +73,19 @@ def test_history_needs_option():
         assert e.value.status == -4
 
 
+MODES = [0, 1, 2]  # rounds of an update: by cost, level by level, in full
+
+
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("early_stop,k", [(False, 2), (True, 10)])
-def test_update_tables_4_and_5(early_stop, k):
+def test_update_tables_4_and_5(early_stop, k, mode):
     """Section 4's example run: Figure 1 plus node 7 and (2,l,7) (Table 4),
     and plus (6,l,5) (Table 5)."""
     torch, kb = need_gpu()
     g = graph_of(load("figure1.json"))
     for upd in (dict(new_labels=[1], add=([1], [1], [6])), dict(add=([5], [1], [4]))):
-        with kb.Graph(g.num_nodes, g.node_label, g.src, g.elab, g.dst, history=True, early_stop=early_stop) as h:
+        with kb.Graph(g.num_nodes, g.node_label, g.src, g.elab, g.dst, history=True, early_stop=early_stop,
+                      update_mode=mode) as h:
             h.refine(k)
             h.update(**upd)
             cur = M.updated_graph(*cur_of(g), **upd)
@@ -105,8 +110,9 @@ def random_gpu_update(rng, cur, n_labels, e_labels, allow_nodes=True):
                                                        rng.integers(0, n, m))))
 
 
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("seed", range(12))
-def test_update_random_small(seed):
+def test_update_random_small(seed, mode):
     torch, kb = need_gpu()
     rng = np.random.default_rng(1000 + seed)
     early_stop = bool(seed % 2)
@@ -114,7 +120,7 @@ def test_update_random_small(seed):
     g = synth.random_small_graph(rng, int(rng.integers(4, 40)), int(rng.integers(0, 120)), 3, 3)
     cur = cur_of(g)
     say("seed %d: N=%d E=%d k=%d early_stop=%s" % (seed, cur[0], cur[2].shape[0], k, early_stop))
-    with kb.Graph(cur[0], *cur[1:], history=True, early_stop=early_stop) as h:
+    with kb.Graph(cur[0], *cur[1:], history=True, early_stop=early_stop, update_mode=mode) as h:
         h.refine(k)
         check_against(h, cur, k, early_stop, "initial")
         for step in range(6):
@@ -124,8 +130,9 @@ def test_update_random_small(seed):
             check_against(h, cur, k, early_stop, "step %d %s" % (step, sorted(upd)))
 
 
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("m", [1, 100, 10000])
-def test_update_powerlaw_200k(m):
+def test_update_powerlaw_200k(m, mode):
     """Edge insertions and deletions on a 200k-node / 2M-edge power-law
     graph (device inputs), every round against the oracle."""
     torch, kb = need_gpu()
@@ -133,7 +140,7 @@ def test_update_powerlaw_200k(m):
     rng = np.random.default_rng(m)
     cur = cur_of(g)
     dev = torch.device("cuda:0")
-    with kb.Graph(g.num_nodes, *to_dev(torch, g), history=True) as h:
+    with kb.Graph(g.num_nodes, *to_dev(torch, g), history=True, update_mode=mode) as h:
         h.refine(10)
         add = tuple(x.astype(np.int32) for x in (rng.integers(0, g.num_nodes, m), rng.integers(0, 8, m),
                                                  rng.integers(0, g.num_nodes, m)))
@@ -149,7 +156,8 @@ def test_update_powerlaw_200k(m):
         check_against(h, cur, 10, True, "delete %d" % m)
 
 
-def test_update_new_label_values():
+@pytest.mark.parametrize("mode", MODES)
+def test_update_new_label_values(mode):
     """New node label values below, between and above the old ones, and new
     edge label values: level 0 and the edge encoding are re-ranked."""
     torch, kb = need_gpu()
@@ -158,7 +166,7 @@ def test_update_new_label_values():
     lab = (np.asarray(g.node_label) * 10 + 5).astype(np.int32)  # 5, 15, 25
     el = (np.asarray(g.elab) * 10 + 5).astype(np.int32)
     cur = (g.num_nodes, lab, np.asarray(g.src, np.int32), el, np.asarray(g.dst, np.int32))
-    with kb.Graph(cur[0], *cur[1:], history=True) as h:
+    with kb.Graph(cur[0], *cur[1:], history=True, update_mode=mode) as h:
         h.refine(8)
         for upd in (dict(new_labels=np.array([0, 10, 40, 15], np.int32)),
                     dict(add=(np.array([0, 31, 2], np.int32), np.array([1, 26, 99], np.int32),
@@ -186,13 +194,14 @@ def test_update_invalid_leaves_state():
         check_against(h, cur, 10, True, "absent triple")
 
 
-def test_update_moves_fixed_point():
+@pytest.mark.parametrize("mode", MODES)
+def test_update_moves_fixed_point(mode):
     """A path of 3 edges reaches its fixed point at round 4; extending it by
     3 more edges needs rounds 5..7 (up to the k asked before)."""
     torch, kb = need_gpu()
     g = synth.path_graph(3)
     cur = cur_of(g)
-    with kb.Graph(g.num_nodes, g.node_label, g.src, g.elab, g.dst, history=True) as h:
+    with kb.Graph(g.num_nodes, g.node_label, g.src, g.elab, g.dst, history=True, update_mode=mode) as h:
         h.refine(20)
         assert h.rounds_done == 4
         upd = dict(new_labels=[0, 0, 0], add=([3, 4, 5], [0, 0, 0], [4, 5, 6]))
@@ -200,3 +209,47 @@ def test_update_moves_fixed_point():
         cur = M.updated_graph(*cur, **upd)
         check_against(h, cur, 20, True, "longer path")
         assert h.rounds_done == 7
+
+
+def test_dbest_no_change():
+    """Dbest (Section 5.3): a full tree with one node and one edge label; an
+    edge from a parent of leaves to another leaf changes no signature, so no
+    id changes, and the update stays level by level (no full round)."""
+    torch, kb = need_gpu()
+    g = synth.tree_graph(3, 5)
+    cur = cur_of(g)
+    n = g.num_nodes
+    leaves0 = n - 3 ** 5
+    parent_of_leaves = (leaves0 - 1) // 3  # the parent of the first leaf
+    other_leaf = n - 1  # a leaf under another parent
+    with kb.Graph(n, *cur[1:], history=True) as h:
+        h.refine(10)
+        before = [h.result_round(j)[0] for j in range(h.rounds_done + 1)]
+        upd = dict(add=([parent_of_leaves], [0], [other_leaf]))
+        h.update(**upd)
+        cur = M.updated_graph(*cur, **upd)
+        check_against(h, cur, 10, True, "dbest")
+        after = [h.result_round(j)[0] for j in range(h.rounds_done + 1)]
+        assert all(np.array_equal(a, b) for a, b in zip(before, after))
+        levels, full_from, rechecked, recomputed, changed = h.update_stats()
+        say("dbest: levels %d full_from %d rechecked %d recomputed %d changed %d" %
+            (levels, full_from, rechecked, recomputed, changed))
+        assert full_from == 0 and levels == h.rounds_done
+
+
+def test_dworst_all_change():
+    """Dworst (Section 5.3): a complete graph with all edges x plus one
+    y-edge to a new isolated node: every node's signature changes; the
+    update's result is still exact (B = [1, 3, 3])."""
+    torch, kb = need_gpu()
+    g = synth.complete_graph(40)
+    cur = cur_of(g)
+    with kb.Graph(g.num_nodes, *cur[1:], history=True, update_mode=1) as h:
+        h.refine(10)
+        upd = dict(new_labels=[0], add=([0], [1], [40]))
+        h.update(**upd)
+        cur = M.updated_graph(*cur, **upd)
+        check_against(h, cur, 10, True, "dworst")
+        _, _, counts = h.result()
+        assert counts == [1, 3, 3]
+        say("dworst: stats %s" % (h.update_stats(),))
