@@ -360,6 +360,98 @@ def bench_batched(args, torch, kb, dev):
     print(json.dumps(line), flush=True)
 
 
+def bench_update_extreme(args, torch, kb, dev):
+    """The two extreme cases of Section 5.3 at about 100M edges, one edge
+    added, k = 10: Dbest, a full 10-ary tree of height 8 (one node and one
+    edge label) and an edge from a parent of leaves to a leaf of another
+    parent (no signature changes); Dworst, the complete graph on 10,000
+    nodes (edges labelled x) and an edge labelled y from node 0 to a new
+    isolated node (every signature changes). The update against a rebuild
+    of the updated graph (plain job), ids compared bit for bit."""
+    import numpy as np
+    import synth
+    k = 10
+    if args.workload == "dbest-100M":
+        g = synth.tree_graph(10, 8)
+        n = g.num_nodes
+        leaves0 = n - 10 ** 8
+        upd = dict(add=(np.array([(leaves0 - 1) // 10], np.int32), np.array([0], np.int32),
+                        np.array([n - 1], np.int32)))
+        new_labels = None
+    else:
+        g = synth.complete_graph(10_000)
+        n = g.num_nodes
+        upd = dict(new_labels=np.array([0], np.int32),
+                   add=(np.array([0], np.int32), np.array([1], np.int32), np.array([n], np.int32)))
+        new_labels = upd["new_labels"]
+    log("%s: N=%d E=%d" % (args.workload, g.num_nodes, g.num_edges))
+    arrs = [torch.from_numpy(np.ascontiguousarray(a, np.int32)).to(dev) for a in (g.node_label, g.src, g.elab, g.dst)]
+    stream = torch.cuda.current_stream()
+    # the updated graph, for the rebuild
+    lab2 = np.concatenate([g.node_label, new_labels]) if new_labels is not None else g.node_label
+    n2 = lab2.shape[0]
+    up = [torch.from_numpy(np.ascontiguousarray(a, np.int32)).to(dev) for a in upd["add"]]
+    arrs2 = [torch.from_numpy(np.ascontiguousarray(lab2, np.int32)).to(dev)] + \
+        [torch.cat([a, b]) for a, b in zip(arrs[1:], up)]
+    out_r = torch.empty(n2, dtype=torch.int32, device=dev)
+    out_u = torch.empty(n2, dtype=torch.int32, device=dev)
+
+    def rebuild():
+        h = kb.kbisim_create(n2, *arrs2, stream=stream)
+        try:
+            rd = kb.kbisim_refine(h, k)
+            kb.kbisim_result(h, out_r)
+        finally:
+            kb.kbisim_destroy(h)
+        return rd
+
+    rebuild()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(max(args.steps, 1)):
+        t0 = time.perf_counter()
+        rd_r = rebuild()
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    t_rebuild = float(np.median(ts))
+    rows = []
+    nl_dev = torch.from_numpy(upd["new_labels"]).to(dev) if "new_labels" in upd else None
+    for mode in (0, 1, 2):
+        tu = []
+        for rep in range(max(args.steps, 1) + 1):
+            h = kb.kbisim_create(n, *arrs, stream=stream, history=True, update_mode=mode)
+            try:
+                rd0 = kb.kbisim_refine(h, k)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                rd1 = kb.kbisim_update(h, new_labels=nl_dev, add=tuple(up))
+                torch.cuda.synchronize()
+                if rep:
+                    tu.append((time.perf_counter() - t0) * 1e3)
+                stats = kb.kbisim_update_stats(h)
+                kb.kbisim_result(h, out_u)
+            finally:
+                kb.kbisim_destroy(h)
+        same = bool(torch.equal(out_u, out_r)) and rd1 == rd_r
+        rows.append({"update_mode": ["by cost", "level by level", "full rounds"][mode],
+                     "update_ms": float(np.median(tu)), "speedup_vs_rebuild": t_rebuild / float(np.median(tu)),
+                     "rounds": rd1, "levels": stats[0], "full_rounds_from": stats[1], "rechecked": stats[2],
+                     "recomputed": stats[3], "changed": stats[4], "identical_to_rebuild": same})
+        log("%s mode %d: update %.2f ms vs rebuild %.2f ms, stats %s, identical %s" % (
+            args.workload, mode, rows[-1]["update_ms"], t_rebuild, stats, same))
+    line = {
+        "metric": "Add_Edges time vs rebuild (ms), %s, one edge added" % args.workload,
+        "value": rows[0]["update_ms"], "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": rows[0]["update_ms"], "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": args.workload, "num_nodes": g.num_nodes, "num_edges": g.num_edges, "k": k,
+                   "rounds": rd_r},
+        "rebuild_ms": t_rebuild, "modes": rows,
+        "identical_to_rebuild": all(r["identical_to_rebuild"] for r in rows),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def bench_update(args, torch, kb, dev):
     """Add_Edges against a rebuild (the paper's multiple-edge experiment,
     Section 5.3): for each batch size m, m edges drawn at random from the
@@ -369,6 +461,8 @@ def bench_update(args, torch, kb, dev):
     refine, result) on the whole graph, with and without the history."""
     import numpy as np
     import synth
+    if args.workload in ("dbest-100M", "dworst-100M"):
+        return bench_update_extreme(args, torch, kb, dev)
     g, k_default = synth.make_config(args.workload, seed=args.seed, progress=log)
     k = args.k if args.k is not None else k_default
     arrs = [torch.from_numpy(a).to(dev) for a in (g.node_label, g.src, g.elab, g.dst)]
