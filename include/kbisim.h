@@ -148,9 +148,13 @@ kbisim_status kbisim_result_round(const kbisim_graph* g, int32_t round, int32_t*
 /* One change to the graph of a handle (Section 4, maintenance), applied in
  * this order: new isolated nodes appended (Algorithm 2, Add_Nodes; ids N,
  * N+1, ...), then deletions of edge triples (every copy of each triple goes;
- * triples not in the graph are ignored), then additions of edge triples
- * (Algorithm 3, Add_Edges; endpoints may be the new nodes). All arrays are
- * in `mem` and read during the call. */
+ * triples not in the graph are ignored), then deletions of nodes (Section 4,
+ * "Deletions": with all their incoming and outgoing edges; the remaining
+ * nodes keep their order and are renumbered 0, 1, ...; ids refer to the
+ * numbering after the new nodes, duplicates allowed), then additions of edge
+ * triples (Algorithm 3, Add_Edges; endpoints in the numbering after the node
+ * deletions, may be new nodes). All arrays are in `mem` and read during the
+ * call. */
 typedef struct {
   int64_t num_new_nodes;          /* >= 0 */
   const int32_t* new_node_label;  /* [num_new_nodes], values >= 0 */
@@ -158,6 +162,8 @@ typedef struct {
   const int32_t* del_src;         /* [num_del_edges] each */
   const int32_t* del_label;
   const int32_t* del_dst;
+  int64_t num_del_nodes;          /* >= 0 */
+  const int32_t* del_nodes;       /* [num_del_nodes] */
   int64_t num_add_edges;          /* >= 0 */
   const int32_t* add_src;         /* [num_add_edges] each */
   const int32_t* add_label;

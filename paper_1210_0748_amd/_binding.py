@@ -42,6 +42,7 @@ class UpdateDesc(ctypes.Structure):
     _fields_ = [("num_new_nodes", ctypes.c_int64), ("new_node_label", ctypes.c_void_p),
                 ("num_del_edges", ctypes.c_int64), ("del_src", ctypes.c_void_p),
                 ("del_label", ctypes.c_void_p), ("del_dst", ctypes.c_void_p),
+                ("num_del_nodes", ctypes.c_int64), ("del_nodes", ctypes.c_void_p),
                 ("num_add_edges", ctypes.c_int64), ("add_src", ctypes.c_void_p),
                 ("add_label", ctypes.c_void_p), ("add_dst", ctypes.c_void_p),
                 ("mem", ctypes.c_int)]
@@ -242,12 +243,14 @@ def kbisim_result_round(handle, round_, pid_out=None):
     return int(nb.value)
 
 
-def kbisim_update(handle, *, new_labels=None, delete=None, add=None):
+def kbisim_update(handle, *, new_labels=None, delete=None, delete_nodes=None, add=None):
     """Applies one update (see kbisim.h): new_labels (new nodes), delete and
-    add as (src, label, dst) triples of arrays; numpy (host) or torch CUDA
-    int32 tensors (device), all of one kind. Returns rounds done."""
+    add as (src, label, dst) triples of arrays, delete_nodes (node ids);
+    numpy (host) or torch CUDA int32 tensors (device), all of one kind.
+    Returns rounds done."""
     parts = []
-    for a in ([new_labels] if new_labels is not None else []) + list(delete or ()) + list(add or ()):
+    for a in ([new_labels] if new_labels is not None else []) + list(delete or ()) + list(add or ()) + \
+            ([delete_nodes] if delete_nodes is not None else []):
         parts.append(a)
     is_dev = False
     try:
@@ -273,10 +276,11 @@ def kbisim_update(handle, *, new_labels=None, delete=None, add=None):
     n_new, p_new = arr(new_labels)
     d = [arr(x) for x in (delete if delete is not None else (None, None, None))]
     a = [arr(x) for x in (add if add is not None else (None, None, None))]
+    n_dn, p_dn = arr(delete_nodes)
     if len({x[0] for x in d}) > 1 or len({x[0] for x in a}) > 1:
         raise KbisimError(-1, "edge arrays of different lengths")
-    desc = UpdateDesc(n_new, p_new, d[0][0], d[0][1], d[1][1], d[2][1], a[0][0], a[0][1], a[1][1], a[2][1],
-                      KBISIM_MEM_DEVICE if is_dev else KBISIM_MEM_HOST)
+    desc = UpdateDesc(n_new, p_new, d[0][0], d[0][1], d[1][1], d[2][1], n_dn, p_dn, a[0][0], a[0][1], a[1][1],
+                      a[2][1], KBISIM_MEM_DEVICE if is_dev else KBISIM_MEM_HOST)
     rd = ctypes.c_int32(0)
     _check(load_library().kbisim_update(handle, ctypes.byref(desc), ctypes.byref(rd)))
     return int(rd.value)
@@ -384,11 +388,15 @@ class Graph:
         nb = kbisim_result_round(self._h, round_, out)
         return out, nb
 
-    def update(self, *, new_labels=None, delete=None, add=None):
+    def update(self, *, new_labels=None, delete=None, delete_nodes=None, add=None):
         """Applies an update (history option); returns rounds done."""
-        self.rounds_done = kbisim_update(self._h, new_labels=new_labels, delete=delete, add=add)
+        self.rounds_done = kbisim_update(self._h, new_labels=new_labels, delete=delete, delete_nodes=delete_nodes,
+                                         add=add)
         if new_labels is not None:
             self.num_nodes += int(len(new_labels))
+        if delete_nodes is not None and len(delete_nodes):
+            self.num_nodes -= int(np.unique(np.asarray(
+                delete_nodes.cpu() if hasattr(delete_nodes, "cpu") else delete_nodes)).size)
         return self.rounds_done
 
     def update_stats(self):

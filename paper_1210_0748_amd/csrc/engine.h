@@ -101,7 +101,9 @@ struct UpdateArgs {
   const int32_t* new_label = nullptr;
   int64_t m_del = 0;
   const int32_t *del_src = nullptr, *del_lab = nullptr, *del_dst = nullptr;
-  int64_t m_add = 0;
+  int64_t n_del = 0;  // nodes deleted (ids after the new nodes), with all their edges
+  const int32_t* del_nodes = nullptr;
+  int64_t m_add = 0;  // endpoints in the numbering after the node deletions
   const int32_t *add_src = nullptr, *add_lab = nullptr, *add_dst = nullptr;
 };
 
@@ -159,6 +161,7 @@ class Engine {
   // stored round up to date, then continues to the round target when the
   // fixed point moved. Needs the history option.
   void update(const UpdateArgs& u);
+  void update_core(const UpdateArgs& u);
   const UpdateStat& update_stat() const { return ustat_; }
   bool history() const { return opt_.history; }
   int32_t round_target() const { return k_target_; }
@@ -224,6 +227,7 @@ class Engine {
   template <typename AdjT, typename KeyT>
   void update_levels();
   void rebuild_active();
+  void remove_nodes(const uint32_t* newid, uint32_t n_keep);
   void grow_nodes(uint64_t n_new);
   void graph_stats();
   // mark: set actr[node] = tag for the active nodes (else already done)

@@ -1697,8 +1697,9 @@ kbisim_status kbisim_result_round(const kbisim_graph* g, int32_t round, int32_t*
 
 kbisim_status kbisim_update(kbisim_graph* g, const kbisim_update_desc* u, int32_t* rounds_done) {
   if (!g || !g->eng || !u) return fail(KBISIM_EINVAL, "null argument");
-  if (u->num_new_nodes < 0 || u->num_del_edges < 0 || u->num_add_edges < 0)
+  if (u->num_new_nodes < 0 || u->num_del_edges < 0 || u->num_add_edges < 0 || u->num_del_nodes < 0)
     return fail(KBISIM_EINVAL, "negative size");
+  if (u->num_del_nodes > 0 && !u->del_nodes) return fail(KBISIM_EINVAL, "null del_nodes");
   if (u->num_new_nodes > 0 && !u->new_node_label) return fail(KBISIM_EINVAL, "null new_node_label");
   if (u->num_del_edges > 0 && (!u->del_src || !u->del_label || !u->del_dst))
     return fail(KBISIM_EINVAL, "null deleted edge array");
@@ -1715,14 +1716,15 @@ kbisim_status kbisim_update(kbisim_graph* g, const kbisim_update_desc* u, int32_
     a.n_new = u->num_new_nodes;
     a.m_del = u->num_del_edges;
     a.m_add = u->num_add_edges;
-    kb::DevBuf b[7];
+    a.n_del = u->num_del_nodes;
+    kb::DevBuf b[8];
     if (u->mem == KBISIM_MEM_HOST) {
-      const int32_t* src[7] = {u->new_node_label, u->del_src, u->del_label, u->del_dst,
-                               u->add_src, u->add_label, u->add_dst};
-      const uint64_t len[7] = {uint64_t(a.n_new), uint64_t(a.m_del), uint64_t(a.m_del), uint64_t(a.m_del),
-                               uint64_t(a.m_add), uint64_t(a.m_add), uint64_t(a.m_add)};
-      const int32_t* dev[7];
-      for (int i = 0; i < 7; ++i) {
+      const int32_t* src[8] = {u->new_node_label, u->del_src, u->del_label, u->del_dst,
+                               u->add_src, u->add_label, u->add_dst, u->del_nodes};
+      const uint64_t len[8] = {uint64_t(a.n_new), uint64_t(a.m_del), uint64_t(a.m_del), uint64_t(a.m_del),
+                               uint64_t(a.m_add), uint64_t(a.m_add), uint64_t(a.m_add), uint64_t(a.n_del)};
+      const int32_t* dev[8];
+      for (int i = 0; i < 8; ++i) {
         b[i].ensure(std::max<uint64_t>(len[i], 1) * 4);
         if (len[i])
           KB_CHECK(hipMemcpyAsync(b[i].p, src[i], len[i] * 4, hipMemcpyHostToDevice, g->eng->stream()));
@@ -1735,7 +1737,9 @@ kbisim_status kbisim_update(kbisim_graph* g, const kbisim_update_desc* u, int32_
       a.add_src = dev[4];
       a.add_lab = dev[5];
       a.add_dst = dev[6];
+      a.del_nodes = dev[7];
     } else {
+      a.del_nodes = u->del_nodes;
       a.new_label = u->new_node_label;
       a.del_src = u->del_src;
       a.del_lab = u->del_label;

@@ -760,4 +760,160 @@ __global__ void level0_ranks_k(const Told* __restrict__ old_rank, uint32_t n_o, 
   narrow[u] = Tnew(r);
 }
 
+// ---- node deletion --------------------------------------------------------------
+
+__global__ void fill_u32_k(uint32_t* __restrict__ a, uint64_t n, uint32_t v) {
+  const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+// alive[v] = 0 for every listed node; err = 1 for an id outside [0, n).
+__global__ void mark_deleted_k(const int32_t* __restrict__ del, uint32_t m, uint32_t n, uint32_t* __restrict__ alive,
+                               uint32_t* __restrict__ err) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const int32_t v = del[i];
+  if (v < 0 || uint32_t(v) >= n) {
+    atomicOr(err, 1u);
+    return;
+  }
+  alive[v] = 0;
+}
+
+// oldid[newid[v]] = v for the surviving nodes (newid[v + 1] > newid[v]).
+__global__ void survivors_k(const uint32_t* __restrict__ newid, uint32_t n, uint32_t* __restrict__ oldid) {
+  const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n && newid[v + 1] != newid[v]) oldid[newid[v]] = v;
+}
+
+// Added edges from the numbering after the deletion to the one before.
+__global__ void unmap_edges_k(const int32_t* __restrict__ src, const int32_t* __restrict__ dst, uint32_t m,
+                              uint32_t n_keep, const uint32_t* __restrict__ oldid, int32_t* __restrict__ osrc,
+                              int32_t* __restrict__ odst, uint32_t* __restrict__ err) {
+  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= m) return;
+  const int32_t s = src[e], t = dst[e];
+  if (s < 0 || uint32_t(s) >= n_keep || t < 0 || uint32_t(t) >= n_keep) {
+    atomicOr(err, 1u);
+    osrc[e] = odst[e] = 0;
+    return;
+  }
+  osrc[e] = int32_t(oldid[s]);
+  odst[e] = int32_t(oldid[t]);
+}
+
+// Out- and in-degree of every deleted node (nodes added in this update have none).
+__global__ void incident_counts_k(const int32_t* __restrict__ del, uint32_t m, uint32_t n_old,
+                                  const uint32_t* __restrict__ rowptr, const uint32_t* __restrict__ rrowptr,
+                                  uint32_t* __restrict__ cnt) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const uint32_t x = uint32_t(del[i]);
+  cnt[i] = x < n_old ? (rowptr[x + 1] - rowptr[x]) + (rrowptr[x + 1] - rrowptr[x]) : 0u;
+}
+
+// The edges of the deleted nodes as (src, label value, dst) triples: one
+// wave per deleted node and table.
+template <typename W>
+__global__ __launch_bounds__(256) void incident_edges_k(const int32_t* __restrict__ del, uint32_t m, uint32_t n_old,
+                                                        const uint32_t* __restrict__ rowptr, const W* __restrict__ adj,
+                                                        const uint32_t* __restrict__ rrowptr,
+                                                        const W* __restrict__ radj, int bits,
+                                                        const int32_t* __restrict__ vals,
+                                                        const uint32_t* __restrict__ off, int32_t* __restrict__ s,
+                                                        int32_t* __restrict__ l, int32_t* __restrict__ d) {
+  const uint32_t lane = __lane_id();
+  const W mask = (W(1) << bits) - 1;
+  for (uint32_t w = (blockIdx.x * blockDim.x + threadIdx.x) / kWave; w < 2 * m;
+       w += (gridDim.x * blockDim.x) / kWave) {
+    const uint32_t i = w >> 1;
+    const uint32_t x = uint32_t(del[i]);
+    if (x >= n_old) continue;
+    const bool reverse = w & 1u;
+    const uint32_t fdeg = rowptr[x + 1] - rowptr[x];
+    const uint32_t b = reverse ? rrowptr[x] : rowptr[x];
+    const uint32_t e = reverse ? rrowptr[x + 1] : rowptr[x + 1];
+    const uint32_t o = off[i] + (reverse ? fdeg : 0u);
+    const W* a = reverse ? radj : adj;
+    for (uint32_t q = b + lane; q < e; q += kWave) {
+      const W word = a[q];
+      const uint32_t other = uint32_t(word & mask);
+      const uint32_t out = o + (q - b);
+      s[out] = int32_t(reverse ? other : x);
+      d[out] = int32_t(reverse ? x : other);
+      l[out] = vals[uint32_t(word >> bits)];
+    }
+  }
+}
+
+// Row offsets of the surviving rows (removed rows are empty).
+__global__ void compact_rowptr_k(const uint32_t* __restrict__ rp, const uint32_t* __restrict__ newid, uint32_t n,
+                                 uint32_t* __restrict__ rp_n) {
+  const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v > n) return;
+  if (v == n) {
+    rp_n[newid[n]] = rp[n];
+    return;
+  }
+  if (newid[v + 1] != newid[v]) rp_n[newid[v]] = rp[v];
+}
+
+// Endpoint ids of every word renumbered (and moved to a narrower field).
+template <typename W>
+__global__ void renumber_words_k(W* __restrict__ adj, uint64_t m, int bits_o, int bits_n,
+                                 const uint32_t* __restrict__ newid) {
+  const W mask = (W(1) << bits_o) - 1;
+  for (uint64_t e = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < m; e += uint64_t(gridDim.x) * blockDim.x) {
+    const W w = adj[e];
+    adj[e] = ((w >> bits_o) << bits_n) | W(newid[uint32_t(w & mask)]);
+  }
+}
+
+// Per position of a stored round: does its node survive.
+__global__ void alive_positions_k(const uint32_t* __restrict__ ord, const uint32_t* __restrict__ newid, uint32_t n,
+                                  uint32_t* __restrict__ alivep) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p > n) return;
+  if (p == n) {
+    alivep[p] = 0;
+    return;
+  }
+  const uint32_t u = ord[p];
+  alivep[p] = newid[u + 1] != newid[u] ? 1u : 0u;
+}
+
+// A stored round closed up: surviving positions move to npos[p] (exclusive
+// scan of the survivors), a class starts at its first surviving member
+// (npos of its old start), ids renumbered; flags of the closed-up round.
+__global__ void close_level_k(const uint32_t* __restrict__ ord, const int32_t* __restrict__ pid, uint32_t n,
+                              const uint32_t* __restrict__ newid, const uint32_t* __restrict__ npos,
+                              uint32_t* __restrict__ ord_n, int32_t* __restrict__ pid_n, uint8_t* __restrict__ flag_n) {
+  const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const uint32_t u = ord[p];
+  if (newid[u + 1] == newid[u]) return;
+  const uint32_t q = npos[p];
+  const uint32_t start = npos[uint32_t(pid[u])];
+  ord_n[q] = newid[u];
+  pid_n[newid[u]] = int32_t(start);
+  flag_n[q] = q == start ? 1 : 0;
+}
+
+// Old narrow pId_0 (label rank) of the first member of every level-0 class.
+template <typename T>
+__global__ void level0_labels_k(const uint32_t* __restrict__ first, const uint32_t* __restrict__ ord, uint32_t B,
+                                const uint32_t* __restrict__ oldid, const T* __restrict__ old_rank,
+                                uint32_t* __restrict__ out) {
+  const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < B) out[b] = uint32_t(old_rank[oldid[ord[first[b]]]]);
+}
+
+// Dense level-0 ids in the narrow type: cls[pid[v]] - 1.
+template <typename T>
+__global__ void dense_level0_k(const int32_t* __restrict__ pid, const uint32_t* __restrict__ cls, uint32_t n,
+                               T* __restrict__ out) {
+  const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v < n) out[v] = T(cls[uint32_t(pid[v])] - 1);
+}
+
 }  // namespace kb

@@ -410,7 +410,7 @@ static void update_tables(Engine& e, DevBuf& rowptr, DevBuf& adj, DevBuf& rrowpt
   if (e_r != *e_n) throw DeviceError(hipErrorUnknown, "edge tables out of step after an update");
 }
 
-void Engine::update(const UpdateArgs& u) {
+void Engine::update_core(const UpdateArgs& u) {
   StreamScope scope(st_);
   if (!opt_.history) throw StateError("updates need the history option");
   if (u.n_new < 0 || u.m_add < 0 || u.m_del < 0) throw InvalidInput("negative update size");
@@ -644,15 +644,13 @@ void Engine::update(const UpdateArgs& u) {
   } else {
     if (key64_) update_levels<uint32_t, uint64_t>(); else update_levels<uint32_t, uint32_t>();
   }
-  // the rest of the rounds asked for, when the fixed point moved
-  if (!(fixed_ && opt_.early_stop) && rounds_ < k_target_) {
-    rebuild_active();
-    while (rounds_ < k_target_) {
-      if (fixed_ && opt_.early_stop) break;
-      run_round();
-    }
-  } else if (rounds_ == 0) {
-    rebuild_active();
+  // the rest of the rounds asked for, when the fixed point moved; the
+  // active set of the next round is rebuilt either way (a later
+  // kbisim_refine continues from it)
+  rebuild_active();
+  while (rounds_ < k_target_) {
+    if (fixed_ && opt_.early_stop) break;
+    run_round();
   }
   KB_CHECK(hipStreamSynchronize(st_));
 }
@@ -900,4 +898,255 @@ void Engine::update_levels() {
   fixed_ = !switched && last >= 1 && counts_[size_t(last)] == counts_[size_t(last) - 1];
   cls_round_ = -1;
   dense_round_ = -1;
+}
+
+// ---- node deletion --------------------------------------------------------------
+
+// An update with deleted nodes: their incoming and outgoing edges are deleted
+// (Section 4, "Deletions": a node goes after its edges), added edges are
+// mapped to the numbering before the deletion, one level-by-level update
+// runs, and the then isolated nodes leave every stored round (a node without
+// edges is in no other node's signature, so the others keep their classes;
+// positions and node ids close up).
+void Engine::update(const UpdateArgs& u) {
+  StreamScope scope(st_);
+  if (!opt_.history) throw StateError("updates need the history option");
+  if (u.n_del < 0 || u.n_new < 0 || u.m_add < 0 || u.m_del < 0) throw InvalidInput("negative update size");
+  if (u.n_del == 0) return update_core(u);
+  const uint64_t n_all = uint64_t(n_) + uint64_t(u.n_new);
+  if (n_all >= (uint64_t(1) << 31)) throw InvalidInput("num_nodes would reach 2^31");
+  uint32_t* hw = reinterpret_cast<uint32_t*>(hw_.p);
+  // survivors: alive[v] over the nodes after the new ones; newid = exclusive scan
+  DevBuf alive, newid, oldid, errb;
+  alive.ensure((n_all + 1) * 4);
+  newid.ensure((n_all + 1) * 4);
+  oldid.ensure(std::max<uint64_t>(n_all, 1) * 4);
+  errb.ensure(8);
+  KB_CHECK(hipMemsetAsync(errb.p, 0, 8, st_));
+  fill_u32_k<<<grid_for(n_all + 1), kNT, 0, st_>>>(alive.as<uint32_t>(), n_all + 1, 1u);
+  KB_LAUNCH_CHECK();
+  KB_CHECK(hipMemsetAsync(alive.as<uint32_t>() + n_all, 0, 4, st_));
+  mark_deleted_k<<<grid_for(uint64_t(u.n_del)), kNT, 0, st_>>>(u.del_nodes, uint32_t(u.n_del), uint32_t(n_all),
+                                                              alive.as<uint32_t>(), errb.as<uint32_t>());
+  KB_LAUNCH_CHECK();
+  scan_dev<uint32_t, uint32_t, false>(alive.as<uint32_t>(), newid.as<uint32_t>(), n_all + 1);
+  KB_CHECK(hipMemcpyAsync(hw, errb.p, 4, hipMemcpyDeviceToHost, st_));
+  KB_CHECK(hipMemcpyAsync(hw + 1, newid.as<uint32_t>() + n_all, 4, hipMemcpyDeviceToHost, st_));
+  KB_CHECK(hipStreamSynchronize(st_));
+  if (hw[0]) throw InvalidInput("deleted node outside [0, num_nodes + num_new_nodes)");
+  const uint32_t n_keep = hw[1];
+  survivors_k<<<grid_for(n_all), kNT, 0, st_>>>(newid.as<uint32_t>(), uint32_t(n_all), oldid.as<uint32_t>());
+  KB_LAUNCH_CHECK();
+  // added edges in the numbering before the deletion
+  DevBuf as, ad;
+  as.ensure(std::max<int64_t>(u.m_add, 1) * 4);
+  ad.ensure(std::max<int64_t>(u.m_add, 1) * 4);
+  if (u.m_add) {
+    KB_CHECK(hipMemsetAsync(errb.p, 0, 4, st_));
+    unmap_edges_k<<<grid_for(uint64_t(u.m_add)), kNT, 0, st_>>>(u.add_src, u.add_dst, uint32_t(u.m_add), n_keep,
+                                                                oldid.as<uint32_t>(), as.as<int32_t>(),
+                                                                ad.as<int32_t>(), errb.as<uint32_t>());
+    KB_LAUNCH_CHECK();
+    KB_CHECK(hipMemcpyAsync(hw, errb.p, 4, hipMemcpyDeviceToHost, st_));
+    KB_CHECK(hipStreamSynchronize(st_));
+    if (hw[0]) throw InvalidInput("added edge endpoint outside [0, num_nodes) after the deletions");
+  }
+  // edges of the deleted nodes (old nodes only: new nodes have none yet),
+  // as triples with label values, plus the explicit deletions
+  const uint32_t n_old = uint32_t(n_);
+  DevBuf dn, cntb, off;
+  dn.ensure(uint64_t(u.n_del) * 4);
+  cntb.ensure((uint64_t(u.n_del) + 1) * 4);
+  off.ensure((uint64_t(u.n_del) + 1) * 4);
+  incident_counts_k<<<grid_for(uint64_t(u.n_del)), kNT, 0, st_>>>(u.del_nodes, uint32_t(u.n_del), n_old,
+                                                                 rowptr_.as<uint32_t>(), rrowptr_.as<uint32_t>(),
+                                                                 cntb.as<uint32_t>());
+  KB_LAUNCH_CHECK();
+  KB_CHECK(hipMemsetAsync(cntb.as<uint32_t>() + u.n_del, 0, 4, st_));
+  scan_dev<uint32_t, uint32_t, false>(cntb.as<uint32_t>(), off.as<uint32_t>(), uint64_t(u.n_del) + 1);
+  KB_CHECK(hipMemcpyAsync(hw, off.as<uint32_t>() + u.n_del, 4, hipMemcpyDeviceToHost, st_));
+  KB_CHECK(hipStreamSynchronize(st_));
+  const uint64_t m_inc = hw[0];
+  const uint64_t m_d = uint64_t(u.m_del) + m_inc;
+  DevBuf ds, dl, dd;
+  for (DevBuf* b : {&ds, &dl, &dd}) b->ensure(std::max<uint64_t>(m_d, 1) * 4);
+  if (u.m_del) {
+    KB_CHECK(hipMemcpyAsync(ds.p, u.del_src, uint64_t(u.m_del) * 4, hipMemcpyDeviceToDevice, st_));
+    KB_CHECK(hipMemcpyAsync(dl.p, u.del_lab, uint64_t(u.m_del) * 4, hipMemcpyDeviceToDevice, st_));
+    KB_CHECK(hipMemcpyAsync(dd.p, u.del_dst, uint64_t(u.m_del) * 4, hipMemcpyDeviceToDevice, st_));
+  }
+  if (m_inc) {
+    upload_values(d_evals_, elab_vals_, st_);
+    const uint32_t waves = uint32_t(u.n_del) * 2;
+    if (adj64_)
+      incident_edges_k<uint64_t><<<std::min<uint32_t>(ceil_div(uint64_t(waves) * kWave, 256), 4096), 256, 0, st_>>>(
+          u.del_nodes, uint32_t(u.n_del), n_old, rowptr_.as<uint32_t>(), adj_.as<uint64_t>(), rrowptr_.as<uint32_t>(),
+          radj_.as<uint64_t>(), dst_bits_, d_evals_.as<int32_t>(), off.as<uint32_t>(), ds.as<int32_t>() + u.m_del,
+          dl.as<int32_t>() + u.m_del, dd.as<int32_t>() + u.m_del);
+    else
+      incident_edges_k<uint32_t><<<std::min<uint32_t>(ceil_div(uint64_t(waves) * kWave, 256), 4096), 256, 0, st_>>>(
+          u.del_nodes, uint32_t(u.n_del), n_old, rowptr_.as<uint32_t>(), adj_.as<uint32_t>(), rrowptr_.as<uint32_t>(),
+          radj_.as<uint32_t>(), dst_bits_, d_evals_.as<int32_t>(), off.as<uint32_t>(), ds.as<int32_t>() + u.m_del,
+          dl.as<int32_t>() + u.m_del, dd.as<int32_t>() + u.m_del);
+    KB_LAUNCH_CHECK();
+  }
+  UpdateArgs core = u;
+  core.n_del = 0;
+  core.del_nodes = nullptr;
+  core.m_del = int64_t(m_d);
+  core.del_src = ds.as<int32_t>();
+  core.del_lab = dl.as<int32_t>();
+  core.del_dst = dd.as<int32_t>();
+  core.add_src = as.as<int32_t>();
+  core.add_dst = ad.as<int32_t>();
+  update_core(core);
+  remove_nodes(newid.as<uint32_t>(), n_keep);
+}
+
+// Removes the nodes with newid[v] == newid[v + 1] (isolated by now) from
+// the tables and every stored round, renumbering the others newid[v].
+void Engine::remove_nodes(const uint32_t* newid, uint32_t n_keep) {
+  const uint32_t n_all = uint32_t(n_);
+  const int32_t K = rounds_;
+  uint32_t* hw = reinterpret_cast<uint32_t*>(hw_.p);
+  if (n_keep == 0) {  // nothing left: the state of an empty graph
+    n_ = 0;
+    m_ = 0;
+    hist_.clear();
+    nlab_vals_.clear();
+    elab_vals_.clear();
+    const int32_t kt = k_target_;
+    build(nullptr, nullptr, nullptr, nullptr);
+    k_target_ = 0;
+    refine(kt);
+    return;
+  }
+  // tables: rows of removed nodes are empty; endpoints renumbered
+  const int bits_n = bits_for(n_keep > 1 ? n_keep - 1 : 1);
+  auto table = [&](DevBuf& rowptr, DevBuf& adj) {
+    DevBuf rp;
+    rp.ensure((uint64_t(n_keep) + 1) * 4);
+    compact_rowptr_k<<<grid_for(uint64_t(n_all) + 1), kNT, 0, st_>>>(rowptr.as<uint32_t>(), newid, n_all,
+                                                                     rp.as<uint32_t>());
+    KB_LAUNCH_CHECK();
+    rowptr.swap(rp);
+    const uint64_t E = uint64_t(m_);
+    if (E) {
+      if (adj64_)
+        renumber_words_k<uint64_t><<<grid_stride_blocks(E), kNT, 0, st_>>>(adj.as<uint64_t>(), E, dst_bits_, bits_n,
+                                                                           newid);
+      else
+        renumber_words_k<uint32_t><<<grid_stride_blocks(E), kNT, 0, st_>>>(adj.as<uint32_t>(), E, dst_bits_, bits_n,
+                                                                           newid);
+      KB_LAUNCH_CHECK();
+    }
+  };
+  table(rowptr_, adj_);
+  table(rrowptr_, radj_);
+  dst_bits_ = bits_n;
+  // (a narrower endpoint field only shrinks the words: the word and key
+  // types stay wide enough)
+  // every stored round: positions close up, class starts move to the first
+  // surviving member, ids renumbered
+  DevBuf alivep, npos, fl8;
+  alivep.ensure((uint64_t(n_all) + 1) * 4);
+  npos.ensure((uint64_t(n_all) + 1) * 4);
+  fl8.ensure(std::max<uint32_t>(n_keep, 1));
+  counts_.assign(size_t(K) + 1, 0);
+  for (int32_t j = 0; j <= K; ++j) {
+    Level& L = hist_[size_t(j)];
+    alive_positions_k<<<grid_for(uint64_t(n_all) + 1), kNT, 0, st_>>>(L.ord.as<uint32_t>(), newid, n_all,
+                                                                      alivep.as<uint32_t>());
+    KB_LAUNCH_CHECK();
+    scan_dev<uint32_t, uint32_t, false>(alivep.as<uint32_t>(), npos.as<uint32_t>(), uint64_t(n_all) + 1);
+    DevBuf no, np;
+    no.ensure(uint64_t(n_keep) * 4);
+    np.ensure(uint64_t(n_keep) * 4);
+    close_level_k<<<grid_for(n_all), kNT, 0, st_>>>(L.ord.as<uint32_t>(), L.pid.as<int32_t>(), n_all, newid,
+                                                    npos.as<uint32_t>(), no.as<uint32_t>(), np.as<int32_t>(),
+                                                    fl8.as<uint8_t>());
+    KB_LAUNCH_CHECK();
+    L.ord.swap(no);
+    L.pid.swap(np);
+    // classes left: flags of the closed-up round
+    scan_dev<uint8_t, uint32_t, true>(fl8.as<uint8_t>(), cls_.as<uint32_t>(), n_keep);
+    KB_CHECK(hipMemcpyAsync(hw, cls_.as<uint32_t>() + (n_keep - 1), 4, hipMemcpyDeviceToHost, st_));
+    KB_CHECK(hipStreamSynchronize(st_));
+    counts_[size_t(j)] = hw[0];
+  }
+  // label values still present (one per level-0 class left, read through
+  // the old narrow pId_0 of each class's first member) and the new narrow
+  // pId_0 (dense level-0 ranks)
+  {
+    const Level& L0 = hist_[0];
+    const uint32_t B0 = uint32_t(counts_[0]);
+    DevBuf first, oldid, oldrank, p0;
+    first.ensure(std::max<uint32_t>(B0, 1) * 4);
+    oldid.ensure(uint64_t(n_keep) * 4);
+    oldrank.ensure(std::max<uint32_t>(B0, 1) * 4);
+    flags_from_level_k<<<grid_for(n_keep), kNT, 0, st_>>>(L0.ord.as<uint32_t>(), L0.pid.as<int32_t>(), n_keep,
+                                                          fl8.as<uint8_t>());
+    KB_LAUNCH_CHECK();
+    scan_dev<uint8_t, uint32_t, true>(fl8.as<uint8_t>(), cls_.as<uint32_t>(), n_keep);
+    class_starts_k<<<grid_for(n_keep), kNT, 0, st_>>>(fl8.as<uint8_t>(), cls_.as<uint32_t>(), n_keep,
+                                                      first.as<uint32_t>());
+    KB_LAUNCH_CHECK();
+    survivors_k<<<grid_for(n_all), kNT, 0, st_>>>(newid, n_all, oldid.as<uint32_t>());
+    KB_LAUNCH_CHECK();
+    auto ranks = [&](auto told) {
+      using To = decltype(told);
+      level0_labels_k<To><<<grid_for(B0), kNT, 0, st_>>>(first.as<uint32_t>(), L0.ord.as<uint32_t>(), B0,
+                                                         oldid.as<uint32_t>(), pid0_.as<To>(), oldrank.as<uint32_t>());
+      KB_LAUNCH_CHECK();
+    };
+    if (pid0_bytes_ == 1) ranks(uint8_t()); else if (pid0_bytes_ == 2) ranks(uint16_t()); else ranks(uint32_t());
+    std::vector<uint32_t> fr(B0);
+    if (B0) KB_CHECK(hipMemcpyAsync(fr.data(), oldrank.p, uint64_t(B0) * 4, hipMemcpyDeviceToHost, st_));
+    KB_CHECK(hipStreamSynchronize(st_));
+    std::vector<int32_t> vals(B0);
+    for (uint32_t b = 0; b < B0; ++b) vals[b] = nlab_vals_[fr[b]];
+    nlab_vals_ = vals;
+    const int nb = B0 <= 256 ? 1 : B0 <= 65536 ? 2 : 4;
+    p0.ensure(uint64_t(n_keep) * uint64_t(nb));
+    auto narrow = [&](auto tnew) {
+      using Tn = decltype(tnew);
+      dense_level0_k<Tn><<<grid_for(n_keep), kNT, 0, st_>>>(L0.pid.as<int32_t>(), cls_.as<uint32_t>(), n_keep,
+                                                            p0.as<Tn>());
+      KB_LAUNCH_CHECK();
+    };
+    if (nb == 1) narrow(uint8_t()); else if (nb == 2) narrow(uint16_t()); else narrow(uint32_t());
+    KB_CHECK(hipStreamSynchronize(st_));
+    pid0_.swap(p0);
+    pid0_bytes_ = nb;
+    b0_ = B0;
+  }
+  n_ = int64_t(n_keep);
+  // the first fixed point of the closed-up counts ends the stored rounds
+  int32_t last = K;
+  if (opt_.early_stop)
+    for (int32_t j = 1; j <= K; ++j)
+      if (counts_[size_t(j)] == counts_[size_t(j - 1)]) {
+        last = j;
+        break;
+      }
+  rounds_ = last;
+  hist_.resize(size_t(last) + 1);
+  counts_.resize(size_t(last) + 1);
+  B_ = counts_.back();
+  fixed_ = last >= 1 && counts_[size_t(last)] == counts_[size_t(last) - 1];
+  for (DevBuf* b : {&rtag_, &ctag_, &dtag_}) KB_CHECK(hipMemsetAsync(b->p, 0, b->bytes, st_));
+  load_level(rounds_);
+  graph_stats();
+  dense_round_ = -1;
+  cls_round_ = -1;
+  if (!(fixed_ && opt_.early_stop) && rounds_ < k_target_) {
+    rebuild_active();
+    while (rounds_ < k_target_) {
+      if (fixed_ && opt_.early_stop) break;
+      run_round();
+    }
+  } else {
+    rebuild_active();
+  }
+  KB_CHECK(hipStreamSynchronize(st_));
 }

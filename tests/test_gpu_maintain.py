@@ -94,9 +94,23 @@ def test_update_tables_4_and_5(early_stop, k, mode):
 
 def random_gpu_update(rng, cur, n_labels, e_labels, allow_nodes=True):
     n = cur[0]
-    kind = int(rng.integers(0, 4 if allow_nodes else 3))
+    kind = int(rng.integers(0, 6 if allow_nodes else 3))
     m = int(rng.integers(1, 6))
-    if kind == 3:
+    if kind == 4 and n > 2:  # delete nodes
+        return dict(delete_nodes=rng.integers(0, n, size=int(rng.integers(1, 3))).astype(np.int32))
+    if kind == 5 and n > 2:  # everything at once
+        nn = int(rng.integers(1, 3))
+        dn = rng.integers(0, n + nn, size=int(rng.integers(1, 3))).astype(np.int32)
+        n_after = n + nn - np.unique(dn).size
+        upd = dict(new_labels=rng.integers(0, n_labels + 2, size=nn).astype(np.int32), delete_nodes=dn)
+        if cur[2].shape[0]:
+            pick = rng.integers(0, cur[2].shape[0], m)
+            upd["delete"] = (cur[2][pick], cur[3][pick], cur[4][pick])
+        if n_after > 0:
+            upd["add"] = tuple(x.astype(np.int32) for x in (rng.integers(0, n_after, m), rng.integers(0, e_labels, m),
+                                                           rng.integers(0, n_after, m)))
+        return upd
+    if kind >= 3:
         return dict(new_labels=rng.integers(0, n_labels + 2, size=int(rng.integers(1, 4))).astype(np.int32))
     if kind == 0 or cur[2].shape[0] == 0:
         return dict(add=tuple(x.astype(np.int32) for x in (rng.integers(0, n, m), rng.integers(0, e_labels + 1, m),
@@ -253,3 +267,28 @@ def test_dworst_all_change():
         _, _, counts = h.result()
         assert counts == [1, 3, 3]
         say("dworst: stats %s" % (h.update_stats(),))
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_delete_nodes(mode):
+    """Node deletions (with self-loops, a node added and deleted in one
+    update, all nodes at once) and a further refine after an update."""
+    torch, kb = need_gpu()
+    g = graph_of(load("figure1.json"))
+    cur = cur_of(g)
+    with kb.Graph(g.num_nodes, *cur[1:], history=True, update_mode=mode) as h:
+        h.refine(3)
+        for upd in (dict(delete_nodes=[1]),  # paper node 2, with its self-loop
+                    dict(new_labels=[0, 1], delete_nodes=[5, 0], add=([4, 2], [0, 1], [0, 4])),
+                    dict(delete_nodes=[2, 2])):
+            h.update(**upd)
+            cur = M.updated_graph(*cur, **upd)
+            check_against(h, cur, 3, True, str(upd))
+        h.refine(10)  # continue after the updates
+        check_against(h, cur, 10, True, "refined further")
+        h.update(delete_nodes=np.arange(cur[0], dtype=np.int32))
+        cur = M.updated_graph(*cur, delete_nodes=np.arange(cur[0]))
+        check_against(h, cur, 10, True, "empty")
+        h.update(new_labels=[3, 3], add=([0], [2], [1]))
+        cur = M.updated_graph(*cur, new_labels=[3, 3], add=([0], [2], [1]))
+        check_against(h, cur, 10, True, "after empty")
