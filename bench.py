@@ -80,17 +80,23 @@ def load_traffic(kernel_class, workload, early_stop, k_cap):
 
 # Workloads up to this many edges: the oracle runs the whole job itself.
 WHOLE_JOB_ORACLE_EDGES = 1_000_000
+# Larger ones: a sample with about this many out-edges (about 16 s of oracle work).
+SAMPLE_EDGES = 25_000_000
 
 
 def cpu_baseline(seed=1, g=None, k=None, early_stop=True):
-    """The oracle (single thread). For a small workload `g` (at most
-    WHOLE_JOB_ORACLE_EDGES edges) the whole job (k rounds, the same stop
-    rule); otherwise a bounded sample: the first two rounds of a 1M-node /
-    10M-edge graph drawn from the same power-law recipe."""
+    """The oracle (single thread) on the measured workload `g`. Small
+    workloads (at most WHOLE_JOB_ORACLE_EDGES edges): the whole job (k rounds,
+    the same stop rule). Larger ones: a bounded sample of the same graph,
+    the oracle's round 1 over a seeded uniform sample of its nodes (a
+    quarter, or fewer so that the sample has about SAMPLE_EDGES out-edges)
+    with all their out-edges (signatures from pId_0, one ordered
+    dictionary), rated per edge of the sample; its scan of the whole edge
+    table is charged to the sample."""
+    import numpy as np
     import oracle
-    import synth
-    if g is not None and g.num_edges <= WHOLE_JOB_ORACLE_EDGES:
-        oracle.build()
+    oracle.build()
+    if g.num_edges <= WHOLE_JOB_ORACLE_EDGES:
         t0 = time.perf_counter()
         r = oracle.refine(g.num_nodes, g.node_label, g.src, g.elab, g.dst, k, early_stop=early_stop)
         dt = time.perf_counter() - t0
@@ -98,15 +104,17 @@ def cpu_baseline(seed=1, g=None, k=None, early_stop=True):
                 "kind": "oracle", "seconds": dt, "rounds": r.rounds_done,
                 "sample": "the whole job (%s, k=%d, %s); %.3f s" % (
                     g.name, k, "early stop" if early_stop else "no early stop", dt)}
-    g = synth.powerlaw_graph(1_000_000, 10_000_000, seed=seed, name="powerlaw-1M-10M")
-    oracle.build()
+    rng = np.random.Generator(np.random.PCG64(seed))
+    frac = min(0.25, SAMPLE_EDGES / g.num_edges)
+    size = max(1, int(g.num_nodes * frac))
+    sample = np.sort(rng.choice(g.num_nodes, size=size, replace=False)).astype(np.int32)
     t0 = time.perf_counter()
-    r = oracle.refine(g.num_nodes, g.node_label, g.src, g.elab, g.dst, 2, early_stop=False)
+    _, edges = oracle.round_sample(g.num_nodes, g.node_label, g.src, g.elab, g.dst, sample)
     dt = time.perf_counter() - t0
-    return {"value": g.num_edges * r.rounds_done / dt, "unit": "edge-rounds/s", "cores": 1,
-            "kind": "oracle",
-            "sample": "oracle rounds 1-2 (plus its adjacency build) of a 1M-node / 10M-edge graph "
-                      "from the same power-law recipe, seed %d; %.1f s" % (seed, dt)}
+    return {"value": edges / dt, "unit": "edge-rounds/s", "cores": 1, "kind": "oracle", "seconds": dt,
+            "sample": "oracle round 1 of the measured graph (%s) over a seeded uniform sample of %.1f%% of its "
+                      "nodes (%d nodes, %d out-edges, seed %d); %.1f s" % (g.name, 100 * frac, size, edges, seed,
+                                                                           dt)}
 
 
 def main():
@@ -260,10 +268,33 @@ def main():
                     / max(x["signature_ms"], 1e-9) / 1e6}
                    for r, x in enumerate(per_round)],
     }
+    # edges whose signature was actually built (active nodes' out-edges),
+    # per second of the step: the rate of work done, beside the headline's
+    # |E| * rounds
+    processed = sum(x["active_edges"] for x in per_round)
+    line["processed_edges"] = {"per_step": processed, "per_s": processed / (ms_per_step / 1e3)}
     if not args.no_cpu_baseline:
         log("timing the oracle on the host ...")
         line["cpu_baseline"] = cpu_baseline(args.seed, g, k, early_stop)
+        full = recorded_full_job(args.workload, args.seed, early_stop, k)
+        if full:
+            line["cpu_baseline"]["full_job_recorded"] = full
     print(json.dumps(line), flush=True)
+
+
+def recorded_full_job(workload, seed, early_stop, k):
+    """The oracle's whole run on this workload as recorded when its golden
+    file was written (tests/golden/make_fullsize.py, one thread), if any."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", "%s%s.json" % (
+        workload, "" if early_stop else "_k%d-no-early-stop" % k))
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("seed") != seed or d.get("k") != k or "oracle_seconds" not in d:
+        return None
+    return {"seconds": d["oracle_seconds"], "value": d["oracle_edge_rounds_per_s"], "unit": "edge-rounds/s",
+            "rounds": d["rounds_done"], "cores": 1, "host": d.get("oracle_host"), "source": os.path.relpath(path)}
 
 
 def copy_probe(torch, dev):

@@ -68,6 +68,8 @@ def _load():
         lib.oracle_signatures.argtypes = [i64, i64, p, p, p, p, i64, p, p, p]
         lib.oracle_signature_lengths.restype = i32
         lib.oracle_signature_lengths.argtypes = [i64, i64, p, p, p, p, p]
+        lib.oracle_round_sample.restype = i32
+        lib.oracle_round_sample.argtypes = [i64, i64, p, p, p, p, i64, p, p, p]
         lib.oracle_state_create.restype = p
         lib.oracle_state_create.argtypes = [i64, p, i64, p, p, p, i32]
         lib.oracle_state_destroy.restype = None
@@ -161,6 +163,25 @@ def longest_multi_member(lengths, pid_prev):
     sizes = np.bincount(pid_prev)
     multi = sizes[pid_prev] >= 2
     return int(max(1, lengths[multi].max())) if multi.any() else 1
+
+
+def round_sample(num_nodes, node_label, src, elab, dst, sample):
+    """Round 1 of Build_Bisim restricted to the sampled nodes (their
+    signatures from pId_0 inserted into one ordered dictionary). Returns
+    (ranks of the sampled nodes' signatures among the sample's distinct
+    signatures, number of out-edges of the sampled nodes)."""
+    lib = _load()
+    n = int(num_nodes)
+    node_label = _i32(node_label)
+    src, elab, dst = _i32(src), _i32(elab), _i32(dst)
+    sample = _i32(sample)
+    rank = np.empty(sample.shape[0], np.int32)
+    edges = np.zeros(1, np.int64)
+    st = lib.oracle_round_sample(n, int(src.shape[0]), _ptr(node_label), _ptr(src), _ptr(elab), _ptr(dst),
+                                 int(sample.shape[0]), _ptr(sample), _ptr(rank), _ptr(edges))
+    if st != 0:
+        raise OracleError("invalid input (status %d)" % st)
+    return rank, int(edges[0])
 
 
 def signatures(num_nodes, src, elab, dst, pid_prev, sample):

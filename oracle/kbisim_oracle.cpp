@@ -228,6 +228,50 @@ int32_t oracle_signatures(int64_t n, int64_t m, const int32_t* src, const int32_
   return ORACLE_OK;
 }
 
+// One round of Build_Bisim restricted to a sample of nodes (used to time the
+// oracle on a bounded part of a large job): iteration 0's ids from the node
+// labels, then for every sampled node its out-edges, its signature from
+// pId_0 and its insertion into an ordered dictionary S; rank_out[j] is the
+// lexicographic rank of sampled node j's signature among the distinct
+// signatures of the sample; *sample_edges the out-edges of the sampled
+// nodes. Returns 0 or -1.
+int32_t oracle_round_sample(int64_t n, int64_t m, const int32_t* node_label, const int32_t* src,
+                            const int32_t* elab, const int32_t* dst, int64_t num_sample, const int32_t* sample,
+                            int32_t* rank_out, int64_t* sample_edges) {
+  int32_t st = validate(n, m, node_label, src, elab, dst, 0);
+  if (st != ORACLE_OK || num_sample < 0) return ORACLE_EINVAL;
+  // iteration 0: the rank of every node label among the distinct labels
+  std::map<int32_t, int32_t> label_rank;
+  for (int64_t v = 0; v < n; ++v) label_rank.emplace(node_label[v], 0);
+  int32_t r0 = 0;
+  for (auto& kv : label_rank) kv.second = r0++;
+  std::vector<int32_t> pid(n);
+  for (int64_t v = 0; v < n; ++v) pid[v] = label_rank.find(node_label[v])->second;
+  std::vector<int64_t> slot(n, -1);
+  for (int64_t j = 0; j < num_sample; ++j) {
+    if (sample[j] < 0 || sample[j] >= n) return ORACLE_EINVAL;
+    if (slot[sample[j]] < 0) slot[sample[j]] = j;
+  }
+  std::vector<std::vector<std::pair<int32_t, int32_t>>> out(num_sample);
+  int64_t edges = 0;
+  for (int64_t e = 0; e < m; ++e) {
+    const int64_t j = slot[src[e]];
+    if (j >= 0) {
+      out[j].emplace_back(elab[e], dst[e]);
+      ++edges;
+    }
+  }
+  std::vector<Sig> sig(num_sample);
+  for (int64_t j = 0; j < num_sample; ++j) sig[j] = build_signature(pid[sample[j]], out[slot[sample[j]]], pid);
+  std::map<Sig, int32_t> store;
+  for (int64_t j = 0; j < num_sample; ++j) store.emplace(sig[j], 0);
+  int32_t rank = 0;
+  for (auto& kv : store) kv.second = rank++;
+  for (int64_t j = 0; j < num_sample; ++j) rank_out[j] = store.find(sig[j])->second;
+  if (sample_edges) *sample_edges = edges;
+  return ORACLE_OK;
+}
+
 // Length (as a count of ints, 1 + 2 * pairs) of every node's signature built
 // from a given previous-round id array; len_out[N]. Returns 0 or -1.
 int32_t oracle_signature_lengths(int64_t n, int64_t m, const int32_t* src, const int32_t* elab,

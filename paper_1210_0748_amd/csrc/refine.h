@@ -367,9 +367,15 @@ __global__ __launch_bounds__(NT) void resolve_k(const uint32_t* __restrict__ gst
     if (!__syncthreads_or(open)) break;  // what is still open consists of copies of its pivot
 
     // (d) bitonic sort of the open list by (subgroup, side key, digits);
-    // padding sorts last
+    // padding sorts last. In a step of stride <= kWave the pairs of the
+    // threads of one wave lie inside the wave's own aligned runs of
+    // 2 * kWave entries (the same runs at every such stride), so between two
+    // such steps the wave only waits for its own LDS operations, which it
+    // performs in order; a workgroup barrier is needed only next to a step
+    // of a larger stride.
     for (uint32_t size = 2; size <= P; size <<= 1) {
       for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+        const uint32_t next = stride > 1 ? stride >> 1 : size;  // stride of the following step
         for (uint32_t t = threadIdx.x; t < P / 2; t += NT) {
           const uint32_t lo = 2 * t - (t & (stride - 1));
           const uint32_t hi = lo + stride;
@@ -386,7 +392,10 @@ __global__ __launch_bounds__(NT) void resolve_k(const uint32_t* __restrict__ gst
             perm[hi] = uint16_t(a);
           }
         }
-        __syncthreads();
+        if (stride > kWave || next > kWave || (size == P && stride == 1))
+          __syncthreads();
+        else
+          __builtin_amdgcn_wave_barrier();
       }
     }
 

@@ -263,3 +263,26 @@ def test_signature_lengths_table1():
     lengths = oracle.signature_lengths(g.num_nodes, g.src, g.elab, g.dst, pn["pid"][1])
     assert oracle.longest_multi_member(lengths, np.asarray(pn["pid"][1]) - 3) == 5
     assert oracle.longest_multi_member(np.array([7, 3, 5]), np.array([0, 1, 2])) == 1
+
+
+def test_round_sample_figure1_and_subsets():
+    """The oracle's round restricted to a node sample (the timed sample of the
+    bench's CPU baseline). On Figure 1 with every node it gives round 1's
+    canonical ids (Appendix A of the survey: [0,0,2,3,2,1]); on a subset the
+    ranks are round 1's ids renumbered densely within the subset, since the
+    lexicographic order of signatures does not depend on which other nodes
+    are present; the edge count is the subset's out-degree sum."""
+    fx = load("figure1.json")
+    g = graph_of(fx)
+    rank, edges = oracle.round_sample(g.num_nodes, g.node_label, g.src, g.elab, g.dst, np.arange(6))
+    assert rank.tolist() == [0, 0, 2, 3, 2, 1] and edges == 7
+    rng = np.random.default_rng(5)
+    h = synth.uniform_graph(300, 1500, num_node_labels=3, num_edge_labels=4, seed=3)
+    full = run(h, 1, early_stop=False).pid
+    outdeg = np.bincount(h.src, minlength=h.num_nodes)
+    for _ in range(5):
+        sample = rng.choice(h.num_nodes, size=int(rng.integers(1, 200)), replace=False).astype(np.int32)
+        rank, edges = oracle.round_sample(h.num_nodes, h.node_label, h.src, h.elab, h.dst, sample)
+        _, dense = np.unique(full[sample], return_inverse=True)
+        assert rank.tolist() == dense.tolist()
+        assert edges == int(outdeg[sample].sum())
