@@ -90,6 +90,21 @@ typedef struct {
                           then full rounds (Section 4, "When to switch back"); 1 level
                           by level in every round; 2 full rounds from round 1. The
                           result does not depend on it. */
+  int64_t edge_window_bytes; /* 0 (default): kbisim_create copies the edge table into device
+                          memory. > 0: graphs whose edge table is to stay out of device
+                          memory (the paper's setting of a graph larger than the fast
+                          memory, Section 2.2): the table, given in host memory
+                          (KBISIM_MEM_HOST), is read in chunks and kept as CSR edge words
+                          in pinned host memory, cut into partitions of consecutive source
+                          nodes; every round moves the partitions through two device
+                          windows of at most edge_window_bytes / 2 each (copies overlap the
+                          signature launch of the previous partition), or, in rounds with
+                          few active nodes, reads their rows in place. Device memory then
+                          holds per edge only the round's signature keys. Needs a window
+                          of at least twice the longest row's edge words (4 bytes, or 8
+                          when label rank and target id need more than 32 bits), edge
+                          labels below 2^24 and history = 0; kbisim_create only.
+                          Results are the same as without it. */
 } kbisim_options;
 
 /* Fills *opt with the defaults above. */
@@ -185,6 +200,13 @@ typedef struct {
  * (an endpoint outside [0, N + num_new_nodes), a negative label) is
  * KBISIM_EINVAL and leaves the handle unchanged. *rounds_done may be NULL. */
 kbisim_status kbisim_update(kbisim_graph* g, const kbisim_update_desc* u, int32_t* rounds_done);
+
+/* Streamed edge table (edge_window_bytes > 0): number of partitions, bytes of
+   the edge table moved host -> device by the rounds so far, and rounds that
+   read their active rows in place instead. All zero for other graphs. Any
+   out-parameter may be NULL. */
+kbisim_status kbisim_stream_stats(const kbisim_graph* g, int64_t* partitions, int64_t* bytes_moved,
+                                  int32_t* direct_rounds);
 
 /* Work of the last kbisim_update: rounds brought up to date level by level,
  * the first round recomputed in full instead (0 if none: when a round's

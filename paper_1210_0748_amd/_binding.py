@@ -35,7 +35,7 @@ class GraphDesc(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("early_stop", ctypes.c_int32), ("profile", ctypes.c_int32),
                 ("medium_cap", ctypes.c_int32), ("history", ctypes.c_int32),
-                ("update_mode", ctypes.c_int32)]
+                ("update_mode", ctypes.c_int32), ("edge_window_bytes", ctypes.c_int64)]
 
 
 class UpdateDesc(ctypes.Structure):
@@ -76,6 +76,8 @@ def load_library():
     lib.kbisim_refine_static.argtypes = [ctypes.POINTER(GraphDesc), i32, ctypes.POINTER(Options), vp, ctypes.c_int,
                                          ctypes.POINTER(i64), ctypes.POINTER(i32)]
     lib.kbisim_refine_static.restype = ctypes.c_int
+    lib.kbisim_stream_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32)]
+    lib.kbisim_stream_stats.restype = ctypes.c_int
     lib.kbisim_result_round.argtypes = [vp, i32, vp, ctypes.c_int, ctypes.POINTER(i64)]
     lib.kbisim_result_round.restype = ctypes.c_int
     lib.kbisim_update.argtypes = [vp, ctypes.POINTER(UpdateDesc), ctypes.POINTER(i32)]
@@ -178,8 +180,10 @@ def _arrays(node_label, src, elab, dst):
 
 
 def kbisim_create(num_nodes, node_label, src, elab, dst, *, stream=None, early_stop=True,
-                  profile=False, medium_cap=None, history=False, update_mode=0):
-    """Creates a device-resident graph handle (see kbisim.h). Returns the handle."""
+                  profile=False, medium_cap=None, history=False, update_mode=0, edge_window_bytes=0):
+    """Creates a device-resident graph handle (see kbisim.h). Returns the handle.
+    edge_window_bytes > 0 keeps the edge table (host arrays) in host memory and
+    streams it through device windows of that total size every round."""
     lib = load_library()
     mem, ptrs, keep = _arrays(node_label, src, elab, dst)
     n, m = int(num_nodes), int(keep[1].shape[0])
@@ -193,11 +197,20 @@ def kbisim_create(num_nodes, node_label, src, elab, dst, *, stream=None, early_s
     opt.profile = 1 if profile else 0
     opt.history = 1 if history else 0
     opt.update_mode = int(update_mode)
+    opt.edge_window_bytes = int(edge_window_bytes)
     if medium_cap is not None:
         opt.medium_cap = int(medium_cap)
     h = ctypes.c_void_p()
     _check(lib.kbisim_create(ctypes.byref(desc), ctypes.byref(opt), ctypes.byref(h)))
     return h
+
+
+def kbisim_stream_stats(handle):
+    """(partitions, bytes of the edge table moved host->device by the rounds,
+    rounds that read their active rows in place) of a streamed graph."""
+    p, b, d = ctypes.c_int64(0), ctypes.c_int64(0), ctypes.c_int32(0)
+    _check(load_library().kbisim_stream_stats(handle, ctypes.byref(p), ctypes.byref(b), ctypes.byref(d)))
+    return int(p.value), int(b.value), int(d.value)
 
 
 def kbisim_refine(handle, k):

@@ -91,6 +91,7 @@ struct Options {
   bool history = false;  // keep pId_0..pId_rounds and the maintenance state (reverse CSR, label values)
   int update_mode = 0;   // rounds of an update: 0 chosen by cost, 1 level by level, 2 in full
   uint32_t medium_cap = kDefaultMediumCap;  // groups above this size use the global passes
+  uint64_t edge_window = 0;  // > 0: the edge table stays in host memory, streamed through this many bytes
 };
 
 // One change to a graph handle's graph (the maintenance of Section 4): new
@@ -143,6 +144,14 @@ class Engine {
 
   // desc arrays: device pointers (copies already made by the caller if host)
   void build(const int32_t* node_label, const int32_t* src, const int32_t* lab, const int32_t* dst);
+  // the same with the edge table in host memory, kept there (pinned) and
+  // streamed through a device window of opt.edge_window bytes every round
+  void build_streamed(const int32_t* node_label_dev, const int32_t* src, const int32_t* lab, const int32_t* dst);
+  void stream_stats(int64_t* partitions, int64_t* bytes_moved, int32_t* direct_rounds) const {
+    if (partitions) *partitions = streamed_ ? int64_t(part_node_.size()) - 1 : 0;
+    if (bytes_moved) *bytes_moved = int64_t(streamed_bytes_);
+    if (direct_rounds) *direct_rounds = int32_t(direct_rounds_);
+  }
   // Runs rounds until `k` rounds are done or the fixed point is hit.
   void refine(int32_t k);
   // Dense ids of the current partition (pId of the last round done).
@@ -198,6 +207,16 @@ class Engine {
   uint32_t num_edge_labels() const { return n_elab_; }
 
  private:
+  void build_nodes(const int32_t* node_label, uint32_t max_nlab, const unsigned long long* masks,
+                   const uint64_t* mask_host);
+  void set_edge_layout();
+  void finish_build();
+  void degree_stats();
+  template <typename AdjT>
+  void stream_adj(const int32_t* src, const int32_t* lab, const int32_t* dst, const uint32_t* rank_table,
+                  uint32_t rank_size);
+  template <typename AdjT, typename KeyT>
+  void streamed_signature(const void* sig_args, const void* sig_work);
   template <typename AdjT>
   void build_adj(const int32_t* src, const int32_t* lab, const int32_t* dst, const uint32_t* erank,
                  const uint32_t* rank_table, uint32_t* hist0);
@@ -305,6 +324,19 @@ class Engine {
   int32_t cls_round_ = -1;  // round whose class scan cls_ holds (-1: none)
   // round scratch
   DevBuf ukey_, ucnt_, head_, cls_, fl_, first_, scanpart_, radix_, part_, bm_, bmslot_;
+  DevBuf bstart_;  // during the build: start position of every k = 0 block (and N)
+  // streamed edge table (opt_.edge_window > 0): the CSR edge words in pinned
+  // host memory, cut into partitions of consecutive source nodes whose rows
+  // fit one of two device windows
+  bool streamed_ = false;
+  void* host_adj_ = nullptr;
+  std::vector<uint32_t> part_node_;  // partition p: nodes [part_node_[p], part_node_[p+1])
+  std::vector<uint64_t> part_edge_;  // and edges [part_edge_[p], part_edge_[p+1])
+  DevBuf win_[2];
+  hipStream_t copy_st_ = nullptr;
+  hipEvent_t win_full_[2] = {nullptr, nullptr}, win_free_[2] = {nullptr, nullptr};
+  uint64_t streamed_bytes_ = 0;  // host->device bytes of the edge table moved by the rounds
+  uint32_t direct_rounds_ = 0;   // rounds that read the rows of their active nodes in place
   DevBuf seg_start_, seg_size_, seg_depth_, seg_done_, cls_meta_;
   SegLists lists_b_[2];  // subgroup lists of alternate global passes
   DevBuf l_fd_, l_long_;

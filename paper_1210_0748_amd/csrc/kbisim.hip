@@ -20,6 +20,7 @@
 #include "common.h"
 #include "engine.h"
 #include "maintain.h"
+#include "stream.h"
 #include "refine.h"
 #include "scan_radix.h"
 #include "server.h"
@@ -53,6 +54,16 @@ Engine::~Engine() {
   }
   for (hipEvent_t e : {ev_side_[0], ev_side_[1], ev_big_[0], ev_big_[1], ev_main_, ev_join_, ev_join_big_})
     if (e) (void)hipEventDestroy(e);
+  if (copy_st_) {
+    (void)hipStreamSynchronize(copy_st_);
+    (void)hipStreamDestroy(copy_st_);
+  }
+  for (hipEvent_t e : {win_full_[0], win_full_[1], win_free_[0], win_free_[1]})
+    if (e) (void)hipEventDestroy(e);
+  if (host_adj_) {
+    (void)hipStreamSynchronize(st_);  // launches may still read the table in place
+    (void)hipHostFree(host_adj_);
+  }
 }
 
 // Streams for the resolvers (default priority, not synchronising with the
@@ -172,7 +183,14 @@ void Engine::build_adj(const int32_t* src, const int32_t* lab, const int32_t* ds
     adj_.ensure(sizeof(AdjT));
     KB_CHECK(hipMemsetAsync(rowptr_.p, 0, (N + 1) * 4, st_));
   }
-  // hubs: radix-sort space for rounds whose keys are too wide for bitmaps
+  degree_stats();
+}
+
+// Out-degree statistics from rowptr_: the hubs' radix-sort space (rounds
+// whose keys are too wide for bitmaps), their edge total and the largest
+// out-degree (synchronises).
+void Engine::degree_stats() {
+  const uint64_t N = uint64_t(n_);
   if (N) {
     DevBuf hd;
     hd.ensure((N + 1) * sizeof(uint32_t));
@@ -301,7 +319,36 @@ void Engine::build(const int32_t* node_label, const int32_t* src, const int32_t*
   if (words[0] & 2u) throw InvalidInput("negative edge label");
   if (words[0] & 4u) throw InvalidInput("negative node label");
   const uint32_t max_nlab = words[1], max_elab = words[2];
+  build_nodes(node_label, max_nlab, masks, mask_host);
 
+  // edge labels: dense ascending ranks
+  DevBuf etable, erank;
+  n_elab_ = label_ranks(lab, E, max_elab, masks + 4, mask_host + 4, etable, erank,
+                        opt_.history ? &elab_vals_ : nullptr);
+  set_edge_layout();
+  const uint32_t* er = erank.p ? erank.as<uint32_t>() : nullptr;
+  const uint32_t* et = etable.p ? etable.as<uint32_t>() : nullptr;
+  if (adj64_)
+    build_adj<uint64_t>(src, lab, dst, er, et, hist0.as<uint32_t>());
+  else
+    build_adj<uint32_t>(src, lab, dst, er, et, hist0.as<uint32_t>());
+  finish_build();
+}
+
+void Engine::set_edge_layout() {
+  const uint64_t N = uint64_t(n_);
+  lab_bits_ = n_elab_ > 1 ? bits_for(n_elab_ - 1) : 0;
+  dst_bits_ = bits_for(N > 1 ? N - 1 : 1);
+  adj64_ = dst_bits_ + lab_bits_ > 32;
+  key64_ = lab_bits_ + bits_for(N > 1 ? N - 1 : 1) > 32;
+}
+
+// Per-node state and the k = 0 partition from the node labels (validated,
+// largest label max_nlab, presence mask of labels below kMaskLabels on the
+// device and the host).
+void Engine::build_nodes(const int32_t* node_label, uint32_t max_nlab, const unsigned long long* masks,
+                         const uint64_t* mask_host) {
+  const uint64_t N = uint64_t(n_);
   const uint64_t N1 = std::max<uint64_t>(N, 1);
   pid_.ensure(N1 * 4);
   ord_.ensure(N1 * 4);
@@ -384,22 +431,14 @@ void Engine::build(const int32_t* node_label, const int32_t* src, const int32_t*
   fixed_ = false;
   dense_round_ = -1;
   cls_round_ = -1;
+  bstart_.swap(bstart);
+}
 
-  // edge labels: dense ascending ranks
-  DevBuf etable, erank;
-  n_elab_ = label_ranks(lab, E, max_elab, masks + 4, mask_host + 4, etable, erank,
-                        opt_.history ? &elab_vals_ : nullptr);
-  lab_bits_ = n_elab_ > 1 ? bits_for(n_elab_ - 1) : 0;
-  dst_bits_ = bits_for(N > 1 ? N - 1 : 1);
-  adj64_ = dst_bits_ + lab_bits_ > 32;
-  key64_ = lab_bits_ + bits_for(N > 1 ? N - 1 : 1) > 32;
-  const uint32_t* er = erank.p ? erank.as<uint32_t>() : nullptr;
-  const uint32_t* et = etable.p ? etable.as<uint32_t>() : nullptr;
-  if (adj64_)
-    build_adj<uint64_t>(src, lab, dst, er, et, hist0.as<uint32_t>());
-  else
-    build_adj<uint32_t>(src, lab, dst, er, et, hist0.as<uint32_t>());
-
+// Per-round buffers and the first round's active set, once the CSR, the
+// degree statistics and the k = 0 blocks (bstart_) are in place.
+void Engine::finish_build() {
+  const uint64_t N = uint64_t(n_), E = uint64_t(m_);
+  const uint64_t N1 = std::max<uint64_t>(N, 1);
   // per-round buffers
   hub_off_.ensure((E / (uint64_t(kBlockMaxDeg) + 1) + 2) * 4);
   ukey_.ensure(std::max<uint64_t>(E, 1) * (key64_ ? 8 : 4));
@@ -410,8 +449,8 @@ void Engine::build(const int32_t* node_label, const int32_t* src, const int32_t*
   if (N) {
     const uint32_t med = std::min(medium_cap(), kMediumCapSmall), big = medium_cap();
     KB_CHECK(hipMemsetAsync(act_.size.p, 0, (uint64_t(B_) + 1) * 4, st_));
-    compact<kSegClasses>(BlockSegOf{bstart.as<uint32_t>(), med, big},
-                         BlockSegWrite{bstart.as<uint32_t>(), act_.start.as<uint32_t>(), act_.size.as<uint32_t>(),
+    compact<kSegClasses>(BlockSegOf{bstart_.as<uint32_t>(), med, big},
+                         BlockSegWrite{bstart_.as<uint32_t>(), act_.start.as<uint32_t>(), act_.size.as<uint32_t>(),
                                        act_.depth.as<uint32_t>()},
                          uint32_t(B_), nullptr, compact_scratch(compact_part_words<kSegClasses>(B_)),
                          info_.as<uint32_t>() + kInfoSeg, st_);
@@ -424,6 +463,7 @@ void Engine::build(const int32_t* node_label, const int32_t* src, const int32_t*
     build_reverse();
   }
   KB_CHECK(hipStreamSynchronize(st_));
+  bstart_.release();
 }
 
 uint32_t Engine::medium_cap() const { return opt_.medium_cap; }
@@ -852,7 +892,7 @@ void Engine::round_impl(bool first) {
     // wide keys: all hubs in one device-wide sort by (hub, key) when that
     // fits 64 bits, else one workgroup per hub
     const int hub_bits = bits_for(w.nh > 1 ? w.nh - 1 : 1);
-    if (hub_bits + key_bits <= 64) {
+    if (hub_bits + key_bits <= 64 && !streamed_) {  // (the device-wide sort reads every hub's row at once)
       if (hub_bits + key_bits <= 32)
         hub_sort<AdjT, KeyT, uint32_t>(&a, w.hl, w.nh, key_bits);
       else
@@ -875,8 +915,12 @@ void Engine::round_impl(bool first) {
     KB_LAUNCH_CHECK();
   }
   const int ev = ev_begin(0);
-  signature_k<AdjT, KeyT><<<w.grid(), kSigNT, 0, st_>>>(a, w);
-  KB_LAUNCH_CHECK();
+  if (streamed_) {
+    streamed_signature<AdjT, KeyT>(&a, &w);
+  } else {
+    signature_k<AdjT, KeyT><<<w.grid(), kSigNT, 0, st_>>>(a, w);
+    KB_LAUNCH_CHECK();
+  }
   if (w.bm && w.nh && w.hub_units > 1) {
     sig_hub_list_k<AdjT, KeyT><<<w.nh, kSigNT, 0, st_>>>(a, w);
     KB_LAUNCH_CHECK();
@@ -1009,6 +1053,7 @@ void Engine::result(int32_t* pid_out, bool to_device) {
 
 
 #include "maintain_engine.h"
+#include "stream_engine.h"
 
 // ---------------------------------------------------------------------------
 // Batched form.
@@ -1547,6 +1592,7 @@ void kbisim_options_default(kbisim_options* opt) {
   opt->medium_cap = int32_t(kb::kDefaultMediumCap);
   opt->history = 0;
   opt->update_mode = 0;
+  opt->edge_window_bytes = 0;
 }
 
 static kbisim_status parse_options(const kbisim_options* opt, kb::Options* o) {
@@ -1559,6 +1605,8 @@ static kbisim_status parse_options(const kbisim_options* opt, kb::Options* o) {
   o->history = opt->history != 0;
   if (opt->update_mode < 0 || opt->update_mode > 2) return fail(KBISIM_EINVAL, "update_mode outside [0, 2]");
   o->update_mode = opt->update_mode;
+  if (opt->edge_window_bytes < 0) return fail(KBISIM_EINVAL, "edge_window_bytes < 0");
+  o->edge_window = uint64_t(opt->edge_window_bytes);
   return KBISIM_OK;
 }
 
@@ -1573,13 +1621,21 @@ kbisim_status kbisim_create(const kbisim_graph_desc* d, const kbisim_options* op
   if (d->mem != KBISIM_MEM_HOST && d->mem != KBISIM_MEM_DEVICE) return fail(KBISIM_EINVAL, "bad mem kind");
   kb::Options o;
   if (parse_options(opt, &o) != KBISIM_OK) return KBISIM_EINVAL;
+  if (o.edge_window > 0 && d->mem != KBISIM_MEM_HOST)
+    return fail(KBISIM_EINVAL, "edge_window_bytes needs the edge table in host memory (KBISIM_MEM_HOST)");
+  if (o.edge_window > 0 && o.history) return fail(KBISIM_EINVAL, "edge_window_bytes with history = 1");
   return guarded([&]() {
     hipStream_t s = static_cast<hipStream_t>(d->stream);
     kb::StreamScope scope(s);
     auto* eng = new kb::Engine(d->num_nodes, d->num_edges, s, o);
     try {
       const uint64_t N = uint64_t(d->num_nodes), E = uint64_t(d->num_edges);
-      if (d->mem == KBISIM_MEM_HOST) {
+      if (o.edge_window > 0) {
+        kb::DevBuf nl;
+        nl.ensure(std::max<uint64_t>(N, 1) * 4);
+        if (N) KB_CHECK(hipMemcpyAsync(nl.p, d->node_label, N * 4, hipMemcpyHostToDevice, s));
+        eng->build_streamed(nl.as<int32_t>(), d->edge_src, d->edge_label, d->edge_dst);
+      } else if (d->mem == KBISIM_MEM_HOST) {
         kb::DevBuf nl, sr, lb, ds;
         nl.ensure(std::max<uint64_t>(N, 1) * 4);
         sr.ensure(std::max<uint64_t>(E, 1) * 4);
@@ -1623,6 +1679,7 @@ kbisim_status kbisim_refine_static(const kbisim_graph_desc* d, int32_t k, const 
     return fail(KBISIM_ENOMEM, "graph too large for the static scratch region (KBISIM_STATIC_SCRATCH_BYTES)");
   kb::Options o;
   if (parse_options(opt, &o) != KBISIM_OK) return KBISIM_EINVAL;
+  if (o.edge_window > 0) return fail(KBISIM_EINVAL, "edge_window_bytes applies to kbisim_create only");
   o.profile = false;
   o.history = false;
   return guarded([&]() {
@@ -1754,6 +1811,13 @@ kbisim_status kbisim_update(kbisim_graph* g, const kbisim_update_desc* u, int32_
   });
 }
 
+kbisim_status kbisim_stream_stats(const kbisim_graph* g, int64_t* partitions, int64_t* bytes_moved,
+                                  int32_t* direct_rounds) {
+  if (!g) return fail(KBISIM_EINVAL, "null handle");
+  g->eng->stream_stats(partitions, bytes_moved, direct_rounds);
+  return KBISIM_OK;
+}
+
 kbisim_status kbisim_update_stats(const kbisim_graph* g, int64_t* levels, int64_t* full_from, int64_t* rechecked,
                                   int64_t* recomputed, int64_t* changed) {
   if (!g || !g->eng) return fail(KBISIM_EINVAL, "null handle");
@@ -1826,6 +1890,7 @@ kbisim_status kbisim_batch_create(int32_t num_graphs, const int64_t* node_off, c
   if (d->mem != KBISIM_MEM_HOST && d->mem != KBISIM_MEM_DEVICE) return fail(KBISIM_EINVAL, "bad mem kind");
   kb::Options o;
   if (parse_options(opt, &o) != KBISIM_OK) return KBISIM_EINVAL;
+  if (o.edge_window > 0) return fail(KBISIM_EINVAL, "edge_window_bytes applies to kbisim_create only");
   return guarded([&]() {
     hipStream_t s = static_cast<hipStream_t>(d->stream);
     auto* b = new kb::Batch(num_graphs, node_off, edge_off, d->node_label, d->edge_src, d->edge_label, d->edge_dst,
@@ -1872,6 +1937,7 @@ kbisim_status kbisim_server_create(uint64_t hbm_budget_bytes, int32_t max_slots,
   if (hbm_budget_bytes == 0) return fail(KBISIM_EINVAL, "zero budget");
   kb::Options o;
   if (parse_options(opt, &o) != KBISIM_OK) return KBISIM_EINVAL;
+  if (o.edge_window > 0) return fail(KBISIM_EINVAL, "edge_window_bytes applies to kbisim_create only");
   o.profile = false;
   return guarded([&]() {
     auto* h = new kbisim_server;

@@ -95,7 +95,11 @@ struct SigWork {
   uint32_t hub_units;     // workgroups per hub (bitmap rounds; else 1)
   uint32_t hub_chunk;     // edges per unit
   int key_bits;
+  // nodes outside [node_lo, node_hi) are skipped: a launch over one
+  // partition of a streamed edge table, whose rows alone are in the window
+  uint32_t node_lo = 0, node_hi = 0xffffffffu;
 
+  __host__ __device__ bool in(uint32_t n) const { return n >= node_lo && n < node_hi; }
   static constexpr uint32_t kWavesPerUnit = kSigNT / kWave;
   __host__ __device__ uint32_t hub_slot0() const { return nm + nb; }
   // two wave-list entries per wave (sig_wave_pair)
@@ -693,6 +697,7 @@ __global__ __launch_bounds__(kSigNT) void signature_k(SigArgs<AdjT, KeyT> a, Sig
   if (b < w.nh * w.hub_units) {
     const uint32_t h = b / w.hub_units;
     const uint32_t n = w.hl[h];
+    if (!w.in(n)) return;
     if (w.bm)
       sig_bitmap_node(a, n, w, w.hub_slot0() + h, b % w.hub_units, w.hub_units, lds.bm.bits[0], lds.bm.shs);
     else
@@ -703,9 +708,11 @@ __global__ __launch_bounds__(kSigNT) void signature_k(SigArgs<AdjT, KeyT> a, Sig
   if (b < w.block_units()) {
     if (w.bm) {
       const uint32_t bi = b * (kSigNT / kWave) + threadIdx.x / kWave;
-      if (bi < w.nm + w.nb)
-        sig_bitmap_wave_node(a, bi < w.nm ? w.ml[bi] : w.bl[bi - w.nm], w, bi, lds.bm.bits[threadIdx.x / kWave]);
-    } else {
+      if (bi < w.nm + w.nb) {
+        const uint32_t n = bi < w.nm ? w.ml[bi] : w.bl[bi - w.nm];
+        if (w.in(n)) sig_bitmap_wave_node(a, n, w, bi, lds.bm.bits[threadIdx.x / kWave]);
+      }
+    } else if (w.in(w.bl[b])) {
       sig_block_node(a, w.bl[b], lds.block, shc);
     }
     return;
@@ -713,22 +720,31 @@ __global__ __launch_bounds__(kSigNT) void signature_k(SigArgs<AdjT, KeyT> a, Sig
   b -= w.block_units();
   if (b < w.mid_units()) {
     const uint32_t mi = b * (kSigNT / kWave) + threadIdx.x / kWave;
-    if (mi < w.nm) sig_mid_node(a, w.ml[mi]);
+    if (mi < w.nm && w.in(w.ml[mi])) sig_mid_node(a, w.ml[mi]);
     return;
   }
   b -= w.mid_units();
   if (b < w.wave_units()) {
     const uint32_t wi = 2 * (b * (kSigNT / kWave) + threadIdx.x / kWave);
-    if (wi < w.nw) sig_wave_pair(a, w.wl[wi], wi + 1 < w.nw ? w.wl[wi + 1] : kNone);
+    if (wi < w.nw) {
+      uint32_t n0 = w.wl[wi], n1 = wi + 1 < w.nw ? w.wl[wi + 1] : kNone;
+      if (n1 != kNone && !w.in(n1)) n1 = kNone;
+      if (!w.in(n0)) {
+        n0 = n1;
+        n1 = kNone;
+      }
+      if (n0 != kNone) sig_wave_pair(a, n0, n1);
+    }
     return;
   }
   b -= w.wave_units();
   const uint32_t j = b * kSigNT + threadIdx.x;
   uint32_t n = kNone;
   if (w.dense) {
-    if (j < w.n_nodes && w.actr[j] == w.tag) n = j;
+    if (j < w.n_nodes && w.in(j) && w.actr[j] == w.tag) n = j;
   } else if (j < w.nact) {
     n = w.anode[j];
+    if (!w.in(n)) n = kNone;
   }
   sig_thread_wave(a, n, lds.th);
 }
