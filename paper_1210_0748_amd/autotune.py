@@ -1,20 +1,27 @@
-"""Autotuner for the ordering kernels' size split (medium_cap).
+"""Autotuner for the ordering's LDS sort tile (medium_cap).
 
 Groups of up to 64 members are ordered by one wave, groups of up to
-`medium_cap` members by one workgroup in LDS, larger groups by global radix
-passes. The best split depends on the workload's block-size distribution, so
-the tuner times a refinement of a sample of the workload with every
-candidate and keeps the fastest. Results are cached in a JSON file keyed by
-GPU architecture and a coarse workload class; ids never depend on the choice.
+`medium_cap` members by one workgroup sorting them in an LDS tile, larger
+groups by global radix passes. The best split depends on the workload's
+block-size distribution, so the tuner times a refinement of a sample of the
+workload with every candidate, several times, interleaved (so drift hits all
+candidates alike), and compares medians. A candidate replaces the library's
+default only when its median beats the default's by more than the noise (the
+larger of MIN_GAIN and twice the default's relative spread); otherwise the
+default stays. Results are cached in a JSON file keyed by GPU architecture
+and a coarse workload class; ids never depend on the choice.
 """
 from __future__ import annotations
 
 import json
 import math
 import os
+import statistics
 import time
 
 CANDIDATES = (64, 512, 1024, 4096)
+DEFAULT = 4096
+MIN_GAIN = 0.03
 
 
 def _cache_path():
@@ -59,31 +66,48 @@ def _store(table):
         pass  # a read-only cache location only costs re-tuning
 
 
-def tune_medium_cap(graphs, k, sample_edges=20_000_000, repeats=2, device="cuda:0", use_cache=True):
-    """Returns (best medium_cap, {candidate: seconds}) for refining `graphs`
-    as one batch with k rounds; times a prefix of the graphs holding about
-    `sample_edges` edges."""
+def choose(runs, default=DEFAULT):
+    """runs: {candidate: [seconds, ...]}. The fastest candidate by median if
+    it beats the default's median by more than the noise (the larger of
+    MIN_GAIN and twice the default's median absolute deviation, relative),
+    else the default. Returns (choice, report)."""
+    med = {c: statistics.median(v) for c, v in runs.items()}
+    mad = {c: statistics.median(abs(x - med[c]) for x in v) for c, v in runs.items()}
+    noise = max(MIN_GAIN, 2.0 * mad[default] / med[default])
+    best = min(med, key=med.get)
+    choice = best if med[best] < med[default] * (1.0 - noise) else default
+    report = {"median_s": {str(c): med[c] for c in runs}, "spread_s": {str(c): mad[c] for c in runs},
+              "noise": noise, "fastest": best, "kept_default": choice == default}
+    return choice, report
+
+
+def tune_medium_cap(graphs, k, sample_edges=20_000_000, repeats=5, device="cuda:0", use_cache=True):
+    """Returns (chosen medium_cap, report) for refining `graphs` as one batch
+    with k rounds; times a prefix of the graphs holding about `sample_edges`
+    edges. report: per candidate the median and spread (median absolute
+    deviation) in seconds, the noise threshold and whether the default was
+    kept."""
     from . import refine_batch
     key = "%s/%s/k%d" % (_arch(), workload_class(graphs), int(k))
     table = _load() if use_cache else {}
     if key in table:
-        return int(table[key]["best"]), table[key]["times"]
+        return int(table[key]["best"]), table[key]["report"]
     sample, acc = [], 0
     for g in graphs:
         sample.append(g)
         acc += len(g.src)
         if acc >= sample_edges:
             break
-    times = {}
-    for cap in CANDIDATES:
-        best = float("inf")
-        for _ in range(repeats):
+    refine_batch(sample, k, device=device)  # warm the allocator and the code
+    runs = {c: [] for c in CANDIDATES}
+    for _ in range(repeats):
+        for cap in CANDIDATES:
             t0 = time.perf_counter()
             refine_batch(sample, k, device=device, medium_cap=cap)
-            best = min(best, time.perf_counter() - t0)
-        times[str(cap)] = best
-    choice = int(min(times, key=times.get))
-    table[key] = {"best": choice, "times": times}
+            runs[cap].append(time.perf_counter() - t0)
+    choice, report = choose(runs)
+    report.update(repeats=repeats, sample_graphs=len(sample), sample_edges=acc)
+    table[key] = {"best": choice, "report": report}
     if use_cache:
         _store(table)
-    return choice, times
+    return choice, report

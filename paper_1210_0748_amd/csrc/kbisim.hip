@@ -1329,52 +1329,138 @@ void Server::worker(int slot) {
   (void)hipSetDevice(device_);
   hipStream_t s = streams_[size_t(slot)];
   for (;;) {
-    std::shared_ptr<Request> r;
+    std::vector<std::shared_ptr<Request>> group;
     {
       std::unique_lock<std::mutex> lk(mu_);
       cv_work_.wait(lk, [&] {
         return stop_ || (!queue_.empty() && in_use_ + queue_.front()->footprint <= budget_);
       });
       if (stop_) return;
-      r = queue_.front();
+      group.push_back(queue_.front());
       queue_.pop_front();
-      in_use_ += r->footprint;
-      r->state = Request::kRunning;
-      r->t_start = std::chrono::steady_clock::now();
-    }
-    int status = 0;
-    std::string err;
-    bool cancelled = false;
-    try {
-      run(*r, s);
-    } catch (const Cancelled&) {
-      cancelled = true;
-    } catch (const InvalidInput& e) {
-      status = KBISIM_EINVAL;
-      err = e.what();
-    } catch (const OutOfMemory& e) {
-      status = KBISIM_ENOMEM;
-      err = e.what();
-    } catch (const std::exception& e) {
-      status = KBISIM_EDEVICE;
-      err = e.what();
-    }
-    {
-      std::lock_guard<std::mutex> lk(mu_);
-      in_use_ -= r->footprint;
-      r->t_end = std::chrono::steady_clock::now();
-      r->status = status;
-      r->error = err;
-      r->state = cancelled ? Request::kCancelled : status ? Request::kFailed : Request::kDone;
-      for (auto& h : r->host) std::vector<int32_t>().swap(h);  // inputs no longer needed
-      if (r->ready) {
-        (void)hipEventDestroy(r->ready);
-        r->ready = nullptr;
+      in_use_ += group[0]->footprint;
+      // small requests right behind a small head join it
+      int64_t edges = group[0]->m;
+      while (group[0]->m <= kServeSmallEdges && !queue_.empty() && group.size() < kServeGroupMax) {
+        const std::shared_ptr<Request>& q = queue_.front();
+        if (q->m > kServeSmallEdges || edges + q->m > kServeGroupEdges || in_use_ + q->footprint > budget_) break;
+        edges += q->m;
+        in_use_ += q->footprint;
+        group.push_back(q);
+        queue_.pop_front();
+      }
+      const auto now = std::chrono::steady_clock::now();
+      for (auto& r : group) {
+        r->state = Request::kRunning;
+        r->t_start = now;
       }
     }
-    cv_done_.notify_all();
-    cv_work_.notify_all();  // memory came back: the queue head may fit now
+    bool alone = group.size() == 1;
+    if (!alone) {
+      try {
+        alone = !run_group(group, s);
+      } catch (const std::exception& e) {
+        for (auto& r : group) finish(*r, KBISIM_EDEVICE, e.what(), false);
+        continue;
+      }
+      if (!alone) continue;
+    }
+    for (auto& r : group) {  // one at a time (also after a rejected union)
+      int status = 0;
+      std::string err;
+      bool cancelled = false;
+      try {
+        run(*r, s);
+      } catch (const Cancelled&) {
+        cancelled = true;
+      } catch (const InvalidInput& e) {
+        status = KBISIM_EINVAL;
+        err = e.what();
+      } catch (const OutOfMemory& e) {
+        status = KBISIM_ENOMEM;
+        err = e.what();
+      } catch (const std::exception& e) {
+        status = KBISIM_EDEVICE;
+        err = e.what();
+      }
+      finish(*r, status, err, cancelled);
+    }
   }
+}
+
+void Server::finish(Request& r, int status, const std::string& err, bool cancelled) {
+  {
+    std::lock_guard<std::mutex> lk(mu_);
+    in_use_ -= r.footprint;
+    r.t_end = std::chrono::steady_clock::now();
+    r.status = status;
+    r.error = err;
+    r.state = cancelled ? Request::kCancelled : status ? Request::kFailed : Request::kDone;
+    for (auto& h : r.host) std::vector<int32_t>().swap(h);  // inputs no longer needed
+    if (r.ready) {
+      (void)hipEventDestroy(r.ready);
+      r.ready = nullptr;
+    }
+  }
+  cv_done_.notify_all();
+  cv_work_.notify_all();  // memory came back: the queue head may fit now
+}
+
+bool Server::run_group(std::vector<std::shared_ptr<Request>>& group, hipStream_t s) {
+  StreamScope scope(s);
+  const int32_t G = int32_t(group.size());
+  std::vector<int64_t> noff(G + 1, 0), eoff(G + 1, 0);
+  std::vector<int32_t> ks(G);
+  for (int32_t g = 0; g < G; ++g) {
+    noff[g + 1] = noff[g] + group[g]->n;
+    eoff[g + 1] = eoff[g] + group[g]->m;
+    ks[g] = group[g]->k;
+  }
+  const uint64_t N = uint64_t(noff[G]), E = uint64_t(eoff[G]);
+  // the requests' inputs, concatenated in device memory (graph-local ids)
+  DevBuf cat[4];
+  const uint64_t tot[4] = {N, E, E, E};
+  for (int i = 0; i < 4; ++i) cat[i].ensure(std::max<uint64_t>(tot[i], 1) * 4);
+  for (int32_t g = 0; g < G; ++g) {
+    Request& r = *group[g];
+    const uint64_t len[4] = {uint64_t(r.n), uint64_t(r.m), uint64_t(r.m), uint64_t(r.m)};
+    const uint64_t at[4] = {uint64_t(noff[g]), uint64_t(eoff[g]), uint64_t(eoff[g]), uint64_t(eoff[g])};
+    if (r.device_inputs) KB_CHECK(hipStreamWaitEvent(s, r.ready, 0));
+    for (int i = 0; i < 4; ++i) {
+      if (!len[i]) continue;
+      int32_t* to = cat[i].as<int32_t>() + at[i];
+      if (r.device_inputs)
+        KB_CHECK(hipMemcpyAsync(to, r.dev[i], len[i] * 4, hipMemcpyDeviceToDevice, s));
+      else
+        KB_CHECK(hipMemcpyAsync(to, r.host[i].data(), len[i] * 4, hipMemcpyHostToDevice, s));
+    }
+  }
+  std::unique_ptr<Batch> b;
+  try {
+    b.reset(new Batch(G, noff.data(), eoff.data(), cat[0].as<int32_t>(), cat[1].as<int32_t>(),
+                      cat[2].as<int32_t>(), cat[3].as<int32_t>(), false, s, opt_));
+  } catch (const InvalidInput&) {
+    KB_CHECK(hipStreamSynchronize(s));  // the copies out of the requests' inputs are done
+    return false;
+  }
+  b->refine(ks);
+  std::vector<int32_t> pid(std::max<uint64_t>(N, 1));
+  std::vector<int64_t> blocks(G);
+  std::vector<int32_t> rounds(G);
+  b->result(N ? pid.data() : nullptr, false, blocks.data(), rounds.data());
+  for (int32_t g = 0; g < G; ++g) {
+    Request& r = *group[g];
+    r.pid.assign(pid.begin() + noff[g], pid.begin() + noff[g + 1]);
+    r.counts.assign(1, blocks[g]);
+    r.rounds = rounds[g];
+    bool cancelled;
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      cancelled = r.cancel;
+    }
+    finish(r, 0, std::string(), cancelled);
+  }
+  return true;
 }
 
 void Server::run(Request& r, hipStream_t s) {

@@ -24,9 +24,19 @@
 #include <thread>
 #include <vector>
 
+#include "batch.h"
 #include "engine.h"
 
 namespace kb {
+
+// Small requests share launches: a worker that takes a small request from
+// the queue head also takes the small requests queued right behind it (up to
+// kServeGroupEdges edges and kServeGroupMax requests in all, within the
+// budget) and refines them as one disjoint union (the batched form, each
+// with its own k); every request's ids are those of a run on its own graph.
+constexpr int64_t kServeSmallEdges = int64_t(1) << 21;
+constexpr int64_t kServeGroupEdges = int64_t(1) << 24;
+constexpr size_t kServeGroupMax = 256;
 
 // Device bytes a job of n nodes and m edges may hold at its peak: inputs
 // (12 m), the CSR sort's key and value buffers (16 m), the adjacency and the
@@ -80,6 +90,10 @@ class Server {
  private:
   void worker(int slot);
   void run(Request& r, hipStream_t s);
+  // several small requests as one union; false when the union was rejected
+  // as invalid input (the requests are then run one by one)
+  bool run_group(std::vector<std::shared_ptr<Request>>& group, hipStream_t s);
+  void finish(Request& r, int status, const std::string& err, bool cancelled);
 
   uint64_t budget_;
   int32_t slots_;

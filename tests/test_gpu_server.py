@@ -48,6 +48,34 @@ def test_mix_equals_alone():
             assert 0 <= q <= tot
 
 
+def test_many_small_requests_share_launches():
+    """Sixty small requests queued at once behind one slot: after the first,
+    the worker takes the small ones queued behind the head together and
+    refines them as one union (each with its own k, host and device inputs
+    mixed, an empty graph among them); every result equals the oracle's run
+    on that graph alone."""
+    torch, kb = need_gpu()
+    rng = np.random.default_rng(11)
+    gs, ks = [], []
+    for i in range(60):
+        n = int(rng.integers(1, 3000)) if i != 17 else 0
+        e = int(rng.integers(0, 6 * n + 1)) if n else 0
+        gs.append(synth.uniform_graph(n, e, num_node_labels=3, num_edge_labels=4, seed=500 + i) if n else
+                  synth.Graph(0, np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.int32),
+                              np.zeros(0, np.int32), name="empty"))
+        ks.append(int(rng.integers(0, 8)))
+    with kb.Server(8 * GB, max_slots=1) as srv:
+        ids = []
+        for i, (g, k) in enumerate(zip(gs, ks)):
+            arrs = to_dev(torch, g) if i % 3 == 1 else (g.node_label, g.src, g.elab, g.dst)
+            ids.append(srv.submit(g.num_nodes, *arrs, k))
+        for rid, g, k in zip(ids, gs, ks):
+            out, nb, rd = srv.wait(rid, timeout_s=120)
+            r = oracle.refine(g.num_nodes, g.node_label, g.src, g.elab, g.dst, k)
+            assert np.array_equal(out, r.pid) and rd == r.rounds_done and nb == r.counts[-1], (rid, g.name, k)
+    say("60 small requests equal the oracle's runs")
+
+
 def test_small_budget_admits_one_at_a_time():
     torch, kb = need_gpu()
     gs = request_graphs()[:5]
