@@ -311,6 +311,7 @@ class Engine {
   int32_t rounds_ = 0;
   bool fixed_ = false;
   std::vector<int64_t> counts_;
+  std::vector<double> round_secs_;  // host seconds of round j as last computed in full (index j)
   // active set: segments (size classes), their positions and nodes, and the
   // signature work lists (wave, block, hub)
   SegLists act_;

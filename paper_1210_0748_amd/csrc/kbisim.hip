@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstdio>
 #include <mutex>
 #include <new>
@@ -947,6 +948,7 @@ void Engine::round_impl(bool first) {
 
 void Engine::run_round() {
   const int64_t B_old = B_;
+  const auto t0 = std::chrono::steady_clock::now();
   const int evr = ev_begin(3);
   if (M_act_ > 0) {
     const bool first = rounds_ == 0;
@@ -968,6 +970,10 @@ void Engine::run_round() {
   fixed_ = (B_ == B_old);
   if (opt_.history) save_level(rounds_);
   ev_collect();
+  // host time of the round (it ended with a read-back), for the update's
+  // choice between level by level and full rounds
+  if (round_secs_.size() <= size_t(rounds_)) round_secs_.resize(size_t(rounds_) + 1, 0.0);
+  round_secs_[size_t(rounds_)] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
 }
 
 void Engine::work_counts(uint64_t* out8) {

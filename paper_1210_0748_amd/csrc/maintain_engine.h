@@ -660,6 +660,9 @@ void Engine::update_core(const UpdateArgs& u) {
 // (re-ordered by signature), the other classes (split as stored), change
 // detection and the new stored round. The number of changed nodes at level
 // 0 is the number of new nodes (listed in clist_, tagged utag_).
+// Graphs from this many nodes on may switch to full rounds on measured times.
+constexpr uint32_t kTimedSwitchNodes = 1u << 20;
+
 template <typename AdjT, typename KeyT>
 void Engine::update_levels() {
   const uint32_t N = uint32_t(n_);
@@ -686,7 +689,14 @@ void Engine::update_levels() {
   const uint32_t med = std::min(medium_cap(), kMediumCapSmall), big = medium_cap();
   int32_t stop_at = -1;
   bool switched = false;
+  auto level_start = std::chrono::steady_clock::now();
+  double last_level_secs = 0.0;  // host time of the previous level, done level by level
   for (int32_t j = 1; j <= K; ++j) {
+    if (j > 1) {
+      const auto now = std::chrono::steady_clock::now();
+      last_level_secs = std::chrono::duration<double>(now - level_start).count();
+      level_start = now;
+    }
     const uint32_t T = ++utag_;
     KB_CHECK(hipMemsetAsync(cnt.p, 0, 32, st_));
     uint32_t* c = cnt.as<uint32_t>();
@@ -751,7 +761,15 @@ void Engine::update_levels() {
       if (opt_.update_mode == 2) return true;
       return fixed_cost + 2 * work > full_members;
     };
-    if (go_full(nr)) {
+    // The estimate's constant depends on the graph (a full round of
+    // identical subtrees is cheap to order); once a level has been done level
+    // by level, its measured time against the last full computation of round
+    // j can also send the rest to full rounds (on graphs large enough for
+    // the times to mean something, with a margin for their noise)
+    const bool slower_than_full = opt_.update_mode == 0 && j > 1 && N >= kTimedSwitchNodes &&
+                                  last_level_secs > 0.0 && size_t(j) < round_secs_.size() &&
+                                  round_secs_[size_t(j)] > 0.0 && last_level_secs > 1.2 * round_secs_[size_t(j)];
+    if (go_full(nr) || slower_than_full) {
       stop_at = j - 1;
       switched = true;
       ustat_.full_from = j;

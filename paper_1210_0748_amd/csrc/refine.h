@@ -274,7 +274,6 @@ __global__ __launch_bounds__(NT) void resolve_k(const uint32_t* __restrict__ gst
                                                 uint32_t* __restrict__ ord, uint8_t* __restrict__ flag,
                                                 KeyView<KeyT> kv) {
   static_assert(CAP < 65535 && CAP % NT == 0, "positions are 16-bit");
-  constexpr uint16_t kPad = 0xffffu;
   constexpr int kPer = CAP / NT;
   __shared__ uint32_t node[CAP];
   __shared__ uint32_t dep[CAP];
@@ -361,43 +360,52 @@ __global__ __launch_bounds__(NT) void resolve_k(const uint32_t* __restrict__ gst
         }
       }
     }
-    uint32_t P = 2;
-    while (P < n) P <<= 1;
-    for (uint32_t k = threadIdx.x; k < P; k += NT) perm[k] = k < n ? opos[k] : kPad;
+    for (uint32_t k = threadIdx.x; k < n; k += NT) perm[k] = opos[k];
     if (!__syncthreads_or(open)) break;  // what is still open consists of copies of its pivot
 
-    // (d) bitonic sort of the open list by (subgroup, side key, digits);
-    // padding sorts last. In a step of stride <= kWave the pairs of the
-    // threads of one wave lie inside the wave's own aligned runs of
-    // 2 * kWave entries (the same runs at every such stride), so between two
-    // such steps the wave only waits for its own LDS operations, which it
-    // performs in order; a workgroup barrier is needed only next to a step
-    // of a larger stride.
-    for (uint32_t size = 2; size <= P; size <<= 1) {
-      for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-        const uint32_t next = stride > 1 ? stride >> 1 : size;  // stride of the following step
-        for (uint32_t t = threadIdx.x; t < P / 2; t += NT) {
-          const uint32_t lo = 2 * t - (t & (stride - 1));
-          const uint32_t hi = lo + stride;
-          const bool up = (lo & size) == 0;
-          const uint32_t a = perm[lo], b = perm[hi];
-          bool gt;
-          if (a == kPad || b == kPad) {
-            gt = a == kPad && b != kPad;
-          } else {
-            gt = sub[a] != sub[b] ? sub[a] > sub[b] : hk[a] != hk[b] ? hk[a] > hk[b] : dig[a] > dig[b];
-          }
-          if (gt == up) {
-            perm[lo] = uint16_t(b);
-            perm[hi] = uint16_t(a);
-          }
+    // (d) stable merge sort of the open list by (subgroup, side key,
+    // digits): runs of width w = 1, 2, 4, ... merged pairwise, one
+    // workgroup barrier per level. Each thread writes a fixed range of
+    // outputs: it finds where its first output splits the pair's two runs
+    // (merge path: the number of entries of the first run among the first
+    // outputs, by binary search) and merges sequentially from there.
+    // Ping-pongs between perm and queue (free after the comparisons).
+    auto before = [&](uint32_t a, uint32_t b) {
+      return sub[a] != sub[b] ? sub[a] < sub[b] : hk[a] != hk[b] ? hk[a] < hk[b] : dig[a] < dig[b];
+    };
+    uint16_t* src = perm;
+    uint16_t* dst = queue;
+    const uint32_t per = (n + NT - 1) / NT;  // outputs per thread
+    for (uint32_t w = 1; w < n; w <<= 1) {
+      uint32_t o = threadIdx.x * per;
+      const uint32_t o_end = min(o + per, n);
+      while (o < o_end) {
+        const uint32_t base = o - o % (2 * w);  // the pair's first run starts here
+        const uint32_t a_len = min(w, n - base);
+        const uint32_t b_beg = base + a_len;
+        const uint32_t b_len = b_beg < n ? min(w, n - b_beg) : 0u;
+        const uint32_t diag = o - base;
+        uint32_t lo = diag > b_len ? diag - b_len : 0u, hi = min(diag, a_len);
+        while (lo < hi) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (!before(src[b_beg + diag - 1 - mid], src[base + mid]))
+            lo = mid + 1;
+          else
+            hi = mid;
         }
-        if (stride > kWave || next > kWave || (size == P && stride == 1))
-          __syncthreads();
-        else
-          __builtin_amdgcn_wave_barrier();
+        uint32_t i = lo, j = diag - lo;
+        const uint32_t stop = min(o_end, b_beg + b_len);
+        for (; o < stop; ++o) {
+          const bool take_a = i < a_len && (j >= b_len || !before(src[b_beg + j], src[base + i]));
+          dst[o] = take_a ? src[base + i++] : src[b_beg + j++];
+        }
       }
+      __syncthreads();
+      uint16_t* t = src;
+      src = dst;
+      dst = t;
     }
+    const uint16_t* sorted = src;
 
     // (e) move: the k-th open position receives the k-th member in order
     uint32_t tn[kPer], td[kPer];
@@ -406,11 +414,11 @@ __global__ __launch_bounds__(NT) void resolve_k(const uint32_t* __restrict__ gst
     for (int j = 0; j < kPer; ++j) {
       const uint32_t k = uint32_t(j) * NT + threadIdx.x;
       if (k < n) {
-        const uint32_t src = perm[k];
-        tn[j] = node[src];
-        td[j] = dep[src];
-        th[j] = hk[src];
-        tg[j] = dig[src];
+        const uint32_t from = sorted[k];
+        tn[j] = node[from];
+        td[j] = dep[from];
+        th[j] = hk[from];
+        tg[j] = dig[from];
       }
     }
     __syncthreads();
