@@ -860,7 +860,9 @@ void Engine::round_impl(bool first) {
   w.actr = actr_.as<uint32_t>();
   w.tag = tag_;
   w.n_nodes = N;
-  w.dense = act_dense_;
+  // the work lists were built in node order when many nodes could have been
+  // active; the thread part goes over all node ids only when many are
+  w.dense = act_dense_ && uint64_t(M_act_) * 8 >= uint64_t(n_);
   w.wl = lists + boff_[kBucketWave];
   w.nw = bcnt_[kBucketWave];
   w.ml = lists + boff_[kBucketMid];
