@@ -603,6 +603,12 @@ def bench_host_io(args, torch, kb):
             kb.kbisim_destroy(h)
         return rd, counts
 
+    # device memory one job holds: the library's cache after a job run from
+    # an empty cache (its blocks are reused within the job, so this is about
+    # the job's peak)
+    kb.kbisim_release_cached()
+    job()
+    device_bytes = kb.kbisim_release_cached()
     for _ in range(args.warmup):
         job()
     torch.cuda.synchronize()
@@ -623,6 +629,8 @@ def bench_host_io(args, torch, kb):
         "config": {"workload": args.workload, "num_nodes": g.num_nodes, "num_edges": g.num_edges, "k_cap": k,
                    "rounds": rd, "counts": counts, "host_io": args.host_io,
                    "bytes_in": in_bytes, "bytes_out": 4 * g.num_nodes, "edge_window_bytes": args.edge_window},
+        "device_bytes": device_bytes,
+        "device_bytes_per_edge": device_bytes / max(g.num_edges, 1),
     }
     if stats:
         line["streamed"] = stats
