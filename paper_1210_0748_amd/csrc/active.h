@@ -27,7 +27,8 @@ constexpr int kInfoClasses = kInfoBucket + 2 * kNumBuckets + 1;  // classes amon
 constexpr int kInfoItems = kInfoClasses + 1;         // positions of the next active segments
 constexpr int kInfoHubEdges = kInfoItems + 1;        // edges of the hubs in the hub list
 constexpr int kInfoLargeItems = kInfoHubEdges + 1;   // items in the large segments
-constexpr int kInfoWords = kInfoLargeItems + 1;
+constexpr int kInfoMaxDeg = kInfoLargeItems + 1;      // largest out-degree (after a build)
+constexpr int kInfoWords = kInfoMaxDeg + 1;
 
 // apos[j] = position of active item j, anode[j] = ord[apos[j]]; segment t of
 // the list covers positions [seg_s[t], seg_s[t] + size), soff is the

@@ -312,20 +312,29 @@ constexpr uint32_t kRowGap = 64;
 __global__ void csr_rowptr_k(const uint32_t* __restrict__ skey, uint64_t m, uint32_t n,
                              uint32_t* __restrict__ rowptr, uint32_t* __restrict__ gaps,
                              uint32_t* __restrict__ ngaps) {
-  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
-  for (uint64_t b = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; b <= m; b += kStreamUnroll * stride) {
-    uint32_t cur[kStreamUnroll], prev[kStreamUnroll];
+  // four consecutive positions per thread (one 16-byte load where they are
+  // all inside the array) plus the one before them
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x * 4;
+  for (uint64_t b = (uint64_t(blockIdx.x) * blockDim.x + threadIdx.x) * 4; b <= m; b += stride) {
+    uint32_t cur[4];
+    if (b + 4 <= m) {
+      const uint4 v = *reinterpret_cast<const uint4*>(skey + b);
+      cur[0] = v.x;
+      cur[1] = v.y;
+      cur[2] = v.z;
+      cur[3] = v.w;
+    } else {
 #pragma unroll
-    for (int q = 0; q < kStreamUnroll; ++q) {
-      const uint64_t p = b + q * stride;
-      cur[q] = p < m ? skey[p] : n;                   // past the end: source n
-      prev[q] = (p > 0 && p <= m) ? skey[p - 1] : 0u;  // before the start: no source
+      for (int q = 0; q < 4; ++q) cur[q] = b + q < m ? skey[b + q] : n;  // past the end: source n
     }
+    uint32_t prev = b > 0 ? skey[b - 1] : 0u;  // before the start: no source
 #pragma unroll
-    for (int q = 0; q < kStreamUnroll; ++q) {
-      const uint64_t p = b + q * stride;
-      if (p > m || (p > 0 && cur[q] == prev[q])) continue;
-      const uint32_t from = p == 0 ? 0u : prev[q] + 1, to = cur[q];
+    for (int q = 0; q < 4; ++q) {
+      const uint64_t p = b + q;
+      const uint32_t c = cur[q], pr = prev;
+      prev = c;
+      if (p > m || (p > 0 && c == pr)) continue;
+      const uint32_t from = p == 0 ? 0u : pr + 1, to = c;
       if (to - from < kRowGap) {
         for (uint32_t w = from; w <= to; ++w) rowptr[w] = uint32_t(p);
       } else {

@@ -212,6 +212,7 @@ class Engine {
   void set_edge_layout();
   void finish_build();
   void degree_stats();
+  void hub_layout();
   template <typename AdjT>
   void stream_adj(const int32_t* src, const int32_t* lab, const int32_t* dst, const uint32_t* rank_table,
                   uint32_t rank_size);
@@ -304,6 +305,8 @@ class Engine {
   uint32_t hub_edges_act_ = 0;
   uint64_t hub_edges_ = 0;
   uint32_t maxdeg_ = 0;  // largest out-degree
+  bool maxdeg_pending_ = false;  // maxdeg_ arrives with the next round summary
+  bool hub_toff_valid_ = false;  // hub_toff_ and hub_edges_ match the graph
   // partition state: ord, class-start flags, class-start position ids, and
   // the dense pId_0 used by the first round's keys
   DevBuf pid_, pid0_, ord_, flag_;

@@ -187,32 +187,39 @@ void Engine::build_adj(const int32_t* src, const int32_t* lab, const int32_t* ds
   degree_stats();
 }
 
-// Out-degree statistics from rowptr_: the hubs' radix-sort space (rounds
-// whose keys are too wide for bitmaps), their edge total and the largest
-// out-degree (synchronises).
+// The largest out-degree, into an info word the next round summary reads
+// back (no synchronisation here); the hubs' radix-sort space is laid out by
+// hub_layout when a round first needs it.
 void Engine::degree_stats() {
   const uint64_t N = uint64_t(n_);
+  hub_toff_valid_ = false;
+  maxdeg_ = 0;
+  if (!N) return;
+  uint32_t* w = info_.as<uint32_t>() + kInfoMaxDeg;
+  set_u32_k<<<1, 1, 0, st_>>>(w, 0u);
+  KB_LAUNCH_CHECK();
+  max_degree_k<<<std::min<uint32_t>(grid_for(N), 1024), kNT, 0, st_>>>(rowptr_.as<uint32_t>(), uint32_t(N), w);
+  KB_LAUNCH_CHECK();
+  maxdeg_pending_ = true;
+}
+
+// Offsets of the hubs' items (exclusive scan of the out-degrees above
+// kBlockMaxDeg) and their total (synchronises; once per graph).
+void Engine::hub_layout() {
+  if (hub_toff_valid_) return;
+  const uint64_t N = uint64_t(n_);
+  hub_toff_.ensure((N + 1) * sizeof(uint32_t));
+  hub_edges_ = 0;
   if (N) {
     DevBuf hd;
     hd.ensure((N + 1) * sizeof(uint32_t));
-    hub_toff_.ensure((N + 1) * sizeof(uint32_t));
     KB_CHECK(hipMemsetAsync(hd.as<uint32_t>() + N, 0, 4, st_));
     hub_degree_k<<<grid_for(N), kNT, 0, st_>>>(rowptr_.as<uint32_t>(), uint32_t(N), kBlockMaxDeg, hd.as<uint32_t>());
     KB_LAUNCH_CHECK();
     scan_dev<uint32_t, uint32_t, false>(hd.as<uint32_t>(), hub_toff_.as<uint32_t>(), N + 1);
-    KB_CHECK(hipMemsetAsync(hd.p, 0, 4, st_));
-    max_degree_k<<<std::min<uint32_t>(grid_for(N), 1024), kNT, 0, st_>>>(rowptr_.as<uint32_t>(), uint32_t(N),
-                                                                       hd.as<uint32_t>());
-    KB_LAUNCH_CHECK();
-    // both words in one read-back (synchronises: `hd` may be freed)
-    uint32_t* hw32 = reinterpret_cast<uint32_t*>(hw_.p);
-    hw32[0] = hw32[1] = 0;
-    KB_CHECK(hipMemcpyAsync(hw32, hub_toff_.as<uint32_t>() + N, 4, hipMemcpyDeviceToHost, st_));
-    KB_CHECK(hipMemcpyAsync(hw32 + 1, hd.p, 4, hipMemcpyDeviceToHost, st_));
-    KB_CHECK(hipStreamSynchronize(st_));
-    hub_edges_ = hw32[0];
-    maxdeg_ = hw32[1];
+    hub_edges_ = read_word(hub_toff_.as<uint32_t>() + N, 4);  // synchronises: `hd` may be freed
   }
+  hub_toff_valid_ = true;
 }
 
 // Dense ascending ranks of the label values `val[0..n)` (all >= 0, max
@@ -514,6 +521,10 @@ void Engine::prepare_active(uint32_t seg_items, uint32_t m_cap, uint32_t tag, bo
   for (int c = 0; c < kSegClasses; ++c) {
     act_.cnt[c] = h[kInfoSeg + c];
     act_.off[c] = h[kInfoSeg + kSegClasses + c];
+  }
+  if (maxdeg_pending_) {
+    maxdeg_ = h[kInfoMaxDeg];
+    maxdeg_pending_ = false;
   }
   S_act_ = h[kInfoSeg + 2 * kSegClasses];
   M_act_ = h[kInfoItems];
@@ -902,6 +913,7 @@ void Engine::round_impl(bool first) {
         hub_sort<AdjT, KeyT, uint64_t>(&a, w.hl, w.nh, key_bits);
       w.nh = 0;
     } else {
+      hub_layout();
       hub_tmp_.ensure(std::max<uint64_t>(hub_edges_, 1) * sizeof(KeyT));
       w.hub_tmp = hub_tmp_.p;
       w.hub_toff = hub_toff_.as<uint32_t>();

@@ -129,6 +129,8 @@ void Engine::graph_stats() {
   KB_CHECK(hipStreamSynchronize(st_));
   hub_edges_ = hw32[0];
   maxdeg_ = hw32[1];
+  hub_toff_valid_ = true;
+  maxdeg_pending_ = false;
 }
 
 // Per-node buffers for n_new nodes; the partition state arrays keep their
