@@ -56,9 +56,10 @@ __global__ __launch_bounds__(256) void tile_count_k(F f, uint32_t n, const uint3
 }
 
 // One workgroup: per class, the exclusive scan of the per-tile counts (in
-// place) and the class totals. All classes of a chunk of 1024 tiles are
-// scanned together (their loads in flight at once, one pair of barriers per
-// chunk), so the cost does not grow with the number of classes.
+// place) and the class totals. Every thread takes kOffPer consecutive tiles
+// of a chunk (all their counts, of every class, loaded at once), so up to
+// 1024 * kOffPer tiles cost one round of loads and one pair of barriers.
+constexpr int kOffPer = 8;
 template <int NC>
 __global__ __launch_bounds__(1024) void tile_offsets_k(uint32_t* __restrict__ part, uint32_t ntiles,
                                                        uint32_t* __restrict__ meta) {
@@ -69,14 +70,19 @@ __global__ __launch_bounds__(1024) void tile_offsets_k(uint32_t* __restrict__ pa
   uint32_t carry[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) carry[c] = 0;
-  for (uint32_t b = 0; b < ntiles; b += 1024) {
-    const uint32_t i = b + threadIdx.x;
-    uint32_t v[NC], inc[NC];
+  for (uint32_t b = 0; b < ntiles; b += 1024u * kOffPer) {
+    const uint32_t i0 = b + threadIdx.x * kOffPer;
+    uint32_t v[NC][kOffPer], sum[NC], inc[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) v[c] = i < ntiles ? part[size_t(c) * ntiles + i] : 0u;
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int q = 0; q < kOffPer; ++q) v[c][q] = i0 + q < ntiles ? part[size_t(c) * ntiles + i0 + q] : 0u;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-      inc[c] = wave_inclusive_scan(v[c]);
+      sum[c] = 0;
+#pragma unroll
+      for (int q = 0; q < kOffPer; ++q) sum[c] += v[c][q];
+      inc[c] = wave_inclusive_scan(sum[c]);
       if (lane == kWave - 1) sh[w][c] = inc[c];
     }
     __syncthreads();
@@ -89,7 +95,12 @@ __global__ __launch_bounds__(1024) void tile_offsets_k(uint32_t* __restrict__ pa
         before += q < w ? x : 0u;
         tot += x;
       }
-      if (i < ntiles) part[size_t(c) * ntiles + i] = carry[c] + before + inc[c] - v[c];
+      uint32_t run = carry[c] + before + inc[c] - sum[c];
+#pragma unroll
+      for (int q = 0; q < kOffPer; ++q) {
+        if (i0 + q < ntiles) part[size_t(c) * ntiles + i0 + q] = run;
+        run += v[c][q];
+      }
       carry[c] += tot;
     }
     __syncthreads();

@@ -26,17 +26,29 @@ __global__ __launch_bounds__(kScanNT) void scan_reduce_k(const Tin* __restrict__
   if (threadIdx.x == 0) partial[blockIdx.x] = tot;
 }
 
-// Exclusive scan of partial[0..nb) in place by one block; partial[nb] = total.
+// Exclusive scan of partial[0..nb) in place by one block; partial[nb] =
+// total. Every thread takes kPartPer consecutive partials of a chunk (loaded
+// at once), so up to 1024 * kPartPer partials cost one round of loads.
+constexpr int kPartPer = 8;
 template <typename Tout>
 __global__ __launch_bounds__(1024) void scan_partials_k(Tout* __restrict__ partial, uint32_t nb) {
   __shared__ Tout sh[1024 / kWave];
   Tout carry = 0;
-  for (uint32_t base = 0; base < nb; base += 1024) {
-    const uint32_t i = base + threadIdx.x;
-    Tout v = i < nb ? partial[i] : Tout(0);
+  for (uint32_t base = 0; base < nb; base += 1024u * kPartPer) {
+    const uint32_t i0 = base + threadIdx.x * kPartPer;
+    Tout v[kPartPer], sum = 0;
+#pragma unroll
+    for (int q = 0; q < kPartPer; ++q) {
+      v[q] = i0 + q < nb ? partial[i0 + q] : Tout(0);
+      sum += v[q];
+    }
     Tout tot;
-    Tout ex = block_exclusive_scan<1024>(v, sh, &tot);
-    if (i < nb) partial[i] = carry + ex;
+    Tout run = carry + block_exclusive_scan<1024>(sum, sh, &tot);
+#pragma unroll
+    for (int q = 0; q < kPartPer; ++q) {
+      if (i0 + q < nb) partial[i0 + q] = run;
+      run += v[q];
+    }
     carry += tot;
   }
   if (threadIdx.x == 0) partial[nb] = carry;
@@ -80,14 +92,25 @@ constexpr uint32_t kScanSmall = 8192;
 template <typename Tin, typename Tout, bool kInclusive>
 __global__ __launch_bounds__(1024) void scan_small_k(const Tin* __restrict__ in, Tout* __restrict__ out,
                                                      uint32_t n, Tout* __restrict__ partial) {
+  // every thread takes kPartPer consecutive elements (loaded at once), so
+  // kScanSmall elements are one step
   __shared__ Tout sh[1024 / kWave];
   Tout carry = 0;
-  for (uint32_t base = 0; base < n; base += 1024) {
-    const uint32_t i = base + threadIdx.x;
-    const Tout v = i < n ? Tout(in[i]) : Tout(0);
+  for (uint32_t base = 0; base < n; base += 1024u * kPartPer) {
+    const uint32_t i0 = base + threadIdx.x * kPartPer;
+    Tout v[kPartPer], sum = 0;
+#pragma unroll
+    for (int q = 0; q < kPartPer; ++q) {
+      v[q] = i0 + q < n ? Tout(in[i0 + q]) : Tout(0);
+      sum += v[q];
+    }
     Tout tot;
-    const Tout ex = block_exclusive_scan<1024>(v, sh, &tot);  // reads all of the step before writes
-    if (i < n) out[i] = carry + (kInclusive ? ex + v : ex);
+    Tout run = carry + block_exclusive_scan<1024>(sum, sh, &tot);  // reads all of the step before writes
+#pragma unroll
+    for (int q = 0; q < kPartPer; ++q) {
+      if (i0 + q < n) out[i0 + q] = kInclusive ? run + v[q] : run;
+      run += v[q];
+    }
     carry += tot;
   }
   if (threadIdx.x == 0) partial[0] = carry;
@@ -265,10 +288,23 @@ __device__ __forceinline__ void radix_scatter_tile(const Load& load, K* __restri
     uint32_t local = block_exclusive_scan<kRadixNT>(tot, shs, &all);
     uint32_t gpos;
     if (kFused) {
-      // items of digit d in earlier tiles, and in all tiles
+      // items of digit d in earlier tiles, and in all tiles (eight counts
+      // in flight at a time: one load per step would wait out the L2
+      // latency nblocks times)
       const uint32_t* h = hist_scan + uint64_t(d) * nblocks;
       uint32_t before = 0, total = 0;
-      for (uint32_t t = 0; t < nblocks; ++t) {
+      uint32_t t = 0;
+      for (; t + 8 <= nblocks; t += 8) {
+        uint32_t c[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) c[q] = h[t + q];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          before += t + q < blockIdx.x ? c[q] : 0u;
+          total += c[q];
+        }
+      }
+      for (; t < nblocks; ++t) {
         const uint32_t c = h[t];
         before += t < blockIdx.x ? c : 0u;
         total += c;
