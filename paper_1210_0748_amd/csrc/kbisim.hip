@@ -496,9 +496,13 @@ void Engine::prepare_active(uint32_t seg_items, uint32_t m_cap, uint32_t tag, bo
                                              apos_.as<uint32_t>(), anode_.as<uint32_t>(),
                                              mark ? actr_.as<uint32_t>() : nullptr, tag, info);
   KB_LAUNCH_CHECK();
-  // when many nodes may be active, the work lists and the thread part go
-  // over node ids in order (neighbouring rows), else over the active list
+  // when many nodes are active, the work lists and the thread part go over
+  // node ids in order (neighbouring rows), else over the active list; when
+  // the bound m_cap leaves it open, the real count decides (one read-back
+  // costs less than a pass over every node id)
   act_dense_ = uint64_t(m_cap) * 8 >= uint64_t(n_);
+  if (act_dense_ && uint64_t(m_cap) * 2 < uint64_t(n_))
+    act_dense_ = read_word(info + kInfoItems, 4) * 8 >= uint64_t(n_);
   if (act_dense_) {
     compact<kNumBuckets>(NodeBucketDenseOf{actr_.as<uint32_t>(), tag, rowptr_.as<uint32_t>()},
                          NodeWriteDense{blists_.as<uint32_t>()}, uint32_t(n_), nullptr,
