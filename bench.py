@@ -72,10 +72,13 @@ def load_traffic(kernel_class, workload, early_stop, k_cap):
         t = json.load(f)
     if t.get("source_digest") != kernel_source_digest():
         return None
-    k = t.get("kernels", {}).get(kernel_class)
-    if k is None or (k.get("workload"), k.get("early_stop"), k.get("k_cap")) != (workload, early_stop, k_cap):
-        return None
-    return k.get("bytes_per_launch")
+    # entries are named "<class>" or "<class>@<workload>"; the one read on this job counts
+    for name, k in t.get("kernels", {}).items():
+        if name.split("@")[0] != kernel_class:
+            continue
+        if (k.get("workload"), k.get("early_stop"), k.get("k_cap")) == (workload, early_stop, k_cap):
+            return k.get("bytes_per_launch")
+    return None
 
 
 # Workloads up to this many edges: the oracle runs the whole job itself.

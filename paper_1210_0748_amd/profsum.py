@@ -5,6 +5,7 @@
   python -m paper_1210_0748_amd.profsum counters <counter_collection.csv> --kernel SUBSTR
   python -m paper_1210_0748_amd.profsum traffic <fetch.csv> --write W.csv --cal-fetch CF.csv
          --cal-write CW.csv --kernel SUBSTR --name NAME --out profiles/traffic.json
+         (NAME: the kernel class, or CLASS@WORKLOAD beside the entry of another workload)
          [--workload W --k-cap K --no-early-stop]   (the bench job the counters ran)
   python -m paper_1210_0748_amd.profsum gbs <kernel_stats.csv> --fetch F.csv --write W.csv
          [--scales profiles/traffic.json] [--top N]
