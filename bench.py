@@ -132,6 +132,7 @@ def main():
     ap.add_argument("--no-early-stop", action="store_true",
                     help="plain form: run all k rounds even past the fixed point")
     ap.add_argument("--medium-cap", type=int, default=None)
+    ap.add_argument("--radix-tile", type=int, default=0, help="items per radix-sort tile (0 = library default)")
     ap.add_argument("--form", choices=["plain", "batched", "served", "update"], default="plain")
     ap.add_argument("--max-batch", type=int, default=1_000_000, help="update: largest batch of added edges")
     ap.add_argument("--graphs", type=int, default=512, help="batched: number of graphs")
@@ -184,7 +185,7 @@ def main():
 
     def step(profile):
         h = kb.kbisim_create(g.num_nodes, *arrs, stream=stream, profile=profile,
-                             medium_cap=args.medium_cap, early_stop=early_stop)
+                             medium_cap=args.medium_cap, radix_tile=args.radix_tile, early_stop=early_stop)
         try:
             rd = kb.kbisim_refine(h, k)
             nb, counts = kb.kbisim_result(h, out, counts_cap=k + 1)
@@ -212,7 +213,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     h = kb.kbisim_create(g.num_nodes, *arrs, stream=stream, medium_cap=args.medium_cap,
-                         early_stop=early_stop)
+                         radix_tile=args.radix_tile, early_stop=early_stop)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kb.kbisim_refine(h, k)
@@ -257,7 +258,8 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": args.workload, "num_nodes": g.num_nodes, "num_edges": g.num_edges,
-                   "k_cap": k, "early_stop": early_stop, "rounds": rd, "counts": counts, "seed": args.seed},
+                   "k_cap": k, "early_stop": early_stop, "rounds": rd, "counts": counts, "seed": args.seed,
+                   **({"radix_tile": args.radix_tile} if args.radix_tile else {})},
         "phases": dict(phases, note="one untimed step, each phase closed by a device sync"),
         "roofline": {"bound": "hbm", "kernel": "signature_k", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
@@ -324,7 +326,7 @@ def pct(xs, q):
 def bench_batched(args, torch, kb, dev):
     """Batched form: many graphs of log-normal size (median 20k nodes, sigma
     1, 1k..1M nodes, mean out-degree 8, 16 node and 16 edge labels), k = 5,
-    refined as one batch (medium_cap from the autotuner) vs the per-graph
+    refined as one batch (medium_cap and radix_tile from the autotuner) vs the per-graph
     plain refine loop on the same GPU; results must be identical."""
     import numpy as np
     import synth
@@ -340,13 +342,13 @@ def bench_batched(args, torch, kb, dev):
     cat = lambda name: np.concatenate([getattr(g, name) for g in graphs])
     arrs = [torch.from_numpy(cat(nm)).to(dev) for nm in ("node_label", "src", "elab", "dst")]
     log("generated %d graphs: N=%d E=%d in %.1f s" % (len(graphs), noff[-1], eoff[-1], time.perf_counter() - t0))
-    cap, tune_report = autotune.tune_medium_cap(graphs, k, use_cache=False)
-    log("autotuned medium_cap=%d %s" % (cap, json.dumps(tune_report)))
+    (cap, tile), tune_report = autotune.tune(graphs, k, use_cache=False)
+    log("autotuned medium_cap=%d radix_tile=%d %s" % (cap, tile, json.dumps(tune_report)))
     out = torch.empty(int(noff[-1]), dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
 
     def batched():
-        h, G = kb.kbisim_batch_create(noff, eoff, *arrs, stream=stream, medium_cap=cap)
+        h, G = kb.kbisim_batch_create(noff, eoff, *arrs, stream=stream, medium_cap=cap, radix_tile=tile)
         try:
             rd = kb.kbisim_batch_refine(h, [k] * G)
             kb.kbisim_batch_result(h, G, out)
@@ -373,7 +375,7 @@ def bench_batched(args, torch, kb, dev):
         a, b = int(noff[i]), int(noff[i + 1])
         c, d = int(eoff[i]), int(eoff[i + 1])
         h = kb.kbisim_create(b - a, arrs[0][a:b], arrs[1][c:d], arrs[2][c:d], arrs[3][c:d], stream=stream,
-                             medium_cap=cap)
+                             medium_cap=cap, radix_tile=tile)
         try:
             kb.kbisim_refine(h, k)
             kb.kbisim_result(h, loop_out[a:b])
@@ -390,7 +392,7 @@ def bench_batched(args, torch, kb, dev):
         "config": {"workload": "batched-%d-graphs" % len(graphs), "graphs": len(graphs),
                    "total_nodes": int(noff[-1]), "total_edges": int(eoff[-1]), "k": k,
                    "median_nodes": 20000, "sigma": 1.0, "avg_degree": 8, "labels": 16},
-        "medium_cap": cap, "tune": tune_report,
+        "medium_cap": cap, "radix_tile": tile, "tune": tune_report,
         "per_graph_loop": {"ms": t_loop * 1e3, "edge_rounds_per_s": edge_rounds / t_loop},
         "speedup_vs_loop": t_loop / t_batch, "identical_to_loop": same,
     }

@@ -90,6 +90,10 @@ typedef struct {
                           then full rounds (Section 4, "When to switch back"); 1 level
                           by level in every round; 2 full rounds from round 1. The
                           result does not depend on it. */
+  int32_t radix_tile;  /* tuning: items per tile of every radix sort pass of this handle
+                          (the edge table's sort by source at create, the ordering's
+                          device-wide passes, the maintenance sorts): 2048, 3072 or 4096;
+                          0 = library default (3072). Ids do not depend on it. */
   int64_t edge_window_bytes; /* 0 (default): kbisim_create copies the edge table into device
                           memory. > 0: graphs whose edge table is to stay out of device
                           memory (the paper's setting of a graph larger than the fast

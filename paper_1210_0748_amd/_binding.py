@@ -35,7 +35,8 @@ class GraphDesc(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("early_stop", ctypes.c_int32), ("profile", ctypes.c_int32),
                 ("medium_cap", ctypes.c_int32), ("history", ctypes.c_int32),
-                ("update_mode", ctypes.c_int32), ("edge_window_bytes", ctypes.c_int64)]
+                ("update_mode", ctypes.c_int32), ("radix_tile", ctypes.c_int32),
+                ("edge_window_bytes", ctypes.c_int64)]
 
 
 class UpdateDesc(ctypes.Structure):
@@ -180,7 +181,8 @@ def _arrays(node_label, src, elab, dst):
 
 
 def kbisim_create(num_nodes, node_label, src, elab, dst, *, stream=None, early_stop=True,
-                  profile=False, medium_cap=None, history=False, update_mode=0, edge_window_bytes=0):
+                  profile=False, medium_cap=None, history=False, update_mode=0, edge_window_bytes=0,
+                  radix_tile=0):
     """Creates a device-resident graph handle (see kbisim.h). Returns the handle.
     edge_window_bytes > 0 keeps the edge table (host arrays) in host memory and
     streams it through device windows of that total size every round."""
@@ -198,6 +200,7 @@ def kbisim_create(num_nodes, node_label, src, elab, dst, *, stream=None, early_s
     opt.history = 1 if history else 0
     opt.update_mode = int(update_mode)
     opt.edge_window_bytes = int(edge_window_bytes)
+    opt.radix_tile = int(radix_tile)
     if medium_cap is not None:
         opt.medium_cap = int(medium_cap)
     h = ctypes.c_void_p()
@@ -300,7 +303,7 @@ def kbisim_update(handle, *, new_labels=None, delete=None, delete_nodes=None, ad
 
 
 def kbisim_refine_static(num_nodes, node_label, src, elab, dst, k, pid_out, *, stream=None, early_stop=True,
-                         medium_cap=None):
+                         medium_cap=None, radix_tile=0):
     """The allocation-free one-shot refine (static scratch region): ids of
     round k (or the fixed point) into pid_out (numpy or torch CUDA int32).
     Returns (num_blocks, rounds_done)."""
@@ -309,7 +312,7 @@ def kbisim_refine_static(num_nodes, node_label, src, elab, dst, k, pid_out, *, s
     n, m = int(num_nodes), int(keep[1].shape[0])
     desc = GraphDesc(n, m, ptrs[0] or None, ptrs[1] or None, ptrs[2] or None, ptrs[3] or None, mem,
                      _stream_ptr(stream) if (mem == KBISIM_MEM_DEVICE or stream is not None) else None)
-    opt = _options(early_stop=early_stop, medium_cap=medium_cap)
+    opt = _options(early_stop=early_stop, medium_cap=medium_cap, radix_tile=radix_tile)
     out_mem, out_ptr = _out_ptr(pid_out)
     nb, rd = ctypes.c_int64(0), ctypes.c_int32(0)
     _check(lib.kbisim_refine_static(ctypes.byref(desc), int(k), ctypes.byref(opt), out_ptr, out_mem,
@@ -450,13 +453,14 @@ def refine(num_nodes, node_label, src, elab, dst, k, **kw):
         return pid, counts, rd
 
 
-def _options(early_stop=True, profile=False, medium_cap=None, history=False):
+def _options(early_stop=True, profile=False, medium_cap=None, history=False, radix_tile=0):
     lib = load_library()
     opt = Options()
     lib.kbisim_options_default(ctypes.byref(opt))
     opt.early_stop = 1 if early_stop else 0
     opt.profile = 1 if profile else 0
     opt.history = 1 if history else 0
+    opt.radix_tile = int(radix_tile)
     if medium_cap is not None:
         opt.medium_cap = int(medium_cap)
     return opt

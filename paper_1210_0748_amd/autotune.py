@@ -1,15 +1,19 @@
-"""Autotuner for the ordering's LDS sort tile (medium_cap).
+"""Autotuner for the ordering's LDS sort tile (medium_cap) and the radix
+sort tile (radix_tile).
 
 Groups of up to 64 members are ordered by one wave, groups of up to
 `medium_cap` members by one workgroup sorting them in an LDS tile, larger
-groups by global radix passes. The best split depends on the workload's
-block-size distribution, so the tuner times a refinement of a sample of the
-workload with every candidate, several times, interleaved (so drift hits all
-candidates alike), and compares medians. A candidate replaces the library's
-default only when its median beats the default's by more than the noise (the
-larger of MIN_GAIN and twice the default's relative spread); otherwise the
-default stays. Results are cached in a JSON file keyed by GPU architecture
-and a coarse workload class; ids never depend on the choice.
+groups by device-wide radix passes; every radix pass (the edge table's sort
+by source at create, the ordering's passes) works on tiles of `radix_tile`
+items (2048, 3072 or 4096 compiled). The best pair depends on the workload's
+sizes and block-size distribution, so the tuner times create + refinement
+of a sample of the workload (inputs already on the device) with every
+candidate pair, several times, interleaved (so drift hits all candidates
+alike), and compares medians. A candidate replaces the library's default
+only when its median beats the default's by more than the noise (the larger
+of MIN_GAIN and twice the default's relative spread); otherwise the default
+stays. Results are cached in a JSON file keyed by GPU architecture and a
+coarse workload class; ids never depend on the choice.
 """
 from __future__ import annotations
 
@@ -19,8 +23,10 @@ import os
 import statistics
 import time
 
-CANDIDATES = (64, 512, 1024, 4096)
-DEFAULT = 4096
+CAPS = (64, 512, 1024, 4096)
+TILES = (2048, 3072, 4096)
+CANDIDATES = tuple((c, t) for c in CAPS for t in TILES)
+DEFAULT = (4096, 3072)
 MIN_GAIN = 0.03
 
 
@@ -81,21 +87,25 @@ def choose(runs, default=DEFAULT):
     return choice, report
 
 
-def tune_medium_cap(graphs, k, sample_edges=20_000_000, repeats=5, device="cuda:0", use_cache=True):
-    """Returns (chosen medium_cap, report) for refining `graphs` as one batch
-    with k rounds. A prefix of the graphs holding about `sample_edges` edges is
-    concatenated and moved to the device once; per run a batch handle is
-    created from those device arrays outside the timed region, and only its
-    refinement (kbisim_batch_refine, synchronised) is timed. report: per
-    candidate the median and spread (median absolute deviation) in seconds,
-    the noise threshold and whether the default was kept."""
+def tune(graphs, k, sample_edges=20_000_000, repeats=5, device="cuda:0", use_cache=True,
+         candidates=CANDIDATES, default=DEFAULT):
+    """Returns ((medium_cap, radix_tile), report) for refining `graphs` as one
+    batch with k rounds. A prefix of the graphs holding about `sample_edges`
+    edges is concatenated and moved to the device once; per run a batch handle
+    is created from those device arrays and refined (kbisim_batch_create +
+    kbisim_batch_refine, synchronised before and after: device work and the
+    library's own host steps, no host copies of the inputs), then destroyed
+    outside the timed region. report: per candidate the median and spread
+    (median absolute deviation) in seconds, the noise threshold and whether
+    the default was kept."""
     import numpy as np
     import torch
     from . import kbisim_batch_create, kbisim_batch_refine, kbisim_batch_destroy
-    key = "%s/%s/k%d" % (_arch(), workload_class(graphs), int(k))
+    cand_id = ",".join("%d:%d" % c for c in candidates)
+    key = "%s/%s/k%d/%s" % (_arch(), workload_class(graphs), int(k), cand_id)
     table = _load() if use_cache else {}
-    if key in table:
-        return int(table[key]["best"]), table[key]["report"]
+    if key in table and "best_pair" in table[key]:
+        return tuple(table[key]["best_pair"]), table[key]["report"]
     sample, acc = [], 0
     for g in graphs:
         sample.append(g)
@@ -112,25 +122,36 @@ def tune_medium_cap(graphs, k, sample_edges=20_000_000, repeats=5, device="cuda:
     ks = [int(k)] * len(sample)
     stream = torch.cuda.current_stream()
 
-    def refine_seconds(cap):
-        h, _ = kbisim_batch_create(noff, eoff, *arrs, stream=stream, medium_cap=cap)
+    def job_seconds(pair):
+        cap, tile = pair
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h, _ = kbisim_batch_create(noff, eoff, *arrs, stream=stream, medium_cap=cap, radix_tile=tile)
         try:
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
             kbisim_batch_refine(h, ks)
             torch.cuda.synchronize()
             return time.perf_counter() - t0
         finally:
             kbisim_batch_destroy(h)
 
-    refine_seconds(DEFAULT)  # warm the allocator and the code
-    runs = {c: [] for c in CANDIDATES}
+    for pair in candidates:  # warm the allocator and every compiled variant
+        job_seconds(pair)
+    runs = {c: [] for c in candidates}
     for _ in range(repeats):
-        for cap in CANDIDATES:
-            runs[cap].append(refine_seconds(cap))
-    choice, report = choose(runs)
-    report.update(repeats=repeats, sample_graphs=len(sample), sample_edges=acc, timed="kbisim_batch_refine only")
-    table[key] = {"best": choice, "report": report}
+        for pair in candidates:
+            runs[pair].append(job_seconds(pair))
+    choice, report = choose(runs, default)
+    report.update(repeats=repeats, sample_graphs=len(sample), sample_edges=acc,
+                  timed="kbisim_batch_create + kbisim_batch_refine from device inputs",
+                  candidates="(medium_cap, radix_tile)")
+    table[key] = {"best_pair": list(choice), "report": report}
     if use_cache:
         _store(table)
     return choice, report
+
+
+def tune_medium_cap(graphs, k, **kw):
+    """medium_cap alone (radix tile at its default): (medium_cap, report)."""
+    cands = tuple((c, DEFAULT[1]) for c in CAPS)
+    pair, report = tune(graphs, k, candidates=cands, **kw)
+    return pair[0], report

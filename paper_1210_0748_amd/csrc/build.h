@@ -61,14 +61,16 @@ __device__ __forceinline__ void report(uint32_t e_bits, uint32_t mx, const Label
 // tiles of the edges in input order:
 //   err bit 1: src/dst outside [0, N); bit 2: negative edge label;
 //   *maxv = largest edge label; lmask = presence of edge labels < 256;
-//   hist[d * nb + t] = edges of tile t whose source has lowest byte d (the
-//   first pass of the sort by source).
+//   hist[d * nb + t] = edges of tile t (kRadixNT * IPT edges) whose source
+//   has lowest byte d (the first pass of the sort by source).
+template <int IPT = kRadixIPT>
 __global__ __launch_bounds__(kRadixNT) void edge_scan_k(const int32_t* __restrict__ src,
                                                         const int32_t* __restrict__ lab,
                                                         const int32_t* __restrict__ dst, uint64_t m, int64_t n,
                                                         uint32_t* __restrict__ err, uint32_t* __restrict__ maxv,
                                                         unsigned long long* __restrict__ lmask,
                                                         uint32_t* __restrict__ hist, uint32_t nb) {
+  constexpr int kTile = kRadixNT * IPT;
   __shared__ uint32_t cnt[kRadixNW][256];
   const int w = threadIdx.x / kWave;
   uint32_t e_bits = 0, mx = 0;
@@ -88,9 +90,9 @@ __global__ __launch_bounds__(kRadixNT) void edge_scan_k(const int32_t* __restric
   for (uint32_t t = blockIdx.x; t < nb; t += gridDim.x) {
     for (int j = threadIdx.x; j < kRadixNW * 256; j += kRadixNT) (&cnt[0][0])[j] = 0;
     __syncthreads();
-    const uint64_t base = uint64_t(t) * kRadixTile;
-    if (vec && base + kRadixTile <= m) {
-      constexpr int kVecs = kRadixIPT / 4;
+    const uint64_t base = uint64_t(t) * kTile;
+    if (vec && base + kTile <= m) {
+      constexpr int kVecs = IPT / 4;
       const uint4* vs = reinterpret_cast<const uint4*>(src + base);
       const uint4* vl = reinterpret_cast<const uint4*>(lab + base);
       const uint4* vd = reinterpret_cast<const uint4*>(dst + base);
@@ -109,7 +111,7 @@ __global__ __launch_bounds__(kRadixNT) void edge_scan_k(const int32_t* __restric
         check(int32_t(rs[i].w), int32_t(rl[i].w), int32_t(rd[i].w));
       }
     } else {
-      for (int i = 0; i < kRadixIPT; ++i) {
+      for (int i = 0; i < IPT; ++i) {
         const uint64_t e = base + uint64_t(i) * kRadixNT + threadIdx.x;
         if (e < m) check(src[e], lab[e], dst[e]);
       }
@@ -295,11 +297,11 @@ struct EdgePackLoad {
 
 // First pass of the sort by source straight from the edge table (the
 // per-tile counts come from edge_scan_k).
-template <typename AdjT, bool kFused>
+template <typename AdjT, bool kFused, int IPT = kRadixIPT>
 __global__ __launch_bounds__(kRadixNT) void pack_scatter_k(EdgePackLoad<AdjT> load, uint32_t* __restrict__ kout,
                                                            AdjT* __restrict__ vout, uint64_t m,
                                                            const uint32_t* __restrict__ hist, uint32_t nb) {
-  radix_scatter_tile<uint32_t, AdjT, true, kFused>(load, kout, vout, m, 0, hist, nb);
+  radix_scatter_tile<uint32_t, AdjT, true, kFused, EdgePackLoad<AdjT>, IPT>(load, kout, vout, m, 0, hist, nb);
 }
 
 // Row offsets of the CSR from the edges sorted by source: rowptr[v] = first

@@ -91,6 +91,7 @@ struct Options {
   bool history = false;  // keep pId_0..pId_rounds and the maintenance state (reverse CSR, label values)
   int update_mode = 0;   // rounds of an update: 0 chosen by cost, 1 level by level, 2 in full
   uint32_t medium_cap = kDefaultMediumCap;  // groups above this size use the global passes
+  uint32_t radix_tile = 0;  // items per radix-sort tile (2048, 3072, 4096); 0 = the default
   uint64_t edge_window = 0;  // > 0: the edge table stays in host memory, streamed through this many bytes
 };
 
@@ -259,6 +260,7 @@ class Engine {
   uint32_t* radix_scratch(uint64_t n);
   uint32_t* compact_scratch(uint64_t words);
   uint32_t medium_cap() const;
+  int ipt() const { return radix_ipt_of(opt_.radix_tile); }  // radix tile: items per thread
 
   int ev_begin(int cls);  // returns a slot for ev_end, or -1 when not profiling
   void ev_end(int slot);

@@ -154,18 +154,21 @@ void Engine::build_adj(const int32_t* src, const int32_t* lab, const int32_t* ds
     kb2.ensure(E * 4);
     adj_.ensure(E * sizeof(AdjT));
     vb.ensure(E * sizeof(AdjT));
-    const uint32_t nb = radix_blocks(E);
+    const uint32_t nb = radix_blocks(E, ipt());
     const EdgePackLoad<AdjT> load{src, lab, dst, erank, rank_table, dst_bits_};
-    if (nb <= kRadixFusedTiles) {
-      pack_scatter_k<AdjT, true><<<nb, kRadixNT, 0, st_>>>(load, ka.as<uint32_t>(), adj_.as<AdjT>(), E, hist0, nb);
-    } else {
-      scan_dev<uint32_t, uint32_t, false>(hist0, hist0, uint64_t(nb) * 256);
-      pack_scatter_k<AdjT, false><<<nb, kRadixNT, 0, st_>>>(load, ka.as<uint32_t>(), adj_.as<AdjT>(), E, hist0, nb);
-    }
+    if (nb > kRadixFusedTiles) scan_dev<uint32_t, uint32_t, false>(hist0, hist0, uint64_t(nb) * 256);
+    with_radix_ipt(ipt(), [&](auto tag) {
+      constexpr int I = decltype(tag)::value;
+      if (nb <= kRadixFusedTiles)
+        pack_scatter_k<AdjT, true, I><<<nb, kRadixNT, 0, st_>>>(load, ka.as<uint32_t>(), adj_.as<AdjT>(), E, hist0, nb);
+      else
+        pack_scatter_k<AdjT, false, I><<<nb, kRadixNT, 0, st_>>>(load, ka.as<uint32_t>(), adj_.as<AdjT>(), E, hist0,
+                                                                 nb);
+    });
     KB_LAUNCH_CHECK();
     const bool f = radix_sort<uint32_t, AdjT>(ka.as<uint32_t>(), adj_.as<AdjT>(), kb2.as<uint32_t>(),
                                               vb.as<AdjT>(), E, 8, bits_for(N > 1 ? N - 1 : 1),
-                                              radix_scratch(E), st_);
+                                              radix_scratch(E), st_, ipt());
     if (f) adj_.swap(vb);
     const uint32_t* skey = f ? kb2.as<uint32_t>() : ka.as<uint32_t>();
     // long runs of nodes without edges: at most N / kRowGap + 1 of them
@@ -270,7 +273,7 @@ uint32_t Engine::label_ranks(const int32_t* val, uint64_t n, uint32_t maxv, cons
   to_u32_iota_k<<<grid_for(n), kNT, 0, st_>>>(val, ka.as<uint32_t>(), va.as<uint32_t>(), uint32_t(n));
   KB_LAUNCH_CHECK();
   const bool f = radix_sort<uint32_t>(ka.as<uint32_t>(), va.as<uint32_t>(), kb2.as<uint32_t>(), vb.as<uint32_t>(),
-                                      n, 0, bits_for(maxv), radix_scratch(n), st_);
+                                      n, 0, bits_for(maxv), radix_scratch(n), st_, ipt());
   uint32_t* keys = f ? kb2.as<uint32_t>() : ka.as<uint32_t>();
   uint32_t* vals = f ? vb.as<uint32_t>() : va.as<uint32_t>();
   uint32_t* fl = f ? ka.as<uint32_t>() : kb2.as<uint32_t>();   // the free key buffer
@@ -306,15 +309,17 @@ void Engine::build(const int32_t* node_label, const int32_t* src, const int32_t*
   uint32_t* err = errb.as<uint32_t>();
   unsigned long long* masks = reinterpret_cast<unsigned long long*>(errb.as<uint8_t>() + 16);
   DevBuf hist0;  // per-tile source counts for the first pass of the sort by source
-  const uint32_t enb = E ? radix_blocks(E) : 0u;
+  const uint32_t enb = E ? radix_blocks(E, ipt()) : 0u;
   if (N) {
     validate_nodes_k<<<validate_blocks(N), kRadixNT, 0, st_>>>(node_label, N, err, err + 1, masks);
     KB_LAUNCH_CHECK();
   }
   if (E) {
     hist0.ensure(uint64_t(enb) * 256 * 4);
-    edge_scan_k<<<std::min<uint32_t>(enb, 2048), kRadixNT, 0, st_>>>(src, lab, dst, E, n_, err, err + 2, masks + 4,
-                                                                     hist0.as<uint32_t>(), enb);
+    with_radix_ipt(ipt(), [&](auto tag) {
+      edge_scan_k<decltype(tag)::value><<<std::min<uint32_t>(enb, 2048), kRadixNT, 0, st_>>>(
+          src, lab, dst, E, n_, err, err + 2, masks + 4, hist0.as<uint32_t>(), enb);
+    });
     KB_LAUNCH_CHECK();
   }
   KB_CHECK(hipMemcpyAsync(hw_.p, errb.p, kErrBytes, hipMemcpyDeviceToHost, st_));
@@ -407,7 +412,7 @@ void Engine::build_nodes(const int32_t* node_label, uint32_t max_nlab, const uns
     KB_LAUNCH_CHECK();
     const bool f = radix_sort<uint32_t>(ka.as<uint32_t>(), va.as<uint32_t>(), kb2.as<uint32_t>(),
                                         vb.as<uint32_t>(), N, 0, bits_for(nl > 1 ? nl - 1 : 1),
-                                        radix_scratch(N), st_);
+                                        radix_scratch(N), st_, ipt());
     const uint32_t* keys = f ? kb2.as<uint32_t>() : ka.as<uint32_t>();
     const uint32_t* vals = f ? vb.as<uint32_t>() : va.as<uint32_t>();
     KB_CHECK(hipMemcpyAsync(ord_.p, vals, N * 4, hipMemcpyDeviceToDevice, st_));
@@ -723,7 +728,7 @@ void Engine::order_groups(const void* kvp) {
                                                         head_w);
       KB_LAUNCH_CHECK();
       const bool f = radix_sort<uint64_t>(k0_.as<uint64_t>(), v0_.as<uint32_t>(), k1_.as<uint64_t>(),
-                                          v1_.as<uint32_t>(), M, 0, hi_bits + lk.dig_bits, radix_scratch(M), st_);
+                                          v1_.as<uint32_t>(), M, 0, hi_bits + lk.dig_bits, radix_scratch(M), st_, ipt());
       KA = f ? k1_.as<uint64_t>() : k0_.as<uint64_t>();
       V = f ? v1_.as<uint32_t>() : v0_.as<uint32_t>();
     } else {
@@ -737,14 +742,14 @@ void Engine::order_groups(const void* kvp) {
       iota_k<<<grid_for(M), kNT, 0, st_>>>(v0_.as<uint32_t>(), M);
       KB_LAUNCH_CHECK();
       const bool f1 = radix_sort<uint64_t>(k0_.as<uint64_t>(), v0_.as<uint32_t>(), k1_.as<uint64_t>(),
-                                           v1_.as<uint32_t>(), M, 0, lk.dig_bits, radix_scratch(M), st_);
+                                           v1_.as<uint32_t>(), M, 0, lk.dig_bits, radix_scratch(M), st_, ipt());
       const uint64_t* L1 = f1 ? k1_.as<uint64_t>() : k0_.as<uint64_t>();
       const uint32_t* I1 = f1 ? v1_.as<uint32_t>() : v0_.as<uint32_t>();
       gather_u64_k<<<grid_for(M), kNT, 0, st_>>>(k2_.as<uint64_t>(), I1, M, k3_.as<uint64_t>());
       iota_k<<<grid_for(M), kNT, 0, st_>>>(v2_.as<uint32_t>(), M);
       KB_LAUNCH_CHECK();
       const bool f2 = radix_sort<uint64_t>(k3_.as<uint64_t>(), v2_.as<uint32_t>(), k4_.as<uint64_t>(),
-                                           v3_.as<uint32_t>(), M, 0, std::max(hi_bits, 1), radix_scratch(M), st_);
+                                           v3_.as<uint32_t>(), M, 0, std::max(hi_bits, 1), radix_scratch(M), st_, ipt());
       KA = f2 ? k4_.as<uint64_t>() : k3_.as<uint64_t>();
       const uint32_t* PS = f2 ? v3_.as<uint32_t>() : v2_.as<uint32_t>();
       uint64_t* lo_out = (L1 == k0_.as<uint64_t>()) ? k1_.as<uint64_t>() : k0_.as<uint64_t>();
@@ -827,7 +832,7 @@ void Engine::hub_sort(const void* sig_args, const uint32_t* hl, uint32_t nh, int
   hub_keys_k<AdjT, KeyT, CompT><<<ceil_div(H, kHubKeyTile), 256, 0, st_>>>(a, hl, hoff, nh, H, key_bits, k0);
   KB_LAUNCH_CHECK();
   const bool f = radix_sort<CompT>(k0, static_cast<uint32_t*>(nullptr), k1, static_cast<uint32_t*>(nullptr), H, 0,
-                                   hub_bits + key_bits, radix_scratch(H), st_);
+                                   hub_bits + key_bits, radix_scratch(H), st_, ipt());
   const CompT* c = f ? k1 : k0;
   hub_flags_k<CompT><<<grid_for(uint64_t(H) + 1), kNT, 0, st_>>>(c, H, fl);
   KB_LAUNCH_CHECK();
@@ -1702,6 +1707,7 @@ void kbisim_options_default(kbisim_options* opt) {
   opt->medium_cap = int32_t(kb::kDefaultMediumCap);
   opt->history = 0;
   opt->update_mode = 0;
+  opt->radix_tile = 0;
   opt->edge_window_bytes = 0;
 }
 
@@ -1712,6 +1718,9 @@ static kbisim_status parse_options(const kbisim_options* opt, kb::Options* o) {
   if (opt->medium_cap < 0 || opt->medium_cap > int32_t(kb::kBigCap))
     return fail(KBISIM_EINVAL, "medium_cap outside [0, 4096]");
   if (opt->medium_cap > 0) o->medium_cap = uint32_t(opt->medium_cap);
+  if (opt->radix_tile < 0 || !kb::radix_tile_valid(uint32_t(opt->radix_tile)))
+    return fail(KBISIM_EINVAL, "radix_tile not 0, 2048, 3072 or 4096");
+  o->radix_tile = uint32_t(opt->radix_tile);
   o->history = opt->history != 0;
   if (opt->update_mode < 0 || opt->update_mode > 2) return fail(KBISIM_EINVAL, "update_mode outside [0, 2]");
   o->update_mode = opt->update_mode;

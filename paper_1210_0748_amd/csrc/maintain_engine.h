@@ -83,13 +83,13 @@ void Engine::build_reverse() {
                                                       dst_bits_, ka.as<uint32_t>(), radj_.as<uint64_t>());
     KB_LAUNCH_CHECK();
     f = radix_sort<uint32_t, uint64_t>(ka.as<uint32_t>(), radj_.as<uint64_t>(), kb2.as<uint32_t>(),
-                                       vb.as<uint64_t>(), E, 0, bits_for(N > 1 ? N - 1 : 1), radix_scratch(E), st_);
+                                       vb.as<uint64_t>(), E, 0, bits_for(N > 1 ? N - 1 : 1), radix_scratch(E), st_, ipt());
   } else {
     reverse_items_k<uint32_t><<<tiles, 256, 0, st_>>>(rowptr_.as<uint32_t>(), uint32_t(N), adj_.as<uint32_t>(), E,
                                                       dst_bits_, ka.as<uint32_t>(), radj_.as<uint32_t>());
     KB_LAUNCH_CHECK();
     f = radix_sort<uint32_t, uint32_t>(ka.as<uint32_t>(), radj_.as<uint32_t>(), kb2.as<uint32_t>(),
-                                       vb.as<uint32_t>(), E, 0, bits_for(N > 1 ? N - 1 : 1), radix_scratch(E), st_);
+                                       vb.as<uint32_t>(), E, 0, bits_for(N > 1 ? N - 1 : 1), radix_scratch(E), st_, ipt());
   }
   if (f) radj_.swap(vb);
   const uint32_t* skey = f ? kb2.as<uint32_t>() : ka.as<uint32_t>();
@@ -594,7 +594,7 @@ void Engine::update_core(const UpdateArgs& u) {
     pid0_.swap(p0);
     pid0_bytes_ = nb;
     const bool f = radix_sort<uint32_t>(ka.as<uint32_t>(), va.as<uint32_t>(), kb2.as<uint32_t>(), vb.as<uint32_t>(),
-                                        N, 0, bits_for(nl > 1 ? nl - 1 : 1), radix_scratch(N), st_);
+                                        N, 0, bits_for(nl > 1 ? nl - 1 : 1), radix_scratch(N), st_, ipt());
     const uint32_t* keys = f ? kb2.as<uint32_t>() : ka.as<uint32_t>();
     const uint32_t* vals = f ? vb.as<uint32_t>() : va.as<uint32_t>();
     KB_CHECK(hipMemcpyAsync(ord_.p, vals, uint64_t(N) * 4, hipMemcpyDeviceToDevice, st_));

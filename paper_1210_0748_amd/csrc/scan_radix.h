@@ -3,6 +3,8 @@
 // inter-block waiting: reduce -> scan of partials -> apply.
 #pragma once
 
+#include <type_traits>
+
 #include "common.h"
 
 namespace kb {
@@ -145,29 +147,40 @@ void scan(const Tin* in, Tout* out, uint64_t n, Tout* partial, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // Stable LSD radix sort, 8 bits per pass.
 
-// 3072-item tiles: on 10M-item passes with 64-bit keys 4096-item tiles ran
-// about 6% slower and 8192-item tiles (one workgroup per CU) far slower;
-// 2048-item tiles slowed the 100M-edge passes of the build by about 7%.
+// Tiles of kRadixNT threads x IPT items. The default, 3072-item tiles: on
+// 10M-item passes with 64-bit keys 4096-item tiles ran about 6% slower and
+// 8192-item tiles (one workgroup per CU) far slower; 2048-item tiles slowed
+// the 100M-edge passes of the build by about 7%. 2048 and 4096 items are
+// compiled too (a tuning option: the best size depends on the item counts).
 constexpr int kRadixNT = 256;
 constexpr int kRadixIPT = 12;  // a multiple of 4: full tiles are read with 16-byte loads
-constexpr int kRadixTile = kRadixNT * kRadixIPT;
+constexpr int kRadixIPTMin = 8;  // smallest tile compiled: sizes the scratch of every choice
 constexpr int kRadixNW = kRadixNT / kWave;
+
+// Items per thread of a tile size in items (2048, 3072 or 4096); 0 = the default.
+inline int radix_ipt_of(uint32_t tile_items) {
+  return tile_items == 0 ? kRadixIPT : int(tile_items / kRadixNT);
+}
+inline bool radix_tile_valid(uint32_t tile_items) {
+  return tile_items == 0 || tile_items == 2048 || tile_items == 3072 || tile_items == 4096;
+}
 
 // Per-tile digit counts, digit-major: hist[d * nblocks + tile]. A full
 // tile whose start is 16-byte aligned is read with 16-byte loads (more
 // bytes in flight per thread); others element by element.
-template <typename K>
+template <typename K, int IPT = kRadixIPT>
 __global__ __launch_bounds__(kRadixNT) void radix_hist_k(const K* __restrict__ keys, uint64_t n,
                                                          int shift, uint32_t* __restrict__ hist,
                                                          uint32_t nblocks) {
+  constexpr int kTile = kRadixNT * IPT;
   __shared__ uint32_t cnt[kRadixNW][256];
   for (int j = threadIdx.x; j < kRadixNW * 256; j += kRadixNT) (&cnt[0][0])[j] = 0;
   __syncthreads();
   const int w = threadIdx.x / kWave;
-  const uint64_t base = uint64_t(blockIdx.x) * kRadixTile;
+  const uint64_t base = uint64_t(blockIdx.x) * kTile;
   constexpr int kPerVec = 16 / sizeof(K);
-  constexpr int kVecs = kRadixIPT / kPerVec;
-  if (base + kRadixTile <= n && (reinterpret_cast<uintptr_t>(keys) & 15u) == 0) {
+  constexpr int kVecs = IPT / kPerVec;
+  if (base + kTile <= n && (reinterpret_cast<uintptr_t>(keys) & 15u) == 0) {
     const uint4* v = reinterpret_cast<const uint4*>(keys + base);
     uint4 r[kVecs];
 #pragma unroll
@@ -189,7 +202,7 @@ __global__ __launch_bounds__(kRadixNT) void radix_hist_k(const K* __restrict__ k
     }
   } else {
 #pragma unroll 4
-    for (int i = 0; i < kRadixIPT; ++i) {
+    for (int i = 0; i < IPT; ++i) {
       const uint64_t idx = base + uint64_t(i) * kRadixNT + threadIdx.x;
       if (idx < n) atomicAdd(&cnt[w][uint32_t(keys[idx] >> shift) & 255u], 1u);
     }
@@ -226,9 +239,9 @@ struct KVLoad {
   }
 };
 
-// Scatter of one kRadixTile-item tile (blockIdx.x). Wave w owns the
-// contiguous sub-tile [w*kRadixIPT*64, (w+1)*kRadixIPT*64) and keeps its
-// kRadixIPT rows of 64 items in registers. The tile is first sorted by digit into LDS (per-wave digit
+// Scatter of one tile of kRadixNT * IPT items (blockIdx.x). Wave w owns the
+// contiguous sub-tile [w*IPT*64, (w+1)*IPT*64) and keeps its IPT rows of 64
+// items in registers. The tile is first sorted by digit into LDS (per-wave digit
 // counts give every wave its local offsets; each wave places its rows in
 // order with wave-local counters, one LDS read and one write per row, which
 // a wave completes in order). Then consecutive threads copy consecutive LDS
@@ -237,22 +250,23 @@ struct KVLoad {
 // kFused: `hist` holds the raw per-tile counts (digit-major) and every
 // workgroup derives its own global offsets from them (for few tiles); else
 // it holds their exclusive scan. `load(i, key, val)` reads item i < n.
-template <typename K, typename V, bool kHasVal, bool kFused, typename Load>
+template <typename K, typename V, bool kHasVal, bool kFused, typename Load, int IPT = kRadixIPT>
 __device__ __forceinline__ void radix_scatter_tile(const Load& load, K* __restrict__ kout, V* __restrict__ vout,
                                                    uint64_t n, int shift, const uint32_t* __restrict__ hist_scan,
                                                    uint32_t nblocks) {
-  constexpr int kRows = kRadixIPT;
+  constexpr int kRows = IPT;
+  constexpr int kTile = kRadixNT * IPT;
   __shared__ uint32_t wh[kRadixNW][256];   // per-wave counts, then running local offsets
   __shared__ uint32_t gdelta[256];         // global position - local position, per digit
-  __shared__ K sk[kRadixTile];
-  __shared__ V sv[kHasVal ? kRadixTile : 1];
+  __shared__ K sk[kTile];
+  __shared__ V sv[kHasVal ? kTile : 1];
   for (int j = threadIdx.x; j < kRadixNW * 256; j += kRadixNT) (&wh[0][0])[j] = 0;
   __syncthreads();
   const int w = threadIdx.x / kWave;
   const int lane = __lane_id();
-  const uint64_t tile = uint64_t(blockIdx.x) * kRadixTile;
+  const uint64_t tile = uint64_t(blockIdx.x) * kTile;
   const uint64_t sub = tile + uint64_t(w) * (kRows * kWave);
-  const uint32_t tile_n = uint32_t(n - tile < uint64_t(kRadixTile) ? n - tile : uint64_t(kRadixTile));
+  const uint32_t tile_n = uint32_t(n - tile < uint64_t(kTile) ? n - tile : uint64_t(kTile));
   K key[kRows];
   V val[kRows];
   uint32_t dg[kRows];
@@ -345,33 +359,34 @@ __device__ __forceinline__ void radix_scatter_tile(const Load& load, K* __restri
   }
 }
 
-template <typename K, typename V, bool kHasVal, bool kFused>
+template <typename K, typename V, bool kHasVal, bool kFused, int IPT = kRadixIPT>
 __global__ __launch_bounds__(kRadixNT) void radix_scatter_k(
     const K* __restrict__ kin, const V* __restrict__ vin, K* __restrict__ kout,
     V* __restrict__ vout, uint64_t n, int shift, const uint32_t* __restrict__ hist_scan,
     uint32_t nblocks) {
-  radix_scatter_tile<K, V, kHasVal, kFused>(KVLoad<K, V, kHasVal>{kin, vin}, kout, vout, n, shift, hist_scan,
-                                            nblocks);
+  radix_scatter_tile<K, V, kHasVal, kFused, KVLoad<K, V, kHasVal>, IPT>(KVLoad<K, V, kHasVal>{kin, vin}, kout, vout,
+                                                                        n, shift, hist_scan, nblocks);
 }
 
-inline uint32_t radix_blocks(uint64_t n) { return ceil_div(n, kRadixTile); }
+inline uint32_t radix_blocks(uint64_t n, int ipt = kRadixIPT) { return ceil_div(n, uint64_t(kRadixNT) * ipt); }
 // Up to this many tiles the scatter derives its offsets from the raw
 // histogram itself, which saves the scan's three launches per digit.
 constexpr uint32_t kRadixFusedTiles = 64;
-// Scratch (uint32 words) radix_sort needs for the histograms and their scan.
+// Scratch (uint32 words) radix_sort needs for the histograms and their scan,
+// for any of the compiled tile sizes.
 inline size_t radix_scratch_words(uint64_t n) {
-  const size_t h = size_t(radix_blocks(n)) * 256;
+  const size_t h = size_t(radix_blocks(n, kRadixIPTMin)) * 256;
   return h + scan_partials_count(h);
 }
 
 // Sorts (keys, vals) of length n by bits [begin_bit, end_bit) of the key,
 // stably. Ping-pongs between (k0,v0) and (k1,v1); returns true when the
 // result ends in (k1,v1). vals may be null (keys only).
-template <typename K, typename V = uint32_t>
-bool radix_sort(K* k0, V* v0, K* k1, V* v1, uint64_t n, int begin_bit, int end_bit,
-                uint32_t* scratch, hipStream_t s) {
+template <typename K, typename V, int IPT>
+bool radix_sort_t(K* k0, V* v0, K* k1, V* v1, uint64_t n, int begin_bit, int end_bit,
+                  uint32_t* scratch, hipStream_t s) {
   if (n <= 1 || end_bit <= begin_bit) return false;
-  const uint32_t nb = radix_blocks(n);
+  const uint32_t nb = radix_blocks(n, IPT);
   uint32_t* hist = scratch;
   uint32_t* part = scratch + size_t(nb) * 256;
   bool flip = false;
@@ -380,24 +395,55 @@ bool radix_sort(K* k0, V* v0, K* k1, V* v1, uint64_t n, int begin_bit, int end_b
     K* ko = flip ? k0 : k1;
     const V* vi = flip ? v1 : v0;
     V* vo = flip ? v0 : v1;
-    radix_hist_k<K><<<nb, kRadixNT, 0, s>>>(ki, n, shift, hist, nb);
+    radix_hist_k<K, IPT><<<nb, kRadixNT, 0, s>>>(ki, n, shift, hist, nb);
     KB_LAUNCH_CHECK();
     if (nb <= kRadixFusedTiles) {
       if (v0 != nullptr)
-        radix_scatter_k<K, V, true, true><<<nb, kRadixNT, 0, s>>>(ki, vi, ko, vo, n, shift, hist, nb);
+        radix_scatter_k<K, V, true, true, IPT><<<nb, kRadixNT, 0, s>>>(ki, vi, ko, vo, n, shift, hist, nb);
       else
-        radix_scatter_k<K, V, false, true><<<nb, kRadixNT, 0, s>>>(ki, nullptr, ko, nullptr, n, shift, hist, nb);
+        radix_scatter_k<K, V, false, true, IPT><<<nb, kRadixNT, 0, s>>>(ki, nullptr, ko, nullptr, n, shift, hist, nb);
     } else {
       scan<uint32_t, uint32_t, false>(hist, hist, uint64_t(nb) * 256, part, s);
       if (v0 != nullptr)
-        radix_scatter_k<K, V, true, false><<<nb, kRadixNT, 0, s>>>(ki, vi, ko, vo, n, shift, hist, nb);
+        radix_scatter_k<K, V, true, false, IPT><<<nb, kRadixNT, 0, s>>>(ki, vi, ko, vo, n, shift, hist, nb);
       else
-        radix_scatter_k<K, V, false, false><<<nb, kRadixNT, 0, s>>>(ki, nullptr, ko, nullptr, n, shift, hist, nb);
+        radix_scatter_k<K, V, false, false, IPT><<<nb, kRadixNT, 0, s>>>(ki, nullptr, ko, nullptr, n, shift, hist, nb);
     }
     KB_LAUNCH_CHECK();
     flip = !flip;
   }
   return flip;
+}
+
+// Calls f(std::integral_constant<int, IPT>{}) for the compiled tile size
+// with `ipt` items per thread (8, 12 or 16; anything else: the default).
+template <typename F>
+inline void with_radix_ipt(int ipt, F&& f) {
+  switch (ipt) {
+    case 8:
+      f(std::integral_constant<int, 8>{});
+      break;
+    case 16:
+      f(std::integral_constant<int, 16>{});
+      break;
+    default:
+      f(std::integral_constant<int, kRadixIPT>{});
+  }
+}
+
+// radix_sort_t with the tile size chosen at run time: ipt = items per
+// thread (8, 12 or 16; radix_ipt_of), 0 = the default.
+template <typename K, typename V = uint32_t>
+bool radix_sort(K* k0, V* v0, K* k1, V* v1, uint64_t n, int begin_bit, int end_bit,
+                uint32_t* scratch, hipStream_t s, int ipt = kRadixIPT) {
+  switch (ipt) {
+    case 8:
+      return radix_sort_t<K, V, 8>(k0, v0, k1, v1, n, begin_bit, end_bit, scratch, s);
+    case 16:
+      return radix_sort_t<K, V, 16>(k0, v0, k1, v1, n, begin_bit, end_bit, scratch, s);
+    default:
+      return radix_sort_t<K, V, kRadixIPT>(k0, v0, k1, v1, n, begin_bit, end_bit, scratch, s);
+  }
 }
 
 }  // namespace kb

@@ -51,6 +51,19 @@ def test_batch_no_early_stop_equals_plain():
         assert np.array_equal(pid, p2), g.name
 
 
+@pytest.mark.parametrize("radix_tile", [2048, 4096])
+def test_batch_radix_tiles(radix_tile):
+    """The batch's union build and ordering on the other compiled radix tile
+    sizes (the tuner's second knob): ids equal the oracle's per graph."""
+    torch, kb = need_gpu()
+    gs = mixed_graphs()
+    ks = [(i * 5) % 9 for i in range(len(gs))]
+    pids, blocks, rounds = kb.refine_batch(gs, ks, device="cuda:0", radix_tile=radix_tile)
+    for g, k, pid, b, rd in zip(gs, ks, pids, blocks, rounds):
+        r = oracle.refine(g.num_nodes, g.node_label, g.src, g.elab, g.dst, k)
+        assert rd == r.rounds_done and b == r.counts[-1] and np.array_equal(pid, r.pid), (g.name, radix_tile)
+
+
 def test_batch_many_small():
     """A few hundred graphs of log-normal size (the batched workload's shape,
     scaled down) against per-graph oracle runs."""

@@ -170,6 +170,30 @@ def test_update_powerlaw_200k(m, mode):
         check_against(h, cur, 10, True, "delete %d" % m)
 
 
+@pytest.mark.parametrize("radix_tile", [2048, 4096])
+def test_update_radix_tiles(radix_tile):
+    """The maintenance sorts (edges by target, merged rows) on the other
+    compiled radix tile sizes."""
+    torch, kb = need_gpu()
+    g = synth.powerlaw_graph(50_000, 400_000, seed=9, num_node_labels=20, num_edge_labels=6)
+    rng = np.random.default_rng(radix_tile)
+    cur = cur_of(g)
+    dev = torch.device("cuda:0")
+    with kb.Graph(g.num_nodes, *to_dev(torch, g), history=True, radix_tile=radix_tile) as h:
+        h.refine(10)
+        m = 5000
+        add = tuple(x.astype(np.int32) for x in (rng.integers(0, g.num_nodes, m), rng.integers(0, 6, m),
+                                                 rng.integers(0, g.num_nodes, m)))
+        h.update(add=tuple(torch.from_numpy(x).to(dev) for x in add))
+        cur = M.updated_graph(*cur, add=add)
+        check_against(h, cur, 10, True, "add %d, tile %d" % (m, radix_tile))
+        pick = rng.integers(0, cur[2].shape[0], m)
+        dele = (cur[2][pick], cur[3][pick], cur[4][pick])
+        h.update(delete=dele)
+        cur = M.updated_graph(*cur, delete=dele)
+        check_against(h, cur, 10, True, "delete %d, tile %d" % (m, radix_tile))
+
+
 @pytest.mark.parametrize("mode", MODES)
 def test_update_new_label_values(mode):
     """New node label values below, between and above the old ones, and new

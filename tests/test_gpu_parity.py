@@ -119,6 +119,26 @@ def test_powerlaw_mid(medium_cap):
     check_parity(g, 10, medium_cap=medium_cap)
 
 
+@pytest.mark.parametrize("radix_tile", [2048, 4096])
+def test_radix_tiles(radix_tile):
+    """Every radix pass (create's sort by source with its fused first pass,
+    the ordering's device-wide passes) on the other compiled tile sizes: the
+    power-law graph (hundreds of tiles per pass) and a small graph whose
+    passes take the single-launch path (at most 64 tiles)."""
+    g = synth.powerlaw_graph(200_000, 2_000_000, seed=7, deg_cap=30_000, name="powerlaw-200k")
+    check_parity(g, 10, radix_tile=radix_tile)
+    check_parity(synth.uniform_graph(20_000, 100_000, num_node_labels=3, num_edge_labels=5, seed=4,
+                                     name="uniform-20k-100k"), 6, radix_tile=radix_tile, medium_cap=64)
+
+
+def test_radix_tile_rejected():
+    torch, kb = need_gpu()
+    g = synth.worked_example()
+    for bad in (1000, 3000, -1):
+        with pytest.raises(kb.KbisimError, match="radix_tile"):
+            kb.Graph(6, g.node_label, g.src, g.elab, g.dst, radix_tile=bad)
+
+
 @pytest.mark.parametrize("members,endings", [(40, 7), (300, 20), (3000, 50)])
 def test_deep_common_prefix(members, endings):
     """Blocks (small, medium, large) whose signatures share their first 1000

@@ -45,6 +45,10 @@ def test_static_matches_ordinary_two_calls():
         host_out = np.empty(g.num_nodes, np.int32)
         nb2, rd2 = kb.kbisim_refine_static(g.num_nodes, g.node_label, g.src, g.elab, g.dst, k, host_out)
         assert (nb2, rd2) == (nb, rd) and np.array_equal(host_out, want)
+        # the smallest radix tile (most tiles, largest histograms) fits the region too
+        out.fill_(-7)
+        nb3, rd3 = kb.kbisim_refine_static(g.num_nodes, *arrs, k, out, stream=stream, radix_tile=2048)
+        assert (nb3, rd3) == (nb, rd) and np.array_equal(out.cpu().numpy(), want)
 
 
 def test_static_rejects_oversize_and_bad_input():
