@@ -149,9 +149,3 @@ def tune(graphs, k, sample_edges=20_000_000, repeats=5, device="cuda:0", use_cac
         _store(table)
     return choice, report
 
-
-def tune_medium_cap(graphs, k, **kw):
-    """medium_cap alone (radix tile at its default): (medium_cap, report)."""
-    cands = tuple((c, DEFAULT[1]) for c in CAPS)
-    pair, report = tune(graphs, k, candidates=cands, **kw)
-    return pair[0], report
