@@ -370,8 +370,11 @@ __global__ __launch_bounds__(kRadixNT) void radix_scatter_k(
 
 inline uint32_t radix_blocks(uint64_t n, int ipt = kRadixIPT) { return ceil_div(n, uint64_t(kRadixNT) * ipt); }
 // Up to this many tiles the scatter derives its offsets from the raw
-// histogram itself, which saves the scan's three launches per digit.
-constexpr uint32_t kRadixFusedTiles = 64;
+// histogram itself, which saves the scan's three launches per digit. On the
+// 10M/100M job (ordering passes of 10^5..10^6 items in rounds 1 and 2) 128
+// tiles gave 9.38 ms per job against 9.58 with 64, 9.47 with 256 and 9.45
+// with 512: each workgroup then reads 256 x nb counts.
+constexpr uint32_t kRadixFusedTiles = 128;
 // Scratch (uint32 words) radix_sort needs for the histograms and their scan,
 // for any of the compiled tile sizes.
 inline size_t radix_scratch_words(uint64_t n) {
