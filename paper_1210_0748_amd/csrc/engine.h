@@ -330,6 +330,7 @@ class Engine {
   int32_t cls_round_ = -1;  // round whose class scan cls_ holds (-1: none)
   // round scratch
   DevBuf ukey_, ucnt_, head_, cls_, fl_, first_, scanpart_, radix_, part_, bm_, bmslot_;
+  DevBuf scanpart_nodes_, radix_nodes_;  // the node part of create, beside the edge table's sort
   DevBuf bstart_;  // during the build: start position of every k = 0 block (and N)
   // streamed edge table (opt_.edge_window > 0): the CSR edge words in pinned
   // host memory, cut into partitions of consecutive source nodes whose rows

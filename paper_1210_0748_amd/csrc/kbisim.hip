@@ -332,7 +332,20 @@ void Engine::build(const int32_t* node_label, const int32_t* src, const int32_t*
   if (words[0] & 2u) throw InvalidInput("negative edge label");
   if (words[0] & 4u) throw InvalidInput("negative node label");
   const uint32_t max_nlab = words[1], max_elab = words[2];
-  build_nodes(node_label, max_nlab, masks, mask_host);
+  info_.ensure(kInfoWords * 4);
+
+  // The node part (pId_0, the order by label, the blocks) does not read the
+  // edge table: unless the handle must stay on one stream, it runs on the
+  // side stream beside the edge table's sort, with scratch of its own, and
+  // the handle's stream waits for it before the first round's set-up. The
+  // edge part is queued first, so its long passes start at once.
+  const bool split = !single_stream_ && N > 0 && E > 0;
+  hipStream_t ns = st_;
+  if (split) {
+    ns = side_stream();
+    KB_CHECK(hipEventRecord(ev_main_, st_));  // the validation pass is done
+    KB_CHECK(hipStreamWaitEvent(ns, ev_main_, 0));
+  }
 
   // edge labels: dense ascending ranks
   DevBuf etable, erank;
@@ -345,6 +358,37 @@ void Engine::build(const int32_t* node_label, const int32_t* src, const int32_t*
     build_adj<uint64_t>(src, lab, dst, er, et, hist0.as<uint32_t>());
   else
     build_adj<uint32_t>(src, lab, dst, er, et, hist0.as<uint32_t>());
+
+  if (split) {
+    // this thread's launches, scans, sorts, read-backs and pool traffic go
+    // to the side stream and its scratch until the node part is queued
+    struct Swap {
+      Engine* e;
+      hipStream_t st;
+      Swap(Engine* eng, hipStream_t s) : e(eng), st(s) { flip(); }
+      ~Swap() { flip(); }
+      void flip() {
+        std::swap(e->st_, st);
+        e->scanpart_.swap(e->scanpart_nodes_);
+        e->radix_.swap(e->radix_nodes_);
+      }
+    };
+    {
+      StreamScope scope(ns);
+      Swap on_side(this, ns);
+      build_nodes(node_label, max_nlab, masks, mask_host);
+    }
+    KB_CHECK(hipEventRecord(ev_join_, ns));
+    KB_CHECK(hipStreamWaitEvent(st_, ev_join_, 0));
+    // the node part's lasting buffers are used on the handle's stream from
+    // here on: their release must be ordered there (the pool records the
+    // release on a buffer's stream)
+    for (DevBuf* b : {&pid_, &ord_, &flag_, &cls_, &act_.start, &act_.size, &act_.depth, &soff_, &apos_, &anode_,
+                      &blists_, &fl_, &first_, &actr_, &pid0_, &bstart_})
+      b->s = st_;
+  } else {
+    build_nodes(node_label, max_nlab, masks, mask_host);
+  }
   finish_build();
 }
 
