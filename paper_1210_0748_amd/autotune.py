@@ -53,6 +53,13 @@ def workload_class(graphs):
     return "n%d_d%d" % (int(math.log2(mean_n)), int(math.log2(max(deg, 1.0))))
 
 
+def cache_key(arch, graphs, k, candidates):
+    """Cache entry of one tuning: architecture, workload class, k and the
+    candidate set (a search over fewer pairs is not reused for a larger one)."""
+    cand_id = ",".join("%d:%d" % tuple(c) for c in candidates)
+    return "%s/%s/k%d/%s" % (arch, workload_class(graphs), int(k), cand_id)
+
+
 def _load():
     try:
         with open(_cache_path()) as f:
@@ -101,8 +108,7 @@ def tune(graphs, k, sample_edges=20_000_000, repeats=5, device="cuda:0", use_cac
     import numpy as np
     import torch
     from . import kbisim_batch_create, kbisim_batch_refine, kbisim_batch_destroy
-    cand_id = ",".join("%d:%d" % c for c in candidates)
-    key = "%s/%s/k%d/%s" % (_arch(), workload_class(graphs), int(k), cand_id)
+    key = cache_key(_arch(), graphs, k, candidates)
     table = _load() if use_cache else {}
     if key in table and "best_pair" in table[key]:
         return tuple(table[key]["best_pair"]), table[key]["report"]

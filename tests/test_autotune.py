@@ -35,3 +35,18 @@ def test_pairs_of_cap_and_tile():
     assert choice == d and rep["fastest"] == (1024, 2048)
     runs[(1024, 2048)] = [0.90, 0.91, 0.90]
     assert autotune.choose(runs, d)[0] == (1024, 2048)
+
+
+def test_cache_key_separates_candidate_sets_and_workloads():
+    class G:
+        def __init__(self, n, e):
+            self.num_nodes, self.src = n, [0] * e
+    small = [G(20_000, 160_000)] * 4
+    big = [G(2_000_000, 16_000_000)] * 4
+    full = autotune.CANDIDATES
+    caps_only = tuple((c, autotune.DEFAULT[1]) for c in autotune.CAPS)
+    keys = {autotune.cache_key("gfx950", small, 5, full), autotune.cache_key("gfx950", small, 5, caps_only),
+            autotune.cache_key("gfx950", big, 5, full), autotune.cache_key("gfx950", small, 10, full),
+            autotune.cache_key("gfx942", small, 5, full)}
+    assert len(keys) == 5
+    assert autotune.cache_key("gfx950", small, 5, full) == autotune.cache_key("gfx950", list(small), 5, list(full))
