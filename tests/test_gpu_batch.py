@@ -1,5 +1,8 @@
 """Batched form: every graph of a batch gets exactly the ids, block count and
 rounds of refining it alone (oracle and plain GPU refine)."""
+import os
+import time
+
 import numpy as np
 import pytest
 
@@ -83,3 +86,25 @@ def test_batch_invalid_endpoint():
     with pytest.raises(kb.KbisimError) as e:
         kb.refine_batch([a, bad], 3)
     assert e.value.status == -1
+
+
+@pytest.mark.slow
+@pytest.mark.skipif(os.environ.get("KBISIM_FULL_BATCH") != "1", reason="about three minutes; set KBISIM_FULL_BATCH=1")
+def test_full_batch_4096_sampled():
+    """The batched configuration itself (4,096 graphs, 136M nodes, 1.09B
+    edges, k = 5, the bench's seed) refined as one batch on the GPU; 48
+    seeded random graphs and the largest one checked against the oracle run
+    on each graph alone (ids, block count, rounds)."""
+    torch, kb = need_gpu()
+    t0 = time.perf_counter()
+    gs = synth.batch_graphs(4096, seed=1, progress=say)
+    say("generated %d graphs, %d edges, in %.1f s" % (len(gs), sum(g.num_edges for g in gs), time.perf_counter() - t0))
+    pids, blocks, rounds = kb.refine_batch(gs, 5, device="cuda:0")
+    rng = np.random.default_rng(4096)
+    pick = sorted(set(rng.choice(len(gs), 48, replace=False).tolist()) | {int(np.argmax([g.num_nodes for g in gs]))})
+    for i in pick:
+        g = gs[i]
+        r = oracle.refine(g.num_nodes, g.node_label, g.src, g.elab, g.dst, 5)
+        assert rounds[i] == r.rounds_done and blocks[i] == r.counts[-1], (g.name, rounds[i], blocks[i], r.counts)
+        assert np.array_equal(pids[i], r.pid), g.name
+    say("%d graphs of the batch agree with the oracle (largest: %d nodes)" % (len(pick), max(gs[i].num_nodes for i in pick)))
