@@ -1,5 +1,6 @@
 """Served form: concurrent requests give the same results as each request
 alone; admission, rejection, failure isolation and cancellation."""
+import os
 import time
 
 import numpy as np
@@ -185,3 +186,48 @@ def test_cancel_running_keeps_neighbours():
             r = oracle.refine(g.num_nodes, g.node_label, g.src, g.elab, g.dst, 6)
             assert np.array_equal(out, r.pid) and rd == r.rounds_done, g.name
         assert srv.in_use() == 0
+
+
+@pytest.mark.slow
+@pytest.mark.skipif(os.environ.get("KBISIM_FULL_SERVED") != "1", reason="about six minutes; set KBISIM_FULL_SERVED=1")
+def test_full_served_stream_sampled():
+    """The served configuration itself (2,000 requests of the bench's stream,
+    seed 1: 24 pool graphs of 10k..50M nodes with |E| = 10 |N|, k in 2..10;
+    HBM budget 200 GB, 4 slots), all submitted at once. Every request on the
+    ten pool graphs of at most 300k nodes is checked against the oracle (its
+    run with the stored rounds on that graph: the ids of round min(k, fixed
+    point) and the rounds done); the others must report their rounds."""
+    torch, kb = need_gpu()
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    sizes = np.unique(np.round(np.geomspace(10_000, 50_000_000, 24)).astype(np.int64))
+    pool = []
+    for i, n in enumerate(sizes):
+        g = synth.powerlaw_graph(int(n), int(10 * n), seed=(1, 1000 + i), deg_cap=max(64, int(n) // 10))
+        pool.append((g, [torch.from_numpy(a).to(dev) for a in (g.node_label, g.src, g.elab, g.dst)]))
+        say("pool graph %d of %d (%d nodes) after %.1f s" % (i + 1, len(sizes), n, time.perf_counter() - t0))
+    reqs = synth.serving_stream(2000, seed=1, rate=200.0, max_nodes=50_000_000)
+    logs = np.log(sizes)
+    for r in reqs:
+        r["pool"] = int(np.argmin(np.abs(logs - np.log(r["num_nodes"]))))
+    small = [i for i, n in enumerate(sizes) if n <= 300_000]
+    ref = {}
+    for i in small:
+        g = pool[i][0]
+        ref[i] = oracle.refine(g.num_nodes, g.node_label, g.src, g.elab, g.dst, 10, history=True)
+    say("oracle on %d pool graphs after %.1f s" % (len(small), time.perf_counter() - t0))
+    checked = 0
+    with kb.Server(200 << 30, max_slots=4) as srv:
+        ids = [srv.submit(pool[r["pool"]][0].num_nodes, *pool[r["pool"]][1], r["k"]) for r in reqs]
+        for rid, r in zip(ids, reqs):
+            pid, nb, rd = srv.wait(rid, timeout_s=600)
+            srv.release(rid)
+            assert 1 <= rd <= r["k"], (r, rd)
+            if r["pool"] in ref:
+                o = ref[r["pool"]]
+                j = min(r["k"], o.rounds_done)
+                assert rd == j, (r, rd, o.rounds_done)
+                assert np.array_equal(pid, o.history[j]), (r["pool"], r["k"])
+                checked += 1
+    say("%d of %d requests checked against the oracle after %.1f s" % (checked, len(reqs), time.perf_counter() - t0))
+    assert checked > 0
