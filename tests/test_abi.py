@@ -42,3 +42,27 @@ def test_status_strings_and_null_handles():
     assert lib.kbisim_refine(None, 1, None) == -1
     assert lib.kbisim_result(None, None, 0, None, None, 0) == -1
     lib.kbisim_destroy(None)
+
+
+def test_options_defaults_and_rejections_before_device_work():
+    """kbisim_options_default and the option checks of kbisim_create, which
+    reject out-of-range values before any device call."""
+    import paper_1210_0748_amd as kb
+    from paper_1210_0748_amd import _binding as B
+    if not os.path.exists(kb.lib_path()):
+        pytest.skip("library not built")
+    lib = kb.load_library()
+    opt = B.Options()
+    lib.kbisim_options_default(ctypes.byref(opt))
+    assert (opt.early_stop, opt.profile, opt.history, opt.update_mode, opt.radix_tile, opt.edge_window_bytes) == \
+        (1, 0, 0, 0, 0, 0)
+    assert opt.medium_cap == 4096
+    desc = B.GraphDesc(0, 0, None, None, None, None, B.KBISIM_MEM_HOST, None)
+    h = ctypes.c_void_p()
+    for field, bad in (("radix_tile", 1000), ("radix_tile", 3000), ("radix_tile", -2048), ("medium_cap", 5000),
+                       ("update_mode", 3), ("edge_window_bytes", -1)):
+        o = B.Options()
+        lib.kbisim_options_default(ctypes.byref(o))
+        setattr(o, field, bad)
+        assert lib.kbisim_create(ctypes.byref(desc), ctypes.byref(o), ctypes.byref(h)) == -1, (field, bad)
+        assert field.split("_")[0] in lib.kbisim_last_error().decode(), field
